@@ -1,0 +1,251 @@
+"""CPU oracle for the truncated Lennard-Jones MD hot path (ctypes binding).
+
+TEST INFRASTRUCTURE ONLY: the test suite, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` are the only users. The GPU library never
+imports, links or calls anything here, and this package imports nothing from
+the GPU package.
+
+The arithmetic lives in ``oracle.c`` (plain FP64 C, OpenMP over particles);
+this module only marshals numpy arrays. Functions and the passages of the
+paper they follow:
+
+* ``phi``, ``fscalar``, ``pair_energy``, ``pair_fscalar`` -- the 12-6
+  Lennard-Jones pair potential, truncated and energy-shifted (Sec. 3 "Code
+  structure": truncation of the interaction range; Sec. 4: the common
+  Lennard-Jones potential).
+* ``forces_brute`` -- the O(N^2) all-pairs sum with the cutoff applied
+  (Sec. 4: the all-to-all interaction the port started from).
+* ``build_lists`` -- Verlet neighbour lists from particle binning (Sec. 3).
+* ``forces_list``, ``kinetic`` -- forces, energy, virial, kinetic energy and
+  momentum from the lists.
+* ``run_nve`` -- velocity-Verlet time stepping with the list rebuilt when
+  particles have moved far enough (Sec. 3 signals integrate/force/finalize;
+  Sec. 5: list updates become more frequent as particles move faster).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import time
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "oracle.c")
+
+CFLAGS = ["-O3", "-march=x86-64-v3", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+          "-fPIC", "-shared", "-std=c11", "-Wall"]
+
+
+def build(verbose: bool = False) -> str:
+    """Compile oracle.c into liboracle.so (gcc)."""
+    tmp = _LIB_PATH + f".tmp{os.getpid()}"
+    cmd = ["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class OLJ(C.Structure):
+    _fields_ = [("nspecies", C.c_int32), ("shift_energy", C.c_int32),
+                ("eps", C.c_double * 4), ("sigma", C.c_double * 4), ("rcut", C.c_double * 4),
+                ("mass", C.c_double * 2), ("skin", C.c_double), ("dt", C.c_double)]
+
+
+def make_params(p) -> OLJ:
+    """Build the C parameter struct from an object with the LJParams fields."""
+    s = OLJ()
+    s.nspecies = int(p.nspecies)
+    s.shift_energy = int(p.shift_energy)
+    for k in range(4):
+        s.eps[k] = float(p.eps[k])
+        s.sigma[k] = float(p.sigma[k])
+        s.rcut[k] = float(p.rcut[k])
+    for k in range(2):
+        s.mass[k] = float(p.mass[k])
+    s.skin = float(p.skin)
+    s.dt = float(p.dt)
+    return s
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = C.CDLL(_LIB_PATH)
+        dp, ip, up = C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_uint32)
+        fp = C.POINTER(C.c_float)
+        pp = C.POINTER(OLJ)
+        L.oracle_phi.restype = C.c_double
+        L.oracle_phi.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.oracle_fscalar.restype = C.c_double
+        L.oracle_fscalar.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.oracle_pair_energy.restype = C.c_double
+        L.oracle_pair_energy.argtypes = [C.c_double, C.c_int, pp]
+        L.oracle_pair_fscalar.restype = C.c_double
+        L.oracle_pair_fscalar.argtypes = [C.c_double, C.c_int, pp]
+        L.oracle_forces_brute.restype = None
+        L.oracle_forces_brute.argtypes = [C.c_int64, dp, ip, dp, pp, dp, dp]
+        L.oracle_build_lists.restype = C.c_int32
+        L.oracle_build_lists.argtypes = [C.c_int64, dp, ip, dp, pp, C.c_int32, C.c_int32, ip, ip]
+        L.oracle_forces_list.restype = None
+        L.oracle_forces_list.argtypes = [C.c_int64, dp, ip, dp, pp, C.c_int32, ip, ip, dp, dp]
+        L.oracle_kinetic.restype = None
+        L.oracle_kinetic.argtypes = [C.c_int64, dp, ip, pp, dp]
+        L.oracle_run_nve.restype = C.c_int64
+        L.oracle_run_nve.argtypes = [C.c_int64, dp, dp, ip, dp, pp, C.c_int64, dp, dp]
+        L.oracle_ds_split.restype = None
+        L.oracle_ds_split.argtypes = [C.c_double, fp, fp]
+        L.oracle_q_from_ds.restype = C.c_uint32
+        L.oracle_q_from_ds.argtypes = [C.c_float, C.c_float, C.c_double]
+        L.oracle_disp_q.restype = C.c_float
+        L.oracle_disp_q.argtypes = [C.c_uint32, C.c_uint32, C.c_double]
+        L.oracle_num_threads.restype = C.c_int32
+        L.oracle_num_threads.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _i(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def phi(r, eps=1.0, sigma=1.0):
+    return lib().oracle_phi(float(r), float(eps), float(sigma))
+
+
+def fscalar(r, eps=1.0, sigma=1.0):
+    return lib().oracle_fscalar(float(r), float(eps), float(sigma))
+
+
+def pair_energy(r, ab, params):
+    s = make_params(params)
+    return lib().oracle_pair_energy(float(r), int(ab), C.byref(s))
+
+
+def pair_fscalar(r, ab, params):
+    s = make_params(params)
+    return lib().oracle_pair_fscalar(float(r), int(ab), C.byref(s))
+
+
+def forces_brute(x, species, box, params):
+    """All-pairs forces. Returns (F (N,3), U, W)."""
+    x = _f64(x, (-1, 3))
+    n = x.shape[0]
+    sp, bx = _i32(species), _f64(box)
+    f = np.zeros((n, 3))
+    out = np.zeros(2)
+    s = make_params(params)
+    lib().oracle_forces_brute(n, _d(x), _i(sp), _d(bx), C.byref(s), _d(f), _d(out))
+    return f, float(out[0]), float(out[1])
+
+
+def build_lists(x, species, box, params, mode: int = 0, cap: int = 160):
+    """Full Verlet lists. mode 0: FP64 criterion, 1: the FP32 sequence.
+    Returns (cnt (N,), nbr (N, cap)); grows cap until every list fits."""
+    x = _f64(x, (-1, 3))
+    n = x.shape[0]
+    sp, bx = _i32(species), _f64(box)
+    s = make_params(params)
+    while True:
+        cnt = np.zeros(n, dtype=np.int32)
+        nbr = np.full((n, cap), -1, dtype=np.int32)
+        mx = lib().oracle_build_lists(n, _d(x), _i(sp), _d(bx), C.byref(s), int(mode), int(cap),
+                                      _i(cnt), _i(nbr))
+        if mx <= cap:
+            return cnt, nbr
+        cap = int(mx) + 16
+
+
+def neighbor_sets(cnt, nbr):
+    return [frozenset(nbr[i, : cnt[i]].tolist()) for i in range(len(cnt))]
+
+
+def forces_list(x, species, box, params, cnt, nbr):
+    x = _f64(x, (-1, 3))
+    n = x.shape[0]
+    sp, bx = _i32(species), _f64(box)
+    nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+    cnt = _i32(cnt)
+    f = np.zeros((n, 3))
+    out = np.zeros(2)
+    s = make_params(params)
+    lib().oracle_forces_list(n, _d(x), _i(sp), _d(bx), C.byref(s), nbr.shape[1], _i(cnt), _i(nbr),
+                             _d(f), _d(out))
+    return f, float(out[0]), float(out[1])
+
+
+def forces(x, species, box, params):
+    """Forces via lists (any N). Returns (F, U, W)."""
+    cnt, nbr = build_lists(x, species, box, params, 0)
+    return forces_list(x, species, box, params, cnt, nbr)
+
+
+def kinetic(v, species, params):
+    v = _f64(v, (-1, 3))
+    sp = _i32(species)
+    out = np.zeros(4)
+    s = make_params(params)
+    lib().oracle_kinetic(v.shape[0], _d(v), _i(sp), C.byref(s), _d(out))
+    return float(out[0]), out[1:].copy()
+
+
+def run_nve(x, v, species, box, params, nsteps: int, want_obs: bool = True):
+    """Velocity-Verlet NVE. Returns dict with x, v (unwrapped, final),
+    f (final forces), obs ((nsteps+1, 6): U, K, W, px, py, pz), builds,
+    seconds (wall time of the stepping call)."""
+    x = _f64(x, (-1, 3)).copy()
+    v = _f64(v, (-1, 3)).copy()
+    n = x.shape[0]
+    sp, bx = _i32(species), _f64(box)
+    obs = np.zeros((nsteps + 1, 6)) if want_obs else None
+    f = np.zeros((n, 3))
+    s = make_params(params)
+    t0 = time.perf_counter()
+    builds = lib().oracle_run_nve(n, _d(x), _d(v), _i(sp), _d(bx), C.byref(s), int(nsteps),
+                                  _d(obs) if obs is not None else None, _d(f))
+    dt = time.perf_counter() - t0
+    if builds < 0:
+        raise MemoryError("oracle_run_nve: allocation failed")
+    return {"x": x, "v": v, "f": f, "obs": obs, "builds": int(builds), "seconds": dt}
+
+
+def ds_split(w: float):
+    hi, lo = C.c_float(), C.c_float()
+    lib().oracle_ds_split(float(w), C.byref(hi), C.byref(lo))
+    return np.float32(hi.value), np.float32(lo.value)
+
+
+def q_from_ds(hi, lo, L):
+    return int(lib().oracle_q_from_ds(float(hi), float(lo), float(L)))
+
+
+def disp_q(qi, qj, L):
+    return np.float32(lib().oracle_disp_q(int(qi) & 0xFFFFFFFF, int(qj) & 0xFFFFFFFF, float(L)))
+
+
+def num_threads() -> int:
+    return int(lib().oracle_num_threads())

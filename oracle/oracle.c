@@ -1,0 +1,447 @@
+/*
+ * oracle.c -- plain, slow, obviously correct CPU reference for the truncated
+ * Lennard-Jones molecular-dynamics hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY. Only the test suite, the smoke entry point and the
+ * CPU-baseline leg of the benchmark may load this library. It shares no code,
+ * header, table or constant with the GPU library, and the GPU library never
+ * calls it.
+ *
+ * What it computes (paper: Sec. 1 time-stepping of Hamiltonian dynamics in a
+ * periodic box; Sec. 3 "Code structure": truncated pair potential, Verlet
+ * neighbour lists built from particle binning, velocity-Verlet half steps
+ * "integrate"/"finalize"; Sec. 4: the common Lennard-Jones potential):
+ *
+ *   phi(r)    = 4 eps [ (sigma/r)^12 - (sigma/r)^6 ]                (textbook LJ)
+ *   phi_s(r)  = phi(r) - phi(r_c)  for r < r_c, else 0   (truncated, energy-shifted)
+ *   f_ij      = fs(r) * r_ij,  fs = 24 eps [ 2 (sigma/r)^12 - (sigma/r)^6 ] / r^2
+ *   r_ij      = x_i - x_j under the minimum image  d - L rint(d / L)
+ *   U = sum_{i<j} phi_s,  W = sum_{i<j} fs r^2,  K = sum m v^2 / 2
+ *
+ * Everything is IEEE FP64. Two functions additionally reproduce, in IEEE
+ * binary32 with explicit fused multiply-adds, the stated FP32 operation
+ * sequence that the single-precision path uses to decide list membership
+ * (double-single split, fixed-point image coordinate, displacement, r^2), so
+ * that neighbour sets can be compared exactly. Compile with
+ * -ffp-contract=off so that no other fusion happens.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Parameters of one system (mirrored by a ctypes Structure in __init__.py). */
+typedef struct {
+    int32_t nspecies;       /* 1 or 2 */
+    int32_t shift_energy;   /* 1: subtract phi(r_c) inside the cutoff */
+    double eps[4];          /* [a*2+b] */
+    double sigma[4];
+    double rcut[4];         /* absolute cutoff length per pair */
+    double mass[2];
+    double skin;            /* list radius = rcut + skin */
+    double dt;
+} olj_t;
+
+static int pair_index(const olj_t *p, int a, int b) {
+    return p->nspecies == 1 ? 0 : a * 2 + b;
+}
+
+/* ---------------------------------------------------------------- O1 ---- */
+
+/* Unshifted 12-6 Lennard-Jones potential at distance r. */
+double oracle_phi(double r, double eps, double sigma) {
+    double sr = sigma / r;
+    double sr6 = sr * sr * sr * sr * sr * sr;
+    return 4.0 * eps * (sr6 * sr6 - sr6);
+}
+
+/* fs(r) = -phi'(r) / r, so that the force on i from j is fs * (x_i - x_j). */
+double oracle_fscalar(double r, double eps, double sigma) {
+    double sr = sigma / r;
+    double sr6 = sr * sr * sr * sr * sr * sr;
+    return 24.0 * eps * (2.0 * sr6 * sr6 - sr6) / (r * r);
+}
+
+/* Truncated (and, if requested, energy-shifted) pair energy of pair type ab. */
+double oracle_pair_energy(double r, int ab, const olj_t *p) {
+    if (r >= p->rcut[ab]) return 0.0;
+    double e = oracle_phi(r, p->eps[ab], p->sigma[ab]);
+    if (p->shift_energy) e -= oracle_phi(p->rcut[ab], p->eps[ab], p->sigma[ab]);
+    return e;
+}
+
+/* Truncated force scalar: fs(r) inside the cutoff, 0 outside (the force is
+ * not shifted, so it jumps at r_c). */
+double oracle_pair_fscalar(double r, int ab, const olj_t *p) {
+    if (r >= p->rcut[ab]) return 0.0;
+    return oracle_fscalar(r, p->eps[ab], p->sigma[ab]);
+}
+
+/* Minimum-image displacement x_i - x_j for any (wrapped or not) positions. */
+static void min_image(const double *xi, const double *xj, const double *box, double d[3]) {
+    for (int k = 0; k < 3; ++k) {
+        double t = xi[k] - xj[k];
+        d[k] = t - box[k] * rint(t / box[k]);
+    }
+}
+
+/* ---------------------------------------------------------------- O2 ---- */
+
+/* Brute force over all pairs i < j (the untruncated-loop definition with the
+ * cutoff applied). f: n*3 output. out[0] = U, out[1] = W. */
+void oracle_forces_brute(int64_t n, const double *x, const int32_t *sp, const double *box,
+                         const olj_t *p, double *f, double *out) {
+    double U = 0.0, W = 0.0;
+    memset(f, 0, sizeof(double) * 3 * (size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = i + 1; j < n; ++j) {
+            double d[3];
+            min_image(x + 3 * i, x + 3 * j, box, d);
+            double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            int ab = pair_index(p, sp[i], sp[j]);
+            if (r >= p->rcut[ab]) continue;
+            double fs = oracle_pair_fscalar(r, ab, p);
+            for (int k = 0; k < 3; ++k) {
+                f[3 * i + k] += fs * d[k];
+                f[3 * j + k] -= fs * d[k];
+            }
+            U += oracle_pair_energy(r, ab, p);
+            W += fs * r * r;
+        }
+    }
+    out[0] = U;
+    out[1] = W;
+}
+
+/* ---------------------------------------------------------------- O3 ---- */
+
+/* Wrap one coordinate into [0, L). */
+static double wrap1(double x, double L) {
+    double w = x - L * floor(x / L);
+    if (w >= L) w -= L;
+    return w;
+}
+
+/* FP64 list criterion: the stated double-precision operation sequence.
+ * d = w_i - w_j; d -= L rint(d / L); r2 = fma(dz,dz, fma(dy,dy, dx*dx)). */
+static double r2_fp64(const double *wi, const double *wj, const double *box) {
+    double d[3];
+    for (int k = 0; k < 3; ++k) {
+        double t = wi[k] - wj[k];
+        double m = rint(t / box[k]);
+        d[k] = t - box[k] * m;
+    }
+    return fma(d[2], d[2], fma(d[1], d[1], d[0] * d[0]));
+}
+
+/* FP32 operation sequence of the single-precision path.
+ * 1) double-single split of a wrapped FP64 coordinate: hi = (float) w,
+ *    lo = (float)(w - hi)  (Dekker's split into an unevaluated float sum).
+ * 2) fixed-point image coordinate q = round((hi + lo) * 2^32 / L) mod 2^32,
+ *    evaluated with an error-free product (TwoProduct by fma) in binary32.
+ * 3) displacement from the wrapping difference of two q's, scaled by the
+ *    double-single quantum L * 2^-32.                                      */
+void oracle_ds_split(double w, float *hi, float *lo) {
+    float h = (float)w;
+    *hi = h;
+    *lo = (float)(w - (double)h);
+}
+
+uint32_t oracle_q_from_ds(float hi, float lo, double L) {
+    double S = 4294967296.0 / L;
+    float S_hi = (float)S;
+    float S_lo = (float)(S - (double)S_hi);
+    float p = hi * S_hi;
+    float e = fmaf(hi, S_hi, -p);
+    float a = hi * S_lo;
+    float b = lo * S_hi;
+    float c = a + b;
+    float t = e + c;
+    float pi = floorf(p);
+    float pf = p - pi;
+    float u = pf + t;
+    int64_t q = (int64_t)pi + (int64_t)(int32_t)rintf(u);
+    return (uint32_t)(uint64_t)q;
+}
+
+float oracle_disp_q(uint32_t qi, uint32_t qj, double L) {
+    double qs = L / 4294967296.0;
+    float qs_hi = (float)qs;
+    float qs_lo = (float)(qs - (double)qs_hi);
+    int32_t dq = (int32_t)(qi - qj);
+    float a = (float)dq;
+    return fmaf(a, qs_hi, a * qs_lo);
+}
+
+static float r2_fp32(const uint32_t *qi, const uint32_t *qj, const double *box) {
+    float dx = oracle_disp_q(qi[0], qj[0], box[0]);
+    float dy = oracle_disp_q(qi[1], qj[1], box[1]);
+    float dz = oracle_disp_q(qi[2], qj[2], box[2]);
+    return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+}
+
+/* Full Verlet lists {j != i : r_ij^2 < (rcut_ab + skin)^2} by particle index,
+ * built with cell binning (cells of edge >= the largest list radius; a
+ * particle's partners then lie in the 27 surrounding cells). With fewer than
+ * three cells along an axis every particle is a candidate (plain all-pairs).
+ * mode 0: FP64 criterion; mode 1: the FP32 sequence above.
+ * cnt[i] = list length; nbr[i*cap + k] = k-th partner (first cap stored).
+ * Returns the largest list length (may exceed cap, in which case the lists
+ * are truncated and the caller must retry with a larger cap). */
+int32_t oracle_build_lists(int64_t n, const double *x, const int32_t *sp, const double *box,
+                           const olj_t *p, int32_t mode, int32_t cap, int32_t *cnt, int32_t *nbr) {
+    double rl_max = 0.0;
+    double rl2[4];
+    float rl2f[4];
+    for (int ab = 0; ab < 4; ++ab) {
+        double rl = p->rcut[ab] + p->skin;
+        rl2[ab] = rl * rl;
+        rl2f[ab] = (float)(rl * rl);
+        int used = p->nspecies == 2 || ab == 0;
+        if (used && rl > rl_max) rl_max = rl;
+    }
+    double *w = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    uint32_t *q = (uint32_t *)malloc(sizeof(uint32_t) * 3 * (size_t)n);
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < 3; ++k) {
+            w[3 * i + k] = wrap1(x[3 * i + k], box[k]);
+            float hi, lo;
+            oracle_ds_split(w[3 * i + k], &hi, &lo);
+            q[3 * i + k] = oracle_q_from_ds(hi, lo, box[k]);
+        }
+    int nc[3];
+    int brute = 0;
+    for (int k = 0; k < 3; ++k) {
+        nc[k] = (int)floor(box[k] / (rl_max * (1.0 + 1e-9)));
+        if (nc[k] < 3) brute = 1;
+    }
+    int64_t ncell = brute ? 1 : (int64_t)nc[0] * nc[1] * nc[2];
+    int64_t *cell_of = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t *start = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
+    int64_t *members = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c = 0;
+        if (!brute) {
+            int ci[3];
+            for (int k = 0; k < 3; ++k) {
+                ci[k] = (int)floor(w[3 * i + k] / box[k] * nc[k]);
+                if (ci[k] >= nc[k]) ci[k] = nc[k] - 1;
+                if (ci[k] < 0) ci[k] = 0;
+            }
+            c = ((int64_t)ci[0] * nc[1] + ci[1]) * nc[2] + ci[2];
+        }
+        cell_of[i] = c;
+        start[c + 1]++;
+    }
+    for (int64_t c = 0; c < ncell; ++c) start[c + 1] += start[c];
+    {
+        int64_t *fill = (int64_t *)calloc((size_t)ncell, sizeof(int64_t));
+        for (int64_t i = 0; i < n; ++i) {  /* increasing index: stable */
+            int64_t c = cell_of[i];
+            members[start[c] + fill[c]++] = i;
+        }
+        free(fill);
+    }
+    int32_t maxcnt = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(max : maxcnt)
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t k = 0;
+        int64_t cells[27];
+        int ncand = 0;
+        if (brute) {
+            cells[0] = 0;
+            ncand = 1;
+        } else {
+            int64_t c = cell_of[i];
+            int cz = (int)(c % nc[2]), cy = (int)((c / nc[2]) % nc[1]), cx = (int)(c / ((int64_t)nc[1] * nc[2]));
+            for (int dx = -1; dx <= 1; ++dx)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dz = -1; dz <= 1; ++dz) {
+                        int ax = (cx + dx + nc[0]) % nc[0];
+                        int ay = (cy + dy + nc[1]) % nc[1];
+                        int az = (cz + dz + nc[2]) % nc[2];
+                        cells[ncand++] = ((int64_t)ax * nc[1] + ay) * nc[2] + az;
+                    }
+        }
+        for (int s = 0; s < ncand; ++s) {
+            int64_t c = cells[s];
+            for (int64_t m = start[c]; m < start[c + 1]; ++m) {
+                int64_t j = members[m];
+                if (j == i) continue;
+                int ab = pair_index(p, sp[i], sp[j]);
+                int in;
+                if (mode == 0)
+                    in = r2_fp64(w + 3 * i, w + 3 * j, box) < rl2[ab];
+                else
+                    in = r2_fp32(q + 3 * i, q + 3 * j, box) < rl2f[ab];
+                if (in) {
+                    if (k < cap) nbr[(size_t)i * cap + k] = (int32_t)j;
+                    k++;
+                }
+            }
+        }
+        cnt[i] = k;
+        if (k > maxcnt) maxcnt = k;
+    }
+    free(w);
+    free(q);
+    free(cell_of);
+    free(start);
+    free(members);
+    return maxcnt;
+}
+
+/* ---------------------------------------------------------------- O4 ---- */
+
+/* Forces, energy and virial from full Verlet lists: f_i = sum_j fs r_ij over
+ * list partners with r < r_c; each pair appears in both lists, so U and W
+ * take half of every list term. out = [U, W]. */
+void oracle_forces_list(int64_t n, const double *x, const int32_t *sp, const double *box,
+                        const olj_t *p, int32_t cap, const int32_t *cnt, const int32_t *nbr,
+                        double *f, double *out) {
+    double U = 0.0, W = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : U, W)
+    for (int64_t i = 0; i < n; ++i) {
+        double fi[3] = {0.0, 0.0, 0.0};
+        double ui = 0.0, wi = 0.0;
+        int32_t m = cnt[i] < cap ? cnt[i] : cap;
+        for (int32_t k = 0; k < m; ++k) {
+            int64_t j = nbr[(size_t)i * cap + k];
+            double d[3];
+            min_image(x + 3 * i, x + 3 * j, box, d);
+            double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            int ab = pair_index(p, sp[i], sp[j]);
+            if (r >= p->rcut[ab]) continue;
+            double fs = oracle_pair_fscalar(r, ab, p);
+            for (int c = 0; c < 3; ++c) fi[c] += fs * d[c];
+            ui += 0.5 * oracle_pair_energy(r, ab, p);
+            wi += 0.5 * fs * r * r;
+        }
+        for (int c = 0; c < 3; ++c) f[3 * i + c] = fi[c];
+        U += ui;
+        W += wi;
+    }
+    out[0] = U;
+    out[1] = W;
+}
+
+/* Kinetic energy and momentum: out = [K, px, py, pz]. */
+void oracle_kinetic(int64_t n, const double *v, const int32_t *sp, const olj_t *p, double *out) {
+    double K = 0.0, px = 0.0, py = 0.0, pz = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double m = p->mass[p->nspecies == 2 ? sp[i] : 0];
+        const double *vi = v + 3 * i;
+        K += 0.5 * m * (vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2]);
+        px += m * vi[0];
+        py += m * vi[1];
+        pz += m * vi[2];
+    }
+    out[0] = K;
+    out[1] = px;
+    out[2] = py;
+    out[3] = pz;
+}
+
+/* ---------------------------------------------------------------- O5 ---- */
+
+typedef struct {
+    int64_t n;
+    int32_t cap;
+    int32_t *cnt, *nbr;
+    double *xref;
+} olist_t;
+
+static int build(olist_t *L, const double *x, const int32_t *sp, const double *box,
+                 const olj_t *p) {
+    for (;;) {
+        int32_t mx = oracle_build_lists(L->n, x, sp, box, p, 0, L->cap, L->cnt, L->nbr);
+        if (mx <= L->cap) break;
+        L->cap = mx + 16;
+        free(L->nbr);
+        L->nbr = (int32_t *)malloc(sizeof(int32_t) * (size_t)L->n * L->cap);
+        if (!L->nbr) return -1;
+    }
+    memcpy(L->xref, x, sizeof(double) * 3 * (size_t)L->n);
+    return 0;
+}
+
+/* The list stays valid while no particle has moved more than half the skin
+ * since the last build; rebuild when the largest displacement exceeds s/2. */
+static int needs_rebuild(const olist_t *L, const double *x, double skin) {
+    double lim2 = 0.25 * skin * skin;
+    for (int64_t i = 0; i < 3 * L->n; i += 3) {
+        double dx = x[i] - L->xref[i], dy = x[i + 1] - L->xref[i + 1], dz = x[i + 2] - L->xref[i + 2];
+        if (dx * dx + dy * dy + dz * dz > lim2) return 1;
+    }
+    return 0;
+}
+
+/* Velocity-Verlet NVE (Sec. 3: the "integrate" half step updates momenta and
+ * positions, a force evaluation follows, "finalize" completes the momenta):
+ *   v <- v + dt/2 F/m ; x <- x + dt v ; [rebuild if needed] ; F <- F(x) ;
+ *   v <- v + dt/2 F/m.
+ * x (unwrapped) and v are updated in place. obs (nullable) receives
+ * (nsteps + 1) rows [U, K, W, px, py, pz] for steps 0..nsteps.
+ * f_out (nullable) receives the final forces. Returns the number of list
+ * builds (including the initial one), or -1 on allocation failure. */
+int64_t oracle_run_nve(int64_t n, double *x, double *v, const int32_t *sp, const double *box,
+                       const olj_t *p, int64_t nsteps, double *obs, double *f_out) {
+    olist_t L;
+    L.n = n;
+    L.cap = 160;
+    L.cnt = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    L.nbr = (int32_t *)malloc(sizeof(int32_t) * (size_t)n * L.cap);
+    L.xref = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    double *f = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    double *invm = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!L.cnt || !L.nbr || !L.xref || !f || !invm) return -1;
+    for (int64_t i = 0; i < n; ++i) invm[i] = 1.0 / p->mass[p->nspecies == 2 ? sp[i] : 0];
+    int64_t builds = 0;
+    if (build(&L, x, sp, box, p)) return -1;
+    builds++;
+    double uw[2], kp[4];
+    oracle_forces_list(n, x, sp, box, p, L.cap, L.cnt, L.nbr, f, uw);
+    if (obs) {
+        oracle_kinetic(n, v, sp, p, kp);
+        double row[6] = {uw[0], kp[0], uw[1], kp[1], kp[2], kp[3]};
+        memcpy(obs, row, sizeof row);
+    }
+    double h = 0.5 * p->dt;
+    for (int64_t s = 1; s <= nsteps; ++s) {
+        for (int64_t i = 0; i < n; ++i)
+            for (int k = 0; k < 3; ++k) {
+                v[3 * i + k] += h * f[3 * i + k] * invm[i];
+                x[3 * i + k] += p->dt * v[3 * i + k];
+            }
+        if (needs_rebuild(&L, x, p->skin)) {
+            if (build(&L, x, sp, box, p)) return -1;
+            builds++;
+        }
+        oracle_forces_list(n, x, sp, box, p, L.cap, L.cnt, L.nbr, f, uw);
+        for (int64_t i = 0; i < n; ++i)
+            for (int k = 0; k < 3; ++k) v[3 * i + k] += h * f[3 * i + k] * invm[i];
+        if (obs) {
+            oracle_kinetic(n, v, sp, p, kp);
+            double row[6] = {uw[0], kp[0], uw[1], kp[1], kp[2], kp[3]};
+            memcpy(obs + 6 * s, row, sizeof row);
+        }
+    }
+    if (f_out) memcpy(f_out, f, sizeof(double) * 3 * (size_t)n);
+    free(L.cnt);
+    free(L.nbr);
+    free(L.xref);
+    free(f);
+    free(invm);
+    return builds;
+}
+
+int32_t oracle_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

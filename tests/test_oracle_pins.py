@@ -1,0 +1,324 @@
+"""Pins of the CPU oracle against what mathematics and physics fix.
+
+The paper prints no worked numerical example (its performance figure is a
+placeholder and it only states that results were verified), so every pin
+here is a closed form, an identity, a special case that reduces to something
+solvable by hand, a brute-force enumeration or a conservation law. Each is
+chosen so that a plausible slip in the oracle (a dropped term, a sign, a
+wrong index or image, a missing half) fails at least one of them.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2406_04210_amd import workloads as W
+
+RMIN = 2.0 ** (1.0 / 6.0)
+
+
+# ---------------------------------------------------------------- P1 ----
+def test_phi_special_values():
+    # phi(sigma) = 0 and phi(2^(1/6) sigma) = -eps are fixed by the 12-6 form.
+    for eps, sig in [(1.0, 1.0), (1.5, 0.8), (0.5, 0.88)]:
+        assert abs(oracle.phi(sig, eps, sig)) < 1e-15
+        assert oracle.phi(RMIN * sig, eps, sig) == pytest.approx(-eps, rel=1e-14)
+        assert abs(oracle.fscalar(RMIN * sig, eps, sig)) < 1e-13
+    # Scaling: phi(l r; eps, l sigma) = phi(r; eps, sigma).
+    for r in [0.9, 1.3, 2.2]:
+        assert oracle.phi(1.7 * r, 1.0, 1.7) == pytest.approx(oracle.phi(r, 1.0, 1.0), rel=1e-14)
+        assert oracle.phi(r, 2.5, 1.0) == pytest.approx(2.5 * oracle.phi(r, 1.0, 1.0), rel=1e-14)
+    # Large r: phi ~ -4 eps (sigma/r)^6 (the dispersion tail).
+    r = 40.0
+    assert oracle.phi(r) == pytest.approx(-4.0 * r ** -6, rel=1e-8)
+
+
+def test_fscalar_is_minus_dphi_over_r():
+    # fs = -phi'(r)/r, checked by a 4th-order central difference of phi.
+    h = 1e-4
+    for r in [0.95, 1.0, RMIN, 1.4, 2.0, 2.49]:
+        d = (-oracle.phi(r + 2 * h) + 8 * oracle.phi(r + h) - 8 * oracle.phi(r - h)
+             + oracle.phi(r - 2 * h)) / (12 * h)
+        assert oracle.fscalar(r) == pytest.approx(-d / r, rel=1e-9, abs=1e-11)
+
+
+def test_curvature_at_minimum():
+    # phi''(r_min) = 72 * 2^(-1/3) eps / sigma^2 = 57.146...; phi'(r) = -r fs(r).
+    h = 1e-5
+    d2 = (-(RMIN + h) * oracle.fscalar(RMIN + h) + (RMIN - h) * oracle.fscalar(RMIN - h)) / (2 * h)
+    assert d2 == pytest.approx(72.0 * 2.0 ** (-1.0 / 3.0), rel=1e-8)
+
+
+def test_truncation_and_shift():
+    p = W.single_species_params()
+    rc = 2.5
+    shift = 4.0 * (rc ** -12 - rc ** -6)
+    assert shift == pytest.approx(-0.016316891136, rel=1e-9)
+    # Energy is shifted so that it vanishes at r_c; force is not shifted.
+    assert oracle.pair_energy(rc * (1 - 1e-12), 0, p) == pytest.approx(0.0, abs=1e-12)
+    assert oracle.pair_energy(rc, 0, p) == 0.0
+    assert oracle.pair_energy(1.3, 0, p) == pytest.approx(oracle.phi(1.3) - shift, rel=1e-14)
+    f_rc = rc * oracle.pair_fscalar(rc * (1 - 1e-14), 0, p)   # |F| just inside r_c
+    assert f_rc == pytest.approx(-0.0389995, rel=1e-5)
+    assert oracle.pair_fscalar(rc, 0, p) == 0.0
+    # Mixture: per-pair cutoffs 2.5 sigma_ab.
+    m = W.binary_mixture_params()
+    for ab in range(4):
+        r = 0.999 * m.rcut[ab]
+        assert oracle.pair_energy(r, ab, m) == pytest.approx(
+            oracle.phi(r, m.eps[ab], m.sigma[ab]) - oracle.phi(m.rcut[ab], m.eps[ab], m.sigma[ab]),
+            rel=1e-13)
+        assert oracle.pair_energy(1.0001 * m.rcut[ab], ab, m) == 0.0
+    assert oracle.phi(2.0, 1.5, 0.8) == pytest.approx(-0.0244753, abs=2e-7)
+    assert oracle.phi(2.2, 0.5, 0.88) == pytest.approx(-0.0081584, abs=2e-7)
+
+
+# ---------------------------------------------------------------- P2 ----
+@pytest.mark.parametrize("nspecies", [1, 2])
+def test_force_is_minus_gradient_of_energy(nspecies):
+    w = W.random_dense(128, 0.8, seed=5 + nspecies, nspecies=nspecies)
+    f, _, _ = oracle.forces_brute(w.x, w.species, w.box, w.params)
+    rng = np.random.default_rng(11)
+    h = 2e-5
+    for _ in range(6):
+        i = int(rng.integers(w.n))
+        k = int(rng.integers(3))
+
+        def U(shift):
+            x = w.x.copy()
+            x[i, k] += shift
+            return oracle.forces_brute(x, w.species, w.box, w.params)[1]
+
+        g = (-U(2 * h) + 8 * U(h) - 8 * U(-h) + U(-2 * h)) / (12 * h)
+        assert -g == pytest.approx(f[i, k], rel=2e-7, abs=2e-7 * np.abs(f).max())
+
+
+# ---------------------------------------------------------------- P3 ----
+def _jittered_fcc(m, amp, seed):
+    x, L = W.fcc_lattice(m, 0.8442)
+    rng = np.random.default_rng(seed)
+    x = x + amp * rng.standard_normal(x.shape)
+    return x, np.full(3, L)
+
+
+@pytest.mark.parametrize("case", ["n256_allpairs", "n864_3cells", "n2048_4cells", "mixture"])
+def test_list_forces_equal_brute_force(case):
+    if case == "n256_allpairs":
+        w = W.random_dense(256, 0.8442, seed=3)
+        x, sp, box, p = w.x, w.species, w.box, w.params
+    elif case == "n864_3cells":
+        x, box = _jittered_fcc(6, 0.08, 1)
+        sp, p = np.zeros(len(x), np.int32), W.single_species_params()
+    elif case == "n2048_4cells":
+        x, box = _jittered_fcc(8, 0.08, 2)
+        sp, p = np.zeros(len(x), np.int32), W.single_species_params()
+    else:
+        w = W.random_dense(1500, 1.1, seed=4, min_dist=0.75, nspecies=2)
+        x, sp, box, p = w.x, w.species, w.box, w.params
+    fb, Ub, Wb = oracle.forces_brute(x, sp, box, p)
+    fl, Ul, Wl = oracle.forces(x, sp, box, p)
+    rms = np.sqrt((fb ** 2).sum(axis=1).mean())
+    assert np.abs(fl - fb).max() <= 1e-13 * rms
+    assert Ul == pytest.approx(Ub, rel=1e-13)
+    assert Wl == pytest.approx(Wb, rel=1e-13)
+
+
+def test_lists_equal_brute_force_enumeration():
+    # Lists from cell binning = every pair within (rc + skin), found by
+    # enumerating all pairs with numpy; also checks symmetry of full lists.
+    for x, box, sp, p in [(*_jittered_fcc(6, 0.1, 7), None, W.single_species_params())]:
+        n = len(x)
+        sp = np.zeros(n, np.int32)
+        cnt, nbr = oracle.build_lists(x, sp, box, p, mode=0)
+        d = x[:, None, :] - x[None, :, :]
+        d -= box * np.rint(d / box)
+        r2 = (d * d).sum(-1)
+        rl2 = (p.rcut[0] + p.skin) ** 2
+        assert np.abs(r2 - rl2).min() > 1e-9          # no boundary ties in this sample
+        want = r2 < rl2
+        np.fill_diagonal(want, False)
+        sets = oracle.neighbor_sets(cnt, nbr)
+        for i in range(n):
+            assert sets[i] == frozenset(np.nonzero(want[i])[0].tolist())
+        for i in range(n):
+            for j in sets[i]:
+                assert i in sets[j]
+
+
+def test_fp32_list_sequence_matches_fp64_away_from_ties():
+    w = W.config_small()
+    x, _ = _jittered_fcc(8, 0.15, 9)
+    p = w.params
+    c0, n0 = oracle.build_lists(x, w.species, w.box, p, mode=0)
+    c1, n1 = oracle.build_lists(x, w.species, w.box, p, mode=1)
+    s0, s1 = oracle.neighbor_sets(c0, n0), oracle.neighbor_sets(c1, n1)
+    rl2 = (p.rcut[0] + p.skin) ** 2
+    for i in range(len(x)):
+        for j in s0[i] ^ s1[i]:
+            d = x[i] - x[j]
+            d -= w.box * np.rint(d / w.box)
+            assert abs((d * d).sum() - rl2) < 1e-5 * rl2
+
+
+# ---------------------------------------------------------------- P4 ----
+def test_newton_third_law():
+    w = W.random_dense(700, 0.9, seed=8, nspecies=2, min_dist=0.8)
+    f, _, _ = oracle.forces(w.x, w.species, w.box, w.params)
+    rms = np.sqrt((f ** 2).sum(axis=1).mean())
+    assert np.abs(f.sum(axis=0)).max() <= 1e-12 * math.sqrt(w.n) * rms
+
+
+# ---------------------------------------------------------------- P5 ----
+def test_perfect_fcc_zero_force_and_lattice_sum():
+    rho = 0.8442
+    x, L = W.fcc_lattice(8, rho)
+    box = np.full(3, L)
+    sp = np.zeros(len(x), np.int32)
+    p = W.single_species_params()
+    f, U, Wv = oracle.forces(x, sp, box, p)
+    assert np.abs(f).max() <= 1e-12
+    # Independent lattice sum: U/N = 1/2 sum over FCC lattice vectors R != 0
+    # with |R| < rc of phi_s(|R|), summed shell by shell in long double.
+    a = (4.0 / rho) ** (1.0 / 3.0)
+    rc = 2.5
+    k = int(math.ceil(rc / a)) + 1
+    rs = []
+    basis = [(0, 0, 0), (0.5, 0.5, 0), (0.5, 0, 0.5), (0, 0.5, 0.5)]
+    for i in range(-k, k + 1):
+        for j in range(-k, k + 1):
+            for l in range(-k, k + 1):
+                for b in basis:
+                    R = a * math.sqrt((i + b[0]) ** 2 + (j + b[1]) ** 2 + (l + b[2]) ** 2)
+                    if 0 < R < rc:
+                        rs.append(R)
+    rs = np.array(rs, dtype=np.longdouble)
+    shift = np.longdouble(4.0) * (np.longdouble(rc) ** -12 - np.longdouble(rc) ** -6)
+    u = 0.5 * (4.0 * (rs ** -12 - rs ** -6) - shift).sum()
+    assert U / len(x) == pytest.approx(float(u), rel=1e-13)
+    # Virial of the lattice: W/N = 1/2 sum fs(R) R^2 = 1/2 sum 24 (2 R^-12 - R^-6).
+    wv = 0.5 * (24.0 * (2.0 * rs ** -12 - rs ** -6)).sum()
+    assert Wv / len(x) == pytest.approx(float(wv), rel=1e-13)
+
+
+# ---------------------------------------------------------------- P6 ----
+def test_free_flight_is_exact():
+    w = W.config_small()
+    p = w.params.copy()
+    p.eps[:] = 0.0
+    nsteps = 50
+    r = oracle.run_nve(w.x, w.v, w.species, w.box, p, nsteps)
+    want = w.x + nsteps * p.dt * w.v
+    assert np.abs(r["x"] - want).max() < 1e-12
+    assert np.array_equal(r["v"], w.v)
+
+
+# ---------------------------------------------------------------- P7 ----
+def test_dimer_oscillation_frequency():
+    p = W.single_species_params()
+    box = np.full(3, 10.0)
+    amp = 0.005
+    x = np.array([[5.0 - 0.5 * (RMIN + amp), 5.0, 5.0], [5.0 + 0.5 * (RMIN + amp), 5.0, 5.0]])
+    v = np.zeros((2, 3))
+    sp = np.zeros(2, np.int32)
+    # Integrate step by step, record separation.
+    seps = [x[1, 0] - x[0, 0]]
+    xs, vs = x, v
+    nsteps = 1200
+    for _ in range(nsteps):
+        r = oracle.run_nve(xs, vs, sp, box, p, 1, want_obs=False)
+        xs, vs = r["x"], r["v"]
+        seps.append(xs[1, 0] - xs[0, 0])
+    s = np.array(seps) - RMIN
+    # Upward zero crossings, linearly interpolated.
+    t = []
+    for k in range(len(s) - 1):
+        if s[k] < 0 <= s[k + 1]:
+            t.append(k + s[k] / (s[k] - s[k + 1]))
+    period_steps = (t[-1] - t[0]) / (len(t) - 1)
+    omega = math.sqrt(2.0 * 72.0 * 2.0 ** (-1.0 / 3.0))   # sqrt(phi''/mu), mu = 1/2
+    # Velocity Verlet shifts the frequency: cos(w' dt) = 1 - (w dt)^2 / 2.
+    wdt = omega * p.dt
+    w_vv = math.acos(1.0 - wdt * wdt / 2.0) / p.dt
+    want = 2.0 * math.pi / w_vv / p.dt
+    assert period_steps == pytest.approx(want, rel=2e-3)
+    assert 2.0 * math.pi / omega == pytest.approx(0.58772, rel=1e-4)
+
+
+# ---------------------------------------------------------------- P8 ----
+def test_translation_and_permutation_invariance():
+    w = W.random_dense(600, 0.85, seed=12, nspecies=2, min_dist=0.8)
+    f0, U0, W0 = oracle.forces(w.x, w.species, w.box, w.params)
+    rng = np.random.default_rng(3)
+    perm = rng.permutation(w.n)
+    f1, U1, W1 = oracle.forces(w.x[perm], w.species[perm], w.box, w.params)
+    rms = np.sqrt((f0 ** 2).sum(axis=1).mean())
+    assert np.abs(f1 - f0[perm]).max() <= 1e-14 * rms
+    shift = rng.uniform(0, w.box[0], size=3)
+    xt = (w.x + shift) % w.box
+    f2, U2, W2 = oracle.forces(xt, w.species, w.box, w.params)
+    assert np.abs(f2 - f0).max() <= 1e-12 * rms
+    assert U2 == pytest.approx(U0, rel=1e-12)
+
+
+# ---------------------------------------------------------------- P9 ----
+def test_stale_but_valid_list_gives_same_forces():
+    x, box = _jittered_fcc(8, 0.05, 21)
+    sp = np.zeros(len(x), np.int32)
+    p = W.single_species_params()
+    cnt, nbr = oracle.build_lists(x, sp, box, p)
+    rng = np.random.default_rng(2)
+    step = rng.standard_normal(x.shape)
+    step *= 0.49 * 0.5 * p.skin / np.linalg.norm(step, axis=1, keepdims=True).max()
+    x2 = x + step
+    f_old, U_old, _ = oracle.forces_list(x2, sp, box, p, cnt, nbr)
+    f_new, U_new, _ = oracle.forces(x2, sp, box, p)
+    rms = np.sqrt((f_new ** 2).sum(axis=1).mean())
+    assert np.abs(f_old - f_new).max() <= 1e-13 * rms
+    assert U_old == pytest.approx(U_new, rel=1e-13)
+
+
+# ---------------------------------------------------------------- P10 ---
+def test_nve_energy_and_momentum_conservation():
+    w = W.config_small()
+    r = oracle.run_nve(w.x, w.v, w.species, w.box, w.params, 400)
+    obs = r["obs"]
+    E = (obs[:, 0] + obs[:, 1]) / w.n
+    assert np.abs(E - E[0]).max() < 2e-3          # lattice-melting transient, dt = 0.005
+    late = E[200:]
+    slope = np.polyfit(np.arange(len(late)) * w.params.dt, late, 1)[0]
+    assert abs(slope) < 2e-4
+    assert np.abs(obs[:, 3:]).max() < 1e-10
+    # dt -> dt/2 reduces the energy fluctuation about 4x (second-order scheme).
+    p2 = w.params.copy()
+    p2.dt = w.params.dt / 2
+    r2 = oracle.run_nve(w.x, w.v, w.species, w.box, p2, 200)
+    E2 = (r2["obs"][:, 0] + r2["obs"][:, 1]) / w.n
+    a1 = np.abs(E[:101] - E[0]).max()
+    a2 = np.abs(E2[:201] - E2[0]).max()
+    assert 2.5 < a1 / a2 < 6.0
+
+
+# ---------------------------------------------------- FP32 sequence ----
+def test_ds_split_and_fixed_point_coordinate():
+    rng = np.random.default_rng(4)
+    for L in [13.43676953, 67.1838476553003, 149.380158]:
+        S = Fraction(2 ** 32) / Fraction(L)
+        for w in np.concatenate([rng.uniform(0, L, 300), [0.0, 1e-30, L * (1 - 1e-16), L / 2]]):
+            hi, lo = oracle.ds_split(w)
+            assert abs(float(hi) + float(lo) - w) <= abs(w) * 2.0 ** -47
+            exact = (Fraction(float(hi)) + Fraction(float(lo))) * S
+            want = int(round(exact)) % 2 ** 32
+            got = oracle.q_from_ds(hi, lo, L)
+            diff = (got - want) % 2 ** 32
+            assert diff in (0, 1, 2 ** 32 - 1)
+        # Displacements from wrapped differences of q reproduce min-image d.
+        for _ in range(200):
+            a, b = rng.uniform(0, L, 2)
+            qa = oracle.q_from_ds(*oracle.ds_split(a), L)
+            qb = oracle.q_from_ds(*oracle.ds_split(b), L)
+            d = a - b
+            d -= L * round(d / L)
+            got = float(oracle.disp_q(qa, qb, L))
+            assert abs(got - d) <= 2.0 * L * 2.0 ** -32 + 2.0 * abs(d) * 2.0 ** -24
