@@ -1,0 +1,177 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the gfx950 truncated-LJ MD hot path.
+
+Workload (one GPU): single-species LJ fluid, N = 256,000 (FCC 40^3 start),
+density 0.8442, T = 1.0 Maxwell-Boltzmann velocities, cutoff 2.5 sigma with
+energy shift, skin 0.3, dt = 0.005, NVE velocity Verlet, list rebuilt on
+half-skin displacement, space-filling-curve resort every 100 steps; FP32 pair
+arithmetic with double-single positions/velocities (the plain FP64 GPU path
+is timed on the same workload for comparison). Synthetic seeded inputs.
+
+Metric: particle-steps/s = N * steps / wall time of the timed ljmd_run
+(inputs resident in HBM, every rebuild, resort and per-step FP64 observable
+reduction included).
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s, LJ NVE N=256k on 1 GPU; adjoint/forward time ratio"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes_per_particle(prec: int, mean_list: float) -> float:
+    """HBM bytes one particle-step of the fused step kernel must move:
+    its list (4 B per entry) and length (4 B), its own record once, its
+    velocity and position state read and written, its reference position,
+    and its new record. Neighbour records are re-reads of records already
+    counted (served by L2/MALL) and are not algorithmic traffic."""
+    if prec == 1:   # FP32 + double-single
+        own_rec, state_rw, rec_out, xref = 16, 2 * (32 + 32), 16, 16
+    else:           # FP64
+        own_rec, state_rw, rec_out, xref = 32, 2 * 32, 32, 16
+    return 4.0 * mean_list + 4.0 + own_rec + state_rw + rec_out + xref
+
+
+def time_gpu(ljmd, torch, w, prec, steps, warmup, lanes, profile):
+    s = ljmd.System(w.n, w.box, w.params, precision=prec, sort_interval=100, lanes=lanes)
+    s.set_state(w.x, w.v, w.species)
+    if warmup:
+        s.run(warmup)
+    s.sync()
+    obs = torch.empty((steps, ljmd.NOBS), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    if profile:
+        s.set_profiling(True)
+    start.record(stream)
+    code = ljmd.lib.ljmd_run(s.ctx, steps, obs.data_ptr())
+    stop.record(stream)
+    torch.cuda.synchronize()
+    if code != 0:
+        raise ljmd.LJMDError(code, ljmd.last_error(s.ctx))
+    s.sync()
+    ms = start.elapsed_time(stop)
+    kt = s.kernel_times() if profile else None
+    o = obs.cpu().numpy()
+    cnt, _ = s.neighbors(cap=1)
+    mean_list = float(cnt.double().mean().item())
+    info = s.observables()
+    s.set_profiling(False)
+    return {"ms": ms, "obs": o, "kt": kt, "mean_list": mean_list, "info": info}
+
+
+def cpu_baseline(w, seconds_target: float = 15.0):
+    import oracle
+    # Calibrate on a few steps, then time a bounded sample of the same workload.
+    r = oracle.run_nve(w.x, w.v, w.species, w.box, w.params, 3, want_obs=False)
+    per_step = r["seconds"] / 4.0
+    steps = int(max(5, min(400, seconds_target / max(per_step, 1e-6))))
+    r = oracle.run_nve(w.x, w.v, w.species, w.box, w.params, steps, want_obs=False)
+    return {
+        "value": w.n * steps / r["seconds"],
+        "unit": "particle-steps/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"FP64 C oracle (OpenMP), N={w.n} same workload, {steps} steps incl. initial "
+                  f"list build and forces, {r['seconds']:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "multi-GPU runs are not part of it.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2406_04210_amd import ljmd
+    from paper_2406_04210_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    w = W.config_headline()
+    print(f"bench: workload {w.name} N={w.n}", file=sys.stderr, flush=True)
+
+    main_run = time_gpu(ljmd, torch, w, ljmd.FP32_DS, args.steps, args.warmup, args.lanes, False)
+    print(f"bench: fp32+ds {main_run['ms']:.2f} ms for {args.steps} steps", file=sys.stderr, flush=True)
+    prof_run = time_gpu(ljmd, torch, w, ljmd.FP32_DS, args.steps, args.warmup, args.lanes, True)
+    ms_step = main_run["ms"] / args.steps
+    value = w.n * args.steps / (main_run["ms"] * 1e-3)
+
+    step_ms, step_n = prof_run["kt"]["step"]
+    avg_step_kernel_s = step_ms * 1e-3 / max(step_n, 1)
+    bpp = algorithmic_bytes_per_particle(ljmd.FP32_DS, prof_run["mean_list"])
+    achieved = bpp * w.n / avg_step_kernel_s / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "kernel": "k_step_ds (forces + velocity Verlet + reductions)",
+                "avg_kernel_us": avg_step_kernel_s * 1e6,
+                "bytes_per_particle": bpp, "mean_list_len": prof_run["mean_list"]}
+    kernel_us = {k: (v[0] * 1e3 / v[1] if v[1] else 0.0) for k, v in prof_run["kt"].items()}
+
+    obs = main_run["obs"]
+    E = (obs[:, 0] + obs[:, 1]) / w.n
+    rebuilds = int(obs[:, 6].sum())
+
+    extra = {}
+    if not args.no_fp64:
+        r64 = time_gpu(ljmd, torch, w, ljmd.FP64, args.steps, args.warmup, args.lanes, False)
+        extra["fp64_value"] = w.n * args.steps / (r64["ms"] * 1e-3)
+        extra["fp64_ms_per_step"] = r64["ms"] / args.steps
+        print(f"bench: fp64 {r64['ms']:.2f} ms", file=sys.stderr, flush=True)
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(w, args.cpu_seconds)
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+ds",
+        "data": "synthetic (seeded FCC 40^3 + Maxwell-Boltzmann T=1.0)",
+        "config": {"workload": "LJ fluid N=256000 (FCC 40^3), rho=0.8442, T=1.0, rc=2.5 shifted, "
+                               "skin=0.3, dt=0.005, NVE velocity Verlet, half-skin rebuild, "
+                               "SFC resort every 100 steps",
+                   "n": w.n, "precision": "fp32 pair math, double-single state",
+                   "lanes": args.lanes or 1,
+                   "nbr_capacity": prof_run["info"]["nbr_capacity"]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernel_avg_us": kernel_us,
+        "rebuilds_in_timed_steps": rebuilds,
+        "energy_per_particle_first_last": [float(E[0]), float(E[-1])],
+        **extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,193 @@
+/*
+ * ljmd.h -- C ABI of the MI355X (gfx950) truncated Lennard-Jones MD hot path.
+ *
+ * The operations follow the problem statement of the paper (arXiv 2406.04210):
+ * time stepping of N particles in a periodic box (Sec. 1) under a truncated
+ * pair potential whose neighbours come from Verlet lists built by particle
+ * binning (Sec. 3, "Code structure"), with the two velocity-Verlet half
+ * steps "integrate" and "finalize" around the force evaluation (Sec. 3 and
+ * Fig. 1), the common 12-6 Lennard-Jones potential (Sec. 4), truncated
+ * forces (Sec. 5, "Truncated Force Performance Study"), list updates driven
+ * by particle movement (same paragraph) and reductions/sorting (Sec. 4,
+ * "Mixed Strategy").
+ *
+ * Conventions for every function below:
+ *   - Units are reduced LJ units; host-facing arrays are float64 and indexed
+ *     by the ORIGINAL particle id 0..n-1 (the library reorders particles
+ *     internally along a space-filling curve and hides that order).
+ *   - Array arguments marked "device" are device pointers on the GPU that
+ *     owns the context; "host" pointers are ordinary host memory.
+ *   - All device memory is CALLER-OWNED: the caller allocates one workspace
+ *     of ljmd_workspace_size() bytes and passes it to ljmd_create(). The
+ *     library never allocates or frees device memory.
+ *   - Work is enqueued on the hip stream given to ljmd_create() and the
+ *     calls return without synchronising, except those documented as
+ *     synchronising (ljmd_sync_status, ljmd_observables).
+ *   - Return value: LJMD_OK (0) or a negative ljmd_status. Functions never
+ *     abort or throw. Errors detected on the device (list or cell overflow,
+ *     non-finite positions) are latched in the context and reported by the
+ *     next synchronising call. ljmd_last_error() describes the last error.
+ *   - A context is not thread-safe; separate contexts are independent.
+ */
+#ifndef LJMD_H
+#define LJMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LJMD_ABI_VERSION 1
+
+enum ljmd_status {
+    LJMD_OK = 0,
+    LJMD_EINVAL = -1,  /* bad argument or parameter */
+    LJMD_ENOMEM = -2,  /* workspace smaller than ljmd_workspace_size() */
+    LJMD_EHIP = -3,    /* a HIP runtime call failed */
+    LJMD_EBOX = -4,    /* box edge < 2 * largest list radius (minimum image breaks) */
+    LJMD_ENLIST = -5,  /* a neighbour list exceeded nbr_capacity */
+    LJMD_ENAN = -6,    /* non-finite position detected */
+    LJMD_ESTATE = -7,  /* call out of order (e.g. run before set_state) */
+    LJMD_ECELL = -8    /* a cell exceeded cell_capacity */
+};
+
+enum ljmd_precision {
+    LJMD_FP64 = 0,     /* positions, velocities and pair arithmetic in FP64 */
+    LJMD_FP32_DS = 1   /* FP32 pair arithmetic and force accumulation; positions and
+                          velocities carried as double-single (unevaluated sums of
+                          two floats); FP64 only in the energy/virial reductions */
+};
+
+/* System and run parameters. Pair tables are indexed [a*2+b] for species
+ * a, b in {0, 1}; with nspecies == 1 only entry [0] is read. */
+typedef struct ljmd_params {
+    int64_t n;              /* number of particles, >= 2 */
+    double box[3];          /* periodic box edges (orthorhombic) */
+    int32_t nspecies;       /* 1 or 2 */
+    int32_t shift_energy;   /* 1: pair energy shifted to vanish at the cutoff */
+    double eps[4];          /* LJ well depth per pair */
+    double sigma[4];        /* LJ length per pair */
+    double rcut[4];         /* absolute cutoff length per pair */
+    double mass[2];         /* mass per species */
+    double skin;            /* Verlet skin: list radius = rcut + skin */
+    double dt;              /* time step */
+    int32_t sort_interval;  /* reorder along the space-filling curve every k steps; 0 = never */
+    int32_t precision;      /* enum ljmd_precision */
+    int32_t nbr_capacity;   /* list slots per particle; 0 = automatic */
+    int32_t cell_capacity;  /* particle slots per cell; 0 = automatic */
+    int32_t lanes;          /* lanes per particle in the force gather: 1,2,4,8,16; 0 = automatic */
+    int32_t reserved;       /* must be 0 */
+} ljmd_params;
+
+/* Per-step observable row written by ljmd_run into a device array:
+ * [U, K, W, px, py, pz, rebuilt, step]  (rebuilt = 1 if the neighbour list
+ * was rebuilt before the force evaluation of that step). U is the total
+ * (shifted) potential energy, K the kinetic energy, W = sum_{i<j} r_ij.f_ij
+ * the pair virial and p the total momentum. */
+#define LJMD_NOBS 8
+
+typedef struct ljmd_obs {
+    double U, K, W;         /* potential, kinetic, virial */
+    double P, T, E;         /* pressure rho T + W/(3V), temperature 2K/(3N-3), U+K */
+    double p[3];            /* total momentum */
+    int64_t step;           /* steps taken since ljmd_set_state */
+    int64_t rebuilds;       /* list builds since ljmd_set_state (including the first) */
+    int32_t max_fill;       /* longest neighbour list seen */
+    int32_t nbr_capacity;   /* list capacity in use */
+} ljmd_obs;
+
+typedef struct ljmd_ctx ljmd_ctx;
+
+/* Version of this ABI (LJMD_ABI_VERSION). */
+int32_t ljmd_abi_version(void);
+
+/* Validate parameters without touching a device. Returns LJMD_OK,
+ * LJMD_EINVAL (bad value, NULL) or LJMD_EBOX (box too small for the
+ * minimum-image convention with the largest list radius). Host only. */
+int ljmd_check_params(const ljmd_params *p);
+
+/* Bytes of device workspace needed for these parameters (pure host
+ * arithmetic, resolves the automatic capacities). 0 if p is invalid. */
+size_t ljmd_workspace_size(const ljmd_params *p);
+
+/* Cell grid the binning uses for these parameters: ncell[0..2] cells per
+ * axis, each edge >= the largest list radius. Host only. */
+int ljmd_cell_grid(const ljmd_params *p, int32_t ncell[3]);
+
+/* Rank of every cell of an nx*ny*nz grid along a 3D Hilbert curve
+ * (Skilling's transpose algorithm, AIP Conf. Proc. 707, 2004, on the
+ * smallest 2^k cube that holds the grid; ranks are then compacted to
+ * 0..nx*ny*nz-1). rank_out (host, nx*ny*nz int32) is indexed
+ * (ix*ny + iy)*nz + iz. This order is the particle order after a
+ * space-filling-curve resort (paper Sec. 4: sorting). Host only. */
+int ljmd_hilbert_ranks(int32_t nx, int32_t ny, int32_t nz, int32_t *rank_out);
+
+/* Create a context on the current HIP device. dev_workspace (device) must
+ * hold >= ljmd_workspace_size(p) bytes, 256-byte aligned, and outlive the
+ * context; hip_stream is a hipStream_t (NULL = default stream). The context
+ * keeps copies of p. Enqueues workspace initialisation on the stream. */
+int ljmd_create(const ljmd_params *p, void *dev_workspace, size_t bytes, void *hip_stream,
+                ljmd_ctx **out);
+
+/* Release the host-side context (device memory stays the caller's). */
+int ljmd_destroy(ljmd_ctx *ctx);
+
+/* Load a state: x, v (device, n*3 float64, by id; x need not be wrapped)
+ * and species (device, n int32 in [0, nspecies)). Wraps positions into the
+ * box, sorts particles along the space-filling curve, builds the lists and
+ * evaluates the forces of this state (the "force" slot before the first
+ * "integrate"). Resets the step and rebuild counters. */
+int ljmd_set_state(ljmd_ctx *ctx, const double *x, const double *v, const int32_t *species);
+
+/* Read the state by id: x (wrapped into [0, L)), v (device, n*3 float64)
+ * and img (device, n*3 int32 periodic image counters, so that the
+ * unwrapped position is x + img * L). Any pointer may be NULL. */
+int ljmd_get_state(ljmd_ctx *ctx, double *x, double *v, int32_t *img);
+
+/* Forces of the current state by id (device, n*3 float64). */
+int ljmd_get_forces(ljmd_ctx *ctx, double *f);
+
+/* Advance nsteps velocity-Verlet steps: per step, half kick + drift
+ * ("integrate"), list rebuild if any particle moved more than skin/2 since
+ * the last build (strict >) or a resort is due, force evaluation, half kick
+ * ("finalize"). obs_dev (device, nsteps * LJMD_NOBS float64, or NULL)
+ * receives one observable row per step. Asynchronous. */
+int ljmd_run(ljmd_ctx *ctx, int64_t nsteps, double *obs_dev);
+
+/* Neighbour lists of the last build, by id: cnt (device, n int32) list
+ * lengths and ids (device, n*cap int32, row id holds the first min(cnt, cap)
+ * partner ids in list order). For tests and inspection. */
+int ljmd_neighbors(ljmd_ctx *ctx, int32_t *cnt, int32_t *ids, int32_t cap);
+
+/* Synchronise the stream and return the first latched device error
+ * (LJMD_ENLIST, LJMD_ECELL, LJMD_ENAN) or LJMD_OK. */
+int ljmd_sync_status(ljmd_ctx *ctx);
+
+/* Synchronise and fill *out with the observables of the current step. */
+int ljmd_observables(ljmd_ctx *ctx, ljmd_obs *out);
+
+/* Kernel timing with HIP events recorded on the context's stream around
+ * every launch of each kernel family during ljmd_run: [0] the fused step
+ * kernel (forces + velocity Verlet + reductions), [1] the rebuild sequence
+ * (binning, canonical order, list build -- launched every step, working
+ * only when a rebuild is due), [2] the space-filling-curve resort,
+ * [3] everything else (integrate at run start, observable flushes).
+ * ljmd_set_profiling(ctx, 1) starts accumulating (and clears the sums);
+ * ljmd_kernel_times synchronises and writes total milliseconds ms[4] and
+ * launch counts count[4] (host arrays). Events cost a few microseconds of
+ * enqueue work per launch; leave profiling off for throughput runs. */
+#define LJMD_NKT 4
+int ljmd_set_profiling(ljmd_ctx *ctx, int enable);
+int ljmd_kernel_times(ljmd_ctx *ctx, double ms[LJMD_NKT], int64_t count[LJMD_NKT]);
+
+/* Text of the last error of ctx (or of the last failed create when ctx is
+ * NULL). The pointer stays valid until the next call on ctx. */
+const char *ljmd_last_error(const ljmd_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LJMD_H */

@@ -1,0 +1,253 @@
+// internal.h -- shared declarations of the gfx950 LJ MD library (device
+// constants, workspace views, double-single and fixed-point helpers, kernel
+// launchers). Not part of the public ABI.
+//
+// Every translation unit is compiled with -ffp-contract=off: multiplies and
+// adds are never fused implicitly, and each fused multiply-add is written out
+// with fmaf/fma. That makes the FP32 list-membership sequence and the
+// error-free transformations of the double-single arithmetic exact as stated.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ljmd.h"
+
+namespace ljmd {
+
+constexpr int kWave = 64;        // CDNA wavefront width
+constexpr int kBlock = 256;      // threads per block of the per-particle kernels
+constexpr int kRing = 64;        // steps of block partials kept before an observable flush
+constexpr int kNP = 8;           // doubles per partial row: U, W, K, px, py, pz, -, -
+
+// Latched device error bits (ctl->flags).
+enum : uint32_t { kErrList = 1u, kErrCell = 2u, kErrNaN = 4u };
+
+// Box constants. The fixed-point image coordinate q = round(x * 2^32 / L)
+// mod 2^32 turns the minimum image into a wrapping 32-bit subtraction.
+struct BoxC {
+    double L[3], invL[3], S[3];  // S = 2^32 / L
+    float Lhi[3], Llo[3];        // L as a double-single pair
+    float qs_hi[3], qs_lo[3];    // quantum L * 2^-32 as a double-single pair
+    float S_hi[3], S_lo[3];      // 2^32 / L as a double-single pair
+    int32_t nc[3];               // cells per axis
+    int32_t ncell;
+};
+
+// Pair constants by symmetric pair type t = a + b (0: AA, 1: AB, 2: BB).
+struct PairC {
+    double rc2[3], rl2[3], sig2[3], eps24[3], eps4[3], shift[3];
+    float rc2f[3], rl2f[3], sig2f[3], eps24f[3], eps4f[3], shiftf[3];
+};
+
+// Integration constants per species.
+struct DynC {
+    double hdt_m[2];                 // dt / (2 m)
+    float hdt_m_hi[2], hdt_m_lo[2];  // the same as double-single pairs
+    double dt;
+    float dt_hi, dt_lo;
+    double mass[2];
+    float massf[2];
+    float thr2;                      // (skin / 2)^2: rebuild when exceeded
+};
+
+// Control words in device memory.
+struct Ctl {
+    uint32_t maxd[2];     // max squared displacement since the last build (float bits), by drift parity
+    uint32_t flags;       // latched error bits
+    int32_t max_fill;     // longest list at any build
+    int64_t rebuilds;     // list builds since set_state
+    int32_t max_cell;     // largest cell occupancy at any build
+    int32_t pad;
+    double last[kNP];     // observables of the last flushed step: U, W, K, px, py, pz, rebuilt, step
+};
+
+// Views of the caller's workspace (all device pointers).
+struct State {
+    // FP64 path
+    double4 *rec64[2];    // gathered record (x, y, z, species) -- ping-pong by step
+    double4 *vel64;       // (vx, vy, vz, 0)
+    double4 *frc64;       // forces of the last step (fx, fy, fz, 0)
+    // FP32 + double-single path
+    int4 *recq[2];        // gathered record (qx, qy, qz, species) -- ping-pong by step
+    float4 *pos_hi, *pos_lo;
+    float4 *vel_hi, *vel_lo;
+    float4 *frc32;
+    // common
+    int4 *img;            // periodic image counters (x, y, z, 0)
+    int32_t *id;          // original id of the particle stored at this slot
+    int4 *xref;           // q at the last list build (x, y, z, 0)
+    int32_t *nbr;         // neighbour list, interleaved by wave chunk (see nbr_index)
+    int32_t *nbr_cnt;     // list length per particle
+    int32_t *cell_count;  // particles binned per cell (cells indexed by Hilbert rank)
+    int32_t *cell_members;// [ncell][cell_cap] particle slots, ascending after canonicalisation
+    int32_t *cell_start;  // [ncell + 1] exclusive scan of counts (resort only)
+    int32_t *rank_of;     // [ncell] Hilbert rank of the cell with linear index (ix*ny+iy)*nz+iz
+    uint8_t *scratch;     // resort staging
+    double *partials;     // [kRing][max_blocks][kNP] per-block observable partials
+    int32_t *rebuilt;     // [kRing] 1 if the list was rebuilt before that step's force
+    Ctl *ctl;
+};
+
+struct Geom {
+    int64_t n;
+    int32_t cap;          // list slots per particle (multiple of 16)
+    int32_t cell_cap;     // slots per cell
+    int32_t lanes;        // lanes per particle in the force gather
+    int32_t nspecies;
+    int32_t prec;
+    int32_t max_blocks;   // rows per ring slot of partials
+};
+
+// ------------------------------------------------------------------------
+// Device helpers
+// ------------------------------------------------------------------------
+
+// Chunked, interleaved neighbour-list layout. A wave owns P = 64/lanes
+// particles; entry k of particle i lives at
+//   chunk*(P*cap) + (k/lanes)*64 + (i%P)*lanes + (k%lanes),  chunk = i/P,
+// so the 64 lanes of a wave always read 64 consecutive int32 (256 bytes).
+__host__ __device__ inline int64_t nbr_index(int64_t i, int32_t k, int32_t lanes, int32_t cap) {
+    int32_t P = kWave / lanes;
+    int64_t chunk = i / P;
+    int32_t p = (int32_t)(i - chunk * P);
+    return chunk * (int64_t)P * cap + (int64_t)(k / lanes) * kWave + p * lanes + (k % lanes);
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs of the chip; remap so
+// that each XCD works on one contiguous eighth of the (space-filling-curve
+// ordered) particles and its L2 holds one compact region of the box.
+__device__ inline int xcd_remap(int b, int nb) {
+    int q = nb >> 3;
+    if (b >= (q << 3)) return b;
+    return (b & 7) * q + (b >> 3);
+}
+
+// Error-free transformations (Knuth's TwoSum, Dekker's Fast2Sum and the
+// fma-based TwoProduct) and double-single arithmetic built on them.
+struct dsf {
+    float hi, lo;
+};
+
+__device__ inline dsf two_sum(float a, float b) {
+    float s = a + b;
+    float bb = s - a;
+    float e = (a - (s - bb)) + (b - bb);
+    return {s, e};
+}
+
+__device__ inline dsf fast_two_sum(float a, float b) {  // requires |a| >= |b| or a == 0
+    float s = a + b;
+    float e = b - (s - a);
+    return {s, e};
+}
+
+__device__ inline dsf ds_add(dsf a, dsf b) {
+    dsf s = two_sum(a.hi, b.hi);
+    float e = s.lo + (a.lo + b.lo);
+    return fast_two_sum(s.hi, e);
+}
+
+// (c_hi + c_lo) * f as a double-single pair.
+__device__ inline dsf ds_mul_f(float c_hi, float c_lo, float f) {
+    float p = c_hi * f;
+    float e = fmaf(c_hi, f, -p);
+    e = fmaf(c_lo, f, e);
+    return fast_two_sum(p, e);
+}
+
+// (a_hi + a_lo) * (b_hi + b_lo) as a double-single pair.
+__device__ inline dsf ds_mul(dsf a, float b_hi, float b_lo) {
+    float p = a.hi * b_hi;
+    float e = fmaf(a.hi, b_hi, -p);
+    e = fmaf(a.hi, b_lo, fmaf(a.lo, b_hi, e));
+    return fast_two_sum(p, e);
+}
+
+// Fixed-point image coordinate of a double-single position (binary32 only):
+// q = round((hi + lo) * S) mod 2^32 with S = 2^32/L given as (S_hi, S_lo).
+__device__ inline uint32_t q_from_ds(float hi, float lo, float S_hi, float S_lo) {
+    float p = hi * S_hi;
+    float e = fmaf(hi, S_hi, -p);
+    float a = hi * S_lo;
+    float b = lo * S_hi;
+    float c = a + b;
+    float t = e + c;
+    float pi = floorf(p);
+    float pf = p - pi;
+    float u = pf + t;
+    long long q = (long long)pi + (long long)(int)rintf(u);
+    return (uint32_t)(unsigned long long)q;
+}
+
+// Fixed-point coordinate of an FP64 position (used for binning and for the
+// displacement check of the FP64 path).
+__device__ inline uint32_t q_from_d(double x, double S) {
+    return (uint32_t)(unsigned long long)(long long)rint(x * S);
+}
+
+// Minimum-image displacement from two fixed-point coordinates.
+__device__ inline float disp_q(uint32_t qi, uint32_t qj, float qs_hi, float qs_lo) {
+    int32_t dq = (int32_t)(qi - qj);
+    float a = (float)dq;
+    return fmaf(a, qs_hi, a * qs_lo);
+}
+
+// Minimum-image displacement of the FP64 path.
+__device__ inline double disp_d(double xi, double xj, double L, double invL) {
+    double t = xi - xj;
+    double m = rint(t * invL);
+    return t - L * m;
+}
+
+// Cell (Hilbert rank) of a particle from its fixed-point coordinates.
+__device__ inline int cell_of_q(uint32_t qx, uint32_t qy, uint32_t qz, const BoxC &b,
+                                const int32_t *rank_of, int *cx, int *cy, int *cz) {
+    int ix = (int)(((uint64_t)qx * (uint32_t)b.nc[0]) >> 32);
+    int iy = (int)(((uint64_t)qy * (uint32_t)b.nc[1]) >> 32);
+    int iz = (int)(((uint64_t)qz * (uint32_t)b.nc[2]) >> 32);
+    *cx = ix;
+    *cy = iy;
+    *cz = iz;
+    return rank_of[(ix * b.nc[1] + iy) * b.nc[2] + iz];
+}
+
+// Whether the list is rebuilt before the force evaluation of a step: forced
+// by the host (state load, resort) or the largest squared displacement since
+// the last build exceeds (skin/2)^2. A NaN displacement also triggers it.
+__device__ inline bool rebuild_due(const Ctl *ctl, int64_t step, int forced, float thr2) {
+    if (forced) return true;
+    uint32_t m = ctl->maxd[step & 1];
+    return m > __float_as_uint(thr2);
+}
+
+// ------------------------------------------------------------------------
+// Kernel launchers (host), one per kernel family.
+// ------------------------------------------------------------------------
+struct Launch {
+    const State *st;
+    const Geom *g;
+    const BoxC *box;
+    const PairC *pc;
+    const DynC *dyn;
+    hipStream_t stream;
+    int cur;              // current ping-pong record buffer
+};
+
+hipError_t launch_set_state(const Launch &L, const double *x, const double *v, const int32_t *sp);
+hipError_t launch_bin(const Launch &L, int64_t step, int forced);
+hipError_t launch_canon(const Launch &L, int64_t step, int forced);
+hipError_t launch_resort(const Launch &L);
+hipError_t launch_nlist(const Launch &L, int64_t step, int forced);
+// mode bits for launch_step
+enum : int { kFinalize = 1, kIntegrate = 2, kStoreForce = 4 };
+hipError_t launch_step(const Launch &L, int64_t step, int forced, int mode, int slot);
+hipError_t launch_integrate(const Launch &L, int64_t step);
+hipError_t launch_obs_reduce(const Launch &L, int64_t first_step, int count, int nblocks,
+                             double *obs_dev, int64_t obs_row0);
+hipError_t launch_get_state(const Launch &L, double *x, double *v, int32_t *img);
+hipError_t launch_get_forces(const Launch &L, double *f);
+hipError_t launch_neighbors(const Launch &L, int32_t *cnt, int32_t *ids, int32_t cap);
+int step_blocks(const Geom &g);
+
+}  // namespace ljmd

@@ -1,0 +1,364 @@
+// k_rebuild.hip -- neighbour-list rebuild on gfx950: particle binning,
+// canonical cell order, space-filling-curve resort and Verlet-list build
+// (paper Sec. 3 "Code structure": Verlet lists built from particle binning;
+// Sec. 4 "Mixed Strategy": sorting).
+//
+// Every kernel here is launched every step and returns at once unless the
+// list is due (host-forced, or the largest displacement since the last build
+// exceeded half the skin -- paper Sec. 5: more movement, more list updates).
+// The decision reads one control word written by the previous step's kernel,
+// so no host synchronisation is needed per step.
+#include "internal.h"
+
+namespace ljmd {
+
+// Fixed-point coordinates of particle i in the current record buffer.
+template <int PREC>
+__device__ inline void load_q(const State &st, int cur, int64_t i, const BoxC &box, uint32_t *q,
+                              int *sp) {
+    if constexpr (PREC == LJMD_FP64) {
+        double4 r = st.rec64[cur][i];
+        q[0] = q_from_d(r.x, box.S[0]);
+        q[1] = q_from_d(r.y, box.S[1]);
+        q[2] = q_from_d(r.z, box.S[2]);
+        *sp = (int)r.w;
+    } else {
+        int4 r = st.recq[cur][i];
+        q[0] = (uint32_t)r.x;
+        q[1] = (uint32_t)r.y;
+        q[2] = (uint32_t)r.z;
+        *sp = r.w;
+    }
+}
+
+// Bin: cell of every particle, counted with an atomic per cell. The slot a
+// particle lands in is arbitrary; k_canon restores a deterministic order.
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_bin(State st, Geom g, BoxC box, int cur, int64_t step,
+                                                int forced, float thr2) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) st.ctl->maxd[(step + 1) & 1] = 0u;
+    if (!rebuild_due(st.ctl, step, forced, thr2)) return;
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= g.n) return;
+    uint32_t q[3];
+    int sp;
+    load_q<PREC>(st, cur, i, box, q, &sp);
+    int cx, cy, cz;
+    int c = cell_of_q(q[0], q[1], q[2], box, st.rank_of, &cx, &cy, &cz);
+    int slot = atomicAdd(&st.cell_count[c], 1);
+    if (slot < g.cell_cap)
+        st.cell_members[(int64_t)c * g.cell_cap + slot] = (int32_t)i;
+    else
+        atomicOr(&st.ctl->flags, kErrCell);
+}
+
+// Canonicalise: one wavefront per cell sorts the cell's particle slots
+// ascending by rank counting in LDS (slots are distinct), so that list order
+// and hence force summation order are reproducible run to run.
+__global__ __launch_bounds__(kBlock) void k_canon(State st, Geom g, BoxC box, int64_t step,
+                                                  int forced, float thr2) {
+    if (!rebuild_due(st.ctl, step, forced, thr2)) return;
+    extern __shared__ int32_t sm[];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t c = (int64_t)blockIdx.x * (kBlock / kWave) + wv;
+    if (c >= box.ncell) return;
+    const int cnt = st.cell_count[c];
+    const int m = cnt < g.cell_cap ? cnt : g.cell_cap;
+    if (lane == 0) atomicMax(&st.ctl->max_cell, cnt);
+    int32_t *src = sm + (size_t)wv * 2 * g.cell_cap;
+    int32_t *dst = src + g.cell_cap;
+    int32_t *mem = st.cell_members + c * g.cell_cap;
+    for (int e = lane; e < m; e += kWave) src[e] = mem[e];
+    __builtin_amdgcn_wave_barrier();
+    for (int e = lane; e < m; e += kWave) {
+        int v = src[e];
+        int r = 0;
+        for (int k = 0; k < m; ++k) r += src[k] < v ? 1 : 0;
+        dst[r] = v;
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int e = lane; e < m; e += kWave) mem[e] = dst[e];
+}
+
+// Exclusive scan of the (capped) cell counts in Hilbert-rank order: the
+// start of every cell in the resorted particle order. One block.
+__global__ __launch_bounds__(1024) void k_scan(State st, Geom g, int ncell) {
+    __shared__ int32_t wsum[16];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    int32_t carry = 0;
+    for (int base = 0; base < ncell; base += 1024) {
+        int idx = base + tid;
+        int v = 0;
+        if (idx < ncell) {
+            v = st.cell_count[idx];
+            v = v < g.cell_cap ? v : g.cell_cap;
+        }
+        int x = v;
+        for (int o = 1; o < kWave; o <<= 1) {
+            int y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        if (lane == kWave - 1) wsum[wv] = x;
+        __syncthreads();
+        if (wv == 0) {
+            int s = lane < 16 ? wsum[lane] : 0;
+            for (int o = 1; o < 16; o <<= 1) {
+                int y = __shfl_up(s, o);
+                if (lane >= o) s += y;
+            }
+            if (lane < 16) wsum[lane] = s;
+        }
+        __syncthreads();
+        int excl = x - v + (wv > 0 ? wsum[wv - 1] : 0) + carry;
+        if (idx < ncell) st.cell_start[idx] = excl;
+        int total = wsum[15];
+        __syncthreads();
+        carry += total;
+    }
+    if (tid == 0) st.cell_start[ncell] = carry;
+}
+
+// Resort views of the scratch region (one copy of every per-particle array).
+struct ResortView {
+    double4 *rec64, *vel64;
+    int4 *recq;
+    float4 *pos_hi, *pos_lo, *vel_hi, *vel_lo;
+    int4 *img;
+    int32_t *id;
+};
+
+__host__ __device__ inline ResortView resort_view(uint8_t *base, int64_t npad, int prec) {
+    ResortView v{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        uint8_t *p = base + off;
+        off += (bytes + 255) & ~(size_t)255;
+        return p;
+    };
+    if (prec == LJMD_FP64) {
+        v.rec64 = (double4 *)take(sizeof(double4) * npad);
+        v.vel64 = (double4 *)take(sizeof(double4) * npad);
+    } else {
+        v.recq = (int4 *)take(sizeof(int4) * npad);
+        v.pos_hi = (float4 *)take(sizeof(float4) * npad);
+        v.pos_lo = (float4 *)take(sizeof(float4) * npad);
+        v.vel_hi = (float4 *)take(sizeof(float4) * npad);
+        v.vel_lo = (float4 *)take(sizeof(float4) * npad);
+    }
+    v.img = (int4 *)take(sizeof(int4) * npad);
+    v.id = (int32_t *)take(sizeof(int32_t) * npad);
+    return v;
+}
+
+size_t resort_scratch_bytes(int64_t npad, int prec) {
+    auto r = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    size_t s = prec == LJMD_FP64 ? 2 * r(sizeof(double4) * npad) : 5 * r(sizeof(float4) * npad);
+    return s + r(sizeof(int4) * npad) + r(sizeof(int32_t) * npad);
+}
+
+// Gather every per-particle array into scratch in (cell rank, slot) order and
+// rewrite the cell members with their new slots. One thread per cell slot.
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_resort_gather(State st, Geom g, BoxC box, int cur,
+                                                          ResortView sv) {
+    int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int64_t c = t / g.cell_cap;
+    int k = (int)(t - c * g.cell_cap);
+    if (c >= box.ncell) return;
+    int cnt = st.cell_count[c];
+    int m = cnt < g.cell_cap ? cnt : g.cell_cap;
+    if (k >= m) return;
+    int64_t slot = c * g.cell_cap + k;
+    int i = st.cell_members[slot];
+    int s = st.cell_start[c] + k;
+    if constexpr (PREC == LJMD_FP64) {
+        sv.rec64[s] = st.rec64[cur][i];
+        sv.vel64[s] = st.vel64[i];
+    } else {
+        sv.recq[s] = st.recq[cur][i];
+        sv.pos_hi[s] = st.pos_hi[i];
+        sv.pos_lo[s] = st.pos_lo[i];
+        sv.vel_hi[s] = st.vel_hi[i];
+        sv.vel_lo[s] = st.vel_lo[i];
+    }
+    sv.img[s] = st.img[i];
+    sv.id[s] = st.id[i];
+    st.cell_members[slot] = s;
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_resort_copy(State st, Geom g, int cur, ResortView sv) {
+    int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= g.n) return;
+    if constexpr (PREC == LJMD_FP64) {
+        st.rec64[cur][s] = sv.rec64[s];
+        st.vel64[s] = sv.vel64[s];
+    } else {
+        st.recq[cur][s] = sv.recq[s];
+        st.pos_hi[s] = sv.pos_hi[s];
+        st.pos_lo[s] = sv.pos_lo[s];
+        st.vel_hi[s] = sv.vel_hi[s];
+        st.vel_lo[s] = sv.vel_lo[s];
+    }
+    st.img[s] = sv.img[s];
+    st.id[s] = sv.id[s];
+}
+
+// Pair-type constant by symmetric type t = a + b.
+template <int NS, class T>
+__device__ inline T by_type(int t, const T (&a)[3]) {
+    if constexpr (NS == 1) {
+        return a[0];
+    } else {
+        return t == 0 ? a[0] : (t == 1 ? a[1] : a[2]);
+    }
+}
+
+// Verlet lists: particle i scans the 27 cells around its own (only the
+// distinct ones when an axis has fewer than 3 cells) in a fixed order, the
+// members of each cell in ascending slot order, and keeps every j != i with
+// r_ij^2 < (r_c + skin)^2 under the stated operation sequence of its
+// precision. Stores the list length and the fixed-point reference position
+// for the displacement check.
+template <int PREC, int NS>
+__global__ __launch_bounds__(kBlock) void k_nlist(State st, Geom g, BoxC box, PairC pc, int cur,
+                                                  int64_t step, int forced, float thr2) {
+    if (!rebuild_due(st.ctl, step, forced, thr2)) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) st.ctl->rebuilds += 1;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t i = (int64_t)blk * kBlock + threadIdx.x;
+    int k = 0;
+    if (i < g.n) {
+        uint32_t q[3];
+        int si;
+        load_q<PREC>(st, cur, i, box, q, &si);
+        double4 ri64;
+        if constexpr (PREC == LJMD_FP64) ri64 = st.rec64[cur][i];
+        int cx, cy, cz;
+        cell_of_q(q[0], q[1], q[2], box, st.rank_of, &cx, &cy, &cz);
+        int lo[3], hi[3];
+        const int cc[3] = {cx, cy, cz};
+        for (int a = 0; a < 3; ++a) {
+            if (box.nc[a] >= 3) {
+                lo[a] = -1;
+                hi[a] = 1;
+            } else {
+                lo[a] = -cc[a];
+                hi[a] = box.nc[a] - 1 - cc[a];
+            }
+        }
+        for (int ox = lo[0]; ox <= hi[0]; ++ox) {
+            int ax = cx + ox;
+            ax += ax < 0 ? box.nc[0] : (ax >= box.nc[0] ? -box.nc[0] : 0);
+            for (int oy = lo[1]; oy <= hi[1]; ++oy) {
+                int ay = cy + oy;
+                ay += ay < 0 ? box.nc[1] : (ay >= box.nc[1] ? -box.nc[1] : 0);
+                for (int oz = lo[2]; oz <= hi[2]; ++oz) {
+                    int az = cz + oz;
+                    az += az < 0 ? box.nc[2] : (az >= box.nc[2] ? -box.nc[2] : 0);
+                    const int c = st.rank_of[(ax * box.nc[1] + ay) * box.nc[2] + az];
+                    int m = st.cell_count[c];
+                    m = m < g.cell_cap ? m : g.cell_cap;
+                    const int32_t *mem = st.cell_members + (int64_t)c * g.cell_cap;
+                    for (int e = 0; e < m; ++e) {
+                        const int j = mem[e];
+                        if (j == (int)i) continue;
+                        bool in;
+                        if constexpr (PREC == LJMD_FP64) {
+                            const double4 rj = st.rec64[cur][j];
+                            const int t = NS == 1 ? 0 : si + (int)rj.w;
+                            double dx = disp_d(ri64.x, rj.x, box.L[0], box.invL[0]);
+                            double dy = disp_d(ri64.y, rj.y, box.L[1], box.invL[1]);
+                            double dz = disp_d(ri64.z, rj.z, box.L[2], box.invL[2]);
+                            double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                            in = r2 < by_type<NS>(t, pc.rl2);
+                        } else {
+                            const int4 rj = st.recq[cur][j];
+                            const int t = NS == 1 ? 0 : si + rj.w;
+                            float dx = disp_q(q[0], (uint32_t)rj.x, box.qs_hi[0], box.qs_lo[0]);
+                            float dy = disp_q(q[1], (uint32_t)rj.y, box.qs_hi[1], box.qs_lo[1]);
+                            float dz = disp_q(q[2], (uint32_t)rj.z, box.qs_hi[2], box.qs_lo[2]);
+                            float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                            in = r2 < by_type<NS>(t, pc.rl2f);
+                        }
+                        if (in) {
+                            if (k < g.cap) st.nbr[nbr_index(i, k, g.lanes, g.cap)] = j;
+                            ++k;
+                        }
+                    }
+                }
+            }
+        }
+        st.nbr_cnt[i] = k;
+        st.xref[i] = make_int4((int)q[0], (int)q[1], (int)q[2], 0);
+        if (k > g.cap) atomicOr(&st.ctl->flags, kErrList);
+    }
+    // One atomic per wavefront for the longest list.
+    int mk = k;
+    for (int o = 32; o > 0; o >>= 1) {
+        int y = __shfl_xor(mk, o);
+        mk = y > mk ? y : mk;
+    }
+    if ((threadIdx.x & 63) == 0 && mk > 0) atomicMax(&st.ctl->max_fill, mk);
+}
+
+// ------------------------------------------------------------------------
+static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+hipError_t launch_bin(const Launch &L, int64_t step, int forced) {
+    unsigned nb = blocks_for(L.g->n, kBlock);
+    if (L.g->prec == LJMD_FP64)
+        hipLaunchKernelGGL(k_bin<LJMD_FP64>, dim3(nb), dim3(kBlock), 0, L.stream, *L.st, *L.g,
+                           *L.box, L.cur, step, forced, L.dyn->thr2);
+    else
+        hipLaunchKernelGGL(k_bin<LJMD_FP32_DS>, dim3(nb), dim3(kBlock), 0, L.stream, *L.st, *L.g,
+                           *L.box, L.cur, step, forced, L.dyn->thr2);
+    return hipGetLastError();
+}
+
+hipError_t launch_canon(const Launch &L, int64_t step, int forced) {
+    const int wpb = kBlock / kWave;
+    unsigned nb = blocks_for(L.box->ncell, wpb);
+    size_t shm = (size_t)wpb * 2 * L.g->cell_cap * sizeof(int32_t);
+    hipLaunchKernelGGL(k_canon, dim3(nb), dim3(kBlock), shm, L.stream, *L.st, *L.g, *L.box, step,
+                       forced, L.dyn->thr2);
+    return hipGetLastError();
+}
+
+hipError_t launch_resort(const Launch &L) {
+    int64_t npad = (L.g->n + 63) / 64 * 64;
+    ResortView sv = resort_view(L.st->scratch, npad, L.g->prec);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, L.stream, *L.st, *L.g, L.box->ncell);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    unsigned nb = blocks_for((int64_t)L.box->ncell * L.g->cell_cap, kBlock);
+    unsigned nc = blocks_for(L.g->n, kBlock);
+    if (L.g->prec == LJMD_FP64) {
+        hipLaunchKernelGGL(k_resort_gather<LJMD_FP64>, dim3(nb), dim3(kBlock), 0, L.stream, *L.st,
+                           *L.g, *L.box, L.cur, sv);
+        hipLaunchKernelGGL(k_resort_copy<LJMD_FP64>, dim3(nc), dim3(kBlock), 0, L.stream, *L.st,
+                           *L.g, L.cur, sv);
+    } else {
+        hipLaunchKernelGGL(k_resort_gather<LJMD_FP32_DS>, dim3(nb), dim3(kBlock), 0, L.stream,
+                           *L.st, *L.g, *L.box, L.cur, sv);
+        hipLaunchKernelGGL(k_resort_copy<LJMD_FP32_DS>, dim3(nc), dim3(kBlock), 0, L.stream, *L.st,
+                           *L.g, L.cur, sv);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_nlist(const Launch &L, int64_t step, int forced) {
+    unsigned nb = blocks_for(L.g->n, kBlock);
+#define NL(P, S)                                                                               \
+    hipLaunchKernelGGL((k_nlist<P, S>), dim3(nb), dim3(kBlock), 0, L.stream, *L.st, *L.g, *L.box, \
+                       *L.pc, L.cur, step, forced, L.dyn->thr2)
+    if (L.g->prec == LJMD_FP64) {
+        if (L.g->nspecies == 1) NL(LJMD_FP64, 1); else NL(LJMD_FP64, 2);
+    } else {
+        if (L.g->nspecies == 1) NL(LJMD_FP32_DS, 1); else NL(LJMD_FP32_DS, 2);
+    }
+#undef NL
+    return hipGetLastError();
+}
+
+}  // namespace ljmd

@@ -1,0 +1,479 @@
+// k_step.hip -- the per-step hot kernel on gfx950: truncated LJ pair forces
+// gathered over the Verlet list, fused with both velocity-Verlet half steps
+// and the reductions that follow them (paper Sec. 3 "Code structure" and
+// Fig. 1: force, finalize and integrate; Sec. 5: truncated pair forces).
+//
+// One launch per step s does, for every particle i:
+//   F_i(x_s)      = sum_j fs(r_ij) r_ij over list partners with r_ij < r_c
+//   finalize      v_s   = v' + dt/(2m) F_i              (completes step s)
+//   observables   e_i, w_i (half of every pair), K_i, m v_i -> FP64 block partials
+//   integrate     v'    = v_s + dt/(2m) F_i ; x_{s+1} = x_s + dt v'  (starts step s+1)
+//   displacement  |x_{s+1} - x_ref|^2 -> max -> rebuild decision of step s+1
+// Positions are read from one record buffer and written to the other, so no
+// wave ever sees a partner that has already moved.
+//
+// Gather geometry: LANES lanes per particle, 64/LANES particles per
+// wavefront; the interleaved list layout makes every list load one 256-byte
+// contiguous read. Each XCD gets a contiguous eighth of the particles.
+#include "internal.h"
+
+namespace ljmd {
+
+struct StepArgs {
+    State st;
+    Geom g;
+    BoxC box;
+    PairC pc;
+    DynC dyn;
+    int cur;
+    int forced;
+    int mode;
+    int slot;
+    int64_t step;
+};
+
+template <int NS, class T>
+__device__ inline T by_t(int t, const T (&a)[3]) {
+    if constexpr (NS == 1) {
+        return a[0];
+    } else {
+        return t == 0 ? a[0] : (t == 1 ? a[1] : a[2]);
+    }
+}
+
+template <class T>
+__device__ inline T by_s(int s, const T (&a)[2]) {
+    return s == 0 ? a[0] : a[1];
+}
+
+template <class T>
+__device__ inline T wave_sum(T v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ inline uint32_t wave_max_u(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        uint32_t y = __shfl_xor(v, o);
+        v = y > v ? y : v;
+    }
+    return v;
+}
+
+// Block-level deterministic reduction of the six observable partials and the
+// displacement maximum; one row of partials per block.
+__device__ inline void block_finish(const StepArgs &a, int blk, double u, double w, double k,
+                                    double px, double py, double pz, uint32_t dmax) {
+    constexpr int WPB = kBlock / kWave;
+    __shared__ double red[WPB][6];
+    __shared__ uint32_t redm[WPB];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double v6[6] = {u, w, k, px, py, pz};
+#pragma unroll
+    for (int q = 0; q < 6; ++q) v6[q] = wave_sum(v6[q]);
+    dmax = wave_max_u(dmax);
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) red[wv][q] = v6[q];
+        redm[wv] = dmax;
+    }
+    __syncthreads();
+    if (threadIdx.x < kNP) {
+        double s = 0.0;
+        if (threadIdx.x < 6)
+            for (int q = 0; q < WPB; ++q) s += red[q][threadIdx.x];
+        a.st.partials[((size_t)a.slot * a.g.max_blocks + blk) * kNP + threadIdx.x] = s;
+    }
+    if (threadIdx.x == 0 && (a.mode & kIntegrate)) {
+        uint32_t m = 0;
+        for (int q = 0; q < WPB; ++q) m = redm[q] > m ? redm[q] : m;
+        atomicMax(&a.st.ctl->maxd[(a.step + 1) & 1], m);
+        if (m > 0x7f800000u) atomicOr(&a.st.ctl->flags, kErrNaN);
+    }
+}
+
+// Housekeeping shared by both precisions: the rebuilt marker of this step and,
+// after a rebuild, clearing the cell counters for the next binning.
+__device__ inline void step_housekeeping(const StepArgs &a) {
+    const bool rb = rebuild_due(a.st.ctl, a.step, a.forced, a.dyn.thr2);
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.st.rebuilt[a.slot] = rb ? 1 : 0;
+    if (rb) {
+        const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
+        for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < a.box.ncell; c += nthr)
+            a.st.cell_count[c] = 0;
+    }
+}
+
+// Double-single wrap into [0, L) with image bookkeeping.
+__device__ inline void wrap_ds(dsf &x, float Lhi, float Llo, int &im) {
+    if (x.hi < 0.0f || (x.hi == 0.0f && x.lo < 0.0f)) {
+        x = ds_add(x, dsf{Lhi, Llo});
+        im -= 1;
+    } else if (x.hi > Lhi || (x.hi == Lhi && x.lo >= Llo)) {
+        x = ds_add(x, dsf{-Lhi, -Llo});
+        im += 1;
+    }
+}
+
+// ---------------------------------------------------------------- FP32 ---
+template <int NS, int LANES>
+__global__ __launch_bounds__(kBlock) void k_step_ds(StepArgs a) {
+    constexpr int P = kWave / LANES;
+    constexpr int WPB = kBlock / kWave;
+    const State &st = a.st;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t chunk = (int64_t)blk * WPB + wv;
+    const int l = lane % LANES;
+    const int64_t i = chunk * P + lane / LANES;
+    const bool valid = i < a.g.n;
+    step_housekeeping(a);
+
+    const int4 *__restrict__ rec = st.recq[a.cur];
+    int4 ri = valid ? rec[i] : make_int4(0, 0, 0, 0);
+    int cnt = valid ? st.nbr_cnt[i] : 0;
+    cnt = cnt < a.g.cap ? cnt : a.g.cap;
+    const int32_t *__restrict__ nb = st.nbr + chunk * (int64_t)(P * a.g.cap) + lane;
+    const int iters = cnt > l ? (cnt - l + LANES - 1) / LANES : 0;
+    const float qsx = a.box.qs_hi[0], qsy = a.box.qs_hi[1], qsz = a.box.qs_hi[2];
+    const float qlx = a.box.qs_lo[0], qly = a.box.qs_lo[1], qlz = a.box.qs_lo[2];
+    float fx = 0.f, fy = 0.f, fz = 0.f, e = 0.f, w = 0.f;
+    for (int m = 0; m < iters; ++m) {
+        const int j = nb[(int64_t)m * kWave];
+        const int4 rj = rec[j];
+        const float dx = disp_q((uint32_t)ri.x, (uint32_t)rj.x, qsx, qlx);
+        const float dy = disp_q((uint32_t)ri.y, (uint32_t)rj.y, qsy, qly);
+        const float dz = disp_q((uint32_t)ri.z, (uint32_t)rj.z, qsz, qlz);
+        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        const int t = NS == 1 ? 0 : ri.w + rj.w;
+        if (r2 < by_t<NS>(t, a.pc.rc2f)) {
+            const float ir2 = __builtin_amdgcn_rcpf(r2);
+            const float s2 = by_t<NS>(t, a.pc.sig2f) * ir2;
+            const float s6 = s2 * s2 * s2;
+            const float fs = by_t<NS>(t, a.pc.eps24f) * s6 * fmaf(2.0f, s6, -1.0f) * ir2;
+            fx = fmaf(fs, dx, fx);
+            fy = fmaf(fs, dy, fy);
+            fz = fmaf(fs, dz, fz);
+            e += fmaf(by_t<NS>(t, a.pc.eps4f) * s6, s6 - 1.0f, -by_t<NS>(t, a.pc.shiftf));
+            w = fmaf(fs, r2, w);
+        }
+    }
+    if constexpr (LANES > 1) {
+#pragma unroll
+        for (int o = LANES / 2; o > 0; o >>= 1) {
+            fx += __shfl_xor(fx, o);
+            fy += __shfl_xor(fy, o);
+            fz += __shfl_xor(fz, o);
+            e += __shfl_xor(e, o);
+            w += __shfl_xor(w, o);
+        }
+    }
+    double pu = 0.0, pw = 0.0, pk = 0.0, ppx = 0.0, ppy = 0.0, ppz = 0.0;
+    uint32_t dm = 0u;
+    if (valid && l == 0) {
+        const int si = ri.w;
+        const float chi = by_s(si, a.dyn.hdt_m_hi), clo = by_s(si, a.dyn.hdt_m_lo);
+        const float mass = by_s(si, a.dyn.massf);
+        const float4 vh = st.vel_hi[i], vl = st.vel_lo[i];
+        dsf vx{vh.x, vl.x}, vy{vh.y, vl.y}, vz{vh.z, vl.z};
+        if (a.mode & kFinalize) {
+            vx = ds_add(vx, ds_mul_f(chi, clo, fx));
+            vy = ds_add(vy, ds_mul_f(chi, clo, fy));
+            vz = ds_add(vz, ds_mul_f(chi, clo, fz));
+        }
+        const float ux = vx.hi + vx.lo, uy = vy.hi + vy.lo, uz = vz.hi + vz.lo;
+        pk = 0.5 * (double)(mass * fmaf(uz, uz, fmaf(uy, uy, ux * ux)));
+        ppx = (double)(mass * ux);
+        ppy = (double)(mass * uy);
+        ppz = (double)(mass * uz);
+        pu = 0.5 * (double)e;
+        pw = 0.5 * (double)w;
+        if (a.mode & kIntegrate) {
+            vx = ds_add(vx, ds_mul_f(chi, clo, fx));
+            vy = ds_add(vy, ds_mul_f(chi, clo, fy));
+            vz = ds_add(vz, ds_mul_f(chi, clo, fz));
+            const float4 ph = st.pos_hi[i], pl = st.pos_lo[i];
+            dsf x{ph.x, pl.x}, y{ph.y, pl.y}, z{ph.z, pl.z};
+            x = ds_add(x, ds_mul(vx, a.dyn.dt_hi, a.dyn.dt_lo));
+            y = ds_add(y, ds_mul(vy, a.dyn.dt_hi, a.dyn.dt_lo));
+            z = ds_add(z, ds_mul(vz, a.dyn.dt_hi, a.dyn.dt_lo));
+            int ix = 0, iy = 0, iz = 0;
+            wrap_ds(x, a.box.Lhi[0], a.box.Llo[0], ix);
+            wrap_ds(y, a.box.Lhi[1], a.box.Llo[1], iy);
+            wrap_ds(z, a.box.Lhi[2], a.box.Llo[2], iz);
+            if (ix | iy | iz) {
+                int4 im = st.img[i];
+                st.img[i] = make_int4(im.x + ix, im.y + iy, im.z + iz, 0);
+            }
+            const uint32_t qx = q_from_ds(x.hi, x.lo, a.box.S_hi[0], a.box.S_lo[0]);
+            const uint32_t qy = q_from_ds(y.hi, y.lo, a.box.S_hi[1], a.box.S_lo[1]);
+            const uint32_t qz = q_from_ds(z.hi, z.lo, a.box.S_hi[2], a.box.S_lo[2]);
+            st.recq[a.cur ^ 1][i] = make_int4((int)qx, (int)qy, (int)qz, si);
+            st.pos_hi[i] = make_float4(x.hi, y.hi, z.hi, 0.f);
+            st.pos_lo[i] = make_float4(x.lo, y.lo, z.lo, 0.f);
+            const int4 xr = st.xref[i];
+            const float ddx = disp_q(qx, (uint32_t)xr.x, qsx, qlx);
+            const float ddy = disp_q(qy, (uint32_t)xr.y, qsy, qly);
+            const float ddz = disp_q(qz, (uint32_t)xr.z, qsz, qlz);
+            const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
+            dm = d2 == d2 ? __float_as_uint(d2) : 0x7fc00000u;
+        }
+        st.vel_hi[i] = make_float4(vx.hi, vy.hi, vz.hi, 0.f);
+        st.vel_lo[i] = make_float4(vx.lo, vy.lo, vz.lo, 0.f);
+        if (a.mode & kStoreForce) st.frc32[i] = make_float4(fx, fy, fz, 0.f);
+    }
+    block_finish(a, blk, pu, pw, pk, ppx, ppy, ppz, dm);
+}
+
+// ---------------------------------------------------------------- FP64 ---
+template <int NS, int LANES>
+__global__ __launch_bounds__(kBlock) void k_step_fp64(StepArgs a) {
+    constexpr int P = kWave / LANES;
+    constexpr int WPB = kBlock / kWave;
+    const State &st = a.st;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t chunk = (int64_t)blk * WPB + wv;
+    const int l = lane % LANES;
+    const int64_t i = chunk * P + lane / LANES;
+    const bool valid = i < a.g.n;
+    step_housekeeping(a);
+
+    const double4 *__restrict__ rec = st.rec64[a.cur];
+    double4 ri = valid ? rec[i] : make_double4(0, 0, 0, 0);
+    const int si = (int)ri.w;
+    int cnt = valid ? st.nbr_cnt[i] : 0;
+    cnt = cnt < a.g.cap ? cnt : a.g.cap;
+    const int32_t *__restrict__ nb = st.nbr + chunk * (int64_t)(P * a.g.cap) + lane;
+    const int iters = cnt > l ? (cnt - l + LANES - 1) / LANES : 0;
+    double fx = 0, fy = 0, fz = 0, e = 0, w = 0;
+    for (int m = 0; m < iters; ++m) {
+        const int j = nb[(int64_t)m * kWave];
+        const double4 rj = rec[j];
+        const double dx = disp_d(ri.x, rj.x, a.box.L[0], a.box.invL[0]);
+        const double dy = disp_d(ri.y, rj.y, a.box.L[1], a.box.invL[1]);
+        const double dz = disp_d(ri.z, rj.z, a.box.L[2], a.box.invL[2]);
+        const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+        const int t = NS == 1 ? 0 : si + (int)rj.w;
+        if (r2 < by_t<NS>(t, a.pc.rc2)) {
+            const double ir2 = 1.0 / r2;
+            const double s2 = by_t<NS>(t, a.pc.sig2) * ir2;
+            const double s6 = s2 * s2 * s2;
+            const double fs = by_t<NS>(t, a.pc.eps24) * s6 * fma(2.0, s6, -1.0) * ir2;
+            fx = fma(fs, dx, fx);
+            fy = fma(fs, dy, fy);
+            fz = fma(fs, dz, fz);
+            e += fma(by_t<NS>(t, a.pc.eps4) * s6, s6 - 1.0, -by_t<NS>(t, a.pc.shift));
+            w = fma(fs, r2, w);
+        }
+    }
+    if constexpr (LANES > 1) {
+#pragma unroll
+        for (int o = LANES / 2; o > 0; o >>= 1) {
+            fx += __shfl_xor(fx, o);
+            fy += __shfl_xor(fy, o);
+            fz += __shfl_xor(fz, o);
+            e += __shfl_xor(e, o);
+            w += __shfl_xor(w, o);
+        }
+    }
+    double pu = 0.0, pw = 0.0, pk = 0.0, ppx = 0.0, ppy = 0.0, ppz = 0.0;
+    uint32_t dm = 0u;
+    if (valid && l == 0) {
+        const double c = by_s(si, a.dyn.hdt_m);
+        const double mass = by_s(si, a.dyn.mass);
+        double4 v = st.vel64[i];
+        if (a.mode & kFinalize) {
+            v.x += c * fx;
+            v.y += c * fy;
+            v.z += c * fz;
+        }
+        pk = 0.5 * mass * fma(v.z, v.z, fma(v.y, v.y, v.x * v.x));
+        ppx = mass * v.x;
+        ppy = mass * v.y;
+        ppz = mass * v.z;
+        pu = 0.5 * e;
+        pw = 0.5 * w;
+        if (a.mode & kIntegrate) {
+            v.x += c * fx;
+            v.y += c * fy;
+            v.z += c * fz;
+            double x[3] = {ri.x + a.dyn.dt * v.x, ri.y + a.dyn.dt * v.y, ri.z + a.dyn.dt * v.z};
+            int d[3] = {0, 0, 0};
+            for (int k = 0; k < 3; ++k) {
+                if (x[k] < 0.0) {
+                    x[k] += a.box.L[k];
+                    d[k] = -1;
+                } else if (x[k] >= a.box.L[k]) {
+                    x[k] -= a.box.L[k];
+                    d[k] = 1;
+                }
+                if (x[k] >= a.box.L[k]) x[k] -= a.box.L[k];
+            }
+            if (d[0] | d[1] | d[2]) {
+                int4 im = st.img[i];
+                st.img[i] = make_int4(im.x + d[0], im.y + d[1], im.z + d[2], 0);
+            }
+            st.rec64[a.cur ^ 1][i] = make_double4(x[0], x[1], x[2], ri.w);
+            const int4 xr = st.xref[i];
+            const float ddx = disp_q(q_from_d(x[0], a.box.S[0]), (uint32_t)xr.x, a.box.qs_hi[0], a.box.qs_lo[0]);
+            const float ddy = disp_q(q_from_d(x[1], a.box.S[1]), (uint32_t)xr.y, a.box.qs_hi[1], a.box.qs_lo[1]);
+            const float ddz = disp_q(q_from_d(x[2], a.box.S[2]), (uint32_t)xr.z, a.box.qs_hi[2], a.box.qs_lo[2]);
+            const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
+            dm = (d2 == d2 && x[0] == x[0] && x[1] == x[1] && x[2] == x[2]) ? __float_as_uint(d2)
+                                                                          : 0x7fc00000u;
+        }
+        st.vel64[i] = v;
+        if (a.mode & kStoreForce) st.frc64[i] = make_double4(fx, fy, fz, 0.0);
+    }
+    block_finish(a, blk, pu, pw, pk, ppx, ppy, ppz, dm);
+}
+
+// Start of a run: "integrate" from the stored forces of the current step.
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_integrate(StepArgs a) {
+    const State &st = a.st;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    uint32_t dm = 0u;
+    if (i < a.g.n) {
+        if constexpr (PREC == LJMD_FP64) {
+            const double4 r = st.rec64[a.cur][i];
+            const int si = (int)r.w;
+            const double c = by_s(si, a.dyn.hdt_m);
+            const double4 f = st.frc64[i];
+            double4 v = st.vel64[i];
+            v.x += c * f.x;
+            v.y += c * f.y;
+            v.z += c * f.z;
+            double x[3] = {r.x + a.dyn.dt * v.x, r.y + a.dyn.dt * v.y, r.z + a.dyn.dt * v.z};
+            int d[3] = {0, 0, 0};
+            for (int k = 0; k < 3; ++k) {
+                if (x[k] < 0.0) {
+                    x[k] += a.box.L[k];
+                    d[k] = -1;
+                } else if (x[k] >= a.box.L[k]) {
+                    x[k] -= a.box.L[k];
+                    d[k] = 1;
+                }
+                if (x[k] >= a.box.L[k]) x[k] -= a.box.L[k];
+            }
+            if (d[0] | d[1] | d[2]) {
+                int4 im = st.img[i];
+                st.img[i] = make_int4(im.x + d[0], im.y + d[1], im.z + d[2], 0);
+            }
+            st.rec64[a.cur ^ 1][i] = make_double4(x[0], x[1], x[2], r.w);
+            st.vel64[i] = v;
+            const int4 xr = st.xref[i];
+            const float ddx = disp_q(q_from_d(x[0], a.box.S[0]), (uint32_t)xr.x, a.box.qs_hi[0], a.box.qs_lo[0]);
+            const float ddy = disp_q(q_from_d(x[1], a.box.S[1]), (uint32_t)xr.y, a.box.qs_hi[1], a.box.qs_lo[1]);
+            const float ddz = disp_q(q_from_d(x[2], a.box.S[2]), (uint32_t)xr.z, a.box.qs_hi[2], a.box.qs_lo[2]);
+            const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
+            dm = d2 == d2 ? __float_as_uint(d2) : 0x7fc00000u;
+        } else {
+            const int4 r = st.recq[a.cur][i];
+            const int si = r.w;
+            const float chi = by_s(si, a.dyn.hdt_m_hi), clo = by_s(si, a.dyn.hdt_m_lo);
+            const float4 f = st.frc32[i];
+            const float4 vh = st.vel_hi[i], vl = st.vel_lo[i];
+            dsf vx{vh.x, vl.x}, vy{vh.y, vl.y}, vz{vh.z, vl.z};
+            vx = ds_add(vx, ds_mul_f(chi, clo, f.x));
+            vy = ds_add(vy, ds_mul_f(chi, clo, f.y));
+            vz = ds_add(vz, ds_mul_f(chi, clo, f.z));
+            const float4 ph = st.pos_hi[i], pl = st.pos_lo[i];
+            dsf x{ph.x, pl.x}, y{ph.y, pl.y}, z{ph.z, pl.z};
+            x = ds_add(x, ds_mul(vx, a.dyn.dt_hi, a.dyn.dt_lo));
+            y = ds_add(y, ds_mul(vy, a.dyn.dt_hi, a.dyn.dt_lo));
+            z = ds_add(z, ds_mul(vz, a.dyn.dt_hi, a.dyn.dt_lo));
+            int ix = 0, iy = 0, iz = 0;
+            wrap_ds(x, a.box.Lhi[0], a.box.Llo[0], ix);
+            wrap_ds(y, a.box.Lhi[1], a.box.Llo[1], iy);
+            wrap_ds(z, a.box.Lhi[2], a.box.Llo[2], iz);
+            if (ix | iy | iz) {
+                int4 im = st.img[i];
+                st.img[i] = make_int4(im.x + ix, im.y + iy, im.z + iz, 0);
+            }
+            const uint32_t qx = q_from_ds(x.hi, x.lo, a.box.S_hi[0], a.box.S_lo[0]);
+            const uint32_t qy = q_from_ds(y.hi, y.lo, a.box.S_hi[1], a.box.S_lo[1]);
+            const uint32_t qz = q_from_ds(z.hi, z.lo, a.box.S_hi[2], a.box.S_lo[2]);
+            st.recq[a.cur ^ 1][i] = make_int4((int)qx, (int)qy, (int)qz, si);
+            st.pos_hi[i] = make_float4(x.hi, y.hi, z.hi, 0.f);
+            st.pos_lo[i] = make_float4(x.lo, y.lo, z.lo, 0.f);
+            st.vel_hi[i] = make_float4(vx.hi, vy.hi, vz.hi, 0.f);
+            st.vel_lo[i] = make_float4(vx.lo, vy.lo, vz.lo, 0.f);
+            const int4 xr = st.xref[i];
+            const float ddx = disp_q(qx, (uint32_t)xr.x, a.box.qs_hi[0], a.box.qs_lo[0]);
+            const float ddy = disp_q(qy, (uint32_t)xr.y, a.box.qs_hi[1], a.box.qs_lo[1]);
+            const float ddz = disp_q(qz, (uint32_t)xr.z, a.box.qs_hi[2], a.box.qs_lo[2]);
+            const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
+            dm = d2 == d2 ? __float_as_uint(d2) : 0x7fc00000u;
+        }
+    }
+    dm = wave_max_u(dm);
+    if ((threadIdx.x & 63) == 0 && dm > 0u) {
+        atomicMax(&st.ctl->maxd[(a.step + 1) & 1], dm);
+        if (dm > 0x7f800000u) atomicOr(&st.ctl->flags, kErrNaN);
+    }
+}
+
+// ------------------------------------------------------------------------
+int step_blocks(const Geom &g) {
+    const int per_block = (kBlock / kWave) * (kWave / g.lanes);
+    return (int)((g.n + per_block - 1) / per_block);
+}
+
+static StepArgs make_args(const Launch &L, int64_t step, int forced, int mode, int slot) {
+    StepArgs a;
+    a.st = *L.st;
+    a.g = *L.g;
+    a.box = *L.box;
+    a.pc = *L.pc;
+    a.dyn = *L.dyn;
+    a.cur = L.cur;
+    a.forced = forced;
+    a.mode = mode;
+    a.slot = slot;
+    a.step = step;
+    return a;
+}
+
+hipError_t launch_step(const Launch &L, int64_t step, int forced, int mode, int slot) {
+    StepArgs a = make_args(L, step, forced, mode, slot);
+    dim3 grid(step_blocks(*L.g)), block(kBlock);
+    const bool ds = L.g->prec == LJMD_FP32_DS;
+    const bool two = L.g->nspecies == 2;
+#define STEP(NS, LN)                                                                     \
+    do {                                                                                 \
+        if (ds)                                                                          \
+            hipLaunchKernelGGL((k_step_ds<NS, LN>), grid, block, 0, L.stream, a);        \
+        else                                                                             \
+            hipLaunchKernelGGL((k_step_fp64<NS, LN>), grid, block, 0, L.stream, a);      \
+    } while (0)
+#define BY_LANES(NS)                          \
+    switch (L.g->lanes) {                     \
+        case 1: STEP(NS, 1); break;           \
+        case 2: STEP(NS, 2); break;           \
+        case 4: STEP(NS, 4); break;           \
+        case 8: STEP(NS, 8); break;           \
+        default: STEP(NS, 16); break;         \
+    }
+    if (two) {
+        BY_LANES(2);
+    } else {
+        BY_LANES(1);
+    }
+#undef BY_LANES
+#undef STEP
+    return hipGetLastError();
+}
+
+hipError_t launch_integrate(const Launch &L, int64_t step) {
+    StepArgs a = make_args(L, step, 0, kIntegrate, 0);
+    dim3 grid((unsigned)((L.g->n + kBlock - 1) / kBlock)), block(kBlock);
+    if (L.g->prec == LJMD_FP64)
+        hipLaunchKernelGGL(k_integrate<LJMD_FP64>, grid, block, 0, L.stream, a);
+    else
+        hipLaunchKernelGGL(k_integrate<LJMD_FP32_DS>, grid, block, 0, L.stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace ljmd

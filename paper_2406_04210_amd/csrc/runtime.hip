@@ -1,0 +1,661 @@
+// runtime.hip -- host side of the C ABI declared in include/ljmd.h:
+// parameter validation, workspace planning, the Hilbert cell order, context
+// lifetime and the per-step launch sequence (paper Sec. 3 Fig. 1: integrate,
+// force, finalize, sample; list updates as particles move, Sec. 5).
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace ljmd {
+size_t resort_scratch_bytes(int64_t npad, int prec);
+}
+
+using namespace ljmd;
+
+struct ljmd_ctx {
+    ljmd_params p;
+    Geom g;
+    BoxC box;
+    PairC pc;
+    DynC dyn;
+    State st;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int cur = 0;
+    int64_t step = 0;
+    bool have_state = false;
+    int nblocks = 0;
+    std::string err;
+    // Kernel timing (ljmd_set_profiling): event pairs per family, resolved lazily.
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::pair<int, size_t>> ev_marks;  // (family, index of start event)
+    double ms[LJMD_NKT] = {0, 0, 0, 0};
+    int64_t count[LJMD_NKT] = {0, 0, 0, 0};
+    ~ljmd_ctx() {
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    }
+};
+
+static thread_local std::string g_create_err;
+
+namespace {
+
+constexpr double kTwo32 = 4294967296.0;
+
+int fail(ljmd_ctx *c, int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(ljmd_ctx *c, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c)
+        c->err = buf;
+    else
+        g_create_err = buf;
+    return code;
+}
+
+int hip_fail(ljmd_ctx *c, hipError_t e, const char *what) {
+    return fail(c, LJMD_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool used_pair(const ljmd_params *p, int ab) { return p->nspecies == 2 || ab == 0; }
+
+double list_radius_max(const ljmd_params *p) {
+    double r = 0.0;
+    for (int ab = 0; ab < 4; ++ab)
+        if (used_pair(p, ab)) r = std::max(r, p->rcut[ab] + p->skin);
+    return r;
+}
+
+int validate(const ljmd_params *p, std::string *why) {
+    auto bad = [&](const char *m) {
+        if (why) *why = m;
+        return LJMD_EINVAL;
+    };
+    if (!p) return bad("params is NULL");
+    if (p->n < 2 || p->n > (int64_t)INT32_MAX - 1024) return bad("n must be in [2, 2^31 - 1024)");
+    for (int k = 0; k < 3; ++k)
+        if (!(p->box[k] > 0.0) || !std::isfinite(p->box[k])) return bad("box edges must be finite and > 0");
+    if (p->nspecies != 1 && p->nspecies != 2) return bad("nspecies must be 1 or 2");
+    for (int ab = 0; ab < 4; ++ab) {
+        if (!used_pair(p, ab)) continue;
+        if (!(p->eps[ab] >= 0.0) || !std::isfinite(p->eps[ab])) return bad("eps must be finite and >= 0");
+        if (!(p->sigma[ab] > 0.0) || !std::isfinite(p->sigma[ab])) return bad("sigma must be finite and > 0");
+        if (!(p->rcut[ab] > 0.0) || !std::isfinite(p->rcut[ab])) return bad("rcut must be finite and > 0");
+    }
+    if (p->nspecies == 2 &&
+        (p->eps[1] != p->eps[2] || p->sigma[1] != p->sigma[2] || p->rcut[1] != p->rcut[2]))
+        return bad("pair tables must be symmetric ([1] == [2])");
+    for (int s = 0; s < p->nspecies; ++s)
+        if (!(p->mass[s] > 0.0) || !std::isfinite(p->mass[s])) return bad("masses must be finite and > 0");
+    if (!(p->skin >= 0.0) || !std::isfinite(p->skin)) return bad("skin must be finite and >= 0");
+    if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return bad("dt must be finite and > 0");
+    if (p->sort_interval < 0) return bad("sort_interval must be >= 0");
+    if (p->precision != LJMD_FP64 && p->precision != LJMD_FP32_DS) return bad("unknown precision");
+    if (p->nbr_capacity < 0 || p->nbr_capacity > 4096) return bad("nbr_capacity must be in [0, 4096]");
+    if (p->cell_capacity < 0 || p->cell_capacity > 1024) return bad("cell_capacity must be in [0, 1024]");
+    if (p->lanes != 0 && p->lanes != 1 && p->lanes != 2 && p->lanes != 4 && p->lanes != 8 && p->lanes != 16)
+        return bad("lanes must be 0, 1, 2, 4, 8 or 16");
+    if (p->reserved != 0) return bad("reserved must be 0");
+    const double rl = list_radius_max(p);
+    for (int k = 0; k < 3; ++k)
+        if (p->box[k] < 2.0 * rl) {
+            if (why) *why = "box edge < 2 * (rcut + skin): minimum image would be ambiguous";
+            return LJMD_EBOX;
+        }
+    return LJMD_OK;
+}
+
+void grid_dims(const ljmd_params *p, int nc[3]) {
+    const double rl = list_radius_max(p);
+    for (int k = 0; k < 3; ++k) {
+        double f = std::floor(p->box[k] / (rl * (1.0 + 1e-6)));
+        nc[k] = (int)std::max(1.0, std::min(f, 1024.0));
+    }
+}
+
+struct Plan {
+    int64_t npad;
+    int32_t cap, cell_cap, lanes;
+    int nc[3];
+    int ncell;
+    int max_blocks;
+    // byte offsets
+    size_t off_rec[2], off_vel, off_frc, off_pos_hi, off_pos_lo, off_vel_lo, off_img, off_id,
+        off_xref, off_nbr, off_cnt, off_ccount, off_cmem, off_cstart, off_rank, off_scratch,
+        off_part, off_rebuilt, off_ctl;
+    size_t total;
+};
+
+inline size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
+
+int32_t round_up(int32_t v, int32_t m) { return (v + m - 1) / m * m; }
+
+Plan make_plan(const ljmd_params *p) {
+    Plan pl{};
+    pl.npad = (p->n + 63) / 64 * 64;
+    grid_dims(p, pl.nc);
+    pl.ncell = pl.nc[0] * pl.nc[1] * pl.nc[2];
+    const double vol = p->box[0] * p->box[1] * p->box[2];
+    const double rho = (double)p->n / vol;
+    const double rl = list_radius_max(p);
+    const double nl = 4.0 / 3.0 * M_PI * rl * rl * rl * rho;
+    int32_t cap = p->nbr_capacity;
+    if (cap == 0) {
+        double c = std::max(1.5 * nl, nl + 40.0);
+        cap = (int32_t)std::min<double>(c, 4096.0);
+        cap = std::min<int64_t>(cap, p->n);
+    }
+    pl.cap = std::max<int32_t>(16, round_up(cap, 16));
+    int32_t cc = p->cell_capacity;
+    if (cc == 0) {
+        double cellv = vol / pl.ncell;
+        double mean = rho * cellv;
+        cc = (int32_t)std::min<double>(2.0 * mean + 32.0, 1024.0);
+        cc = (int32_t)std::min<int64_t>(cc, p->n);
+    }
+    pl.cell_cap = std::max<int32_t>(8, round_up(cc, 8));
+    if (pl.cell_cap > 1024) pl.cell_cap = 1024;
+    pl.lanes = p->lanes == 0 ? 1 : p->lanes;
+    const int per_block = (kBlock / kWave) * (kWave / pl.lanes);
+    pl.max_blocks = (int)((p->n + per_block - 1) / per_block);
+
+    const int64_t N = pl.npad;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += al(bytes);
+        return o;
+    };
+    if (p->precision == LJMD_FP64) {
+        pl.off_rec[0] = take(sizeof(double4) * N);
+        pl.off_rec[1] = take(sizeof(double4) * N);
+        pl.off_vel = take(sizeof(double4) * N);
+        pl.off_frc = take(sizeof(double4) * N);
+    } else {
+        pl.off_rec[0] = take(sizeof(int4) * N);
+        pl.off_rec[1] = take(sizeof(int4) * N);
+        pl.off_pos_hi = take(sizeof(float4) * N);
+        pl.off_pos_lo = take(sizeof(float4) * N);
+        pl.off_vel = take(sizeof(float4) * N);
+        pl.off_vel_lo = take(sizeof(float4) * N);
+        pl.off_frc = take(sizeof(float4) * N);
+    }
+    pl.off_img = take(sizeof(int4) * N);
+    pl.off_id = take(sizeof(int32_t) * N);
+    pl.off_xref = take(sizeof(int4) * N);
+    pl.off_cnt = take(sizeof(int32_t) * N);
+    pl.off_nbr = take(sizeof(int32_t) * (size_t)N * pl.cap);
+    pl.off_ccount = take(sizeof(int32_t) * pl.ncell);
+    pl.off_cmem = take(sizeof(int32_t) * (size_t)pl.ncell * pl.cell_cap);
+    pl.off_cstart = take(sizeof(int32_t) * (pl.ncell + 1));
+    pl.off_rank = take(sizeof(int32_t) * pl.ncell);
+    pl.off_scratch = take(resort_scratch_bytes(N, p->precision));
+    pl.off_part = take(sizeof(double) * (size_t)kRing * pl.max_blocks * kNP);
+    pl.off_rebuilt = take(sizeof(int32_t) * kRing);
+    pl.off_ctl = take(sizeof(Ctl));
+    pl.total = off;
+    return pl;
+}
+
+// Skilling's transform from axes to the transposed Hilbert index (AIP Conf.
+// Proc. 707, 381 (2004)), then bit interleaving to a scalar index.
+uint64_t hilbert_index3(uint32_t x, uint32_t y, uint32_t z, int bits) {
+    uint32_t X[3] = {x, y, z};
+    if (bits <= 0) return 0;
+    const uint32_t M = 1u << (bits - 1);
+    for (uint32_t Q = M; Q > 1; Q >>= 1) {
+        const uint32_t P = Q - 1;
+        for (int i = 0; i < 3; ++i) {
+            if (X[i] & Q) {
+                X[0] ^= P;
+            } else {
+                const uint32_t t = (X[0] ^ X[i]) & P;
+                X[0] ^= t;
+                X[i] ^= t;
+            }
+        }
+    }
+    for (int i = 1; i < 3; ++i) X[i] ^= X[i - 1];
+    uint32_t t = 0;
+    for (uint32_t Q = M; Q > 1; Q >>= 1)
+        if (X[2] & Q) t ^= Q - 1;
+    for (int i = 0; i < 3; ++i) X[i] ^= t;
+    uint64_t h = 0;
+    for (int b = bits - 1; b >= 0; --b)
+        for (int i = 0; i < 3; ++i) h = (h << 1) | ((X[i] >> b) & 1u);
+    return h;
+}
+
+void fill_constants(ljmd_ctx *c, const Plan &pl) {
+    const ljmd_params &p = c->p;
+    BoxC &b = c->box;
+    for (int k = 0; k < 3; ++k) {
+        const double L = p.box[k];
+        b.L[k] = L;
+        b.invL[k] = 1.0 / L;
+        b.S[k] = kTwo32 / L;
+        b.Lhi[k] = (float)L;
+        b.Llo[k] = (float)(L - (double)b.Lhi[k]);
+        const double qs = L / kTwo32;
+        b.qs_hi[k] = (float)qs;
+        b.qs_lo[k] = (float)(qs - (double)b.qs_hi[k]);
+        const double S = kTwo32 / L;
+        b.S_hi[k] = (float)S;
+        b.S_lo[k] = (float)(S - (double)b.S_hi[k]);
+        b.nc[k] = pl.nc[k];
+    }
+    b.ncell = pl.ncell;
+    PairC &q = c->pc;
+    const int src[3] = {0, 1, 3};
+    for (int t = 0; t < 3; ++t) {
+        const int ab = p.nspecies == 1 ? 0 : src[t];
+        const double rc = p.rcut[ab], rl = p.rcut[ab] + p.skin;
+        const double eps = p.eps[ab], sig = p.sigma[ab];
+        q.rc2[t] = rc * rc;
+        q.rl2[t] = rl * rl;
+        q.sig2[t] = sig * sig;
+        q.eps24[t] = 24.0 * eps;
+        q.eps4[t] = 4.0 * eps;
+        const double sr6 = std::pow(sig / rc, 6.0);
+        q.shift[t] = p.shift_energy ? 4.0 * eps * (sr6 * sr6 - sr6) : 0.0;
+        q.rc2f[t] = (float)q.rc2[t];
+        q.rl2f[t] = (float)(rl * rl);
+        q.sig2f[t] = (float)q.sig2[t];
+        q.eps24f[t] = (float)q.eps24[t];
+        q.eps4f[t] = (float)q.eps4[t];
+        q.shiftf[t] = (float)q.shift[t];
+    }
+    DynC &d = c->dyn;
+    for (int s = 0; s < 2; ++s) {
+        const double m = p.mass[p.nspecies == 2 ? s : 0];
+        d.mass[s] = m;
+        d.massf[s] = (float)m;
+        d.hdt_m[s] = 0.5 * p.dt / m;
+        d.hdt_m_hi[s] = (float)d.hdt_m[s];
+        d.hdt_m_lo[s] = (float)(d.hdt_m[s] - (double)d.hdt_m_hi[s]);
+    }
+    d.dt = p.dt;
+    d.dt_hi = (float)p.dt;
+    d.dt_lo = (float)(p.dt - (double)d.dt_hi);
+    d.thr2 = (float)(0.25 * p.skin * p.skin);
+}
+
+// Timing bracket around a group of launches of one kernel family.
+struct Bracket {
+    ljmd_ctx *c;
+    int fam;
+    size_t start = 0;
+    bool on = false;
+    Bracket(ljmd_ctx *cc, int f) : c(cc), fam(f) {
+        if (!c->profiling) return;
+        if (c->ev_used + 2 > c->ev_pool.size()) {
+            for (int k = 0; k < 64; ++k) {
+                hipEvent_t e;
+                if (hipEventCreate(&e) != hipSuccess) return;
+                c->ev_pool.push_back(e);
+            }
+        }
+        start = c->ev_used;
+        c->ev_used += 2;
+        on = hipEventRecord(c->ev_pool[start], c->stream) == hipSuccess;
+    }
+    ~Bracket() {
+        if (!on) return;
+        if (hipEventRecord(c->ev_pool[start + 1], c->stream) == hipSuccess)
+            c->ev_marks.push_back({fam, start});
+    }
+};
+
+// Resolve recorded brackets into the per-family sums (synchronises).
+int resolve_times(ljmd_ctx *c) {
+    if (c->ev_marks.empty()) return LJMD_OK;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "synchronise");
+    for (auto &m : c->ev_marks) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->ev_pool[m.second], c->ev_pool[m.second + 1]) == hipSuccess) {
+            c->ms[m.first] += ms;
+            c->count[m.first] += 1;
+        }
+    }
+    c->ev_marks.clear();
+    c->ev_used = 0;
+    return LJMD_OK;
+}
+
+Launch launcher(ljmd_ctx *c) {
+    Launch L;
+    L.st = &c->st;
+    L.g = &c->g;
+    L.box = &c->box;
+    L.pc = &c->pc;
+    L.dyn = &c->dyn;
+    L.stream = c->stream;
+    L.cur = c->cur;
+    return L;
+}
+
+// The list rebuild of one step: binning, canonical cell order, [resort],
+// list build. All kernels decide on the device whether to do anything.
+int rebuild_sequence(ljmd_ctx *c, int64_t step, int forced, bool resort) {
+    Launch L = launcher(c);
+    hipError_t e;
+    if (resort) {
+        {
+            Bracket b(c, 1);
+            if ((e = launch_bin(L, step, forced)) != hipSuccess) return hip_fail(c, e, "bin");
+            if ((e = launch_canon(L, step, forced)) != hipSuccess) return hip_fail(c, e, "canon");
+        }
+        {
+            Bracket b(c, 2);
+            if ((e = launch_resort(L)) != hipSuccess) return hip_fail(c, e, "resort");
+        }
+        Bracket b(c, 1);
+        if ((e = launch_nlist(L, step, forced)) != hipSuccess) return hip_fail(c, e, "nlist");
+        return LJMD_OK;
+    }
+    Bracket b(c, 1);
+    if ((e = launch_bin(L, step, forced)) != hipSuccess) return hip_fail(c, e, "bin");
+    if ((e = launch_canon(L, step, forced)) != hipSuccess) return hip_fail(c, e, "canon");
+    if ((e = launch_nlist(L, step, forced)) != hipSuccess) return hip_fail(c, e, "nlist");
+    return LJMD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t ljmd_abi_version(void) { return LJMD_ABI_VERSION; }
+
+int ljmd_check_params(const ljmd_params *p) { return validate(p, nullptr); }
+
+size_t ljmd_workspace_size(const ljmd_params *p) {
+    if (validate(p, nullptr) != LJMD_OK) return 0;
+    return make_plan(p).total;
+}
+
+int ljmd_cell_grid(const ljmd_params *p, int32_t ncell[3]) {
+    int r = validate(p, nullptr);
+    if (r != LJMD_OK) return r;
+    if (!ncell) return LJMD_EINVAL;
+    int nc[3];
+    grid_dims(p, nc);
+    for (int k = 0; k < 3; ++k) ncell[k] = nc[k];
+    return LJMD_OK;
+}
+
+int ljmd_hilbert_ranks(int32_t nx, int32_t ny, int32_t nz, int32_t *rank_out) {
+    if (nx < 1 || ny < 1 || nz < 1 || !rank_out) return LJMD_EINVAL;
+    if ((int64_t)nx * ny * nz > (int64_t)1 << 28) return LJMD_EINVAL;
+    int bits = 0;
+    while ((1 << bits) < std::max(nx, std::max(ny, nz))) ++bits;
+    const int64_t nc = (int64_t)nx * ny * nz;
+    std::vector<std::pair<uint64_t, int32_t>> keys;
+    try {
+        keys.resize(nc);
+    } catch (...) {
+        return LJMD_EINVAL;
+    }
+    for (int32_t x = 0; x < nx; ++x)
+        for (int32_t y = 0; y < ny; ++y)
+            for (int32_t z = 0; z < nz; ++z) {
+                const int32_t lin = (x * ny + y) * nz + z;
+                keys[lin] = {hilbert_index3(x, y, z, bits), lin};
+            }
+    std::sort(keys.begin(), keys.end());
+    for (int64_t r = 0; r < nc; ++r) rank_out[keys[r].second] = (int32_t)r;
+    return LJMD_OK;
+}
+
+int ljmd_create(const ljmd_params *p, void *ws, size_t bytes, void *stream, ljmd_ctx **out) {
+    if (!out) return fail(nullptr, LJMD_EINVAL, "out is NULL");
+    *out = nullptr;
+    std::string why;
+    int r = validate(p, &why);
+    if (r != LJMD_OK) return fail(nullptr, r, "%s", why.c_str());
+    if (!ws) return fail(nullptr, LJMD_EINVAL, "workspace is NULL");
+    if (((uintptr_t)ws & 255) != 0) return fail(nullptr, LJMD_EINVAL, "workspace must be 256-byte aligned");
+    Plan pl = make_plan(p);
+    if (bytes < pl.total)
+        return fail(nullptr, LJMD_ENOMEM, "workspace has %zu bytes, needs %zu", bytes, pl.total);
+    ljmd_ctx *c = new (std::nothrow) ljmd_ctx();
+    if (!c) return fail(nullptr, LJMD_ENOMEM, "host allocation failed");
+    c->p = *p;
+    c->stream = (hipStream_t)stream;
+    if (hipGetDevice(&c->device) != hipSuccess) c->device = -1;
+    fill_constants(c, pl);
+    Geom &g = c->g;
+    g.n = p->n;
+    g.cap = pl.cap;
+    g.cell_cap = pl.cell_cap;
+    g.lanes = pl.lanes;
+    g.nspecies = p->nspecies;
+    g.prec = p->precision;
+    g.max_blocks = pl.max_blocks;
+    c->nblocks = pl.max_blocks;
+    uint8_t *b = (uint8_t *)ws;
+    State &s = c->st;
+    std::memset(&s, 0, sizeof s);
+    if (p->precision == LJMD_FP64) {
+        s.rec64[0] = (double4 *)(b + pl.off_rec[0]);
+        s.rec64[1] = (double4 *)(b + pl.off_rec[1]);
+        s.vel64 = (double4 *)(b + pl.off_vel);
+        s.frc64 = (double4 *)(b + pl.off_frc);
+    } else {
+        s.recq[0] = (int4 *)(b + pl.off_rec[0]);
+        s.recq[1] = (int4 *)(b + pl.off_rec[1]);
+        s.pos_hi = (float4 *)(b + pl.off_pos_hi);
+        s.pos_lo = (float4 *)(b + pl.off_pos_lo);
+        s.vel_hi = (float4 *)(b + pl.off_vel);
+        s.vel_lo = (float4 *)(b + pl.off_vel_lo);
+        s.frc32 = (float4 *)(b + pl.off_frc);
+    }
+    s.img = (int4 *)(b + pl.off_img);
+    s.id = (int32_t *)(b + pl.off_id);
+    s.xref = (int4 *)(b + pl.off_xref);
+    s.nbr = (int32_t *)(b + pl.off_nbr);
+    s.nbr_cnt = (int32_t *)(b + pl.off_cnt);
+    s.cell_count = (int32_t *)(b + pl.off_ccount);
+    s.cell_members = (int32_t *)(b + pl.off_cmem);
+    s.cell_start = (int32_t *)(b + pl.off_cstart);
+    s.rank_of = (int32_t *)(b + pl.off_rank);
+    s.scratch = b + pl.off_scratch;
+    s.partials = (double *)(b + pl.off_part);
+    s.rebuilt = (int32_t *)(b + pl.off_rebuilt);
+    s.ctl = (Ctl *)(b + pl.off_ctl);
+
+    std::vector<int32_t> rank(pl.ncell);
+    ljmd_hilbert_ranks(pl.nc[0], pl.nc[1], pl.nc[2], rank.data());
+    hipError_t e = hipMemcpyAsync(s.rank_of, rank.data(), sizeof(int32_t) * pl.ncell,
+                                  hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s.cell_count, 0, sizeof(int32_t) * pl.ncell, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s.ctl, 0, sizeof(Ctl), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s.nbr_cnt, 0, sizeof(int32_t) * pl.npad, c->stream);
+    // The rank table comes from pageable host memory: finish before it goes away.
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        int rc = fail(nullptr, LJMD_EHIP, "workspace initialisation: %s", hipGetErrorString(e));
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return LJMD_OK;
+}
+
+int ljmd_destroy(ljmd_ctx *c) {
+    delete c;
+    return LJMD_OK;
+}
+
+int ljmd_set_state(ljmd_ctx *c, const double *x, const double *v, const int32_t *species) {
+    if (!c) return LJMD_EINVAL;
+    if (!x || !v || !species) return fail(c, LJMD_EINVAL, "set_state: NULL array");
+    c->cur = 0;
+    c->step = 0;
+    hipError_t e = hipMemsetAsync(c->st.ctl, 0, sizeof(Ctl), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->st.cell_count, 0, sizeof(int32_t) * c->box.ncell, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "set_state memset");
+    Launch L = launcher(c);
+    if ((e = launch_set_state(L, x, v, species)) != hipSuccess) return hip_fail(c, e, "set_state");
+    int r = rebuild_sequence(c, 0, 1, true);
+    if (r) return r;
+    L = launcher(c);
+    if ((e = launch_step(L, 0, 1, kStoreForce, 0)) != hipSuccess) return hip_fail(c, e, "force");
+    if ((e = launch_obs_reduce(L, 0, 1, c->nblocks, nullptr, 0)) != hipSuccess)
+        return hip_fail(c, e, "obs");
+    c->have_state = true;
+    return LJMD_OK;
+}
+
+int ljmd_run(ljmd_ctx *c, int64_t nsteps, double *obs_dev) {
+    if (!c) return LJMD_EINVAL;
+    if (!c->have_state) return fail(c, LJMD_ESTATE, "run before set_state");
+    if (nsteps < 0) return fail(c, LJMD_EINVAL, "nsteps < 0");
+    if (nsteps == 0) return LJMD_OK;
+    hipError_t e;
+    Launch L = launcher(c);
+    {
+        Bracket b(c, 3);
+        if ((e = launch_integrate(L, c->step)) != hipSuccess) return hip_fail(c, e, "integrate");
+    }
+    c->cur ^= 1;
+    int64_t first = c->step + 1;
+    int pending = 0;
+    int64_t row = 0;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        const int64_t s = c->step + 1 + k;
+        const bool resort = c->p.sort_interval > 0 && s % c->p.sort_interval == 0;
+        const int forced = resort ? 1 : 0;
+        int r = rebuild_sequence(c, s, forced, resort);
+        if (r) return r;
+        const bool last = k == nsteps - 1;
+        const int mode = kFinalize | (last ? kStoreForce : kIntegrate);
+        L = launcher(c);
+        {
+            Bracket b(c, 0);
+            if ((e = launch_step(L, s, forced, mode, (int)(s % kRing))) != hipSuccess)
+                return hip_fail(c, e, "step");
+        }
+        if (!last) c->cur ^= 1;
+        ++pending;
+        if (obs_dev && (pending == kRing || last)) {
+            Bracket b(c, 3);
+            if ((e = launch_obs_reduce(L, first, pending, c->nblocks, obs_dev, row)) != hipSuccess)
+                return hip_fail(c, e, "obs");
+            row += pending;
+            first += pending;
+            pending = 0;
+        }
+    }
+    if (!obs_dev) {
+        Bracket b(c, 3);
+        if ((e = launch_obs_reduce(L, c->step + nsteps, 1, c->nblocks, nullptr, 0)) != hipSuccess)
+            return hip_fail(c, e, "obs");
+    }
+    c->step += nsteps;
+    // Keep the event pool bounded on long profiled runs.
+    if (c->profiling && c->ev_used > 8192) return resolve_times(c);
+    return LJMD_OK;
+}
+
+int ljmd_set_profiling(ljmd_ctx *c, int enable) {
+    if (!c) return LJMD_EINVAL;
+    int r = resolve_times(c);
+    for (int k = 0; k < LJMD_NKT; ++k) {
+        c->ms[k] = 0.0;
+        c->count[k] = 0;
+    }
+    c->profiling = enable != 0;
+    return r;
+}
+
+int ljmd_kernel_times(ljmd_ctx *c, double ms[LJMD_NKT], int64_t count[LJMD_NKT]) {
+    if (!c || !ms || !count) return LJMD_EINVAL;
+    int r = resolve_times(c);
+    for (int k = 0; k < LJMD_NKT; ++k) {
+        ms[k] = c->ms[k];
+        count[k] = c->count[k];
+    }
+    return r;
+}
+
+int ljmd_get_state(ljmd_ctx *c, double *x, double *v, int32_t *img) {
+    if (!c) return LJMD_EINVAL;
+    if (!c->have_state) return fail(c, LJMD_ESTATE, "get_state before set_state");
+    hipError_t e = launch_get_state(launcher(c), x, v, img);
+    return e == hipSuccess ? LJMD_OK : hip_fail(c, e, "get_state");
+}
+
+int ljmd_get_forces(ljmd_ctx *c, double *f) {
+    if (!c) return LJMD_EINVAL;
+    if (!c->have_state) return fail(c, LJMD_ESTATE, "get_forces before set_state");
+    if (!f) return fail(c, LJMD_EINVAL, "get_forces: NULL array");
+    hipError_t e = launch_get_forces(launcher(c), f);
+    return e == hipSuccess ? LJMD_OK : hip_fail(c, e, "get_forces");
+}
+
+int ljmd_neighbors(ljmd_ctx *c, int32_t *cnt, int32_t *ids, int32_t cap) {
+    if (!c) return LJMD_EINVAL;
+    if (!c->have_state) return fail(c, LJMD_ESTATE, "neighbors before set_state");
+    if (!cnt || !ids || cap < 1) return fail(c, LJMD_EINVAL, "neighbors: bad arguments");
+    hipError_t e = launch_neighbors(launcher(c), cnt, ids, cap);
+    return e == hipSuccess ? LJMD_OK : hip_fail(c, e, "neighbors");
+}
+
+int ljmd_sync_status(ljmd_ctx *c) {
+    if (!c) return LJMD_EINVAL;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "synchronise");
+    uint32_t flags = 0;
+    e = hipMemcpy(&flags, &c->st.ctl->flags, sizeof flags, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(c, e, "read flags");
+    if (flags & kErrNaN) return fail(c, LJMD_ENAN, "non-finite position detected");
+    if (flags & kErrCell)
+        return fail(c, LJMD_ECELL, "a cell exceeded cell_capacity=%d", c->g.cell_cap);
+    if (flags & kErrList)
+        return fail(c, LJMD_ENLIST, "a neighbour list exceeded nbr_capacity=%d", c->g.cap);
+    return LJMD_OK;
+}
+
+int ljmd_observables(ljmd_ctx *c, ljmd_obs *out) {
+    if (!c || !out) return LJMD_EINVAL;
+    if (!c->have_state) return fail(c, LJMD_ESTATE, "observables before set_state");
+    int r = ljmd_sync_status(c);
+    Ctl h;
+    hipError_t e = hipMemcpy(&h, c->st.ctl, sizeof h, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(c, e, "read observables");
+    const double n = (double)c->p.n;
+    const double vol = c->p.box[0] * c->p.box[1] * c->p.box[2];
+    out->U = h.last[0];
+    out->K = h.last[1];
+    out->W = h.last[2];
+    out->p[0] = h.last[3];
+    out->p[1] = h.last[4];
+    out->p[2] = h.last[5];
+    out->T = 2.0 * out->K / (3.0 * n - 3.0);
+    out->P = n / vol * out->T + out->W / (3.0 * vol);
+    out->E = out->U + out->K;
+    out->step = c->step;
+    out->rebuilds = h.rebuilds;
+    out->max_fill = h.max_fill;
+    out->nbr_capacity = c->g.cap;
+    return r;
+}
+
+const char *ljmd_last_error(const ljmd_ctx *c) {
+    return c ? c->err.c_str() : g_create_err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,259 @@
+"""ctypes binding of libljmd.so, the gfx950 truncated-LJ MD library.
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels. PyTorch supplies device memory (the workspace and the I/O
+tensors) and the stream. There is no CPU fallback: importing this module
+raises if the library is missing, and creating a ``System`` raises if no
+GPU is present.
+
+Function names mirror include/ljmd.h.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libljmd.so")
+
+FP64 = 0
+FP32_DS = 1
+NOBS = 8
+OBS_FIELDS = ("U", "K", "W", "px", "py", "pz", "rebuilt", "step")
+
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EBOX", -5: "ENLIST",
+          -6: "ENAN", -7: "ESTATE", -8: "ECELL"}
+
+
+class LJMDError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ljmd {STATUS.get(code, code)} ({code}): {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("n", C.c_int64), ("box", C.c_double * 3), ("nspecies", C.c_int32),
+                ("shift_energy", C.c_int32), ("eps", C.c_double * 4), ("sigma", C.c_double * 4),
+                ("rcut", C.c_double * 4), ("mass", C.c_double * 2), ("skin", C.c_double),
+                ("dt", C.c_double), ("sort_interval", C.c_int32), ("precision", C.c_int32),
+                ("nbr_capacity", C.c_int32), ("cell_capacity", C.c_int32), ("lanes", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class Obs(C.Structure):
+    _fields_ = [("U", C.c_double), ("K", C.c_double), ("W", C.c_double), ("P", C.c_double),
+                ("T", C.c_double), ("E", C.c_double), ("p", C.c_double * 3),
+                ("step", C.c_int64), ("rebuilds", C.c_int64), ("max_fill", C.c_int32),
+                ("nbr_capacity", C.c_int32)]
+
+
+# Every exported function: name -> (restype, argtypes).
+_vp, _dp, _ip = C.c_void_p, C.c_void_p, C.c_void_p
+SIGNATURES = {
+    "ljmd_abi_version": (C.c_int32, []),
+    "ljmd_check_params": (C.c_int, [C.POINTER(Params)]),
+    "ljmd_workspace_size": (C.c_size_t, [C.POINTER(Params)]),
+    "ljmd_cell_grid": (C.c_int, [C.POINTER(Params), C.POINTER(C.c_int32)]),
+    "ljmd_hilbert_ranks": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]),
+    "ljmd_create": (C.c_int, [C.POINTER(Params), _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
+    "ljmd_destroy": (C.c_int, [_vp]),
+    "ljmd_set_state": (C.c_int, [_vp, _dp, _dp, _ip]),
+    "ljmd_get_state": (C.c_int, [_vp, _dp, _dp, _ip]),
+    "ljmd_get_forces": (C.c_int, [_vp, _dp]),
+    "ljmd_run": (C.c_int, [_vp, C.c_int64, _dp]),
+    "ljmd_neighbors": (C.c_int, [_vp, _ip, _ip, C.c_int32]),
+    "ljmd_sync_status": (C.c_int, [_vp]),
+    "ljmd_observables": (C.c_int, [_vp, C.POINTER(Obs)]),
+    "ljmd_set_profiling": (C.c_int, [_vp, C.c_int]),
+    "ljmd_kernel_times": (C.c_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "ljmd_last_error": (C.c_char_p, [_vp]),
+}
+NKT = 4
+KERNEL_FAMILIES = ("step", "rebuild", "resort", "other")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -c 'import __graft_entry__ as g; g.build()'` "
+                          "(there is no CPU fallback)")
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def last_error(ctx=None) -> str:
+    s = lib.ljmd_last_error(ctx)
+    return s.decode() if s else ""
+
+
+def _check(code: int, ctx=None):
+    if code != 0:
+        raise LJMDError(code, last_error(ctx))
+
+
+def make_params(n: int, box, p, precision: int = FP32_DS, sort_interval: int = 100,
+                nbr_capacity: int = 0, cell_capacity: int = 0, lanes: int = 0) -> Params:
+    """Build the C parameter struct from an LJParams-like object ``p``."""
+    s = Params()
+    s.n = int(n)
+    for k in range(3):
+        s.box[k] = float(box[k])
+    s.nspecies = int(p.nspecies)
+    s.shift_energy = int(p.shift_energy)
+    for k in range(4):
+        s.eps[k] = float(p.eps[k])
+        s.sigma[k] = float(p.sigma[k])
+        s.rcut[k] = float(p.rcut[k])
+    for k in range(2):
+        s.mass[k] = float(p.mass[k])
+    s.skin = float(p.skin)
+    s.dt = float(p.dt)
+    s.sort_interval = int(sort_interval)
+    s.precision = int(precision)
+    s.nbr_capacity = int(nbr_capacity)
+    s.cell_capacity = int(cell_capacity)
+    s.lanes = int(lanes)
+    s.reserved = 0
+    return s
+
+
+def check_params(params: Params) -> int:
+    return int(lib.ljmd_check_params(C.byref(params)))
+
+
+def workspace_size(params: Params) -> int:
+    return int(lib.ljmd_workspace_size(C.byref(params)))
+
+
+def cell_grid(params: Params):
+    out = (C.c_int32 * 3)()
+    _check(lib.ljmd_cell_grid(C.byref(params), out))
+    return tuple(out)
+
+
+def hilbert_ranks(nx: int, ny: int, nz: int) -> np.ndarray:
+    out = np.zeros(nx * ny * nz, dtype=np.int32)
+    _check(lib.ljmd_hilbert_ranks(nx, ny, nz, out.ctypes.data_as(C.POINTER(C.c_int32))))
+    return out
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+class System:
+    """One simulation box on the current GPU.
+
+    ``p`` is an LJParams-like object; ``precision`` is FP64 or FP32_DS. The
+    workspace is a torch uint8 tensor owned by this object; work is enqueued
+    on torch's current stream.
+    """
+
+    def __init__(self, n: int, box, p, precision: int = FP32_DS, sort_interval: int = 100,
+                 nbr_capacity: int = 0, cell_capacity: int = 0, lanes: int = 0, device=None):
+        import torch
+        self.torch = torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("ljmd.System needs a HIP GPU; none is visible")
+        self.device = torch.device(device if device is not None else "cuda")
+        self.params = make_params(n, box, p, precision, sort_interval, nbr_capacity,
+                                  cell_capacity, lanes)
+        self.n = int(n)
+        self.box = np.asarray(box, dtype=np.float64)
+        _check(check_params(self.params))
+        size = workspace_size(self.params)
+        self.workspace = torch.empty(size, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        ctx = C.c_void_p()
+        code = lib.ljmd_create(C.byref(self.params), C.c_void_p(_ptr(self.workspace)), size,
+                               C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
+        if code != 0:
+            raise LJMDError(code, last_error(None))
+        self.ctx = ctx
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib.ljmd_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self, a, dtype):
+        t = self.torch
+        if isinstance(a, np.ndarray):
+            a = t.from_numpy(np.ascontiguousarray(a))
+        return a.to(device=self.device, dtype=dtype).contiguous()
+
+    def set_state(self, x, v, species):
+        t = self.torch
+        x = self._dev(x, t.float64).reshape(self.n, 3)
+        v = self._dev(v, t.float64).reshape(self.n, 3)
+        s = self._dev(species, t.int32).reshape(self.n)
+        _check(lib.ljmd_set_state(self.ctx, _ptr(x), _ptr(v), _ptr(s)), self.ctx)
+        self._keep = (x, v, s)
+
+    def run(self, nsteps: int, observe: bool = True):
+        """Advance nsteps; returns a (nsteps, 8) float64 device tensor of
+        per-step observables (U, K, W, px, py, pz, rebuilt, step) or None."""
+        t = self.torch
+        obs = t.empty((max(nsteps, 1), NOBS), dtype=t.float64, device=self.device) if observe else None
+        _check(lib.ljmd_run(self.ctx, int(nsteps), _ptr(obs) if obs is not None else None), self.ctx)
+        return obs[:nsteps] if obs is not None else None
+
+    def get_state(self):
+        t = self.torch
+        x = t.empty((self.n, 3), dtype=t.float64, device=self.device)
+        v = t.empty_like(x)
+        img = t.empty((self.n, 3), dtype=t.int32, device=self.device)
+        _check(lib.ljmd_get_state(self.ctx, _ptr(x), _ptr(v), _ptr(img)), self.ctx)
+        return x, v, img
+
+    def unwrapped_positions(self):
+        x, _, img = self.get_state()
+        return x + img.to(x.dtype) * self.torch.as_tensor(self.box, device=self.device)
+
+    def forces(self):
+        t = self.torch
+        f = t.empty((self.n, 3), dtype=t.float64, device=self.device)
+        _check(lib.ljmd_get_forces(self.ctx, _ptr(f)), self.ctx)
+        return f
+
+    def neighbors(self, cap: int = 256):
+        t = self.torch
+        cnt = t.empty(self.n, dtype=t.int32, device=self.device)
+        ids = t.full((self.n, cap), -1, dtype=t.int32, device=self.device)
+        _check(lib.ljmd_neighbors(self.ctx, _ptr(cnt), _ptr(ids), int(cap)), self.ctx)
+        return cnt, ids
+
+    def sync(self):
+        _check(lib.ljmd_sync_status(self.ctx), self.ctx)
+
+    def set_profiling(self, enable: bool):
+        _check(lib.ljmd_set_profiling(self.ctx, int(bool(enable))), self.ctx)
+
+    def kernel_times(self) -> dict:
+        """{family: (total ms, launches)} accumulated since set_profiling(True)."""
+        ms = (C.c_double * NKT)()
+        cnt = (C.c_int64 * NKT)()
+        _check(lib.ljmd_kernel_times(self.ctx, ms, cnt), self.ctx)
+        return {KERNEL_FAMILIES[k]: (ms[k], cnt[k]) for k in range(NKT)}
+
+    def observables(self) -> dict:
+        o = Obs()
+        _check(lib.ljmd_observables(self.ctx, C.byref(o)), self.ctx)
+        return {"U": o.U, "K": o.K, "W": o.W, "P": o.P, "T": o.T, "E": o.E,
+                "p": (o.p[0], o.p[1], o.p[2]), "step": o.step, "rebuilds": o.rebuilds,
+                "max_fill": o.max_fill, "nbr_capacity": o.nbr_capacity}

@@ -1,0 +1,250 @@
+"""Parity of the HIP path with the CPU oracle, through the C ABI.
+
+Inputs come from the shared seeded generators; every expected value comes
+from the oracle. Tolerances:
+  * neighbour sets: identical (FP64 criterion in the FP64 path, the stated
+    FP32 sequence in the FP32 path, both evaluated from the same FP64 input);
+  * forces: max_i |dF_i| / rms_j |F_j| <= 1e-12 (FP64), <= 1e-5 (FP32+DS);
+  * U/N, W/N: relative 1e-12 (FP64), 1e-6 (FP32+DS);
+  * 100-step trajectories (N=2048): max |dx| <= 1e-10 sigma, |dv| <= 1e-9
+    (FP64); <= 1e-4 and <= 1e-3 (FP32+DS).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2406_04210_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = 0, 1
+TOL_F = {FP64: 1e-12, FP32: 1e-5}
+TOL_E = {FP64: 1e-12, FP32: 1e-6}
+
+
+@pytest.fixture(scope="module")
+def ljmd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_04210_amd import ljmd as L
+    return L
+
+
+def jittered_fcc(m, amp, seed, rho=0.8442):
+    x, L = W.fcc_lattice(m, rho)
+    rng = np.random.default_rng(seed)
+    x = x + amp * rng.standard_normal(x.shape)
+    return x, np.full(3, L)
+
+
+def cases():
+    """(name, x, v, species, box, params) small parity cases that span several
+    wave chunks, a ragged tail, two cells per axis and the mixture."""
+    out = []
+    w = W.config_small()
+    out.append(("fcc8_lattice_mb", w.x, w.v, w.species, w.box, w.params))
+    x, box = jittered_fcc(8, 0.1, 3)
+    out.append(("fcc8_jitter", x, w.v, w.species, box, w.params))
+    r = W.random_dense(777, 0.8442, seed=5)          # ragged: 777 = 12*64 + 9
+    out.append(("random777", r.x, r.v, r.species, r.box, r.params))
+    r = W.random_dense(256, 0.8442, seed=6)          # 2 cells per axis
+    out.append(("random256_2cells", r.x, r.v, r.species, r.box, r.params))
+    r = W.random_dense(1500, 1.1, seed=7, nspecies=2, min_dist=0.75)
+    out.append(("mixture1500", r.x, r.v, r.species, r.box, r.params))
+    return out
+
+
+CASES = cases()
+IDS = [c[0] for c in CASES]
+
+
+def rel_force_err(f, g):
+    rms = math.sqrt(float((g ** 2).sum(axis=1).mean()))
+    return float(np.abs(f - g).max()) / rms
+
+
+def make_system(ljmd, x, v, sp, box, p, prec, **kw):
+    s = ljmd.System(len(x), box, p, precision=prec, **kw)
+    s.set_state(x, v, sp)
+    return s
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_neighbor_sets_exact(ljmd, case, prec):
+    name, x, v, sp, box, p = case
+    s = make_system(ljmd, x, v, sp, box, p, prec)
+    cnt, ids = s.neighbors(cap=256)
+    s.sync()
+    cnt, ids = cnt.cpu().numpy(), ids.cpu().numpy()
+    oc, on = oracle.build_lists(x, sp, box, p, mode=0 if prec == FP64 else 1)
+    assert np.array_equal(cnt, oc)
+    for i in range(len(x)):
+        assert set(ids[i, : cnt[i]].tolist()) == set(on[i, : oc[i]].tolist()), (name, i)
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_forces_energy_virial(ljmd, case, prec):
+    name, x, v, sp, box, p = case
+    s = make_system(ljmd, x, v, sp, box, p, prec)
+    f = s.forces().cpu().numpy()
+    o = s.observables()
+    fb, Ub, Wb = oracle.forces_brute(x, sp, box, p)
+    K, mom = oracle.kinetic(v, sp, p)
+    assert rel_force_err(f, fb) <= TOL_F[prec], name
+    n = len(x)
+    assert abs(o["U"] - Ub) / n <= TOL_E[prec] * max(1.0, abs(Ub) / n)
+    assert abs(o["W"] - Wb) / n <= TOL_E[prec] * max(1.0, abs(Wb) / n)
+    assert o["K"] == pytest.approx(K, rel=1e-12 if prec == FP64 else 1e-6)
+    assert o["rebuilds"] == 1 and o["step"] == 0
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16])
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_gather_lanes_agree(ljmd, lanes, prec):
+    name, x, v, sp, box, p = CASES[4]
+    s = make_system(ljmd, x, v, sp, box, p, prec, lanes=lanes)
+    f = s.forces().cpu().numpy()
+    fb, _, _ = oracle.forces_brute(x, sp, box, p)
+    assert rel_force_err(f, fb) <= TOL_F[prec]
+
+
+def _trajectory(ljmd, w, prec, nsteps, **kw):
+    s = make_system(ljmd, w.x, w.v, w.species, w.box, w.params, prec, **kw)
+    obs = s.run(nsteps)
+    s.sync()
+    xu = s.unwrapped_positions().cpu().numpy()
+    _, v, _ = s.get_state()
+    return s, obs.cpu().numpy(), xu, v.cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_trajectory_100_steps(ljmd, prec):
+    w = W.config_small()
+    s, obs, xu, v = _trajectory(ljmd, w, prec, 100, sort_interval=25)
+    r = oracle.run_nve(w.x, w.v, w.species, w.box, w.params, 100)
+    dx = np.abs(xu - r["x"]).max()
+    dv = np.abs(v - r["v"]).max()
+    tol_x, tol_v = (1e-10, 1e-9) if prec == FP64 else (1e-4, 1e-3)
+    assert dx <= tol_x and dv <= tol_v, (dx, dv)
+    n = w.n
+    U, K = obs[:, 0], obs[:, 1]
+    ro = r["obs"][1:]
+    tol = 1e-10 if prec == FP64 else 1e-5
+    assert np.abs(U - ro[:, 0]).max() / n <= tol
+    assert np.abs(K - ro[:, 1]).max() / n <= tol
+    assert np.array_equal(obs[:, 7], np.arange(1, 101))
+    # Momentum stays zero.
+    assert np.abs(obs[:, 3:6]).max() < (1e-10 if prec == FP64 else 1e-3)
+    o = s.observables()
+    assert o["step"] == 100 and o["rebuilds"] >= 1 + int(obs[:, 6].sum()) - 4
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_split_runs_and_resort_do_not_change_results(ljmd, prec):
+    w = W.config_small()
+    s1 = make_system(ljmd, w.x, w.v, w.species, w.box, w.params, prec, sort_interval=0)
+    s1.run(60, observe=False)
+    x1 = s1.unwrapped_positions().cpu().numpy()
+    s2 = make_system(ljmd, w.x, w.v, w.species, w.box, w.params, prec, sort_interval=7)
+    for k in (1, 13, 46):
+        s2.run(k, observe=False)
+    x2 = s2.unwrapped_positions().cpu().numpy()
+    s2.sync()
+    # Same physics; only summation order may differ after a resort.
+    tol = 1e-11 if prec == FP64 else 1e-4
+    assert np.abs(x1 - x2).max() <= tol
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_bitwise_reproducible(ljmd, prec):
+    w = W.config_small()
+    res = []
+    for _ in range(2):
+        s = make_system(ljmd, w.x, w.v, w.species, w.box, w.params, prec, sort_interval=10)
+        obs = s.run(40)
+        x, v, img = s.get_state()
+        res.append((obs.cpu().numpy(), x.cpu().numpy(), v.cpu().numpy()))
+    for a, b in zip(res[0], res[1]):
+        assert np.array_equal(a, b)
+
+
+def test_free_flight_ds_matches_closed_form(ljmd):
+    # eps = 0: x_n = x_0 + n dt v exactly; double-single keeps ~48 bits.
+    w = W.config_small()
+    p = w.params.copy()
+    p.eps[:] = 0.0
+    s = make_system(ljmd, w.x, w.v, w.species, w.box, p, FP32, sort_interval=0)
+    nsteps = 20000
+    s.run(nsteps, observe=False)
+    xu = s.unwrapped_positions().cpu().numpy()
+    s.sync()
+    want = w.x + (nsteps * p.dt) * w.v
+    err_ds = np.abs(xu - want).max()
+    assert err_ds < 1e-9
+    # A plain FP32 accumulation of the same walk is far worse (negative control).
+    xf = w.x.astype(np.float32)
+    step = (np.float32(p.dt) * w.v.astype(np.float32)).astype(np.float32)
+    for _ in range(2000):
+        xf = (xf + step).astype(np.float32)
+    err_f32 = np.abs(xf - (w.x + 2000 * p.dt * w.v)).max()
+    assert err_f32 > 100 * err_ds
+
+
+def test_nbr_overflow_is_reported(ljmd):
+    w = W.config_small()
+    s = ljmd.System(w.n, w.box, w.params, precision=FP64, nbr_capacity=32)
+    s.set_state(w.x, w.v, w.species)
+    with pytest.raises(ljmd.LJMDError) as e:
+        s.sync()
+    assert e.value.code == -5
+
+
+def test_run_before_state_is_rejected(ljmd):
+    w = W.config_small()
+    s = ljmd.System(w.n, w.box, w.params, precision=FP64)
+    with pytest.raises(ljmd.LJMDError) as e:
+        s.run(1)
+    assert e.value.code == -7
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_full_size_forces_and_sampled_lists(ljmd, prec):
+    # The headline workload at full size: N = 256,000 (FCC 40^3, rho 0.8442),
+    # jittered so that forces are non-trivial.
+    w = W.config_headline()
+    x, box = jittered_fcc(40, 0.08, 17)
+    s = make_system(ljmd, x, w.v, w.species, box, w.params, prec)
+    f = s.forces().cpu().numpy()
+    o = s.observables()
+    fo, Uo, Wo = oracle.forces(x, w.species, box, w.params)
+    assert rel_force_err(f, fo) <= TOL_F[prec]
+    assert abs(o["U"] - Uo) <= TOL_E[prec] * abs(Uo)
+    assert abs(o["W"] - Wo) <= TOL_E[prec] * abs(Wo)
+    cnt, ids = s.neighbors(cap=256)
+    cnt, ids = cnt.cpu().numpy(), ids.cpu().numpy()
+    oc, on = oracle.build_lists(x, w.species, box, w.params, mode=0 if prec == FP64 else 1)
+    assert np.array_equal(cnt, oc)
+    rng = np.random.default_rng(1)
+    for i in rng.choice(len(x), 2000, replace=False):
+        assert set(ids[i, : cnt[i]].tolist()) == set(on[i, : oc[i]].tolist())
+
+
+def test_fp32_energy_conservation_tracks_fp64(ljmd):
+    w = W.config_small()
+    drifts = {}
+    for prec in (FP64, FP32):
+        s = make_system(ljmd, w.x, w.v, w.species, w.box, w.params, prec)
+        obs = s.run(1000).cpu().numpy()
+        E = (obs[:, 0] + obs[:, 1]) / w.n
+        late = E[200:]
+        drifts[prec] = (np.polyfit(np.arange(len(late)) * w.params.dt, late, 1)[0],
+                        np.abs(E - E.mean()).max())
+    slope64, fl64 = drifts[FP64]
+    slope32, fl32 = drifts[FP32]
+    assert abs(slope32) < 5e-5 and abs(slope64) < 5e-5
+    assert fl32 < 1.5 * fl64 + 1e-5
