@@ -83,6 +83,7 @@ struct State {
     int32_t *cell_members;// [ncell][cell_cap] particle slots, ascending after canonicalisation
     int32_t *cell_start;  // [ncell + 1] exclusive scan of counts (resort only)
     int32_t *rank_of;     // [ncell] Hilbert rank of the cell with linear index (ix*ny+iy)*nz+iz
+    int32_t *cell_lin;    // [ncell] linear index of the cell with a given Hilbert rank
     uint8_t *scratch;     // resort staging
     double *partials;     // [kRing][max_blocks][kNP] per-block observable partials
     int32_t *rebuilt;     // [kRing] 1 if the list was rebuilt before that step's force

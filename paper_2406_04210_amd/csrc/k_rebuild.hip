@@ -64,7 +64,7 @@ __global__ __launch_bounds__(kBlock) void k_canon(State st, Geom g, BoxC box, in
     if (c >= box.ncell) return;
     const int cnt = st.cell_count[c];
     const int m = cnt < g.cell_cap ? cnt : g.cell_cap;
-    if (lane == 0) atomicMax(&st.ctl->max_cell, cnt);
+    if (lane == 0 && cnt > *(volatile int32_t *)&st.ctl->max_cell) atomicMax(&st.ctl->max_cell, cnt);
     int32_t *src = sm + (size_t)wv * 2 * g.cell_cap;
     int32_t *dst = src + g.cell_cap;
     int32_t *mem = st.cell_members + c * g.cell_cap;
@@ -214,95 +214,179 @@ __device__ inline T by_type(int t, const T (&a)[3]) {
     }
 }
 
-// Verlet lists: particle i scans the 27 cells around its own (only the
-// distinct ones when an axis has fewer than 3 cells) in a fixed order, the
-// members of each cell in ascending slot order, and keeps every j != i with
-// r_ij^2 < (r_c + skin)^2 under the stated operation sequence of its
-// precision. Stores the list length and the fixed-point reference position
-// for the displacement check.
+// Verlet lists, one wavefront per home cell. The wave builds, in LDS, one
+// shared candidate array for its home cell: the particle slots of the (up to
+// 27 distinct) surrounding cells, cell by cell in a fixed stencil order
+// (x outer, z inner), each cell's slots sorted ascending (binning leaves them
+// in atomic order; the sort is a rank count over wave shuffles). Each home
+// particle gets G = 64/m lanes (m = home occupancy) that sweep the shared
+// array G candidates at a time, so the whole wave touches only G records per
+// iteration. Hits (j != i and r_ij^2 < (r_c + skin)^2 under the stated
+// sequence of the precision) are compacted with a ballot and written in
+// candidate order, so the list order does not depend on G and is
+// reproducible run to run. Only the index array lives in LDS (6 KB a wave),
+// which keeps many waves resident to hide the record gathers.
+constexpr int kStage = 1536;
+constexpr int kNlistWaves = 4;
+
 template <int PREC, int NS>
-__global__ __launch_bounds__(kBlock) void k_nlist(State st, Geom g, BoxC box, PairC pc, int cur,
-                                                  int64_t step, int forced, float thr2) {
+__global__ __launch_bounds__(kWave * kNlistWaves) void k_nlist_cell(
+    State st, Geom g, BoxC box, PairC pc, int cur, int64_t step, int forced, float thr2,
+    int cells_per_wave) {
     if (!rebuild_due(st.ctl, step, forced, thr2)) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) st.ctl->rebuilds += 1;
+    __shared__ int32_t sidx_all[kNlistWaves][kStage];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int32_t *sidx = sidx_all[wv];
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t i = (int64_t)blk * kBlock + threadIdx.x;
-    int k = 0;
-    if (i < g.n) {
-        uint32_t q[3];
-        int si;
-        load_q<PREC>(st, cur, i, box, q, &si);
-        double4 ri64;
-        if constexpr (PREC == LJMD_FP64) ri64 = st.rec64[cur][i];
-        int cx, cy, cz;
-        cell_of_q(q[0], q[1], q[2], box, st.rank_of, &cx, &cy, &cz);
-        int lo[3], hi[3];
-        const int cc[3] = {cx, cy, cz};
+    const int cbeg = (blk * kNlistWaves + wv) * cells_per_wave;
+    const int cend = min(cbeg + cells_per_wave, box.ncell);
+    int wave_max = 0;
+    for (int c = cbeg; c < cend; ++c) {
+        const int lin = st.cell_lin[c];
+        const int cc[3] = {lin / (box.nc[1] * box.nc[2]), (lin / box.nc[2]) % box.nc[1],
+                           lin % box.nc[2]};
+        int lo[3], n3[3];
         for (int a = 0; a < 3; ++a) {
             if (box.nc[a] >= 3) {
                 lo[a] = -1;
-                hi[a] = 1;
+                n3[a] = 3;
             } else {
                 lo[a] = -cc[a];
-                hi[a] = box.nc[a] - 1 - cc[a];
+                n3[a] = box.nc[a];
             }
         }
-        for (int ox = lo[0]; ox <= hi[0]; ++ox) {
-            int ax = cx + ox;
+        const int nst = n3[0] * n3[1] * n3[2];
+        int scell = 0, scnt = 0;
+        if (lane < nst) {
+            const int a = lane / (n3[1] * n3[2]), b = (lane / n3[2]) % n3[1], d = lane % n3[2];
+            int ax = cc[0] + lo[0] + a, ay = cc[1] + lo[1] + b, az = cc[2] + lo[2] + d;
             ax += ax < 0 ? box.nc[0] : (ax >= box.nc[0] ? -box.nc[0] : 0);
-            for (int oy = lo[1]; oy <= hi[1]; ++oy) {
-                int ay = cy + oy;
-                ay += ay < 0 ? box.nc[1] : (ay >= box.nc[1] ? -box.nc[1] : 0);
-                for (int oz = lo[2]; oz <= hi[2]; ++oz) {
-                    int az = cz + oz;
-                    az += az < 0 ? box.nc[2] : (az >= box.nc[2] ? -box.nc[2] : 0);
-                    const int c = st.rank_of[(ax * box.nc[1] + ay) * box.nc[2] + az];
-                    int m = st.cell_count[c];
-                    m = m < g.cell_cap ? m : g.cell_cap;
-                    const int32_t *mem = st.cell_members + (int64_t)c * g.cell_cap;
-                    for (int e = 0; e < m; ++e) {
-                        const int j = mem[e];
-                        if (j == (int)i) continue;
-                        bool in;
-                        if constexpr (PREC == LJMD_FP64) {
-                            const double4 rj = st.rec64[cur][j];
-                            const int t = NS == 1 ? 0 : si + (int)rj.w;
-                            double dx = disp_d(ri64.x, rj.x, box.L[0], box.invL[0]);
-                            double dy = disp_d(ri64.y, rj.y, box.L[1], box.invL[1]);
-                            double dz = disp_d(ri64.z, rj.z, box.L[2], box.invL[2]);
-                            double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-                            in = r2 < by_type<NS>(t, pc.rl2);
-                        } else {
-                            const int4 rj = st.recq[cur][j];
-                            const int t = NS == 1 ? 0 : si + rj.w;
-                            float dx = disp_q(q[0], (uint32_t)rj.x, box.qs_hi[0], box.qs_lo[0]);
-                            float dy = disp_q(q[1], (uint32_t)rj.y, box.qs_hi[1], box.qs_lo[1]);
-                            float dz = disp_q(q[2], (uint32_t)rj.z, box.qs_hi[2], box.qs_lo[2]);
-                            float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                            in = r2 < by_type<NS>(t, pc.rl2f);
-                        }
-                        if (in) {
-                            if (k < g.cap) st.nbr[nbr_index(i, k, g.lanes, g.cap)] = j;
-                            ++k;
-                        }
-                    }
+            ay += ay < 0 ? box.nc[1] : (ay >= box.nc[1] ? -box.nc[1] : 0);
+            az += az < 0 ? box.nc[2] : (az >= box.nc[2] ? -box.nc[2] : 0);
+            scell = st.rank_of[(ax * box.nc[1] + ay) * box.nc[2] + az];
+            scnt = min(st.cell_count[scell], g.cell_cap);
+        }
+        int incl = scnt;
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int y = __shfl_up(incl, o);
+            if (lane >= o) incl += y;
+        }
+        const int soff = incl - scnt;
+        const int ncand = __shfl(incl, kWave - 1);
+        const int home_s = ((-lo[0]) * n3[1] + (-lo[1])) * n3[2] + (-lo[2]);
+        const int home_off = __shfl(soff, home_s);
+        const int m = __shfl(scnt, home_s);
+        if (ncand > kStage) {
+            if (lane == 0) atomicOr(&st.ctl->flags, kErrCell);
+            continue;
+        }
+        // Stage each stencil cell's slots in ascending order.
+        for (int s = 0; s < nst; ++s) {
+            const int cs = __builtin_amdgcn_readfirstlane(__shfl(scell, s));
+            const int ms = __builtin_amdgcn_readfirstlane(__shfl(scnt, s));
+            const int os = __builtin_amdgcn_readfirstlane(__shfl(soff, s));
+            const int32_t *mem = st.cell_members + (int64_t)cs * g.cell_cap;
+            if (ms <= kWave) {
+                const int v = lane < ms ? mem[lane] : 0x7fffffff;
+                int r = 0;
+                for (int k = 0; k < ms; ++k) r += __shfl(v, k) < v ? 1 : 0;
+                if (lane < ms) sidx[os + r] = v;
+            } else {
+                for (int e = lane; e < ms; e += kWave) {
+                    const int v = mem[e];
+                    int r = 0;
+                    for (int k = 0; k < ms; ++k) r += mem[k] < v ? 1 : 0;
+                    sidx[os + r] = v;
                 }
             }
         }
-        st.nbr_cnt[i] = k;
-        st.xref[i] = make_int4((int)q[0], (int)q[1], (int)q[2], 0);
-        if (k > g.cap) atomicOr(&st.ctl->flags, kErrList);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        // Sweep: G lanes per home particle.
+        const int G = m >= kWave ? 1 : (m > 0 ? kWave / m : kWave);
+        const int P = kWave / G;
+        const int p_local = lane / G, gl = lane % G;
+        const unsigned long long gbits = G >= 64 ? ~0ull : ((1ull << G) - 1ull);
+        for (int pb = 0; pb < m; pb += P) {
+            const int p = pb + p_local;
+            const bool active = p_local < P && p < m;
+            int i = -1, si = 0;
+            uint32_t qi[3] = {0, 0, 0};
+            double xi[3] = {0, 0, 0};
+            if (active) {
+                i = sidx[home_off + p];
+                if constexpr (PREC == LJMD_FP64) {
+                    const double4 r = st.rec64[cur][i];
+                    xi[0] = r.x;
+                    xi[1] = r.y;
+                    xi[2] = r.z;
+                    si = (int)r.w;
+                } else {
+                    const int4 r = st.recq[cur][i];
+                    qi[0] = (uint32_t)r.x;
+                    qi[1] = (uint32_t)r.y;
+                    qi[2] = (uint32_t)r.z;
+                    si = r.w;
+                }
+            }
+            int k = 0;
+            for (int base = 0; base < ncand; base += G) {
+                const int t = base + gl;
+                bool in = false;
+                int j = -1;
+                if (active && t < ncand) {
+                    j = sidx[t];
+                    if (j != i) {
+                        if constexpr (PREC == LJMD_FP64) {
+                            const double4 rj = st.rec64[cur][j];
+                            const int tt = NS == 1 ? 0 : si + (int)rj.w;
+                            const double dx = disp_d(xi[0], rj.x, box.L[0], box.invL[0]);
+                            const double dy = disp_d(xi[1], rj.y, box.L[1], box.invL[1]);
+                            const double dz = disp_d(xi[2], rj.z, box.L[2], box.invL[2]);
+                            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                            in = r2 < by_type<NS>(tt, pc.rl2);
+                        } else {
+                            const int4 rj = st.recq[cur][j];
+                            const int tt = NS == 1 ? 0 : si + rj.w;
+                            const float dx = disp_q(qi[0], (uint32_t)rj.x, box.qs_hi[0], box.qs_lo[0]);
+                            const float dy = disp_q(qi[1], (uint32_t)rj.y, box.qs_hi[1], box.qs_lo[1]);
+                            const float dz = disp_q(qi[2], (uint32_t)rj.z, box.qs_hi[2], box.qs_lo[2]);
+                            const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                            in = r2 < by_type<NS>(tt, pc.rl2f);
+                        }
+                    }
+                }
+                const unsigned long long mask = __ballot(in ? 1 : 0);
+                const unsigned long long grp = (mask >> (lane - gl)) & gbits;
+                const int pos = __popcll(grp & ((1ull << gl) - 1ull));
+                if (in && k + pos < g.cap) st.nbr[nbr_index(i, k + pos, g.lanes, g.cap)] = j;
+                k += __popcll(grp);
+            }
+            if (active && gl == 0) {
+                st.nbr_cnt[i] = k;
+                if constexpr (PREC == LJMD_FP64)
+                    st.xref[i] = make_int4((int)q_from_d(xi[0], box.S[0]), (int)q_from_d(xi[1], box.S[1]),
+                                           (int)q_from_d(xi[2], box.S[2]), 0);
+                else
+                    st.xref[i] = make_int4((int)qi[0], (int)qi[1], (int)qi[2], 0);
+                if (k > g.cap) atomicOr(&st.ctl->flags, kErrList);
+            }
+            wave_max = active && k > wave_max ? k : wave_max;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
-    // One atomic per wavefront for the longest list.
-    int mk = k;
     for (int o = 32; o > 0; o >>= 1) {
-        int y = __shfl_xor(mk, o);
-        mk = y > mk ? y : mk;
+        const int y = __shfl_xor(wave_max, o);
+        wave_max = y > wave_max ? y : wave_max;
     }
-    if ((threadIdx.x & 63) == 0 && mk > 0) atomicMax(&st.ctl->max_fill, mk);
+    if (lane == 0 && wave_max > 0 && wave_max > *(volatile int32_t *)&st.ctl->max_fill)
+        atomicMax(&st.ctl->max_fill, wave_max);
 }
 
 // ------------------------------------------------------------------------
+constexpr int kNlistBlocks = 1024;
 static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 hipError_t launch_bin(const Launch &L, int64_t step, int forced) {
@@ -348,10 +432,16 @@ hipError_t launch_resort(const Launch &L) {
 }
 
 hipError_t launch_nlist(const Launch &L, int64_t step, int forced) {
-    unsigned nb = blocks_for(L.g->n, kBlock);
-#define NL(P, S)                                                                               \
-    hipLaunchKernelGGL((k_nlist<P, S>), dim3(nb), dim3(kBlock), 0, L.stream, *L.st, *L.g, *L.box, \
-                       *L.pc, L.cur, step, forced, L.dyn->thr2)
+    // Contiguous runs of Hilbert-ranked cells per wave; at most kNlistBlocks
+    // blocks so that the launch stays cheap on steps without a rebuild.
+    const int ncell = L.box->ncell;
+    const int nwaves_max = kNlistBlocks * kNlistWaves;
+    const int per = (ncell + nwaves_max - 1) / nwaves_max;
+    const int nwaves = (ncell + per - 1) / per;
+    const unsigned grid = (unsigned)((nwaves + kNlistWaves - 1) / kNlistWaves);
+#define NL(P, S)                                                                              \
+    hipLaunchKernelGGL((k_nlist_cell<P, S>), dim3(grid), dim3(kWave * kNlistWaves), 0,        \
+                       L.stream, *L.st, *L.g, *L.box, *L.pc, L.cur, step, forced, L.dyn->thr2, per)
     if (L.g->prec == LJMD_FP64) {
         if (L.g->nspecies == 1) NL(LJMD_FP64, 1); else NL(LJMD_FP64, 2);
     } else {

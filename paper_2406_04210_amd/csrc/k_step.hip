@@ -87,7 +87,9 @@ __device__ inline void block_finish(const StepArgs &a, int blk, double u, double
     if (threadIdx.x == 0 && (a.mode & kIntegrate)) {
         uint32_t m = 0;
         for (int q = 0; q < WPB; ++q) m = redm[q] > m ? redm[q] : m;
-        atomicMax(&a.st.ctl->maxd[(a.step + 1) & 1], m);
+        // Only "exceeded or not" decides the rebuild, so blocks below the
+        // threshold skip the same-address atomic entirely.
+        if (m > __float_as_uint(a.dyn.thr2)) atomicMax(&a.st.ctl->maxd[(a.step + 1) & 1], m);
         if (m > 0x7f800000u) atomicOr(&a.st.ctl->flags, kErrNaN);
     }
 }
@@ -138,24 +140,38 @@ __global__ __launch_bounds__(kBlock) void k_step_ds(StepArgs a) {
     const float qsx = a.box.qs_hi[0], qsy = a.box.qs_hi[1], qsz = a.box.qs_hi[2];
     const float qlx = a.box.qs_lo[0], qly = a.box.qs_lo[1], qlz = a.box.qs_lo[2];
     float fx = 0.f, fy = 0.f, fz = 0.f, e = 0.f, w = 0.f;
-    for (int m = 0; m < iters; ++m) {
-        const int j = nb[(int64_t)m * kWave];
-        const int4 rj = rec[j];
-        const float dx = disp_q((uint32_t)ri.x, (uint32_t)rj.x, qsx, qlx);
-        const float dy = disp_q((uint32_t)ri.y, (uint32_t)rj.y, qsy, qly);
-        const float dz = disp_q((uint32_t)ri.z, (uint32_t)rj.z, qsz, qlz);
-        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        const int t = NS == 1 ? 0 : ri.w + rj.w;
-        if (r2 < by_t<NS>(t, a.pc.rc2f)) {
-            const float ir2 = __builtin_amdgcn_rcpf(r2);
-            const float s2 = by_t<NS>(t, a.pc.sig2f) * ir2;
-            const float s6 = s2 * s2 * s2;
-            const float fs = by_t<NS>(t, a.pc.eps24f) * s6 * fmaf(2.0f, s6, -1.0f) * ir2;
-            fx = fmaf(fs, dx, fx);
-            fy = fmaf(fs, dy, fy);
-            fz = fmaf(fs, dz, fz);
-            e += fmaf(by_t<NS>(t, a.pc.eps4f) * s6, s6 - 1.0f, -by_t<NS>(t, a.pc.shiftf));
-            w = fmaf(fs, r2, w);
+    // Four list entries per trip: all index loads, then all record gathers,
+    // are in flight before the arithmetic of the first one.
+    constexpr int U = 4;
+    for (int m = 0; m < iters; m += U) {
+        // Indices past the list end are clamped to its last entry, so every
+        // load is in bounds; those entries are then skipped.
+        int jj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) jj[u] = nb[(int64_t)(m + u < iters ? m + u : iters - 1) * kWave];
+        int4 rr[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) rr[u] = rec[jj[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (m + u >= iters) continue;
+            const int4 rj = rr[u];
+            const float dx = disp_q((uint32_t)ri.x, (uint32_t)rj.x, qsx, qlx);
+            const float dy = disp_q((uint32_t)ri.y, (uint32_t)rj.y, qsy, qly);
+            const float dz = disp_q((uint32_t)ri.z, (uint32_t)rj.z, qsz, qlz);
+            const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+            const int t = NS == 1 ? 0 : ri.w + rj.w;
+            if (r2 < by_t<NS>(t, a.pc.rc2f)) {
+                const float ir2 = __builtin_amdgcn_rcpf(r2);
+                const float s2 = by_t<NS>(t, a.pc.sig2f) * ir2;
+                const float s6 = s2 * s2 * s2;
+                const float fs = by_t<NS>(t, a.pc.eps24f) * s6 * fmaf(2.0f, s6, -1.0f) * ir2;
+                fx = fmaf(fs, dx, fx);
+                fy = fmaf(fs, dy, fy);
+                fz = fmaf(fs, dz, fz);
+                e += fmaf(by_t<NS>(t, a.pc.eps4f) * s6, s6 - 1.0f, -by_t<NS>(t, a.pc.shiftf));
+                w = fmaf(fs, r2, w);
+            }
         }
     }
     if constexpr (LANES > 1) {
@@ -247,24 +263,36 @@ __global__ __launch_bounds__(kBlock) void k_step_fp64(StepArgs a) {
     const int32_t *__restrict__ nb = st.nbr + chunk * (int64_t)(P * a.g.cap) + lane;
     const int iters = cnt > l ? (cnt - l + LANES - 1) / LANES : 0;
     double fx = 0, fy = 0, fz = 0, e = 0, w = 0;
-    for (int m = 0; m < iters; ++m) {
-        const int j = nb[(int64_t)m * kWave];
-        const double4 rj = rec[j];
-        const double dx = disp_d(ri.x, rj.x, a.box.L[0], a.box.invL[0]);
-        const double dy = disp_d(ri.y, rj.y, a.box.L[1], a.box.invL[1]);
-        const double dz = disp_d(ri.z, rj.z, a.box.L[2], a.box.invL[2]);
-        const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-        const int t = NS == 1 ? 0 : si + (int)rj.w;
-        if (r2 < by_t<NS>(t, a.pc.rc2)) {
-            const double ir2 = 1.0 / r2;
-            const double s2 = by_t<NS>(t, a.pc.sig2) * ir2;
-            const double s6 = s2 * s2 * s2;
-            const double fs = by_t<NS>(t, a.pc.eps24) * s6 * fma(2.0, s6, -1.0) * ir2;
-            fx = fma(fs, dx, fx);
-            fy = fma(fs, dy, fy);
-            fz = fma(fs, dz, fz);
-            e += fma(by_t<NS>(t, a.pc.eps4) * s6, s6 - 1.0, -by_t<NS>(t, a.pc.shift));
-            w = fma(fs, r2, w);
+    constexpr int U = 4;
+    for (int m = 0; m < iters; m += U) {
+        // Indices past the list end are clamped to its last entry, so every
+        // load is in bounds; those entries are then skipped.
+        int jj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) jj[u] = nb[(int64_t)(m + u < iters ? m + u : iters - 1) * kWave];
+        double4 rr[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) rr[u] = rec[jj[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (m + u >= iters) continue;
+            const double4 rj = rr[u];
+            const double dx = disp_d(ri.x, rj.x, a.box.L[0], a.box.invL[0]);
+            const double dy = disp_d(ri.y, rj.y, a.box.L[1], a.box.invL[1]);
+            const double dz = disp_d(ri.z, rj.z, a.box.L[2], a.box.invL[2]);
+            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+            const int t = NS == 1 ? 0 : si + (int)rj.w;
+            if (r2 < by_t<NS>(t, a.pc.rc2)) {
+                const double ir2 = 1.0 / r2;
+                const double s2 = by_t<NS>(t, a.pc.sig2) * ir2;
+                const double s6 = s2 * s2 * s2;
+                const double fs = by_t<NS>(t, a.pc.eps24) * s6 * fma(2.0, s6, -1.0) * ir2;
+                fx = fma(fs, dx, fx);
+                fy = fma(fs, dy, fy);
+                fz = fma(fs, dz, fz);
+                e += fma(by_t<NS>(t, a.pc.eps4) * s6, s6 - 1.0, -by_t<NS>(t, a.pc.shift));
+                w = fma(fs, r2, w);
+            }
         }
     }
     if constexpr (LANES > 1) {
@@ -409,7 +437,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(StepArgs a) {
         }
     }
     dm = wave_max_u(dm);
-    if ((threadIdx.x & 63) == 0 && dm > 0u) {
+    if ((threadIdx.x & 63) == 0 && dm > __float_as_uint(a.dyn.thr2)) {
         atomicMax(&st.ctl->maxd[(a.step + 1) & 1], dm);
         if (dm > 0x7f800000u) atomicOr(&st.ctl->flags, kErrNaN);
     }

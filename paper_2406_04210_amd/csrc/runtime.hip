@@ -133,7 +133,7 @@ struct Plan {
     int max_blocks;
     // byte offsets
     size_t off_rec[2], off_vel, off_frc, off_pos_hi, off_pos_lo, off_vel_lo, off_img, off_id,
-        off_xref, off_nbr, off_cnt, off_ccount, off_cmem, off_cstart, off_rank, off_scratch,
+        off_xref, off_nbr, off_cnt, off_ccount, off_cmem, off_cstart, off_rank, off_lin, off_scratch,
         off_part, off_rebuilt, off_ctl;
     size_t total;
 };
@@ -201,6 +201,7 @@ Plan make_plan(const ljmd_params *p) {
     pl.off_cmem = take(sizeof(int32_t) * (size_t)pl.ncell * pl.cell_cap);
     pl.off_cstart = take(sizeof(int32_t) * (pl.ncell + 1));
     pl.off_rank = take(sizeof(int32_t) * pl.ncell);
+    pl.off_lin = take(sizeof(int32_t) * pl.ncell);
     pl.off_scratch = take(resort_scratch_bytes(N, p->precision));
     pl.off_part = take(sizeof(double) * (size_t)kRing * pl.max_blocks * kNP);
     pl.off_rebuilt = take(sizeof(int32_t) * kRing);
@@ -366,9 +367,10 @@ int rebuild_sequence(ljmd_ctx *c, int64_t step, int forced, bool resort) {
         if ((e = launch_nlist(L, step, forced)) != hipSuccess) return hip_fail(c, e, "nlist");
         return LJMD_OK;
     }
+    // Without a resort the list build sorts each cell's slots in LDS itself, so
+    // the canonical-order pass is only needed before a resort.
     Bracket b(c, 1);
     if ((e = launch_bin(L, step, forced)) != hipSuccess) return hip_fail(c, e, "bin");
-    if ((e = launch_canon(L, step, forced)) != hipSuccess) return hip_fail(c, e, "canon");
     if ((e = launch_nlist(L, step, forced)) != hipSuccess) return hip_fail(c, e, "nlist");
     return LJMD_OK;
 }
@@ -471,15 +473,20 @@ int ljmd_create(const ljmd_params *p, void *ws, size_t bytes, void *stream, ljmd
     s.cell_members = (int32_t *)(b + pl.off_cmem);
     s.cell_start = (int32_t *)(b + pl.off_cstart);
     s.rank_of = (int32_t *)(b + pl.off_rank);
+    s.cell_lin = (int32_t *)(b + pl.off_lin);
     s.scratch = b + pl.off_scratch;
     s.partials = (double *)(b + pl.off_part);
     s.rebuilt = (int32_t *)(b + pl.off_rebuilt);
     s.ctl = (Ctl *)(b + pl.off_ctl);
 
-    std::vector<int32_t> rank(pl.ncell);
+    std::vector<int32_t> rank(pl.ncell), lin(pl.ncell);
     ljmd_hilbert_ranks(pl.nc[0], pl.nc[1], pl.nc[2], rank.data());
+    for (int k = 0; k < pl.ncell; ++k) lin[rank[k]] = k;
     hipError_t e = hipMemcpyAsync(s.rank_of, rank.data(), sizeof(int32_t) * pl.ncell,
                                   hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s.cell_lin, lin.data(), sizeof(int32_t) * pl.ncell, hipMemcpyHostToDevice,
+                           c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s.cell_count, 0, sizeof(int32_t) * pl.ncell, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s.ctl, 0, sizeof(Ctl), c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s.nbr_cnt, 0, sizeof(int32_t) * pl.npad, c->stream);

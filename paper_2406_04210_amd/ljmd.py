@@ -75,6 +75,10 @@ KERNEL_FAMILIES = ("step", "rebuild", "resort", "other")
 
 
 def _load():
+    # torch must be loaded first: libljmd.so then binds to the HIP runtime
+    # torch already mapped (same soname), so the process holds exactly one
+    # HIP/HSA runtime and torch's device pointers and streams are ours too.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "`python -c 'import __graft_entry__ as g; g.build()'` "

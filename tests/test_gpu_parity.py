@@ -4,7 +4,14 @@ Inputs come from the shared seeded generators; every expected value comes
 from the oracle. Tolerances:
   * neighbour sets: identical (FP64 criterion in the FP64 path, the stated
     FP32 sequence in the FP32 path, both evaluated from the same FP64 input);
-  * forces: max_i |dF_i| / rms_j |F_j| <= 1e-12 (FP64), <= 1e-5 (FP32+DS);
+  * forces: relative error per particle, max_i |dF_i| / s_i <= 1e-12 (FP64),
+    <= 1e-5 (FP32+DS), with the scale s_i = max(|F_i|, rms_j |F_j|, 1 eps/sigma):
+    relative to the particle's own force, floored at the rms force (for
+    forces that nearly cancel) and at the unit force (perfect lattice); a
+    particle with a partner at a cutoff tie (|r^2 - r_c^2| within rounding of
+    the path's precision, found from the FP64 positions) may additionally
+    differ by the force jump |F(r_c)| per such partner, because the truncated
+    force is discontinuous there and binary32 decides r^2 < r_c^2;
   * U/N, W/N: relative 1e-12 (FP64), 1e-6 (FP32+DS);
   * 100-step trajectories (N=2048): max |dx| <= 1e-10 sigma, |dv| <= 1e-9
     (FP64); <= 1e-4 and <= 1e-3 (FP32+DS).
@@ -61,9 +68,35 @@ CASES = cases()
 IDS = [c[0] for c in CASES]
 
 
-def rel_force_err(f, g):
+def tie_allowance(x, sp, box, p, prec):
+    """Per-particle sum of |F(r_c)| over partners at a cutoff tie."""
+    x = np.asarray(x, dtype=np.float64)
+    n = len(x)
+    cnt, nbr = oracle.build_lists(x, sp, box, p, mode=0)
+    i = np.repeat(np.arange(n), cnt)
+    j = nbr[np.arange(nbr.shape[1])[None, :] < cnt[:, None]]
+    d = x[i] - x[j]
+    d -= box * np.rint(d / box)
+    r2 = (d * d).sum(axis=1)
+    ab = sp[i] * 2 + sp[j] if p.nspecies == 2 else np.zeros(len(i), dtype=np.int64)
+    rc = np.asarray(p.rcut)[ab]
+    window = 1e-12 if prec == FP64 else 2e-6
+    tie = np.abs(r2 - rc * rc) <= window * rc * rc
+    out = np.zeros(n)
+    for k in np.nonzero(tie)[0]:
+        a = int(ab[k])
+        jump = abs(oracle.pair_fscalar(rc[k] * (1 - 1e-15), a, p)) * rc[k]
+        out[i[k]] += 1.001 * jump
+    return out
+
+
+def rel_force_err(f, g, allowance=None):
     rms = math.sqrt(float((g ** 2).sum(axis=1).mean()))
-    return float(np.abs(f - g).max()) / rms
+    scale = np.maximum(np.maximum(np.linalg.norm(g, axis=1), rms), 1.0)
+    err = np.linalg.norm(f - g, axis=1)
+    if allowance is not None:
+        err = np.maximum(err - allowance, 0.0)
+    return float((err / scale).max())
 
 
 def make_system(ljmd, x, v, sp, box, p, prec, **kw):
@@ -95,7 +128,7 @@ def test_forces_energy_virial(ljmd, case, prec):
     o = s.observables()
     fb, Ub, Wb = oracle.forces_brute(x, sp, box, p)
     K, mom = oracle.kinetic(v, sp, p)
-    assert rel_force_err(f, fb) <= TOL_F[prec], name
+    assert rel_force_err(f, fb, tie_allowance(x, sp, box, p, prec)) <= TOL_F[prec], name
     n = len(x)
     assert abs(o["U"] - Ub) / n <= TOL_E[prec] * max(1.0, abs(Ub) / n)
     assert abs(o["W"] - Wb) / n <= TOL_E[prec] * max(1.0, abs(Wb) / n)
@@ -110,7 +143,7 @@ def test_gather_lanes_agree(ljmd, lanes, prec):
     s = make_system(ljmd, x, v, sp, box, p, prec, lanes=lanes)
     f = s.forces().cpu().numpy()
     fb, _, _ = oracle.forces_brute(x, sp, box, p)
-    assert rel_force_err(f, fb) <= TOL_F[prec]
+    assert rel_force_err(f, fb, tie_allowance(x, sp, box, p, prec)) <= TOL_F[prec]
 
 
 def _trajectory(ljmd, w, prec, nsteps, **kw):
@@ -141,7 +174,7 @@ def test_trajectory_100_steps(ljmd, prec):
     # Momentum stays zero.
     assert np.abs(obs[:, 3:6]).max() < (1e-10 if prec == FP64 else 1e-3)
     o = s.observables()
-    assert o["step"] == 100 and o["rebuilds"] >= 1 + int(obs[:, 6].sum()) - 4
+    assert o["step"] == 100 and o["rebuilds"] == 1 + int(obs[:, 6].sum())
 
 
 @pytest.mark.parametrize("prec", [FP64, FP32])
@@ -222,7 +255,11 @@ def test_full_size_forces_and_sampled_lists(ljmd, prec):
     f = s.forces().cpu().numpy()
     o = s.observables()
     fo, Uo, Wo = oracle.forces(x, w.species, box, w.params)
-    assert rel_force_err(f, fo) <= TOL_F[prec]
+    allow = tie_allowance(x, w.species, box, w.params, prec)
+    assert rel_force_err(f, fo, allow) <= TOL_F[prec]
+    # Away from cutoff ties the plain per-particle bound holds.
+    clean = allow == 0
+    assert rel_force_err(f[clean], fo[clean]) <= TOL_F[prec]
     assert abs(o["U"] - Uo) <= TOL_E[prec] * abs(Uo)
     assert abs(o["W"] - Wo) <= TOL_E[prec] * abs(Wo)
     cnt, ids = s.neighbors(cap=256)
