@@ -99,6 +99,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device-to-device (a reference kernel of known "
+                         "traffic for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -111,6 +114,14 @@ def main():
     from paper_2406_04210_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = W.config_headline()
     print(f"bench: workload {w.name} N={w.n}", file=sys.stderr, flush=True)
 
@@ -161,7 +172,7 @@ def main():
                                "skin=0.3, dt=0.005, NVE velocity Verlet, half-skin rebuild, "
                                "SFC resort every 100 steps",
                    "n": w.n, "precision": "fp32 pair math, double-single state",
-                   "lanes": args.lanes or 1,
+                   "lanes": args.lanes or 2,
                    "nbr_capacity": prof_run["info"]["nbr_capacity"]},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -214,20 +214,62 @@ __device__ inline T by_type(int t, const T (&a)[3]) {
     }
 }
 
-// Verlet lists, one wavefront per home cell. The wave builds, in LDS, one
-// shared candidate array for its home cell: the particle slots of the (up to
-// 27 distinct) surrounding cells, cell by cell in a fixed stencil order
-// (x outer, z inner), each cell's slots sorted ascending (binning leaves them
-// in atomic order; the sort is a rank count over wave shuffles). Each home
-// particle gets G = 64/m lanes (m = home occupancy) that sweep the shared
-// array G candidates at a time, so the whole wave touches only G records per
-// iteration. Hits (j != i and r_ij^2 < (r_c + skin)^2 under the stated
-// sequence of the precision) are compacted with a ballot and written in
-// candidate order, so the list order does not depend on G and is
-// reproducible run to run. Only the index array lives in LDS (6 KB a wave),
-// which keeps many waves resident to hide the record gathers.
-constexpr int kStage = 1536;
+// Verlet lists, one wavefront per home cell. Candidates are the particle
+// slots of the (up to 27 distinct) surrounding cells taken cell by cell in a
+// fixed stencil order (x outer, z inner), each cell's slots ascending
+// (binning leaves them in atomic order; a rank count in LDS sorts them).
+// The wave stages whole stencil cells into LDS in groups that fit kStage
+// (all member loads of a group in flight together, so a cell costs a few
+// memory latencies, not one per neighbour cell) and sweeps each group: a
+// home particle gets G = 64/m lanes (m = home occupancy) that take four
+// G-wide runs of candidates per trip, record gathers in flight together, so
+// the whole wave touches only 4G records per trip. Hits (j != i and
+// r_ij^2 < (r_c + skin)^2 under the stated sequence of the precision) are
+// compacted with ballots and written in candidate order: the list order
+// depends neither on G nor on the grouping and is reproducible.
+constexpr int kStage = 1024;
 constexpr int kNlistWaves = 4;
+
+// Stage the slots of stencil cells [s0, s1) (tot slots; lane s of the wave
+// holds cell id scell, count scnt and prefix offset soff of stencil cell s)
+// into dst, each cell's slots ascending. Wave-uniform control flow: every
+// lane executes every shuffle; only memory accesses are predicated.
+__device__ inline void stage_cells(const State &st, const Geom &g, int lane, int s0, int s1, int tot,
+                                   int scell, int scnt, int soff, int32_t *sraw, int32_t *dst) {
+    const int base_off = __shfl(soff, s0);
+    for (int b = 0; b < tot; b += kWave) {
+        const int t = b + lane, tg = base_off + t;
+        int sel = s0;
+        for (int s = s0 + 1; s < s1; ++s) sel = __shfl(soff, s) <= tg ? s : sel;
+        const int cs = __shfl(scell, sel), os = __shfl(soff, sel) - base_off;
+        if (t < tot) {
+            int v = st.cell_members[(int64_t)cs * g.cell_cap + (t - os)];
+            // A slot outside [0, n) would mean corrupted cell data: replace it
+            // and report, so that no later gather can leave the arrays.
+            if ((unsigned)v >= (unsigned)g.n) {
+                v = 0;
+                atomicOr(&st.ctl->flags, kErrCell);
+            }
+            sraw[t] = v;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int b = 0; b < tot; b += kWave) {
+        const int t = b + lane, tg = base_off + t;
+        int sel = s0;
+        for (int s = s0 + 1; s < s1; ++s) sel = __shfl(soff, s) <= tg ? s : sel;
+        const int os = __shfl(soff, sel) - base_off, ms = __shfl(scnt, sel);
+        if (t < tot) {
+            const int v = sraw[t];
+            int r = 0;
+            for (int k = 0; k < ms; ++k) r += sraw[os + k] < v ? 1 : 0;
+            dst[os + (r < ms ? r : ms - 1)] = v;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
 
 template <int PREC, int NS>
 __global__ __launch_bounds__(kWave * kNlistWaves) void k_nlist_cell(
@@ -235,9 +277,11 @@ __global__ __launch_bounds__(kWave * kNlistWaves) void k_nlist_cell(
     int cells_per_wave) {
     if (!rebuild_due(st.ctl, step, forced, thr2)) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) st.ctl->rebuilds += 1;
-    __shared__ int32_t sidx_all[kNlistWaves][kStage];
+    extern __shared__ int32_t lds[];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int32_t *sidx = sidx_all[wv];
+    int32_t *sraw = lds + (size_t)wv * (2 * kStage + g.cell_cap);
+    int32_t *sidx = sraw + kStage;
+    int32_t *shome = sidx + kStage;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int cbeg = (blk * kNlistWaves + wv) * cells_per_wave;
     const int cend = min(cbeg + cells_per_wave, box.ncell);
@@ -273,49 +317,25 @@ __global__ __launch_bounds__(kWave * kNlistWaves) void k_nlist_cell(
             if (lane >= o) incl += y;
         }
         const int soff = incl - scnt;
-        const int ncand = __shfl(incl, kWave - 1);
         const int home_s = ((-lo[0]) * n3[1] + (-lo[1])) * n3[2] + (-lo[2]);
-        const int home_off = __shfl(soff, home_s);
         const int m = __shfl(scnt, home_s);
-        if (ncand > kStage) {
-            if (lane == 0) atomicOr(&st.ctl->flags, kErrCell);
-            continue;
-        }
-        // Stage each stencil cell's slots in ascending order.
-        for (int s = 0; s < nst; ++s) {
-            const int cs = __builtin_amdgcn_readfirstlane(__shfl(scell, s));
-            const int ms = __builtin_amdgcn_readfirstlane(__shfl(scnt, s));
-            const int os = __builtin_amdgcn_readfirstlane(__shfl(soff, s));
-            const int32_t *mem = st.cell_members + (int64_t)cs * g.cell_cap;
-            if (ms <= kWave) {
-                const int v = lane < ms ? mem[lane] : 0x7fffffff;
-                int r = 0;
-                for (int k = 0; k < ms; ++k) r += __shfl(v, k) < v ? 1 : 0;
-                if (lane < ms) sidx[os + r] = v;
-            } else {
-                for (int e = lane; e < ms; e += kWave) {
-                    const int v = mem[e];
-                    int r = 0;
-                    for (int k = 0; k < ms; ++k) r += mem[k] < v ? 1 : 0;
-                    sidx[os + r] = v;
-                }
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        // Sweep: G lanes per home particle.
-        const int G = m >= kWave ? 1 : (m > 0 ? kWave / m : kWave);
+        if (m == 0) continue;
+        stage_cells(st, g, lane, home_s, home_s + 1, m, scell, scnt, soff, sraw, shome);
+
+        const int G = m >= kWave ? 1 : kWave / m;
         const int P = kWave / G;
         const int p_local = lane / G, gl = lane % G;
         const unsigned long long gbits = G >= 64 ? ~0ull : ((1ull << G) - 1ull);
+        const unsigned long long below = (1ull << gl) - 1ull;
+        constexpr int U = 4;
         for (int pb = 0; pb < m; pb += P) {
             const int p = pb + p_local;
             const bool active = p_local < P && p < m;
-            int i = -1, si = 0;
+            int i = 0, si = 0;
             uint32_t qi[3] = {0, 0, 0};
             double xi[3] = {0, 0, 0};
             if (active) {
-                i = sidx[home_off + p];
+                i = shome[p];
                 if constexpr (PREC == LJMD_FP64) {
                     const double4 r = st.rec64[cur][i];
                     xi[0] = r.x;
@@ -331,37 +351,69 @@ __global__ __launch_bounds__(kWave * kNlistWaves) void k_nlist_cell(
                 }
             }
             int k = 0;
-            for (int base = 0; base < ncand; base += G) {
-                const int t = base + gl;
-                bool in = false;
-                int j = -1;
-                if (active && t < ncand) {
-                    j = sidx[t];
-                    if (j != i) {
-                        if constexpr (PREC == LJMD_FP64) {
-                            const double4 rj = st.rec64[cur][j];
-                            const int tt = NS == 1 ? 0 : si + (int)rj.w;
-                            const double dx = disp_d(xi[0], rj.x, box.L[0], box.invL[0]);
-                            const double dy = disp_d(xi[1], rj.y, box.L[1], box.invL[1]);
-                            const double dz = disp_d(xi[2], rj.z, box.L[2], box.invL[2]);
+            for (int s0 = 0; s0 < nst;) {
+                // Next group of whole stencil cells that fits the stage.
+                int s1 = s0, tot = 0;
+                while (s1 < nst) {
+                    const int cn = __shfl(scnt, s1);
+                    if (tot + cn > kStage) break;
+                    tot += cn;
+                    ++s1;
+                }
+                if (s1 == s0) {  // unreachable: cell_cap <= kStage; guarantees progress
+                    if (lane == 0) atomicOr(&st.ctl->flags, kErrCell);
+                    s1 = s0 + 1;
+                    tot = 0;
+                }
+                stage_cells(st, g, lane, s0, s1, tot, scell, scnt, soff, sraw, sidx);
+                for (int base = 0; base < tot; base += U * G) {
+                    int jj[U];
+                    bool ok[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int t = base + u * G + gl;
+                        ok[u] = active && t < tot;
+                        jj[u] = sidx[ok[u] ? t : 0];
+                        ok[u] = ok[u] && jj[u] != i;
+                    }
+                    bool in[U];
+                    if constexpr (PREC == LJMD_FP64) {
+                        double4 rj[U];
+#pragma unroll
+                        for (int u = 0; u < U; ++u) rj[u] = st.rec64[cur][jj[u]];
+#pragma unroll
+                        for (int u = 0; u < U; ++u) {
+                            const int tt = NS == 1 ? 0 : si + (int)rj[u].w;
+                            const double dx = disp_d(xi[0], rj[u].x, box.L[0], box.invL[0]);
+                            const double dy = disp_d(xi[1], rj[u].y, box.L[1], box.invL[1]);
+                            const double dz = disp_d(xi[2], rj[u].z, box.L[2], box.invL[2]);
                             const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-                            in = r2 < by_type<NS>(tt, pc.rl2);
-                        } else {
-                            const int4 rj = st.recq[cur][j];
-                            const int tt = NS == 1 ? 0 : si + rj.w;
-                            const float dx = disp_q(qi[0], (uint32_t)rj.x, box.qs_hi[0], box.qs_lo[0]);
-                            const float dy = disp_q(qi[1], (uint32_t)rj.y, box.qs_hi[1], box.qs_lo[1]);
-                            const float dz = disp_q(qi[2], (uint32_t)rj.z, box.qs_hi[2], box.qs_lo[2]);
+                            in[u] = ok[u] && r2 < by_type<NS>(tt, pc.rl2);
+                        }
+                    } else {
+                        int4 rj[U];
+#pragma unroll
+                        for (int u = 0; u < U; ++u) rj[u] = st.recq[cur][jj[u]];
+#pragma unroll
+                        for (int u = 0; u < U; ++u) {
+                            const int tt = NS == 1 ? 0 : si + rj[u].w;
+                            const float dx = disp_q(qi[0], (uint32_t)rj[u].x, box.qs_hi[0], box.qs_lo[0]);
+                            const float dy = disp_q(qi[1], (uint32_t)rj[u].y, box.qs_hi[1], box.qs_lo[1]);
+                            const float dz = disp_q(qi[2], (uint32_t)rj[u].z, box.qs_hi[2], box.qs_lo[2]);
                             const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                            in = r2 < by_type<NS>(tt, pc.rl2f);
+                            in[u] = ok[u] && r2 < by_type<NS>(tt, pc.rl2f);
                         }
                     }
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const unsigned long long mask = __ballot(in[u] ? 1 : 0);
+                        const unsigned long long grp = (mask >> (lane - gl)) & gbits;
+                        const int pos = __popcll(grp & below);
+                        if (in[u] && k + pos < g.cap) st.nbr[nbr_index(i, k + pos, g.lanes, g.cap)] = jj[u];
+                        k += __popcll(grp);
+                    }
                 }
-                const unsigned long long mask = __ballot(in ? 1 : 0);
-                const unsigned long long grp = (mask >> (lane - gl)) & gbits;
-                const int pos = __popcll(grp & ((1ull << gl) - 1ull));
-                if (in && k + pos < g.cap) st.nbr[nbr_index(i, k + pos, g.lanes, g.cap)] = j;
-                k += __popcll(grp);
+                s0 = s1;
             }
             if (active && gl == 0) {
                 st.nbr_cnt[i] = k;
@@ -374,8 +426,6 @@ __global__ __launch_bounds__(kWave * kNlistWaves) void k_nlist_cell(
             }
             wave_max = active && k > wave_max ? k : wave_max;
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
     }
     for (int o = 32; o > 0; o >>= 1) {
         const int y = __shfl_xor(wave_max, o);
@@ -439,8 +489,9 @@ hipError_t launch_nlist(const Launch &L, int64_t step, int forced) {
     const int per = (ncell + nwaves_max - 1) / nwaves_max;
     const int nwaves = (ncell + per - 1) / per;
     const unsigned grid = (unsigned)((nwaves + kNlistWaves - 1) / kNlistWaves);
+    const size_t shm = (size_t)kNlistWaves * (2 * kStage + L.g->cell_cap) * sizeof(int32_t);
 #define NL(P, S)                                                                              \
-    hipLaunchKernelGGL((k_nlist_cell<P, S>), dim3(grid), dim3(kWave * kNlistWaves), 0,        \
+    hipLaunchKernelGGL((k_nlist_cell<P, S>), dim3(grid), dim3(kWave * kNlistWaves), shm,      \
                        L.stream, *L.st, *L.g, *L.box, *L.pc, L.cur, step, forced, L.dyn->thr2, per)
     if (L.g->prec == LJMD_FP64) {
         if (L.g->nspecies == 1) NL(LJMD_FP64, 1); else NL(LJMD_FP64, 2);
