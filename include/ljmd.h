@@ -76,7 +76,7 @@ typedef struct ljmd_params {
     int32_t sort_interval;  /* reorder along the space-filling curve every k steps; 0 = never */
     int32_t precision;      /* enum ljmd_precision */
     int32_t nbr_capacity;   /* list slots per particle; 0 = automatic */
-    int32_t cell_capacity;  /* particle slots per cell; 0 = automatic */
+    int32_t cell_capacity;  /* particle slots per cell, <= 768; 0 = automatic */
     int32_t lanes;          /* lanes per particle in the force gather: 1,2,4,8,16; 0 = automatic */
     int32_t reserved;       /* must be 0 */
 } ljmd_params;

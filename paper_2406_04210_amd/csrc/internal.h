@@ -55,10 +55,9 @@ struct DynC {
 struct Ctl {
     uint32_t maxd[2];     // max squared displacement since the last build (float bits), by drift parity
     uint32_t flags;       // latched error bits
-    int32_t max_fill;     // longest list at any build
+    int32_t max_fill;     // longest current list (computed on request)
     int64_t rebuilds;     // list builds since set_state
-    int32_t max_cell;     // largest cell occupancy at any build
-    int32_t pad;
+    int32_t pad[2];
     double last[kNP];     // observables of the last flushed step: U, W, K, px, py, pz, rebuilt, step
 };
 
@@ -80,7 +79,9 @@ struct State {
     int32_t *nbr;         // neighbour list, interleaved by wave chunk (see nbr_index)
     int32_t *nbr_cnt;     // list length per particle
     int32_t *cell_count;  // particles binned per cell (cells indexed by Hilbert rank)
-    int32_t *cell_members;// [ncell][cell_cap] particle slots, ascending after canonicalisation
+    void *cell_rec;       // [ncell][cell_cap] slot records (int4 FP32 / double4 FP64):
+                          // position record with (index << 1 | species) in .w,
+                          // ascending by index after canonicalisation
     int32_t *cell_start;  // [ncell + 1] exclusive scan of counts (resort only)
     int32_t *rank_of;     // [ncell] Hilbert rank of the cell with linear index (ix*ny+iy)*nz+iz
     int32_t *cell_lin;    // [ncell] linear index of the cell with a given Hilbert rank
@@ -98,6 +99,7 @@ struct Geom {
     int32_t nspecies;
     int32_t prec;
     int32_t max_blocks;   // rows per ring slot of partials
+    int32_t ncu;          // compute units of the device (grid of the per-step rebuild kernels)
 };
 
 // ------------------------------------------------------------------------
@@ -108,11 +110,14 @@ struct Geom {
 // particles; entry k of particle i lives at
 //   chunk*(P*cap) + (k/lanes)*64 + (i%P)*lanes + (k%lanes),  chunk = i/P,
 // so the 64 lanes of a wave always read 64 consecutive int32 (256 bytes).
+// lanes is a power of two, so the index is shifts and masks only (this runs
+// once per list entry written).
 __host__ __device__ inline int64_t nbr_index(int64_t i, int32_t k, int32_t lanes, int32_t cap) {
-    int32_t P = kWave / lanes;
-    int64_t chunk = i / P;
-    int32_t p = (int32_t)(i - chunk * P);
-    return chunk * (int64_t)P * cap + (int64_t)(k / lanes) * kWave + p * lanes + (k % lanes);
+    const int lg = lanes >= 16 ? 4 : (lanes >= 8 ? 3 : (lanes >= 4 ? 2 : (lanes >= 2 ? 1 : 0)));
+    const int pg = 6 - lg;  // log2 of particles per chunk
+    const int64_t chunk = i >> pg;
+    const int32_t p = (int32_t)(i & ((1 << pg) - 1));
+    return ((chunk * (int64_t)cap) << pg) + ((int64_t)(k >> lg) << 6) + (p << lg) + (k & (lanes - 1));
 }
 
 // Blocks are dispatched round-robin over the 8 XCDs of the chip; remap so
@@ -195,10 +200,12 @@ __device__ inline float disp_q(uint32_t qi, uint32_t qj, float qs_hi, float qs_l
 }
 
 // Minimum-image displacement of the FP64 path.
+// Wrapped inputs give m in {-1, 0, 1}, so L*m is exact and the fused form
+// equals t - L*m bit for bit.
 __device__ inline double disp_d(double xi, double xj, double L, double invL) {
     double t = xi - xj;
     double m = rint(t * invL);
-    return t - L * m;
+    return fma(-L, m, t);
 }
 
 // Cell (Hilbert rank) of a particle from its fixed-point coordinates.
@@ -249,6 +256,9 @@ hipError_t launch_obs_reduce(const Launch &L, int64_t first_step, int count, int
 hipError_t launch_get_state(const Launch &L, double *x, double *v, int32_t *img);
 hipError_t launch_get_forces(const Launch &L, double *f);
 hipError_t launch_neighbors(const Launch &L, int32_t *cnt, int32_t *ids, int32_t cap);
+hipError_t launch_max_fill(const Launch &L);
+size_t resort_scratch_bytes(int64_t npad, int prec);
+size_t cell_rec_bytes(int prec);
 int step_blocks(const Geom &g);
 
 }  // namespace ljmd

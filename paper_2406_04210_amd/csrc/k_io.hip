@@ -164,8 +164,33 @@ __global__ __launch_bounds__(kBlock) void k_obs_reduce(State st, Geom g, int64_t
     }
 }
 
+// Longest current neighbour list (one block; only run on request).
+__global__ __launch_bounds__(kBlock) void k_max_fill(State st, Geom g) {
+    __shared__ int32_t red[kBlock / kWave];
+    int m = 0;
+    for (int64_t i = threadIdx.x; i < g.n; i += kBlock) {
+        const int c = st.nbr_cnt[i];
+        m = c > m ? c : m;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const int y = __shfl_xor(m, o);
+        m = y > m ? y : m;
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < kBlock / kWave; ++q) m = red[q] > m ? red[q] : m;
+        st.ctl->max_fill = m;
+    }
+}
+
 // ------------------------------------------------------------------------
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+hipError_t launch_max_fill(const Launch &L) {
+    hipLaunchKernelGGL(k_max_fill, dim3(1), dim3(kBlock), 0, L.stream, *L.st, *L.g);
+    return hipGetLastError();
+}
 
 hipError_t launch_set_state(const Launch &L, const double *x, const double *v, const int32_t *sp) {
     if (L.g->prec == LJMD_FP64)

@@ -139,7 +139,19 @@ __global__ __launch_bounds__(kBlock) void k_step_ds(StepArgs a) {
     const int iters = cnt > l ? (cnt - l + LANES - 1) / LANES : 0;
     const float qsx = a.box.qs_hi[0], qsy = a.box.qs_hi[1], qsz = a.box.qs_hi[2];
     const float qlx = a.box.qs_lo[0], qly = a.box.qs_lo[1], qlz = a.box.qs_lo[2];
-    float fx = 0.f, fy = 0.f, fz = 0.f, e = 0.f, w = 0.f;
+    // Pair arithmetic: d = (q_i - q_j) * quantum (wrapping difference, i.e.
+    // the minimum image), u = sigma^2 / r^2, s6 = u^3. With one species the
+    // per-pair constants are factored out: the lanes accumulate
+    //   f' = sum s6 (2 s6 - 1) / r^2 * d,  a12 = sum s6^2,  a6 = sum s6,  an = #pairs,
+    // and F = 24 eps f', sum phi_s = 4 eps (a12 - a6) - an phi(r_c),
+    // sum fs r^2 = 24 eps (2 a12 - a6). With two species every pair carries
+    // its own constants.
+    // Energy and virial terms are summed in FP64 (they feed the FP64
+    // energy/virial reductions); forces are accumulated in FP32.
+    float fx = 0.f, fy = 0.f, fz = 0.f;
+    double e = 0.0, w = 0.0, a12 = 0.0, a6 = 0.0;
+    int an = 0;
+    const float rc2_1 = a.pc.rc2f[0], sig2_1 = a.pc.sig2f[0];
     // Four list entries per trip: all index loads, then all record gathers,
     // are in flight before the arithmetic of the first one.
     constexpr int U = 4;
@@ -156,21 +168,38 @@ __global__ __launch_bounds__(kBlock) void k_step_ds(StepArgs a) {
         for (int u = 0; u < U; ++u) {
             if (m + u >= iters) continue;
             const int4 rj = rr[u];
-            const float dx = disp_q((uint32_t)ri.x, (uint32_t)rj.x, qsx, qlx);
-            const float dy = disp_q((uint32_t)ri.y, (uint32_t)rj.y, qsy, qly);
-            const float dz = disp_q((uint32_t)ri.z, (uint32_t)rj.z, qsz, qlz);
+            const float dx = (float)(int32_t)((uint32_t)ri.x - (uint32_t)rj.x) * qsx;
+            const float dy = (float)(int32_t)((uint32_t)ri.y - (uint32_t)rj.y) * qsy;
+            const float dz = (float)(int32_t)((uint32_t)ri.z - (uint32_t)rj.z) * qsz;
             const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-            const int t = NS == 1 ? 0 : ri.w + rj.w;
-            if (r2 < by_t<NS>(t, a.pc.rc2f)) {
-                const float ir2 = __builtin_amdgcn_rcpf(r2);
-                const float s2 = by_t<NS>(t, a.pc.sig2f) * ir2;
-                const float s6 = s2 * s2 * s2;
-                const float fs = by_t<NS>(t, a.pc.eps24f) * s6 * fmaf(2.0f, s6, -1.0f) * ir2;
-                fx = fmaf(fs, dx, fx);
-                fy = fmaf(fs, dy, fy);
-                fz = fmaf(fs, dz, fz);
-                e += fmaf(by_t<NS>(t, a.pc.eps4f) * s6, s6 - 1.0f, -by_t<NS>(t, a.pc.shiftf));
-                w = fmaf(fs, r2, w);
+            if constexpr (NS == 1) {
+                if (r2 < rc2_1) {
+                    const float ir2 = __builtin_amdgcn_rcpf(r2);
+                    const float s2 = sig2_1 * ir2;
+                    const float s6 = s2 * s2 * s2;
+                    const float t = (s6 * ir2) * fmaf(2.0f, s6, -1.0f);
+                    fx = fmaf(t, dx, fx);
+                    fy = fmaf(t, dy, fy);
+                    fz = fmaf(t, dz, fz);
+                    a12 += (double)(s6 * s6);
+                    a6 += (double)s6;
+                    an += 1;
+                }
+            } else {
+                const int tt = ri.w + rj.w;
+                if (r2 < by_t<NS>(tt, a.pc.rc2f)) {
+                    const float ir2 = __builtin_amdgcn_rcpf(r2);
+                    const float s2 = by_t<NS>(tt, a.pc.sig2f) * ir2;
+                    const float s6 = s2 * s2 * s2;
+                    const float s12 = s6 * s6;
+                    const float c24 = by_t<NS>(tt, a.pc.eps24f);
+                    const float fs = c24 * ((s6 * ir2) * fmaf(2.0f, s6, -1.0f));
+                    fx = fmaf(fs, dx, fx);
+                    fy = fmaf(fs, dy, fy);
+                    fz = fmaf(fs, dz, fz);
+                    e += (double)fmaf(by_t<NS>(tt, a.pc.eps4f), s12 - s6, -by_t<NS>(tt, a.pc.shiftf));
+                    w += (double)(c24 * fmaf(2.0f, s12, -s6));
+                }
             }
         }
     }
@@ -180,9 +209,23 @@ __global__ __launch_bounds__(kBlock) void k_step_ds(StepArgs a) {
             fx += __shfl_xor(fx, o);
             fy += __shfl_xor(fy, o);
             fz += __shfl_xor(fz, o);
-            e += __shfl_xor(e, o);
-            w += __shfl_xor(w, o);
+            if constexpr (NS == 1) {
+                a12 += __shfl_xor(a12, o);
+                a6 += __shfl_xor(a6, o);
+                an += __shfl_xor(an, o);
+            } else {
+                e += __shfl_xor(e, o);
+                w += __shfl_xor(w, o);
+            }
         }
+    }
+    if constexpr (NS == 1) {
+        const float c24 = a.pc.eps24f[0];
+        fx *= c24;
+        fy *= c24;
+        fz *= c24;
+        e = a.pc.eps4[0] * (a12 - a6) - (double)an * a.pc.shift[0];
+        w = a.pc.eps24[0] * (2.0 * a12 - a6);
     }
     double pu = 0.0, pw = 0.0, pk = 0.0, ppx = 0.0, ppy = 0.0, ppz = 0.0;
     uint32_t dm = 0u;
@@ -202,8 +245,8 @@ __global__ __launch_bounds__(kBlock) void k_step_ds(StepArgs a) {
         ppx = (double)(mass * ux);
         ppy = (double)(mass * uy);
         ppz = (double)(mass * uz);
-        pu = 0.5 * (double)e;
-        pw = 0.5 * (double)w;
+        pu = 0.5 * e;
+        pw = 0.5 * w;
         if (a.mode & kIntegrate) {
             vx = ds_add(vx, ds_mul_f(chi, clo, fx));
             vy = ds_add(vy, ds_mul_f(chi, clo, fy));
@@ -283,7 +326,10 @@ __global__ __launch_bounds__(kBlock) void k_step_fp64(StepArgs a) {
             const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
             const int t = NS == 1 ? 0 : si + (int)rj.w;
             if (r2 < by_t<NS>(t, a.pc.rc2)) {
-                const double ir2 = 1.0 / r2;
+                // Reciprocal: hardware estimate refined by two Newton steps.
+                double ir2 = __builtin_amdgcn_rcp(r2);
+                ir2 = fma(ir2, fma(-r2, ir2, 1.0), ir2);
+                ir2 = fma(ir2, fma(-r2, ir2, 1.0), ir2);
                 const double s2 = by_t<NS>(t, a.pc.sig2) * ir2;
                 const double s6 = s2 * s2 * s2;
                 const double fs = by_t<NS>(t, a.pc.eps24) * s6 * fma(2.0, s6, -1.0) * ir2;

@@ -14,7 +14,6 @@
 #include "internal.h"
 
 namespace ljmd {
-size_t resort_scratch_bytes(int64_t npad, int prec);
 }
 
 using namespace ljmd;
@@ -104,7 +103,7 @@ int validate(const ljmd_params *p, std::string *why) {
     if (p->sort_interval < 0) return bad("sort_interval must be >= 0");
     if (p->precision != LJMD_FP64 && p->precision != LJMD_FP32_DS) return bad("unknown precision");
     if (p->nbr_capacity < 0 || p->nbr_capacity > 4096) return bad("nbr_capacity must be in [0, 4096]");
-    if (p->cell_capacity < 0 || p->cell_capacity > 1024) return bad("cell_capacity must be in [0, 1024]");
+    if (p->cell_capacity < 0 || p->cell_capacity > 768) return bad("cell_capacity must be in [0, 768]");
     if (p->lanes != 0 && p->lanes != 1 && p->lanes != 2 && p->lanes != 4 && p->lanes != 8 && p->lanes != 16)
         return bad("lanes must be 0, 1, 2, 4, 8 or 16");
     if (p->reserved != 0) return bad("reserved must be 0");
@@ -162,11 +161,11 @@ Plan make_plan(const ljmd_params *p) {
     if (cc == 0) {
         double cellv = vol / pl.ncell;
         double mean = rho * cellv;
-        cc = (int32_t)std::min<double>(2.0 * mean + 32.0, 1024.0);
+        cc = (int32_t)std::min<double>(2.0 * mean + 32.0, 768.0);
         cc = (int32_t)std::min<int64_t>(cc, p->n);
     }
     pl.cell_cap = std::max<int32_t>(8, round_up(cc, 8));
-    if (pl.cell_cap > 1024) pl.cell_cap = 1024;
+    if (pl.cell_cap > 768) pl.cell_cap = 768;
     // Measured on MI355X at N=256,000: 2 lanes per particle for FP32, 4 for FP64.
     pl.lanes = p->lanes != 0 ? p->lanes : (p->precision == LJMD_FP64 ? 4 : 2);
     const int per_block = (kBlock / kWave) * (kWave / pl.lanes);
@@ -199,7 +198,7 @@ Plan make_plan(const ljmd_params *p) {
     pl.off_cnt = take(sizeof(int32_t) * N);
     pl.off_nbr = take(sizeof(int32_t) * (size_t)N * pl.cap);
     pl.off_ccount = take(sizeof(int32_t) * pl.ncell);
-    pl.off_cmem = take(sizeof(int32_t) * (size_t)pl.ncell * pl.cell_cap);
+    pl.off_cmem = take(cell_rec_bytes(p->precision) * (size_t)pl.ncell * pl.cell_cap);
     pl.off_cstart = take(sizeof(int32_t) * (pl.ncell + 1));
     pl.off_rank = take(sizeof(int32_t) * pl.ncell);
     pl.off_lin = take(sizeof(int32_t) * pl.ncell);
@@ -368,10 +367,9 @@ int rebuild_sequence(ljmd_ctx *c, int64_t step, int forced, bool resort) {
         if ((e = launch_nlist(L, step, forced)) != hipSuccess) return hip_fail(c, e, "nlist");
         return LJMD_OK;
     }
-    // Without a resort the list build sorts each cell's slots in LDS itself, so
-    // the canonical-order pass is only needed before a resort.
     Bracket b(c, 1);
     if ((e = launch_bin(L, step, forced)) != hipSuccess) return hip_fail(c, e, "bin");
+    if ((e = launch_canon(L, step, forced)) != hipSuccess) return hip_fail(c, e, "canon");
     if ((e = launch_nlist(L, step, forced)) != hipSuccess) return hip_fail(c, e, "nlist");
     return LJMD_OK;
 }
@@ -447,6 +445,14 @@ int ljmd_create(const ljmd_params *p, void *ws, size_t bytes, void *stream, ljmd
     g.nspecies = p->nspecies;
     g.prec = p->precision;
     g.max_blocks = pl.max_blocks;
+    g.ncu = 256;
+    if (c->device >= 0) {
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) ==
+                hipSuccess &&
+            ncu > 0)
+            g.ncu = ncu;
+    }
     c->nblocks = pl.max_blocks;
     uint8_t *b = (uint8_t *)ws;
     State &s = c->st;
@@ -471,7 +477,7 @@ int ljmd_create(const ljmd_params *p, void *ws, size_t bytes, void *stream, ljmd
     s.nbr = (int32_t *)(b + pl.off_nbr);
     s.nbr_cnt = (int32_t *)(b + pl.off_cnt);
     s.cell_count = (int32_t *)(b + pl.off_ccount);
-    s.cell_members = (int32_t *)(b + pl.off_cmem);
+    s.cell_rec = (void *)(b + pl.off_cmem);
     s.cell_start = (int32_t *)(b + pl.off_cstart);
     s.rank_of = (int32_t *)(b + pl.off_rank);
     s.cell_lin = (int32_t *)(b + pl.off_lin);
@@ -640,6 +646,8 @@ int ljmd_sync_status(ljmd_ctx *c) {
 int ljmd_observables(ljmd_ctx *c, ljmd_obs *out) {
     if (!c || !out) return LJMD_EINVAL;
     if (!c->have_state) return fail(c, LJMD_ESTATE, "observables before set_state");
+    hipError_t e0 = launch_max_fill(launcher(c));
+    if (e0 != hipSuccess) return hip_fail(c, e0, "max_fill");
     int r = ljmd_sync_status(c);
     Ctl h;
     hipError_t e = hipMemcpy(&h, c->st.ctl, sizeof h, hipMemcpyDeviceToHost);
