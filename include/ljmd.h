@@ -156,6 +156,18 @@ int ljmd_get_forces(ljmd_ctx *ctx, double *f);
  * receives one observable row per step. Asynchronous. */
 int ljmd_run(ljmd_ctx *ctx, int64_t nsteps, double *obs_dev);
 
+/* Steepest descent to relax a starting configuration (random positions
+ * overlap): per iteration, forces of the truncated potential with every pair
+ * distance clamped from below at clamp * sigma_ab (this mode only), then
+ * x_i += max_disp * F_i / max_j |F_j|, so no particle moves more than
+ * max_disp; lists follow the half-skin rebuild rule. Velocities are left
+ * as they are; at the end the lists are rebuilt (with a resort) and the
+ * unclamped forces of the relaxed state evaluated, as after ljmd_set_state.
+ * fmax_dev (device, nsteps float64, or NULL) receives max_j |F_j| at the
+ * start of every iteration. Requires a loaded state. Asynchronous. */
+int ljmd_minimize_sd(ljmd_ctx *ctx, int32_t nsteps, double max_disp, double clamp,
+                     double *fmax_dev);
+
 /* Neighbour lists of the last build, by id: cnt (device, n int32) list
  * lengths and ids (device, n*cap int32, row id holds the first min(cnt, cap)
  * partner ids in list order). For tests and inspection. */

@@ -108,6 +108,9 @@ def lib():
         L.oracle_q_from_ds.argtypes = [C.c_float, C.c_float, C.c_double]
         L.oracle_disp_q.restype = C.c_float
         L.oracle_disp_q.argtypes = [C.c_uint32, C.c_uint32, C.c_double]
+        L.oracle_minimize_sd.restype = C.c_int64
+        L.oracle_minimize_sd.argtypes = [C.c_int64, dp, ip, dp, pp, C.c_int64, C.c_double,
+                                         C.c_double, dp, dp]
         L.oracle_num_threads.restype = C.c_int32
         L.oracle_num_threads.argtypes = []
         _lib = L
@@ -231,6 +234,22 @@ def run_nve(x, v, species, box, params, nsteps: int, want_obs: bool = True):
     if builds < 0:
         raise MemoryError("oracle_run_nve: allocation failed")
     return {"x": x, "v": v, "f": f, "obs": obs, "builds": int(builds), "seconds": dt}
+
+
+def minimize_sd(x, species, box, params, nsteps: int, delta: float = 0.01, clamp: float = 0.6):
+    """Steepest descent with capped step and clamped pair distance.
+    Returns dict x (relaxed, unwrapped), U ((nsteps+1,) clamped energies),
+    fmax ((nsteps+1,)), builds."""
+    x = _f64(x, (-1, 3)).copy()
+    sp, bx = _i32(species), _f64(box)
+    u = np.zeros(nsteps + 1)
+    fm = np.zeros(nsteps + 1)
+    s = make_params(params)
+    b = lib().oracle_minimize_sd(x.shape[0], _d(x), _i(sp), _d(bx), C.byref(s), int(nsteps),
+                                 float(delta), float(clamp), _d(u), _d(fm))
+    if b < 0:
+        raise MemoryError("oracle_minimize_sd: allocation failed")
+    return {"x": x, "U": u, "fmax": fm, "builds": int(b)}
 
 
 def ds_split(w: float):

@@ -438,6 +438,92 @@ int64_t oracle_run_nve(int64_t n, double *x, double *v, const int32_t *sp, const
     return builds;
 }
 
+/* ---------------------------------------------------------------- O6 ---- */
+
+/* Steepest descent used to relax random starting positions (the 4M-particle
+ * mixture workload) before dynamics:
+ *   F = forces of the truncated potential with every pair distance clamped
+ *       from below at clamp * sigma_ab (random positions overlap; the clamp
+ *       keeps forces finite and is used only here);
+ *   F_max = max_i |F_i|;   x_i <- x_i + delta * F_i / F_max,
+ * so that no particle moves more than delta per step. Lists are rebuilt with
+ * the same half-skin rule as the dynamics. x (unwrapped) is updated in place.
+ * u_out (nullable) receives nsteps+1 clamped energies U_k (before step k+1 and
+ * after the last step); fmax_out (nullable) the nsteps+1 values F_max.
+ * Returns the number of list builds, -1 on allocation failure. */
+static void forces_list_clamped(int64_t n, const double *x, const int32_t *sp, const double *box,
+                                const olj_t *p, int32_t cap, const int32_t *cnt,
+                                const int32_t *nbr, double clamp, double *f, double *U_out) {
+    double U = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : U)
+    for (int64_t i = 0; i < n; ++i) {
+        double fi[3] = {0.0, 0.0, 0.0};
+        double ui = 0.0;
+        int32_t m = cnt[i] < cap ? cnt[i] : cap;
+        for (int32_t k = 0; k < m; ++k) {
+            int64_t j = nbr[(size_t)i * cap + k];
+            double d[3];
+            min_image(x + 3 * i, x + 3 * j, box, d);
+            double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            int ab = pair_index(p, sp[i], sp[j]);
+            if (r >= p->rcut[ab]) continue;
+            double rmin = clamp * p->sigma[ab];
+            double re = r < rmin ? rmin : r;
+            double fs = oracle_pair_fscalar(re, ab, p);
+            for (int c = 0; c < 3; ++c) fi[c] += fs * d[c];
+            ui += 0.5 * oracle_pair_energy(re, ab, p);
+        }
+        for (int c = 0; c < 3; ++c) f[3 * i + c] = fi[c];
+        U += ui;
+    }
+    *U_out = U;
+}
+
+int64_t oracle_minimize_sd(int64_t n, double *x, const int32_t *sp, const double *box,
+                           const olj_t *p, int64_t nsteps, double delta, double clamp,
+                           double *u_out, double *fmax_out) {
+    olist_t L;
+    L.n = n;
+    L.cap = 160;
+    L.cnt = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    L.nbr = (int32_t *)malloc(sizeof(int32_t) * (size_t)n * L.cap);
+    L.xref = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    double *f = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    if (!L.cnt || !L.nbr || !L.xref || !f) return -1;
+    int64_t builds = 0;
+    if (build(&L, x, sp, box, p)) return -1;
+    builds++;
+    for (int64_t s = 0; s <= nsteps; ++s) {
+        if (s > 0 && needs_rebuild(&L, x, p->skin)) {
+            if (build(&L, x, sp, box, p)) return -1;
+            builds++;
+        }
+        double U;
+        forces_list_clamped(n, x, sp, box, p, L.cap, L.cnt, L.nbr, clamp, f, &U);
+        double fmax = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            double a = sqrt(f[3 * i] * f[3 * i] + f[3 * i + 1] * f[3 * i + 1] + f[3 * i + 2] * f[3 * i + 2]);
+            if (a > fmax) fmax = a;
+        }
+        if (u_out) u_out[s] = U;
+        if (fmax_out) fmax_out[s] = fmax;
+        if (s == nsteps || fmax == 0.0) {
+            for (int64_t t = s + 1; t <= nsteps; ++t) {
+                if (u_out) u_out[t] = U;
+                if (fmax_out) fmax_out[t] = fmax;
+            }
+            break;
+        }
+        double scale = delta / fmax;
+        for (int64_t k = 0; k < 3 * n; ++k) x[k] += scale * f[k];
+    }
+    free(L.cnt);
+    free(L.nbr);
+    free(L.xref);
+    free(f);
+    return builds;
+}
+
 int32_t oracle_num_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();

@@ -30,6 +30,8 @@ struct BoxC {
     float Lhi[3], Llo[3];        // L as a double-single pair
     float qs_hi[3], qs_lo[3];    // quantum L * 2^-32 as a double-single pair
     float S_hi[3], S_lo[3];      // 2^32 / L as a double-single pair
+    float r2c[3];                // (quantum / qs_hi)^2: removes the systematic rounding
+                                 // of the single-float quantum from r^2 in the force kernel
     int32_t nc[3];               // cells per axis
     int32_t ncell;
 };
@@ -57,6 +59,7 @@ struct Ctl {
     uint32_t flags;       // latched error bits
     int32_t max_fill;     // longest current list (computed on request)
     int64_t rebuilds;     // list builds since set_state
+    unsigned long long fmax[2];  // steepest descent: max |F| (double bits), by iteration parity
     int32_t pad[2];
     double last[kNP];     // observables of the last flushed step: U, W, K, px, py, pz, rebuilt, step
 };
@@ -257,6 +260,8 @@ hipError_t launch_get_state(const Launch &L, double *x, double *v, int32_t *img)
 hipError_t launch_get_forces(const Launch &L, double *f);
 hipError_t launch_neighbors(const Launch &L, int32_t *cnt, int32_t *ids, int32_t cap);
 hipError_t launch_max_fill(const Launch &L);
+hipError_t launch_sd(const Launch &L, int64_t step, int forced, int iter, double delta,
+                     double clamp, double *fmax_out);
 size_t resort_scratch_bytes(int64_t npad, int prec);
 size_t cell_rec_bytes(int prec);
 int step_blocks(const Geom &g);

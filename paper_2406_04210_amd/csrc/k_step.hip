@@ -15,50 +15,9 @@
 // Gather geometry: LANES lanes per particle, 64/LANES particles per
 // wavefront; the interleaved list layout makes every list load one 256-byte
 // contiguous read. Each XCD gets a contiguous eighth of the particles.
-#include "internal.h"
+#include "step_common.h"
 
 namespace ljmd {
-
-struct StepArgs {
-    State st;
-    Geom g;
-    BoxC box;
-    PairC pc;
-    DynC dyn;
-    int cur;
-    int forced;
-    int mode;
-    int slot;
-    int64_t step;
-};
-
-template <int NS, class T>
-__device__ inline T by_t(int t, const T (&a)[3]) {
-    if constexpr (NS == 1) {
-        return a[0];
-    } else {
-        return t == 0 ? a[0] : (t == 1 ? a[1] : a[2]);
-    }
-}
-
-template <class T>
-__device__ inline T by_s(int s, const T (&a)[2]) {
-    return s == 0 ? a[0] : a[1];
-}
-
-template <class T>
-__device__ inline T wave_sum(T v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
-__device__ inline uint32_t wave_max_u(uint32_t v) {
-    for (int o = 32; o > 0; o >>= 1) {
-        uint32_t y = __shfl_xor(v, o);
-        v = y > v ? y : v;
-    }
-    return v;
-}
 
 // Block-level deterministic reduction of the six observable partials and the
 // displacement maximum; one row of partials per block.
@@ -106,17 +65,6 @@ __device__ inline void step_housekeeping(const StepArgs &a) {
     }
 }
 
-// Double-single wrap into [0, L) with image bookkeeping.
-__device__ inline void wrap_ds(dsf &x, float Lhi, float Llo, int &im) {
-    if (x.hi < 0.0f || (x.hi == 0.0f && x.lo < 0.0f)) {
-        x = ds_add(x, dsf{Lhi, Llo});
-        im -= 1;
-    } else if (x.hi > Lhi || (x.hi == Lhi && x.lo >= Llo)) {
-        x = ds_add(x, dsf{-Lhi, -Llo});
-        im += 1;
-    }
-}
-
 // ---------------------------------------------------------------- FP32 ---
 template <int NS, int LANES>
 __global__ __launch_bounds__(kBlock) void k_step_ds(StepArgs a) {
@@ -152,6 +100,7 @@ __global__ __launch_bounds__(kBlock) void k_step_ds(StepArgs a) {
     double e = 0.0, w = 0.0, a12 = 0.0, a6 = 0.0;
     int an = 0;
     const float rc2_1 = a.pc.rc2f[0], sig2_1 = a.pc.sig2f[0];
+    const float c2x = a.box.r2c[0], c2y = a.box.r2c[1], c2z = a.box.r2c[2];
     // Four list entries per trip: all index loads, then all record gathers,
     // are in flight before the arithmetic of the first one.
     constexpr int U = 4;
@@ -171,7 +120,9 @@ __global__ __launch_bounds__(kBlock) void k_step_ds(StepArgs a) {
             const float dx = (float)(int32_t)((uint32_t)ri.x - (uint32_t)rj.x) * qsx;
             const float dy = (float)(int32_t)((uint32_t)ri.y - (uint32_t)rj.y) * qsy;
             const float dz = (float)(int32_t)((uint32_t)ri.z - (uint32_t)rj.z) * qsz;
-            const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+            // d carries the single-float quantum's relative rounding (a few
+            // 1e-8, the same for every pair); r^2 takes it out exactly per axis.
+            const float r2 = fmaf(dz * c2z, dz, fmaf(dy * c2y, dy, (dx * c2x) * dx));
             if constexpr (NS == 1) {
                 if (r2 < rc2_1) {
                     const float ir2 = __builtin_amdgcn_rcpf(r2);

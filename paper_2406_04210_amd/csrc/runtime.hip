@@ -252,6 +252,8 @@ void fill_constants(ljmd_ctx *c, const Plan &pl) {
         const double qs = L / kTwo32;
         b.qs_hi[k] = (float)qs;
         b.qs_lo[k] = (float)(qs - (double)b.qs_hi[k]);
+        const double ratio = qs / (double)b.qs_hi[k];
+        b.r2c[k] = (float)(ratio * ratio);
         const double S = kTwo32 / L;
         b.S_hi[k] = (float)S;
         b.S_lo[k] = (float)(S - (double)b.S_hi[k]);
@@ -603,6 +605,34 @@ int ljmd_kernel_times(ljmd_ctx *c, double ms[LJMD_NKT], int64_t count[LJMD_NKT])
         count[k] = c->count[k];
     }
     return r;
+}
+
+int ljmd_minimize_sd(ljmd_ctx *c, int32_t nsteps, double max_disp, double clamp, double *fmax_dev) {
+    if (!c) return LJMD_EINVAL;
+    if (!c->have_state) return fail(c, LJMD_ESTATE, "minimize_sd before set_state");
+    if (nsteps < 0 || !(max_disp > 0.0) || !std::isfinite(max_disp) || !(clamp >= 0.0) ||
+        !std::isfinite(clamp))
+        return fail(c, LJMD_EINVAL, "minimize_sd: bad arguments");
+    hipError_t e = hipMemsetAsync(c->st.ctl->fmax, 0, sizeof(c->st.ctl->fmax), c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "minimize_sd memset");
+    // Iteration s uses the control-word parity of id c->step + 1 + s; the
+    // final state load below uses c->step again, as after ljmd_set_state.
+    for (int32_t s = 0; s < nsteps; ++s) {
+        const int64_t t = c->step + 1 + s;
+        int r = rebuild_sequence(c, t, s == 0 ? 1 : 0, false);
+        if (r) return r;
+        if ((e = launch_sd(launcher(c), t, s == 0 ? 1 : 0, s, max_disp, clamp, fmax_dev)) !=
+            hipSuccess)
+            return hip_fail(c, e, "steepest descent");
+    }
+    int r = rebuild_sequence(c, c->step, 1, true);
+    if (r) return r;
+    Launch L = launcher(c);
+    if ((e = launch_step(L, c->step, 1, kStoreForce, (int)(c->step % kRing))) != hipSuccess)
+        return hip_fail(c, e, "force");
+    if ((e = launch_obs_reduce(L, c->step, 1, c->nblocks, nullptr, 0)) != hipSuccess)
+        return hip_fail(c, e, "obs");
+    return LJMD_OK;
 }
 
 int ljmd_get_state(ljmd_ctx *c, double *x, double *v, int32_t *img) {

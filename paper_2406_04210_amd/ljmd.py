@@ -64,6 +64,7 @@ SIGNATURES = {
     "ljmd_get_forces": (C.c_int, [_vp, _dp]),
     "ljmd_run": (C.c_int, [_vp, C.c_int64, _dp]),
     "ljmd_neighbors": (C.c_int, [_vp, _ip, _ip, C.c_int32]),
+    "ljmd_minimize_sd": (C.c_int, [_vp, C.c_int32, C.c_double, C.c_double, _dp]),
     "ljmd_sync_status": (C.c_int, [_vp]),
     "ljmd_observables": (C.c_int, [_vp, C.POINTER(Obs)]),
     "ljmd_set_profiling": (C.c_int, [_vp, C.c_int]),
@@ -216,6 +217,16 @@ class System:
         obs = t.empty((max(nsteps, 1), NOBS), dtype=t.float64, device=self.device) if observe else None
         _check(lib.ljmd_run(self.ctx, int(nsteps), _ptr(obs) if obs is not None else None), self.ctx)
         return obs[:nsteps] if obs is not None else None
+
+    def minimize_sd(self, nsteps: int, max_disp: float = 0.01, clamp: float = 0.6,
+                    record: bool = True):
+        """Steepest-descent relaxation; returns the (nsteps,) device tensor of
+        max |F| at the start of every iteration (or None)."""
+        t = self.torch
+        fm = t.zeros(max(nsteps, 1), dtype=t.float64, device=self.device) if record else None
+        _check(lib.ljmd_minimize_sd(self.ctx, int(nsteps), float(max_disp), float(clamp),
+                                    _ptr(fm) if fm is not None else None), self.ctx)
+        return fm[:nsteps] if fm is not None else None
 
     def get_state(self):
         t = self.torch

@@ -285,3 +285,23 @@ def test_fp32_energy_conservation_tracks_fp64(ljmd):
     slope32, fl32 = drifts[FP32]
     assert abs(slope32) < 5e-5 and abs(slope64) < 5e-5
     assert fl32 < 1.5 * fl64 + 1e-5
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_steepest_descent_matches_oracle(ljmd, prec):
+    # Uniform random binary mixture (overlapping pairs): the relaxation path.
+    w = W.config_mixture(n=1500, seed_index=2)
+    nsteps = 30
+    s = make_system(ljmd, w.x, w.v, w.species, w.box, w.params, prec)
+    fm = s.minimize_sd(nsteps, 0.01, 0.6).cpu().numpy()
+    xu = s.unwrapped_positions().cpu().numpy()
+    f = s.forces().cpu().numpy()
+    s.sync()
+    r = oracle.minimize_sd(w.x, w.species, w.box, w.params, nsteps, delta=0.01, clamp=0.6)
+    tol_f, tol_x = (1e-10, 1e-9) if prec == FP64 else (1e-5, 1e-4)
+    assert np.abs(fm - r["fmax"][:nsteps]).max() <= tol_f * r["fmax"][0]
+    assert np.abs(xu - r["x"]).max() <= tol_x
+    # After relaxation the context holds the unclamped forces of the new state.
+    fo, _, _ = oracle.forces(r["x"], w.species, w.box, w.params)
+    rms = np.sqrt((fo ** 2).sum(axis=1).mean())
+    assert np.abs(f - fo).max() <= (1e-9 if prec == FP64 else 1e-3) * max(rms, np.abs(fo).max())

@@ -322,3 +322,43 @@ def test_ds_split_and_fixed_point_coordinate():
             d -= L * round(d / L)
             got = float(oracle.disp_q(qa, qb, L))
             assert abs(got - d) <= 2.0 * L * 2.0 ** -32 + 2.0 * abs(d) * 2.0 ** -24
+
+
+# ---------------------------------------------------------------- SD ----
+def test_sd_energy_decreases_and_step_is_capped():
+    w = W.config_mixture(n=3000, seed_index=2)
+    r = oracle.minimize_sd(w.x, w.species, w.box, w.params, 60, delta=0.01, clamp=0.6)
+    U, fm = r["U"], r["fmax"]
+    assert np.all(np.diff(U) < 0)                        # monotone descent
+    assert U[-1] < 0.5 * U[0] and fm[-1] < fm[0]
+    d = r["x"] - w.x
+    # No particle moves more than delta per iteration.
+    assert np.linalg.norm(d, axis=1).max() <= 60 * 0.01 * (1 + 1e-12)
+
+
+def test_sd_step_follows_unclamped_force_when_no_overlap():
+    # Away from overlaps the clamp is inactive: one step is x += delta F / max|F|
+    # with F the plain truncated force from the independent list-force routine.
+    x, box = _jittered_fcc(6, 0.05, 31)
+    sp = np.zeros(len(x), np.int32)
+    p = W.single_species_params()
+    f, _, _ = oracle.forces(x, sp, box, p)
+    r = oracle.minimize_sd(x, sp, box, p, 1, delta=0.02, clamp=0.6)
+    fmax = np.linalg.norm(f, axis=1).max()
+    assert r["fmax"][0] == pytest.approx(fmax, rel=1e-13)
+    assert np.abs(r["x"] - (x + 0.02 * f / fmax)).max() < 1e-14
+
+
+def test_sd_clamp_closed_form_for_overlapping_dimer():
+    # Two particles 0.3 sigma apart: the force is evaluated at the clamp
+    # distance 0.6 sigma, magnitude fs(0.6) * 0.3, equal and opposite; each
+    # particle moves exactly delta apart along the axis.
+    p = W.single_species_params()
+    box = np.full(3, 10.0)
+    x = np.array([[5.0, 5.0, 5.0], [5.3, 5.0, 5.0]])
+    sp = np.zeros(2, np.int32)
+    r = oracle.minimize_sd(x, sp, box, p, 1, delta=0.01, clamp=0.6)
+    assert r["fmax"][0] == pytest.approx(oracle.fscalar(0.6) * 0.3, rel=1e-14)
+    assert r["x"][0, 0] == pytest.approx(4.99, abs=1e-14)
+    assert r["x"][1, 0] == pytest.approx(5.31, abs=1e-14)
+    assert r["U"][0] == pytest.approx(oracle.phi(0.6) - oracle.phi(2.5), rel=1e-14)
