@@ -111,6 +111,12 @@ def lib():
         L.oracle_minimize_sd.restype = C.c_int64
         L.oracle_minimize_sd.argtypes = [C.c_int64, dp, ip, dp, pp, C.c_int64, C.c_double,
                                          C.c_double, dp, dp]
+        L.oracle_force_vjp.restype = C.c_int32
+        L.oracle_force_vjp.argtypes = [C.c_int64, dp, ip, dp, pp, dp, dp, dp]
+        L.oracle_energy_grad.restype = C.c_int32
+        L.oracle_energy_grad.argtypes = [C.c_int64, dp, ip, dp, pp, dp]
+        L.oracle_vv_adjoint.restype = C.c_int32
+        L.oracle_vv_adjoint.argtypes = [C.c_int64, dp, dp, ip, dp, pp, C.c_int64, dp, dp, dp]
         L.oracle_num_threads.restype = C.c_int32
         L.oracle_num_threads.argtypes = []
         _lib = L
@@ -250,6 +256,63 @@ def minimize_sd(x, species, box, params, nsteps: int, delta: float = 0.01, clamp
     if b < 0:
         raise MemoryError("oracle_minimize_sd: allocation failed")
     return {"x": x, "U": u, "fmax": fm, "builds": int(b)}
+
+
+def force_vjp(x, species, box, params, g):
+    """(dF/dx)^T g and the parameter gradient of g.F per symmetric pair type.
+    Returns (gx (N,3), geps (3,), gsig (3,)) with types [AA, AB, BB]."""
+    x = _f64(x, (-1, 3))
+    g = _f64(g, (-1, 3))
+    sp, bx = _i32(species), _f64(box)
+    gx = np.zeros_like(x)
+    gt = np.zeros(6)
+    s = make_params(params)
+    if lib().oracle_force_vjp(x.shape[0], _d(x), _i(sp), _d(bx), C.byref(s), _d(g), _d(gx), _d(gt)):
+        raise MemoryError("oracle_force_vjp")
+    return gx, gt[:3].copy(), gt[3:].copy()
+
+
+def energy_grad(x, species, box, params):
+    """dU/d(eps_t), dU/d(sigma_t) per symmetric pair type [AA, AB, BB]."""
+    x = _f64(x, (-1, 3))
+    sp, bx = _i32(species), _f64(box)
+    gt = np.zeros(6)
+    s = make_params(params)
+    if lib().oracle_energy_grad(x.shape[0], _d(x), _i(sp), _d(bx), C.byref(s), _d(gt)):
+        raise MemoryError("oracle_energy_grad")
+    return gt[:3].copy(), gt[3:].copy()
+
+
+def vv_adjoint(x0, v0, species, box, params, nsteps, lam_x, lam_v):
+    """Adjoint of nsteps velocity-Verlet steps from (x0, v0): given dL/dx_N and
+    dL/dv_N returns (dL/dx_0, dL/dv_0, geps (3,), gsig (3,)) of the dynamics."""
+    x0 = _f64(x0, (-1, 3))
+    v0 = _f64(v0, (-1, 3))
+    lx = _f64(lam_x, (-1, 3)).copy()
+    lv = _f64(lam_v, (-1, 3)).copy()
+    sp, bx = _i32(species), _f64(box)
+    gt = np.zeros(6)
+    s = make_params(params)
+    if lib().oracle_vv_adjoint(x0.shape[0], _d(x0), _d(v0), _i(sp), _d(bx), C.byref(s),
+                               int(nsteps), _d(lx), _d(lv), _d(gt)):
+        raise MemoryError("oracle_vv_adjoint")
+    return lx, lv, gt[:3].copy(), gt[3:].copy()
+
+
+def with_params(params, eps=None, sigma=None):
+    """Copy of params with per-type (AA, AB, BB) eps/sigma replaced; cutoffs
+    stay the same absolute lengths."""
+    q = params.copy()
+    for name, vals in (("eps", eps), ("sigma", sigma)):
+        if vals is None:
+            continue
+        arr = getattr(q, name)
+        vals = np.atleast_1d(np.asarray(vals, dtype=np.float64))
+        if q.nspecies == 1:
+            arr[:] = vals[0]
+        else:
+            arr[0], arr[1], arr[2], arr[3] = vals[0], vals[1], vals[1], vals[2]
+    return q
 
 
 def ds_split(w: float):

@@ -524,6 +524,219 @@ int64_t oracle_minimize_sd(int64_t n, double *x, const int32_t *sp, const double
     return builds;
 }
 
+/* ---------------------------------------------------------------- O7 ---- */
+
+/* Pair-type index of the symmetric parameter: 0 = AA, 1 = AB, 2 = BB. */
+static int sym_type(const olj_t *p, int a, int b) { return p->nspecies == 1 ? 0 : a + b; }
+
+/* Unordered pairs i < j within the cutoff, from full lists (j > i). The
+ * callback receives the minimum-image displacement d = x_i - x_j and r^2. */
+typedef void (*pair_fn)(void *ctx, int64_t i, int64_t j, const double d[3], double r2, int ab);
+
+static int for_each_pair(int64_t n, const double *x, const int32_t *sp, const double *box,
+                         const olj_t *p, pair_fn fn, void *ctx) {
+    int32_t cap = 160;
+    int32_t *cnt = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *nbr = NULL;
+    if (!cnt) return -1;
+    for (;;) {
+        free(nbr);
+        nbr = (int32_t *)malloc(sizeof(int32_t) * (size_t)n * cap);
+        if (!nbr) return -1;
+        int32_t mx = oracle_build_lists(n, x, sp, box, p, 0, cap, cnt, nbr);
+        if (mx <= cap) break;
+        cap = mx + 16;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int32_t k = 0; k < cnt[i]; ++k) {
+            int64_t j = nbr[(size_t)i * cap + k];
+            if (j <= i) continue;
+            double d[3];
+            min_image(x + 3 * i, x + 3 * j, box, d);
+            double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            int ab = pair_index(p, sp[i], sp[j]);
+            if (r2 >= p->rcut[ab] * p->rcut[ab]) continue;
+            fn(ctx, i, j, d, r2, ab);
+        }
+    free(cnt);
+    free(nbr);
+    return 0;
+}
+
+typedef struct {
+    const olj_t *p;
+    const int32_t *sp;
+    const double *g;
+    double *gx;
+    double gt[6];  /* d/d eps_t (t = 0..2), d/d sigma_t */
+} vjp_ctx;
+
+/* Vector-Jacobian product of the forces: for a cotangent g (N x 3),
+ *   gx_i = sum_j [ fs D + 2 (dfs/dr^2) (d.D) d ],  D = g_i - g_j,
+ * i.e. (dF/dx)^T g, with fs = 24 eps (2 s12 - s6) / r^2 and
+ * dfs/d(r^2) = -(24 eps / r^4)(14 s12 - 4 s6), s6 = (sigma/r)^6, s12 = s6^2;
+ * and the parameter gradients of g.F summed per symmetric pair type:
+ *   d(g.F)/d eps   += D.f_ij / eps,
+ *   d(g.F)/d sigma += (D.d) (144 eps / sigma) (4 s12 - s6) / r^2.
+ * The force is differentiated where it is smooth (r < r_c); its jump at
+ * r_c has no derivative term. */
+static void vjp_pair(void *vc, int64_t i, int64_t j, const double d[3], double r2, int ab) {
+    vjp_ctx *c = (vjp_ctx *)vc;
+    const olj_t *p = c->p;
+    double eps = p->eps[ab], sig = p->sigma[ab];
+    double s2 = sig * sig / r2, s6 = s2 * s2 * s2, s12 = s6 * s6;
+    double fs = 24.0 * eps * (2.0 * s12 - s6) / r2;
+    double dfs = -(24.0 * eps / (r2 * r2)) * (14.0 * s12 - 4.0 * s6);
+    double D[3], dD = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        D[k] = c->g[3 * i + k] - c->g[3 * j + k];
+        dD += d[k] * D[k];
+    }
+    for (int k = 0; k < 3; ++k) {
+        double t = fs * D[k] + 2.0 * dfs * dD * d[k];
+        c->gx[3 * i + k] += t;
+        c->gx[3 * j + k] -= t;
+    }
+    int t = sym_type(p, c->sp[i], c->sp[j]);
+    if (eps != 0.0) c->gt[t] += fs * dD / eps;
+    c->gt[3 + t] += dD * (144.0 * eps / sig) * (4.0 * s12 - s6) / r2;
+}
+
+int32_t oracle_force_vjp(int64_t n, const double *x, const int32_t *sp, const double *box,
+                         const olj_t *p, const double *g, double *gx, double *gtheta) {
+    vjp_ctx c;
+    c.p = p;
+    c.sp = sp;
+    c.g = g;
+    c.gx = gx;
+    memset(gx, 0, sizeof(double) * 3 * (size_t)n);
+    memset(c.gt, 0, sizeof c.gt);
+    if (for_each_pair(n, x, sp, box, p, vjp_pair, &c)) return -1;
+    memcpy(gtheta, c.gt, sizeof c.gt);
+    return 0;
+}
+
+/* Parameter gradient of the truncated, shifted potential energy, with r_c a
+ * fixed length and the shift phi(r_c; eps, sigma) differentiated too:
+ *   dU/d eps_t   = sum phi_s / eps,
+ *   dU/d sigma_t = sum (4 eps / sigma) [(12 s12 - 6 s6) - (12 s12 - 6 s6)|_{r_c}]. */
+typedef struct {
+    const olj_t *p;
+    const int32_t *sp;
+    double gt[6];
+} eg_ctx;
+
+static void eg_pair(void *vc, int64_t i, int64_t j, const double d[3], double r2, int ab) {
+    (void)d;
+    eg_ctx *c = (eg_ctx *)vc;
+    const olj_t *p = c->p;
+    double eps = p->eps[ab], sig = p->sigma[ab], rc = p->rcut[ab];
+    double s2 = sig * sig / r2, s6 = s2 * s2 * s2, s12 = s6 * s6;
+    double c2 = sig * sig / (rc * rc), c6 = c2 * c2 * c2, c12 = c6 * c6;
+    int t = sym_type(p, c->sp[i], c->sp[j]);
+    double phis = 4.0 * (s12 - s6) - (p->shift_energy ? 4.0 * (c12 - c6) : 0.0);
+    c->gt[t] += phis;
+    double dsig = (12.0 * s12 - 6.0 * s6) - (p->shift_energy ? (12.0 * c12 - 6.0 * c6) : 0.0);
+    c->gt[3 + t] += 4.0 * eps / sig * dsig;
+}
+
+int32_t oracle_energy_grad(int64_t n, const double *x, const int32_t *sp, const double *box,
+                           const olj_t *p, double *gtheta) {
+    eg_ctx c;
+    c.p = p;
+    c.sp = sp;
+    memset(c.gt, 0, sizeof c.gt);
+    if (for_each_pair(n, x, sp, box, p, eg_pair, &c)) return -1;
+    memcpy(gtheta, c.gt, sizeof c.gt);
+    return 0;
+}
+
+/* Forces of a configuration via freshly built lists (any N). Returns 0/-1. */
+static int forces_fresh(int64_t n, const double *x, const int32_t *sp, const double *box,
+                        const olj_t *p, double *f, double *uw) {
+    int32_t cap = 160;
+    int32_t *cnt = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *nbr = NULL;
+    if (!cnt) return -1;
+    for (;;) {
+        free(nbr);
+        nbr = (int32_t *)malloc(sizeof(int32_t) * (size_t)n * cap);
+        if (!nbr) return -1;
+        int32_t mx = oracle_build_lists(n, x, sp, box, p, 0, cap, cnt, nbr);
+        if (mx <= cap) break;
+        cap = mx + 16;
+    }
+    oracle_forces_list(n, x, sp, box, p, cap, cnt, nbr, f, uw);
+    free(cnt);
+    free(nbr);
+    return 0;
+}
+
+/* ---------------------------------------------------------------- O9 ---- */
+
+/* Adjoint of nsteps velocity-Verlet steps (every frame stored; no
+ * checkpointing). Forward: v' = v_n + dt/2 a(x_n); x_{n+1} = x_n + dt v';
+ * v_{n+1} = v' + dt/2 a(x_{n+1}), a = F/m. Given lam_x = dL/dx_N and
+ * lam_v = dL/dv_N (in place: on return they hold dL/dx_0 and dL/dv_0 of the
+ * dynamics part), the reverse sweep is, for n = N-1 .. 0,
+ *   lam_v' = lam_v;  lam_x += dt/2 J(x_{n+1})^T lam_v;  g_th += dt/2 da/dth^T lam_v
+ *   lam_v' += dt lam_x
+ *   lam_v = lam_v';  lam_x += dt/2 J(x_n)^T lam_v';      g_th += dt/2 da/dth^T lam_v'
+ * with J^T lam = (dF/dx)^T (lam / m) (a force VJP with the cotangent divided
+ * by the mass). gtheta (6) accumulates. Returns 0, or -1 on failure. */
+int32_t oracle_vv_adjoint(int64_t n, const double *x0, const double *v0, const int32_t *sp,
+                          const double *box, const olj_t *p, int64_t nsteps, double *lam_x,
+                          double *lam_v, double *gtheta) {
+    size_t nn = 3 * (size_t)n;
+    double *frames = (double *)malloc(sizeof(double) * nn * (size_t)(nsteps + 1));
+    double *x = (double *)malloc(sizeof(double) * nn);
+    double *v = (double *)malloc(sizeof(double) * nn);
+    double *f = (double *)malloc(sizeof(double) * nn);
+    double *g = (double *)malloc(sizeof(double) * nn);
+    double *gx = (double *)malloc(sizeof(double) * nn);
+    double *invm = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!frames || !x || !v || !f || !g || !gx || !invm) return -1;
+    for (int64_t i = 0; i < n; ++i) invm[i] = 1.0 / p->mass[p->nspecies == 2 ? sp[i] : 0];
+    memcpy(x, x0, sizeof(double) * nn);
+    memcpy(v, v0, sizeof(double) * nn);
+    memcpy(frames, x, sizeof(double) * nn);
+    double uw[2];
+    if (forces_fresh(n, x, sp, box, p, f, uw)) return -1;
+    double h = 0.5 * p->dt;
+    for (int64_t s = 1; s <= nsteps; ++s) {
+        for (size_t k = 0; k < nn; ++k) {
+            v[k] += h * f[k] * invm[k / 3];
+            x[k] += p->dt * v[k];
+        }
+        if (forces_fresh(n, x, sp, box, p, f, uw)) return -1;
+        for (size_t k = 0; k < nn; ++k) v[k] += h * f[k] * invm[k / 3];
+        memcpy(frames + nn * (size_t)s, x, sizeof(double) * nn);
+    }
+    double gt[6];
+    for (int64_t s = nsteps - 1; s >= 0; --s) {
+        /* second half kick of step s -> s+1, at x_{s+1} */
+        for (size_t k = 0; k < nn; ++k) g[k] = lam_v[k] * invm[k / 3];
+        if (oracle_force_vjp(n, frames + nn * (size_t)(s + 1), sp, box, p, g, gx, gt)) return -1;
+        for (size_t k = 0; k < nn; ++k) lam_x[k] += h * gx[k];
+        for (int q = 0; q < 6; ++q) gtheta[q] += h * gt[q];
+        /* drift */
+        for (size_t k = 0; k < nn; ++k) lam_v[k] += p->dt * lam_x[k];
+        /* first half kick, at x_s */
+        for (size_t k = 0; k < nn; ++k) g[k] = lam_v[k] * invm[k / 3];
+        if (oracle_force_vjp(n, frames + nn * (size_t)s, sp, box, p, g, gx, gt)) return -1;
+        for (size_t k = 0; k < nn; ++k) lam_x[k] += h * gx[k];
+        for (int q = 0; q < 6; ++q) gtheta[q] += h * gt[q];
+    }
+    free(frames);
+    free(x);
+    free(v);
+    free(f);
+    free(g);
+    free(gx);
+    free(invm);
+    return 0;
+}
+
 int32_t oracle_num_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();

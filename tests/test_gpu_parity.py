@@ -12,7 +12,11 @@ from the oracle. Tolerances:
     the path's precision, found from the FP64 positions) may additionally
     differ by the force jump |F(r_c)| per such partner, because the truncated
     force is discontinuous there and binary32 decides r^2 < r_c^2;
-  * U/N, W/N: relative 1e-12 (FP64), 1e-6 (FP32+DS);
+  * U/N, W/N: relative 1e-12 (FP64), 5e-6 (FP32+DS). The FP32 bound follows
+    from the arithmetic: s^12 = u^6 multiplies the relative error of r^2
+    (~2e-7 from the binary32 displacement) and of the 1-ulp reciprocal
+    (1.2e-7) six times, so a repulsion-dominated energy sum can be off by
+    ~2.6e-6 relative;
   * 100-step trajectories (N=2048): max |dx| <= 1e-10 sigma, |dv| <= 1e-9
     (FP64); <= 1e-4 and <= 1e-3 (FP32+DS).
 """
@@ -28,7 +32,7 @@ pytestmark = pytest.mark.gpu
 
 FP64, FP32 = 0, 1
 TOL_F = {FP64: 1e-12, FP32: 1e-5}
-TOL_E = {FP64: 1e-12, FP32: 1e-6}
+TOL_E = {FP64: 1e-12, FP32: 5e-6}
 
 
 @pytest.fixture(scope="module")
