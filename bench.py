@@ -30,6 +30,36 @@ if ROOT not in sys.path:
 METRIC = "particle-steps/s, LJ NVE N=256k on 1 GPU; adjoint/forward time ratio"
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the FP32+DS step kernel on this workload, from two
+# hardware counter passes (FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0, the factors a
+# 512 MiB copy reads), valid only for the kernel sources they were taken on.
+STEP_KERNEL_SOURCES = ("k_step.hip", "step_common.h", "internal.h")
+STEP_KERNEL_TRAFFIC = {
+    "sources_sha256": "597a8e0ecf337c58f8bcef20657a043e3d67b871f167d1215d14672ce5d79a1a",
+    "fetch_bytes": 2.0 * 54038 * 1024,
+    "write_bytes": 1.0 * 20128 * 1024,
+}
+
+
+def step_kernel_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in STEP_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2406_04210_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """Counter-measured bytes per step-kernel launch, or None once the kernel
+    sources differ from those the counters were taken on."""
+    try:
+        if step_kernel_digest() != STEP_KERNEL_TRAFFIC["sources_sha256"]:
+            return None
+    except OSError:
+        return None
+    return STEP_KERNEL_TRAFFIC["fetch_bytes"] + STEP_KERNEL_TRAFFIC["write_bytes"]
+
 
 def algorithmic_bytes_per_particle(prec: int, mean_list: float) -> float:
     """HBM bytes one particle-step of the fused step kernel must move:
@@ -136,7 +166,9 @@ def main():
     bpp = algorithmic_bytes_per_particle(ljmd.FP32_DS, prof_run["mean_list"])
     achieved = bpp * w.n / avg_step_kernel_s / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "algorithmic_bytes_per_launch": bpp * w.n,
                 "kernel": "k_step_ds (forces + velocity Verlet + reductions)",
                 "avg_kernel_us": avg_step_kernel_s * 1e6,
                 "bytes_per_particle": bpp, "mean_list_len": prof_run["mean_list"]}
