@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define LJMD_ABI_VERSION 1
+#define LJMD_ABI_VERSION 2
 
 enum ljmd_status {
     LJMD_OK = 0,
@@ -185,14 +185,88 @@ int ljmd_observables(ljmd_ctx *ctx, ljmd_obs *out);
  * kernel (forces + velocity Verlet + reductions), [1] the rebuild sequence
  * (binning, canonical order, list build -- launched every step, working
  * only when a rebuild is due), [2] the space-filling-curve resort,
- * [3] everything else (integrate at run start, observable flushes).
- * ljmd_set_profiling(ctx, 1) starts accumulating (and clears the sums);
- * ljmd_kernel_times synchronises and writes total milliseconds ms[4] and
- * launch counts count[4] (host arrays). Events cost a few microseconds of
- * enqueue work per launch; leave profiling off for throughput runs. */
-#define LJMD_NKT 4
+ * [3] everything else (integrate at run start, observable flushes),
+ * [4] the adjoint pair pass (force VJP) of ljmd_vv_backward and
+ * ljmd_force_vjp. ljmd_set_profiling(ctx, 1) starts accumulating (and
+ * clears the sums); ljmd_kernel_times synchronises and writes total
+ * milliseconds ms[5] and launch counts count[5] (host arrays). Events cost a
+ * few microseconds of enqueue work per launch; leave profiling off for
+ * throughput runs. */
+#define LJMD_NKT 5
 int ljmd_set_profiling(ljmd_ctx *ctx, int enable);
 int ljmd_kernel_times(ljmd_ctx *ctx, double ms[LJMD_NKT], int64_t count[LJMD_NKT]);
+
+/* ---- Gradients ------------------------------------------------------------
+ * The paper computes no gradients; these differentiate its truncated 12-6
+ * pair potential (Sec. 4, Sec. 5) and its velocity-Verlet step (Sec. 3,
+ * Fig. 1). Only pairs inside the cutoff contribute: the force jump at r_c
+ * adds nothing, so every gradient is that of the truncated function almost
+ * everywhere. The cutoff r_c is a fixed length (it does not scale with
+ * sigma); the energy shift moves with eps and sigma. Parameter gradients are
+ * six float64 in the order
+ *   [d/d eps_AA, d/d eps_AB, d/d eps_BB, d/d sigma_AA, d/d sigma_AB, d/d sigma_BB]
+ * (one species: entries 0 and 3, the rest 0). Pair arithmetic runs in the
+ * context's precision; parameter sums are float64 in a fixed order. */
+
+/* Replace eps and sigma (host, 4 entries each, the ljmd_params layout
+ * [AA, AB, BA, BB] with AB == BA; cutoffs, masses and skin stay). With a
+ * state loaded, its forces and observables are re-evaluated (the lists
+ * depend only on cutoffs and skin and are kept). Asynchronous. */
+int ljmd_set_pair_params(ljmd_ctx *ctx, const double eps[4], const double sigma[4]);
+
+/* Force vector-Jacobian product at the current state: for a cotangent g
+ * (device, n*3 float64, by id) writes gx = (dF/dx)^T g (device, n*3
+ * float64, by id; dF/dx is minus the Hessian of U) and gtheta =
+ * d(g.F)/d(eps, sigma) (device, 6 float64). g is read before gx is
+ * written, so they may alias. Uses the workspace's scratch area.
+ * Asynchronous. */
+int ljmd_force_vjp(ljmd_ctx *ctx, const double *g, double *gx, double *gtheta);
+
+/* Parameter gradient of the potential energy at the current state: gtheta
+ * (device, 6 float64) = dU/d(eps, sigma). The position gradient of U is -F
+ * (ljmd_get_forces). Asynchronous. */
+int ljmd_energy_grad(ljmd_ctx *ctx, double *gtheta);
+
+/* Flags of a differentiable rollout. LJMD_ADJ_STORE_ALL: the forward run
+ * keeps every position frame and the reverse sweep reads them instead of
+ * recomputing segments (more memory, no recompute; same results bit for
+ * bit, since a recompute repeats the forward run exactly). */
+#define LJMD_ADJ_STORE_ALL 1
+
+/* Device bytes ljmd_vv_forward needs for nsteps >= 1 steps with a
+ * checkpoint every ckpt_every >= 1 steps (0 if an argument is invalid):
+ * ceil(nsteps / ckpt_every) + 1 state copies, ckpt_every + 1 position
+ * frames for the recompute (nsteps + 1 with LJMD_ADJ_STORE_ALL) and three
+ * per-particle adjoint vectors. */
+size_t ljmd_adjoint_workspace_size(const ljmd_params *p, int32_t nsteps, int32_t ckpt_every,
+                                   int32_t flags);
+
+/* Differentiable rollout: nsteps velocity-Verlet steps from the current
+ * state, as ljmd_run except that (a) before every ckpt_every-th step the
+ * state is stored in adj_ws and that step's list build is forced, (b) no
+ * space-filling-curve resort happens, (c) the lists are rebuilt at the final
+ * state. With (a) the recompute of a segment from its checkpoint repeats
+ * the forward run bit for bit. adj_ws (device, >= ljmd_adjoint_workspace_size
+ * bytes for the same arguments, 256-byte aligned) stays the caller's and
+ * must live until the matching ljmd_vv_backward. flags: 0 or
+ * LJMD_ADJ_STORE_ALL. obs_dev as in ljmd_run. Asynchronous. */
+int ljmd_vv_forward(ljmd_ctx *ctx, int32_t nsteps, int32_t ckpt_every, int32_t flags, void *adj_ws,
+                    size_t bytes, double *obs_dev);
+
+/* Reverse sweep of the last ljmd_vv_forward. From lam_x = dL/dx_N and
+ * lam_v = dL/dv_N (device, n*3 float64, by id) for a loss L of the final
+ * state, writes gx0 = dL/dx_0 and gv0 = dL/dv_0 (device, n*3 float64, by
+ * id; may alias lam_x, lam_v) and gtheta = dL/d(eps, sigma) through the
+ * dynamics (device, 6 float64). Segments are taken last first: each is
+ * recomputed from its checkpoint (or read, with LJMD_ADJ_STORE_ALL) and its
+ * frames swept backwards with one force VJP per frame (cotangent lam_v / m,
+ * weight dt/2 at x_N and x_0, dt between). The lists are built afresh at
+ * the first frame of every segment and again whenever a frame is more than
+ * skin/2 from the last build. Leaves the context at the final state, as
+ * ljmd_vv_forward did. LJMD_ESTATE if no rollout is recorded or the state
+ * changed since. Asynchronous. */
+int ljmd_vv_backward(ljmd_ctx *ctx, const double *lam_x, const double *lam_v, double *gx0,
+                     double *gv0, double *gtheta);
 
 /* Text of the last error of ctx (or of the last failed create when ctx is
  * NULL). The pointer stays valid until the next call on ctx. */

@@ -1,0 +1,44 @@
+// adjoint.h -- launchers of the adjoint kernels (k_adjoint.hip): the force
+// vector-Jacobian product with the parameter gradients, the energy parameter
+// gradient, and the per-particle vector operations of the reverse
+// velocity-Verlet sweep.
+#pragma once
+
+#include "internal.h"
+
+namespace ljmd {
+
+// Pair pass modes.
+enum : int { kAdjVjp = 0, kAdjEnergy = 1 };
+
+// Per-particle operations of the reverse sweep (slot order unless noted).
+enum : int {
+    kOpGatherById = 0,   // a[i] = src_id[id[i]]        (FP64 triples by original id)
+    kOpScatterById = 1,  // dst_id[id[i]] = a[i]
+    kOpCotangent = 2,    // gvec[i] = b[i] / m_i        (path precision: double4 or float4)
+    kOpDrift = 3,        // b[i] += scale * a[i]
+    kOpZero = 4,         // a[i] = 0
+    kOpGatherG = 5,      // gvec[i] = src_id[id[i]]     (path precision)
+};
+
+// One pair pass over the current lists at the positions in record buffer
+// L.cur. kAdjVjp: gx[i] += weight * ((dF/dx)^T g)_i with g = gvec (slot order),
+// and gtheta[0..5] (+)= weight * d(g.F)/d(eps_t, sigma_t). kAdjEnergy:
+// gtheta (+)= weight * dU/d(eps_t, sigma_t). gtheta is overwritten when init
+// is set, else accumulated. Block partial rows go to the first ring slot of
+// the observable partials.
+hipError_t launch_adjoint_pairs(const Launch &L, int mode, const void *gvec, double4 *gx, double weight,
+                                double *gtheta, int init);
+
+// Clear the cell counters if the lists were rebuilt for `step` (in a forward
+// run the step kernel does this).
+hipError_t launch_adjoint_cells(const Launch &L, int64_t step, int forced);
+
+hipError_t launch_adjoint_vec(const Launch &L, int op, const double *src_id, double *dst_id, double4 *a,
+                              double4 *b, void *gvec, double scale);
+
+// Displacement of the positions in record buffer L.cur from the list
+// reference, folded into the rebuild decision of `step`.
+hipError_t launch_frame_disp(const Launch &L, int64_t step);
+
+}  // namespace ljmd

@@ -11,12 +11,34 @@
 #include <string>
 #include <vector>
 
+#include "adjoint.h"
 #include "internal.h"
 
 namespace ljmd {
 }
 
 using namespace ljmd;
+
+// Workspace layout of a differentiable rollout (ljmd_vv_forward).
+struct AdjPlan {
+    int32_t nsteps = 0, every = 0, nseg = 0;
+    bool store_all = false;   // every frame kept by the forward run
+    size_t ckpt_stride = 0;   // bytes of one stored state
+    size_t off_ckpt = 0;      // (nseg + 1) stored states
+    size_t frame_stride = 0;  // bytes of one position frame (record buffer)
+    size_t off_frames = 0;    // every + 1 frames (nsteps + 1 when store_all)
+    size_t off_lx = 0, off_lv = 0, off_g = 0;
+    size_t total = 0;
+};
+
+// The rollout recorded by the last ljmd_vv_forward.
+struct AdjRecord {
+    bool valid = false;
+    AdjPlan plan;
+    uint8_t *ws = nullptr;
+    int64_t step0 = 0;
+    uint64_t gen = 0;
+};
 
 struct ljmd_ctx {
     ljmd_params p;
@@ -37,8 +59,11 @@ struct ljmd_ctx {
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<std::pair<int, size_t>> ev_marks;  // (family, index of start event)
-    double ms[LJMD_NKT] = {0, 0, 0, 0};
-    int64_t count[LJMD_NKT] = {0, 0, 0, 0};
+    double ms[LJMD_NKT] = {};
+    int64_t count[LJMD_NKT] = {};
+    // Bumped by every call that changes the dynamical state or the potential.
+    uint64_t gen = 0;
+    AdjRecord adj;
     ~ljmd_ctx() {
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     }
@@ -239,6 +264,8 @@ uint64_t hilbert_index3(uint32_t x, uint32_t y, uint32_t z, int bits) {
     return h;
 }
 
+void fill_pairs(PairC &q, const ljmd_params &p);
+
 void fill_constants(ljmd_ctx *c, const Plan &pl) {
     const ljmd_params &p = c->p;
     BoxC &b = c->box;
@@ -260,7 +287,24 @@ void fill_constants(ljmd_ctx *c, const Plan &pl) {
         b.nc[k] = pl.nc[k];
     }
     b.ncell = pl.ncell;
-    PairC &q = c->pc;
+    fill_pairs(c->pc, p);
+    DynC &d = c->dyn;
+    for (int s = 0; s < 2; ++s) {
+        const double m = p.mass[p.nspecies == 2 ? s : 0];
+        d.mass[s] = m;
+        d.massf[s] = (float)m;
+        d.hdt_m[s] = 0.5 * p.dt / m;
+        d.hdt_m_hi[s] = (float)d.hdt_m[s];
+        d.hdt_m_lo[s] = (float)(d.hdt_m[s] - (double)d.hdt_m_hi[s]);
+    }
+    d.dt = p.dt;
+    d.dt_hi = (float)p.dt;
+    d.dt_lo = (float)(p.dt - (double)d.dt_hi);
+    d.thr2 = (float)(0.25 * p.skin * p.skin);
+}
+
+// Pair constants per symmetric type (AA, AB, BB) from the 4-entry tables.
+void fill_pairs(PairC &q, const ljmd_params &p) {
     const int src[3] = {0, 1, 3};
     for (int t = 0; t < 3; ++t) {
         const int ab = p.nspecies == 1 ? 0 : src[t];
@@ -280,19 +324,6 @@ void fill_constants(ljmd_ctx *c, const Plan &pl) {
         q.eps4f[t] = (float)q.eps4[t];
         q.shiftf[t] = (float)q.shift[t];
     }
-    DynC &d = c->dyn;
-    for (int s = 0; s < 2; ++s) {
-        const double m = p.mass[p.nspecies == 2 ? s : 0];
-        d.mass[s] = m;
-        d.massf[s] = (float)m;
-        d.hdt_m[s] = 0.5 * p.dt / m;
-        d.hdt_m_hi[s] = (float)d.hdt_m[s];
-        d.hdt_m_lo[s] = (float)(d.hdt_m[s] - (double)d.hdt_m_hi[s]);
-    }
-    d.dt = p.dt;
-    d.dt_hi = (float)p.dt;
-    d.dt_lo = (float)(p.dt - (double)d.dt_hi);
-    d.thr2 = (float)(0.25 * p.skin * p.skin);
 }
 
 // Timing bracket around a group of launches of one kernel family.
@@ -374,6 +405,164 @@ int rebuild_sequence(ljmd_ctx *c, int64_t step, int forced, bool resort) {
     if ((e = launch_canon(L, step, forced)) != hipSuccess) return hip_fail(c, e, "canon");
     if ((e = launch_nlist(L, step, forced)) != hipSuccess) return hip_fail(c, e, "nlist");
     return LJMD_OK;
+}
+
+int64_t padded(int64_t n) { return (n + 63) / 64 * 64; }
+
+size_t rec_bytes(int prec) { return prec == LJMD_FP64 ? sizeof(double4) : sizeof(int4); }
+
+void *rec_ptr(const ljmd_ctx *c, int which) {
+    return c->g.prec == LJMD_FP64 ? (void *)c->st.rec64[which] : (void *)c->st.recq[which];
+}
+
+struct RunOpts {
+    bool force_first = false;   // force the list build of the first step
+    bool allow_resort = true;   // space-filling-curve resort every sort_interval steps
+    bool final_obs = true;      // refresh the stored observables when obs_dev is NULL
+    uint8_t *frames = nullptr;  // if set: record buffer before the run and after every step
+    size_t frame_stride = 0;
+};
+
+// nsteps velocity-Verlet steps from a state at rest (positions, velocities
+// and forces of step c->step): integrate from the stored forces, then per
+// step the rebuild sequence and the fused step kernel.
+int run_steps(ljmd_ctx *c, int64_t nsteps, double *obs_dev, const RunOpts &o) {
+    hipError_t e;
+    const size_t fb = rec_bytes(c->g.prec) * (size_t)c->g.n;
+    if (o.frames && (e = hipMemcpyAsync(o.frames, rec_ptr(c, c->cur), fb, hipMemcpyDeviceToDevice,
+                                        c->stream)) != hipSuccess)
+        return hip_fail(c, e, "frame copy");
+    Launch L = launcher(c);
+    {
+        Bracket b(c, 3);
+        if ((e = launch_integrate(L, c->step)) != hipSuccess) return hip_fail(c, e, "integrate");
+    }
+    c->cur ^= 1;
+    int64_t first = c->step + 1;
+    int pending = 0;
+    int64_t row = 0;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        const int64_t s = c->step + 1 + k;
+        const bool resort = o.allow_resort && c->p.sort_interval > 0 && s % c->p.sort_interval == 0;
+        const int forced = (resort || (o.force_first && k == 0)) ? 1 : 0;
+        int r = rebuild_sequence(c, s, forced, resort);
+        if (r) return r;
+        const bool last = k == nsteps - 1;
+        const int mode = kFinalize | (last ? kStoreForce : kIntegrate);
+        L = launcher(c);
+        {
+            Bracket b(c, 0);
+            if ((e = launch_step(L, s, forced, mode, (int)(s % kRing))) != hipSuccess)
+                return hip_fail(c, e, "step");
+        }
+        if (o.frames &&
+            (e = hipMemcpyAsync(o.frames + (size_t)(k + 1) * o.frame_stride, rec_ptr(c, c->cur), fb,
+                                hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
+            return hip_fail(c, e, "frame copy");
+        if (!last) c->cur ^= 1;
+        ++pending;
+        if (obs_dev && (pending == kRing || last)) {
+            Bracket b(c, 3);
+            if ((e = launch_obs_reduce(L, first, pending, c->nblocks, obs_dev, row)) != hipSuccess)
+                return hip_fail(c, e, "obs");
+            row += pending;
+            first += pending;
+            pending = 0;
+        }
+    }
+    if (!obs_dev && o.final_obs) {
+        Bracket b(c, 3);
+        if ((e = launch_obs_reduce(L, c->step + nsteps, 1, c->nblocks, nullptr, 0)) != hipSuccess)
+            return hip_fail(c, e, "obs");
+    }
+    c->step += nsteps;
+    // Keep the event pool bounded on long profiled runs.
+    if (c->profiling && c->ev_used > 8192) return resolve_times(c);
+    return LJMD_OK;
+}
+
+// ---- differentiable rollout ----------------------------------------------
+// A stored state is the record buffer in use plus the dynamical arrays:
+// positions (double-single parts), velocities, forces of the step and image
+// counters -- everything the next "integrate" reads.
+int ckpt_elems(int prec, size_t elem[8]) {
+    int k = 0;
+    elem[k++] = rec_bytes(prec);
+    if (prec == LJMD_FP64) {
+        elem[k++] = sizeof(double4);  // velocities
+        elem[k++] = sizeof(double4);  // forces
+    } else {
+        for (int q = 0; q < 5; ++q) elem[k++] = sizeof(float4);  // pos hi/lo, vel hi/lo, forces
+    }
+    elem[k++] = sizeof(int4);  // image counters
+    return k;
+}
+
+AdjPlan adj_plan(const ljmd_params *p, int32_t nsteps, int32_t every, int32_t flags) {
+    AdjPlan a;
+    const int64_t npad = padded(p->n);
+    size_t elem[8];
+    const int ne = ckpt_elems(p->precision, elem);
+    for (int q = 0; q < ne; ++q) a.ckpt_stride += al(elem[q] * (size_t)npad);
+    a.nsteps = nsteps;
+    a.every = every;
+    a.nseg = (nsteps + every - 1) / every;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += al(bytes);
+        return o;
+    };
+    a.off_ckpt = take((size_t)(a.nseg + 1) * a.ckpt_stride);
+    a.frame_stride = al(rec_bytes(p->precision) * (size_t)npad);
+    a.store_all = (flags & LJMD_ADJ_STORE_ALL) != 0;
+    const int32_t nframes = a.store_all ? nsteps + 1 : std::min(every, nsteps) + 1;
+    a.off_frames = take((size_t)nframes * a.frame_stride);
+    a.off_lx = take(sizeof(double4) * (size_t)npad);
+    a.off_lv = take(sizeof(double4) * (size_t)npad);
+    a.off_g = take(sizeof(double4) * (size_t)npad);
+    a.total = off;
+    return a;
+}
+
+// Copy the state into (save) or out of (restore) one stored state.
+int ckpt_copy(ljmd_ctx *c, uint8_t *dst, bool save) {
+    void *arr[8];
+    int k = 0;
+    arr[k++] = rec_ptr(c, c->cur);
+    if (c->g.prec == LJMD_FP64) {
+        arr[k++] = c->st.vel64;
+        arr[k++] = c->st.frc64;
+    } else {
+        arr[k++] = c->st.pos_hi;
+        arr[k++] = c->st.pos_lo;
+        arr[k++] = c->st.vel_hi;
+        arr[k++] = c->st.vel_lo;
+        arr[k++] = c->st.frc32;
+    }
+    arr[k++] = c->st.img;
+    size_t elem[8];
+    const int ne = ckpt_elems(c->g.prec, elem);
+    if (ne != k) return fail(c, LJMD_EINVAL, "internal: checkpoint layout");
+    const int64_t npad = padded(c->g.n);
+    size_t off = 0;
+    for (int q = 0; q < ne; ++q) {
+        const size_t bytes = elem[q] * (size_t)c->g.n;
+        hipError_t e = save ? hipMemcpyAsync(dst + off, arr[q], bytes, hipMemcpyDeviceToDevice, c->stream)
+                            : hipMemcpyAsync(arr[q], dst + off, bytes, hipMemcpyDeviceToDevice, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, save ? "checkpoint save" : "checkpoint restore");
+        off += al(elem[q] * (size_t)npad);
+    }
+    return LJMD_OK;
+}
+
+// Lists built for `step` at the positions in use, cell counters cleared:
+// the state at rest that ljmd_vv_forward leaves and ljmd_vv_backward restores.
+int rebuild_at_rest(ljmd_ctx *c, int64_t step) {
+    int r = rebuild_sequence(c, step, 1, false);
+    if (r) return r;
+    hipError_t e = launch_adjoint_cells(launcher(c), step, 1);
+    return e == hipSuccess ? LJMD_OK : hip_fail(c, e, "clear cells");
 }
 
 }  // namespace
@@ -520,6 +709,7 @@ int ljmd_set_state(ljmd_ctx *c, const double *x, const double *v, const int32_t 
     if (!x || !v || !species) return fail(c, LJMD_EINVAL, "set_state: NULL array");
     c->cur = 0;
     c->step = 0;
+    ++c->gen;
     hipError_t e = hipMemsetAsync(c->st.ctl, 0, sizeof(Ctl), c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->st.cell_count, 0, sizeof(int32_t) * c->box.ncell, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "set_state memset");
@@ -540,50 +730,8 @@ int ljmd_run(ljmd_ctx *c, int64_t nsteps, double *obs_dev) {
     if (!c->have_state) return fail(c, LJMD_ESTATE, "run before set_state");
     if (nsteps < 0) return fail(c, LJMD_EINVAL, "nsteps < 0");
     if (nsteps == 0) return LJMD_OK;
-    hipError_t e;
-    Launch L = launcher(c);
-    {
-        Bracket b(c, 3);
-        if ((e = launch_integrate(L, c->step)) != hipSuccess) return hip_fail(c, e, "integrate");
-    }
-    c->cur ^= 1;
-    int64_t first = c->step + 1;
-    int pending = 0;
-    int64_t row = 0;
-    for (int64_t k = 0; k < nsteps; ++k) {
-        const int64_t s = c->step + 1 + k;
-        const bool resort = c->p.sort_interval > 0 && s % c->p.sort_interval == 0;
-        const int forced = resort ? 1 : 0;
-        int r = rebuild_sequence(c, s, forced, resort);
-        if (r) return r;
-        const bool last = k == nsteps - 1;
-        const int mode = kFinalize | (last ? kStoreForce : kIntegrate);
-        L = launcher(c);
-        {
-            Bracket b(c, 0);
-            if ((e = launch_step(L, s, forced, mode, (int)(s % kRing))) != hipSuccess)
-                return hip_fail(c, e, "step");
-        }
-        if (!last) c->cur ^= 1;
-        ++pending;
-        if (obs_dev && (pending == kRing || last)) {
-            Bracket b(c, 3);
-            if ((e = launch_obs_reduce(L, first, pending, c->nblocks, obs_dev, row)) != hipSuccess)
-                return hip_fail(c, e, "obs");
-            row += pending;
-            first += pending;
-            pending = 0;
-        }
-    }
-    if (!obs_dev) {
-        Bracket b(c, 3);
-        if ((e = launch_obs_reduce(L, c->step + nsteps, 1, c->nblocks, nullptr, 0)) != hipSuccess)
-            return hip_fail(c, e, "obs");
-    }
-    c->step += nsteps;
-    // Keep the event pool bounded on long profiled runs.
-    if (c->profiling && c->ev_used > 8192) return resolve_times(c);
-    return LJMD_OK;
+    ++c->gen;
+    return run_steps(c, nsteps, obs_dev, RunOpts{});
 }
 
 int ljmd_set_profiling(ljmd_ctx *c, int enable) {
@@ -613,6 +761,7 @@ int ljmd_minimize_sd(ljmd_ctx *c, int32_t nsteps, double max_disp, double clamp,
     if (nsteps < 0 || !(max_disp > 0.0) || !std::isfinite(max_disp) || !(clamp >= 0.0) ||
         !std::isfinite(clamp))
         return fail(c, LJMD_EINVAL, "minimize_sd: bad arguments");
+    ++c->gen;
     hipError_t e = hipMemsetAsync(c->st.ctl->fmax, 0, sizeof(c->st.ctl->fmax), c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "minimize_sd memset");
     // Iteration s uses the control-word parity of id c->step + 1 + s; the
@@ -702,6 +851,193 @@ int ljmd_observables(ljmd_ctx *c, ljmd_obs *out) {
 
 const char *ljmd_last_error(const ljmd_ctx *c) {
     return c ? c->err.c_str() : g_create_err.c_str();
+}
+
+// ---- gradients --------------------------------------------------------------
+
+int ljmd_set_pair_params(ljmd_ctx *c, const double eps[4], const double sigma[4]) {
+    if (!c) return LJMD_EINVAL;
+    if (!eps || !sigma) return fail(c, LJMD_EINVAL, "set_pair_params: NULL array");
+    ljmd_params q = c->p;
+    for (int k = 0; k < 4; ++k) {
+        q.eps[k] = eps[k];
+        q.sigma[k] = sigma[k];
+    }
+    std::string why;
+    int r = validate(&q, &why);
+    if (r != LJMD_OK) return fail(c, r, "set_pair_params: %s", why.c_str());
+    c->p = q;
+    fill_pairs(c->pc, c->p);
+    ++c->gen;
+    if (!c->have_state) return LJMD_OK;
+    // Forces and observables of the current positions under the new values.
+    Launch L = launcher(c);
+    hipError_t e;
+    if ((e = launch_step(L, c->step, 0, kStoreForce, (int)(c->step % kRing))) != hipSuccess)
+        return hip_fail(c, e, "force");
+    if ((e = launch_obs_reduce(L, c->step, 1, c->nblocks, nullptr, 0)) != hipSuccess)
+        return hip_fail(c, e, "obs");
+    return LJMD_OK;
+}
+
+int ljmd_force_vjp(ljmd_ctx *c, const double *g, double *gx, double *gtheta) {
+    if (!c) return LJMD_EINVAL;
+    if (!c->have_state) return fail(c, LJMD_ESTATE, "force_vjp before set_state");
+    if (!g || !gx || !gtheta) return fail(c, LJMD_EINVAL, "force_vjp: NULL array");
+    // Scratch: the FP64 accumulator, then the cotangent in the path precision.
+    const int64_t npad = padded(c->g.n);
+    const size_t need = 2 * al(sizeof(double4) * (size_t)npad);
+    if (resort_scratch_bytes(npad, c->g.prec) < need) return fail(c, LJMD_ENOMEM, "internal: scratch");
+    uint8_t *scr = (uint8_t *)c->st.scratch;
+    double4 *acc = (double4 *)scr;
+    void *gv = scr + al(sizeof(double4) * (size_t)npad);
+    Launch L = launcher(c);
+    hipError_t e;
+    if ((e = launch_adjoint_vec(L, kOpGatherG, g, nullptr, nullptr, nullptr, gv, 0.0)) != hipSuccess ||
+        (e = launch_adjoint_vec(L, kOpZero, nullptr, nullptr, acc, nullptr, nullptr, 0.0)) != hipSuccess)
+        return hip_fail(c, e, "force_vjp setup");
+    {
+        Bracket b(c, 4);
+        if ((e = launch_adjoint_pairs(L, kAdjVjp, gv, acc, 1.0, gtheta, 1)) != hipSuccess)
+            return hip_fail(c, e, "force_vjp");
+    }
+    if ((e = launch_adjoint_vec(L, kOpScatterById, nullptr, gx, acc, nullptr, nullptr, 0.0)) != hipSuccess)
+        return hip_fail(c, e, "force_vjp scatter");
+    return LJMD_OK;
+}
+
+int ljmd_energy_grad(ljmd_ctx *c, double *gtheta) {
+    if (!c) return LJMD_EINVAL;
+    if (!c->have_state) return fail(c, LJMD_ESTATE, "energy_grad before set_state");
+    if (!gtheta) return fail(c, LJMD_EINVAL, "energy_grad: NULL array");
+    hipError_t e = launch_adjoint_pairs(launcher(c), kAdjEnergy, nullptr, nullptr, 1.0, gtheta, 1);
+    return e == hipSuccess ? LJMD_OK : hip_fail(c, e, "energy_grad");
+}
+
+size_t ljmd_adjoint_workspace_size(const ljmd_params *p, int32_t nsteps, int32_t ckpt_every,
+                                   int32_t flags) {
+    if (validate(p, nullptr) != LJMD_OK || nsteps < 1 || ckpt_every < 1 || (flags & ~LJMD_ADJ_STORE_ALL))
+        return 0;
+    return adj_plan(p, nsteps, ckpt_every, flags).total;
+}
+
+int ljmd_vv_forward(ljmd_ctx *c, int32_t nsteps, int32_t ckpt_every, int32_t flags, void *adj_ws,
+                    size_t bytes, double *obs_dev) {
+    if (!c) return LJMD_EINVAL;
+    if (!c->have_state) return fail(c, LJMD_ESTATE, "vv_forward before set_state");
+    if (nsteps < 1 || ckpt_every < 1) return fail(c, LJMD_EINVAL, "vv_forward: nsteps and ckpt_every must be >= 1");
+    if (flags & ~LJMD_ADJ_STORE_ALL) return fail(c, LJMD_EINVAL, "vv_forward: unknown flags");
+    if (!adj_ws || ((uintptr_t)adj_ws & 255) != 0)
+        return fail(c, LJMD_EINVAL, "vv_forward: workspace must be non-NULL and 256-byte aligned");
+    const AdjPlan P = adj_plan(&c->p, nsteps, ckpt_every, flags);
+    if (bytes < P.total)
+        return fail(c, LJMD_ENOMEM, "vv_forward: workspace has %zu bytes, needs %zu", bytes, P.total);
+    c->adj = AdjRecord{};
+    ++c->gen;
+    uint8_t *ws = (uint8_t *)adj_ws;
+    const int64_t step0 = c->step;
+    RunOpts o;
+    o.force_first = true;
+    o.allow_resort = false;
+    o.frame_stride = P.frame_stride;
+    for (int32_t seg = 0; seg < P.nseg; ++seg) {
+        int r = ckpt_copy(c, ws + P.off_ckpt + (size_t)seg * P.ckpt_stride, true);
+        if (r) return r;
+        const int32_t s0 = seg * ckpt_every;
+        const int32_t n = std::min(ckpt_every, nsteps - s0);
+        if (P.store_all) o.frames = ws + P.off_frames + (size_t)s0 * P.frame_stride;
+        if ((r = run_steps(c, n, obs_dev ? obs_dev + (size_t)s0 * LJMD_NOBS : nullptr, o))) return r;
+    }
+    int r = ckpt_copy(c, ws + P.off_ckpt + (size_t)P.nseg * P.ckpt_stride, true);
+    if (r) return r;
+    if ((r = rebuild_at_rest(c, c->step))) return r;
+    c->adj.valid = true;
+    c->adj.plan = P;
+    c->adj.ws = ws;
+    c->adj.step0 = step0;
+    c->adj.gen = c->gen;
+    return LJMD_OK;
+}
+
+int ljmd_vv_backward(ljmd_ctx *c, const double *lam_x, const double *lam_v, double *gx0, double *gv0,
+                     double *gtheta) {
+    if (!c) return LJMD_EINVAL;
+    if (!c->adj.valid || c->adj.gen != c->gen)
+        return fail(c, LJMD_ESTATE, "vv_backward without a matching vv_forward (state changed since)");
+    if (!lam_x || !lam_v || !gx0 || !gv0 || !gtheta) return fail(c, LJMD_EINVAL, "vv_backward: NULL array");
+    const AdjPlan &P = c->adj.plan;
+    uint8_t *ws = c->adj.ws;
+    double4 *lx = (double4 *)(ws + P.off_lx);
+    double4 *lv = (double4 *)(ws + P.off_lv);
+    void *gv = ws + P.off_g;
+    uint8_t *frames = ws + P.off_frames;
+    const int64_t N = P.nsteps;
+    const double dt = c->p.dt, h = 0.5 * c->p.dt;
+    const size_t fb = rec_bytes(c->g.prec) * (size_t)c->g.n;
+    hipError_t e;
+    Launch L = launcher(c);
+    if ((e = launch_adjoint_vec(L, kOpGatherById, lam_x, nullptr, lx, nullptr, nullptr, 0.0)) != hipSuccess ||
+        (e = launch_adjoint_vec(L, kOpGatherById, lam_v, nullptr, lv, nullptr, nullptr, 0.0)) != hipSuccess)
+        return hip_fail(c, e, "vv_backward gather");
+    RunOpts o;
+    o.force_first = true;
+    o.allow_resort = false;
+    o.final_obs = false;
+    o.frames = frames;
+    o.frame_stride = P.frame_stride;
+    bool first = true;
+    for (int32_t seg = P.nseg - 1; seg >= 0; --seg) {
+        const int32_t s0 = seg * P.every;
+        const int32_t n = std::min(P.every, P.nsteps - s0);
+        int r;
+        uint8_t *seg_frames = frames;
+        if (P.store_all) {
+            seg_frames = frames + (size_t)s0 * P.frame_stride;
+            c->step = c->adj.step0 + s0 + n;
+        } else {
+            // Recompute the segment from its stored state, keeping its frames.
+            if ((r = ckpt_copy(c, ws + P.off_ckpt + (size_t)seg * P.ckpt_stride, false))) return r;
+            c->step = c->adj.step0 + s0;
+            if ((r = run_steps(c, n, nullptr, o))) return r;
+        }
+        // Sweep the frames backwards. The lists are built afresh at the first
+        // frame, so the sweep does not depend on how the frames were obtained;
+        // later frames follow the half-skin rule, with step ids that continue
+        // after the segment's end (parity of the displacement words).
+        int64_t t = c->step + 1;
+        const int32_t top = seg == P.nseg - 1 ? n : n - 1;
+        for (int32_t j = top; j >= 0; --j, ++t) {
+            const int64_t s = (int64_t)s0 + j;
+            const int forced = j == top ? 1 : 0;
+            L = launcher(c);
+            if (s != N &&
+                (e = launch_adjoint_vec(L, kOpDrift, nullptr, nullptr, lx, lv, nullptr, dt)) != hipSuccess)
+                return hip_fail(c, e, "vv_backward drift");
+            if ((e = hipMemcpyAsync(rec_ptr(c, c->cur), seg_frames + (size_t)j * P.frame_stride, fb,
+                                    hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
+                return hip_fail(c, e, "frame load");
+            if (!forced && (e = launch_frame_disp(L, t)) != hipSuccess)
+                return hip_fail(c, e, "frame displacement");
+            if ((r = rebuild_sequence(c, t, forced, false))) return r;
+            if ((e = launch_adjoint_cells(L, t, forced)) != hipSuccess) return hip_fail(c, e, "clear cells");
+            if ((e = launch_adjoint_vec(L, kOpCotangent, nullptr, nullptr, nullptr, lv, gv, 0.0)) != hipSuccess)
+                return hip_fail(c, e, "vv_backward cotangent");
+            const double w = (s == N || s == 0) ? h : dt;
+            Bracket b(c, 4);
+            if ((e = launch_adjoint_pairs(L, kAdjVjp, gv, lx, w, gtheta, first ? 1 : 0)) != hipSuccess)
+                return hip_fail(c, e, "vv_backward vjp");
+            first = false;
+        }
+    }
+    L = launcher(c);
+    if ((e = launch_adjoint_vec(L, kOpScatterById, nullptr, gx0, lx, nullptr, nullptr, 0.0)) != hipSuccess ||
+        (e = launch_adjoint_vec(L, kOpScatterById, nullptr, gv0, lv, nullptr, nullptr, 0.0)) != hipSuccess)
+        return hip_fail(c, e, "vv_backward scatter");
+    // Back to the final state of the rollout, lists as ljmd_vv_forward left them.
+    int r = ckpt_copy(c, ws + P.off_ckpt + (size_t)P.nseg * P.ckpt_stride, false);
+    if (r) return r;
+    c->step = c->adj.step0 + N;
+    return rebuild_at_rest(c, c->step);
 }
 
 }  // extern "C"

@@ -18,8 +18,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libljmd.so")
 
+ABI_VERSION = 2
 FP64 = 0
 FP32_DS = 1
+ADJ_STORE_ALL = 1
 NOBS = 8
 OBS_FIELDS = ("U", "K", "W", "px", "py", "pz", "rebuilt", "step")
 
@@ -70,9 +72,18 @@ SIGNATURES = {
     "ljmd_set_profiling": (C.c_int, [_vp, C.c_int]),
     "ljmd_kernel_times": (C.c_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "ljmd_last_error": (C.c_char_p, [_vp]),
+    "ljmd_set_pair_params": (C.c_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "ljmd_force_vjp": (C.c_int, [_vp, _dp, _dp, _dp]),
+    "ljmd_energy_grad": (C.c_int, [_vp, _dp]),
+    "ljmd_adjoint_workspace_size": (C.c_size_t, [C.POINTER(Params), C.c_int32, C.c_int32, C.c_int32]),
+    "ljmd_vv_forward": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _vp, C.c_size_t, _dp]),
+    "ljmd_vv_backward": (C.c_int, [_vp, _dp, _dp, _dp, _dp, _dp]),
 }
-NKT = 4
-KERNEL_FAMILIES = ("step", "rebuild", "resort", "other")
+NKT = 5
+KERNEL_FAMILIES = ("step", "rebuild", "resort", "other", "adjoint")
+# Parameter-gradient layout of the library: (eps_AA, eps_AB, eps_BB,
+# sigma_AA, sigma_AB, sigma_BB); entries 1, 2, 4, 5 are unused with one species.
+THETA_FIELDS = ("eps_AA", "eps_AB", "eps_BB", "sigma_AA", "sigma_AB", "sigma_BB")
 
 
 def _load():
@@ -184,6 +195,7 @@ class System:
         if code != 0:
             raise LJMDError(code, last_error(None))
         self.ctx = ctx
+        self._gen = 0
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -209,12 +221,18 @@ class System:
         s = self._dev(species, t.int32).reshape(self.n)
         _check(lib.ljmd_set_state(self.ctx, _ptr(x), _ptr(v), _ptr(s)), self.ctx)
         self._keep = (x, v, s)
+        self._gen += 1
+
+    def gen(self) -> int:
+        """Counter of calls that changed the state or the potential."""
+        return self._gen
 
     def run(self, nsteps: int, observe: bool = True):
         """Advance nsteps; returns a (nsteps, 8) float64 device tensor of
         per-step observables (U, K, W, px, py, pz, rebuilt, step) or None."""
         t = self.torch
         obs = t.empty((max(nsteps, 1), NOBS), dtype=t.float64, device=self.device) if observe else None
+        self._gen += 1
         _check(lib.ljmd_run(self.ctx, int(nsteps), _ptr(obs) if obs is not None else None), self.ctx)
         return obs[:nsteps] if obs is not None else None
 
@@ -224,6 +242,7 @@ class System:
         max |F| at the start of every iteration (or None)."""
         t = self.torch
         fm = t.zeros(max(nsteps, 1), dtype=t.float64, device=self.device) if record else None
+        self._gen += 1
         _check(lib.ljmd_minimize_sd(self.ctx, int(nsteps), float(max_disp), float(clamp),
                                     _ptr(fm) if fm is not None else None), self.ctx)
         return fm[:nsteps] if fm is not None else None
@@ -272,3 +291,155 @@ class System:
         return {"U": o.U, "K": o.K, "W": o.W, "P": o.P, "T": o.T, "E": o.E,
                 "p": (o.p[0], o.p[1], o.p[2]), "step": o.step, "rebuilds": o.rebuilds,
                 "max_fill": o.max_fill, "nbr_capacity": o.nbr_capacity}
+
+    # ---- gradients -----------------------------------------------------------
+
+    def theta(self) -> np.ndarray:
+        """Current (eps_AA, eps_AB, eps_BB, sigma_AA, sigma_AB, sigma_BB)."""
+        e, s = self.params.eps, self.params.sigma
+        return np.array([e[0], e[1], e[3], s[0], s[1], s[3]], dtype=np.float64)
+
+    def set_pair_params(self, eps, sigma):
+        """Replace eps and sigma (4 entries each, [AA, AB, BA, BB]); the
+        forces of a loaded state are re-evaluated."""
+        e = (C.c_double * 4)(*[float(v) for v in eps])
+        s = (C.c_double * 4)(*[float(v) for v in sigma])
+        _check(lib.ljmd_set_pair_params(self.ctx, e, s), self.ctx)
+        for k in range(4):
+            self.params.eps[k] = e[k]
+            self.params.sigma[k] = s[k]
+        self._gen += 1
+
+    def set_theta(self, theta):
+        """set_pair_params from the 6-entry gradient layout (one species: only
+        entries 0 and 3 are used)."""
+        t = [float(v) for v in theta]
+        if self.params.nspecies == 1:
+            eps, sig = [t[0]] * 4, [t[3]] * 4
+        else:
+            eps, sig = [t[0], t[1], t[1], t[2]], [t[3], t[4], t[4], t[5]]
+        self.set_pair_params(eps, sig)
+
+    def force_vjp(self, g):
+        """(dF/dx)^T g by id and d(g.F)/dtheta at the current state."""
+        t = self.torch
+        g = self._dev(g, t.float64).reshape(self.n, 3)
+        gx = t.empty((self.n, 3), dtype=t.float64, device=self.device)
+        gth = t.empty(6, dtype=t.float64, device=self.device)
+        _check(lib.ljmd_force_vjp(self.ctx, _ptr(g), _ptr(gx), _ptr(gth)), self.ctx)
+        self._keep_g = g
+        return gx, gth
+
+    def energy_grad(self):
+        """dU/dtheta at the current state (dU/dx = -forces())."""
+        t = self.torch
+        gth = t.empty(6, dtype=t.float64, device=self.device)
+        _check(lib.ljmd_energy_grad(self.ctx, _ptr(gth)), self.ctx)
+        return gth
+
+    def adjoint_workspace_size(self, nsteps: int, every: int, store_all: bool = False) -> int:
+        return int(lib.ljmd_adjoint_workspace_size(C.byref(self.params), int(nsteps), int(every),
+                                                   ADJ_STORE_ALL if store_all else 0))
+
+    def vv_forward(self, nsteps: int, every: int = 10, observe: bool = True,
+                   store_all: bool = False):
+        """Differentiable rollout of nsteps with a stored state every `every`
+        steps (and every frame kept if store_all); returns the (nsteps, 8)
+        observables (or None)."""
+        t = self.torch
+        flags = ADJ_STORE_ALL if store_all else 0
+        size = self.adjoint_workspace_size(nsteps, every, store_all)
+        if size == 0:
+            raise LJMDError(-1, "vv_forward: invalid nsteps/every")
+        ws = getattr(self, "_adj_ws", None)
+        if ws is None or ws.numel() < size:
+            ws = t.empty(size, dtype=t.uint8, device=self.device)
+            self._adj_ws = ws
+        obs = t.empty((nsteps, NOBS), dtype=t.float64, device=self.device) if observe else None
+        self._gen += 1
+        _check(lib.ljmd_vv_forward(self.ctx, int(nsteps), int(every), flags, C.c_void_p(_ptr(ws)),
+                                   ws.numel(), _ptr(obs) if obs is not None else None), self.ctx)
+        return obs
+
+    def vv_backward(self, lam_x, lam_v):
+        """(dL/dx_0, dL/dv_0, dL/dtheta through the dynamics) of the last
+        rollout from dL/dx_N and dL/dv_N (by id)."""
+        t = self.torch
+        lx = self._dev(lam_x, t.float64).reshape(self.n, 3)
+        lv = self._dev(lam_v, t.float64).reshape(self.n, 3)
+        gx0 = t.empty((self.n, 3), dtype=t.float64, device=self.device)
+        gv0 = t.empty_like(gx0)
+        gth = t.empty(6, dtype=t.float64, device=self.device)
+        _check(lib.ljmd_vv_backward(self.ctx, _ptr(lx), _ptr(lv), _ptr(gx0), _ptr(gv0), _ptr(gth)),
+               self.ctx)
+        self._keep_l = (lx, lv)
+        return gx0, gv0, gth
+
+
+# ---- torch.autograd front ends ----------------------------------------------
+# theta is a float64 tensor of 6 entries in THETA_FIELDS order. The System's
+# state is overwritten by every call (the functions load x and theta first).
+
+def _autograd():
+    import torch
+
+    class LJForceFn(torch.autograd.Function):
+        """F(x; theta) by id for a System; backward is the library's force VJP."""
+
+        @staticmethod
+        def forward(ctx, x, theta, system, species):
+            system.set_theta(theta.detach().cpu().numpy())
+            x = x.detach()
+            system.set_state(x, torch.zeros_like(x), species)
+            ctx.system, ctx.species = system, species
+            ctx.save_for_backward(x, theta)
+            return system.forces()
+
+        @staticmethod
+        def backward(ctx, gF):
+            x, theta = ctx.saved_tensors
+            s = ctx.system
+            s.set_theta(theta.detach().cpu().numpy())
+            s.set_state(x, torch.zeros_like(x), ctx.species)
+            gx, gth = s.force_vjp(gF.contiguous())
+            return gx, gth.to(theta.device), None, None
+
+    class VVRollout(torch.autograd.Function):
+        """(x_N unwrapped, v_N, U_N) after nsteps velocity-Verlet steps from
+        (x0, v0) under theta; backward recomputes from checkpoints."""
+
+        @staticmethod
+        def forward(ctx, x0, v0, theta, system, species, nsteps, every):
+            system.set_theta(theta.detach().cpu().numpy())
+            system.set_state(x0.detach(), v0.detach(), species)
+            obs = system.vv_forward(nsteps, every)
+            xN = system.unwrapped_positions()
+            _, vN, _ = system.get_state()
+            ctx.system, ctx.species, ctx.nsteps, ctx.every = system, species, nsteps, every
+            ctx.gen = system.gen()
+            ctx.save_for_backward(x0, v0, theta)
+            return xN, vN, obs[-1, 0].clone()
+
+        @staticmethod
+        def backward(ctx, gxN, gvN, gU):
+            x0, v0, theta = ctx.saved_tensors
+            s = ctx.system
+            if s.gen() != ctx.gen:
+                # The System was used since: repeat the (deterministic) forward.
+                s.set_theta(theta.detach().cpu().numpy())
+                s.set_state(x0.detach(), v0.detach(), ctx.species)
+                s.vv_forward(ctx.nsteps, ctx.every, observe=False)
+            lam_x = gxN.contiguous() if gxN is not None else torch.zeros((s.n, 3), dtype=torch.float64,
+                                                                         device=s.device)
+            lam_v = gvN.contiguous() if gvN is not None else torch.zeros_like(lam_x)
+            if gU is not None:
+                lam_x = lam_x - gU * s.forces()      # dU/dx_N = -F(x_N)
+            gx0, gv0, gth = s.vv_backward(lam_x, lam_v)
+            if gU is not None:
+                gth = gth + gU * s.energy_grad()     # the context is back at x_N
+            return gx0, gv0, gth.to(theta.device), None, None, None, None
+
+    return LJForceFn, VVRollout
+
+
+LJForceFn, VVRollout = _autograd()

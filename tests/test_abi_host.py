@@ -34,7 +34,9 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_abi_version():
-    assert ljmd.lib.ljmd_abi_version() == 1
+    hdr = open(os.path.join(ROOT, "include", "ljmd.h")).read()
+    declared = int(re.search(r"#define LJMD_ABI_VERSION (\d+)", hdr).group(1))
+    assert ljmd.lib.ljmd_abi_version() == declared == ljmd.ABI_VERSION
 
 
 def _params(**kw):

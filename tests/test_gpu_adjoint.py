@@ -1,0 +1,339 @@
+"""Parity of the HIP adjoint (force VJP, parameter gradients, velocity-Verlet
+reverse sweep with checkpoints) with the CPU oracle, through the C ABI and
+the torch.autograd front ends.
+
+Expected values come from the oracle (its own pins: finite differences,
+symmetry, exact identities) or, for the recompute, from the same GPU run
+with every frame stored. Tolerances, with the per-particle scale
+s_i = max(|ref_i|, rms_j |ref_j|):
+  * force VJP: max_i |d gx_i| / s_i <= 1e-11 (FP64), 2e-5 (FP32+DS). The
+    FP32 product sums terms fs D + c (d.D) d whose magnitude reaches
+    ~1e3 |D| for close pairs; binary32 rounding of ~40 such terms and of
+    r^2 (amplified by u^7 in c) leaves ~1e-6 relative. A partner at a cutoff
+    tie may add its whole term (the truncation is discontinuous there);
+    the allowance per tie is (|fs(r_c)| + |c(r_c)| r_c^2) |D|.
+  * parameter gradients: relative 1e-10 (FP64), 2e-5 (FP32+DS), against
+    the larger of the value and the sum of its terms' magnitudes estimated
+    as |value| + 1 (FP64 pair sums in a fixed order on both sides).
+  * rollouts (N=500, 20 steps): relative to max |ref| per array, 1e-9
+    (FP64); 1e-4 (FP32+DS: forces carry 1e-6 relative error and the
+    trajectories differ by ~1e-6 sigma after 20 steps, which moves every
+    Jacobian by the same relative amount).
+  * checkpointed recompute vs every frame stored: bitwise equal.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2406_04210_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = 0, 1
+TOL_VJP = {FP64: 1e-11, FP32: 2e-5}
+TOL_TH = {FP64: 1e-10, FP32: 2e-5}
+TOL_ROLL = {FP64: 1e-9, FP32: 1e-4}
+
+
+@pytest.fixture(scope="module")
+def ljmd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_04210_amd import ljmd as L
+    return L
+
+
+def jittered_fcc(m, amp, seed, rho=0.8442):
+    x, L = W.fcc_lattice(m, rho)
+    rng = np.random.default_rng(seed)
+    return x + amp * rng.standard_normal(x.shape), np.full(3, L)
+
+
+def cases():
+    out = []
+    p1 = W.single_species_params()
+    x, box = jittered_fcc(8, 0.1, 21)
+    out.append(("fcc8_jitter", x, np.zeros(len(x), np.int32), box, p1))
+    r = W.random_dense(777, 0.8442, seed=22, min_dist=0.85)
+    out.append(("random777", r.x, r.species, r.box, r.params))
+    r = W.random_dense(1500, 1.1, seed=23, nspecies=2, min_dist=0.75)
+    out.append(("mixture1500", r.x, r.species, r.box, r.params))
+    return out
+
+
+CASES = cases()
+IDS = [c[0] for c in CASES]
+
+
+def vjp_tie_allowance(x, sp, box, p, g, prec):
+    """Per-particle bound on what pairs at a cutoff tie may add or drop."""
+    if prec == FP64:
+        return np.zeros(len(x))
+    n = len(x)
+    cnt, nbr = oracle.build_lists(x, sp, box, p, mode=0)
+    i = np.repeat(np.arange(n), cnt)
+    j = nbr[np.arange(nbr.shape[1])[None, :] < cnt[:, None]]
+    d = x[i] - x[j]
+    d -= box * np.rint(d / box)
+    r2 = (d * d).sum(axis=1)
+    ab = sp[i] * 2 + sp[j] if p.nspecies == 2 else np.zeros(len(i), dtype=np.int64)
+    rc = np.asarray(p.rcut)[ab]
+    tie = np.abs(r2 - rc * rc) <= 2e-6 * rc * rc
+    out = np.zeros(n)
+    for k in np.nonzero(tie)[0]:
+        a = int(ab[k])
+        eps, sig = p.eps[a], p.sigma[a]
+        s6 = (sig / rc[k]) ** 6
+        fs = 24 * eps * (2 * s6 * s6 - s6) / rc[k] ** 2
+        c = 96 * eps * (7 * s6 * s6 - 2 * s6) / rc[k] ** 4
+        out[i[k]] += 1.001 * (abs(fs) + abs(c) * rc[k] ** 2) * np.linalg.norm(g[i[k]] - g[j[k]])
+    return out
+
+
+def rel_err(a, ref, allowance=None):
+    rms = math.sqrt(float((ref ** 2).sum(axis=1).mean()))
+    scale = np.maximum(np.linalg.norm(ref, axis=1), rms)
+    err = np.linalg.norm(a - ref, axis=1)
+    if allowance is not None:
+        err = np.maximum(err - allowance, 0.0)
+    return float((err / scale).max())
+
+
+def theta_of(p):
+    return np.array([p.eps[0], p.eps[1], p.eps[3], p.sigma[0], p.sigma[1], p.sigma[3]])
+
+
+def check_theta(gpu, ge, gs, nspecies, tol, what):
+    ref = np.concatenate([ge, gs])
+    used = [0, 3] if nspecies == 1 else range(6)
+    for k in used:
+        err = abs(gpu[k] - ref[k]) / (abs(ref[k]) + 1.0)
+        assert err <= tol, f"{what}[{k}]: gpu {gpu[k]!r} oracle {ref[k]!r} rel {err:.3e}"
+    if nspecies == 1:
+        assert np.all(gpu[[1, 2, 4, 5]] == 0.0)
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_force_vjp_matches_oracle(ljmd, case, prec):
+    name, x, sp, box, p = case
+    s = ljmd.System(len(x), box, p, precision=prec)
+    s.set_state(x, np.zeros_like(x), sp)
+    g = np.random.default_rng(31).standard_normal(x.shape)
+    gx, gth = s.force_vjp(g)
+    s.sync()
+    gx, gth = gx.cpu().numpy(), gth.cpu().numpy()
+    ox, ge, gs = oracle.force_vjp(x, sp, box, p, g)
+    err = rel_err(gx, ox, vjp_tie_allowance(x, sp, box, p, g, prec))
+    print(f"vjp {name} prec={prec} max rel err {err:.3e}", flush=True)
+    assert err <= TOL_VJP[prec], (name, err)
+    check_theta(gth, ge, gs, p.nspecies, TOL_TH[prec], f"{name} dgF/dtheta")
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_energy_grad_matches_oracle(ljmd, case, prec):
+    name, x, sp, box, p = case
+    s = ljmd.System(len(x), box, p, precision=prec)
+    s.set_state(x, np.zeros_like(x), sp)
+    gth = s.energy_grad()
+    s.sync()
+    ue, us = oracle.energy_grad(x, sp, box, p)
+    check_theta(gth.cpu().numpy(), ue, us, p.nspecies, TOL_TH[prec] * 2, f"{name} dU/dtheta")
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_set_pair_params_reevaluates_forces(ljmd, prec):
+    name, x, sp, box, p = CASES[2]
+    s = ljmd.System(len(x), box, p, precision=prec)
+    s.set_state(x, np.zeros_like(x), sp)
+    th = theta_of(p) * np.array([1.03, 0.98, 1.05, 0.99, 1.01, 0.97])
+    s.set_theta(th)
+    f = s.forces().cpu().numpy()
+    o = s.observables()
+    q = oracle.with_params(p, eps=th[:3], sigma=th[3:])
+    fb, Ub, _ = oracle.forces_brute(x, sp, box, q)
+    assert rel_err(f, fb) <= (1e-12 if prec == FP64 else 2e-5)
+    assert abs(o["U"] - Ub) / len(x) <= (1e-12 if prec == FP64 else 5e-6) * max(1.0, abs(Ub) / len(x))
+    assert np.allclose(s.theta(), th, rtol=0, atol=0)
+
+
+def rollout_case(seed=41):
+    x, box = jittered_fcc(5, 0.05, seed)
+    p = W.single_species_params()
+    sp = np.zeros(len(x), np.int32)
+    v = W.maxwell_boltzmann(len(x), 1.0, p.mass, sp, np.random.default_rng(seed + 1))
+    return x, v, sp, box, p
+
+
+def gpu_rollout_grad(ljmd, prec, x, v, sp, box, p, nsteps, every, lam_x, lam_v, store_all=False):
+    s = ljmd.System(len(x), box, p, precision=prec)
+    s.set_state(x, v, sp)
+    s.vv_forward(nsteps, every, store_all=store_all)
+    gx0, gv0, gth = s.vv_backward(lam_x, lam_v)
+    s.sync()
+    return s, gx0.cpu().numpy(), gv0.cpu().numpy(), gth.cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("every", [10, 7])
+def test_vv_adjoint_matches_oracle(ljmd, prec, every):
+    x, v, sp, box, p = rollout_case()
+    nsteps = 20
+    rng = np.random.default_rng(43)
+    lam_x, lam_v = rng.standard_normal(x.shape), rng.standard_normal(x.shape)
+    _, gx0, gv0, gth = gpu_rollout_grad(ljmd, prec, x, v, sp, box, p, nsteps, every, lam_x, lam_v)
+    ox, ov, ge, gs = oracle.vv_adjoint(x, v, sp, box, p, nsteps, lam_x, lam_v)
+    ex = float(np.abs(gx0 - ox).max() / np.abs(ox).max())
+    ev = float(np.abs(gv0 - ov).max() / np.abs(ov).max())
+    print(f"vv adjoint prec={prec} every={every}: rel err x0 {ex:.3e} v0 {ev:.3e} "
+          f"theta gpu {gth[[0, 3]]} oracle {ge[0]:.10g} {gs[0]:.10g}", flush=True)
+    assert ex <= TOL_ROLL[prec] and ev <= TOL_ROLL[prec], (ex, ev)
+    for k, ref in ((0, ge[0]), (3, gs[0])):
+        assert abs(gth[k] - ref) <= TOL_ROLL[prec] * (abs(ref) + 1.0), (k, gth[k], ref)
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_recompute_equals_stored_frames_bitwise(ljmd, prec):
+    x, v, sp, box, p = rollout_case(51)
+    rng = np.random.default_rng(52)
+    lam_x, lam_v = rng.standard_normal(x.shape), rng.standard_normal(x.shape)
+    a = gpu_rollout_grad(ljmd, prec, x, v, sp, box, p, 25, 10, lam_x, lam_v, store_all=False)
+    b = gpu_rollout_grad(ljmd, prec, x, v, sp, box, p, 25, 10, lam_x, lam_v, store_all=True)
+    for u, w in zip(a[1:], b[1:]):
+        assert np.array_equal(u, w)
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_backward_restores_final_state(ljmd, prec):
+    import torch
+    x, v, sp, box, p = rollout_case(61)
+    rng = np.random.default_rng(62)
+    lam = rng.standard_normal(x.shape)
+    s1 = ljmd.System(len(x), box, p, precision=prec)
+    s1.set_state(x, v, sp)
+    s1.vv_forward(13, 5)
+    st_fwd = [t.clone() for t in s1.get_state()]
+    f_fwd = s1.forces().clone()
+    s1.vv_backward(lam, lam)
+    st_bwd = s1.get_state()
+    assert all(torch.equal(a, b) for a, b in zip(st_fwd, st_bwd))
+    assert torch.equal(f_fwd, s1.forces())
+    # Continuing after the backward sweep equals continuing right after the forward run.
+    s2 = ljmd.System(len(x), box, p, precision=prec)
+    s2.set_state(x, v, sp)
+    s2.vv_forward(13, 5)
+    s1.run(30)
+    s2.run(30)
+    assert all(torch.equal(a, b) for a, b in zip(s1.get_state(), s2.get_state()))
+
+
+def test_backward_state_errors(ljmd):
+    x, v, sp, box, p = rollout_case(71)
+    s = ljmd.System(len(x), box, p, precision=FP64)
+    s.set_state(x, v, sp)
+    with pytest.raises(ljmd.LJMDError) as e:
+        s.vv_backward(np.zeros_like(x), np.zeros_like(x))
+    assert e.value.code == -7
+    s.vv_forward(4, 2)
+    s.run(1)
+    with pytest.raises(ljmd.LJMDError) as e:
+        s.vv_backward(np.zeros_like(x), np.zeros_like(x))
+    assert e.value.code == -7
+    s.vv_forward(3, 5)                    # checkpoint interval longer than the rollout
+    g = s.vv_backward(np.ones_like(x), np.zeros_like(x))
+    s.sync()
+    assert all(bool(np.isfinite(t.cpu().numpy()).all()) for t in g)
+
+
+def rollout_loss_gpu(ljmd, x, v, sp, box, p, nsteps, gX, gV):
+    s = ljmd.System(len(x), box, p, precision=FP64)
+    s.set_state(x, v, sp)
+    s.run(nsteps, observe=False)
+    xN = s.unwrapped_positions().cpu().numpy()
+    _, vN, _ = s.get_state()
+    return float((gX * xN).sum() + (gV * vN.cpu().numpy()).sum())
+
+
+def test_vv_adjoint_directional_fd_fp64(ljmd):
+    """The GPU's own FP64 rollout differentiated by central differences."""
+    x, v, sp, box, p = rollout_case(81)
+    nsteps = 20
+    rng = np.random.default_rng(82)
+    gX, gV = rng.standard_normal(x.shape), rng.standard_normal(x.shape)
+    _, gx0, gv0, _ = gpu_rollout_grad(ljmd, FP64, x, v, sp, box, p, nsteps, 10, gX, gV)
+    h = 1e-6
+    done = 0
+    for _ in range(6):
+        dx, dv = rng.standard_normal(x.shape), rng.standard_normal(x.shape)
+        f = lambda t: rollout_loss_gpu(ljmd, x + t * dx, v + t * dv, sp, box, p, nsteps, gX, gV)
+        fd1 = (f(h) - f(-h)) / (2 * h)
+        fd2 = (f(2 * h) - f(-2 * h)) / (4 * h)
+        if abs(fd1 - fd2) > 1e-5 * abs(fd1):   # a pair crossed the cutoff between the runs
+            continue
+        ad = float((gx0 * dx).sum() + (gv0 * dv).sum())
+        assert ad == pytest.approx(fd1, rel=1e-6), (ad, fd1, fd2)
+        done += 1
+        if done == 2:
+            break
+    assert done >= 1
+
+
+def config4_problem(m, seed):
+    """Differentiable-workload loss: force matching at x_0 plus the energy
+    after the rollout, L = |F(x_0; th) - F(x_0; th*)|^2 / 3N + U(x_N; th) / N."""
+    x, box = jittered_fcc(m, 0.05, seed)
+    p = W.single_species_params()
+    sp = np.zeros(len(x), np.int32)
+    rng = np.random.default_rng(seed + 1)
+    v = W.maxwell_boltzmann(len(x), 1.0, p.mass, sp, rng)
+    th = theta_of(p)
+    th_star = th * (1.0 + rng.uniform(-0.05, 0.05, 6))
+    return x, v, sp, box, p, th, th_star
+
+
+def config4_oracle(x, v, sp, box, p, th, th_star, nsteps):
+    n = len(x)
+    q = oracle.with_params(p, eps=th[:3], sigma=th[3:])
+    qs = oracle.with_params(p, eps=th_star[:3], sigma=th_star[3:])
+    F, _, _ = oracle.forces_brute(x, sp, box, q)
+    Fs, _, _ = oracle.forces_brute(x, sp, box, qs)
+    gF = 2.0 * (F - Fs) / (3 * n)
+    gxa, gea, gsa = oracle.force_vjp(x, sp, box, q, gF)
+    r = oracle.run_nve(x, v, sp, box, q, nsteps, want_obs=False)
+    fN, UN, _ = oracle.forces_brute(r["x"], sp, box, q)
+    lx, lv, geb, gsb = oracle.vv_adjoint(x, v, sp, box, q, nsteps, -fN / n, np.zeros_like(x))
+    ue, us = oracle.energy_grad(r["x"], sp, box, q)
+    L = float(((F - Fs) ** 2).sum() / (3 * n) + UN / n)
+    return L, gxa + lx, lv, gea + geb + ue / n, gsa + gsb + us / n
+
+
+def test_config4_loss_gradient_autograd(ljmd):
+    import torch
+    x, v, sp, box, p, th, th_star = config4_problem(6, 91)
+    n, nsteps = len(x), 30
+    sF = ljmd.System(n, box, p, precision=FP64)
+    sR = ljmd.System(n, box, p, precision=FP64)
+    x0 = torch.tensor(x, dtype=torch.float64, device="cuda", requires_grad=True)
+    v0 = torch.tensor(v, dtype=torch.float64, device="cuda", requires_grad=True)
+    tt = torch.tensor(th, dtype=torch.float64, requires_grad=True)
+    F = ljmd.LJForceFn.apply(x0, tt, sF, sp)
+    Fs = ljmd.LJForceFn.apply(x0.detach(), torch.tensor(th_star), sF, sp).detach()
+    xN, vN, UN = ljmd.VVRollout.apply(x0, v0, tt, sR, sp, nsteps, 10)
+    L = ((F - Fs) ** 2).sum() / (3 * n) + UN / n
+    L.backward()
+    Lo, gxo, gvo, geo, gso = config4_oracle(x, v, sp, box, p, th, th_star, nsteps)
+    assert float(L) == pytest.approx(Lo, rel=1e-10)
+    gx = x0.grad.cpu().numpy()
+    gv = v0.grad.cpu().numpy()
+    gt = tt.grad.numpy()
+    ex = float(np.abs(gx - gxo).max() / np.abs(gxo).max())
+    ev = float(np.abs(gv - gvo).max() / np.abs(gvo).max())
+    print(f"config-4 loss {float(L):.12g} oracle {Lo:.12g}; grad rel err x0 {ex:.3e} v0 {ev:.3e}; "
+          f"theta gpu {gt[[0, 3]]} oracle {geo[0]:.10g} {gso[0]:.10g}", flush=True)
+    assert ex <= 1e-9 and ev <= 1e-9
+    assert gt[0] == pytest.approx(geo[0], rel=1e-9)
+    assert gt[3] == pytest.approx(gso[0], rel=1e-9)
