@@ -120,6 +120,62 @@ def cpu_baseline(w, seconds_target: float = 15.0):
     }
 
 
+def time_adjoint(ljmd, torch, W, nsteps: int = 50, every: int = 10, reps: int = 3):
+    """Differentiable workload: jittered FCC 40^3 (N=256,000), target
+    parameters eps*, sigma* within 5%, loss
+        L = |F(x_0; th) - F(x_0; th*)|^2 / 3N + U(x_N; th) / N,  N = 50 steps,
+    a stored state every 10 steps. Forward = force evaluation at x_0 + the
+    checkpointed rollout + the loss; backward = force VJP at x_0 + the reverse
+    sweep (segment recompute, one VJP per frame) + dU/dtheta at x_N. Both
+    timed with HIP events on the library's stream (FP32 pair math, DS state)."""
+    import numpy as np
+    wl, eps_t, sig_t = W.jittered_fcc(40)
+    n = wl.n
+    sp = torch.as_tensor(wl.species, device="cuda")
+    x0 = torch.as_tensor(wl.x, device="cuda")
+    v0 = torch.as_tensor(wl.v, device="cuda")
+    sR = ljmd.System(n, wl.box, wl.params, precision=ljmd.FP32_DS)
+    sF = ljmd.System(n, wl.box, wl.params, precision=ljmd.FP32_DS)
+    sF.set_state(x0, torch.zeros_like(x0), sp)
+    th = sF.theta()
+    th_star = np.array([eps_t[0], eps_t[1], eps_t[3], sig_t[0], sig_t[1], sig_t[3]])
+    sF.set_theta(th_star)
+    F_star = sF.forces().clone()
+    sF.set_theta(th)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    fwd, bwd = [], []
+    for r in range(reps + 1):
+        sR.set_state(x0, v0, sp)
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        sF.set_theta(th)                                   # forces at x_0 under theta
+        F = sF.forces()
+        obs = sR.vv_forward(nsteps, every)
+        loss = ((F - F_star) ** 2).sum() / (3 * n) + obs[-1, 0] / n
+        ev[1].record(stream)
+        gF = 2.0 * (F - F_star) / (3 * n)
+        gx_a, gth_a = sF.force_vjp(gF)
+        lam_x = -sR.forces() / n
+        gx0, gv0, gth = sR.vv_backward(lam_x, torch.zeros_like(lam_x))
+        gth = gth + gth_a + sR.energy_grad() / n
+        gx0 = gx0 + gx_a
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        sR.sync()
+        if r > 0:                                          # the first pass is warmup
+            fwd.append(ev[0].elapsed_time(ev[1]))
+            bwd.append(ev[1].elapsed_time(ev[2]))
+    f_ms, b_ms = float(np.median(fwd)), float(np.median(bwd))
+    return {
+        "workload": f"force-matching + final-energy loss, jittered FCC 40^3 N={n}, {nsteps} steps, "
+                    f"checkpoint every {every}, FP32 pair math + DS state",
+        "forward_ms": f_ms, "backward_ms": b_ms, "ratio": b_ms / f_ms,
+        "loss": float(loss), "grad_norm_x0": float(gx0.norm()),
+        "dL_deps": float(gth[0]), "dL_dsigma": float(gth[3]),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +184,7 @@ def main():
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiable-workload timing")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device (a reference kernel of known "
@@ -184,6 +241,10 @@ def main():
         extra["fp64_value"] = w.n * args.steps / (r64["ms"] * 1e-3)
         extra["fp64_ms_per_step"] = r64["ms"] / args.steps
         print(f"bench: fp64 {r64['ms']:.2f} ms", file=sys.stderr, flush=True)
+
+    if not args.no_adjoint:
+        extra["adjoint"] = time_adjoint(ljmd, torch, W)
+        print(f"bench: adjoint/forward {extra['adjoint']['ratio']:.3f}", file=sys.stderr, flush=True)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(w, args.cpu_seconds)
 

@@ -392,6 +392,7 @@ def _autograd():
             x = x.detach()
             system.set_state(x, torch.zeros_like(x), species)
             ctx.system, ctx.species = system, species
+            ctx.gen = system.gen()
             ctx.save_for_backward(x, theta)
             return system.forces()
 
@@ -399,8 +400,10 @@ def _autograd():
         def backward(ctx, gF):
             x, theta = ctx.saved_tensors
             s = ctx.system
-            s.set_theta(theta.detach().cpu().numpy())
-            s.set_state(x, torch.zeros_like(x), ctx.species)
+            if s.gen() != ctx.gen:
+                # The System was used since: load x and theta again.
+                s.set_theta(theta.detach().cpu().numpy())
+                s.set_state(x, torch.zeros_like(x), ctx.species)
             gx, gth = s.force_vjp(gF.contiguous())
             return gx, gth.to(theta.device), None, None
 

@@ -282,7 +282,7 @@ def test_vv_adjoint_directional_fd_fp64(ljmd):
     assert done >= 1
 
 
-def config4_problem(m, seed):
+def loss_problem(m, seed):
     """Differentiable-workload loss: force matching at x_0 plus the energy
     after the rollout, L = |F(x_0; th) - F(x_0; th*)|^2 / 3N + U(x_N; th) / N."""
     x, box = jittered_fcc(m, 0.05, seed)
@@ -295,7 +295,7 @@ def config4_problem(m, seed):
     return x, v, sp, box, p, th, th_star
 
 
-def config4_oracle(x, v, sp, box, p, th, th_star, nsteps):
+def loss_oracle(x, v, sp, box, p, th, th_star, nsteps):
     n = len(x)
     q = oracle.with_params(p, eps=th[:3], sigma=th[3:])
     qs = oracle.with_params(p, eps=th_star[:3], sigma=th_star[3:])
@@ -311,9 +311,9 @@ def config4_oracle(x, v, sp, box, p, th, th_star, nsteps):
     return L, gxa + lx, lv, gea + geb + ue / n, gsa + gsb + us / n
 
 
-def test_config4_loss_gradient_autograd(ljmd):
+def test_force_matching_energy_loss_autograd(ljmd):
     import torch
-    x, v, sp, box, p, th, th_star = config4_problem(6, 91)
+    x, v, sp, box, p, th, th_star = loss_problem(6, 91)
     n, nsteps = len(x), 30
     sF = ljmd.System(n, box, p, precision=FP64)
     sR = ljmd.System(n, box, p, precision=FP64)
@@ -325,14 +325,14 @@ def test_config4_loss_gradient_autograd(ljmd):
     xN, vN, UN = ljmd.VVRollout.apply(x0, v0, tt, sR, sp, nsteps, 10)
     L = ((F - Fs) ** 2).sum() / (3 * n) + UN / n
     L.backward()
-    Lo, gxo, gvo, geo, gso = config4_oracle(x, v, sp, box, p, th, th_star, nsteps)
+    Lo, gxo, gvo, geo, gso = loss_oracle(x, v, sp, box, p, th, th_star, nsteps)
     assert float(L) == pytest.approx(Lo, rel=1e-10)
     gx = x0.grad.cpu().numpy()
     gv = v0.grad.cpu().numpy()
     gt = tt.grad.numpy()
     ex = float(np.abs(gx - gxo).max() / np.abs(gxo).max())
     ev = float(np.abs(gv - gvo).max() / np.abs(gvo).max())
-    print(f"config-4 loss {float(L):.12g} oracle {Lo:.12g}; grad rel err x0 {ex:.3e} v0 {ev:.3e}; "
+    print(f"loss {float(L):.12g} oracle {Lo:.12g}; grad rel err x0 {ex:.3e} v0 {ev:.3e}; "
           f"theta gpu {gt[[0, 3]]} oracle {geo[0]:.10g} {gso[0]:.10g}", flush=True)
     assert ex <= 1e-9 and ev <= 1e-9
     assert gt[0] == pytest.approx(geo[0], rel=1e-9)
