@@ -142,8 +142,9 @@ static double r2_fp64(const double *wi, const double *wj, const double *box) {
  *    lo = (float)(w - hi)  (Dekker's split into an unevaluated float sum).
  * 2) fixed-point image coordinate q = round((hi + lo) * 2^32 / L) mod 2^32,
  *    evaluated with an error-free product (TwoProduct by fma) in binary32.
- * 3) displacement from the wrapping difference of two q's, scaled by the
- *    double-single quantum L * 2^-32.                                      */
+ * 3) displacement from the wrapping difference of two q's, converted to
+ *    binary32 and scaled by the single-float quantum (float)(L * 2^-32):
+ *    one rounding of the product.                                          */
 void oracle_ds_split(double w, float *hi, float *lo) {
     float h = (float)w;
     *hi = h;
@@ -168,12 +169,9 @@ uint32_t oracle_q_from_ds(float hi, float lo, double L) {
 }
 
 float oracle_disp_q(uint32_t qi, uint32_t qj, double L) {
-    double qs = L / 4294967296.0;
-    float qs_hi = (float)qs;
-    float qs_lo = (float)(qs - (double)qs_hi);
+    float qs = (float)(L / 4294967296.0);
     int32_t dq = (int32_t)(qi - qj);
-    float a = (float)dq;
-    return fmaf(a, qs_hi, a * qs_lo);
+    return (float)dq * qs;
 }
 
 static float r2_fp32(const uint32_t *qi, const uint32_t *qj, const double *box) {
@@ -183,7 +181,8 @@ static float r2_fp32(const uint32_t *qi, const uint32_t *qj, const double *box) 
     return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
 }
 
-/* Full Verlet lists {j != i : r_ij^2 < (rcut_ab + skin)^2} by particle index,
+/* Full Verlet lists {j : 0 < r_ij^2 < (rcut_ab + skin)^2} by particle index
+ * (a particle is never its own partner, nor is one at exactly its position),
  * built with cell binning (cells of edge >= the largest list radius; a
  * particle's partners then lie in the 27 surrounding cells). With fewer than
  * three cells along an axis every particle is a candidate (plain all-pairs).
@@ -273,10 +272,13 @@ int32_t oracle_build_lists(int64_t n, const double *x, const int32_t *sp, const 
                 if (j == i) continue;
                 int ab = pair_index(p, sp[i], sp[j]);
                 int in;
-                if (mode == 0)
-                    in = r2_fp64(w + 3 * i, w + 3 * j, box) < rl2[ab];
-                else
-                    in = r2_fp32(q + 3 * i, q + 3 * j, box) < rl2f[ab];
+                if (mode == 0) {
+                    double r2 = r2_fp64(w + 3 * i, w + 3 * j, box);
+                    in = r2 > 0.0 && r2 < rl2[ab];
+                } else {
+                    float r2 = r2_fp32(q + 3 * i, q + 3 * j, box);
+                    in = r2 > 0.0f && r2 < rl2f[ab];
+                }
                 if (in) {
                     if (k < cap) nbr[(size_t)i * cap + k] = (int32_t)j;
                     k++;

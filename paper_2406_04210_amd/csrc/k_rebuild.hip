@@ -290,9 +290,9 @@ __device__ inline double cand_r2(const double4 &ri, const double4 &rj, const Box
     return fma(dz, dz, fma(dy, dy, dx * dx));
 }
 __device__ inline float cand_r2(const int4 &ri, const int4 &rj, const BoxC &box) {
-    const float dx = disp_q((uint32_t)ri.x, (uint32_t)rj.x, box.qs_hi[0], box.qs_lo[0]);
-    const float dy = disp_q((uint32_t)ri.y, (uint32_t)rj.y, box.qs_hi[1], box.qs_lo[1]);
-    const float dz = disp_q((uint32_t)ri.z, (uint32_t)rj.z, box.qs_hi[2], box.qs_lo[2]);
+    const float dx = (float)(int32_t)((uint32_t)ri.x - (uint32_t)rj.x) * box.qs_hi[0];
+    const float dy = (float)(int32_t)((uint32_t)ri.y - (uint32_t)rj.y) * box.qs_hi[1];
+    const float dz = (float)(int32_t)((uint32_t)ri.z - (uint32_t)rj.z) * box.qs_hi[2];
     return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
 }
 
@@ -306,30 +306,47 @@ __device__ inline float cand_r2(const int4 &ri, const int4 &rj, const BoxC &box)
 // stated sequence of the precision, j != i), and a ballot compacts the hits
 // into the particle's list in candidate order. No lane ever idles on a
 // shorter loop than its neighbours, and the list order is reproducible.
+//
+// The home particles (up to 64 at a time) and their running list lengths
+// live in registers, one per lane; the loop over them reads both with
+// readlane, so the inner loop needs no LDS traffic and no wave barrier,
+// and the list stores are never waited on.
 template <int PREC>
 struct NlistChunk {
     static constexpr int CH = PREC == LJMD_FP64 ? 4 : 8;  // 64-candidate blocks per chunk
 };
 
-template <int PREC>
-__host__ __device__ inline size_t nlist_lds_per_wave(int cell_cap, size_t rec_bytes) {
-    return (((size_t)cell_cap * (rec_bytes + sizeof(int32_t))) + 15) & ~(size_t)15;
+// Waves per list-build block, and blocks per compute unit when a rebuild is
+// due (the kernel strides over contiguous runs of cells).
+constexpr int kNlWaves = 4;
+constexpr int kNlBlocksPerCu = 4;
+
+__device__ inline int lane_read(int v, int p) { return __builtin_amdgcn_readlane(v, p); }
+__device__ inline int4 lane_read(const int4 &v, int p) {
+    return make_int4(lane_read(v.x, p), lane_read(v.y, p), lane_read(v.z, p), lane_read(v.w, p));
+}
+__device__ inline double lane_read(double v, int p) {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)lane_read((int)(b & 0xffffffffll), p);
+    const unsigned hi = (unsigned)lane_read((int)(b >> 32), p);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ inline double4 lane_read(const double4 &v, int p) {
+    return make_double4(lane_read(v.x, p), lane_read(v.y, p), lane_read(v.z, p), lane_read(v.w, p));
 }
 
 template <int PREC, int NS>
-__global__ __launch_bounds__(kRbBlock) void k_nlist(State st, Geom g, BoxC box, PairC pc, int cur,
-                                                    int64_t step, int forced, float thr2) {
+__global__ __launch_bounds__(kNlWaves * kWave) void k_nlist(State st, Geom g, BoxC box, PairC pc, int cur,
+                                                            int64_t step, int forced, float thr2) {
     if (!rebuild_due(st.ctl, step, forced, thr2)) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) st.ctl->rebuilds += 1;
     using CR = CellRec<PREC>;
     using T = typename CR::T;
     constexpr int CH = NlistChunk<PREC>::CH;
-    extern __shared__ int4 lds_nl[];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, W = blockDim.x >> 6;
-    T *shome = (T *)((uint8_t *)lds_nl + (size_t)wv * nlist_lds_per_wave<PREC>(g.cell_cap, sizeof(T)));
-    int32_t *kcnt = (int32_t *)(shome + g.cell_cap);
     const T *__restrict__ cr = cell_recs<PREC>(st);
-    const unsigned long long below = (1ull << lane) - 1ull;
+    const int lg = g.lanes >= 16 ? 4 : (g.lanes >= 8 ? 3 : (g.lanes >= 4 ? 2 : (g.lanes >= 2 ? 1 : 0)));
+    const int lmask = g.lanes - 1;
     // Contiguous runs of Hilbert-ranked cells per wave; each XCD gets one
     // contiguous share of the box.
     const int tw = gridDim.x * W;
@@ -371,73 +388,90 @@ __global__ __launch_bounds__(kRbBlock) void k_nlist(State st, Geom g, BoxC box, 
         const int home_s = ((-lo[0]) * n3[1] + (-lo[1])) * n3[2] + (-lo[2]);
         const int home = __shfl(scell, home_s);
         const int m = __shfl(scnt, home_s);
-        if (m == 0) continue;
-        for (int e = lane; e < m; e += kWave) {
-            shome[e] = cr[(int64_t)home * g.cell_cap + e];
-            kcnt[e] = 0;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        for (int cb = 0; cb < ncand; cb += CH * kWave) {
-            T cand[CH];
-            bool cv[CH];
-#pragma unroll
-            for (int b = 0; b < CH; ++b) {
-                const int t = cb + b * kWave + lane;
-                // Largest stencil cell s with soff[s] <= t: a fixed 5-step
-                // binary search, every lane shuffling in every step.
-                int sel = 0;
-                for (int stp = 16; stp >= 1; stp >>= 1) {
-                    const int cand_s = sel + stp;
-                    const int v = __shfl(soff, cand_s < nst ? cand_s : nst - 1);
-                    if (cand_s < nst && v <= t) sel = cand_s;
-                }
-                const int cs = __shfl(scell, sel), os = __shfl(soff, sel);
-                cv[b] = t < ncand;
-                int e = t - os;
-                e = e < 0 ? 0 : (e >= g.cell_cap ? g.cell_cap - 1 : e);
-                const int64_t at = cv[b] ? (int64_t)cs * g.cell_cap + e : 0;
-                cand[b] = cr[at];
-            }
-            for (int p = 0; p < m; ++p) {
-                const T ri = shome[p];
-                const int i = CR::index(ri);
-                const int si = CR::species(ri);
-                int k = kcnt[p];
+        for (int h0 = 0; h0 < m; h0 += kWave) {
+            const int hm = min(m - h0, kWave);
+            // Lane e holds home particle h0 + e and the length of its list so far.
+            T hrec;
+            if (lane < hm) hrec = cr[(int64_t)home * g.cell_cap + h0 + lane];
+            else hrec = T{};
+            int kreg = 0;
+            for (int cb = 0; cb < ncand; cb += CH * kWave) {
+                // Blocks of 64 candidates this chunk holds (wave-uniform): the
+                // last chunk of a cell is usually short.
+                const int nbk = min(CH, (ncand - cb + kWave - 1) / kWave);
+                T cand[CH];
+                bool cv[CH];
+                uint32_t thr[CH];
 #pragma unroll
                 for (int b = 0; b < CH; ++b) {
-                    const int j = CR::index(cand[b]);
-                    const int tt = NS == 1 ? 0 : si + CR::species(cand[b]);
-                    bool hit;
-                    if constexpr (PREC == LJMD_FP64)
-                        hit = cand_r2(ri, cand[b], box) < by_type<NS>(tt, pc.rl2);
-                    else
-                        hit = cand_r2(ri, cand[b], box) < by_type<NS>(tt, pc.rl2f);
-                    hit = hit && cv[b] && j != i && (unsigned)j < (unsigned)g.n;
-                    const unsigned long long mask = __ballot(hit ? 1 : 0);
-                    const int pos = __popcll(mask & below);
-                    if (hit && k + pos < g.cap && (unsigned)i < (unsigned)g.n)
-                        st.nbr[nbr_index(i, k + pos, g.lanes, g.cap)] = j;
-                    k += __popcll(mask);
+                    cv[b] = false;
+                    cand[b] = T{};
+                    thr[b] = 0u;
+                    if (b >= nbk) continue;
+                    const int t = cb + b * kWave + lane;
+                    // Largest stencil cell s with soff[s] <= t: a fixed 5-step
+                    // binary search, every lane shuffling in every step.
+                    int sel = 0;
+                    for (int stp = 16; stp >= 1; stp >>= 1) {
+                        const int cand_s = sel + stp;
+                        const int v = __shfl(soff, cand_s < nst ? cand_s : nst - 1);
+                        if (cand_s < nst && v <= t) sel = cand_s;
+                    }
+                    const int cs = __shfl(scell, sel), os = __shfl(soff, sel);
+                    cv[b] = t < ncand;
+                    int e = t - os;
+                    e = e < 0 ? 0 : (e >= g.cell_cap ? g.cell_cap - 1 : e);
+                    const int64_t at = cv[b] ? (int64_t)cs * g.cell_cap + e : 0;
+                    cand[b] = cr[at];
+                    cv[b] = cv[b] && (unsigned)CR::index(cand[b]) < (unsigned)g.n;
+                    if constexpr (PREC == LJMD_FP32_DS)
+                        thr[b] = cv[b] ? __float_as_uint(pc.rl2f[0]) - 1u : 0u;
                 }
-                if (lane == 0) kcnt[p] = k;
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                __builtin_amdgcn_wave_barrier();
+                for (int p = 0; p < hm; ++p) {
+                    const T ri = lane_read(hrec, p);
+                    const int i = CR::index(ri);
+                    if ((unsigned)i >= (unsigned)g.n) continue;
+                    const int si = CR::species(ri);
+                    int k = lane_read(kreg, p);
+                    // Entry kk of particle i: row[((kk >> lg) << 6) | (kk & (lanes - 1))].
+                    int32_t *__restrict__ row = st.nbr + nbr_index(i, 0, g.lanes, g.cap);
+#pragma unroll
+                    for (int b = 0; b < CH; ++b) {
+                        if (b >= nbk) break;
+                        const int j = CR::index(cand[b]);
+                        const int tt = NS == 1 ? 0 : si + CR::species(cand[b]);
+                        bool hit;
+                        if constexpr (PREC == LJMD_FP64) {
+                            const double r2 = cand_r2(ri, cand[b], box);
+                            hit = cv[b] && r2 > 0.0 && r2 < by_type<NS>(tt, pc.rl2);
+                        } else {
+                            // 0 < r^2 < r_L^2 as one unsigned compare of the bit
+                            // patterns (r^2 >= 0); thr[b] is 0 for empty lanes.
+                            const uint32_t lim = NS == 1 ? thr[b] : (cv[b] ? __float_as_uint(by_type<NS>(tt, pc.rl2f)) - 1u : 0u);
+                            hit = __float_as_uint(cand_r2(ri, cand[b], box)) - 1u < lim;
+                        }
+                        const unsigned long long mask = __ballot(hit ? 1 : 0);
+                        if (mask == 0ull) continue;
+                        const uint32_t kk = (uint32_t)k + __builtin_amdgcn_mbcnt_hi(
+                                                              (uint32_t)(mask >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                        if (hit && kk < (uint32_t)g.cap) row[((kk >> lg) << 6) | (kk & (uint32_t)lmask)] = j;
+                        k += __popcll(mask);
+                    }
+                    kreg = lane == p ? k : kreg;
+                }
+            }
+            if (lane < hm) {
+                const int i = CR::index(hrec);
+                if ((unsigned)i < (unsigned)g.n) {
+                    uint32_t q[3];
+                    rec_q(hrec, box, q);
+                    st.nbr_cnt[i] = kreg;
+                    st.xref[i] = make_int4((int)q[0], (int)q[1], (int)q[2], 0);
+                    if (kreg > g.cap) atomicOr(&st.ctl->flags, kErrList);
+                }
             }
         }
-        for (int e = lane; e < m; e += kWave) {
-            const T r = shome[e];
-            const int i = CR::index(r);
-            if ((unsigned)i >= (unsigned)g.n) continue;
-            const int k = kcnt[e];
-            uint32_t q[3];
-            rec_q(r, box, q);
-            st.nbr_cnt[i] = k;
-            st.xref[i] = make_int4((int)q[0], (int)q[1], (int)q[2], 0);
-            if (k > g.cap) atomicOr(&st.ctl->flags, kErrList);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -501,12 +535,12 @@ hipError_t launch_resort(const Launch &L) {
 
 template <int PREC, int NS>
 static void nlist_launch(const Launch &L, int64_t step, int forced) {
-    const size_t per_wave = nlist_lds_per_wave<PREC>(L.g->cell_cap, cell_rec_bytes(PREC));
-    int W = kRbBlock / kWave;
-    while (W > 1 && (size_t)W * per_wave > 65536) --W;
-    const unsigned nb = rebuild_blocks(L, L.box->ncell, W);
-    hipLaunchKernelGGL((k_nlist<PREC, NS>), dim3(nb), dim3(W * kWave), (size_t)W * per_wave,
-                       L.stream, *L.st, *L.g, *L.box, *L.pc, L.cur, step, forced, L.dyn->thr2);
+    const unsigned need = blocks_for(L.box->ncell, kNlWaves);
+    const unsigned ncu = L.g->ncu > 0 ? (unsigned)L.g->ncu : 256u;
+    const unsigned cap = ncu * kNlBlocksPerCu;
+    const unsigned nb = need < cap ? (need > 0 ? need : 1u) : cap;
+    hipLaunchKernelGGL((k_nlist<PREC, NS>), dim3(nb), dim3(kNlWaves * kWave), 0, L.stream, *L.st, *L.g,
+                       *L.box, *L.pc, L.cur, step, forced, L.dyn->thr2);
 }
 
 hipError_t launch_nlist(const Launch &L, int64_t step, int forced) {
