@@ -22,6 +22,9 @@ constexpr int kNP = 8;           // doubles per partial row: U, W, K, px, py, pz
 
 // Latched device error bits (ctl->flags).
 enum : uint32_t { kErrList = 1u, kErrCell = 2u, kErrNaN = 4u };
+// List slots allocated past the last row: the FP32 force loop reads up to
+// three unrolled entries beyond a list without clamping.
+constexpr size_t kListPad = 4 * 64;
 
 // Box constants. The fixed-point image coordinate q = round(x * 2^32 / L)
 // mod 2^32 turns the minimum image into a wrapping 32-bit subtraction.
@@ -34,12 +37,17 @@ struct BoxC {
                                  // of the single-float quantum from r^2 in the force kernel
     int32_t nc[3];               // cells per axis
     int32_t ncell;
+    int32_t cubic;               // all three edges equal: forces may work in quanta
 };
 
 // Pair constants by symmetric pair type t = a + b (0: AA, 1: AB, 2: BB).
 struct PairC {
     double rc2[3], rl2[3], sig2[3], eps24[3], eps4[3], shift[3];
     float rc2f[3], rl2f[3], sig2f[3], eps24f[3], eps4f[3], shiftf[3];
+    // Cubic boxes: r_c^2 and sigma^2 in units of the squared quantum
+    // (L 2^-32)^2, and 24 eps / quantum, so that the force kernel can use
+    // raw fixed-point differences as displacements.
+    float rc2q[3], sig2q[3], fq[3];
 };
 
 // Integration constants per species.

@@ -17,9 +17,12 @@
 // visit adds half of the parameter terms. Only pairs inside the cutoff
 // contribute: the truncated force is differentiated where it is smooth.
 //
-// Geometry and pair arithmetic repeat those of the step kernel of the same
-// precision (same displacement, same r^2, same cutoff test), so the product
-// is the derivative of exactly the forces the dynamics uses. The FP32 path
+// Geometry and pair arithmetic follow the step kernel of the same precision:
+// FP64 repeats its displacement, r^2 and cutoff test; FP32 uses its general
+// form (fixed-point difference times the single-float quantum, r^2 corrected
+// per axis for the quantum's rounding), which the one-species cubic-box force
+// loop evaluates in quanta instead -- the same r^2 up to rounding, so the two
+// can disagree only about pairs within rounding of r_c. The FP32 path
 // accumulates gx in FP32 like the forces; parameter sums are FP64 everywhere,
 // reduced per block and then over blocks in a fixed order.
 #include "adjoint.h"

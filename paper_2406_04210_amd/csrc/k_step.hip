@@ -66,7 +66,14 @@ __device__ inline void step_housekeeping(const StepArgs &a) {
 }
 
 // ---------------------------------------------------------------- FP32 ---
-template <int NS, int LANES>
+// Q: one species in a cubic box. Then the pair loop works in quanta: the
+// raw wrapped fixed-point differences are the displacements, r_c^2 and
+// sigma^2 are pre-divided by the squared quantum (exactly, in FP64, before
+// one rounding), and the quantum goes into the final force factor
+// 24 eps / quantum. The lists are padded and every slot holds a valid index,
+// so the entries the unrolled loop reads past a list are loaded unclamped
+// and skipped.
+template <int NS, int LANES, bool Q>
 __global__ __launch_bounds__(kBlock) void k_step_ds(StepArgs a) {
     constexpr int P = kWave / LANES;
     constexpr int WPB = kBlock / kWave;
@@ -104,6 +111,40 @@ __global__ __launch_bounds__(kBlock) void k_step_ds(StepArgs a) {
     // Four list entries per trip: all index loads, then all record gathers,
     // are in flight before the arithmetic of the first one.
     constexpr int U = 4;
+    if constexpr (Q) {
+        static_assert(NS == 1, "quanta path is single-species");
+        const float rc2q = a.pc.rc2q[0], sig2q = a.pc.sig2q[0];
+        float sa = 0.f, sb = 0.f;  // per lane: sum s6^2 and sum s6 over a few dozen pairs
+        for (int m = 0; m < iters; m += U) {
+            int jj[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) jj[u] = nb[(int64_t)(m + u) * kWave];
+            int4 rr[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) rr[u] = rec[jj[u]];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const float dx = (float)(int32_t)((uint32_t)ri.x - (uint32_t)rr[u].x);
+                const float dy = (float)(int32_t)((uint32_t)ri.y - (uint32_t)rr[u].y);
+                const float dz = (float)(int32_t)((uint32_t)ri.z - (uint32_t)rr[u].z);
+                const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                if (m + u < iters && r2 < rc2q) {
+                    const float ir2 = __builtin_amdgcn_rcpf(r2);
+                    const float s2 = sig2q * ir2;
+                    const float s6 = s2 * s2 * s2;
+                    const float t = (s6 * ir2) * fmaf(2.0f, s6, -1.0f);
+                    fx = fmaf(t, dx, fx);
+                    fy = fmaf(t, dy, fy);
+                    fz = fmaf(t, dz, fz);
+                    sa = fmaf(s6, s6, sa);
+                    sb += s6;
+                    an += 1;
+                }
+            }
+        }
+        a12 = (double)sa;
+        a6 = (double)sb;
+    } else {
     for (int m = 0; m < iters; m += U) {
         // Indices past the list end are clamped to its last entry, so every
         // load is in bounds; those entries are then skipped.
@@ -154,6 +195,7 @@ __global__ __launch_bounds__(kBlock) void k_step_ds(StepArgs a) {
             }
         }
     }
+    }
     if constexpr (LANES > 1) {
 #pragma unroll
         for (int o = LANES / 2; o > 0; o >>= 1) {
@@ -171,7 +213,7 @@ __global__ __launch_bounds__(kBlock) void k_step_ds(StepArgs a) {
         }
     }
     if constexpr (NS == 1) {
-        const float c24 = a.pc.eps24f[0];
+        const float c24 = Q ? a.pc.fq[0] : a.pc.eps24f[0];
         fx *= c24;
         fy *= c24;
         fz *= c24;
@@ -466,10 +508,13 @@ hipError_t launch_step(const Launch &L, int64_t step, int forced, int mode, int 
     dim3 grid(step_blocks(*L.g)), block(kBlock);
     const bool ds = L.g->prec == LJMD_FP32_DS;
     const bool two = L.g->nspecies == 2;
+    const bool quanta = ds && !two && L.box->cubic;
 #define STEP(NS, LN)                                                                     \
     do {                                                                                 \
-        if (ds)                                                                          \
-            hipLaunchKernelGGL((k_step_ds<NS, LN>), grid, block, 0, L.stream, a);        \
+        if (ds && NS == 1 && quanta)                                                     \
+            hipLaunchKernelGGL((k_step_ds<1, LN, true>), grid, block, 0, L.stream, a);   \
+        else if (ds)                                                                     \
+            hipLaunchKernelGGL((k_step_ds<NS, LN, false>), grid, block, 0, L.stream, a); \
         else                                                                             \
             hipLaunchKernelGGL((k_step_fp64<NS, LN>), grid, block, 0, L.stream, a);      \
     } while (0)

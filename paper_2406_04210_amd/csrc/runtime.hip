@@ -221,7 +221,9 @@ Plan make_plan(const ljmd_params *p) {
     pl.off_id = take(sizeof(int32_t) * N);
     pl.off_xref = take(sizeof(int4) * N);
     pl.off_cnt = take(sizeof(int32_t) * N);
-    pl.off_nbr = take(sizeof(int32_t) * (size_t)N * pl.cap);
+    // Lists, plus one row block past the end: the force kernel reads a few
+    // entries beyond a list (they hold valid indices and are not used).
+    pl.off_nbr = take(sizeof(int32_t) * ((size_t)N * pl.cap + kListPad));
     pl.off_ccount = take(sizeof(int32_t) * pl.ncell);
     pl.off_cmem = take(cell_rec_bytes(p->precision) * (size_t)pl.ncell * pl.cell_cap);
     pl.off_cstart = take(sizeof(int32_t) * (pl.ncell + 1));
@@ -287,6 +289,7 @@ void fill_constants(ljmd_ctx *c, const Plan &pl) {
         b.nc[k] = pl.nc[k];
     }
     b.ncell = pl.ncell;
+    b.cubic = (p.box[0] == p.box[1] && p.box[1] == p.box[2]) ? 1 : 0;
     fill_pairs(c->pc, p);
     DynC &d = c->dyn;
     for (int s = 0; s < 2; ++s) {
@@ -323,6 +326,11 @@ void fill_pairs(PairC &q, const ljmd_params &p) {
         q.eps24f[t] = (float)q.eps24[t];
         q.eps4f[t] = (float)q.eps4[t];
         q.shiftf[t] = (float)q.shift[t];
+        // In units of the quantum of a cubic box (edge box[0]).
+        const double qs = p.box[0] / kTwo32;
+        q.rc2q[t] = (float)(q.rc2[t] / (qs * qs));
+        q.sig2q[t] = (float)(q.sig2[t] / (qs * qs));
+        q.fq[t] = (float)(q.eps24[t] / qs);
     }
 }
 
@@ -688,6 +696,9 @@ int ljmd_create(const ljmd_params *p, void *ws, size_t bytes, void *stream, ljmd
     if (e == hipSuccess) e = hipMemsetAsync(s.cell_count, 0, sizeof(int32_t) * pl.ncell, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s.ctl, 0, sizeof(Ctl), c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s.nbr_cnt, 0, sizeof(int32_t) * pl.npad, c->stream);
+    // Every list slot holds a valid particle index from the start (0).
+    if (e == hipSuccess)
+        e = hipMemsetAsync(s.nbr, 0, sizeof(int32_t) * ((size_t)pl.npad * pl.cap + kListPad), c->stream);
     // The rank table comes from pageable host memory: finish before it goes away.
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
