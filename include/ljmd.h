@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define LJMD_ABI_VERSION 2
+#define LJMD_ABI_VERSION 3
 
 enum ljmd_status {
     LJMD_OK = 0,
@@ -267,6 +267,56 @@ int ljmd_vv_forward(ljmd_ctx *ctx, int32_t nsteps, int32_t ckpt_every, int32_t f
  * changed since. Asynchronous. */
 int ljmd_vv_backward(ljmd_ctx *ctx, const double *lam_x, const double *lam_v, double *gx0,
                      double *gv0, double *gtheta);
+
+/* ---- Batches of systems ------------------------------------------------------
+ * Many independent one-species systems (replicas) of uneven size in cubic
+ * boxes, stepped together: every kernel of a step spans all of them at once
+ * over a flattened list of particles, cells and blocks, and each system keeps
+ * its own list-rebuild decisions and observables. A system's trajectory is
+ * the one it has as a single box with the same parameters (the batch is a
+ * layout, not an approximation). Shared parameters (potential, masses, dt,
+ * skin, sort_interval, lanes, capacities) come from one ljmd_params whose n
+ * and box are ignored; nspecies must be 1 and precision LJMD_FP32_DS. The
+ * paper runs one box per launch; batching is this library's addition. */
+typedef struct ljmd_batch ljmd_batch;
+
+typedef struct {
+    int64_t n;   /* particles */
+    double box;  /* edge of the cubic box */
+} ljmd_system;
+
+/* Device bytes a batch of these systems needs (0 if any is invalid). */
+size_t ljmd_batch_workspace_size(const ljmd_params *shared, const ljmd_system *sys, int32_t nsys);
+
+/* Create a batch on the current device (workspace as for ljmd_create).
+ * Enqueues initialisation on the stream and waits for it. */
+int ljmd_batch_create(const ljmd_params *shared, const ljmd_system *sys, int32_t nsys, void *dev_workspace,
+                      size_t bytes, void *hip_stream, ljmd_batch **out);
+
+int ljmd_batch_destroy(ljmd_batch *b);
+
+/* Load every system: x, v (device, sum(n)*3 float64) and species (device,
+ * sum(n) int32), system k's rows following system k-1's. Then, per system,
+ * what ljmd_set_state does. */
+int ljmd_batch_set_state(ljmd_batch *b, const double *x, const double *v, const int32_t *species);
+
+/* Advance every system nsteps (as ljmd_run). obs_dev (device, nsys *
+ * LJMD_NOBS float64, or NULL) receives each system's observables of the last
+ * step, with column 6 holding its list builds so far. Asynchronous. */
+int ljmd_batch_run(ljmd_batch *b, int64_t nsteps, double *obs_dev);
+
+/* State and forces in the concatenated row order of ljmd_batch_set_state. */
+int ljmd_batch_get_state(ljmd_batch *b, double *x, double *v, int32_t *img);
+int ljmd_batch_get_forces(ljmd_batch *b, double *f);
+
+/* Synchronise and copy each system's last observable row to obs_host (host,
+ * nsys * LJMD_NOBS float64). */
+int ljmd_batch_observables(ljmd_batch *b, double *obs_host);
+
+/* Synchronise; the first latched device error of any system, or LJMD_OK. */
+int ljmd_batch_sync_status(ljmd_batch *b);
+
+const char *ljmd_batch_last_error(const ljmd_batch *b);
 
 /* Text of the last error of ctx (or of the last failed create when ctx is
  * NULL). The pointer stays valid until the next call on ctx. */

@@ -38,16 +38,16 @@ struct BoxC {
     int32_t nc[3];               // cells per axis
     int32_t ncell;
     int32_t cubic;               // all three edges equal: forces may work in quanta
+    // Cubic boxes, species pair AA: r_c^2 and sigma^2 in units of the squared
+    // quantum (L 2^-32)^2, and 24 eps / quantum, so that the force kernel can
+    // use raw fixed-point differences as displacements.
+    float rc2q, sig2q, fq;
 };
 
 // Pair constants by symmetric pair type t = a + b (0: AA, 1: AB, 2: BB).
 struct PairC {
     double rc2[3], rl2[3], sig2[3], eps24[3], eps4[3], shift[3];
     float rc2f[3], rl2f[3], sig2f[3], eps24f[3], eps4f[3], shiftf[3];
-    // Cubic boxes: r_c^2 and sigma^2 in units of the squared quantum
-    // (L 2^-32)^2, and 24 eps / quantum, so that the force kernel can use
-    // raw fixed-point differences as displacements.
-    float rc2q[3], sig2q[3], fq[3];
 };
 
 // Integration constants per species.
@@ -71,6 +71,23 @@ struct Ctl {
     int32_t pad[2];
     double last[kNP];     // observables of the last flushed step: U, W, K, px, py, pz, rebuilt, step
 };
+
+// One system of a batch (independent boxes sharing the potential and the
+// integration constants). Its particles occupy slots [p_off, p_off + n) of
+// the flattened arrays, padded to a multiple of kSysAlign slots; its cells
+// are [c_off, c_off + box.ncell); its step-kernel blocks [b_off, b_off + nb).
+struct SysC {
+    BoxC box;
+    int64_t p_off;   // first slot
+    int64_t in_off;  // first row of the caller's concatenated arrays
+    int32_t n;       // particles
+    int32_t id;      // index of the system (its control words are ctl[id])
+    int32_t c_off;   // first cell
+    int32_t b_off;   // first step-kernel block
+    int32_t nb;      // step-kernel blocks
+    int32_t pad;
+};
+constexpr int kSysAlign = 256;
 
 // Views of the caller's workspace (all device pointers).
 struct State {

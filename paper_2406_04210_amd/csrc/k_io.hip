@@ -2,6 +2,7 @@
 // reading state, forces and lists back by id, and the deterministic FP64
 // reduction of per-block observable partials (paper Sec. 4 "Mixed
 // Strategy": reductions; Sec. 3: observables sampled between steps).
+#include "batch.h"
 #include "internal.h"
 
 namespace ljmd {
@@ -10,19 +11,17 @@ namespace ljmd {
 //   f = floor(x / L); w = x - L f; if (w >= L) { w -= L; f += 1; }
 // and, in the FP32 path, split w and v into double-single pairs
 // (hi = (float) w, lo = (float)(w - hi)) and form the fixed-point record.
+// Slot i takes row `row` of the caller's arrays (its id).
 template <int PREC>
-__global__ __launch_bounds__(kBlock) void k_set_state(State st, Geom g, BoxC box, int cur,
-                                                      const double *__restrict__ x,
-                                                      const double *__restrict__ v,
-                                                      const int32_t *__restrict__ sp) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= g.n) return;
-    int s = sp[i];
+__device__ inline void set_one(const State &st, const Geom &g, const BoxC &box, int cur, int64_t i,
+                               int64_t row, const double *__restrict__ x, const double *__restrict__ v,
+                               const int32_t *__restrict__ sp) {
+    int s = sp[row];
     s = s < 0 ? 0 : (s >= g.nspecies ? g.nspecies - 1 : s);
     double w[3];
     int im[3];
     for (int k = 0; k < 3; ++k) {
-        const double xi = x[3 * i + k];
+        const double xi = x[3 * row + k];
         double f = floor(xi / box.L[k]);
         double t = xi - box.L[k] * f;
         if (t >= box.L[k]) {
@@ -33,8 +32,8 @@ __global__ __launch_bounds__(kBlock) void k_set_state(State st, Geom g, BoxC box
         im[k] = (int)f;
     }
     st.img[i] = make_int4(im[0], im[1], im[2], 0);
-    st.id[i] = (int32_t)i;
-    const double vx = v[3 * i], vy = v[3 * i + 1], vz = v[3 * i + 2];
+    st.id[i] = (int32_t)row;
+    const double vx = v[3 * row], vy = v[3 * row + 1], vz = v[3 * row + 2];
     if constexpr (PREC == LJMD_FP64) {
         st.rec64[cur][i] = make_double4(w[0], w[1], w[2], (double)s);
         st.vel64[i] = make_double4(vx, vy, vz, 0.0);
@@ -54,6 +53,16 @@ __global__ __launch_bounds__(kBlock) void k_set_state(State st, Geom g, BoxC box
         st.vel_lo[i] = make_float4((float)(vx - (double)vhx), (float)(vy - (double)vhy),
                                    (float)(vz - (double)vhz), 0.f);
     }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_set_state(State st, Geom g, BoxC box, int cur,
+                                                      const double *__restrict__ x,
+                                                      const double *__restrict__ v,
+                                                      const int32_t *__restrict__ sp) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= g.n) return;
+    set_one<PREC>(st, g, box, cur, i, i, x, v, sp);
 }
 
 template <int PREC>
@@ -184,6 +193,100 @@ __global__ __launch_bounds__(kBlock) void k_max_fill(State st, Geom g) {
     }
 }
 
+// ---- batches of systems -------------------------------------------------
+// Slot i of a batch belongs to the system sys[sys_of_g16[i >> 4]] (systems
+// are padded to whole blocks of slots); slots past a system's particles are
+// padding and stay inert (no id, no list, never binned or moved).
+__device__ inline const SysC &sys_of(const SysC *sys, const int32_t *sys_of_g16, int64_t i) {
+    return sys[sys_of_g16[i >> 4]];
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_set_state(State st, Geom g, const SysC *sys,
+                                                            const int32_t *sys_of_g16, int cur,
+                                                            const double *__restrict__ x,
+                                                            const double *__restrict__ v,
+                                                            const int32_t *__restrict__ sp) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= g.n) return;
+    const SysC &y = sys_of(sys, sys_of_g16, i);
+    const int64_t local = i - y.p_off;
+    if (local >= y.n) {
+        st.id[i] = -1;
+        st.img[i] = make_int4(0, 0, 0, 0);
+        st.recq[cur][i] = make_int4(0, 0, 0, 0);
+        st.pos_hi[i] = st.pos_lo[i] = st.vel_hi[i] = st.vel_lo[i] = st.frc32[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        st.nbr_cnt[i] = 0;
+        return;
+    }
+    set_one<LJMD_FP32_DS>(st, g, y.box, cur, i, y.in_off + local, x, v, sp);
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_get(State st, Geom g, const SysC *sys,
+                                                      const int32_t *sys_of_g16, int cur, double *x,
+                                                      double *v, int32_t *img, double *f) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= g.n) return;
+    const SysC &y = sys_of(sys, sys_of_g16, i);
+    if (i - y.p_off >= y.n) return;
+    const int64_t row = st.id[i];
+    if (row < y.in_off || row >= y.in_off + y.n) return;
+    if (x || v) {
+        const float4 h = st.pos_hi[i], l = st.pos_lo[i];
+        const float4 vh = st.vel_hi[i], vl = st.vel_lo[i];
+        if (x) {
+            x[3 * row] = (double)h.x + (double)l.x;
+            x[3 * row + 1] = (double)h.y + (double)l.y;
+            x[3 * row + 2] = (double)h.z + (double)l.z;
+        }
+        if (v) {
+            v[3 * row] = (double)vh.x + (double)vl.x;
+            v[3 * row + 1] = (double)vh.y + (double)vl.y;
+            v[3 * row + 2] = (double)vh.z + (double)vl.z;
+        }
+    }
+    if (img) {
+        const int4 m = st.img[i];
+        img[3 * row] = m.x;
+        img[3 * row + 1] = m.y;
+        img[3 * row + 2] = m.z;
+    }
+    if (f) {
+        const float4 r = st.frc32[i];
+        f[3 * row] = r.x;
+        f[3 * row + 1] = r.y;
+        f[3 * row + 2] = r.z;
+    }
+}
+
+// One block per system: its step-kernel rows of ring slot `slot`, reduced in
+// the same fixed order as a single box's (strided per thread, then the LDS
+// tree), so a system's observables match its run as a single box.
+__global__ __launch_bounds__(kBlock) void k_batch_obs(State st, Geom g, const SysC *sys, int slot, int64_t step,
+                                                      double *out) {
+    __shared__ double red[kBlock][6];
+    const SysC &y = sys[blockIdx.x];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < y.nb; b += kBlock) {
+        const double *r = st.partials + ((size_t)slot * g.max_blocks + y.b_off + b) * kNP;
+        for (int q = 0; q < 6; ++q) acc[q] += r[q];
+    }
+    for (int q = 0; q < 6; ++q) red[threadIdx.x][q] = acc[q];
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+            for (int q = 0; q < 6; ++q) red[threadIdx.x][q] += red[threadIdx.x + s][q];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        Ctl *ctl = st.ctl + y.id;
+        double row[kNP] = {red[0][0], red[0][2], red[0][1], red[0][3],
+                           red[0][4], red[0][5], (double)ctl->rebuilds, (double)step};
+        for (int q = 0; q < kNP; ++q) ctl->last[q] = row[q];
+        if (out)
+            for (int q = 0; q < kNP; ++q) out[(size_t)y.id * kNP + q] = row[q];
+    }
+}
+
 // ------------------------------------------------------------------------
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
@@ -233,6 +336,33 @@ hipError_t launch_obs_reduce(const Launch &L, int64_t first_step, int count, int
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_obs_reduce, dim3(count), dim3(kBlock), 0, L.stream, *L.st, *L.g,
                        first_step, nblocks, obs_dev, obs_row0, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_set_state(const Launch &L, const SysC *sys, const int32_t *sys_of_g16, int64_t nslots,
+                                  const double *x, const double *v, const int32_t *sp) {
+    hipLaunchKernelGGL(k_batch_set_state, dim3(nblk(nslots)), dim3(kBlock), 0, L.stream, *L.st, *L.g, sys,
+                       sys_of_g16, L.cur, x, v, sp);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_get_state(const Launch &L, const SysC *sys, const int32_t *sys_of_g16, int64_t nslots,
+                                  double *x, double *v, int32_t *img) {
+    hipLaunchKernelGGL(k_batch_get, dim3(nblk(nslots)), dim3(kBlock), 0, L.stream, *L.st, *L.g, sys, sys_of_g16,
+                       L.cur, x, v, img, (double *)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_get_forces(const Launch &L, const SysC *sys, const int32_t *sys_of_g16, int64_t nslots,
+                                   double *f) {
+    hipLaunchKernelGGL(k_batch_get, dim3(nblk(nslots)), dim3(kBlock), 0, L.stream, *L.st, *L.g, sys, sys_of_g16,
+                       L.cur, (double *)nullptr, (double *)nullptr, (int32_t *)nullptr, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_obs(const Launch &L, const SysC *sys, int nsys, int slot, int64_t step, double *out) {
+    hipLaunchKernelGGL(k_batch_obs, dim3((unsigned)nsys), dim3(kBlock), 0, L.stream, *L.st, *L.g, sys, slot, step,
+                       out);
     return hipGetLastError();
 }
 

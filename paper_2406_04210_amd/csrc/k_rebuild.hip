@@ -14,6 +14,7 @@
 // build exceeded half the skin -- paper Sec. 5: more movement, more list
 // updates). The decision reads one control word written by the previous
 // step's kernel, so no host synchronisation is needed per step.
+#include "batch.h"
 #include "internal.h"
 
 namespace ljmd {
@@ -82,66 +83,76 @@ __device__ inline const typename CellRec<PREC>::T *records(const State &st, int 
 // inside the grid), counted with an atomic per cell. The slot a particle
 // lands in is arbitrary; k_canon restores a deterministic order.
 template <int PREC>
+__device__ inline void bin_one(const State &st, const Geom &g, const BoxC &box, const int32_t *rank_of,
+                               int64_t c_off, int cur, int64_t i, Ctl *ctl) {
+    using CR = CellRec<PREC>;
+    const auto r = records<PREC>(st, cur)[i];
+    uint32_t q[3];
+    rec_q(r, box, q);
+    int cx, cy, cz;
+    const int64_t c = c_off + cell_of_q(q[0], q[1], q[2], box, rank_of, &cx, &cy, &cz);
+    const int slot = atomicAdd(&st.cell_count[c], 1);
+    if (slot < g.cell_cap)
+        cell_recs<PREC>(st)[c * g.cell_cap + slot] = CR::pack(r, (int)i);
+    else
+        atomicOr(&ctl->flags, kErrCell);
+}
+
+template <int PREC>
 __global__ __launch_bounds__(kRbBlock) void k_bin(State st, Geom g, BoxC box, int cur, int64_t step,
                                                 int forced, float thr2) {
     if (blockIdx.x == 0 && threadIdx.x == 0) st.ctl->maxd[(step + 1) & 1] = 0u;
     if (!rebuild_due(st.ctl, step, forced, thr2)) return;
-    using CR = CellRec<PREC>;
-    const auto *rec = records<PREC>(st, cur);
-    auto *cr = cell_recs<PREC>(st);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.n; i += stride) {
-        const auto r = rec[i];
-        uint32_t q[3];
-        rec_q(r, box, q);
-        int cx, cy, cz;
-        const int c = cell_of_q(q[0], q[1], q[2], box, st.rank_of, &cx, &cy, &cz);
-        const int slot = atomicAdd(&st.cell_count[c], 1);
-        if (slot < g.cell_cap)
-            cr[(int64_t)c * g.cell_cap + slot] = CR::pack(r, (int)i);
-        else
-            atomicOr(&st.ctl->flags, kErrCell);
-    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.n; i += stride)
+        bin_one<PREC>(st, g, box, st.rank_of, 0, cur, i, st.ctl);
 }
 
 // Canonicalise: one wavefront per cell sorts the cell's slots by particle
 // index (distinct keys, rank counting in LDS), so that list order and hence
 // force summation order are reproducible run to run.
 template <int PREC>
+__device__ inline void canon_cell(const State &st, const Geom &g, int64_t c, typename CellRec<PREC>::T *tmp,
+                                  int32_t *key) {
+    using CR = CellRec<PREC>;
+    using T = typename CR::T;
+    const int lane = threadIdx.x & 63;
+    const int cnt = st.cell_count[c];
+    const int m = cnt < g.cell_cap ? cnt : g.cell_cap;
+    T *mem = cell_recs<PREC>(st) + c * g.cell_cap;
+    for (int e = lane; e < m; e += kWave) key[e] = CR::index(mem[e]);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int e = lane; e < m; e += kWave) {
+        const int v = key[e];
+        int r = 0;
+        for (int k = 0; k < m; ++k) r += key[k] < v ? 1 : 0;
+        tmp[r < m ? r : m - 1] = mem[e];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int e = lane; e < m; e += kWave) mem[e] = tmp[e];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <int PREC>
 __global__ __launch_bounds__(kRbBlock) void k_canon(State st, Geom g, BoxC box, int64_t step,
                                                  int forced, float thr2) {
     if (!rebuild_due(st.ctl, step, forced, thr2)) return;
-    using CR = CellRec<PREC>;
-    using T = typename CR::T;
+    using T = typename CellRec<PREC>::T;
     extern __shared__ int4 sm_raw[];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, W = blockDim.x >> 6;
+    const int wv = threadIdx.x >> 6, W = blockDim.x >> 6;
     T *tmp = (T *)((uint8_t *)sm_raw + (size_t)wv * canon_lds_per_wave(g.cell_cap, sizeof(T)));
     int32_t *key = (int32_t *)(tmp + g.cell_cap);
-    auto *cr = cell_recs<PREC>(st);
-    for (int c = blockIdx.x * W + wv; c < box.ncell; c += gridDim.x * W) {
-        const int cnt = st.cell_count[c];
-        const int m = cnt < g.cell_cap ? cnt : g.cell_cap;
-        T *mem = cr + (int64_t)c * g.cell_cap;
-        for (int e = lane; e < m; e += kWave) key[e] = CR::index(mem[e]);
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        for (int e = lane; e < m; e += kWave) {
-            const int v = key[e];
-            int r = 0;
-            for (int k = 0; k < m; ++k) r += key[k] < v ? 1 : 0;
-            tmp[r < m ? r : m - 1] = mem[e];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        for (int e = lane; e < m; e += kWave) mem[e] = tmp[e];
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-    }
+    for (int c = blockIdx.x * W + wv; c < box.ncell; c += gridDim.x * W) canon_cell<PREC>(st, g, c, tmp, key);
 }
 
 // Exclusive scan of the (capped) cell counts in Hilbert-rank order: the
 // start of every cell in the resorted particle order. One block.
-__global__ __launch_bounds__(1024) void k_scan(State st, Geom g, int ncell) {
+// Exclusive scan of the capped counts of cells [c_off, c_off + ncell) into
+// cell_start, offset by `base` (one 1024-thread block).
+__device__ inline void scan_cells(const State &st, const Geom &g, int64_t c_off, int ncell, int64_t base_slot) {
     __shared__ int32_t wsum[16];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     int32_t carry = 0;
@@ -149,7 +160,7 @@ __global__ __launch_bounds__(1024) void k_scan(State st, Geom g, int ncell) {
         const int idx = base + tid;
         int v = 0;
         if (idx < ncell) {
-            v = st.cell_count[idx];
+            v = st.cell_count[c_off + idx];
             v = v < g.cell_cap ? v : g.cell_cap;
         }
         int x = v;
@@ -169,13 +180,14 @@ __global__ __launch_bounds__(1024) void k_scan(State st, Geom g, int ncell) {
         }
         __syncthreads();
         const int excl = x - v + (wv > 0 ? wsum[wv - 1] : 0) + carry;
-        if (idx < ncell) st.cell_start[idx] = excl;
+        if (idx < ncell) st.cell_start[c_off + idx] = (int32_t)(base_slot + excl);
         const int total = wsum[15];
         __syncthreads();
         carry += total;
     }
-    if (tid == 0) st.cell_start[ncell] = carry;
 }
+
+__global__ __launch_bounds__(1024) void k_scan(State st, Geom g, int ncell) { scan_cells(st, g, 0, ncell, 0); }
 
 // Resort views of the scratch region (one copy of every per-particle array).
 struct ResortView {
@@ -335,144 +347,276 @@ __device__ inline double4 lane_read(const double4 &v, int p) {
     return make_double4(lane_read(v.x, p), lane_read(v.y, p), lane_read(v.z, p), lane_read(v.w, p));
 }
 
+// One home cell (local Hilbert rank c of a box whose cells start at c_off in
+// the flattened cell arrays; rank_of and cell_lin are that box's tables).
 template <int PREC, int NS>
-__global__ __launch_bounds__(kNlWaves * kWave) void k_nlist(State st, Geom g, BoxC box, PairC pc, int cur,
-                                                            int64_t step, int forced, float thr2) {
-    if (!rebuild_due(st.ctl, step, forced, thr2)) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) st.ctl->rebuilds += 1;
+__device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &box, const PairC &pc,
+                                  const int32_t *rank_of, const int32_t *cell_lin, int64_t c_off, int c,
+                                  Ctl *ctl) {
     using CR = CellRec<PREC>;
     using T = typename CR::T;
     constexpr int CH = NlistChunk<PREC>::CH;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, W = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63;
     const T *__restrict__ cr = cell_recs<PREC>(st);
     const int lg = g.lanes >= 16 ? 4 : (g.lanes >= 8 ? 3 : (g.lanes >= 4 ? 2 : (g.lanes >= 2 ? 1 : 0)));
     const int lmask = g.lanes - 1;
+    const int lin = cell_lin[c];
+    const int cc[3] = {lin / (box.nc[1] * box.nc[2]), (lin / box.nc[2]) % box.nc[1],
+                       lin % box.nc[2]};
+    int lo[3], n3[3];
+    for (int a = 0; a < 3; ++a) {
+        if (box.nc[a] >= 3) {
+            lo[a] = -1;
+            n3[a] = 3;
+        } else {
+            lo[a] = -cc[a];
+            n3[a] = box.nc[a];
+        }
+    }
+    const int nst = n3[0] * n3[1] * n3[2];
+    int scell = 0, scnt = 0;
+    if (lane < nst) {
+        const int a = lane / (n3[1] * n3[2]), bb = (lane / n3[2]) % n3[1], d = lane % n3[2];
+        int ax = cc[0] + lo[0] + a, ay = cc[1] + lo[1] + bb, az = cc[2] + lo[2] + d;
+        ax += ax < 0 ? box.nc[0] : (ax >= box.nc[0] ? -box.nc[0] : 0);
+        ay += ay < 0 ? box.nc[1] : (ay >= box.nc[1] ? -box.nc[1] : 0);
+        az += az < 0 ? box.nc[2] : (az >= box.nc[2] ? -box.nc[2] : 0);
+        scell = (int)c_off + rank_of[(ax * box.nc[1] + ay) * box.nc[2] + az];
+        scnt = min(st.cell_count[scell], g.cell_cap);
+    }
+    int incl = scnt;
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    const int soff = incl - scnt;
+    const int ncand = __shfl(incl, kWave - 1);
+    const int home_s = ((-lo[0]) * n3[1] + (-lo[1])) * n3[2] + (-lo[2]);
+    const int home = __shfl(scell, home_s);
+    const int m = __shfl(scnt, home_s);
+    for (int h0 = 0; h0 < m; h0 += kWave) {
+        const int hm = min(m - h0, kWave);
+        // Lane e holds home particle h0 + e and the length of its list so far.
+        T hrec;
+        if (lane < hm) hrec = cr[(int64_t)home * g.cell_cap + h0 + lane];
+        else hrec = T{};
+        int kreg = 0;
+        for (int cb = 0; cb < ncand; cb += CH * kWave) {
+            // Blocks of 64 candidates this chunk holds (wave-uniform): the
+            // last chunk of a cell is usually short.
+            const int nbk = min(CH, (ncand - cb + kWave - 1) / kWave);
+            T cand[CH];
+            bool cv[CH];
+            uint32_t thr[CH];
+#pragma unroll
+            for (int b = 0; b < CH; ++b) {
+                cv[b] = false;
+                cand[b] = T{};
+                thr[b] = 0u;
+                if (b >= nbk) continue;
+                const int t = cb + b * kWave + lane;
+                // Largest stencil cell s with soff[s] <= t: a fixed 5-step
+                // binary search, every lane shuffling in every step.
+                int sel = 0;
+                for (int stp = 16; stp >= 1; stp >>= 1) {
+                    const int cand_s = sel + stp;
+                    const int v = __shfl(soff, cand_s < nst ? cand_s : nst - 1);
+                    if (cand_s < nst && v <= t) sel = cand_s;
+                }
+                const int cs = __shfl(scell, sel), os = __shfl(soff, sel);
+                cv[b] = t < ncand;
+                int e = t - os;
+                e = e < 0 ? 0 : (e >= g.cell_cap ? g.cell_cap - 1 : e);
+                const int64_t at = cv[b] ? (int64_t)cs * g.cell_cap + e : 0;
+                cand[b] = cr[at];
+                cv[b] = cv[b] && (unsigned)CR::index(cand[b]) < (unsigned)g.n;
+                if constexpr (PREC == LJMD_FP32_DS)
+                    thr[b] = cv[b] ? __float_as_uint(pc.rl2f[0]) - 1u : 0u;
+            }
+            for (int p = 0; p < hm; ++p) {
+                const T ri = lane_read(hrec, p);
+                const int i = CR::index(ri);
+                if ((unsigned)i >= (unsigned)g.n) continue;
+                const int si = CR::species(ri);
+                int k = lane_read(kreg, p);
+                // Entry kk of particle i: row[((kk >> lg) << 6) | (kk & (lanes - 1))].
+                int32_t *__restrict__ row = st.nbr + nbr_index(i, 0, g.lanes, g.cap);
+#pragma unroll
+                for (int b = 0; b < CH; ++b) {
+                    if (b >= nbk) break;
+                    const int j = CR::index(cand[b]);
+                    const int tt = NS == 1 ? 0 : si + CR::species(cand[b]);
+                    bool hit;
+                    if constexpr (PREC == LJMD_FP64) {
+                        const double r2 = cand_r2(ri, cand[b], box);
+                        hit = cv[b] && r2 > 0.0 && r2 < by_type<NS>(tt, pc.rl2);
+                    } else {
+                        // 0 < r^2 < r_L^2 as one unsigned compare of the bit
+                        // patterns (r^2 >= 0); thr[b] is 0 for empty lanes.
+                        const uint32_t lim = NS == 1 ? thr[b] : (cv[b] ? __float_as_uint(by_type<NS>(tt, pc.rl2f)) - 1u : 0u);
+                        hit = __float_as_uint(cand_r2(ri, cand[b], box)) - 1u < lim;
+                    }
+                    const unsigned long long mask = __ballot(hit ? 1 : 0);
+                    if (mask == 0ull) continue;
+                    const uint32_t kk = (uint32_t)k + __builtin_amdgcn_mbcnt_hi(
+                                                          (uint32_t)(mask >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                    if (hit && kk < (uint32_t)g.cap) row[((kk >> lg) << 6) | (kk & (uint32_t)lmask)] = j;
+                    k += __popcll(mask);
+                }
+                kreg = lane == p ? k : kreg;
+            }
+        }
+        if (lane < hm) {
+            const int i = CR::index(hrec);
+            if ((unsigned)i < (unsigned)g.n) {
+                uint32_t q[3];
+                rec_q(hrec, box, q);
+                st.nbr_cnt[i] = kreg;
+                st.xref[i] = make_int4((int)q[0], (int)q[1], (int)q[2], 0);
+                if (kreg > g.cap) atomicOr(&ctl->flags, kErrList);
+            }
+        }
+    }
+}
+
+template <int PREC, int NS>
+__global__ __launch_bounds__(kNlWaves * kWave) void k_nlist(State st, Geom g, BoxC box, PairC pc, int cur,
+                                                            int64_t step, int forced, float thr2) {
+    (void)cur;
+    if (!rebuild_due(st.ctl, step, forced, thr2)) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) st.ctl->rebuilds += 1;
+    const int wv = threadIdx.x >> 6, W = blockDim.x >> 6;
     // Contiguous runs of Hilbert-ranked cells per wave; each XCD gets one
     // contiguous share of the box.
     const int tw = gridDim.x * W;
     const int gw = xcd_remap(blockIdx.x, gridDim.x) * W + wv;
     const int per = (box.ncell + tw - 1) / tw;
     const int cbeg = gw * per, cend = min(cbeg + per, box.ncell);
-    for (int c = cbeg; c < cend; ++c) {
-        const int lin = st.cell_lin[c];
-        const int cc[3] = {lin / (box.nc[1] * box.nc[2]), (lin / box.nc[2]) % box.nc[1],
-                           lin % box.nc[2]};
-        int lo[3], n3[3];
-        for (int a = 0; a < 3; ++a) {
-            if (box.nc[a] >= 3) {
-                lo[a] = -1;
-                n3[a] = 3;
-            } else {
-                lo[a] = -cc[a];
-                n3[a] = box.nc[a];
-            }
-        }
-        const int nst = n3[0] * n3[1] * n3[2];
-        int scell = 0, scnt = 0;
-        if (lane < nst) {
-            const int a = lane / (n3[1] * n3[2]), bb = (lane / n3[2]) % n3[1], d = lane % n3[2];
-            int ax = cc[0] + lo[0] + a, ay = cc[1] + lo[1] + bb, az = cc[2] + lo[2] + d;
-            ax += ax < 0 ? box.nc[0] : (ax >= box.nc[0] ? -box.nc[0] : 0);
-            ay += ay < 0 ? box.nc[1] : (ay >= box.nc[1] ? -box.nc[1] : 0);
-            az += az < 0 ? box.nc[2] : (az >= box.nc[2] ? -box.nc[2] : 0);
-            scell = st.rank_of[(ax * box.nc[1] + ay) * box.nc[2] + az];
-            scnt = min(st.cell_count[scell], g.cell_cap);
-        }
-        int incl = scnt;
-        for (int o = 1; o < kWave; o <<= 1) {
-            const int y = __shfl_up(incl, o);
-            if (lane >= o) incl += y;
-        }
-        const int soff = incl - scnt;
-        const int ncand = __shfl(incl, kWave - 1);
-        const int home_s = ((-lo[0]) * n3[1] + (-lo[1])) * n3[2] + (-lo[2]);
-        const int home = __shfl(scell, home_s);
-        const int m = __shfl(scnt, home_s);
-        for (int h0 = 0; h0 < m; h0 += kWave) {
-            const int hm = min(m - h0, kWave);
-            // Lane e holds home particle h0 + e and the length of its list so far.
-            T hrec;
-            if (lane < hm) hrec = cr[(int64_t)home * g.cell_cap + h0 + lane];
-            else hrec = T{};
-            int kreg = 0;
-            for (int cb = 0; cb < ncand; cb += CH * kWave) {
-                // Blocks of 64 candidates this chunk holds (wave-uniform): the
-                // last chunk of a cell is usually short.
-                const int nbk = min(CH, (ncand - cb + kWave - 1) / kWave);
-                T cand[CH];
-                bool cv[CH];
-                uint32_t thr[CH];
-#pragma unroll
-                for (int b = 0; b < CH; ++b) {
-                    cv[b] = false;
-                    cand[b] = T{};
-                    thr[b] = 0u;
-                    if (b >= nbk) continue;
-                    const int t = cb + b * kWave + lane;
-                    // Largest stencil cell s with soff[s] <= t: a fixed 5-step
-                    // binary search, every lane shuffling in every step.
-                    int sel = 0;
-                    for (int stp = 16; stp >= 1; stp >>= 1) {
-                        const int cand_s = sel + stp;
-                        const int v = __shfl(soff, cand_s < nst ? cand_s : nst - 1);
-                        if (cand_s < nst && v <= t) sel = cand_s;
-                    }
-                    const int cs = __shfl(scell, sel), os = __shfl(soff, sel);
-                    cv[b] = t < ncand;
-                    int e = t - os;
-                    e = e < 0 ? 0 : (e >= g.cell_cap ? g.cell_cap - 1 : e);
-                    const int64_t at = cv[b] ? (int64_t)cs * g.cell_cap + e : 0;
-                    cand[b] = cr[at];
-                    cv[b] = cv[b] && (unsigned)CR::index(cand[b]) < (unsigned)g.n;
-                    if constexpr (PREC == LJMD_FP32_DS)
-                        thr[b] = cv[b] ? __float_as_uint(pc.rl2f[0]) - 1u : 0u;
-                }
-                for (int p = 0; p < hm; ++p) {
-                    const T ri = lane_read(hrec, p);
-                    const int i = CR::index(ri);
-                    if ((unsigned)i >= (unsigned)g.n) continue;
-                    const int si = CR::species(ri);
-                    int k = lane_read(kreg, p);
-                    // Entry kk of particle i: row[((kk >> lg) << 6) | (kk & (lanes - 1))].
-                    int32_t *__restrict__ row = st.nbr + nbr_index(i, 0, g.lanes, g.cap);
-#pragma unroll
-                    for (int b = 0; b < CH; ++b) {
-                        if (b >= nbk) break;
-                        const int j = CR::index(cand[b]);
-                        const int tt = NS == 1 ? 0 : si + CR::species(cand[b]);
-                        bool hit;
-                        if constexpr (PREC == LJMD_FP64) {
-                            const double r2 = cand_r2(ri, cand[b], box);
-                            hit = cv[b] && r2 > 0.0 && r2 < by_type<NS>(tt, pc.rl2);
-                        } else {
-                            // 0 < r^2 < r_L^2 as one unsigned compare of the bit
-                            // patterns (r^2 >= 0); thr[b] is 0 for empty lanes.
-                            const uint32_t lim = NS == 1 ? thr[b] : (cv[b] ? __float_as_uint(by_type<NS>(tt, pc.rl2f)) - 1u : 0u);
-                            hit = __float_as_uint(cand_r2(ri, cand[b], box)) - 1u < lim;
-                        }
-                        const unsigned long long mask = __ballot(hit ? 1 : 0);
-                        if (mask == 0ull) continue;
-                        const uint32_t kk = (uint32_t)k + __builtin_amdgcn_mbcnt_hi(
-                                                              (uint32_t)(mask >> 32),
-                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-                        if (hit && kk < (uint32_t)g.cap) row[((kk >> lg) << 6) | (kk & (uint32_t)lmask)] = j;
-                        k += __popcll(mask);
-                    }
-                    kreg = lane == p ? k : kreg;
-                }
-            }
-            if (lane < hm) {
-                const int i = CR::index(hrec);
-                if ((unsigned)i < (unsigned)g.n) {
-                    uint32_t q[3];
-                    rec_q(hrec, box, q);
-                    st.nbr_cnt[i] = kreg;
-                    st.xref[i] = make_int4((int)q[0], (int)q[1], (int)q[2], 0);
-                    if (kreg > g.cap) atomicOr(&st.ctl->flags, kErrList);
-                }
-            }
+    for (int c = cbeg; c < cend; ++c)
+        nlist_cell<PREC, NS>(st, g, box, pc, st.rank_of, st.cell_lin, 0, c, st.ctl);
+}
+
+// ---- batches of systems -------------------------------------------------
+// Plan entry k holds flattened items [off[k], off[k + 1]): the last k with
+// off[k] <= t.
+__device__ inline int plan_find(const int64_t *off, int count, int64_t t) {
+    int lo = 0, hi = count;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= t) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// One block: per system the rebuild decision (forced, or its largest
+// displacement since its last build exceeded skin/2), the reset of the
+// other parity word, and the compacted list of systems that rebuild with
+// prefix sums of their particle and cell counts.
+__global__ __launch_bounds__(1024) void k_batch_plan(State st, const SysC *sys, int nsys, BatchPlan bp,
+                                                     int64_t step, int forced, float thr2) {
+    __shared__ int32_t sn[1024];
+    __shared__ int64_t sp[1024], sc[1024];
+    const int t = threadIdx.x;
+    const int per = (nsys + 1023) / 1024;
+    const int s0 = t * per, s1 = min(s0 + per, nsys);
+    int cnt = 0;
+    int64_t np = 0, nc = 0;
+    for (int s = s0; s < s1; ++s) {
+        Ctl *ctl = st.ctl + s;
+        const bool d = rebuild_due(ctl, step, forced, thr2);
+        ctl->maxd[(step + 1) & 1] = 0u;
+        bp.due[s] = d ? 1 : 0;
+        if (d) {
+            ++cnt;
+            np += sys[s].n;
+            nc += sys[s].box.ncell;
+            ctl->rebuilds += 1;
         }
     }
+    sn[t] = cnt;
+    sp[t] = np;
+    sc[t] = nc;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int a = t >= o ? sn[t - o] : 0;
+        const int64_t b = t >= o ? sp[t - o] : 0, c = t >= o ? sc[t - o] : 0;
+        __syncthreads();
+        sn[t] += a;
+        sp[t] += b;
+        sc[t] += c;
+        __syncthreads();
+    }
+    int k = sn[t] - cnt;
+    int64_t po = sp[t] - np, co = sc[t] - nc;
+    for (int s = s0; s < s1; ++s) {
+        if (!bp.due[s]) continue;
+        bp.wl_sys[k] = s;
+        bp.wl_poff[k] = po;
+        bp.wl_coff[k] = co;
+        ++k;
+        po += sys[s].n;
+        co += sys[s].box.ncell;
+    }
+    if (t == 1023) {
+        bp.wl_count[0] = sn[1023];
+        bp.wl_poff[sn[1023]] = sp[1023];
+        bp.wl_coff[sn[1023]] = sc[1023];
+    }
+}
+
+__global__ __launch_bounds__(kRbBlock) void k_batch_bin(State st, Geom g, const SysC *sys, BatchPlan bp, int cur) {
+    const int count = bp.wl_count[0];
+    const int64_t total = bp.wl_poff[count];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+        const int k = plan_find(bp.wl_poff, count, t);
+        const int s = bp.wl_sys[k];
+        const SysC &y = sys[s];
+        bin_one<LJMD_FP32_DS>(st, g, y.box, st.rank_of + y.c_off, y.c_off, cur, y.p_off + (t - bp.wl_poff[k]),
+                              st.ctl + s);
+    }
+}
+
+__global__ __launch_bounds__(kRbBlock) void k_batch_canon(State st, Geom g, const SysC *sys, BatchPlan bp) {
+    using T = typename CellRec<LJMD_FP32_DS>::T;
+    extern __shared__ int4 sm_raw[];
+    const int wv = threadIdx.x >> 6, W = blockDim.x >> 6;
+    T *tmp = (T *)((uint8_t *)sm_raw + (size_t)wv * canon_lds_per_wave(g.cell_cap, sizeof(T)));
+    int32_t *key = (int32_t *)(tmp + g.cell_cap);
+    const int count = bp.wl_count[0];
+    const int64_t total = bp.wl_coff[count];
+    for (int64_t w = (int64_t)blockIdx.x * W + wv; w < total; w += (int64_t)gridDim.x * W) {
+        const int k = plan_find(bp.wl_coff, count, w);
+        const SysC &y = sys[bp.wl_sys[k]];
+        canon_cell<LJMD_FP32_DS>(st, g, y.c_off + (w - bp.wl_coff[k]), tmp, key);
+    }
+}
+
+__global__ __launch_bounds__(kNlWaves * kWave) void k_batch_nlist(State st, Geom g, const SysC *sys, BatchPlan bp,
+                                                                  PairC pc) {
+    const int wv = threadIdx.x >> 6, W = blockDim.x >> 6;
+    const int count = bp.wl_count[0];
+    const int64_t total = bp.wl_coff[count];
+    // Contiguous runs of the flattened cells per wave.
+    const int64_t tw = (int64_t)gridDim.x * W;
+    const int64_t gw = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * W + wv;
+    const int64_t per = (total + tw - 1) / tw;
+    const int64_t cbeg = gw * per, cend = min(cbeg + per, total);
+    for (int64_t w = cbeg; w < cend; ++w) {
+        const int k = plan_find(bp.wl_coff, count, w);
+        const int s = bp.wl_sys[k];
+        const SysC &y = sys[s];
+        nlist_cell<LJMD_FP32_DS, 1>(st, g, y.box, pc, st.rank_of + y.c_off, st.cell_lin + y.c_off, y.c_off,
+                                     (int)(w - bp.wl_coff[k]), st.ctl + s);
+    }
+}
+
+// One block per system: slot offsets of its cells for a resort.
+__global__ __launch_bounds__(1024) void k_batch_scan(State st, Geom g, const SysC *sys) {
+    const SysC &y = sys[blockIdx.x];
+    scan_cells(st, g, y.c_off, y.box.ncell, y.p_off);
 }
 
 // ------------------------------------------------------------------------
@@ -551,6 +695,59 @@ hipError_t launch_nlist(const Launch &L, int64_t step, int forced) {
         if (L.g->nspecies == 1) nlist_launch<LJMD_FP32_DS, 1>(L, step, forced);
         else nlist_launch<LJMD_FP32_DS, 2>(L, step, forced);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_plan(const Launch &L, const SysC *sys, int nsys, const BatchPlan &bp, int64_t step,
+                             int forced) {
+    hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(1024), 0, L.stream, *L.st, sys, nsys, bp, step, forced,
+                       L.dyn->thr2);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_bin(const Launch &L, const SysC *sys, const BatchPlan &bp, int64_t total_particles) {
+    const unsigned nb = rebuild_blocks(L, total_particles, kRbBlock);
+    hipLaunchKernelGGL(k_batch_bin, dim3(nb), dim3(kRbBlock), 0, L.stream, *L.st, *L.g, sys, bp, L.cur);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_canon(const Launch &L, const SysC *sys, const BatchPlan &bp, int64_t total_cells) {
+    const size_t per_wave = canon_lds_per_wave(L.g->cell_cap, cell_rec_bytes(LJMD_FP32_DS));
+    int W = kRbBlock / kWave;
+    while (W > 1 && (size_t)W * per_wave > 65536) --W;
+    const unsigned nb = rebuild_blocks(L, total_cells, W);
+    hipLaunchKernelGGL(k_batch_canon, dim3(nb), dim3(W * kWave), (size_t)W * per_wave, L.stream, *L.st, *L.g, sys,
+                       bp);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_nlist(const Launch &L, const SysC *sys, const BatchPlan &bp, int64_t total_cells) {
+    const unsigned need = blocks_for(total_cells, kNlWaves);
+    const unsigned ncu = L.g->ncu > 0 ? (unsigned)L.g->ncu : 256u;
+    const unsigned cap = ncu * kNlBlocksPerCu;
+    const unsigned nb = need < cap ? (need > 0 ? need : 1u) : cap;
+    hipLaunchKernelGGL(k_batch_nlist, dim3(nb), dim3(kNlWaves * kWave), 0, L.stream, *L.st, *L.g, sys, bp, *L.pc);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_scan(const Launch &L, const SysC *sys, int nsys) {
+    hipLaunchKernelGGL(k_batch_scan, dim3((unsigned)nsys), dim3(1024), 0, L.stream, *L.st, *L.g, sys);
+    return hipGetLastError();
+}
+
+// Gather and copy of a resort over every slot of the batch (one flat range).
+hipError_t launch_batch_resort_move(const Launch &L, int64_t ncell_total) {
+    const int64_t npad = (L.g->n + 63) / 64 * 64;
+    ResortView sv = resort_view(L.st->scratch, npad, LJMD_FP32_DS);
+    BoxC all = *L.box;
+    all.ncell = (int32_t)ncell_total;
+    const int64_t slots = (int64_t)all.ncell * L.g->cell_cap;
+    hipLaunchKernelGGL(k_resort_gather<LJMD_FP32_DS>, dim3(blocks_for(slots, kBlock)), dim3(kBlock), 0, L.stream,
+                       *L.st, *L.g, all, L.cur, sv);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_resort_copy<LJMD_FP32_DS>, dim3(blocks_for(L.g->n, kBlock)), dim3(kBlock), 0, L.stream,
+                       *L.st, *L.g, L.cur, sv);
     return hipGetLastError();
 }
 

@@ -15,13 +15,14 @@
 // Gather geometry: LANES lanes per particle, 64/LANES particles per
 // wavefront; the interleaved list layout makes every list load one 256-byte
 // contiguous read. Each XCD gets a contiguous eighth of the particles.
+#include "batch.h"
 #include "step_common.h"
 
 namespace ljmd {
 
 // Block-level deterministic reduction of the six observable partials and the
 // displacement maximum; one row of partials per block.
-__device__ inline void block_finish(const StepArgs &a, int blk, double u, double w, double k,
+__device__ inline void block_finish(const StepArgs &a, Ctl *ctl, int blk, double u, double w, double k,
                                     double px, double py, double pz, uint32_t dmax) {
     constexpr int WPB = kBlock / kWave;
     __shared__ double red[WPB][6];
@@ -48,19 +49,22 @@ __device__ inline void block_finish(const StepArgs &a, int blk, double u, double
         for (int q = 0; q < WPB; ++q) m = redm[q] > m ? redm[q] : m;
         // Only "exceeded or not" decides the rebuild, so blocks below the
         // threshold skip the same-address atomic entirely.
-        if (m > __float_as_uint(a.dyn.thr2)) atomicMax(&a.st.ctl->maxd[(a.step + 1) & 1], m);
-        if (m > 0x7f800000u) atomicOr(&a.st.ctl->flags, kErrNaN);
+        if (m > __float_as_uint(a.dyn.thr2)) atomicMax(&ctl->maxd[(a.step + 1) & 1], m);
+        if (m > 0x7f800000u) atomicOr(&ctl->flags, kErrNaN);
     }
 }
 
 // Housekeeping shared by both precisions: the rebuilt marker of this step and,
 // after a rebuild, clearing the cell counters for the next binning.
-__device__ inline void step_housekeeping(const StepArgs &a) {
-    const bool rb = rebuild_due(a.st.ctl, a.step, a.forced, a.dyn.thr2);
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.st.rebuilt[a.slot] = rb ? 1 : 0;
+// Cells [c_lo, c_hi) belong to this system; block bj of its nbj blocks
+// clears every nbj-th stretch of them. rebuilt (may be NULL) receives the marker.
+__device__ inline void step_housekeeping(const StepArgs &a, const Ctl *ctl, int64_t c_lo, int64_t c_hi,
+                                         int bj, int nbj, int32_t *rebuilt) {
+    const bool rb = rebuild_due(ctl, a.step, a.forced, a.dyn.thr2);
+    if (rebuilt && bj == 0 && threadIdx.x == 0) *rebuilt = rb ? 1 : 0;
     if (rb) {
-        const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
-        for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < a.box.ncell; c += nthr)
+        const int64_t nthr = (int64_t)nbj * blockDim.x;
+        for (int64_t c = c_lo + (int64_t)bj * blockDim.x + threadIdx.x; c < c_hi; c += nthr)
             a.st.cell_count[c] = 0;
     }
 }
@@ -73,18 +77,23 @@ __device__ inline void step_housekeeping(const StepArgs &a) {
 // 24 eps / quantum. The lists are padded and every slot holds a valid index,
 // so the entries the unrolled loop reads past a list are loaded unclamped
 // and skipped.
+//
+// The body serves one block of one system: box holds its constants, ctl its
+// control words, particles below i_end are real (the rest of the block is
+// padding), and the block is number bj of the nbj blocks that share the
+// clearing of its cells [c_lo, c_hi).
 template <int NS, int LANES, bool Q>
-__global__ __launch_bounds__(kBlock) void k_step_ds(StepArgs a) {
+__device__ inline void step_ds_body(const StepArgs &a, const BoxC &box, Ctl *ctl, int blk, int64_t i_end,
+                                    int64_t c_lo, int64_t c_hi, int bj, int nbj, int32_t *rebuilt) {
     constexpr int P = kWave / LANES;
     constexpr int WPB = kBlock / kWave;
     const State &st = a.st;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t chunk = (int64_t)blk * WPB + wv;
     const int l = lane % LANES;
     const int64_t i = chunk * P + lane / LANES;
-    const bool valid = i < a.g.n;
-    step_housekeeping(a);
+    const bool valid = i < i_end;
+    step_housekeeping(a, ctl, c_lo, c_hi, bj, nbj, rebuilt);
 
     const int4 *__restrict__ rec = st.recq[a.cur];
     int4 ri = valid ? rec[i] : make_int4(0, 0, 0, 0);
@@ -92,8 +101,8 @@ __global__ __launch_bounds__(kBlock) void k_step_ds(StepArgs a) {
     cnt = cnt < a.g.cap ? cnt : a.g.cap;
     const int32_t *__restrict__ nb = st.nbr + chunk * (int64_t)(P * a.g.cap) + lane;
     const int iters = cnt > l ? (cnt - l + LANES - 1) / LANES : 0;
-    const float qsx = a.box.qs_hi[0], qsy = a.box.qs_hi[1], qsz = a.box.qs_hi[2];
-    const float qlx = a.box.qs_lo[0], qly = a.box.qs_lo[1], qlz = a.box.qs_lo[2];
+    const float qsx = box.qs_hi[0], qsy = box.qs_hi[1], qsz = box.qs_hi[2];
+    const float qlx = box.qs_lo[0], qly = box.qs_lo[1], qlz = box.qs_lo[2];
     // Pair arithmetic: d = (q_i - q_j) * quantum (wrapping difference, i.e.
     // the minimum image), u = sigma^2 / r^2, s6 = u^3. With one species the
     // per-pair constants are factored out: the lanes accumulate
@@ -107,13 +116,13 @@ __global__ __launch_bounds__(kBlock) void k_step_ds(StepArgs a) {
     double e = 0.0, w = 0.0, a12 = 0.0, a6 = 0.0;
     int an = 0;
     const float rc2_1 = a.pc.rc2f[0], sig2_1 = a.pc.sig2f[0];
-    const float c2x = a.box.r2c[0], c2y = a.box.r2c[1], c2z = a.box.r2c[2];
+    const float c2x = box.r2c[0], c2y = box.r2c[1], c2z = box.r2c[2];
     // Four list entries per trip: all index loads, then all record gathers,
     // are in flight before the arithmetic of the first one.
     constexpr int U = 4;
     if constexpr (Q) {
         static_assert(NS == 1, "quanta path is single-species");
-        const float rc2q = a.pc.rc2q[0], sig2q = a.pc.sig2q[0];
+        const float rc2q = box.rc2q, sig2q = box.sig2q;
         float sa = 0.f, sb = 0.f;  // per lane: sum s6^2 and sum s6 over a few dozen pairs
         for (int m = 0; m < iters; m += U) {
             int jj[U];
@@ -213,7 +222,7 @@ __global__ __launch_bounds__(kBlock) void k_step_ds(StepArgs a) {
         }
     }
     if constexpr (NS == 1) {
-        const float c24 = Q ? a.pc.fq[0] : a.pc.eps24f[0];
+        const float c24 = Q ? box.fq : a.pc.eps24f[0];
         fx *= c24;
         fy *= c24;
         fz *= c24;
@@ -250,16 +259,16 @@ __global__ __launch_bounds__(kBlock) void k_step_ds(StepArgs a) {
             y = ds_add(y, ds_mul(vy, a.dyn.dt_hi, a.dyn.dt_lo));
             z = ds_add(z, ds_mul(vz, a.dyn.dt_hi, a.dyn.dt_lo));
             int ix = 0, iy = 0, iz = 0;
-            wrap_ds(x, a.box.Lhi[0], a.box.Llo[0], ix);
-            wrap_ds(y, a.box.Lhi[1], a.box.Llo[1], iy);
-            wrap_ds(z, a.box.Lhi[2], a.box.Llo[2], iz);
+            wrap_ds(x, box.Lhi[0], box.Llo[0], ix);
+            wrap_ds(y, box.Lhi[1], box.Llo[1], iy);
+            wrap_ds(z, box.Lhi[2], box.Llo[2], iz);
             if (ix | iy | iz) {
                 int4 im = st.img[i];
                 st.img[i] = make_int4(im.x + ix, im.y + iy, im.z + iz, 0);
             }
-            const uint32_t qx = q_from_ds(x.hi, x.lo, a.box.S_hi[0], a.box.S_lo[0]);
-            const uint32_t qy = q_from_ds(y.hi, y.lo, a.box.S_hi[1], a.box.S_lo[1]);
-            const uint32_t qz = q_from_ds(z.hi, z.lo, a.box.S_hi[2], a.box.S_lo[2]);
+            const uint32_t qx = q_from_ds(x.hi, x.lo, box.S_hi[0], box.S_lo[0]);
+            const uint32_t qy = q_from_ds(y.hi, y.lo, box.S_hi[1], box.S_lo[1]);
+            const uint32_t qz = q_from_ds(z.hi, z.lo, box.S_hi[2], box.S_lo[2]);
             st.recq[a.cur ^ 1][i] = make_int4((int)qx, (int)qy, (int)qz, si);
             st.pos_hi[i] = make_float4(x.hi, y.hi, z.hi, 0.f);
             st.pos_lo[i] = make_float4(x.lo, y.lo, z.lo, 0.f);
@@ -274,7 +283,25 @@ __global__ __launch_bounds__(kBlock) void k_step_ds(StepArgs a) {
         st.vel_lo[i] = make_float4(vx.lo, vy.lo, vz.lo, 0.f);
         if (a.mode & kStoreForce) st.frc32[i] = make_float4(fx, fy, fz, 0.f);
     }
-    block_finish(a, blk, pu, pw, pk, ppx, ppy, ppz, dm);
+    block_finish(a, ctl, blk, pu, pw, pk, ppx, ppy, ppz, dm);
+}
+
+template <int NS, int LANES, bool Q>
+__global__ __launch_bounds__(kBlock) void k_step_ds(StepArgs a) {
+    step_ds_body<NS, LANES, Q>(a, a.box, a.st.ctl, xcd_remap(blockIdx.x, gridDim.x), a.g.n, 0, a.box.ncell,
+                               blockIdx.x, gridDim.x, a.st.rebuilt + a.slot);
+}
+
+// A batch of independent one-species cubic systems, each over its own run of
+// blocks (particle ranges padded to whole blocks): the block finds its
+// system, then runs the same body with that system's box and control words.
+template <int LANES>
+__global__ __launch_bounds__(kBlock) void k_batch_step(StepArgs a, const SysC *sys, const int32_t *sys_of_g16) {
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t first = (int64_t)blk * (kBlock / LANES);
+    const SysC &y = sys[sys_of_g16[first >> 4]];
+    step_ds_body<1, LANES, true>(a, y.box, a.st.ctl + y.id, blk, y.p_off + y.n, y.c_off, y.c_off + y.box.ncell,
+                                 blk - y.b_off, y.nb, nullptr);
 }
 
 // ---------------------------------------------------------------- FP64 ---
@@ -289,7 +316,7 @@ __global__ __launch_bounds__(kBlock) void k_step_fp64(StepArgs a) {
     const int l = lane % LANES;
     const int64_t i = chunk * P + lane / LANES;
     const bool valid = i < a.g.n;
-    step_housekeeping(a);
+    step_housekeeping(a, a.st.ctl, 0, a.box.ncell, blockIdx.x, gridDim.x, a.st.rebuilt + a.slot);
 
     const double4 *__restrict__ rec = st.rec64[a.cur];
     double4 ri = valid ? rec[i] : make_double4(0, 0, 0, 0);
@@ -393,16 +420,16 @@ __global__ __launch_bounds__(kBlock) void k_step_fp64(StepArgs a) {
         st.vel64[i] = v;
         if (a.mode & kStoreForce) st.frc64[i] = make_double4(fx, fy, fz, 0.0);
     }
-    block_finish(a, blk, pu, pw, pk, ppx, ppy, ppz, dm);
+    block_finish(a, a.st.ctl, blk, pu, pw, pk, ppx, ppy, ppz, dm);
 }
 
 // Start of a run: "integrate" from the stored forces of the current step.
 template <int PREC>
-__global__ __launch_bounds__(kBlock) void k_integrate(StepArgs a) {
+__device__ inline void integrate_body(const StepArgs &a, const BoxC &box, Ctl *ctl, int64_t i_end) {
     const State &st = a.st;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     uint32_t dm = 0u;
-    if (i < a.g.n) {
+    if (i < i_end) {
         if constexpr (PREC == LJMD_FP64) {
             const double4 r = st.rec64[a.cur][i];
             const int si = (int)r.w;
@@ -416,13 +443,13 @@ __global__ __launch_bounds__(kBlock) void k_integrate(StepArgs a) {
             int d[3] = {0, 0, 0};
             for (int k = 0; k < 3; ++k) {
                 if (x[k] < 0.0) {
-                    x[k] += a.box.L[k];
+                    x[k] += box.L[k];
                     d[k] = -1;
-                } else if (x[k] >= a.box.L[k]) {
-                    x[k] -= a.box.L[k];
+                } else if (x[k] >= box.L[k]) {
+                    x[k] -= box.L[k];
                     d[k] = 1;
                 }
-                if (x[k] >= a.box.L[k]) x[k] -= a.box.L[k];
+                if (x[k] >= box.L[k]) x[k] -= box.L[k];
             }
             if (d[0] | d[1] | d[2]) {
                 int4 im = st.img[i];
@@ -431,9 +458,9 @@ __global__ __launch_bounds__(kBlock) void k_integrate(StepArgs a) {
             st.rec64[a.cur ^ 1][i] = make_double4(x[0], x[1], x[2], r.w);
             st.vel64[i] = v;
             const int4 xr = st.xref[i];
-            const float ddx = disp_q(q_from_d(x[0], a.box.S[0]), (uint32_t)xr.x, a.box.qs_hi[0], a.box.qs_lo[0]);
-            const float ddy = disp_q(q_from_d(x[1], a.box.S[1]), (uint32_t)xr.y, a.box.qs_hi[1], a.box.qs_lo[1]);
-            const float ddz = disp_q(q_from_d(x[2], a.box.S[2]), (uint32_t)xr.z, a.box.qs_hi[2], a.box.qs_lo[2]);
+            const float ddx = disp_q(q_from_d(x[0], box.S[0]), (uint32_t)xr.x, box.qs_hi[0], box.qs_lo[0]);
+            const float ddy = disp_q(q_from_d(x[1], box.S[1]), (uint32_t)xr.y, box.qs_hi[1], box.qs_lo[1]);
+            const float ddz = disp_q(q_from_d(x[2], box.S[2]), (uint32_t)xr.z, box.qs_hi[2], box.qs_lo[2]);
             const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
             dm = d2 == d2 ? __float_as_uint(d2) : 0x7fc00000u;
         } else {
@@ -452,34 +479,46 @@ __global__ __launch_bounds__(kBlock) void k_integrate(StepArgs a) {
             y = ds_add(y, ds_mul(vy, a.dyn.dt_hi, a.dyn.dt_lo));
             z = ds_add(z, ds_mul(vz, a.dyn.dt_hi, a.dyn.dt_lo));
             int ix = 0, iy = 0, iz = 0;
-            wrap_ds(x, a.box.Lhi[0], a.box.Llo[0], ix);
-            wrap_ds(y, a.box.Lhi[1], a.box.Llo[1], iy);
-            wrap_ds(z, a.box.Lhi[2], a.box.Llo[2], iz);
+            wrap_ds(x, box.Lhi[0], box.Llo[0], ix);
+            wrap_ds(y, box.Lhi[1], box.Llo[1], iy);
+            wrap_ds(z, box.Lhi[2], box.Llo[2], iz);
             if (ix | iy | iz) {
                 int4 im = st.img[i];
                 st.img[i] = make_int4(im.x + ix, im.y + iy, im.z + iz, 0);
             }
-            const uint32_t qx = q_from_ds(x.hi, x.lo, a.box.S_hi[0], a.box.S_lo[0]);
-            const uint32_t qy = q_from_ds(y.hi, y.lo, a.box.S_hi[1], a.box.S_lo[1]);
-            const uint32_t qz = q_from_ds(z.hi, z.lo, a.box.S_hi[2], a.box.S_lo[2]);
+            const uint32_t qx = q_from_ds(x.hi, x.lo, box.S_hi[0], box.S_lo[0]);
+            const uint32_t qy = q_from_ds(y.hi, y.lo, box.S_hi[1], box.S_lo[1]);
+            const uint32_t qz = q_from_ds(z.hi, z.lo, box.S_hi[2], box.S_lo[2]);
             st.recq[a.cur ^ 1][i] = make_int4((int)qx, (int)qy, (int)qz, si);
             st.pos_hi[i] = make_float4(x.hi, y.hi, z.hi, 0.f);
             st.pos_lo[i] = make_float4(x.lo, y.lo, z.lo, 0.f);
             st.vel_hi[i] = make_float4(vx.hi, vy.hi, vz.hi, 0.f);
             st.vel_lo[i] = make_float4(vx.lo, vy.lo, vz.lo, 0.f);
             const int4 xr = st.xref[i];
-            const float ddx = disp_q(qx, (uint32_t)xr.x, a.box.qs_hi[0], a.box.qs_lo[0]);
-            const float ddy = disp_q(qy, (uint32_t)xr.y, a.box.qs_hi[1], a.box.qs_lo[1]);
-            const float ddz = disp_q(qz, (uint32_t)xr.z, a.box.qs_hi[2], a.box.qs_lo[2]);
+            const float ddx = disp_q(qx, (uint32_t)xr.x, box.qs_hi[0], box.qs_lo[0]);
+            const float ddy = disp_q(qy, (uint32_t)xr.y, box.qs_hi[1], box.qs_lo[1]);
+            const float ddz = disp_q(qz, (uint32_t)xr.z, box.qs_hi[2], box.qs_lo[2]);
             const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
             dm = d2 == d2 ? __float_as_uint(d2) : 0x7fc00000u;
         }
     }
     dm = wave_max_u(dm);
     if ((threadIdx.x & 63) == 0 && dm > __float_as_uint(a.dyn.thr2)) {
-        atomicMax(&st.ctl->maxd[(a.step + 1) & 1], dm);
-        if (dm > 0x7f800000u) atomicOr(&st.ctl->flags, kErrNaN);
+        atomicMax(&ctl->maxd[(a.step + 1) & 1], dm);
+        if (dm > 0x7f800000u) atomicOr(&ctl->flags, kErrNaN);
     }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_integrate(StepArgs a) {
+    integrate_body<PREC>(a, a.box, a.st.ctl, a.g.n);
+}
+
+// Batch form: a block of kBlock slots lies inside one system (systems are
+// padded to kSysAlign slots).
+__global__ __launch_bounds__(kBlock) void k_batch_integrate(StepArgs a, const SysC *sys, const int32_t *sys_of_g16) {
+    const SysC &y = sys[sys_of_g16[((int64_t)blockIdx.x * kBlock) >> 4]];
+    integrate_body<LJMD_FP32_DS>(a, y.box, a.st.ctl + y.id, y.p_off + y.n);
 }
 
 // ------------------------------------------------------------------------
@@ -543,6 +582,29 @@ hipError_t launch_integrate(const Launch &L, int64_t step) {
         hipLaunchKernelGGL(k_integrate<LJMD_FP64>, grid, block, 0, L.stream, a);
     else
         hipLaunchKernelGGL(k_integrate<LJMD_FP32_DS>, grid, block, 0, L.stream, a);
+    return hipGetLastError();
+}
+
+
+hipError_t launch_batch_step(const Launch &L, const SysC *sys, const int32_t *sys_of_g16, int nblocks,
+                             int64_t step, int forced, int mode, int slot) {
+    StepArgs a = make_args(L, step, forced, mode, slot);
+    const dim3 grid((unsigned)nblocks), block(kBlock);
+    switch (L.g->lanes) {
+        case 1: hipLaunchKernelGGL(k_batch_step<1>, grid, block, 0, L.stream, a, sys, sys_of_g16); break;
+        case 2: hipLaunchKernelGGL(k_batch_step<2>, grid, block, 0, L.stream, a, sys, sys_of_g16); break;
+        case 4: hipLaunchKernelGGL(k_batch_step<4>, grid, block, 0, L.stream, a, sys, sys_of_g16); break;
+        case 8: hipLaunchKernelGGL(k_batch_step<8>, grid, block, 0, L.stream, a, sys, sys_of_g16); break;
+        default: hipLaunchKernelGGL(k_batch_step<16>, grid, block, 0, L.stream, a, sys, sys_of_g16); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_integrate(const Launch &L, const SysC *sys, const int32_t *sys_of_g16, int64_t nslots,
+                                  int64_t step) {
+    StepArgs a = make_args(L, step, 0, kIntegrate, 0);
+    const dim3 grid((unsigned)(nslots / kBlock)), block(kBlock);
+    hipLaunchKernelGGL(k_batch_integrate, grid, block, 0, L.stream, a, sys, sys_of_g16);
     return hipGetLastError();
 }
 

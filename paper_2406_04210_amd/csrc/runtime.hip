@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "adjoint.h"
+#include "batch.h"
 #include "internal.h"
 
 namespace ljmd {
@@ -166,6 +167,8 @@ inline size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
 
 int32_t round_up(int32_t v, int32_t m) { return (v + m - 1) / m * m; }
 
+void lay_out(Plan &pl, int prec, int nctl);
+
 Plan make_plan(const ljmd_params *p) {
     Plan pl{};
     pl.npad = (p->n + 63) / 64 * 64;
@@ -195,7 +198,13 @@ Plan make_plan(const ljmd_params *p) {
     pl.lanes = p->lanes != 0 ? p->lanes : (p->precision == LJMD_FP64 ? 4 : 2);
     const int per_block = (kBlock / kWave) * (kWave / pl.lanes);
     pl.max_blocks = (int)((p->n + per_block - 1) / per_block);
+    lay_out(pl, p->precision, 1);
+    return pl;
+}
 
+// Byte offsets of every array in a workspace for pl.npad slots, pl.ncell
+// cells, pl.max_blocks step-kernel blocks and nctl control-word sets.
+void lay_out(Plan &pl, int prec, int nctl) {
     const int64_t N = pl.npad;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -203,7 +212,7 @@ Plan make_plan(const ljmd_params *p) {
         off += al(bytes);
         return o;
     };
-    if (p->precision == LJMD_FP64) {
+    if (prec == LJMD_FP64) {
         pl.off_rec[0] = take(sizeof(double4) * N);
         pl.off_rec[1] = take(sizeof(double4) * N);
         pl.off_vel = take(sizeof(double4) * N);
@@ -225,16 +234,15 @@ Plan make_plan(const ljmd_params *p) {
     // entries beyond a list (they hold valid indices and are not used).
     pl.off_nbr = take(sizeof(int32_t) * ((size_t)N * pl.cap + kListPad));
     pl.off_ccount = take(sizeof(int32_t) * pl.ncell);
-    pl.off_cmem = take(cell_rec_bytes(p->precision) * (size_t)pl.ncell * pl.cell_cap);
+    pl.off_cmem = take(cell_rec_bytes(prec) * (size_t)pl.ncell * pl.cell_cap);
     pl.off_cstart = take(sizeof(int32_t) * (pl.ncell + 1));
     pl.off_rank = take(sizeof(int32_t) * pl.ncell);
     pl.off_lin = take(sizeof(int32_t) * pl.ncell);
-    pl.off_scratch = take(resort_scratch_bytes(N, p->precision));
+    pl.off_scratch = take(resort_scratch_bytes(N, prec));
     pl.off_part = take(sizeof(double) * (size_t)kRing * pl.max_blocks * kNP);
     pl.off_rebuilt = take(sizeof(int32_t) * kRing);
-    pl.off_ctl = take(sizeof(Ctl));
+    pl.off_ctl = take(sizeof(Ctl) * (size_t)nctl);
     pl.total = off;
-    return pl;
 }
 
 // Skilling's transform from axes to the transposed Hilbert index (AIP Conf.
@@ -267,6 +275,7 @@ uint64_t hilbert_index3(uint32_t x, uint32_t y, uint32_t z, int bits) {
 }
 
 void fill_pairs(PairC &q, const ljmd_params &p);
+void fill_quanta(BoxC &b, const PairC &q, double L);
 
 void fill_constants(ljmd_ctx *c, const Plan &pl) {
     const ljmd_params &p = c->p;
@@ -291,6 +300,7 @@ void fill_constants(ljmd_ctx *c, const Plan &pl) {
     b.ncell = pl.ncell;
     b.cubic = (p.box[0] == p.box[1] && p.box[1] == p.box[2]) ? 1 : 0;
     fill_pairs(c->pc, p);
+    fill_quanta(b, c->pc, p.box[0]);
     DynC &d = c->dyn;
     for (int s = 0; s < 2; ++s) {
         const double m = p.mass[p.nspecies == 2 ? s : 0];
@@ -326,12 +336,15 @@ void fill_pairs(PairC &q, const ljmd_params &p) {
         q.eps24f[t] = (float)q.eps24[t];
         q.eps4f[t] = (float)q.eps4[t];
         q.shiftf[t] = (float)q.shift[t];
-        // In units of the quantum of a cubic box (edge box[0]).
-        const double qs = p.box[0] / kTwo32;
-        q.rc2q[t] = (float)(q.rc2[t] / (qs * qs));
-        q.sig2q[t] = (float)(q.sig2[t] / (qs * qs));
-        q.fq[t] = (float)(q.eps24[t] / qs);
     }
+}
+
+// Pair-AA constants in units of the quantum of a cubic box of edge L.
+void fill_quanta(BoxC &b, const PairC &q, double L) {
+    const double qs = L / kTwo32;
+    b.rc2q = (float)(q.rc2[0] / (qs * qs));
+    b.sig2q = (float)(q.sig2[0] / (qs * qs));
+    b.fq = (float)(q.eps24[0] / qs);
 }
 
 // Timing bracket around a group of launches of one kernel family.
@@ -573,6 +586,184 @@ int rebuild_at_rest(ljmd_ctx *c, int64_t step) {
     return e == hipSuccess ? LJMD_OK : hip_fail(c, e, "clear cells");
 }
 
+// Device pointers of every array of a workspace laid out by lay_out.
+void bind_state(State &s, const Plan &pl, uint8_t *b, int prec) {
+    std::memset(&s, 0, sizeof s);
+    if (prec == LJMD_FP64) {
+        s.rec64[0] = (double4 *)(b + pl.off_rec[0]);
+        s.rec64[1] = (double4 *)(b + pl.off_rec[1]);
+        s.vel64 = (double4 *)(b + pl.off_vel);
+        s.frc64 = (double4 *)(b + pl.off_frc);
+    } else {
+        s.recq[0] = (int4 *)(b + pl.off_rec[0]);
+        s.recq[1] = (int4 *)(b + pl.off_rec[1]);
+        s.pos_hi = (float4 *)(b + pl.off_pos_hi);
+        s.pos_lo = (float4 *)(b + pl.off_pos_lo);
+        s.vel_hi = (float4 *)(b + pl.off_vel);
+        s.vel_lo = (float4 *)(b + pl.off_vel_lo);
+        s.frc32 = (float4 *)(b + pl.off_frc);
+    }
+    s.img = (int4 *)(b + pl.off_img);
+    s.id = (int32_t *)(b + pl.off_id);
+    s.xref = (int4 *)(b + pl.off_xref);
+    s.nbr = (int32_t *)(b + pl.off_nbr);
+    s.nbr_cnt = (int32_t *)(b + pl.off_cnt);
+    s.cell_count = (int32_t *)(b + pl.off_ccount);
+    s.cell_rec = (void *)(b + pl.off_cmem);
+    s.cell_start = (int32_t *)(b + pl.off_cstart);
+    s.rank_of = (int32_t *)(b + pl.off_rank);
+    s.cell_lin = (int32_t *)(b + pl.off_lin);
+    s.scratch = b + pl.off_scratch;
+    s.partials = (double *)(b + pl.off_part);
+    s.rebuilt = (int32_t *)(b + pl.off_rebuilt);
+    s.ctl = (Ctl *)(b + pl.off_ctl);
+}
+
+// ---- batches of systems ------------------------------------------------------
+
+// Host description of a batch: per-system geometry and the flattened layout.
+struct BatchGeom {
+    std::vector<SysC> sys;
+    std::vector<int32_t> sys_of_g16;
+    std::vector<std::vector<int32_t>> rank;  // per system, local Hilbert ranks
+    int64_t nslots = 0, ntot = 0, ncell = 0;
+    int32_t cap = 0, cell_cap = 0, lanes = 0;
+    int nblocks = 0;
+    std::string why;
+};
+
+// Parameters of system k: the shared ones with its own count and cubic edge.
+ljmd_params system_params(const ljmd_params *shared, const ljmd_system &y) {
+    ljmd_params q = *shared;
+    q.n = y.n;
+    q.box[0] = q.box[1] = q.box[2] = y.box;
+    return q;
+}
+
+int batch_geom(const ljmd_params *shared, const ljmd_system *ys, int32_t nsys, BatchGeom &bg, bool ranks) {
+    if (!shared || !ys || nsys < 1 || nsys > 65536) {
+        bg.why = "batch: NULL argument or nsys outside [1, 65536]";
+        return LJMD_EINVAL;
+    }
+    if (shared->nspecies != 1 || shared->precision != LJMD_FP32_DS) {
+        bg.why = "batch: one species and the FP32 + double-single path only";
+        return LJMD_EINVAL;
+    }
+    bg.sys.resize(nsys);
+    bg.lanes = shared->lanes != 0 ? shared->lanes : 2;
+    const int per_block = (kBlock / kWave) * (kWave / bg.lanes);
+    int64_t p_off = 0, in_off = 0, c_off = 0;
+    int b_off = 0;
+    int32_t cap = 0, cc = 0;
+    for (int k = 0; k < nsys; ++k) {
+        const ljmd_params q = system_params(shared, ys[k]);
+        std::string why;
+        const int r = validate(&q, &why);
+        if (r != LJMD_OK) {
+            bg.why = "batch system " + std::to_string(k) + ": " + why;
+            return r;
+        }
+        const Plan pk = make_plan(&q);
+        cap = std::max(cap, pk.cap);
+        cc = std::max(cc, pk.cell_cap);
+        SysC &y = bg.sys[k];
+        std::memset(&y, 0, sizeof y);
+        const int64_t npad = (q.n + kSysAlign - 1) / kSysAlign * kSysAlign;
+        y.p_off = p_off;
+        y.in_off = in_off;
+        y.n = (int32_t)q.n;
+        y.id = k;
+        y.c_off = (int32_t)c_off;
+        y.b_off = b_off;
+        y.nb = (int)(npad / per_block);
+        // Box constants exactly as a single box of these parameters has them.
+        BoxC &b = y.box;
+        for (int a = 0; a < 3; ++a) {
+            const double L = q.box[a];
+            b.L[a] = L;
+            b.invL[a] = 1.0 / L;
+            b.S[a] = kTwo32 / L;
+            b.Lhi[a] = (float)L;
+            b.Llo[a] = (float)(L - (double)b.Lhi[a]);
+            const double qs = L / kTwo32;
+            b.qs_hi[a] = (float)qs;
+            b.qs_lo[a] = (float)(qs - (double)b.qs_hi[a]);
+            const double ratio = qs / (double)b.qs_hi[a];
+            b.r2c[a] = (float)(ratio * ratio);
+            b.S_hi[a] = (float)b.S[a];
+            b.S_lo[a] = (float)(b.S[a] - (double)b.S_hi[a]);
+            b.nc[a] = pk.nc[a];
+        }
+        b.ncell = pk.ncell;
+        b.cubic = 1;
+        PairC pc;
+        fill_pairs(pc, q);
+        fill_quanta(b, pc, q.box[0]);
+        if (ranks) {
+            std::vector<int32_t> rk(pk.ncell);
+            ljmd_hilbert_ranks(pk.nc[0], pk.nc[1], pk.nc[2], rk.data());
+            bg.rank.push_back(std::move(rk));
+        }
+        p_off += npad;
+        in_off += q.n;
+        c_off += pk.ncell;
+        b_off += y.nb;
+    }
+    if (p_off > (int64_t)INT32_MAX - 1024) {
+        bg.why = "batch: more than 2^31 particle slots";
+        return LJMD_EINVAL;
+    }
+    bg.nslots = p_off;
+    bg.ntot = in_off;
+    bg.ncell = c_off;
+    bg.nblocks = b_off;
+    bg.cap = shared->nbr_capacity != 0 ? std::max<int32_t>(16, round_up(shared->nbr_capacity, 16)) : cap;
+    bg.cell_cap = shared->cell_capacity != 0 ? std::min<int32_t>(768, std::max<int32_t>(8, round_up(shared->cell_capacity, 8))) : cc;
+    bg.sys_of_g16.resize(bg.nslots / 16);
+    for (int k = 0; k < nsys; ++k) {
+        const SysC &y = bg.sys[k];
+        const int64_t npad = (int64_t)y.nb * per_block;
+        for (int64_t g = y.p_off / 16; g < (y.p_off + npad) / 16; ++g) bg.sys_of_g16[g] = k;
+    }
+    return LJMD_OK;
+}
+
+// Workspace of a batch: the single-box layout over every slot and cell, one
+// set of control words per system, then the system tables and the plan.
+struct BatchLayout {
+    Plan pl;
+    size_t off_sys = 0, off_g16 = 0, off_due = 0, off_wlsys = 0, off_wlpoff = 0, off_wlcoff = 0,
+           off_wlcnt = 0, total = 0;
+};
+
+BatchLayout batch_layout(const BatchGeom &bg, int nsys) {
+    BatchLayout bl;
+    Plan &pl = bl.pl;
+    pl = Plan{};
+    pl.npad = bg.nslots;
+    pl.ncell = (int)bg.ncell;
+    pl.cap = bg.cap;
+    pl.cell_cap = bg.cell_cap;
+    pl.lanes = bg.lanes;
+    pl.max_blocks = bg.nblocks;
+    lay_out(pl, LJMD_FP32_DS, nsys);
+    size_t off = pl.total;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += al(bytes);
+        return o;
+    };
+    bl.off_sys = take(sizeof(SysC) * (size_t)nsys);
+    bl.off_g16 = take(sizeof(int32_t) * bg.sys_of_g16.size());
+    bl.off_due = take(sizeof(int32_t) * (size_t)nsys);
+    bl.off_wlsys = take(sizeof(int32_t) * (size_t)nsys);
+    bl.off_wlpoff = take(sizeof(int64_t) * (size_t)(nsys + 1));
+    bl.off_wlcoff = take(sizeof(int64_t) * (size_t)(nsys + 1));
+    bl.off_wlcnt = take(sizeof(int32_t));
+    bl.total = off;
+    return bl;
+}
+
 }  // namespace
 
 extern "C" {
@@ -655,35 +846,7 @@ int ljmd_create(const ljmd_params *p, void *ws, size_t bytes, void *stream, ljmd
     c->nblocks = pl.max_blocks;
     uint8_t *b = (uint8_t *)ws;
     State &s = c->st;
-    std::memset(&s, 0, sizeof s);
-    if (p->precision == LJMD_FP64) {
-        s.rec64[0] = (double4 *)(b + pl.off_rec[0]);
-        s.rec64[1] = (double4 *)(b + pl.off_rec[1]);
-        s.vel64 = (double4 *)(b + pl.off_vel);
-        s.frc64 = (double4 *)(b + pl.off_frc);
-    } else {
-        s.recq[0] = (int4 *)(b + pl.off_rec[0]);
-        s.recq[1] = (int4 *)(b + pl.off_rec[1]);
-        s.pos_hi = (float4 *)(b + pl.off_pos_hi);
-        s.pos_lo = (float4 *)(b + pl.off_pos_lo);
-        s.vel_hi = (float4 *)(b + pl.off_vel);
-        s.vel_lo = (float4 *)(b + pl.off_vel_lo);
-        s.frc32 = (float4 *)(b + pl.off_frc);
-    }
-    s.img = (int4 *)(b + pl.off_img);
-    s.id = (int32_t *)(b + pl.off_id);
-    s.xref = (int4 *)(b + pl.off_xref);
-    s.nbr = (int32_t *)(b + pl.off_nbr);
-    s.nbr_cnt = (int32_t *)(b + pl.off_cnt);
-    s.cell_count = (int32_t *)(b + pl.off_ccount);
-    s.cell_rec = (void *)(b + pl.off_cmem);
-    s.cell_start = (int32_t *)(b + pl.off_cstart);
-    s.rank_of = (int32_t *)(b + pl.off_rank);
-    s.cell_lin = (int32_t *)(b + pl.off_lin);
-    s.scratch = b + pl.off_scratch;
-    s.partials = (double *)(b + pl.off_part);
-    s.rebuilt = (int32_t *)(b + pl.off_rebuilt);
-    s.ctl = (Ctl *)(b + pl.off_ctl);
+    bind_state(s, pl, b, p->precision);
 
     std::vector<int32_t> rank(pl.ncell), lin(pl.ncell);
     ljmd_hilbert_ranks(pl.nc[0], pl.nc[1], pl.nc[2], rank.data());
@@ -879,6 +1042,7 @@ int ljmd_set_pair_params(ljmd_ctx *c, const double eps[4], const double sigma[4]
     if (r != LJMD_OK) return fail(c, r, "set_pair_params: %s", why.c_str());
     c->p = q;
     fill_pairs(c->pc, c->p);
+    fill_quanta(c->box, c->pc, c->p.box[0]);
     ++c->gen;
     if (!c->have_state) return LJMD_OK;
     // Forces and observables of the current positions under the new values.
@@ -1052,3 +1216,287 @@ int ljmd_vv_backward(ljmd_ctx *c, const double *lam_x, const double *lam_v, doub
 }
 
 }  // extern "C"
+
+struct ljmd_batch {
+    ljmd_params p;  // shared parameters
+    int nsys = 0;
+    BatchGeom bg;
+    BatchLayout bl;
+    Geom g;
+    BoxC all;       // only ncell (every cell of the batch) is used
+    PairC pc;
+    DynC dyn;
+    State st;
+    SysC *sys = nullptr;
+    int32_t *g16 = nullptr;
+    BatchPlan bp;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int cur = 0;
+    int64_t step = 0;
+    bool have_state = false;
+    std::string err;
+};
+
+namespace {
+
+int bfail(ljmd_batch *b, int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+int bfail(ljmd_batch *b, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (b)
+        b->err = buf;
+    else
+        g_create_err = buf;
+    return code;
+}
+
+int bhip(ljmd_batch *b, hipError_t e, const char *what) {
+    return bfail(b, LJMD_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+Launch blauncher(ljmd_batch *b) {
+    Launch L;
+    L.st = &b->st;
+    L.g = &b->g;
+    L.box = &b->all;
+    L.pc = &b->pc;
+    L.dyn = &b->dyn;
+    L.stream = b->stream;
+    L.cur = b->cur;
+    return L;
+}
+
+// The list rebuild of one step for every system that needs it; a resort
+// (every sort_interval steps, and at a state load) forces all of them.
+int batch_rebuild(ljmd_batch *b, int64_t step, int forced, bool resort) {
+    Launch L = blauncher(b);
+    hipError_t e;
+    if ((e = launch_batch_plan(L, b->sys, b->nsys, b->bp, step, forced)) != hipSuccess) return bhip(b, e, "plan");
+    if ((e = launch_batch_bin(L, b->sys, b->bp, b->bg.ntot)) != hipSuccess) return bhip(b, e, "bin");
+    if ((e = launch_batch_canon(L, b->sys, b->bp, b->bg.ncell)) != hipSuccess) return bhip(b, e, "canon");
+    if (resort) {
+        if ((e = launch_batch_scan(L, b->sys, b->nsys)) != hipSuccess) return bhip(b, e, "scan");
+        if ((e = launch_batch_resort_move(L, b->bg.ncell)) != hipSuccess) return bhip(b, e, "resort");
+    }
+    if ((e = launch_batch_nlist(L, b->sys, b->bp, b->bg.ncell)) != hipSuccess) return bhip(b, e, "nlist");
+    return LJMD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ljmd_batch_workspace_size(const ljmd_params *shared, const ljmd_system *sys, int32_t nsys) {
+    BatchGeom bg;
+    if (batch_geom(shared, sys, nsys, bg, false) != LJMD_OK) return 0;
+    return batch_layout(bg, nsys).total;
+}
+
+int ljmd_batch_create(const ljmd_params *shared, const ljmd_system *sys, int32_t nsys, void *ws, size_t bytes,
+                      void *stream, ljmd_batch **out) {
+    if (!out) return bfail(nullptr, LJMD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ws) return bfail(nullptr, LJMD_EINVAL, "workspace is NULL");
+    if (((uintptr_t)ws & 255) != 0) return bfail(nullptr, LJMD_EINVAL, "workspace must be 256-byte aligned");
+    ljmd_batch *b = new (std::nothrow) ljmd_batch();
+    if (!b) return bfail(nullptr, LJMD_ENOMEM, "host allocation failed");
+    int r = batch_geom(shared, sys, nsys, b->bg, true);
+    if (r != LJMD_OK) {
+        bfail(nullptr, r, "%s", b->bg.why.c_str());
+        delete b;
+        return r;
+    }
+    b->bl = batch_layout(b->bg, nsys);
+    if (bytes < b->bl.total) {
+        delete b;
+        return bfail(nullptr, LJMD_ENOMEM, "workspace has %zu bytes, needs %zu", bytes, b->bl.total);
+    }
+    b->p = *shared;
+    b->nsys = nsys;
+    b->stream = (hipStream_t)stream;
+    if (hipGetDevice(&b->device) != hipSuccess) b->device = -1;
+    // Shared constants from the first system's parameters (the potential,
+    // masses, time step and skin are common).
+    const ljmd_params q0 = system_params(shared, sys[0]);
+    fill_pairs(b->pc, q0);
+    DynC &d = b->dyn;
+    for (int s = 0; s < 2; ++s) {
+        const double m = q0.mass[0];
+        d.mass[s] = m;
+        d.massf[s] = (float)m;
+        d.hdt_m[s] = 0.5 * q0.dt / m;
+        d.hdt_m_hi[s] = (float)d.hdt_m[s];
+        d.hdt_m_lo[s] = (float)(d.hdt_m[s] - (double)d.hdt_m_hi[s]);
+    }
+    d.dt = q0.dt;
+    d.dt_hi = (float)q0.dt;
+    d.dt_lo = (float)(q0.dt - (double)d.dt_hi);
+    d.thr2 = (float)(0.25 * q0.skin * q0.skin);
+    std::memset(&b->all, 0, sizeof b->all);
+    b->all.ncell = (int32_t)b->bg.ncell;
+    Geom &g = b->g;
+    g.n = b->bg.nslots;
+    g.cap = b->bg.cap;
+    g.cell_cap = b->bg.cell_cap;
+    g.lanes = b->bg.lanes;
+    g.nspecies = 1;
+    g.prec = LJMD_FP32_DS;
+    g.max_blocks = b->bg.nblocks;
+    g.ncu = 256;
+    if (b->device >= 0) {
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b->device) == hipSuccess && ncu > 0)
+            g.ncu = ncu;
+    }
+    uint8_t *base = (uint8_t *)ws;
+    const Plan &pl = b->bl.pl;
+    bind_state(b->st, pl, base, LJMD_FP32_DS);
+    b->sys = (SysC *)(base + b->bl.off_sys);
+    b->g16 = (int32_t *)(base + b->bl.off_g16);
+    b->bp.due = (int32_t *)(base + b->bl.off_due);
+    b->bp.wl_sys = (int32_t *)(base + b->bl.off_wlsys);
+    b->bp.wl_poff = (int64_t *)(base + b->bl.off_wlpoff);
+    b->bp.wl_coff = (int64_t *)(base + b->bl.off_wlcoff);
+    b->bp.wl_count = (int32_t *)(base + b->bl.off_wlcnt);
+    // Tables: concatenated Hilbert ranks and their inverses, systems, slot groups.
+    std::vector<int32_t> rank(b->bg.ncell), lin(b->bg.ncell);
+    for (int k = 0; k < nsys; ++k) {
+        const SysC &y = b->bg.sys[k];
+        const std::vector<int32_t> &rk = b->bg.rank[k];
+        for (int c = 0; c < y.box.ncell; ++c) {
+            rank[y.c_off + c] = rk[c];
+            lin[y.c_off + rk[c]] = c;
+        }
+    }
+    hipError_t e = hipMemcpyAsync(b->st.rank_of, rank.data(), sizeof(int32_t) * rank.size(), hipMemcpyHostToDevice,
+                                  b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->st.cell_lin, lin.data(), sizeof(int32_t) * lin.size(), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->sys, b->bg.sys.data(), sizeof(SysC) * nsys, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->g16, b->bg.sys_of_g16.data(), sizeof(int32_t) * b->bg.sys_of_g16.size(),
+                           hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(b->st.cell_count, 0, sizeof(int32_t) * b->bg.ncell, b->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(b->st.ctl, 0, sizeof(Ctl) * nsys, b->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(b->st.nbr_cnt, 0, sizeof(int32_t) * pl.npad, b->stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(b->st.nbr, 0, sizeof(int32_t) * ((size_t)pl.npad * pl.cap + kListPad), b->stream);
+    // The tables come from pageable host memory: finish before they go away.
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        int rc = bfail(nullptr, LJMD_EHIP, "batch workspace initialisation: %s", hipGetErrorString(e));
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return LJMD_OK;
+}
+
+int ljmd_batch_destroy(ljmd_batch *b) {
+    delete b;
+    return LJMD_OK;
+}
+
+int ljmd_batch_set_state(ljmd_batch *b, const double *x, const double *v, const int32_t *species) {
+    if (!b) return LJMD_EINVAL;
+    if (!x || !v || !species) return bfail(b, LJMD_EINVAL, "batch_set_state: NULL array");
+    b->cur = 0;
+    b->step = 0;
+    hipError_t e = hipMemsetAsync(b->st.ctl, 0, sizeof(Ctl) * b->nsys, b->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(b->st.cell_count, 0, sizeof(int32_t) * b->bg.ncell, b->stream);
+    if (e != hipSuccess) return bhip(b, e, "batch_set_state memset");
+    Launch L = blauncher(b);
+    if ((e = launch_batch_set_state(L, b->sys, b->g16, b->bg.nslots, x, v, species)) != hipSuccess)
+        return bhip(b, e, "batch_set_state");
+    int r = batch_rebuild(b, 0, 1, true);
+    if (r) return r;
+    L = blauncher(b);
+    if ((e = launch_batch_step(L, b->sys, b->g16, b->bg.nblocks, 0, 1, kStoreForce, 0)) != hipSuccess)
+        return bhip(b, e, "batch force");
+    if ((e = launch_batch_obs(L, b->sys, b->nsys, 0, 0, nullptr)) != hipSuccess) return bhip(b, e, "batch obs");
+    b->have_state = true;
+    return LJMD_OK;
+}
+
+int ljmd_batch_run(ljmd_batch *b, int64_t nsteps, double *obs_dev) {
+    if (!b) return LJMD_EINVAL;
+    if (!b->have_state) return bfail(b, LJMD_ESTATE, "batch_run before batch_set_state");
+    if (nsteps < 0) return bfail(b, LJMD_EINVAL, "nsteps < 0");
+    if (nsteps == 0) return LJMD_OK;
+    hipError_t e;
+    Launch L = blauncher(b);
+    if ((e = launch_batch_integrate(L, b->sys, b->g16, b->bg.nslots, b->step)) != hipSuccess)
+        return bhip(b, e, "batch integrate");
+    b->cur ^= 1;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        const int64_t s = b->step + 1 + k;
+        const bool resort = b->p.sort_interval > 0 && s % b->p.sort_interval == 0;
+        const int forced = resort ? 1 : 0;
+        int r = batch_rebuild(b, s, forced, resort);
+        if (r) return r;
+        const bool last = k == nsteps - 1;
+        L = blauncher(b);
+        if ((e = launch_batch_step(L, b->sys, b->g16, b->bg.nblocks, s, forced,
+                                   kFinalize | (last ? kStoreForce : kIntegrate), (int)(s % kRing))) != hipSuccess)
+            return bhip(b, e, "batch step");
+        if (!last) b->cur ^= 1;
+    }
+    b->step += nsteps;
+    if ((e = launch_batch_obs(L, b->sys, b->nsys, (int)(b->step % kRing), b->step, obs_dev)) != hipSuccess)
+        return bhip(b, e, "batch obs");
+    return LJMD_OK;
+}
+
+int ljmd_batch_get_state(ljmd_batch *b, double *x, double *v, int32_t *img) {
+    if (!b) return LJMD_EINVAL;
+    if (!b->have_state) return bfail(b, LJMD_ESTATE, "batch_get_state before batch_set_state");
+    hipError_t e = launch_batch_get_state(blauncher(b), b->sys, b->g16, b->bg.nslots, x, v, img);
+    return e == hipSuccess ? LJMD_OK : bhip(b, e, "batch_get_state");
+}
+
+int ljmd_batch_get_forces(ljmd_batch *b, double *f) {
+    if (!b) return LJMD_EINVAL;
+    if (!b->have_state) return bfail(b, LJMD_ESTATE, "batch_get_forces before batch_set_state");
+    if (!f) return bfail(b, LJMD_EINVAL, "batch_get_forces: NULL array");
+    hipError_t e = launch_batch_get_forces(blauncher(b), b->sys, b->g16, b->bg.nslots, f);
+    return e == hipSuccess ? LJMD_OK : bhip(b, e, "batch_get_forces");
+}
+
+int ljmd_batch_observables(ljmd_batch *b, double *obs_host) {
+    if (!b || !obs_host) return LJMD_EINVAL;
+    if (!b->have_state) return bfail(b, LJMD_ESTATE, "batch_observables before batch_set_state");
+    int r = ljmd_batch_sync_status(b);
+    std::vector<Ctl> h(b->nsys);
+    hipError_t e = hipMemcpy(h.data(), b->st.ctl, sizeof(Ctl) * b->nsys, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return bhip(b, e, "read observables");
+    for (int k = 0; k < b->nsys; ++k)
+        for (int q = 0; q < LJMD_NOBS; ++q) obs_host[(size_t)k * LJMD_NOBS + q] = h[k].last[q];
+    return r;
+}
+
+int ljmd_batch_sync_status(ljmd_batch *b) {
+    if (!b) return LJMD_EINVAL;
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bhip(b, e, "synchronise");
+    std::vector<Ctl> h(b->nsys);
+    e = hipMemcpy(h.data(), b->st.ctl, sizeof(Ctl) * b->nsys, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return bhip(b, e, "read flags");
+    for (int k = 0; k < b->nsys; ++k) {
+        const uint32_t flags = h[k].flags;
+        if (flags & kErrNaN) return bfail(b, LJMD_ENAN, "system %d: non-finite position detected", k);
+        if (flags & kErrCell) return bfail(b, LJMD_ECELL, "system %d: a cell exceeded cell_capacity=%d", k, b->g.cell_cap);
+        if (flags & kErrList)
+            return bfail(b, LJMD_ENLIST, "system %d: a neighbour list exceeded nbr_capacity=%d", k, b->g.cap);
+    }
+    return LJMD_OK;
+}
+
+const char *ljmd_batch_last_error(const ljmd_batch *b) { return b ? b->err.c_str() : g_create_err.c_str(); }
+
+}  // extern "C"
+

@@ -18,7 +18,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libljmd.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 FP64 = 0
 FP32_DS = 1
 ADJ_STORE_ALL = 1
@@ -51,6 +51,10 @@ class Obs(C.Structure):
                 ("nbr_capacity", C.c_int32)]
 
 
+class SystemDesc(C.Structure):
+    _fields_ = [("n", C.c_int64), ("box", C.c_double)]
+
+
 # Every exported function: name -> (restype, argtypes).
 _vp, _dp, _ip = C.c_void_p, C.c_void_p, C.c_void_p
 SIGNATURES = {
@@ -78,6 +82,17 @@ SIGNATURES = {
     "ljmd_adjoint_workspace_size": (C.c_size_t, [C.POINTER(Params), C.c_int32, C.c_int32, C.c_int32]),
     "ljmd_vv_forward": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _vp, C.c_size_t, _dp]),
     "ljmd_vv_backward": (C.c_int, [_vp, _dp, _dp, _dp, _dp, _dp]),
+    "ljmd_batch_workspace_size": (C.c_size_t, [C.POINTER(Params), C.POINTER(SystemDesc), C.c_int32]),
+    "ljmd_batch_create": (C.c_int, [C.POINTER(Params), C.POINTER(SystemDesc), C.c_int32, _vp, C.c_size_t, _vp,
+                                    C.POINTER(_vp)]),
+    "ljmd_batch_destroy": (C.c_int, [_vp]),
+    "ljmd_batch_set_state": (C.c_int, [_vp, _dp, _dp, _ip]),
+    "ljmd_batch_run": (C.c_int, [_vp, C.c_int64, _dp]),
+    "ljmd_batch_get_state": (C.c_int, [_vp, _dp, _dp, _ip]),
+    "ljmd_batch_get_forces": (C.c_int, [_vp, _dp]),
+    "ljmd_batch_observables": (C.c_int, [_vp, C.POINTER(C.c_double)]),
+    "ljmd_batch_sync_status": (C.c_int, [_vp]),
+    "ljmd_batch_last_error": (C.c_char_p, [_vp]),
 }
 NKT = 5
 KERNEL_FAMILIES = ("step", "rebuild", "resort", "other", "adjoint")
@@ -374,6 +389,105 @@ class System:
                self.ctx)
         self._keep_l = (lx, lv)
         return gx0, gv0, gth
+
+
+class Batch:
+    """Independent one-species systems in cubic boxes, stepped together.
+
+    ``sizes`` and ``edges`` give each system's particle count and box edge;
+    ``p`` (an LJParams-like object) the shared potential and integration
+    settings. State arrays are the systems' rows concatenated in order.
+    """
+
+    def __init__(self, sizes, edges, p, sort_interval: int = 100, nbr_capacity: int = 0,
+                 cell_capacity: int = 0, lanes: int = 0, device=None):
+        import torch
+        self.torch = torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("ljmd.Batch needs a HIP GPU; none is visible")
+        self.device = torch.device(device if device is not None else "cuda")
+        self.sizes = np.asarray(sizes, dtype=np.int64)
+        self.edges = np.asarray(edges, dtype=np.float64)
+        if self.sizes.shape != self.edges.shape or self.sizes.ndim != 1:
+            raise ValueError("sizes and edges must be equal-length 1-D sequences")
+        self.nsys = len(self.sizes)
+        self.ntot = int(self.sizes.sum())
+        self.offsets = np.concatenate([[0], np.cumsum(self.sizes)])
+        self.params = make_params(int(self.sizes[0]), [self.edges[0]] * 3, p, FP32_DS, sort_interval,
+                                  nbr_capacity, cell_capacity, lanes)
+        self.desc = (SystemDesc * self.nsys)(*[SystemDesc(int(n), float(L))
+                                               for n, L in zip(self.sizes, self.edges)])
+        size = int(lib.ljmd_batch_workspace_size(C.byref(self.params), self.desc, self.nsys))
+        if size == 0:
+            raise LJMDError(-1, "invalid batch (see ljmd_check_params for each system)")
+        self.workspace = torch.empty(size, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        b = C.c_void_p()
+        code = lib.ljmd_batch_create(C.byref(self.params), self.desc, self.nsys,
+                                     C.c_void_p(_ptr(self.workspace)), size,
+                                     C.c_void_p(self.stream.cuda_stream), C.byref(b))
+        if code != 0:
+            raise LJMDError(code, lib.ljmd_batch_last_error(None).decode())
+        self.b = b
+
+    def _err(self, code):
+        if code != 0:
+            raise LJMDError(code, lib.ljmd_batch_last_error(self.b).decode())
+
+    def close(self):
+        if getattr(self, "b", None):
+            lib.ljmd_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self, a, dtype):
+        t = self.torch
+        if isinstance(a, np.ndarray):
+            a = t.from_numpy(np.ascontiguousarray(a))
+        return a.to(device=self.device, dtype=dtype).contiguous()
+
+    def set_state(self, x, v, species):
+        t = self.torch
+        x = self._dev(x, t.float64).reshape(self.ntot, 3)
+        v = self._dev(v, t.float64).reshape(self.ntot, 3)
+        s = self._dev(species, t.int32).reshape(self.ntot)
+        self._err(lib.ljmd_batch_set_state(self.b, _ptr(x), _ptr(v), _ptr(s)))
+        self._keep = (x, v, s)
+
+    def run(self, nsteps: int, observe: bool = False):
+        """Advance every system; returns the (nsys, 8) device tensor of each
+        system's last-step observables when observe is set."""
+        t = self.torch
+        obs = t.empty((self.nsys, NOBS), dtype=t.float64, device=self.device) if observe else None
+        self._err(lib.ljmd_batch_run(self.b, int(nsteps), _ptr(obs) if obs is not None else None))
+        return obs
+
+    def get_state(self):
+        t = self.torch
+        x = t.empty((self.ntot, 3), dtype=t.float64, device=self.device)
+        v = t.empty_like(x)
+        img = t.empty((self.ntot, 3), dtype=t.int32, device=self.device)
+        self._err(lib.ljmd_batch_get_state(self.b, _ptr(x), _ptr(v), _ptr(img)))
+        return x, v, img
+
+    def forces(self):
+        t = self.torch
+        f = t.empty((self.ntot, 3), dtype=t.float64, device=self.device)
+        self._err(lib.ljmd_batch_get_forces(self.b, _ptr(f)))
+        return f
+
+    def observables(self) -> np.ndarray:
+        out = np.zeros((self.nsys, NOBS), dtype=np.float64)
+        self._err(lib.ljmd_batch_observables(self.b, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
+
+    def sync(self):
+        self._err(lib.ljmd_batch_sync_status(self.b))
 
 
 # ---- torch.autograd front ends ----------------------------------------------
