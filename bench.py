@@ -176,6 +176,39 @@ def time_adjoint(ljmd, torch, W, nsteps: int = 50, every: int = 10, reps: int = 
     }
 
 
+def time_batch(ljmd, torch, W, steps: int = 500, warmup: int = 50):
+    """Batched replicas: 512 independent one-species LJ systems, N
+    log-uniform in [500, 32000] (sum about 3.9 million), rho in [0.7, 1.2],
+    T in [0.7, 1.5], FP32 pair math with double-single state, stepped
+    together (every kernel spans all systems). Batched particle-steps/s =
+    sum(N) * steps / wall time of the timed ljmd_batch_run."""
+    import numpy as np
+    ws = W.replica_draws(512)
+    b = ljmd.Batch([w.n for w in ws], [w.box[0] for w in ws], ws[0].params, sort_interval=100)
+    b.set_state(np.concatenate([w.x for w in ws]), np.concatenate([w.v for w in ws]),
+                np.concatenate([w.species for w in ws]))
+    b.run(warmup)
+    b.sync()
+    stream = torch.cuda.current_stream()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    b.run(steps)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    b.sync()
+    ms = start.elapsed_time(stop)
+    obs = b.observables()
+    ntot = sum(w.n for w in ws)
+    return {
+        "workload": f"512 replicas, sum N = {ntot}, N in [{min(w.n for w in ws)}, {max(w.n for w in ws)}], "
+                    "rho U(0.7,1.2), T U(0.7,1.5), FP32 pair math + DS state",
+        "value": ntot * steps / (ms * 1e-3), "unit": "particle-steps/s", "steps": steps,
+        "ms_per_step": ms / steps,
+        "rebuilds_per_system_mean": float(obs[:, 6].mean()),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,6 +218,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiable-workload timing")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-replica timing")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device (a reference kernel of known "
@@ -245,6 +279,10 @@ def main():
     if not args.no_adjoint:
         extra["adjoint"] = time_adjoint(ljmd, torch, W)
         print(f"bench: adjoint/forward {extra['adjoint']['ratio']:.3f}", file=sys.stderr, flush=True)
+
+    if not args.no_batch:
+        extra["batched"] = time_batch(ljmd, torch, W)
+        print(f"bench: batched {extra['batched']['value']:.3e} particle-steps/s", file=sys.stderr, flush=True)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(w, args.cpu_seconds)
 

@@ -268,6 +268,37 @@ int ljmd_vv_forward(ljmd_ctx *ctx, int32_t nsteps, int32_t ckpt_every, int32_t f
 int ljmd_vv_backward(ljmd_ctx *ctx, const double *lam_x, const double *lam_v, double *gx0,
                      double *gv0, double *gtheta);
 
+/* ---- Autotuning -------------------------------------------------------------
+ * The paper picks launch configurations per device (Sec. 4, 5); this
+ * library's tuner times short runs of a system on the device for each
+ * candidate force-gather shape (lanes per particle 1, 2, 4, 8, 16) and sizes
+ * the list capacity from the longest list seen (1.25x, at least +24, in
+ * units of 16). Results are cached as JSON lines in cache_path (may be NULL)
+ * under a key of device architecture, precision, species count, size (power
+ * of two), density (to 0.05) and list radius; a cached key is returned
+ * without timing. */
+typedef struct ljmd_tuning {
+    int32_t lanes;          /* fastest lanes per particle */
+    int32_t nbr_capacity;   /* suggested list capacity */
+    int32_t cell_capacity;  /* cell capacity used (0 = automatic) */
+    int32_t max_fill;       /* longest list seen while timing */
+    double ms_per_step;     /* time per step of the fastest shape */
+    int32_t from_cache;     /* 1 if read from the cache */
+    int32_t reserved;
+} ljmd_tuning;
+
+/* Device bytes the tuner needs for p (the largest workspace of its
+ * candidates; 0 if p is invalid). */
+size_t ljmd_autotune_workspace_size(const ljmd_params *p);
+
+/* Tune for the state x, v, species (device, as ljmd_set_state) with steps
+ * timed steps per candidate (after 10 warm-up steps), using dev_workspace
+ * (>= ljmd_autotune_workspace_size bytes) for temporary contexts. Writes the
+ * result to *out (host). Synchronises. */
+int ljmd_autotune(const ljmd_params *p, const double *x, const double *v, const int32_t *species,
+                  void *dev_workspace, size_t bytes, void *hip_stream, int32_t steps,
+                  const char *cache_path, ljmd_tuning *out);
+
 /* ---- Batches of systems ------------------------------------------------------
  * Many independent one-species systems (replicas) of uneven size in cubic
  * boxes, stepped together: every kernel of a step spans all of them at once

@@ -55,6 +55,12 @@ class SystemDesc(C.Structure):
     _fields_ = [("n", C.c_int64), ("box", C.c_double)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("lanes", C.c_int32), ("nbr_capacity", C.c_int32), ("cell_capacity", C.c_int32),
+                ("max_fill", C.c_int32), ("ms_per_step", C.c_double), ("from_cache", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
 # Every exported function: name -> (restype, argtypes).
 _vp, _dp, _ip = C.c_void_p, C.c_void_p, C.c_void_p
 SIGNATURES = {
@@ -93,6 +99,9 @@ SIGNATURES = {
     "ljmd_batch_observables": (C.c_int, [_vp, C.POINTER(C.c_double)]),
     "ljmd_batch_sync_status": (C.c_int, [_vp]),
     "ljmd_batch_last_error": (C.c_char_p, [_vp]),
+    "ljmd_autotune_workspace_size": (C.c_size_t, [C.POINTER(Params)]),
+    "ljmd_autotune": (C.c_int, [C.POINTER(Params), _dp, _dp, _ip, _vp, C.c_size_t, _vp, C.c_int32, C.c_char_p,
+                                C.POINTER(Tuning)]),
 }
 NKT = 5
 KERNEL_FAMILIES = ("step", "rebuild", "resort", "other", "adjoint")
@@ -389,6 +398,30 @@ class System:
                self.ctx)
         self._keep_l = (lx, lv)
         return gx0, gv0, gth
+
+
+def autotune(n: int, box, p, x, v, species, precision: int = FP32_DS, steps: int = 20,
+             cache_path: str | None = None, sort_interval: int = 100) -> dict:
+    """Time every force-gather shape on this state and return the fastest
+    (lanes) with a list capacity sized from the longest list seen; a cached
+    result (same device, precision, species count, size and density) is
+    returned without timing."""
+    import torch
+    params = make_params(n, box, p, precision, sort_interval)
+    _check(check_params(params))
+    size = int(lib.ljmd_autotune_workspace_size(C.byref(params)))
+    ws = torch.empty(size, dtype=torch.uint8, device="cuda")
+    dev = lambda a, dt: (torch.from_numpy(np.ascontiguousarray(a)) if isinstance(a, np.ndarray) else a).to(
+        device="cuda", dtype=dt).contiguous()
+    xs, vs, sp = dev(x, torch.float64), dev(v, torch.float64), dev(species, torch.int32)
+    out = Tuning()
+    stream = torch.cuda.current_stream()
+    code = lib.ljmd_autotune(C.byref(params), _ptr(xs), _ptr(vs), _ptr(sp), C.c_void_p(_ptr(ws)), size,
+                             C.c_void_p(stream.cuda_stream), int(steps),
+                             cache_path.encode() if cache_path else None, C.byref(out))
+    _check(code)
+    return {"lanes": out.lanes, "nbr_capacity": out.nbr_capacity, "cell_capacity": out.cell_capacity,
+            "max_fill": out.max_fill, "ms_per_step": out.ms_per_step, "from_cache": bool(out.from_cache)}
 
 
 class Batch:

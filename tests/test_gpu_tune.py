@@ -1,0 +1,47 @@
+"""The autotuner through the C ABI: it times every force-gather shape on the
+device, returns the fastest with a list capacity above the longest list seen,
+caches the result and reads it back; a system built with the tuned shape and
+capacity gives the forces of the oracle."""
+import pytest
+
+import oracle
+from paper_2406_04210_amd import workloads as W
+from test_gpu_parity import rel_force_err, tie_allowance
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ljmd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_04210_amd import ljmd as L
+    return L
+
+
+def test_autotune_times_caches_and_runs(ljmd, tmp_path):
+    w = W.config_small()
+    cache = str(tmp_path / "tune.jsonl")
+    t = ljmd.autotune(w.n, w.box, w.params, w.x, w.v, w.species, steps=10, cache_path=cache)
+    print("tuned", t, flush=True)
+    assert t["lanes"] in (1, 2, 4, 8, 16)
+    assert t["ms_per_step"] > 0.0 and not t["from_cache"]
+    assert t["max_fill"] > 0 and t["nbr_capacity"] >= t["max_fill"] + 16 and t["nbr_capacity"] % 16 == 0
+    again = ljmd.autotune(w.n, w.box, w.params, w.x, w.v, w.species, steps=10, cache_path=cache)
+    assert again["from_cache"]
+    assert {k: again[k] for k in ("lanes", "nbr_capacity", "max_fill")} == \
+           {k: t[k] for k in ("lanes", "nbr_capacity", "max_fill")}
+    with open(cache) as fh:
+        assert len(fh.readlines()) == 1
+    s = ljmd.System(w.n, w.box, w.params, lanes=t["lanes"], nbr_capacity=t["nbr_capacity"])
+    s.set_state(w.x, w.v, w.species)
+    s.run(50, observe=False)
+    s.sync()
+    x, v, _ = s.get_state()
+    f = s.forces().cpu().numpy()
+    xh = x.cpu().numpy()
+    ref, _, _ = oracle.forces_brute(xh, w.species, w.box, w.params)
+    # Forces of the state the GPU reached, to the FP32 tolerance of
+    # test_gpu_parity.py (with its allowance at cutoff ties).
+    assert rel_force_err(f, ref, tie_allowance(xh, w.species, w.box, w.params, 1)) <= 2e-5
