@@ -22,9 +22,10 @@ constexpr int kNP = 8;           // doubles per partial row: U, W, K, px, py, pz
 
 // Latched device error bits (ctl->flags).
 enum : uint32_t { kErrList = 1u, kErrCell = 2u, kErrNaN = 4u };
-// List slots allocated past the last row: the FP32 force loop reads up to
-// three unrolled entries beyond a list without clamping.
-constexpr size_t kListPad = 4 * 64;
+// List slots allocated past the last row: the force loop of one species in a
+// cubic box prefetches index rows (of 64 entries) up to eleven rows past a
+// list without clamping.
+constexpr size_t kListPad = 16 * 64;
 
 // Box constants. The fixed-point image coordinate q = round(x * 2^32 / L)
 // mod 2^32 turns the minimum image into a wrapping 32-bit subtraction.
@@ -276,7 +277,13 @@ hipError_t launch_canon(const Launch &L, int64_t step, int forced);
 hipError_t launch_resort(const Launch &L);
 hipError_t launch_nlist(const Launch &L, int64_t step, int forced);
 // mode bits for launch_step
-enum : int { kFinalize = 1, kIntegrate = 2, kStoreForce = 4 };
+// kObserve: the step's observable partials (energy, virial, kinetic energy,
+// momentum) will be reduced; without it the one-species cubic kernels skip
+// them (positions, velocities and forces are the same either way).
+enum : int { kFinalize = 1, kIntegrate = 2, kStoreForce = 4, kObserve = 8 };
+// Particle slots below which the quanta force loop addresses records by a
+// 32-bit byte offset.
+constexpr int64_t kQuantaMaxSlots = (int64_t)1 << 28;
 hipError_t launch_step(const Launch &L, int64_t step, int forced, int mode, int slot);
 hipError_t launch_integrate(const Launch &L, int64_t step);
 hipError_t launch_obs_reduce(const Launch &L, int64_t first_step, int count, int nblocks,

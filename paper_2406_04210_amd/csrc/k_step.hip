@@ -22,6 +22,8 @@ namespace ljmd {
 
 // Block-level deterministic reduction of the six observable partials and the
 // displacement maximum; one row of partials per block.
+// Without OBS only the displacement maximum is reduced.
+template <bool OBS = true>
 __device__ inline void block_finish(const StepArgs &a, Ctl *ctl, int blk, double u, double w, double k,
                                     double px, double py, double pz, uint32_t dmax) {
     constexpr int WPB = kBlock / kWave;
@@ -29,16 +31,20 @@ __device__ inline void block_finish(const StepArgs &a, Ctl *ctl, int blk, double
     __shared__ uint32_t redm[WPB];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     double v6[6] = {u, w, k, px, py, pz};
+    if constexpr (OBS) {
 #pragma unroll
-    for (int q = 0; q < 6; ++q) v6[q] = wave_sum(v6[q]);
+        for (int q = 0; q < 6; ++q) v6[q] = wave_sum(v6[q]);
+    }
     dmax = wave_max_u(dmax);
     if (lane == 0) {
+        if constexpr (OBS) {
 #pragma unroll
-        for (int q = 0; q < 6; ++q) red[wv][q] = v6[q];
+            for (int q = 0; q < 6; ++q) red[wv][q] = v6[q];
+        }
         redm[wv] = dmax;
     }
     __syncthreads();
-    if (threadIdx.x < kNP) {
+    if (OBS && threadIdx.x < kNP) {
         double s = 0.0;
         if (threadIdx.x < 6)
             for (int q = 0; q < WPB; ++q) s += red[q][threadIdx.x];
@@ -78,11 +84,15 @@ __device__ inline void step_housekeeping(const StepArgs &a, const Ctl *ctl, int6
 // so the entries the unrolled loop reads past a list are loaded unclamped
 // and skipped.
 //
+// OBS: accumulate the pair energy and virial terms and reduce the
+// observable partials; steps whose observables nobody reads skip them.
+// Records are addressed by 32-bit byte offsets (fewer than 2^28 slots).
+//
 // The body serves one block of one system: box holds its constants, ctl its
 // control words, particles below i_end are real (the rest of the block is
 // padding), and the block is number bj of the nbj blocks that share the
 // clearing of its cells [c_lo, c_hi).
-template <int NS, int LANES, bool Q>
+template <int NS, int LANES, bool Q, bool OBS>
 __device__ inline void step_ds_body(const StepArgs &a, const BoxC &box, Ctl *ctl, int blk, int64_t i_end,
                                     int64_t c_lo, int64_t c_hi, int bj, int nbj, int32_t *rebuilt) {
     constexpr int P = kWave / LANES;
@@ -123,16 +133,20 @@ __device__ inline void step_ds_body(const StepArgs &a, const BoxC &box, Ctl *ctl
     if constexpr (Q) {
         static_assert(NS == 1, "quanta path is single-species");
         const float rc2q = box.rc2q, sig2q = box.sig2q;
+        const char *__restrict__ recb = reinterpret_cast<const char *>(rec);
         float sa = 0.f, sb = 0.f;  // per lane: sum s6^2 and sum s6 over a few dozen pairs
-        for (int m = 0; m < iters; m += U) {
-            int jj[U];
+        // Eight entries per trip keep more of the list stream in flight.
+        constexpr int UQ = 8;
+        static_assert((size_t)UQ * kWave <= kListPad, "list padding below the unroll depth");
+        for (int m = 0; m < iters; m += UQ) {
+            int jj[UQ];
 #pragma unroll
-            for (int u = 0; u < U; ++u) jj[u] = nb[(int64_t)(m + u) * kWave];
-            int4 rr[U];
+            for (int u = 0; u < UQ; ++u) jj[u] = nb[(int64_t)(m + u) * kWave];
+            int4 rr[UQ];
 #pragma unroll
-            for (int u = 0; u < U; ++u) rr[u] = rec[jj[u]];
+            for (int u = 0; u < UQ; ++u) rr[u] = *reinterpret_cast<const int4 *>(recb + ((uint32_t)jj[u] << 4));
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
+            for (int u = 0; u < UQ; ++u) {
                 const float dx = (float)(int32_t)((uint32_t)ri.x - (uint32_t)rr[u].x);
                 const float dy = (float)(int32_t)((uint32_t)ri.y - (uint32_t)rr[u].y);
                 const float dz = (float)(int32_t)((uint32_t)ri.z - (uint32_t)rr[u].z);
@@ -145,9 +159,11 @@ __device__ inline void step_ds_body(const StepArgs &a, const BoxC &box, Ctl *ctl
                     fx = fmaf(t, dx, fx);
                     fy = fmaf(t, dy, fy);
                     fz = fmaf(t, dz, fz);
-                    sa = fmaf(s6, s6, sa);
-                    sb += s6;
-                    an += 1;
+                    if constexpr (OBS) {
+                        sa = fmaf(s6, s6, sa);
+                        sb += s6;
+                        an += 1;
+                    }
                 }
             }
         }
@@ -212,9 +228,11 @@ __device__ inline void step_ds_body(const StepArgs &a, const BoxC &box, Ctl *ctl
             fy += __shfl_xor(fy, o);
             fz += __shfl_xor(fz, o);
             if constexpr (NS == 1) {
-                a12 += __shfl_xor(a12, o);
-                a6 += __shfl_xor(a6, o);
-                an += __shfl_xor(an, o);
+                if constexpr (OBS) {
+                    a12 += __shfl_xor(a12, o);
+                    a6 += __shfl_xor(a6, o);
+                    an += __shfl_xor(an, o);
+                }
             } else {
                 e += __shfl_xor(e, o);
                 w += __shfl_xor(w, o);
@@ -243,12 +261,14 @@ __device__ inline void step_ds_body(const StepArgs &a, const BoxC &box, Ctl *ctl
             vz = ds_add(vz, ds_mul_f(chi, clo, fz));
         }
         const float ux = vx.hi + vx.lo, uy = vy.hi + vy.lo, uz = vz.hi + vz.lo;
-        pk = 0.5 * (double)(mass * fmaf(uz, uz, fmaf(uy, uy, ux * ux)));
-        ppx = (double)(mass * ux);
-        ppy = (double)(mass * uy);
-        ppz = (double)(mass * uz);
-        pu = 0.5 * e;
-        pw = 0.5 * w;
+        if constexpr (OBS) {
+            pk = 0.5 * (double)(mass * fmaf(uz, uz, fmaf(uy, uy, ux * ux)));
+            ppx = (double)(mass * ux);
+            ppy = (double)(mass * uy);
+            ppz = (double)(mass * uz);
+            pu = 0.5 * e;
+            pw = 0.5 * w;
+        }
         if (a.mode & kIntegrate) {
             vx = ds_add(vx, ds_mul_f(chi, clo, fx));
             vy = ds_add(vy, ds_mul_f(chi, clo, fy));
@@ -283,24 +303,25 @@ __device__ inline void step_ds_body(const StepArgs &a, const BoxC &box, Ctl *ctl
         st.vel_lo[i] = make_float4(vx.lo, vy.lo, vz.lo, 0.f);
         if (a.mode & kStoreForce) st.frc32[i] = make_float4(fx, fy, fz, 0.f);
     }
-    block_finish(a, ctl, blk, pu, pw, pk, ppx, ppy, ppz, dm);
+    block_finish<OBS>(a, ctl, blk, pu, pw, pk, ppx, ppy, ppz, dm);
 }
 
-template <int NS, int LANES, bool Q>
+template <int NS, int LANES, bool Q, bool OBS>
 __global__ __launch_bounds__(kBlock) void k_step_ds(StepArgs a) {
-    step_ds_body<NS, LANES, Q>(a, a.box, a.st.ctl, xcd_remap(blockIdx.x, gridDim.x), a.g.n, 0, a.box.ncell,
+    static_assert(OBS || Q, "observables are skipped on the quanta path only");
+    step_ds_body<NS, LANES, Q, OBS>(a, a.box, a.st.ctl, xcd_remap(blockIdx.x, gridDim.x), a.g.n, 0, a.box.ncell,
                                blockIdx.x, gridDim.x, a.st.rebuilt + a.slot);
 }
 
 // A batch of independent one-species cubic systems, each over its own run of
 // blocks (particle ranges padded to whole blocks): the block finds its
 // system, then runs the same body with that system's box and control words.
-template <int LANES>
+template <int LANES, bool OBS>
 __global__ __launch_bounds__(kBlock) void k_batch_step(StepArgs a, const SysC *sys, const int32_t *sys_of_g16) {
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t first = (int64_t)blk * (kBlock / LANES);
     const SysC &y = sys[sys_of_g16[first >> 4]];
-    step_ds_body<1, LANES, true>(a, y.box, a.st.ctl + y.id, blk, y.p_off + y.n, y.c_off, y.c_off + y.box.ncell,
+    step_ds_body<1, LANES, true, OBS>(a, y.box, a.st.ctl + y.id, blk, y.p_off + y.n, y.c_off, y.c_off + y.box.ncell,
                                  blk - y.b_off, y.nb, nullptr);
 }
 
@@ -547,15 +568,18 @@ hipError_t launch_step(const Launch &L, int64_t step, int forced, int mode, int 
     dim3 grid(step_blocks(*L.g)), block(kBlock);
     const bool ds = L.g->prec == LJMD_FP32_DS;
     const bool two = L.g->nspecies == 2;
-    const bool quanta = ds && !two && L.box->cubic;
-#define STEP(NS, LN)                                                                     \
-    do {                                                                                 \
-        if (ds && NS == 1 && quanta)                                                     \
-            hipLaunchKernelGGL((k_step_ds<1, LN, true>), grid, block, 0, L.stream, a);   \
-        else if (ds)                                                                     \
-            hipLaunchKernelGGL((k_step_ds<NS, LN, false>), grid, block, 0, L.stream, a); \
-        else                                                                             \
-            hipLaunchKernelGGL((k_step_fp64<NS, LN>), grid, block, 0, L.stream, a);      \
+    const bool quanta = ds && !two && L.box->cubic && L.g->n < kQuantaMaxSlots;
+    const bool obs = (mode & kObserve) != 0;
+#define STEP(NS, LN)                                                                            \
+    do {                                                                                        \
+        if (ds && NS == 1 && quanta && obs)                                                     \
+            hipLaunchKernelGGL((k_step_ds<1, LN, true, true>), grid, block, 0, L.stream, a);    \
+        else if (ds && NS == 1 && quanta)                                                       \
+            hipLaunchKernelGGL((k_step_ds<1, LN, true, false>), grid, block, 0, L.stream, a);   \
+        else if (ds)                                                                            \
+            hipLaunchKernelGGL((k_step_ds<NS, LN, false, true>), grid, block, 0, L.stream, a);  \
+        else                                                                                    \
+            hipLaunchKernelGGL((k_step_fp64<NS, LN>), grid, block, 0, L.stream, a);             \
     } while (0)
 #define BY_LANES(NS)                          \
     switch (L.g->lanes) {                     \
@@ -590,13 +614,21 @@ hipError_t launch_batch_step(const Launch &L, const SysC *sys, const int32_t *sy
                              int64_t step, int forced, int mode, int slot) {
     StepArgs a = make_args(L, step, forced, mode, slot);
     const dim3 grid((unsigned)nblocks), block(kBlock);
+#define BSTEP(LN)                                                                                        \
+    do {                                                                                                 \
+        if (mode & kObserve)                                                                             \
+            hipLaunchKernelGGL((k_batch_step<LN, true>), grid, block, 0, L.stream, a, sys, sys_of_g16);  \
+        else                                                                                             \
+            hipLaunchKernelGGL((k_batch_step<LN, false>), grid, block, 0, L.stream, a, sys, sys_of_g16); \
+    } while (0)
     switch (L.g->lanes) {
-        case 1: hipLaunchKernelGGL(k_batch_step<1>, grid, block, 0, L.stream, a, sys, sys_of_g16); break;
-        case 2: hipLaunchKernelGGL(k_batch_step<2>, grid, block, 0, L.stream, a, sys, sys_of_g16); break;
-        case 4: hipLaunchKernelGGL(k_batch_step<4>, grid, block, 0, L.stream, a, sys, sys_of_g16); break;
-        case 8: hipLaunchKernelGGL(k_batch_step<8>, grid, block, 0, L.stream, a, sys, sys_of_g16); break;
-        default: hipLaunchKernelGGL(k_batch_step<16>, grid, block, 0, L.stream, a, sys, sys_of_g16); break;
+        case 1: BSTEP(1); break;
+        case 2: BSTEP(2); break;
+        case 4: BSTEP(4); break;
+        case 8: BSTEP(8); break;
+        default: BSTEP(16); break;
     }
+#undef BSTEP
     return hipGetLastError();
 }
 

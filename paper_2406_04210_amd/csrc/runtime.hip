@@ -469,7 +469,8 @@ int run_steps(ljmd_ctx *c, int64_t nsteps, double *obs_dev, const RunOpts &o) {
         int r = rebuild_sequence(c, s, forced, resort);
         if (r) return r;
         const bool last = k == nsteps - 1;
-        const int mode = kFinalize | (last ? kStoreForce : kIntegrate);
+        const bool observe = obs_dev != nullptr || (last && o.final_obs);
+        const int mode = kFinalize | (last ? kStoreForce : kIntegrate) | (observe ? kObserve : 0);
         L = launcher(c);
         {
             Bracket b(c, 0);
@@ -709,8 +710,8 @@ int batch_geom(const ljmd_params *shared, const ljmd_system *ys, int32_t nsys, B
         c_off += pk.ncell;
         b_off += y.nb;
     }
-    if (p_off > (int64_t)INT32_MAX - 1024) {
-        bg.why = "batch: more than 2^31 particle slots";
+    if (p_off >= kQuantaMaxSlots) {
+        bg.why = "batch: 2^28 particle slots or more";
         return LJMD_EINVAL;
     }
     bg.nslots = p_off;
@@ -892,7 +893,7 @@ int ljmd_set_state(ljmd_ctx *c, const double *x, const double *v, const int32_t 
     int r = rebuild_sequence(c, 0, 1, true);
     if (r) return r;
     L = launcher(c);
-    if ((e = launch_step(L, 0, 1, kStoreForce, 0)) != hipSuccess) return hip_fail(c, e, "force");
+    if ((e = launch_step(L, 0, 1, kStoreForce | kObserve, 0)) != hipSuccess) return hip_fail(c, e, "force");
     if ((e = launch_obs_reduce(L, 0, 1, c->nblocks, nullptr, 0)) != hipSuccess)
         return hip_fail(c, e, "obs");
     c->have_state = true;
@@ -951,7 +952,7 @@ int ljmd_minimize_sd(ljmd_ctx *c, int32_t nsteps, double max_disp, double clamp,
     int r = rebuild_sequence(c, c->step, 1, true);
     if (r) return r;
     Launch L = launcher(c);
-    if ((e = launch_step(L, c->step, 1, kStoreForce, (int)(c->step % kRing))) != hipSuccess)
+    if ((e = launch_step(L, c->step, 1, kStoreForce | kObserve, (int)(c->step % kRing))) != hipSuccess)
         return hip_fail(c, e, "force");
     if ((e = launch_obs_reduce(L, c->step, 1, c->nblocks, nullptr, 0)) != hipSuccess)
         return hip_fail(c, e, "obs");
@@ -1048,7 +1049,7 @@ int ljmd_set_pair_params(ljmd_ctx *c, const double eps[4], const double sigma[4]
     // Forces and observables of the current positions under the new values.
     Launch L = launcher(c);
     hipError_t e;
-    if ((e = launch_step(L, c->step, 0, kStoreForce, (int)(c->step % kRing))) != hipSuccess)
+    if ((e = launch_step(L, c->step, 0, kStoreForce | kObserve, (int)(c->step % kRing))) != hipSuccess)
         return hip_fail(c, e, "force");
     if ((e = launch_obs_reduce(L, c->step, 1, c->nblocks, nullptr, 0)) != hipSuccess)
         return hip_fail(c, e, "obs");
@@ -1416,7 +1417,7 @@ int ljmd_batch_set_state(ljmd_batch *b, const double *x, const double *v, const 
     int r = batch_rebuild(b, 0, 1, true);
     if (r) return r;
     L = blauncher(b);
-    if ((e = launch_batch_step(L, b->sys, b->g16, b->bg.nblocks, 0, 1, kStoreForce, 0)) != hipSuccess)
+    if ((e = launch_batch_step(L, b->sys, b->g16, b->bg.nblocks, 0, 1, kStoreForce | kObserve, 0)) != hipSuccess)
         return bhip(b, e, "batch force");
     if ((e = launch_batch_obs(L, b->sys, b->nsys, 0, 0, nullptr)) != hipSuccess) return bhip(b, e, "batch obs");
     b->have_state = true;
@@ -1442,7 +1443,8 @@ int ljmd_batch_run(ljmd_batch *b, int64_t nsteps, double *obs_dev) {
         const bool last = k == nsteps - 1;
         L = blauncher(b);
         if ((e = launch_batch_step(L, b->sys, b->g16, b->bg.nblocks, s, forced,
-                                   kFinalize | (last ? kStoreForce : kIntegrate), (int)(s % kRing))) != hipSuccess)
+                                   kFinalize | (last ? kStoreForce | kObserve : kIntegrate), (int)(s % kRing))) !=
+            hipSuccess)
             return bhip(b, e, "batch step");
         if (!last) b->cur ^= 1;
     }
