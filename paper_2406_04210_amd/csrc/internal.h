@@ -23,9 +23,9 @@ constexpr int kNP = 8;           // doubles per partial row: U, W, K, px, py, pz
 // Latched device error bits (ctl->flags).
 enum : uint32_t { kErrList = 1u, kErrCell = 2u, kErrNaN = 4u };
 // List slots allocated past the last row: the force loop of one species in a
-// cubic box prefetches index rows (of 64 entries) up to eleven rows past a
-// list without clamping.
-constexpr size_t kListPad = 16 * 64;
+// cubic box reads index rows (of 64 entries) up to seven rows past a list
+// without clamping.
+constexpr size_t kListPad = 8 * 64;
 
 // Box constants. The fixed-point image coordinate q = round(x * 2^32 / L)
 // mod 2^32 turns the minimum image into a wrapping 32-bit subtraction.
