@@ -16,7 +16,7 @@
 namespace ljmd {
 
 constexpr int kWave = 64;        // CDNA wavefront width
-constexpr int kBlock = 256;      // threads per block of the per-particle kernels
+constexpr int kBlock = 1024;     // threads per block of the per-particle kernels
 constexpr int kRing = 64;        // steps of block partials kept before an observable flush
 constexpr int kNP = 8;           // doubles per partial row: U, W, K, px, py, pz, -, -
 
@@ -88,7 +88,7 @@ struct SysC {
     int32_t nb;      // step-kernel blocks
     int32_t pad;
 };
-constexpr int kSysAlign = 256;
+constexpr int kSysAlign = 1024;
 
 // Views of the caller's workspace (all device pointers).
 struct State {

@@ -126,6 +126,8 @@ __device__ inline void step_ds_body(const StepArgs &a, const BoxC &box, Ctl *ctl
     double e = 0.0, w = 0.0, a12 = 0.0, a6 = 0.0;
     int an = 0;
     const float rc2_1 = a.pc.rc2f[0], sig2_1 = a.pc.sig2f[0];
+    const Tri<float> t_rc2(a.pc.rc2f), t_sig2(a.pc.sig2f), t_eps24(a.pc.eps24f), t_eps4(a.pc.eps4f),
+        t_shift(a.pc.shiftf);
     const float c2x = box.r2c[0], c2y = box.r2c[1], c2z = box.r2c[2];
     // Four list entries per trip: all index loads, then all record gathers,
     // are in flight before the arithmetic of the first one.
@@ -204,17 +206,17 @@ __device__ inline void step_ds_body(const StepArgs &a, const BoxC &box, Ctl *ctl
                 }
             } else {
                 const int tt = ri.w + rj.w;
-                if (r2 < by_t<NS>(tt, a.pc.rc2f)) {
+                if (r2 < t_rc2(tt)) {
                     const float ir2 = __builtin_amdgcn_rcpf(r2);
-                    const float s2 = by_t<NS>(tt, a.pc.sig2f) * ir2;
+                    const float s2 = t_sig2(tt) * ir2;
                     const float s6 = s2 * s2 * s2;
                     const float s12 = s6 * s6;
-                    const float c24 = by_t<NS>(tt, a.pc.eps24f);
+                    const float c24 = t_eps24(tt);
                     const float fs = c24 * ((s6 * ir2) * fmaf(2.0f, s6, -1.0f));
                     fx = fmaf(fs, dx, fx);
                     fy = fmaf(fs, dy, fy);
                     fz = fmaf(fs, dz, fz);
-                    e += (double)fmaf(by_t<NS>(tt, a.pc.eps4f), s12 - s6, -by_t<NS>(tt, a.pc.shiftf));
+                    e += (double)fmaf(t_eps4(tt), s12 - s6, -t_shift(tt));
                     w += (double)(c24 * fmaf(2.0f, s12, -s6));
                 }
             }
@@ -347,6 +349,8 @@ __global__ __launch_bounds__(kBlock) void k_step_fp64(StepArgs a) {
     const int32_t *__restrict__ nb = st.nbr + chunk * (int64_t)(P * a.g.cap) + lane;
     const int iters = cnt > l ? (cnt - l + LANES - 1) / LANES : 0;
     double fx = 0, fy = 0, fz = 0, e = 0, w = 0;
+    const Tri<double> t_rc2(a.pc.rc2), t_sig2(a.pc.sig2), t_eps24(a.pc.eps24), t_eps4(a.pc.eps4),
+        t_shift(a.pc.shift);
     constexpr int U = 4;
     for (int m = 0; m < iters; m += U) {
         // Indices past the list end are clamped to its last entry, so every
@@ -366,18 +370,18 @@ __global__ __launch_bounds__(kBlock) void k_step_fp64(StepArgs a) {
             const double dz = disp_d(ri.z, rj.z, a.box.L[2], a.box.invL[2]);
             const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
             const int t = NS == 1 ? 0 : si + (int)rj.w;
-            if (r2 < by_t<NS>(t, a.pc.rc2)) {
+            if (r2 < t_rc2(t)) {
                 // Reciprocal: hardware estimate refined by two Newton steps.
                 double ir2 = __builtin_amdgcn_rcp(r2);
                 ir2 = fma(ir2, fma(-r2, ir2, 1.0), ir2);
                 ir2 = fma(ir2, fma(-r2, ir2, 1.0), ir2);
-                const double s2 = by_t<NS>(t, a.pc.sig2) * ir2;
+                const double s2 = t_sig2(t) * ir2;
                 const double s6 = s2 * s2 * s2;
-                const double fs = by_t<NS>(t, a.pc.eps24) * s6 * fma(2.0, s6, -1.0) * ir2;
+                const double fs = t_eps24(t) * s6 * fma(2.0, s6, -1.0) * ir2;
                 fx = fma(fs, dx, fx);
                 fy = fma(fs, dy, fy);
                 fz = fma(fs, dz, fz);
-                e += fma(by_t<NS>(t, a.pc.eps4) * s6, s6 - 1.0, -by_t<NS>(t, a.pc.shift));
+                e += fma(t_eps4(t) * s6, s6 - 1.0, -t_shift(t));
                 w = fma(fs, r2, w);
             }
         }

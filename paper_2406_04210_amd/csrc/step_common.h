@@ -29,6 +29,15 @@ __device__ inline T by_t(int t, const T (&a)[3]) {
     }
 }
 
+// A per-pair-type table held in registers: selecting among loaded values,
+// never indexing the kernel-argument copy (which would place it in scratch).
+template <class T>
+struct Tri {
+    T v0, v1, v2;
+    __device__ explicit Tri(const T (&a)[3]) : v0(a[0]), v1(a[1]), v2(a[2]) {}
+    __device__ T operator()(int t) const { return t == 0 ? v0 : (t == 1 ? v1 : v2); }
+};
+
 template <class T>
 __device__ inline T by_s(int s, const T (&a)[2]) {
     return s == 0 ? a[0] : a[1];
