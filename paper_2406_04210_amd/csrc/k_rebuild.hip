@@ -91,7 +91,25 @@ __device__ inline void bin_one(const State &st, const Geom &g, const BoxC &box, 
     rec_q(r, box, q);
     int cx, cy, cz;
     const int64_t c = c_off + cell_of_q(q[0], q[1], q[2], box, rank_of, &cx, &cy, &cz);
-    const int slot = atomicAdd(&st.cell_count[c], 1);
+    // The lanes of a wavefront that land in one cell take their slots with a
+    // single atomic: consecutive particles (space-filling-curve order) share
+    // a few cells. Every active lane runs the same number of rounds.
+    const int lane = threadIdx.x & 63;
+    const int ci = (int)c;
+    unsigned long long pending = __ballot(1);
+    int slot = 0;
+    while (pending) {
+        const int leader = __ffsll(pending) - 1;
+        const int cl = __shfl(ci, leader);
+        const unsigned long long same = __ballot(ci == cl);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&st.cell_count[cl], __popcll(same));
+        base = __shfl(base, leader);
+        if (ci == cl)
+            slot = base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(same >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)same, 0u));
+        pending &= ~same;
+    }
     if (slot < g.cell_cap)
         cell_recs<PREC>(st)[c * g.cell_cap + slot] = CR::pack(r, (int)i);
     else
