@@ -23,10 +23,10 @@ namespace ljmd {
 // Block-level deterministic reduction of the six observable partials and the
 // displacement maximum; one row of partials per block.
 // Without OBS only the displacement maximum is reduced.
-template <bool OBS = true>
+template <bool OBS = true, int BS = kBlock>
 __device__ inline void block_finish(const StepArgs &a, Ctl *ctl, int blk, double u, double w, double k,
                                     double px, double py, double pz, uint32_t dmax) {
-    constexpr int WPB = kBlock / kWave;
+    constexpr int WPB = BS / kWave;
     __shared__ double red[WPB][6];
     __shared__ uint32_t redm[WPB];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -329,9 +329,9 @@ __global__ __launch_bounds__(kBlock) void k_batch_step(StepArgs a, const SysC *s
 
 // ---------------------------------------------------------------- FP64 ---
 template <int NS, int LANES>
-__global__ __launch_bounds__(kBlock) void k_step_fp64(StepArgs a) {
+__global__ __launch_bounds__(kBlockF64) void k_step_fp64(StepArgs a) {
     constexpr int P = kWave / LANES;
-    constexpr int WPB = kBlock / kWave;
+    constexpr int WPB = kBlockF64 / kWave;
     const State &st = a.st;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -445,7 +445,7 @@ __global__ __launch_bounds__(kBlock) void k_step_fp64(StepArgs a) {
         st.vel64[i] = v;
         if (a.mode & kStoreForce) st.frc64[i] = make_double4(fx, fy, fz, 0.0);
     }
-    block_finish(a, a.st.ctl, blk, pu, pw, pk, ppx, ppy, ppz, dm);
+    block_finish<true, kBlockF64>(a, a.st.ctl, blk, pu, pw, pk, ppx, ppy, ppz, dm);
 }
 
 // Start of a run: "integrate" from the stored forces of the current step.
@@ -548,7 +548,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_integrate(StepArgs a, const Sy
 
 // ------------------------------------------------------------------------
 int step_blocks(const Geom &g) {
-    const int per_block = (kBlock / kWave) * (kWave / g.lanes);
+    const int per_block = (step_block_threads(g.prec) / kWave) * (kWave / g.lanes);
     return (int)((g.n + per_block - 1) / per_block);
 }
 
@@ -569,7 +569,7 @@ static StepArgs make_args(const Launch &L, int64_t step, int forced, int mode, i
 
 hipError_t launch_step(const Launch &L, int64_t step, int forced, int mode, int slot) {
     StepArgs a = make_args(L, step, forced, mode, slot);
-    dim3 grid(step_blocks(*L.g)), block(kBlock);
+    dim3 grid(step_blocks(*L.g)), block(step_block_threads(L.g->prec));
     const bool ds = L.g->prec == LJMD_FP32_DS;
     const bool two = L.g->nspecies == 2;
     const bool quanta = ds && !two && L.box->cubic && L.g->n < kQuantaMaxSlots;

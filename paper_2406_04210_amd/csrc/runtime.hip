@@ -196,7 +196,7 @@ Plan make_plan(const ljmd_params *p) {
     if (pl.cell_cap > 768) pl.cell_cap = 768;
     // Measured on MI355X at N=256,000: 2 lanes per particle for FP32, 4 for FP64.
     pl.lanes = p->lanes != 0 ? p->lanes : (p->precision == LJMD_FP64 ? 4 : 2);
-    const int per_block = (kBlock / kWave) * (kWave / pl.lanes);
+    const int per_block = (step_block_threads(p->precision) / kWave) * (kWave / pl.lanes);
     pl.max_blocks = (int)((p->n + per_block - 1) / per_block);
     lay_out(pl, p->precision, 1);
     return pl;
