@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define LJMD_ABI_VERSION 3
+#define LJMD_ABI_VERSION 4
 
 enum ljmd_status {
     LJMD_OK = 0,
@@ -333,8 +333,17 @@ int ljmd_batch_set_state(ljmd_batch *b, const double *x, const double *v, const 
 
 /* Advance every system nsteps (as ljmd_run). obs_dev (device, nsys *
  * LJMD_NOBS float64, or NULL) receives each system's observables of the last
- * step, with column 6 holding its list builds so far. Asynchronous. */
+ * step, with column 6 holding its list builds so far. Asynchronous.
+ * Whole resort periods (sort_interval steps, doubled when odd; 64 without
+ * resorts) that start at a multiple of the period and do not hold the run's
+ * last step are replayed from a HIP graph captured on first use (one per
+ * parity of the record buffers, kept until ljmd_batch_destroy); the results
+ * are bitwise those of launching every step. The stream must not be under
+ * capture by the caller while graphs are enabled. */
 int ljmd_batch_run(ljmd_batch *b, int64_t nsteps, double *obs_dev);
+
+/* Enable (default) or disable the graph replay of ljmd_batch_run. */
+int ljmd_batch_use_graphs(ljmd_batch *b, int32_t enable);
 
 /* State and forces in the concatenated row order of ljmd_batch_set_state. */
 int ljmd_batch_get_state(ljmd_batch *b, double *x, double *v, int32_t *img);

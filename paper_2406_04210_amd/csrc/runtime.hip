@@ -1237,6 +1237,20 @@ struct ljmd_batch {
     int64_t step = 0;
     bool have_state = false;
     std::string err;
+    // Graph replay of whole periods of steps (see batch_period): one graph
+    // per value of cur at the period's start, captured on first use on a
+    // private stream and launched on the batch's stream.
+    bool graphs = true;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t period_graph[2] = {nullptr, nullptr};
+    hipGraphExec_t period_exec[2] = {nullptr, nullptr};
+    ~ljmd_batch() {
+        for (int k = 0; k < 2; ++k) {
+            if (period_exec[k]) (void)hipGraphExecDestroy(period_exec[k]);
+            if (period_graph[k]) (void)hipGraphDestroy(period_graph[k]);
+        }
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    }
 };
 
 namespace {
@@ -1284,6 +1298,71 @@ int batch_rebuild(ljmd_batch *b, int64_t step, int forced, bool resort) {
         if ((e = launch_batch_resort_move(L, b->bg.ncell)) != hipSuccess) return bhip(b, e, "resort");
     }
     if ((e = launch_batch_nlist(L, b->sys, b->bp, b->bg.ncell)) != hipSuccess) return bhip(b, e, "nlist");
+    return LJMD_OK;
+}
+
+// One step s of every system: rebuild if due, then forces and both
+// velocity-Verlet halves (the last step of a run stores forces and
+// observables instead of starting the next step).
+int batch_one_step(ljmd_batch *b, int64_t s, bool last) {
+    const bool resort = b->p.sort_interval > 0 && s % b->p.sort_interval == 0;
+    const int forced = resort ? 1 : 0;
+    int r = batch_rebuild(b, s, forced, resort);
+    if (r) return r;
+    Launch L = blauncher(b);
+    hipError_t e = launch_batch_step(L, b->sys, b->g16, b->bg.nblocks, s, forced,
+                                     kFinalize | (last ? kStoreForce | kObserve : kIntegrate), (int)(s % kRing));
+    if (e != hipSuccess) return bhip(b, e, "batch step");
+    if (!last) b->cur ^= 1;
+    return LJMD_OK;
+}
+
+// Steps per replayed graph: the resort period (doubled when odd), or 64
+// without resorts. Every kernel of a step depends on the step number only
+// through its parity, the resort schedule and the partials slot of observed
+// steps (never inside a period), so a period captured at one multiple of
+// this length replays unchanged at every other; its length is even, so the
+// record buffer in use (cur) is the same at its start and end.
+int64_t batch_period(const ljmd_batch *b) {
+    const int64_t si = b->p.sort_interval;
+    if (si <= 0) return 64;
+    return si % 2 == 0 ? si : 2 * si;
+}
+
+// Steps s0 + 1 .. s0 + period as one graph launch (s0 a multiple of the
+// period, none of them the last step of the run).
+int batch_period_graph(ljmd_batch *b, int64_t s0) {
+    const int64_t P = batch_period(b);
+    const int k = b->cur;
+    hipError_t e;
+    if (!b->period_exec[k]) {
+        if (!b->cap_stream && (e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+            return bhip(b, e, "capture stream");
+        hipStream_t user = b->stream;
+        const int cur0 = b->cur;
+        if ((e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return bhip(b, e, "begin capture");
+        b->stream = b->cap_stream;
+        int r = LJMD_OK;
+        for (int64_t q = 1; q <= P && r == LJMD_OK; ++q) r = batch_one_step(b, s0 + q, false);
+        b->stream = user;
+        b->cur = cur0;
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(b->cap_stream, &g);
+        if (r != LJMD_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return r;
+        }
+        if (e != hipSuccess) return bhip(b, e, "end capture");
+        hipGraphExec_t x = nullptr;
+        if ((e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0)) != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return bhip(b, e, "graph instantiate");
+        }
+        b->period_graph[k] = g;
+        b->period_exec[k] = x;
+    }
+    if ((e = hipGraphLaunch(b->period_exec[k], b->stream)) != hipSuccess) return bhip(b, e, "graph launch");
     return LJMD_OK;
 }
 
@@ -1403,6 +1482,12 @@ int ljmd_batch_destroy(ljmd_batch *b) {
     return LJMD_OK;
 }
 
+int ljmd_batch_use_graphs(ljmd_batch *b, int32_t enable) {
+    if (!b) return LJMD_EINVAL;
+    b->graphs = enable != 0;
+    return LJMD_OK;
+}
+
 int ljmd_batch_set_state(ljmd_batch *b, const double *x, const double *v, const int32_t *species) {
     if (!b) return LJMD_EINVAL;
     if (!x || !v || !species) return bfail(b, LJMD_EINVAL, "batch_set_state: NULL array");
@@ -1434,20 +1519,23 @@ int ljmd_batch_run(ljmd_batch *b, int64_t nsteps, double *obs_dev) {
     if ((e = launch_batch_integrate(L, b->sys, b->g16, b->bg.nslots, b->step)) != hipSuccess)
         return bhip(b, e, "batch integrate");
     b->cur ^= 1;
-    for (int64_t k = 0; k < nsteps; ++k) {
+    // Whole periods that do not hold the run's last step replay a captured
+    // graph; the other steps are launched one by one.
+    const int64_t P = batch_period(b);
+    int64_t k = 0;
+    while (k < nsteps) {
         const int64_t s = b->step + 1 + k;
-        const bool resort = b->p.sort_interval > 0 && s % b->p.sort_interval == 0;
-        const int forced = resort ? 1 : 0;
-        int r = batch_rebuild(b, s, forced, resort);
+        int r;
+        if (b->graphs && (s - 1) % P == 0 && nsteps - k > P) {
+            r = batch_period_graph(b, s - 1);
+            k += P;
+        } else {
+            r = batch_one_step(b, s, k == nsteps - 1);
+            ++k;
+        }
         if (r) return r;
-        const bool last = k == nsteps - 1;
-        L = blauncher(b);
-        if ((e = launch_batch_step(L, b->sys, b->g16, b->bg.nblocks, s, forced,
-                                   kFinalize | (last ? kStoreForce | kObserve : kIntegrate), (int)(s % kRing))) !=
-            hipSuccess)
-            return bhip(b, e, "batch step");
-        if (!last) b->cur ^= 1;
     }
+    L = blauncher(b);
     b->step += nsteps;
     if ((e = launch_batch_obs(L, b->sys, b->nsys, (int)(b->step % kRing), b->step, obs_dev)) != hipSuccess)
         return bhip(b, e, "batch obs");

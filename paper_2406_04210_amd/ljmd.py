@@ -18,7 +18,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libljmd.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 FP64 = 0
 FP32_DS = 1
 ADJ_STORE_ALL = 1
@@ -94,6 +94,7 @@ SIGNATURES = {
     "ljmd_batch_destroy": (C.c_int, [_vp]),
     "ljmd_batch_set_state": (C.c_int, [_vp, _dp, _dp, _ip]),
     "ljmd_batch_run": (C.c_int, [_vp, C.c_int64, _dp]),
+    "ljmd_batch_use_graphs": (C.c_int, [_vp, C.c_int32]),
     "ljmd_batch_get_state": (C.c_int, [_vp, _dp, _dp, _ip]),
     "ljmd_batch_get_forces": (C.c_int, [_vp, _dp]),
     "ljmd_batch_observables": (C.c_int, [_vp, C.POINTER(C.c_double)]),
@@ -491,6 +492,11 @@ class Batch:
         s = self._dev(species, t.int32).reshape(self.ntot)
         self._err(lib.ljmd_batch_set_state(self.b, _ptr(x), _ptr(v), _ptr(s)))
         self._keep = (x, v, s)
+
+    def use_graphs(self, enable: bool):
+        """Replay whole resort periods of run() from captured HIP graphs
+        (default) or launch every step."""
+        self._err(lib.ljmd_batch_use_graphs(self.b, 1 if enable else 0))
 
     def run(self, nsteps: int, observe: bool = False):
         """Advance every system; returns the (nsys, 8) device tensor of each

@@ -78,6 +78,34 @@ def test_batch_matches_single_boxes_bitwise(ljmd, replicas):
         assert int(ob[k, 6]) == o["rebuilds"] and int(ob[k, 7]) == o["step"] == 135
 
 
+def batch_snapshot(b):
+    x, v, img = b.get_state()
+    f = b.forces()
+    o = b.observables()
+    b.sync()
+    return x, v, img, f, o
+
+
+@pytest.mark.parametrize("sort_interval,runs", [(20, (70, 55, 41)), (15, (100, 61))])
+def test_batch_graph_replay_matches_eager_bitwise(ljmd, replicas, sort_interval, runs):
+    # Whole resort periods (20 steps; 30 for the odd interval 15) replay a
+    # captured graph; the eager batch launches every step. After every run
+    # (graph replays, eager steps and host synchronisation in between) both
+    # hold bitwise the same state, forces and observables.
+    import torch
+    ws = replicas[:5]
+    a = make_batch(ljmd, ws, sort_interval=sort_interval)
+    e = make_batch(ljmd, ws, sort_interval=sort_interval)
+    e.use_graphs(False)
+    for n in runs:
+        a.run(n)
+        e.run(n)
+        sa, se = batch_snapshot(a), batch_snapshot(e)
+        for k in range(4):
+            assert torch.equal(sa[k], se[k]), (n, k)
+        assert np.array_equal(sa[4], se[4]), n
+
+
 def test_batch_forces_match_oracle(ljmd, replicas):
     ws = replicas[:4]
     b = make_batch(ljmd, ws)
