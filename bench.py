@@ -204,9 +204,14 @@ def time_batch(ljmd, torch, W, steps: int = 1000, warmup: int = 50):
     sum(N) * steps / wall time of the timed ljmd_batch_run."""
     import numpy as np
     ws = W.replica_draws(512)
-    b = ljmd.Batch([w.n for w in ws], [w.box[0] for w in ws], ws[0].params, sort_interval=100)
-    b.set_state(np.concatenate([w.x for w in ws]), np.concatenate([w.v for w in ws]),
+    sizes, edges = [w.n for w in ws], [w.box[0] for w in ws]
+    x, v, sp = (np.concatenate([w.x for w in ws]), np.concatenate([w.v for w in ws]),
                 np.concatenate([w.species for w in ws]))
+    # Lanes per particle and list capacity from the batch autotuner (not timed).
+    tune = ljmd.autotune_batch(sizes, edges, ws[0].params, x, v, sp, steps=20)
+    b = ljmd.Batch(sizes, edges, ws[0].params, sort_interval=100, lanes=tune["lanes"],
+                   nbr_capacity=tune["nbr_capacity"])
+    b.set_state(x, v, sp)
     b.run(warmup)
     b.sync()
     stream = torch.cuda.current_stream()
@@ -234,6 +239,7 @@ def time_batch(ljmd, torch, W, steps: int = 1000, warmup: int = 50):
         "value": ntot * steps / (ms * 1e-3), "unit": "particle-steps/s", "steps": steps,
         "ms_per_step": ms / steps, "launch": "HIP graph per 100-step resort period",
         "ms_per_step_eager_launches": ms_eager / steps,
+        "autotuned": {"lanes": tune["lanes"], "nbr_capacity": tune["nbr_capacity"], "max_fill": tune["max_fill"]},
         "rebuilds_per_system_mean": float(obs[:, 6].mean()),
     }
 

@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define LJMD_ABI_VERSION 4
+#define LJMD_ABI_VERSION 5
 
 enum ljmd_status {
     LJMD_OK = 0,
@@ -355,6 +355,22 @@ int ljmd_batch_observables(ljmd_batch *b, double *obs_host);
 
 /* Synchronise; the first latched device error of any system, or LJMD_OK. */
 int ljmd_batch_sync_status(ljmd_batch *b);
+
+/* Synchronise; *out (host) receives the longest neighbour list of any
+ * system as built last. */
+int ljmd_batch_max_fill(ljmd_batch *b, int32_t *out);
+
+/* Batch autotuner: as ljmd_autotune, timed on the whole batch. For each
+ * lanes candidate a batch of these systems is created in dev_workspace
+ * (>= ljmd_batch_autotune_workspace_size bytes), loaded with x, v, species
+ * (device, as ljmd_batch_set_state), warmed up 10 steps and timed over
+ * steps steps; the fastest is kept, and the list capacity is sized from the
+ * longest list seen. Cached under a key of the device, the number of
+ * systems, their total size and mean density. Synchronises. */
+size_t ljmd_batch_autotune_workspace_size(const ljmd_params *shared, const ljmd_system *sys, int32_t nsys);
+int ljmd_batch_autotune(const ljmd_params *shared, const ljmd_system *sys, int32_t nsys, const double *x,
+                        const double *v, const int32_t *species, void *dev_workspace, size_t bytes,
+                        void *hip_stream, int32_t steps, const char *cache_path, ljmd_tuning *out);
 
 const char *ljmd_batch_last_error(const ljmd_batch *b);
 

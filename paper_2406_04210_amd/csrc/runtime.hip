@@ -1482,6 +1482,19 @@ int ljmd_batch_destroy(ljmd_batch *b) {
     return LJMD_OK;
 }
 
+int ljmd_batch_max_fill(ljmd_batch *b, int32_t *out) {
+    if (!b || !out) return LJMD_EINVAL;
+    if (!b->have_state) return bfail(b, LJMD_ESTATE, "batch_max_fill before batch_set_state");
+    hipError_t e = launch_max_fill(blauncher(b));
+    if (e != hipSuccess) return bhip(b, e, "max_fill");
+    // k_max_fill scans every slot of the batch into the first control set.
+    if ((e = hipMemcpyAsync(out, &b->st.ctl->max_fill, sizeof(int32_t), hipMemcpyDeviceToHost, b->stream)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(b->stream)) != hipSuccess)
+        return bhip(b, e, "read max_fill");
+    return LJMD_OK;
+}
+
 int ljmd_batch_use_graphs(ljmd_batch *b, int32_t enable) {
     if (!b) return LJMD_EINVAL;
     b->graphs = enable != 0;

@@ -76,6 +76,33 @@ void cache_store(const char *path, const std::string &key, const ljmd_tuning &t)
     std::fclose(f);
 }
 
+std::string batch_key(const ljmd_params *p, const ljmd_system *sys, int32_t nsys) {
+    hipDeviceProp_t prop;
+    int dev = 0;
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        arch = prop.gcnArchName;
+    for (char &ch : arch)
+        if (ch == '"' || ch == ' ') ch = '_';
+    double ntot = 0.0, vol = 0.0;
+    for (int32_t k = 0; k < nsys; ++k) {
+        ntot += (double)sys[k].n;
+        vol += sys[k].box * sys[k].box * sys[k].box;
+    }
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "batch|%s|nsys%d|n2^%d|rho%.2f|rl%.1f", arch.c_str(), nsys,
+                  (int)std::lround(std::log2(ntot)), std::round(ntot / vol * 20.0) / 20.0, p->rcut[0] + p->skin);
+    return buf;
+}
+
+// List capacity from the longest list seen: a margin for density
+// fluctuations, in whole 16-slot units.
+int capacity_for(int fill) {
+    int cap = (int)std::ceil(std::fmax(1.25 * fill, fill + 24.0));
+    cap = (cap + 15) / 16 * 16;
+    return cap < 16 ? 16 : (cap > 4096 ? 4096 : cap);
+}
+
 }  // namespace
 
 extern "C" {
@@ -143,12 +170,79 @@ int ljmd_autotune(const ljmd_params *p, const double *x, const double *v, const 
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != LJMD_OK) return rc;
-    // List capacity: the longest list seen with a margin for density
-    // fluctuations, in whole 16-slot units.
-    const int fill = out->max_fill;
-    int cap = (int)std::ceil(std::fmax(1.25 * fill, fill + 24.0));
-    cap = (cap + 15) / 16 * 16;
-    out->nbr_capacity = cap < 16 ? 16 : (cap > 4096 ? 4096 : cap);
+    out->nbr_capacity = capacity_for(out->max_fill);
+    out->ms_per_step = best_ms;
+    out->from_cache = 0;
+    if (cache_path) cache_store(cache_path, key, *out);
+    return LJMD_OK;
+}
+
+size_t ljmd_batch_autotune_workspace_size(const ljmd_params *shared, const ljmd_system *sys, int32_t nsys) {
+    if (!shared || !sys || nsys < 1) return 0;
+    size_t best = 0;
+    for (int lanes : kLaneCandidates) {
+        ljmd_params q = *shared;
+        q.lanes = lanes;
+        const size_t s = ljmd_batch_workspace_size(&q, sys, nsys);
+        if (s == 0) return 0;
+        best = s > best ? s : best;
+    }
+    return best;
+}
+
+int ljmd_batch_autotune(const ljmd_params *shared, const ljmd_system *sys, int32_t nsys, const double *x,
+                        const double *v, const int32_t *species, void *ws, size_t bytes, void *stream,
+                        int32_t steps, const char *cache_path, ljmd_tuning *out) {
+    if (!shared || !sys || nsys < 1 || !x || !v || !species || !ws || !out || steps < 1) return LJMD_EINVAL;
+    std::memset(out, 0, sizeof *out);
+    const size_t need = ljmd_batch_autotune_workspace_size(shared, sys, nsys);
+    if (need == 0) return LJMD_EINVAL;
+    const std::string key = batch_key(shared, sys, nsys);
+    if (cache_path && cache_lookup(cache_path, key, out)) {
+        out->from_cache = 1;
+        return LJMD_OK;
+    }
+    if (bytes < need) return LJMD_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return LJMD_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return LJMD_EHIP;
+    }
+    double best_ms = 0.0;
+    int rc = LJMD_OK;
+    for (int lanes : kLaneCandidates) {
+        ljmd_params q = *shared;
+        q.lanes = lanes;
+        ljmd_batch *b = nullptr;
+        if ((rc = ljmd_batch_create(&q, sys, nsys, ws, bytes, stream, &b)) != LJMD_OK) break;
+        float ms = 0.f;
+        int32_t fill = 0;
+        rc = ljmd_batch_set_state(b, x, v, species);
+        if (rc == LJMD_OK) rc = ljmd_batch_run(b, 10, nullptr);  // warm-up
+        if (rc == LJMD_OK) rc = ljmd_batch_sync_status(b);
+        if (rc == LJMD_OK && hipEventRecord(e0, s) != hipSuccess) rc = LJMD_EHIP;
+        if (rc == LJMD_OK) rc = ljmd_batch_run(b, steps, nullptr);
+        if (rc == LJMD_OK && hipEventRecord(e1, s) != hipSuccess) rc = LJMD_EHIP;
+        if (rc == LJMD_OK && hipEventSynchronize(e1) != hipSuccess) rc = LJMD_EHIP;
+        if (rc == LJMD_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = LJMD_EHIP;
+        if (rc == LJMD_OK) rc = ljmd_batch_sync_status(b);
+        if (rc == LJMD_OK) rc = ljmd_batch_max_fill(b, &fill);
+        ljmd_batch_destroy(b);
+        if (rc != LJMD_OK) break;
+        const double per = (double)ms / steps;
+        if (out->lanes == 0 || per < best_ms) {
+            best_ms = per;
+            out->lanes = lanes;
+            out->cell_capacity = q.cell_capacity;
+        }
+        out->max_fill = fill > out->max_fill ? fill : out->max_fill;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != LJMD_OK) return rc;
+    out->nbr_capacity = capacity_for(out->max_fill);
     out->ms_per_step = best_ms;
     out->from_cache = 0;
     if (cache_path) cache_store(cache_path, key, *out);

@@ -18,7 +18,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libljmd.so")
 
-ABI_VERSION = 4
+ABI_VERSION = 5
 FP64 = 0
 FP32_DS = 1
 ADJ_STORE_ALL = 1
@@ -100,6 +100,10 @@ SIGNATURES = {
     "ljmd_batch_observables": (C.c_int, [_vp, C.POINTER(C.c_double)]),
     "ljmd_batch_sync_status": (C.c_int, [_vp]),
     "ljmd_batch_last_error": (C.c_char_p, [_vp]),
+    "ljmd_batch_max_fill": (C.c_int, [_vp, C.POINTER(C.c_int32)]),
+    "ljmd_batch_autotune_workspace_size": (C.c_size_t, [C.POINTER(Params), C.POINTER(SystemDesc), C.c_int32]),
+    "ljmd_batch_autotune": (C.c_int, [C.POINTER(Params), C.POINTER(SystemDesc), C.c_int32, _dp, _dp, _ip, _vp,
+                                      C.c_size_t, _vp, C.c_int32, C.c_char_p, C.POINTER(Tuning)]),
     "ljmd_autotune_workspace_size": (C.c_size_t, [C.POINTER(Params)]),
     "ljmd_autotune": (C.c_int, [C.POINTER(Params), _dp, _dp, _ip, _vp, C.c_size_t, _vp, C.c_int32, C.c_char_p,
                                 C.POINTER(Tuning)]),
@@ -425,6 +429,35 @@ def autotune(n: int, box, p, x, v, species, precision: int = FP32_DS, steps: int
             "max_fill": out.max_fill, "ms_per_step": out.ms_per_step, "from_cache": bool(out.from_cache)}
 
 
+def autotune_batch(sizes, edges, p, x, v, species, steps: int = 20, cache_path: str | None = None,
+                   sort_interval: int = 100) -> dict:
+    """ljmd_batch_autotune: time every force-gather shape on the whole batch
+    (systems of the given sizes and cubic box edges, state concatenated as
+    for Batch.set_state) and return the fastest with a list capacity sized
+    from the longest list of any system; cached like autotune()."""
+    import torch
+    sizes = np.asarray(sizes, dtype=np.int64)
+    edges = np.asarray(edges, dtype=np.float64)
+    params = make_params(int(sizes[0]), [edges[0]] * 3, p, FP32_DS, sort_interval)
+    desc = (SystemDesc * len(sizes))(*[SystemDesc(int(n), float(L)) for n, L in zip(sizes, edges)])
+    size = int(lib.ljmd_batch_autotune_workspace_size(C.byref(params), desc, len(sizes)))
+    if size == 0:
+        raise LJMDError(-1, "invalid batch (see ljmd_check_params for each system)")
+    ws = torch.empty(size, dtype=torch.uint8, device="cuda")
+    dev = lambda a, dt: (torch.from_numpy(np.ascontiguousarray(a)) if isinstance(a, np.ndarray) else a).to(
+        device="cuda", dtype=dt).contiguous()
+    xs, vs, sp = dev(x, torch.float64), dev(v, torch.float64), dev(species, torch.int32)
+    out = Tuning()
+    stream = torch.cuda.current_stream()
+    code = lib.ljmd_batch_autotune(C.byref(params), desc, len(sizes), _ptr(xs), _ptr(vs), _ptr(sp),
+                                   C.c_void_p(_ptr(ws)), size, C.c_void_p(stream.cuda_stream), int(steps),
+                                   cache_path.encode() if cache_path else None, C.byref(out))
+    if code != 0:
+        raise LJMDError(code, lib.ljmd_batch_last_error(None).decode())
+    return {"lanes": out.lanes, "nbr_capacity": out.nbr_capacity, "cell_capacity": out.cell_capacity,
+            "max_fill": out.max_fill, "ms_per_step": out.ms_per_step, "from_cache": bool(out.from_cache)}
+
+
 class Batch:
     """Independent one-species systems in cubic boxes, stepped together.
 
@@ -527,6 +560,12 @@ class Batch:
 
     def sync(self):
         self._err(lib.ljmd_batch_sync_status(self.b))
+
+    def max_fill(self) -> int:
+        """Longest neighbour list of any system as built last (synchronises)."""
+        out = C.c_int32(0)
+        self._err(lib.ljmd_batch_max_fill(self.b, C.byref(out)))
+        return int(out.value)
 
 
 # ---- torch.autograd front ends ----------------------------------------------

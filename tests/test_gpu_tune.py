@@ -45,3 +45,31 @@ def test_autotune_times_caches_and_runs(ljmd, tmp_path):
     # Forces of the state the GPU reached, to the FP32 tolerance of
     # test_gpu_parity.py (with its allowance at cutoff ties).
     assert rel_force_err(f, ref, tie_allowance(xh, w.species, w.box, w.params, 1)) <= 2e-5
+
+
+def test_batch_autotune_times_caches_and_runs(ljmd, tmp_path):
+    import numpy as np
+    ws = W.replica_draws(nrep=5)
+    sizes, edges = [w.n for w in ws], [w.box[0] for w in ws]
+    x = np.concatenate([w.x for w in ws])
+    v = np.concatenate([w.v for w in ws])
+    sp = np.concatenate([w.species for w in ws])
+    cache = str(tmp_path / "tune_batch.jsonl")
+    t = ljmd.autotune_batch(sizes, edges, ws[0].params, x, v, sp, steps=10, cache_path=cache)
+    print("tuned batch", t, flush=True)
+    assert t["lanes"] in (1, 2, 4, 8, 16) and t["ms_per_step"] > 0.0 and not t["from_cache"]
+    assert t["max_fill"] > 0 and t["nbr_capacity"] >= t["max_fill"] + 16 and t["nbr_capacity"] % 16 == 0
+    again = ljmd.autotune_batch(sizes, edges, ws[0].params, x, v, sp, steps=10, cache_path=cache)
+    assert again["from_cache"] and again["lanes"] == t["lanes"] and again["nbr_capacity"] == t["nbr_capacity"]
+    b = ljmd.Batch(sizes, edges, ws[0].params, lanes=t["lanes"], nbr_capacity=t["nbr_capacity"])
+    b.set_state(x, v, sp)
+    assert 0 < b.max_fill() <= t["nbr_capacity"]
+    f = b.forces().cpu().numpy()
+    b.sync()
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    for k, w in enumerate(ws):
+        ref, _, _ = oracle.forces_brute(w.x, w.species, w.box, w.params)
+        g = f[off[k]:off[k + 1]]
+        # FP32 pair arithmetic, allowance at cutoff ties as in test_gpu_parity.py.
+        allow = tie_allowance(w.x, w.species, w.box, w.params, 1)
+        assert rel_force_err(g, ref, allow) <= 2e-5, k
