@@ -144,7 +144,12 @@ static double r2_fp64(const double *wi, const double *wj, const double *box) {
  *    evaluated with an error-free product (TwoProduct by fma) in binary32.
  * 3) displacement from the wrapping difference of two q's, converted to
  *    binary32 and scaled by the single-float quantum (float)(L * 2^-32):
- *    one rounding of the product.                                          */
+ *    one rounding of the product.
+ * 4) list membership: r^2 = fma(dz, dz, fma(dy, dy, dx * dx)) in binary32
+ *    and 0 < r^2 < (float) r_L^2. In a cubic box the displacements are the
+ *    converted differences themselves (no scaling), compared with
+ *    (float)(r_L^2 / (L 2^-32)^2), the squared list radius in squared
+ *    quanta computed in FP64 and rounded once.                              */
 void oracle_ds_split(double w, float *hi, float *lo) {
     float h = (float)w;
     *hi = h;
@@ -181,12 +186,20 @@ static float r2_fp32(const uint32_t *qi, const uint32_t *qj, const double *box) 
     return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
 }
 
+/* Step 4 in a cubic box: r^2 in squared quanta. */
+static float r2_fp32_quanta(const uint32_t *qi, const uint32_t *qj) {
+    float dx = (float)(int32_t)(qi[0] - qj[0]);
+    float dy = (float)(int32_t)(qi[1] - qj[1]);
+    float dz = (float)(int32_t)(qi[2] - qj[2]);
+    return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+}
+
 /* Full Verlet lists {j : 0 < r_ij^2 < (rcut_ab + skin)^2} by particle index
  * (a particle is never its own partner, nor is one at exactly its position),
  * built with cell binning (cells of edge >= the largest list radius; a
  * particle's partners then lie in the 27 surrounding cells). With fewer than
  * three cells along an axis every particle is a candidate (plain all-pairs).
- * mode 0: FP64 criterion; mode 1: the FP32 sequence above.
+ * mode 0: FP64 criterion; mode 1: the FP32 sequence above (step 4).
  * cnt[i] = list length; nbr[i*cap + k] = k-th partner (first cap stored).
  * Returns the largest list length (may exceed cap, in which case the lists
  * are truncated and the caller must retry with a larger cap). */
@@ -195,10 +208,12 @@ int32_t oracle_build_lists(int64_t n, const double *x, const int32_t *sp, const 
     double rl_max = 0.0;
     double rl2[4];
     float rl2f[4];
+    const int cubic = box[0] == box[1] && box[1] == box[2];
+    const double quantum = box[0] / 4294967296.0;
     for (int ab = 0; ab < 4; ++ab) {
         double rl = p->rcut[ab] + p->skin;
         rl2[ab] = rl * rl;
-        rl2f[ab] = (float)(rl * rl);
+        rl2f[ab] = cubic ? (float)(rl * rl / (quantum * quantum)) : (float)(rl * rl);
         int used = p->nspecies == 2 || ab == 0;
         if (used && rl > rl_max) rl_max = rl;
     }
@@ -276,7 +291,7 @@ int32_t oracle_build_lists(int64_t n, const double *x, const int32_t *sp, const 
                     double r2 = r2_fp64(w + 3 * i, w + 3 * j, box);
                     in = r2 > 0.0 && r2 < rl2[ab];
                 } else {
-                    float r2 = r2_fp32(q + 3 * i, q + 3 * j, box);
+                    float r2 = cubic ? r2_fp32_quanta(q + 3 * i, q + 3 * j) : r2_fp32(q + 3 * i, q + 3 * j, box);
                     in = r2 > 0.0f && r2 < rl2f[ab];
                 }
                 if (in) {

@@ -45,6 +45,9 @@ struct BoxC {
     // quantum (L 2^-32)^2, and 24 eps / quantum, so that the force kernel can
     // use raw fixed-point differences as displacements.
     float rc2q, sig2q, fq;
+    // Cubic boxes: list radius squared per pair type in squared quanta (the
+    // FP32 list criterion of a cubic box compares raw differences).
+    float rl2q[3];
 };
 
 // Pair constants by symmetric pair type t = a + b (0: AA, 1: AB, 2: BB).

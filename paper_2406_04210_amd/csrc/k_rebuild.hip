@@ -325,6 +325,13 @@ __device__ inline float cand_r2(const int4 &ri, const int4 &rj, const BoxC &box)
     const float dz = (float)(int32_t)((uint32_t)ri.z - (uint32_t)rj.z) * box.qs_hi[2];
     return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
 }
+// Cubic boxes: r^2 in squared quanta from the raw wrapped differences.
+__device__ inline float cand_r2q(const int4 &ri, const int4 &rj) {
+    const float dx = (float)(int32_t)((uint32_t)ri.x - (uint32_t)rj.x);
+    const float dy = (float)(int32_t)((uint32_t)ri.y - (uint32_t)rj.y);
+    const float dz = (float)(int32_t)((uint32_t)ri.z - (uint32_t)rj.z);
+    return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+}
 
 // Verlet lists, candidate-major: one wavefront per home cell. The
 // candidates are the slots of the (up to 27 distinct) cells around the home
@@ -367,7 +374,9 @@ __device__ inline double4 lane_read(const double4 &v, int p) {
 
 // One home cell (local Hilbert rank c of a box whose cells start at c_off in
 // the flattened cell arrays; rank_of and cell_lin are that box's tables).
-template <int PREC, int NS>
+// QC: FP32 criterion of a cubic box, in squared quanta (raw differences
+// against r_L^2 / quantum^2).
+template <int PREC, int NS, bool QC>
 __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &box, const PairC &pc,
                                   const int32_t *rank_of, const int32_t *cell_lin, int64_t c_off, int c,
                                   Ctl *ctl) {
@@ -449,7 +458,7 @@ __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &bo
                 cand[b] = cr[at];
                 cv[b] = cv[b] && (unsigned)CR::index(cand[b]) < (unsigned)g.n;
                 if constexpr (PREC == LJMD_FP32_DS)
-                    thr[b] = cv[b] ? __float_as_uint(pc.rl2f[0]) - 1u : 0u;
+                    thr[b] = cv[b] ? __float_as_uint(QC ? box.rl2q[0] : pc.rl2f[0]) - 1u : 0u;
             }
             for (int p = 0; p < hm; ++p) {
                 const T ri = lane_read(hrec, p);
@@ -471,8 +480,11 @@ __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &bo
                     } else {
                         // 0 < r^2 < r_L^2 as one unsigned compare of the bit
                         // patterns (r^2 >= 0); thr[b] is 0 for empty lanes.
-                        const uint32_t lim = NS == 1 ? thr[b] : (cv[b] ? __float_as_uint(by_type<NS>(tt, pc.rl2f)) - 1u : 0u);
-                        hit = __float_as_uint(cand_r2(ri, cand[b], box)) - 1u < lim;
+                        const uint32_t lim =
+                            NS == 1 ? thr[b]
+                                    : (cv[b] ? __float_as_uint(by_type<NS>(tt, QC ? box.rl2q : pc.rl2f)) - 1u : 0u);
+                        const float r2 = QC ? cand_r2q(ri, cand[b]) : cand_r2(ri, cand[b], box);
+                        hit = __float_as_uint(r2) - 1u < lim;
                     }
                     const unsigned long long mask = __ballot(hit ? 1 : 0);
                     if (mask == 0ull) continue;
@@ -498,7 +510,7 @@ __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &bo
     }
 }
 
-template <int PREC, int NS>
+template <int PREC, int NS, bool QC>
 __global__ __launch_bounds__(kNlWaves * kWave) void k_nlist(State st, Geom g, BoxC box, PairC pc, int cur,
                                                             int64_t step, int forced, float thr2) {
     (void)cur;
@@ -512,7 +524,7 @@ __global__ __launch_bounds__(kNlWaves * kWave) void k_nlist(State st, Geom g, Bo
     const int per = (box.ncell + tw - 1) / tw;
     const int cbeg = gw * per, cend = min(cbeg + per, box.ncell);
     for (int c = cbeg; c < cend; ++c)
-        nlist_cell<PREC, NS>(st, g, box, pc, st.rank_of, st.cell_lin, 0, c, st.ctl);
+        nlist_cell<PREC, NS, QC>(st, g, box, pc, st.rank_of, st.cell_lin, 0, c, st.ctl);
 }
 
 // ---- batches of systems -------------------------------------------------
@@ -626,7 +638,7 @@ __global__ __launch_bounds__(kNlWaves * kWave) void k_batch_nlist(State st, Geom
         const int k = plan_find(bp.wl_coff, count, w);
         const int s = bp.wl_sys[k];
         const SysC &y = sys[s];
-        nlist_cell<LJMD_FP32_DS, 1>(st, g, y.box, pc, st.rank_of + y.c_off, st.cell_lin + y.c_off, y.c_off,
+        nlist_cell<LJMD_FP32_DS, 1, true>(st, g, y.box, pc, st.rank_of + y.c_off, st.cell_lin + y.c_off, y.c_off,
                                      (int)(w - bp.wl_coff[k]), st.ctl + s);
     }
 }
@@ -701,8 +713,12 @@ static void nlist_launch(const Launch &L, int64_t step, int forced) {
     const unsigned ncu = L.g->ncu > 0 ? (unsigned)L.g->ncu : 256u;
     const unsigned cap = ncu * kNlBlocksPerCu;
     const unsigned nb = need < cap ? (need > 0 ? need : 1u) : cap;
-    hipLaunchKernelGGL((k_nlist<PREC, NS>), dim3(nb), dim3(kNlWaves * kWave), 0, L.stream, *L.st, *L.g,
-                       *L.box, *L.pc, L.cur, step, forced, L.dyn->thr2);
+    if (PREC == LJMD_FP32_DS && L.box->cubic)
+        hipLaunchKernelGGL((k_nlist<PREC, NS, PREC == LJMD_FP32_DS>), dim3(nb), dim3(kNlWaves * kWave), 0, L.stream,
+                           *L.st, *L.g, *L.box, *L.pc, L.cur, step, forced, L.dyn->thr2);
+    else
+        hipLaunchKernelGGL((k_nlist<PREC, NS, false>), dim3(nb), dim3(kNlWaves * kWave), 0, L.stream, *L.st,
+                           *L.g, *L.box, *L.pc, L.cur, step, forced, L.dyn->thr2);
 }
 
 hipError_t launch_nlist(const Launch &L, int64_t step, int forced) {

@@ -345,6 +345,7 @@ void fill_quanta(BoxC &b, const PairC &q, double L) {
     b.rc2q = (float)(q.rc2[0] / (qs * qs));
     b.sig2q = (float)(q.sig2[0] / (qs * qs));
     b.fq = (float)(q.eps24[0] / qs);
+    for (int t = 0; t < 3; ++t) b.rl2q[t] = (float)(q.rl2[t] / (qs * qs));
 }
 
 // Timing bracket around a group of launches of one kernel family.

@@ -162,6 +162,27 @@ def test_fp32_list_sequence_matches_fp64_away_from_ties():
             assert abs((d * d).sum() - rl2) < 1e-5 * rl2
 
 
+def test_fp32_list_sequence_noncubic_matches_fp64_away_from_ties():
+    # The scaled-displacement form of the FP32 list test (boxes with unequal
+    # edges) against the FP64 criterion: they differ only at list-radius ties.
+    w = W.config_small()
+    p = w.params
+    rng = np.random.default_rng(11)
+    box = np.array([13.4368, 13.4368, 10.0776])
+    x = rng.uniform(0.0, 1.0, size=(1500, 3)) * box
+    sp = np.zeros(len(x), np.int32)
+    c0, n0 = oracle.build_lists(x, sp, box, p, mode=0)
+    c1, n1 = oracle.build_lists(x, sp, box, p, mode=1)
+    s0, s1 = oracle.neighbor_sets(c0, n0), oracle.neighbor_sets(c1, n1)
+    rl2 = (p.rcut[0] + p.skin) ** 2
+    assert sum(len(a) for a in s0) > 0
+    for i in range(len(x)):
+        for j in s0[i] ^ s1[i]:
+            d = x[i] - x[j]
+            d -= box * np.rint(d / box)
+            assert abs((d * d).sum() - rl2) < 1e-5 * rl2
+
+
 # ---------------------------------------------------------------- P4 ----
 def test_newton_third_law():
     w = W.random_dense(700, 0.9, seed=8, nspecies=2, min_dist=0.8)
