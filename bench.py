@@ -196,6 +196,59 @@ def copy_bandwidth(torch, mib: int = 1024, reps: int = 5):
     return 2.0 * n / (best * 1e-3) / 1e9
 
 
+def time_mixture(ljmd, torch, W, copy_gbs, steps: int = 500, warmup: int = 20):
+    """Binary 80:20 mixture, N = 4,000,000, rho = 1.2: uniform random
+    positions relaxed by 200 steepest-descent steps (largest move 0.05 sigma
+    per step, pair distances clamped at 0.6 sigma_ab), then velocities at
+    T = 0.8 and NVE, FP32 pair math with double-single state, observables
+    every step. Timed: steps NVE steps; then 100 more with per-kernel event
+    brackets for the step kernel's average duration."""
+    w = W.config_mixture()
+    s = ljmd.System(w.n, w.box, w.params, precision=ljmd.FP32_DS, sort_interval=100)
+    s.set_state(w.x, w.v, w.species)
+    s.minimize_sd(200, 0.05, 0.6, record=False)
+    x, _, _ = s.get_state()
+    s.set_state(x, torch.as_tensor(w.v, device="cuda"), torch.as_tensor(w.species, device="cuda"))
+    s.run(warmup)
+    s.sync()
+    obs = torch.empty((steps, ljmd.NOBS), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    code = ljmd.lib.ljmd_run(s.ctx, steps, obs.data_ptr())
+    stop.record(stream)
+    torch.cuda.synchronize()
+    if code != 0:
+        raise ljmd.LJMDError(code, ljmd.last_error(s.ctx))
+    s.sync()
+    ms = start.elapsed_time(stop)
+    o = obs.cpu().numpy()
+    E = (o[:, 0] + o[:, 1]) / w.n
+    s.set_profiling(True)
+    s.run(100, observe=True)
+    s.sync()
+    kt = s.kernel_times()
+    s.set_profiling(False)
+    cnt, _ = s.neighbors(cap=1)
+    mean_list = float(cnt.double().mean().item())
+    step_ms, step_n = kt["step"]
+    avg_s = step_ms * 1e-3 / max(step_n, 1)
+    bpp = algorithmic_bytes_per_particle(ljmd.FP32_DS, mean_list)
+    achieved = bpp * w.n / avg_s / 1e9
+    return {
+        "workload": "binary 80:20 LJ mixture N=4000000, rho=1.2, eps_AB=1.5 sigma_AB=0.8 eps_BB=0.5 "
+                    "sigma_BB=0.88, rc=2.5 sigma_ab, 200 steepest-descent steps then NVE at T=0.8, "
+                    "dt=0.005, FP32 pair math + DS state",
+        "value": w.n * steps / (ms * 1e-3), "unit": "particle-steps/s", "steps": steps,
+        "ms_per_step": ms / steps, "rebuilds_in_timed_steps": int(o[:, 6].sum()),
+        "energy_per_particle_first_last": [float(E[0]), float(E[-1])],
+        "step_kernel_us": avg_s * 1e6, "mean_list_len": mean_list, "bytes_per_particle": bpp,
+        "achieved_gbs": achieved, "frac_of_peak": achieved / HBM_PEAK_GBS,
+        "frac_of_achievable": achieved / copy_gbs,
+    }
+
+
 def time_batch(ljmd, torch, W, steps: int = 1000, warmup: int = 50):
     """Batched replicas: 512 independent one-species LJ systems, N
     log-uniform in [500, 32000] (sum about 3.9 million), rho in [0.7, 1.2],
@@ -254,6 +307,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiable-workload timing")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-replica timing")
+    ap.add_argument("--no-mixture", action="store_true", help="skip the 4M binary-mixture timing")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device (a reference kernel of known "
@@ -312,6 +366,10 @@ def main():
         extra["fp64_value"] = w.n * args.steps / (r64["ms"] * 1e-3)
         extra["fp64_ms_per_step"] = r64["ms"] / args.steps
         print(f"bench: fp64 {r64['ms']:.2f} ms", file=sys.stderr, flush=True)
+
+    if not args.no_mixture:
+        extra["mixture"] = time_mixture(ljmd, torch, W, copy_gbs)
+        print(f"bench: mixture {extra['mixture']['value']:.3e} particle-steps/s", file=sys.stderr, flush=True)
 
     if not args.no_adjoint:
         extra["adjoint"] = time_adjoint(ljmd, torch, W)

@@ -41,10 +41,10 @@ struct BoxC {
     int32_t nc[3];               // cells per axis
     int32_t ncell;
     int32_t cubic;               // all three edges equal: forces may work in quanta
-    // Cubic boxes, species pair AA: r_c^2 and sigma^2 in units of the squared
+    // Cubic boxes, per pair type: r_c^2 and sigma^2 in units of the squared
     // quantum (L 2^-32)^2, and 24 eps / quantum, so that the force kernel can
     // use raw fixed-point differences as displacements.
-    float rc2q, sig2q, fq;
+    float rc2q[3], sig2q[3], fq[3];
     // Cubic boxes: list radius squared per pair type in squared quanta (the
     // FP32 list criterion of a cubic box compares raw differences).
     float rl2q[3];

@@ -308,7 +308,7 @@ __device__ inline T by_type(int t, const T (&a)[3]) {
     if constexpr (NS == 1) {
         return a[0];
     } else {
-        return t == 0 ? a[0] : (t == 1 ? a[1] : a[2]);
+        return (t & 2) ? a[2] : ((t & 1) ? a[1] : a[0]);  // t in {0, 1, 2}
     }
 }
 

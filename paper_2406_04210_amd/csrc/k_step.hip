@@ -76,11 +76,13 @@ __device__ inline void step_housekeeping(const StepArgs &a, const Ctl *ctl, int6
 }
 
 // ---------------------------------------------------------------- FP32 ---
-// Q: one species in a cubic box. Then the pair loop works in quanta: the
-// raw wrapped fixed-point differences are the displacements, r_c^2 and
-// sigma^2 are pre-divided by the squared quantum (exactly, in FP64, before
-// one rounding), and the quantum goes into the final force factor
-// 24 eps / quantum. The lists are padded and every slot holds a valid index,
+// Q: a cubic box. Then the pair loop works in quanta: the raw wrapped
+// fixed-point differences are the displacements, r_c^2 and sigma^2 are
+// pre-divided by the squared quantum (exactly, in FP64, before one
+// rounding), and the quantum goes into the force factor 24 eps / quantum
+// (once per particle with one species, per pair with two). The energy and
+// virial terms are summed per lane in FP32 over the lane's few dozen pairs
+// before the FP64 reductions. The lists are padded and every slot holds a valid index,
 // so the entries the unrolled loop reads past a list are loaded unclamped
 // and skipped.
 //
@@ -119,24 +121,25 @@ __device__ inline void step_ds_body(const StepArgs &a, const BoxC &box, Ctl *ctl
     //   f' = sum s6 (2 s6 - 1) / r^2 * d,  a12 = sum s6^2,  a6 = sum s6,  an = #pairs,
     // and F = 24 eps f', sum phi_s = 4 eps (a12 - a6) - an phi(r_c),
     // sum fs r^2 = 24 eps (2 a12 - a6). With two species every pair carries
-    // its own constants.
-    // Energy and virial terms are summed in FP64 (they feed the FP64
-    // energy/virial reductions); forces are accumulated in FP32.
+    // its own constants. Forces are accumulated in FP32; outside the quanta
+    // loop the energy and virial terms are summed in FP64.
     float fx = 0.f, fy = 0.f, fz = 0.f;
     double e = 0.0, w = 0.0, a12 = 0.0, a6 = 0.0;
     int an = 0;
     const float rc2_1 = a.pc.rc2f[0], sig2_1 = a.pc.sig2f[0];
-    const Tri<float> t_rc2(a.pc.rc2f), t_sig2(a.pc.sig2f), t_eps24(a.pc.eps24f), t_eps4(a.pc.eps4f),
-        t_shift(a.pc.shiftf);
+    const PairRow<float> t_rc2(a.pc.rc2f, ri.w), t_sig2(a.pc.sig2f, ri.w), t_eps24(a.pc.eps24f, ri.w),
+        t_eps4(a.pc.eps4f, ri.w), t_shift(a.pc.shiftf, ri.w);
     const float c2x = box.r2c[0], c2y = box.r2c[1], c2z = box.r2c[2];
     // Four list entries per trip: all index loads, then all record gathers,
     // are in flight before the arithmetic of the first one.
     constexpr int U = 4;
     if constexpr (Q) {
-        static_assert(NS == 1, "quanta path is single-species");
-        const float rc2q = box.rc2q, sig2q = box.sig2q;
+        const float rc2q = box.rc2q[0], sig2q = box.sig2q[0];
+        const PairRow<float> q_rc2(box.rc2q, ri.w), q_sig2(box.sig2q, ri.w), q_f(box.fq, ri.w);
         const char *__restrict__ recb = reinterpret_cast<const char *>(rec);
-        float sa = 0.f, sb = 0.f;  // per lane: sum s6^2 and sum s6 over a few dozen pairs
+        // Per lane over a few dozen pairs, in FP32: one species, sum s6^2 and
+        // sum s6; two species, the pair energies and virials themselves.
+        float sa = 0.f, sb = 0.f;
         // Eight entries per trip keep more of the list stream in flight.
         constexpr int UQ = 8;
         static_assert((size_t)UQ * kWave <= kListPad, "list padding below the unroll depth");
@@ -153,24 +156,37 @@ __device__ inline void step_ds_body(const StepArgs &a, const BoxC &box, Ctl *ctl
                 const float dy = (float)(int32_t)((uint32_t)ri.y - (uint32_t)rr[u].y);
                 const float dz = (float)(int32_t)((uint32_t)ri.z - (uint32_t)rr[u].z);
                 const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                if (m + u < iters && r2 < rc2q) {
+                const int sj = rr[u].w;
+                if (m + u < iters && r2 < (NS == 1 ? rc2q : q_rc2(sj))) {
                     const float ir2 = __builtin_amdgcn_rcpf(r2);
-                    const float s2 = sig2q * ir2;
+                    const float s2 = (NS == 1 ? sig2q : q_sig2(sj)) * ir2;
                     const float s6 = s2 * s2 * s2;
-                    const float t = (s6 * ir2) * fmaf(2.0f, s6, -1.0f);
+                    float t = (s6 * ir2) * fmaf(2.0f, s6, -1.0f);
+                    if constexpr (NS == 2) t *= q_f(sj);
                     fx = fmaf(t, dx, fx);
                     fy = fmaf(t, dy, fy);
                     fz = fmaf(t, dz, fz);
                     if constexpr (OBS) {
-                        sa = fmaf(s6, s6, sa);
-                        sb += s6;
-                        an += 1;
+                        if constexpr (NS == 1) {
+                            sa = fmaf(s6, s6, sa);
+                            sb += s6;
+                            an += 1;
+                        } else {
+                            const float s12 = s6 * s6;
+                            sa += fmaf(t_eps4(sj), s12 - s6, -t_shift(sj));
+                            sb += t_eps24(sj) * fmaf(2.0f, s12, -s6);
+                        }
                     }
                 }
             }
         }
-        a12 = (double)sa;
-        a6 = (double)sb;
+        if constexpr (NS == 1) {
+            a12 = (double)sa;
+            a6 = (double)sb;
+        } else {
+            e = (double)sa;
+            w = (double)sb;
+        }
     } else {
     for (int m = 0; m < iters; m += U) {
         // Indices past the list end are clamped to its last entry, so every
@@ -205,18 +221,18 @@ __device__ inline void step_ds_body(const StepArgs &a, const BoxC &box, Ctl *ctl
                     an += 1;
                 }
             } else {
-                const int tt = ri.w + rj.w;
-                if (r2 < t_rc2(tt)) {
+                const int sj = rj.w;
+                if (r2 < t_rc2(sj)) {
                     const float ir2 = __builtin_amdgcn_rcpf(r2);
-                    const float s2 = t_sig2(tt) * ir2;
+                    const float s2 = t_sig2(sj) * ir2;
                     const float s6 = s2 * s2 * s2;
                     const float s12 = s6 * s6;
-                    const float c24 = t_eps24(tt);
+                    const float c24 = t_eps24(sj);
                     const float fs = c24 * ((s6 * ir2) * fmaf(2.0f, s6, -1.0f));
                     fx = fmaf(fs, dx, fx);
                     fy = fmaf(fs, dy, fy);
                     fz = fmaf(fs, dz, fz);
-                    e += (double)fmaf(t_eps4(tt), s12 - s6, -t_shift(tt));
+                    e += (double)fmaf(t_eps4(sj), s12 - s6, -t_shift(sj));
                     w += (double)(c24 * fmaf(2.0f, s12, -s6));
                 }
             }
@@ -242,7 +258,7 @@ __device__ inline void step_ds_body(const StepArgs &a, const BoxC &box, Ctl *ctl
         }
     }
     if constexpr (NS == 1) {
-        const float c24 = Q ? box.fq : a.pc.eps24f[0];
+        const float c24 = Q ? box.fq[0] : a.pc.eps24f[0];
         fx *= c24;
         fy *= c24;
         fz *= c24;
@@ -349,8 +365,8 @@ __global__ __launch_bounds__(kBlockF64) void k_step_fp64(StepArgs a) {
     const int32_t *__restrict__ nb = st.nbr + chunk * (int64_t)(P * a.g.cap) + lane;
     const int iters = cnt > l ? (cnt - l + LANES - 1) / LANES : 0;
     double fx = 0, fy = 0, fz = 0, e = 0, w = 0;
-    const Tri<double> t_rc2(a.pc.rc2), t_sig2(a.pc.sig2), t_eps24(a.pc.eps24), t_eps4(a.pc.eps4),
-        t_shift(a.pc.shift);
+    const PairRow<double> t_rc2(a.pc.rc2, si), t_sig2(a.pc.sig2, si), t_eps24(a.pc.eps24, si),
+        t_eps4(a.pc.eps4, si), t_shift(a.pc.shift, si);
     constexpr int U = 4;
     for (int m = 0; m < iters; m += U) {
         // Indices past the list end are clamped to its last entry, so every
@@ -369,19 +385,20 @@ __global__ __launch_bounds__(kBlockF64) void k_step_fp64(StepArgs a) {
             const double dy = disp_d(ri.y, rj.y, a.box.L[1], a.box.invL[1]);
             const double dz = disp_d(ri.z, rj.z, a.box.L[2], a.box.invL[2]);
             const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-            const int t = NS == 1 ? 0 : si + (int)rj.w;
-            if (r2 < t_rc2(t)) {
+            const int sj = (int)rj.w;
+            if (r2 < (NS == 1 ? a.pc.rc2[0] : t_rc2(sj))) {
                 // Reciprocal: hardware estimate refined by two Newton steps.
                 double ir2 = __builtin_amdgcn_rcp(r2);
                 ir2 = fma(ir2, fma(-r2, ir2, 1.0), ir2);
                 ir2 = fma(ir2, fma(-r2, ir2, 1.0), ir2);
-                const double s2 = t_sig2(t) * ir2;
+                const double s2 = (NS == 1 ? a.pc.sig2[0] : t_sig2(sj)) * ir2;
                 const double s6 = s2 * s2 * s2;
-                const double fs = t_eps24(t) * s6 * fma(2.0, s6, -1.0) * ir2;
+                const double fs = (NS == 1 ? a.pc.eps24[0] : t_eps24(sj)) * s6 * fma(2.0, s6, -1.0) * ir2;
                 fx = fma(fs, dx, fx);
                 fy = fma(fs, dy, fy);
                 fz = fma(fs, dz, fz);
-                e += fma(t_eps4(t) * s6, s6 - 1.0, -t_shift(t));
+                e += fma((NS == 1 ? a.pc.eps4[0] : t_eps4(sj)) * s6, s6 - 1.0,
+                         -(NS == 1 ? a.pc.shift[0] : t_shift(sj)));
                 w = fma(fs, r2, w);
             }
         }
@@ -572,14 +589,14 @@ hipError_t launch_step(const Launch &L, int64_t step, int forced, int mode, int 
     dim3 grid(step_blocks(*L.g)), block(step_block_threads(L.g->prec));
     const bool ds = L.g->prec == LJMD_FP32_DS;
     const bool two = L.g->nspecies == 2;
-    const bool quanta = ds && !two && L.box->cubic && L.g->n < kQuantaMaxSlots;
+    const bool quanta = ds && L.box->cubic && L.g->n < kQuantaMaxSlots;
     const bool obs = (mode & kObserve) != 0;
 #define STEP(NS, LN)                                                                            \
     do {                                                                                        \
-        if (ds && NS == 1 && quanta && obs)                                                     \
-            hipLaunchKernelGGL((k_step_ds<1, LN, true, true>), grid, block, 0, L.stream, a);    \
-        else if (ds && NS == 1 && quanta)                                                       \
-            hipLaunchKernelGGL((k_step_ds<1, LN, true, false>), grid, block, 0, L.stream, a);   \
+        if (ds && quanta && obs)                                                                \
+            hipLaunchKernelGGL((k_step_ds<NS, LN, true, true>), grid, block, 0, L.stream, a);   \
+        else if (ds && quanta)                                                                  \
+            hipLaunchKernelGGL((k_step_ds<NS, LN, true, false>), grid, block, 0, L.stream, a);  \
         else if (ds)                                                                            \
             hipLaunchKernelGGL((k_step_ds<NS, LN, false, true>), grid, block, 0, L.stream, a);  \
         else                                                                                    \

@@ -339,13 +339,15 @@ void fill_pairs(PairC &q, const ljmd_params &p) {
     }
 }
 
-// Pair-AA constants in units of the quantum of a cubic box of edge L.
+// Pair constants in units of the quantum of a cubic box of edge L.
 void fill_quanta(BoxC &b, const PairC &q, double L) {
     const double qs = L / kTwo32;
-    b.rc2q = (float)(q.rc2[0] / (qs * qs));
-    b.sig2q = (float)(q.sig2[0] / (qs * qs));
-    b.fq = (float)(q.eps24[0] / qs);
-    for (int t = 0; t < 3; ++t) b.rl2q[t] = (float)(q.rl2[t] / (qs * qs));
+    for (int t = 0; t < 3; ++t) {
+        b.rc2q[t] = (float)(q.rc2[t] / (qs * qs));
+        b.sig2q[t] = (float)(q.sig2[t] / (qs * qs));
+        b.fq[t] = (float)(q.eps24[t] / qs);
+        b.rl2q[t] = (float)(q.rl2[t] / (qs * qs));
+    }
 }
 
 // Timing bracket around a group of launches of one kernel family.

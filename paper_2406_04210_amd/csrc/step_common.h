@@ -25,17 +25,20 @@ __device__ inline T by_t(int t, const T (&a)[3]) {
     if constexpr (NS == 1) {
         return a[0];
     } else {
-        return t == 0 ? a[0] : (t == 1 ? a[1] : a[2]);
+        return (t & 2) ? a[2] : ((t & 1) ? a[1] : a[0]);  // t in {0, 1, 2}
     }
 }
 
-// A per-pair-type table held in registers: selecting among loaded values,
-// never indexing the kernel-argument copy (which would place it in scratch).
+// The per-pair-type values (types 0: AA, 1: AB, 2: BB) seen from a particle
+// of species si: partner species 0 gives type si, partner species 1 type
+// si + 1. Picked once per particle, so a pair costs one select on the
+// partner's species (a three-way choice per pair can be compiled into a
+// table lookup in scratch or LDS).
 template <class T>
-struct Tri {
-    T v0, v1, v2;
-    __device__ explicit Tri(const T (&a)[3]) : v0(a[0]), v1(a[1]), v2(a[2]) {}
-    __device__ T operator()(int t) const { return t == 0 ? v0 : (t == 1 ? v1 : v2); }
+struct PairRow {
+    T c0, c1;
+    __device__ PairRow(const T (&a)[3], int si) : c0(si ? a[1] : a[0]), c1(si ? a[2] : a[1]) {}
+    __device__ T operator()(int sj) const { return sj ? c1 : c0; }
 };
 
 template <class T>
