@@ -181,6 +181,37 @@ def test_trajectory_100_steps(ljmd, prec):
     assert o["step"] == 100 and o["rebuilds"] == 1 + int(obs[:, 6].sum())
 
 
+@pytest.mark.parametrize("nspecies", [1, 2])
+def test_observing_steps_does_not_change_the_trajectory(ljmd, nspecies):
+    # Steps whose observables are not reduced skip the energy and virial
+    # terms; positions, velocities and forces are bitwise those of a run that
+    # observes every step, and the last step's observables agree.
+    import torch
+    if nspecies == 1:
+        w = W.config_small()
+    else:
+        w = W.config_mixture(n=3000, seed_index=2)
+    runs = []
+    for observe in (True, False):
+        s = make_system(ljmd, w.x, w.v, w.species, w.box, w.params, FP32)
+        if nspecies == 2:
+            s.minimize_sd(100, 0.05, 0.6, record=False)
+            x, _, _ = s.get_state()
+            s.set_state(x, torch.as_tensor(w.v, device="cuda"), torch.as_tensor(w.species, device="cuda"))
+        s.run(40, observe=observe)
+        s.run(25, observe=observe)
+        x, v, img = s.get_state()
+        f = s.forces()
+        o = s.observables()
+        s.sync()
+        runs.append((x, v, img, f, o))
+    a, b = runs
+    for k in range(4):
+        assert torch.equal(a[k], b[k]), k
+    for key in ("U", "K", "W", "step", "rebuilds"):
+        assert a[4][key] == b[4][key], key
+
+
 @pytest.mark.parametrize("prec", [FP64, FP32])
 def test_split_runs_and_resort_do_not_change_results(ljmd, prec):
     w = W.config_small()
