@@ -24,9 +24,9 @@ constexpr int kNP = 8;           // doubles per partial row: U, W, K, px, py, pz
 
 // Latched device error bits (ctl->flags).
 enum : uint32_t { kErrList = 1u, kErrCell = 2u, kErrNaN = 4u };
-// List slots allocated past the last row: the force loop of one species in a
-// cubic box reads index rows (of 64 entries) up to seven rows past a list
-// without clamping.
+// List slots allocated past the last row: the force loop of a cubic box
+// reads up to one group row (256 entries) past a chunk's lists without
+// clamping.
 constexpr size_t kListPad = 8 * 64;
 
 // Box constants. The fixed-point image coordinate q = round(x * 2^32 / L)
@@ -141,18 +141,27 @@ struct Geom {
 // ------------------------------------------------------------------------
 
 // Chunked, interleaved neighbour-list layout. A wave owns P = 64/lanes
-// particles; entry k of particle i lives at
-//   chunk*(P*cap) + (k/lanes)*64 + (i%P)*lanes + (k%lanes),  chunk = i/P,
-// so the 64 lanes of a wave always read 64 consecutive int32 (256 bytes).
-// lanes is a power of two, so the index is shifts and masks only (this runs
-// once per list entry written).
+// particles; particle i's entry k belongs to lane L = (i%P)*lanes + k%lanes
+// of its chunk as that lane's entry m = k/lanes, and lanes keep their entries
+// in groups of four:
+//   chunk*(P*cap) + (m/4)*256 + L*4 + m%4,   chunk = i/P,
+// so one 16-byte load per lane fetches four consecutive entries and a wave
+// reads 1 KiB contiguous. cap is a multiple of 4*lanes; lanes is a power of
+// two, so the index is shifts and masks only.
 __host__ __device__ inline int64_t nbr_index(int64_t i, int32_t k, int32_t lanes, int32_t cap) {
     const int lg = lanes >= 16 ? 4 : (lanes >= 8 ? 3 : (lanes >= 4 ? 2 : (lanes >= 2 ? 1 : 0)));
     const int pg = 6 - lg;  // log2 of particles per chunk
     const int64_t chunk = i >> pg;
     const int32_t p = (int32_t)(i & ((1 << pg) - 1));
-    return ((chunk * (int64_t)cap) << pg) + ((int64_t)(k >> lg) << 6) + (p << lg) + (k & (lanes - 1));
+    const int32_t m = k >> lg, L = (p << lg) + (k & (lanes - 1));
+    return ((chunk * (int64_t)cap) << pg) + ((int64_t)(m >> 2) << 8) + (L << 2) + (m & 3);
 }
+
+// Entry m of the lane whose entries start at nbl (its chunk's base + 4*L).
+__device__ inline int32_t nb_entry(const int32_t *nbl, int m) { return nbl[((int64_t)(m >> 2) << 8) + (m & 3)]; }
+
+// List capacity granule: whole groups of four entries per lane.
+__host__ __device__ inline int32_t cap_granule(int32_t lanes) { return 4 * lanes > 16 ? 4 * lanes : 16; }
 
 // Blocks are dispatched round-robin over the 8 XCDs of the chip; remap so
 // that each XCD works on one contiguous eighth of the (space-filling-curve

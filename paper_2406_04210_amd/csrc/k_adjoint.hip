@@ -98,7 +98,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_pairs(AdjArgs a) {
     const bool valid = i < a.g.n;
     int cnt = valid ? st.nbr_cnt[i] : 0;
     cnt = cnt < a.g.cap ? cnt : a.g.cap;
-    const int32_t *__restrict__ nb = st.nbr + ((chunk * (int64_t)a.g.cap) << (6 - lg)) + lane;
+    const int32_t *__restrict__ nb = st.nbr + ((chunk * (int64_t)a.g.cap) << (6 - lg)) + 4 * lane;
     const int iters = cnt > l ? (cnt - l + lanes - 1) >> lg : 0;
     Theta th;
     double ox = 0, oy = 0, oz = 0;
@@ -110,11 +110,11 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_pairs(AdjArgs a) {
         const double4 gi = (MODE == kAdjVjp && valid) ? gv[i] : make_double4(0, 0, 0, 0);
         const int si = (int)ri.w;
         for (int m = 0; m < iters; m += U) {
-            // Indices past the list end are clamped to its last entry (every
-            // load stays in bounds); those entries are skipped.
-            int jj[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) jj[u] = nb[(int64_t)(m + u < iters ? m + u : iters - 1) * kWave];
+            // One 16-byte group load per lane: its four entries m .. m+3
+            // (entries past the list end are valid indices and are skipped).
+            static_assert(U == 4, "one entry group per trip");
+            const int4 grp = *reinterpret_cast<const int4 *>(nb + ((int64_t)(m >> 2) << 8));
+            const int jj[U] = {grp.x, grp.y, grp.z, grp.w};
             double4 rr[U], gg[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -166,9 +166,8 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_pairs(AdjArgs a) {
         const float c2x = a.box.r2c[0], c2y = a.box.r2c[1], c2z = a.box.r2c[2];
         float fx = 0.f, fy = 0.f, fz = 0.f;
         for (int m = 0; m < iters; m += U) {
-            int jj[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) jj[u] = nb[(int64_t)(m + u < iters ? m + u : iters - 1) * kWave];
+            const int4 grp = *reinterpret_cast<const int4 *>(nb + ((int64_t)(m >> 2) << 8));
+            const int jj[U] = {grp.x, grp.y, grp.z, grp.w};
             int4 rr[U];
             float4 gg[U];
 #pragma unroll

@@ -466,7 +466,8 @@ __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &bo
                 if ((unsigned)i >= (unsigned)g.n) continue;
                 const int si = CR::species(ri);
                 int k = lane_read(kreg, p);
-                // Entry kk of particle i: row[((kk >> lg) << 6) | (kk & (lanes - 1))].
+                // Entry kk of particle i: lane kk % lanes, its entry m = kk / lanes
+                // at row[(m / 4) * 256 + (kk % lanes) * 4 + m % 4].
                 int32_t *__restrict__ row = st.nbr + nbr_index(i, 0, g.lanes, g.cap);
 #pragma unroll
                 for (int b = 0; b < CH; ++b) {
@@ -491,7 +492,10 @@ __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &bo
                     const uint32_t kk = (uint32_t)k + __builtin_amdgcn_mbcnt_hi(
                                                           (uint32_t)(mask >> 32),
                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-                    if (hit && kk < (uint32_t)g.cap) row[((kk >> lg) << 6) | (kk & (uint32_t)lmask)] = j;
+                    if (hit && kk < (uint32_t)g.cap) {
+                        const uint32_t mm = kk >> lg;
+                        row[((mm >> 2) << 8) + ((kk & (uint32_t)lmask) << 2) + (mm & 3u)] = j;
+                    }
                     k += __popcll(mask);
                 }
                 kreg = lane == p ? k : kreg;

@@ -53,7 +53,7 @@ __global__ __launch_bounds__(kBlock) void k_sd_force(SdArgs sa) {
     }
     int cnt = valid ? st.nbr_cnt[i] : 0;
     cnt = cnt < a.g.cap ? cnt : a.g.cap;
-    const int32_t *__restrict__ nb = st.nbr + ((chunk * (int64_t)a.g.cap) << (6 - lg)) + lane;
+    const int32_t *__restrict__ nb = st.nbr + ((chunk * (int64_t)a.g.cap) << (6 - lg)) + 4 * lane;
     const int iters = cnt > l ? (cnt - l + lanes - 1) >> lg : 0;
     double fxd = 0, fyd = 0, fzd = 0;
     float fxf = 0, fyf = 0, fzf = 0;
@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kBlock) void k_sd_force(SdArgs sa) {
         const double4 ri = valid ? rec[i] : make_double4(0, 0, 0, 0);
         const int si = (int)ri.w;
         for (int m = 0; m < iters; ++m) {
-            const int j = nb[(int64_t)m * kWave];
+            const int j = nb_entry(nb, m);
             const double4 rj = rec[j];
             const double dx = disp_d(ri.x, rj.x, a.box.L[0], a.box.invL[0]);
             const double dy = disp_d(ri.y, rj.y, a.box.L[1], a.box.invL[1]);
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(kBlock) void k_sd_force(SdArgs sa) {
         const int4 *__restrict__ rec = st.recq[a.cur];
         const int4 ri = valid ? rec[i] : make_int4(0, 0, 0, 0);
         for (int m = 0; m < iters; ++m) {
-            const int j = nb[(int64_t)m * kWave];
+            const int j = nb_entry(nb, m);
             const int4 rj = rec[j];
             const float dx = disp_q((uint32_t)ri.x, (uint32_t)rj.x, a.box.qs_hi[0], a.box.qs_lo[0]);
             const float dy = disp_q((uint32_t)ri.y, (uint32_t)rj.y, a.box.qs_hi[1], a.box.qs_lo[1]);

@@ -111,7 +111,7 @@ __device__ inline void step_ds_body(const StepArgs &a, const BoxC &box, Ctl *ctl
     int4 ri = valid ? rec[i] : make_int4(0, 0, 0, 0);
     int cnt = valid ? st.nbr_cnt[i] : 0;
     cnt = cnt < a.g.cap ? cnt : a.g.cap;
-    const int32_t *__restrict__ nb = st.nbr + chunk * (int64_t)(P * a.g.cap) + lane;
+    const int32_t *__restrict__ nb = st.nbr + chunk * (int64_t)(P * a.g.cap) + 4 * lane;
     const int iters = cnt > l ? (cnt - l + LANES - 1) / LANES : 0;
     const float qsx = box.qs_hi[0], qsy = box.qs_hi[1], qsz = box.qs_hi[2];
     const float qlx = box.qs_lo[0], qly = box.qs_lo[1], qlz = box.qs_lo[2];
@@ -140,13 +140,15 @@ __device__ inline void step_ds_body(const StepArgs &a, const BoxC &box, Ctl *ctl
         // Per lane over a few dozen pairs, in FP32: one species, sum s6^2 and
         // sum s6; two species, the pair energies and virials themselves.
         float sa = 0.f, sb = 0.f;
-        // Eight entries per trip keep more of the list stream in flight.
+        // Eight entries per trip (two 16-byte group loads per lane) keep more
+        // of the list stream in flight; groups past a list end read padding
+        // or other lists (valid indices) and are skipped.
         constexpr int UQ = 8;
-        static_assert((size_t)UQ * kWave <= kListPad, "list padding below the unroll depth");
+        static_assert((size_t)4 * kWave <= kListPad, "list padding below the unroll depth");
         for (int m = 0; m < iters; m += UQ) {
-            int jj[UQ];
-#pragma unroll
-            for (int u = 0; u < UQ; ++u) jj[u] = nb[(int64_t)(m + u) * kWave];
+            const int4 g0 = *reinterpret_cast<const int4 *>(nb + ((int64_t)(m >> 2) << 8));
+            const int4 g1 = *reinterpret_cast<const int4 *>(nb + ((int64_t)((m >> 2) + 1) << 8));
+            const int jj[UQ] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
             int4 rr[UQ];
 #pragma unroll
             for (int u = 0; u < UQ; ++u) rr[u] = *reinterpret_cast<const int4 *>(recb + ((uint32_t)jj[u] << 4));
@@ -189,11 +191,11 @@ __device__ inline void step_ds_body(const StepArgs &a, const BoxC &box, Ctl *ctl
         }
     } else {
     for (int m = 0; m < iters; m += U) {
-        // Indices past the list end are clamped to its last entry, so every
-        // load is in bounds; those entries are then skipped.
-        int jj[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) jj[u] = nb[(int64_t)(m + u < iters ? m + u : iters - 1) * kWave];
+        // One 16-byte group load per lane: its four entries m .. m+3 (entries
+        // past the list end are valid indices and are skipped).
+        static_assert(U == 4, "one entry group per trip");
+        const int4 grp = *reinterpret_cast<const int4 *>(nb + ((int64_t)(m >> 2) << 8));
+        const int jj[U] = {grp.x, grp.y, grp.z, grp.w};
         int4 rr[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) rr[u] = rec[jj[u]];
@@ -362,18 +364,18 @@ __global__ __launch_bounds__(kBlockF64) void k_step_fp64(StepArgs a) {
     const int si = (int)ri.w;
     int cnt = valid ? st.nbr_cnt[i] : 0;
     cnt = cnt < a.g.cap ? cnt : a.g.cap;
-    const int32_t *__restrict__ nb = st.nbr + chunk * (int64_t)(P * a.g.cap) + lane;
+    const int32_t *__restrict__ nb = st.nbr + chunk * (int64_t)(P * a.g.cap) + 4 * lane;
     const int iters = cnt > l ? (cnt - l + LANES - 1) / LANES : 0;
     double fx = 0, fy = 0, fz = 0, e = 0, w = 0;
     const PairRow<double> t_rc2(a.pc.rc2, si), t_sig2(a.pc.sig2, si), t_eps24(a.pc.eps24, si),
         t_eps4(a.pc.eps4, si), t_shift(a.pc.shift, si);
     constexpr int U = 4;
     for (int m = 0; m < iters; m += U) {
-        // Indices past the list end are clamped to its last entry, so every
-        // load is in bounds; those entries are then skipped.
-        int jj[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) jj[u] = nb[(int64_t)(m + u < iters ? m + u : iters - 1) * kWave];
+        // One 16-byte group load per lane: its four entries m .. m+3 (entries
+        // past the list end are valid indices and are skipped).
+        static_assert(U == 4, "one entry group per trip");
+        const int4 grp = *reinterpret_cast<const int4 *>(nb + ((int64_t)(m >> 2) << 8));
+        const int jj[U] = {grp.x, grp.y, grp.z, grp.w};
         double4 rr[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) rr[u] = rec[jj[u]];

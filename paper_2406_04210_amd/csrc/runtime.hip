@@ -184,7 +184,9 @@ Plan make_plan(const ljmd_params *p) {
         cap = (int32_t)std::min<double>(c, 4096.0);
         cap = std::min<int64_t>(cap, p->n);
     }
-    pl.cap = std::max<int32_t>(16, round_up(cap, 16));
+    // Measured on MI355X at N=256,000: 2 lanes per particle for FP32, 4 for FP64.
+    pl.lanes = p->lanes != 0 ? p->lanes : (p->precision == LJMD_FP64 ? 4 : 2);
+    pl.cap = std::max<int32_t>(16, round_up(cap, cap_granule(pl.lanes)));
     int32_t cc = p->cell_capacity;
     if (cc == 0) {
         double cellv = vol / pl.ncell;
@@ -194,8 +196,6 @@ Plan make_plan(const ljmd_params *p) {
     }
     pl.cell_cap = std::max<int32_t>(8, round_up(cc, 8));
     if (pl.cell_cap > 768) pl.cell_cap = 768;
-    // Measured on MI355X at N=256,000: 2 lanes per particle for FP32, 4 for FP64.
-    pl.lanes = p->lanes != 0 ? p->lanes : (p->precision == LJMD_FP64 ? 4 : 2);
     const int per_block = (step_block_threads(p->precision) / kWave) * (kWave / pl.lanes);
     pl.max_blocks = (int)((p->n + per_block - 1) / per_block);
     lay_out(pl, p->precision, 1);
@@ -721,7 +721,8 @@ int batch_geom(const ljmd_params *shared, const ljmd_system *ys, int32_t nsys, B
     bg.ntot = in_off;
     bg.ncell = c_off;
     bg.nblocks = b_off;
-    bg.cap = shared->nbr_capacity != 0 ? std::max<int32_t>(16, round_up(shared->nbr_capacity, 16)) : cap;
+    bg.cap = std::max<int32_t>(
+        16, round_up(shared->nbr_capacity != 0 ? shared->nbr_capacity : cap, cap_granule(bg.lanes)));
     bg.cell_cap = shared->cell_capacity != 0 ? std::min<int32_t>(768, std::max<int32_t>(8, round_up(shared->cell_capacity, 8))) : cc;
     bg.sys_of_g16.resize(bg.nslots / 16);
     for (int k = 0; k < nsys; ++k) {
