@@ -35,9 +35,9 @@ HBM_PEAK_GBS = 8000.0
 # 512 MiB copy reads), valid only for the kernel sources they were taken on.
 STEP_KERNEL_SOURCES = ("k_step.hip", "step_common.h", "internal.h")
 STEP_KERNEL_TRAFFIC = {
-    "sources_sha256": "597a8e0ecf337c58f8bcef20657a043e3d67b871f167d1215d14672ce5d79a1a",
-    "fetch_bytes": 2.0 * 54038 * 1024,
-    "write_bytes": 1.0 * 20128 * 1024,
+    "sources_sha256": "8b981b5d9b2d0bdc96aea5733ea5dec507e2077b75c71c85a2c52ce073adbbaf",
+    "fetch_bytes": 2.0 * 54934 * 1024,
+    "write_bytes": 1.0 * 20035 * 1024,
 }
 
 

@@ -434,12 +434,16 @@ __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &bo
             const int nbk = min(CH, (ncand - cb + kWave - 1) / kWave);
             T cand[CH];
             bool cv[CH];
-            uint32_t thr[CH];
+            // FP32 bound of each candidate as bits(r_L^2) - 1 (0 for empty
+            // lanes), for a home particle of species 0 (thr) and, with two
+            // species, of species 1 (thr1).
+            uint32_t thr[CH], thr1[CH];
 #pragma unroll
             for (int b = 0; b < CH; ++b) {
                 cv[b] = false;
                 cand[b] = T{};
                 thr[b] = 0u;
+                thr1[b] = 0u;
                 if (b >= nbk) continue;
                 const int t = cb + b * kWave + lane;
                 // Largest stencil cell s with soff[s] <= t: a fixed 5-step
@@ -457,8 +461,16 @@ __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &bo
                 const int64_t at = cv[b] ? (int64_t)cs * g.cell_cap + e : 0;
                 cand[b] = cr[at];
                 cv[b] = cv[b] && (unsigned)CR::index(cand[b]) < (unsigned)g.n;
-                if constexpr (PREC == LJMD_FP32_DS)
-                    thr[b] = cv[b] ? __float_as_uint(QC ? box.rl2q[0] : pc.rl2f[0]) - 1u : 0u;
+                if constexpr (PREC == LJMD_FP32_DS) {
+                    const float *tab = QC ? box.rl2q : pc.rl2f;
+                    if constexpr (NS == 1) {
+                        thr[b] = cv[b] ? __float_as_uint(tab[0]) - 1u : 0u;
+                    } else {
+                        const bool sj = CR::species(cand[b]) != 0;  // pair type = home species + sj
+                        thr[b] = cv[b] ? __float_as_uint(sj ? tab[1] : tab[0]) - 1u : 0u;
+                        thr1[b] = cv[b] ? __float_as_uint(sj ? tab[2] : tab[1]) - 1u : 0u;
+                    }
+                }
             }
             for (int p = 0; p < hm; ++p) {
                 const T ri = lane_read(hrec, p);
@@ -473,17 +485,15 @@ __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &bo
                 for (int b = 0; b < CH; ++b) {
                     if (b >= nbk) break;
                     const int j = CR::index(cand[b]);
-                    const int tt = NS == 1 ? 0 : si + CR::species(cand[b]);
                     bool hit;
                     if constexpr (PREC == LJMD_FP64) {
+                        const int tt = NS == 1 ? 0 : si + CR::species(cand[b]);
                         const double r2 = cand_r2(ri, cand[b], box);
                         hit = cv[b] && r2 > 0.0 && r2 < by_type<NS>(tt, pc.rl2);
                     } else {
                         // 0 < r^2 < r_L^2 as one unsigned compare of the bit
                         // patterns (r^2 >= 0); thr[b] is 0 for empty lanes.
-                        const uint32_t lim =
-                            NS == 1 ? thr[b]
-                                    : (cv[b] ? __float_as_uint(by_type<NS>(tt, QC ? box.rl2q : pc.rl2f)) - 1u : 0u);
+                        const uint32_t lim = (NS == 2 && si != 0) ? thr1[b] : thr[b];
                         const float r2 = QC ? cand_r2q(ri, cand[b]) : cand_r2(ri, cand[b], box);
                         hit = __float_as_uint(r2) - 1u < lim;
                     }
