@@ -65,6 +65,23 @@ def cases():
     out.append(("random256_2cells", r.x, r.v, r.species, r.box, r.params))
     r = W.random_dense(1500, 1.1, seed=7, nspecies=2, min_dist=0.75)
     out.append(("mixture1500", r.x, r.v, r.species, r.box, r.params))
+    # Unequal box edges (the scaled-displacement paths): the jittered 8^3
+    # lattice cut to 6 of its 8 cells along z, which keeps it periodic; once
+    # with one species and once as an 80:20 mixture.
+    x, L = W.fcc_lattice(8, 0.8442)
+    a = L / 8.0
+    x = x[x[:, 2] < 6.0 * a - 1e-9]
+    box = np.array([L, L, 6.0 * a])
+    rng = np.random.default_rng(12)
+    x = np.ascontiguousarray((x + 0.05 * rng.standard_normal(x.shape)) % box)
+    sp1 = np.zeros(len(x), np.int32)
+    v = W.maxwell_boltzmann(len(x), 1.0, w.params.mass, sp1, rng)
+    out.append(("fcc8x8x6_noncubic", x, v, sp1, box, w.params))
+    pm = W.binary_mixture_params()
+    sp2 = np.ones(len(x), np.int32)
+    sp2[rng.permutation(len(x))[: int(round(0.8 * len(x)))]] = 0
+    v2 = W.maxwell_boltzmann(len(x), 1.0, pm.mass, sp2, rng)
+    out.append(("fcc8x8x6_noncubic_mixture", x, v2, sp2, box, pm))
     return out
 
 
