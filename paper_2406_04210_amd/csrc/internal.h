@@ -75,6 +75,7 @@ struct Ctl {
     int64_t rebuilds;     // list builds since set_state
     unsigned long long fmax[2];  // steepest descent: max |F| (double bits), by iteration parity
     int32_t pad[2];
+    uint32_t nlq[8];      // list-build work queues (next cell), one per XCD; reset before each build
     double last[kNP];     // observables of the last flushed step: U, W, K, px, py, pz, rebuilt, step
 };
 

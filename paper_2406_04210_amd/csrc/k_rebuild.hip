@@ -121,6 +121,7 @@ __global__ __launch_bounds__(kRbBlock) void k_bin(State st, Geom g, BoxC box, in
                                                 int forced, float thr2) {
     if (blockIdx.x == 0 && threadIdx.x == 0) st.ctl->maxd[(step + 1) & 1] = 0u;
     if (!rebuild_due(st.ctl, step, forced, thr2)) return;
+    if (blockIdx.x == 0 && threadIdx.x < 8) st.ctl->nlq[threadIdx.x] = 0u;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.n; i += stride)
         bin_one<PREC>(st, g, box, st.rank_of, 0, cur, i, st.ctl);
@@ -531,14 +532,33 @@ __global__ __launch_bounds__(kNlWaves * kWave) void k_nlist(State st, Geom g, Bo
     if (!rebuild_due(st.ctl, step, forced, thr2)) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) st.ctl->rebuilds += 1;
     const int wv = threadIdx.x >> 6, W = blockDim.x >> 6;
-    // Contiguous runs of Hilbert-ranked cells per wave; each XCD gets one
-    // contiguous share of the box.
     const int tw = gridDim.x * W;
-    const int gw = xcd_remap(blockIdx.x, gridDim.x) * W + wv;
-    const int per = (box.ncell + tw - 1) / tw;
-    const int cbeg = gw * per, cend = min(cbeg + per, box.ncell);
-    for (int c = cbeg; c < cend; ++c)
+    if (box.ncell < 8 * tw) {
+        // A few cells per wave: contiguous runs of Hilbert-ranked cells, each
+        // XCD one contiguous share of the box.
+        const int gw = xcd_remap(blockIdx.x, gridDim.x) * W + wv;
+        const int per = (box.ncell + tw - 1) / tw;
+        const int cbeg = gw * per, cend = min(cbeg + per, box.ncell);
+        for (int c = cbeg; c < cend; ++c)
+            nlist_cell<PREC, NS, QC>(st, g, box, pc, st.rank_of, st.cell_lin, 0, c, st.ctl);
+        return;
+    }
+    // Many cells per wave: each XCD (blocks are dispatched to XCD
+    // blockIdx % 8) owns one contiguous share of the cells and its waves take
+    // the next cell of that share from a queue, since cells differ in
+    // occupancy. With fewer than 8 blocks, each block owns a share. Every
+    // wave leaves once its share is used up.
+    const int nq = gridDim.x < 8 ? (int)gridDim.x : 8;
+    const int q = (int)(blockIdx.x % (unsigned)nq);
+    const int lo = (int)((int64_t)box.ncell * q / nq), hi = (int)((int64_t)box.ncell * (q + 1) / nq);
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        int c = 0;
+        if (lane == 0) c = lo + (int)atomicAdd(&st.ctl->nlq[q], 1u);
+        c = __shfl(c, 0);
+        if (c >= hi) break;
         nlist_cell<PREC, NS, QC>(st, g, box, pc, st.rank_of, st.cell_lin, 0, c, st.ctl);
+    }
 }
 
 // ---- batches of systems -------------------------------------------------
@@ -563,6 +583,7 @@ __global__ __launch_bounds__(1024) void k_batch_plan(State st, const SysC *sys, 
     __shared__ int32_t sn[1024];
     __shared__ int64_t sp[1024], sc[1024];
     const int t = threadIdx.x;
+    if (t < 8) st.ctl->nlq[t] = 0u;  // list-build queues of this step
     const int per = (nsys + 1023) / 1024;
     const int s0 = t * per, s1 = min(s0 + per, nsys);
     int cnt = 0;
@@ -640,15 +661,20 @@ __global__ __launch_bounds__(kRbBlock) void k_batch_canon(State st, Geom g, cons
 
 __global__ __launch_bounds__(kNlWaves * kWave) void k_batch_nlist(State st, Geom g, const SysC *sys, BatchPlan bp,
                                                                   PairC pc) {
-    const int wv = threadIdx.x >> 6, W = blockDim.x >> 6;
     const int count = bp.wl_count[0];
     const int64_t total = bp.wl_coff[count];
-    // Contiguous runs of the flattened cells per wave.
-    const int64_t tw = (int64_t)gridDim.x * W;
-    const int64_t gw = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * W + wv;
-    const int64_t per = (total + tw - 1) / tw;
-    const int64_t cbeg = gw * per, cend = min(cbeg + per, total);
-    for (int64_t w = cbeg; w < cend; ++w) {
+    // The flattened cells of the systems due, split into one contiguous share
+    // per XCD whose waves take the next cell from a queue (as k_nlist; the
+    // queues live in the first system's control words, reset by the plan).
+    const int nq = gridDim.x < 8 ? (int)gridDim.x : 8;
+    const int q = (int)(blockIdx.x % (unsigned)nq);
+    const int64_t lo = total * q / nq, hi = total * (q + 1) / nq;
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        int64_t w = 0;
+        if (lane == 0) w = lo + (int64_t)atomicAdd(&st.ctl->nlq[q], 1u);
+        w = __shfl(w, 0);
+        if (w >= hi) break;
         const int k = plan_find(bp.wl_coff, count, w);
         const int s = bp.wl_sys[k];
         const SysC &y = sys[s];
