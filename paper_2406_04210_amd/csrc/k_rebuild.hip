@@ -357,7 +357,7 @@ struct NlistChunk {
 // Waves per list-build block, and blocks per compute unit when a rebuild is
 // due (the kernel strides over contiguous runs of cells).
 constexpr int kNlWaves = 4;
-constexpr int kNlBlocksPerCu = 4;
+constexpr int kNlBlocksPerCu = 12;
 
 __device__ inline int lane_read(int v, int p) { return __builtin_amdgcn_readlane(v, p); }
 __device__ inline int4 lane_read(const int4 &v, int p) {
