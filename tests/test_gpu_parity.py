@@ -111,6 +111,38 @@ def tie_allowance(x, sp, box, p, prec):
     return out
 
 
+def representation_allowance(x, sp, box, p, chunk=250000):
+    """Per-particle force error the FP32 path's representation admits:
+    sum over partners within the cutoff of sqrt(3) * (L / 2^32) * (|dF/dr| +
+    |F| / r) (pair displacement from 32-bit fixed-point coordinates) plus
+    3e-6 |F| (binary32 pair arithmetic and per-lane sums). Pair forces from
+    the oracle's FP64 lists and the textbook LJ formulas."""
+    x = np.asarray(x, dtype=np.float64)
+    n = len(x)
+    cnt, nbr = oracle.build_lists(x, sp, box, p, mode=0)
+    qs = float(np.max(box)) / 2.0 ** 32
+    src = [0, 1, 3] if p.nspecies == 2 else [0, 0, 0]
+    sig_t = np.array([p.sigma[a] for a in src]); eps_t = np.array([p.eps[a] for a in src])
+    rc_t = np.array([p.rcut[a] for a in src])
+    out = np.zeros(n)
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        c = cnt[a:b]
+        ii = np.repeat(np.arange(a, b), c)
+        jj = nbr[a:b][np.arange(nbr.shape[1])[None, :] < c[:, None]]
+        d = x[ii] - x[jj]
+        d -= box * np.rint(d / box)
+        r = np.sqrt((d * d).sum(axis=1))
+        t = (sp[ii] + sp[jj]) if p.nspecies == 2 else np.zeros(len(ii), dtype=np.int64)
+        u = sig_t[t] / r
+        F = 24.0 * eps_t[t] * (2.0 * u ** 12 - u ** 6) / r
+        dF = 24.0 * eps_t[t] * (-26.0 * u ** 12 + 7.0 * u ** 6) / r ** 2
+        inside = r < rc_t[t]
+        wgt = (math.sqrt(3.0) * qs * (np.abs(dF) + np.abs(F) / r) + 3e-6 * np.abs(F)) * inside
+        out[a:b] += np.bincount(ii - a, weights=wgt, minlength=b - a)
+    return out
+
+
 def rel_force_err(f, g, allowance=None):
     rms = math.sqrt(float((g ** 2).sum(axis=1).mean()))
     scale = np.maximum(np.maximum(np.linalg.norm(g, axis=1), rms), 1.0)
@@ -320,6 +352,57 @@ def test_full_size_forces_and_sampled_lists(ljmd, prec):
     assert np.array_equal(cnt, oc)
     rng = np.random.default_rng(1)
     for i in rng.choice(len(x), 2000, replace=False):
+        assert set(ids[i, : cnt[i]].tolist()) == set(on[i, : oc[i]].tolist())
+
+
+def test_full_size_mixture_after_relaxation(ljmd):
+    # The binary-mixture workload at full size (N = 4,000,000, rho = 1.2) in
+    # the bench's configuration: 200 steepest-descent steps, then the forces
+    # and lists of the relaxed state (two-species quanta kernels; the list
+    # build takes cells from per-XCD queues at this size).
+    import torch
+    w = W.config_mixture()
+    s = make_system(ljmd, w.x, w.v, w.species, w.box, w.params, FP32)
+    s.minimize_sd(200, 0.05, 0.6, record=False)
+    x, _, _ = s.get_state()
+    s.set_state(x, torch.as_tensor(w.v, device="cuda"), torch.as_tensor(w.species, device="cuda"))
+    f = s.forces().cpu().numpy()
+    o = s.observables()
+    cnt, ids = s.neighbors(cap=160)
+    cnt, ids = cnt.cpu().numpy(), ids.cpu().numpy()
+    s.sync()
+    del s
+    xh = x.cpu().numpy()
+    fo, Uo, Wo = oracle.forces(xh, w.species, w.box, w.params)
+    # Per-particle bound: 1e-5 of max(|F_i|, rms |F|, 1), plus what the
+    # representation allows in a dense, relaxed liquid (net forces far below
+    # the pair forces): pair displacements come from 32-bit fixed-point
+    # coordinates (an error up to sqrt(3) L 2^-32 per pair) and each pair
+    # force from ~10 binary32 operations summed over a few dozen pairs per
+    # lane (3e-6 |F_ij|). A particle above it must owe the excess to
+    # partners at a cutoff tie (found by brute force for those few only).
+    rms = math.sqrt(float((fo ** 2).sum(axis=1).mean()))
+    scale = np.maximum(np.maximum(np.linalg.norm(fo, axis=1), rms), 1.0)
+    allow = representation_allowance(xh, w.species, w.box, w.params)
+    err = np.linalg.norm(f - fo, axis=1)
+    over = np.nonzero(err > TOL_F[FP32] * scale + allow)[0]
+    assert len(over) <= 100, len(over)
+    p = w.params
+    for i in over:
+        d = xh - xh[i]
+        d -= w.box * np.rint(d / w.box)
+        r2 = (d * d).sum(axis=1)
+        ab = w.species[i] * 2 + w.species
+        rc = np.asarray(p.rcut)[ab]
+        near = np.nonzero((np.abs(r2 - rc * rc) <= 2e-6 * rc * rc) & (np.arange(len(xh)) != i))[0]
+        tie = sum(1.001 * abs(oracle.pair_fscalar(rc[j] * (1 - 1e-15), int(ab[j]), p)) * rc[j] for j in near)
+        assert err[i] - tie <= TOL_F[FP32] * scale[i] + allow[i], (i, err[i], tie)
+    assert abs(o["U"] - Uo) <= TOL_E[FP32] * abs(Uo)
+    assert abs(o["W"] - Wo) <= TOL_E[FP32] * abs(Wo)
+    oc, on = oracle.build_lists(xh, w.species, w.box, w.params, mode=1, cap=160)
+    assert np.array_equal(cnt, oc)
+    rng = np.random.default_rng(2)
+    for i in rng.choice(len(xh), 2000, replace=False):
         assert set(ids[i, : cnt[i]].tolist()) == set(on[i, : oc[i]].tolist())
 
 
