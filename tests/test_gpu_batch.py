@@ -14,6 +14,7 @@ import pytest
 
 import oracle
 from paper_2406_04210_amd import workloads as W
+from test_gpu_parity import rel_force_err, representation_allowance, tie_allowance
 
 pytestmark = pytest.mark.gpu
 FP32 = 1
@@ -139,3 +140,40 @@ def test_batch_rejects_small_box(ljmd):
     p = W.single_species_params()
     with pytest.raises(ljmd.LJMDError):
         ljmd.Batch([500, 500], [7.5, 4.0], p)      # 4.0 < 2 (r_c + skin)
+
+
+def test_full_batch_sampled_systems(ljmd):
+    # The 512-replica workload at full size (sum N about 3.9 million), in the
+    # bench's launch configuration: 120 steps (a graph-replayed resort period
+    # and eager steps, list builds from per-XCD cell queues), then sampled
+    # systems against single-box runs (bitwise) and the oracle (forces).
+    import torch
+    ws = W.replica_draws(512)
+    b = make_batch(ljmd, ws, sort_interval=100)
+    b.run(120)
+    xb, vb, ib = b.get_state()
+    fb = b.forces()
+    b.sync()
+    off = np.concatenate([[0], np.cumsum([w.n for w in ws])])
+    rng = np.random.default_rng(4)
+    for k in rng.choice(len(ws), 3, replace=False):
+        w = ws[k]
+        s = ljmd.System(w.n, w.box, w.params, precision=FP32, sort_interval=100)
+        s.set_state(w.x, w.v, w.species)
+        s.run(120, observe=False)
+        x, v, img = s.get_state()
+        f = s.forces()
+        s.sync()
+        sl = slice(off[k], off[k + 1])
+        assert torch.equal(x, xb[sl]) and torch.equal(v, vb[sl]) and torch.equal(f, fb[sl]), (k, w.name)
+    fh = fb.cpu().numpy()
+    xh = xb.cpu().numpy()
+    for k in rng.choice(len(ws), 6, replace=False):
+        w = ws[k]
+        sl = slice(off[k], off[k + 1])
+        ref, _, _ = oracle.forces(xh[sl], w.species, w.box, w.params)
+        # The FP32 bound of test_gpu_parity.py: 1e-5 per particle, plus the
+        # cutoff ties and the fixed-point representation allowance.
+        allow = tie_allowance(xh[sl], w.species, w.box, w.params, FP32) + \
+            representation_allowance(xh[sl], w.species, w.box, w.params)
+        assert rel_force_err(fh[sl], ref, allow) <= 1e-5, (k, w.name)
