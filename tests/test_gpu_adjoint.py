@@ -337,3 +337,35 @@ def test_force_matching_energy_loss_autograd(ljmd):
     assert ex <= 1e-9 and ev <= 1e-9
     assert gt[0] == pytest.approx(geo[0], rel=1e-9)
     assert gt[3] == pytest.approx(gso[0], rel=1e-9)
+
+
+def test_full_size_differentiable_workload(ljmd):
+    # The differentiable workload at full size (jittered FCC 40^3, N =
+    # 256,000), FP32 pair math as in the bench: the force VJP and dU/dtheta
+    # at x_0, and the 50-step rollout gradient with a stored state every 10
+    # steps, against the oracle.
+    wl, _, _ = W.jittered_fcc(40)
+    x, v, sp, box, p = wl.x, wl.v, wl.species, wl.box, wl.params
+    s = ljmd.System(len(x), box, p, precision=FP32)
+    s.set_state(x, np.zeros_like(x), sp)
+    rng = np.random.default_rng(44)
+    g = rng.standard_normal(x.shape)
+    gx, gth = s.force_vjp(g)
+    ue = s.energy_grad()
+    s.sync()
+    ox, ge, gs = oracle.force_vjp(x, sp, box, p, g)
+    err = rel_err(gx.cpu().numpy(), ox, vjp_tie_allowance(x, sp, box, p, g, FP32))
+    assert err <= TOL_VJP[FP32], err
+    check_theta(gth.cpu().numpy(), ge, gs, 1, TOL_TH[FP32], "full-size dgF/dtheta")
+    oue, ous = oracle.energy_grad(x, sp, box, p)
+    check_theta(ue.cpu().numpy(), oue, ous, 1, TOL_TH[FP32] * 2, "full-size dU/dtheta")
+    del s
+    lam_x, lam_v = rng.standard_normal(x.shape), rng.standard_normal(x.shape)
+    _, gx0, gv0, gtr = gpu_rollout_grad(ljmd, FP32, x, v, sp, box, p, 50, 10, lam_x, lam_v)
+    rx, rv, re, rs = oracle.vv_adjoint(x, v, sp, box, p, 50, lam_x, lam_v)
+    ex = float(np.abs(gx0 - rx).max() / np.abs(rx).max())
+    ev = float(np.abs(gv0 - rv).max() / np.abs(rv).max())
+    print(f"full-size rollout: rel err x0 {ex:.3e} v0 {ev:.3e}", flush=True)
+    assert ex <= TOL_ROLL[FP32] and ev <= TOL_ROLL[FP32], (ex, ev)
+    for k, ref in ((0, re[0]), (3, rs[0])):
+        assert abs(gtr[k] - ref) <= TOL_ROLL[FP32] * (abs(ref) + 1.0), (k, gtr[k], ref)
