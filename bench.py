@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # 512 MiB copy reads), valid only for the kernel sources they were taken on.
 STEP_KERNEL_SOURCES = ("k_step.hip", "step_common.h", "internal.h")
 STEP_KERNEL_TRAFFIC = {
-    "sources_sha256": "96104006b15e45f43f9b8c134f714d40dfe59bc7edbabca2c88c82a98d47f59e",
+    "sources_sha256": "dc68b77b053a3625119d7fc4b27d54d81214a3869005f1e340946bd091bc0454",
     "fetch_bytes": 2.0 * 54934 * 1024,
     "write_bytes": 1.0 * 20035 * 1024,
 }

@@ -13,8 +13,9 @@
 // wave ever sees a partner that has already moved.
 //
 // Gather geometry: LANES lanes per particle, 64/LANES particles per
-// wavefront; the interleaved list layout makes every list load one 256-byte
-// contiguous read. Each XCD gets a contiguous eighth of the particles.
+// wavefront; in the interleaved list layout a lane's entries come in groups
+// of four, so every list load of a wave is one 1 KiB contiguous read. Each
+// XCD gets a contiguous eighth of the particles.
 #include "batch.h"
 #include "step_common.h"
 
@@ -130,8 +131,8 @@ __device__ inline void step_ds_body(const StepArgs &a, const BoxC &box, Ctl *ctl
     const PairRow<float> t_rc2(a.pc.rc2f, ri.w), t_sig2(a.pc.sig2f, ri.w), t_eps24(a.pc.eps24f, ri.w),
         t_eps4(a.pc.eps4f, ri.w), t_shift(a.pc.shiftf, ri.w);
     const float c2x = box.r2c[0], c2y = box.r2c[1], c2z = box.r2c[2];
-    // Four list entries per trip: all index loads, then all record gathers,
-    // are in flight before the arithmetic of the first one.
+    // Outside the quanta loop: four list entries per trip (one group load),
+    // all record gathers in flight before the arithmetic of the first one.
     constexpr int U = 4;
     if constexpr (Q) {
         const float rc2q = box.rc2q[0], sig2q = box.sig2q[0];
