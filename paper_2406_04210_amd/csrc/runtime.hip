@@ -439,6 +439,27 @@ void *rec_ptr(const ljmd_ctx *c, int which) {
     return c->g.prec == LJMD_FP64 ? (void *)c->st.rec64[which] : (void *)c->st.recq[which];
 }
 
+// Point record buffer `which` at other device memory of the same size (the
+// kernels take the buffers from the state at each launch).
+void set_rec_ptr(ljmd_ctx *c, int which, void *p) {
+    if (c->g.prec == LJMD_FP64)
+        c->st.rec64[which] = (double4 *)p;
+    else
+        c->st.recq[which] = (int4 *)p;
+}
+
+// Puts the context's own record buffers back on restore() and on scope exit.
+struct RecBuffers {
+    ljmd_ctx *c;
+    void *p0, *p1;
+    explicit RecBuffers(ljmd_ctx *ctx) : c(ctx), p0(rec_ptr(ctx, 0)), p1(rec_ptr(ctx, 1)) {}
+    void restore() {
+        set_rec_ptr(c, 0, p0);
+        set_rec_ptr(c, 1, p1);
+    }
+    ~RecBuffers() { restore(); }
+};
+
 struct RunOpts {
     bool force_first = false;   // force the list build of the first step
     bool allow_resort = true;   // space-filling-curve resort every sort_interval steps
@@ -453,9 +474,15 @@ struct RunOpts {
 int run_steps(ljmd_ctx *c, int64_t nsteps, double *obs_dev, const RunOpts &o) {
     hipError_t e;
     const size_t fb = rec_bytes(c->g.prec) * (size_t)c->g.n;
+    // With frames, every step writes its new records straight into the next
+    // frame (the record buffers are pointed there); the buffers are restored
+    // and the last frame copied back at the end.
+    const bool redirect = o.frames && nsteps > 0;
+    RecBuffers own(c);
     if (o.frames && (e = hipMemcpyAsync(o.frames, rec_ptr(c, c->cur), fb, hipMemcpyDeviceToDevice,
                                         c->stream)) != hipSuccess)
         return hip_fail(c, e, "frame copy");
+    if (redirect) set_rec_ptr(c, c->cur ^ 1, o.frames + o.frame_stride);
     Launch L = launcher(c);
     {
         Bracket b(c, 3);
@@ -474,16 +501,14 @@ int run_steps(ljmd_ctx *c, int64_t nsteps, double *obs_dev, const RunOpts &o) {
         const bool last = k == nsteps - 1;
         const bool observe = obs_dev != nullptr || (last && o.final_obs);
         const int mode = kFinalize | (last ? kStoreForce : kIntegrate) | (observe ? kObserve : 0);
+        // Records of step s are frame k + 1; the integrate half writes frame k + 2.
+        if (redirect && !last) set_rec_ptr(c, c->cur ^ 1, o.frames + (size_t)(k + 2) * o.frame_stride);
         L = launcher(c);
         {
             Bracket b(c, 0);
             if ((e = launch_step(L, s, forced, mode, (int)(s % kRing))) != hipSuccess)
                 return hip_fail(c, e, "step");
         }
-        if (o.frames &&
-            (e = hipMemcpyAsync(o.frames + (size_t)(k + 1) * o.frame_stride, rec_ptr(c, c->cur), fb,
-                                hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
-            return hip_fail(c, e, "frame copy");
         if (!last) c->cur ^= 1;
         ++pending;
         if (obs_dev && (pending == kRing || last)) {
@@ -499,6 +524,13 @@ int run_steps(ljmd_ctx *c, int64_t nsteps, double *obs_dev, const RunOpts &o) {
         Bracket b(c, 3);
         if ((e = launch_obs_reduce(L, c->step + nsteps, 1, c->nblocks, nullptr, 0)) != hipSuccess)
             return hip_fail(c, e, "obs");
+    }
+    if (redirect) {
+        void *final_frame = rec_ptr(c, c->cur);
+        own.restore();
+        if ((e = hipMemcpyAsync(rec_ptr(c, c->cur), final_frame, fb, hipMemcpyDeviceToDevice, c->stream)) !=
+            hipSuccess)
+            return hip_fail(c, e, "frame copy");
     }
     c->step += nsteps;
     // Keep the event pool bounded on long profiled runs.
@@ -1153,8 +1185,11 @@ int ljmd_vv_backward(ljmd_ctx *c, const double *lam_x, const double *lam_v, doub
     uint8_t *frames = ws + P.off_frames;
     const int64_t N = P.nsteps;
     const double dt = c->p.dt, h = 0.5 * c->p.dt;
-    const size_t fb = rec_bytes(c->g.prec) * (size_t)c->g.n;
     hipError_t e;
+    // The sweep reads each frame in place (the current record buffer is
+    // pointed at it); the context's buffers come back before every segment's
+    // recompute, at the end and on any error.
+    RecBuffers own(c);
     Launch L = launcher(c);
     if ((e = launch_adjoint_vec(L, kOpGatherById, lam_x, nullptr, lx, nullptr, nullptr, 0.0)) != hipSuccess ||
         (e = launch_adjoint_vec(L, kOpGatherById, lam_v, nullptr, lv, nullptr, nullptr, 0.0)) != hipSuccess)
@@ -1176,6 +1211,7 @@ int ljmd_vv_backward(ljmd_ctx *c, const double *lam_x, const double *lam_v, doub
             c->step = c->adj.step0 + s0 + n;
         } else {
             // Recompute the segment from its stored state, keeping its frames.
+            own.restore();
             if ((r = ckpt_copy(c, ws + P.off_ckpt + (size_t)seg * P.ckpt_stride, false))) return r;
             c->step = c->adj.step0 + s0;
             if ((r = run_steps(c, n, nullptr, o))) return r;
@@ -1193,9 +1229,7 @@ int ljmd_vv_backward(ljmd_ctx *c, const double *lam_x, const double *lam_v, doub
             if (s != N &&
                 (e = launch_adjoint_vec(L, kOpDrift, nullptr, nullptr, lx, lv, nullptr, dt)) != hipSuccess)
                 return hip_fail(c, e, "vv_backward drift");
-            if ((e = hipMemcpyAsync(rec_ptr(c, c->cur), seg_frames + (size_t)j * P.frame_stride, fb,
-                                    hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
-                return hip_fail(c, e, "frame load");
+            set_rec_ptr(c, c->cur, seg_frames + (size_t)j * P.frame_stride);
             if (!forced && (e = launch_frame_disp(L, t)) != hipSuccess)
                 return hip_fail(c, e, "frame displacement");
             if ((r = rebuild_sequence(c, t, forced, false))) return r;
@@ -1214,6 +1248,7 @@ int ljmd_vv_backward(ljmd_ctx *c, const double *lam_x, const double *lam_v, doub
         (e = launch_adjoint_vec(L, kOpScatterById, nullptr, gv0, lv, nullptr, nullptr, 0.0)) != hipSuccess)
         return hip_fail(c, e, "vv_backward scatter");
     // Back to the final state of the rollout, lists as ljmd_vv_forward left them.
+    own.restore();
     int r = ckpt_copy(c, ws + P.off_ckpt + (size_t)P.nseg * P.ckpt_stride, false);
     if (r) return r;
     c->step = c->adj.step0 + N;
