@@ -15,10 +15,10 @@ enum : int { kAdjVjp = 0, kAdjEnergy = 1 };
 enum : int {
     kOpGatherById = 0,   // a[i] = src_id[id[i]]        (FP64 triples by original id)
     kOpScatterById = 1,  // dst_id[id[i]] = a[i]
-    kOpCotangent = 2,    // gvec[i] = b[i] / m_i        (path precision: double4 or float4)
-    kOpDrift = 3,        // b[i] += scale * a[i]
     kOpZero = 4,         // a[i] = 0
     kOpGatherG = 5,      // gvec[i] = src_id[id[i]]     (path precision)
+    kOpDriftCotangent = 6,  // b[i] += scale * a[i] (skipped when scale == 0); gvec[i] = b[i] / m_i
+                            // (path precision: double4 or float4)
 };
 
 // One pair pass over the current lists at the positions in record buffer

@@ -299,27 +299,25 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_vec(VecArgs v) {
             }
             break;
         }
-        case kOpCotangent: {
+        case kOpDriftCotangent: {
+            double4 y = v.b[i];
+            if (v.scale != 0.0) {
+                const double4 x = v.a[i];
+                y.x = fma(v.scale, x.x, y.x);
+                y.y = fma(v.scale, x.y, y.y);
+                y.z = fma(v.scale, x.z, y.z);
+                v.b[i] = y;
+            }
             int sp;
             if constexpr (PREC == LJMD_FP64)
                 sp = (int)v.st.rec64[v.cur][i].w;
             else
                 sp = v.st.recq[v.cur][i].w;
             const double im = 1.0 / by_s(sp, v.dyn.mass);
-            const double4 l = v.b[i];
             if constexpr (PREC == LJMD_FP64)
-                ((double4 *)v.gvec)[i] = make_double4(l.x * im, l.y * im, l.z * im, 0.0);
+                ((double4 *)v.gvec)[i] = make_double4(y.x * im, y.y * im, y.z * im, 0.0);
             else
-                ((float4 *)v.gvec)[i] = make_float4((float)(l.x * im), (float)(l.y * im), (float)(l.z * im), 0.f);
-            break;
-        }
-        case kOpDrift: {
-            const double4 x = v.a[i];
-            double4 y = v.b[i];
-            y.x = fma(v.scale, x.x, y.x);
-            y.y = fma(v.scale, x.y, y.y);
-            y.z = fma(v.scale, x.z, y.z);
-            v.b[i] = y;
+                ((float4 *)v.gvec)[i] = make_float4((float)(y.x * im), (float)(y.y * im), (float)(y.z * im), 0.f);
             break;
         }
         case kOpZero:

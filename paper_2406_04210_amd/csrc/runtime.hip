@@ -1226,16 +1226,16 @@ int ljmd_vv_backward(ljmd_ctx *c, const double *lam_x, const double *lam_v, doub
             const int64_t s = (int64_t)s0 + j;
             const int forced = j == top ? 1 : 0;
             L = launcher(c);
-            if (s != N &&
-                (e = launch_adjoint_vec(L, kOpDrift, nullptr, nullptr, lx, lv, nullptr, dt)) != hipSuccess)
-                return hip_fail(c, e, "vv_backward drift");
             set_rec_ptr(c, c->cur, seg_frames + (size_t)j * P.frame_stride);
+            // Drift (lambda_v += dt lambda_x, none at the last frame) and the
+            // force cotangent lambda_v / m in one pass.
+            if ((e = launch_adjoint_vec(L, kOpDriftCotangent, nullptr, nullptr, lx, lv, gv, s != N ? dt : 0.0)) !=
+                hipSuccess)
+                return hip_fail(c, e, "vv_backward drift and cotangent");
             if (!forced && (e = launch_frame_disp(L, t)) != hipSuccess)
                 return hip_fail(c, e, "frame displacement");
             if ((r = rebuild_sequence(c, t, forced, false))) return r;
             if ((e = launch_adjoint_cells(L, t, forced)) != hipSuccess) return hip_fail(c, e, "clear cells");
-            if ((e = launch_adjoint_vec(L, kOpCotangent, nullptr, nullptr, nullptr, lv, gv, 0.0)) != hipSuccess)
-                return hip_fail(c, e, "vv_backward cotangent");
             const double w = (s == N || s == 0) ? h : dt;
             Bracket b(c, 4);
             if ((e = launch_adjoint_pairs(L, kAdjVjp, gv, lx, w, gtheta, first ? 1 : 0)) != hipSuccess)
