@@ -349,9 +349,11 @@ __device__ inline float cand_r2q(const int4 &ri, const int4 &rj) {
 // live in registers, one per lane; the loop over them reads both with
 // readlane, so the inner loop needs no LDS traffic and no wave barrier,
 // and the list stores are never waited on.
-template <int PREC>
+template <int PREC, bool FILT = false>
 struct NlistChunk {
-    static constexpr int CH = PREC == LJMD_FP64 ? 4 : 8;  // 64-candidate blocks per chunk
+    // 64-candidate blocks per chunk (FILT: chunks reduced before the home
+    // loop; six blocks stay within 88 VGPRs and 6 KiB of LDS per wave)
+    static constexpr int CH = FILT ? 6 : (PREC == LJMD_FP64 ? 4 : 8);
 };
 
 // Waves per list-build block, and blocks per compute unit when a rebuild is
@@ -373,17 +375,56 @@ __device__ inline double4 lane_read(const double4 &v, int p) {
     return make_double4(lane_read(v.x, p), lane_read(v.y, p), lane_read(v.z, p), lane_read(v.w, p));
 }
 
+// Smallest wrapped distance, in quanta along one axis, from coordinate q to
+// any coordinate of [mn, mn + span] (the wrapped difference of two
+// coordinates is their minimum-image displacement).
+__device__ inline uint32_t gap_q(uint32_t q, uint32_t mn, uint32_t span) {
+    const uint32_t t = q - mn;
+    const uint32_t a = t - span, b = 0u - t;
+    return t <= span ? 0u : (a < b ? a : b);
+}
+
+__device__ inline uint32_t wave_min_u32(uint32_t v) {
+    for (int o = 32; o >= 1; o >>= 1) {
+        const uint32_t w = (uint32_t)__shfl_xor((int)v, o);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+__device__ inline uint32_t wave_max_u32(uint32_t v) {
+    for (int o = 32; o >= 1; o >>= 1) {
+        const uint32_t w = (uint32_t)__shfl_xor((int)v, o);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
 // One home cell (local Hilbert rank c of a box whose cells start at c_off in
 // the flattened cell arrays; rank_of and cell_lin are that box's tables).
 // QC: FP32 criterion of a cubic box, in squared quanta (raw differences
 // against r_L^2 / quantum^2).
+//
+// With QC, each chunk of candidates is first reduced to those that can be
+// within r_L of some home particle: a candidate is dropped when its distance
+// to the bounding box of the home particles (in quanta, per axis the wrapped
+// gap to the box's extent) exceeds r_L with a margin of 2^-18 relative,
+// which covers the roundings of both that bound and the exact test (a few
+// units of 2^-24 each), so a dropped candidate fails the exact test for
+// every home particle. The survivors keep their order (ballot compaction
+// through LDS), so the lists are the same entries in the same order as
+// without the reduction. At liquid density the home-particle loop then
+// runs over about three quarters of the blocks (a quarter fewer list
+// stores, an eighth fewer VALU instructions); the kernel is bound by issue
+// latency as much as by VALU throughput, so the chunk is kept small enough
+// for five waves per SIMD.
 template <int PREC, int NS, bool QC>
 __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &box, const PairC &pc,
                                   const int32_t *rank_of, const int32_t *cell_lin, int64_t c_off, int c,
-                                  Ctl *ctl) {
+                                  Ctl *ctl, typename CellRec<PREC>::T *stage) {
     using CR = CellRec<PREC>;
     using T = typename CR::T;
-    constexpr int CH = NlistChunk<PREC>::CH;
+    constexpr bool FILT = PREC == LJMD_FP32_DS && QC;
+    constexpr int CH = NlistChunk<PREC, FILT>::CH;
     const int lane = threadIdx.x & 63;
     const T *__restrict__ cr = cell_recs<PREC>(st);
     const int lg = g.lanes >= 16 ? 4 : (g.lanes >= 8 ? 3 : (g.lanes >= 4 ? 2 : (g.lanes >= 2 ? 1 : 0)));
@@ -422,17 +463,34 @@ __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &bo
     const int home_s = ((-lo[0]) * n3[1] + (-lo[1])) * n3[2] + (-lo[2]);
     const int home = __shfl(scell, home_s);
     const int m = __shfl(scnt, home_s);
+    // Largest list radius of any pair type, with the margin of the reduction.
+    float reach = 0.0f;
+    if constexpr (FILT) {
+        reach = box.rl2q[0];
+        if constexpr (NS == 2) reach = fmaxf(reach, fmaxf(box.rl2q[1], box.rl2q[2]));
+        reach *= 1.0f + 0x1p-18f;
+    }
     for (int h0 = 0; h0 < m; h0 += kWave) {
         const int hm = min(m - h0, kWave);
         // Lane e holds home particle h0 + e and the length of its list so far.
         T hrec;
         if (lane < hm) hrec = cr[(int64_t)home * g.cell_cap + h0 + lane];
         else hrec = T{};
+        uint32_t bmn[3] = {0u, 0u, 0u}, bspan[3] = {0u, 0u, 0u};
+        if constexpr (FILT) {
+            const uint32_t hq[3] = {(uint32_t)hrec.x, (uint32_t)hrec.y, (uint32_t)hrec.z};
+            for (int a = 0; a < 3; ++a) {
+                const uint32_t mn = wave_min_u32(lane < hm ? hq[a] : 0xffffffffu);
+                const uint32_t mx = wave_max_u32(lane < hm ? hq[a] : 0u);
+                bmn[a] = (uint32_t)__builtin_amdgcn_readfirstlane((int)mn);
+                bspan[a] = (uint32_t)__builtin_amdgcn_readfirstlane((int)(mx - mn));
+            }
+        }
         int kreg = 0;
         for (int cb = 0; cb < ncand; cb += CH * kWave) {
             // Blocks of 64 candidates this chunk holds (wave-uniform): the
             // last chunk of a cell is usually short.
-            const int nbk = min(CH, (ncand - cb + kWave - 1) / kWave);
+            int nbk = min(CH, (ncand - cb + kWave - 1) / kWave);
             T cand[CH];
             bool cv[CH];
             // FP32 bound of each candidate as bits(r_L^2) - 1 (0 for empty
@@ -462,7 +520,40 @@ __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &bo
                 const int64_t at = cv[b] ? (int64_t)cs * g.cell_cap + e : 0;
                 cand[b] = cr[at];
                 cv[b] = cv[b] && (unsigned)CR::index(cand[b]) < (unsigned)g.n;
-                if constexpr (PREC == LJMD_FP32_DS) {
+            }
+            if constexpr (FILT) {
+                // Keep the candidates within reach of the home box, in order.
+                int kept = 0;
+#pragma unroll
+                for (int b = 0; b < CH; ++b) {
+                    if (b >= nbk) break;
+                    const float gx = (float)gap_q((uint32_t)cand[b].x, bmn[0], bspan[0]);
+                    const float gy = (float)gap_q((uint32_t)cand[b].y, bmn[1], bspan[1]);
+                    const float gz = (float)gap_q((uint32_t)cand[b].z, bmn[2], bspan[2]);
+                    const bool keep = cv[b] && fmaf(gz, gz, fmaf(gy, gy, gx * gx)) <= reach;
+                    const unsigned long long km = __ballot(keep ? 1 : 0);
+                    const uint32_t pos = __builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, (uint32_t)kept));
+                    if (keep) stage[pos] = cand[b];
+                    kept += __popcll(km);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                nbk = (kept + kWave - 1) / kWave;
+#pragma unroll
+                for (int b = 0; b < CH; ++b) {
+                    if (b >= nbk) break;
+                    const int t = b * kWave + lane;
+                    cv[b] = t < kept;
+                    cand[b] = stage[cv[b] ? t : 0];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+            }
+            if constexpr (PREC == LJMD_FP32_DS) {
+#pragma unroll
+                for (int b = 0; b < CH; ++b) {
+                    if (b >= nbk) break;
                     const float *tab = QC ? box.rl2q : pc.rl2f;
                     if constexpr (NS == 1) {
                         thr[b] = cv[b] ? __float_as_uint(tab[0]) - 1u : 0u;
@@ -480,8 +571,9 @@ __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &bo
                 const int si = CR::species(ri);
                 int k = lane_read(kreg, p);
                 // Entry kk of particle i: lane kk % lanes, its entry m = kk / lanes
-                // at row[(m / 4) * 256 + (kk % lanes) * 4 + m % 4].
-                int32_t *__restrict__ row = st.nbr + nbr_index(i, 0, g.lanes, g.cap);
+                // at row[(m / 4) * 256 + (kk % lanes) * 4 + m % 4], addressed
+                // by a 32-bit byte offset from the particle's row.
+                uint8_t *__restrict__ row = (uint8_t *)(st.nbr + nbr_index(i, 0, g.lanes, g.cap));
 #pragma unroll
                 for (int b = 0; b < CH; ++b) {
                     if (b >= nbk) break;
@@ -500,14 +592,18 @@ __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &bo
                     }
                     const unsigned long long mask = __ballot(hit ? 1 : 0);
                     if (mask == 0ull) continue;
-                    const uint32_t kk = (uint32_t)k + __builtin_amdgcn_mbcnt_hi(
-                                                          (uint32_t)(mask >> 32),
-                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-                    if (hit && kk < (uint32_t)g.cap) {
-                        const uint32_t mm = kk >> lg;
-                        row[((mm >> 2) << 8) + ((kk & (uint32_t)lmask) << 2) + (mm & 3u)] = j;
-                    }
+                    const uint32_t kk = __builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, (uint32_t)k));
                     k += __popcll(mask);
+                    // Entry index (m / 4) * 256 + (kk % lanes) * 4 + m % 4.
+                    const uint32_t e = ((kk >> (lg + 2)) << 8) |
+                                       (((kk & (uint32_t)lmask) << 2) | __builtin_amdgcn_ubfe(kk, lg, 2));
+                    // Past the capacity only the overflow count is kept.
+                    if (__builtin_expect(k <= g.cap, 1)) {
+                        if (hit) *(int32_t *)(row + (e << 2)) = j;
+                    } else if (hit && kk < (uint32_t)g.cap) {
+                        *(int32_t *)(row + (e << 2)) = j;
+                    }
                 }
                 kreg = lane == p ? k : kreg;
             }
@@ -525,6 +621,12 @@ __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &bo
     }
 }
 
+// Per-wave staging for the candidate reduction (FP32 cubic boxes only).
+template <int PREC, bool QC>
+struct NlistStage {
+    static constexpr int kEntries = (PREC == LJMD_FP32_DS && QC) ? kNlWaves * NlistChunk<PREC, true>::CH * kWave : 1;
+};
+
 template <int PREC, int NS, bool QC>
 __global__ __launch_bounds__(kNlWaves * kWave) void k_nlist(State st, Geom g, BoxC box, PairC pc, int cur,
                                                             int64_t step, int forced, float thr2) {
@@ -533,6 +635,10 @@ __global__ __launch_bounds__(kNlWaves * kWave) void k_nlist(State st, Geom g, Bo
     if (blockIdx.x == 0 && threadIdx.x == 0) st.ctl->rebuilds += 1;
     const int wv = threadIdx.x >> 6, W = blockDim.x >> 6;
     const int tw = gridDim.x * W;
+    using T = typename CellRec<PREC>::T;
+    constexpr int SE = NlistStage<PREC, QC>::kEntries;
+    __shared__ T stage_all[SE];
+    T *stage = SE > 1 ? stage_all + wv * (SE / kNlWaves) : stage_all;
     if (box.ncell < 8 * tw) {
         // A few cells per wave: contiguous runs of Hilbert-ranked cells, each
         // XCD one contiguous share of the box.
@@ -540,7 +646,7 @@ __global__ __launch_bounds__(kNlWaves * kWave) void k_nlist(State st, Geom g, Bo
         const int per = (box.ncell + tw - 1) / tw;
         const int cbeg = gw * per, cend = min(cbeg + per, box.ncell);
         for (int c = cbeg; c < cend; ++c)
-            nlist_cell<PREC, NS, QC>(st, g, box, pc, st.rank_of, st.cell_lin, 0, c, st.ctl);
+            nlist_cell<PREC, NS, QC>(st, g, box, pc, st.rank_of, st.cell_lin, 0, c, st.ctl, stage);
         return;
     }
     // Many cells per wave: each XCD (blocks are dispatched to XCD
@@ -557,7 +663,7 @@ __global__ __launch_bounds__(kNlWaves * kWave) void k_nlist(State st, Geom g, Bo
         if (lane == 0) c = lo + (int)atomicAdd(&st.ctl->nlq[q], 1u);
         c = __shfl(c, 0);
         if (c >= hi) break;
-        nlist_cell<PREC, NS, QC>(st, g, box, pc, st.rank_of, st.cell_lin, 0, c, st.ctl);
+        nlist_cell<PREC, NS, QC>(st, g, box, pc, st.rank_of, st.cell_lin, 0, c, st.ctl, stage);
     }
 }
 
@@ -670,6 +776,9 @@ __global__ __launch_bounds__(kNlWaves * kWave) void k_batch_nlist(State st, Geom
     const int q = (int)(blockIdx.x % (unsigned)nq);
     const int64_t lo = total * q / nq, hi = total * (q + 1) / nq;
     const int lane = threadIdx.x & 63;
+    constexpr int SE = NlistStage<LJMD_FP32_DS, true>::kEntries;
+    __shared__ int4 stage_all[SE];
+    int4 *stage = stage_all + (threadIdx.x >> 6) * (SE / kNlWaves);
     for (;;) {
         int64_t w = 0;
         if (lane == 0) w = lo + (int64_t)atomicAdd(&st.ctl->nlq[q], 1u);
@@ -679,7 +788,7 @@ __global__ __launch_bounds__(kNlWaves * kWave) void k_batch_nlist(State st, Geom
         const int s = bp.wl_sys[k];
         const SysC &y = sys[s];
         nlist_cell<LJMD_FP32_DS, 1, true>(st, g, y.box, pc, st.rank_of + y.c_off, st.cell_lin + y.c_off, y.c_off,
-                                     (int)(w - bp.wl_coff[k]), st.ctl + s);
+                                     (int)(w - bp.wl_coff[k]), st.ctl + s, stage);
     }
 }
 

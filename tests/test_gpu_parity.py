@@ -172,6 +172,49 @@ def test_neighbor_sets_exact(ljmd, case, prec):
         assert set(ids[i, : cnt[i]].tolist()) == set(on[i, : oc[i]].tolist()), (name, i)
 
 
+def list_radius_ties(nspecies, seed):
+    """Sparse cubic box of partner pairs at the list radius of their pair type
+    times (1 + delta), delta from -3e-7 to 3e-7 (a few units of the FP32
+    rounding of r^2 in quanta), in random directions. Most cells hold one or
+    two particles, so the candidate reduction of the list build bounds the
+    distance to a home box that is (nearly) a point: the list must still
+    match the oracle pair for pair."""
+    p = W.single_species_params() if nspecies == 1 else W.binary_mixture_params()
+    L = 20.0
+    rng = np.random.default_rng(seed)
+    deltas = [-3e-7, -1e-7, -3e-8, 0.0, 3e-8, 1e-7, 3e-7]
+    xs, sps = [], []
+    for k in range(240):
+        si, sj = (int(rng.integers(0, 2)), int(rng.integers(0, 2))) if nspecies == 2 else (0, 0)
+        ab = si + sj if nspecies == 2 else 0
+        rl = float(p.rcut[[0, 1, 3][ab]] + p.skin)
+        u = rng.standard_normal(3)
+        if k % 3 == 0:
+            u = np.eye(3)[k % 9 // 3] * rng.choice([-1.0, 1.0])  # along an axis
+        u /= np.linalg.norm(u)
+        c = rng.uniform(0.0, L, 3)
+        xs += [c, c + rl * (1.0 + deltas[k % len(deltas)]) * u]
+        sps += [si, sj]
+    x = np.ascontiguousarray(np.array(xs) % L)
+    sp = np.array(sps, np.int32)
+    return x, sp, np.full(3, L), p
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("nspecies", [1, 2])
+def test_neighbor_sets_at_list_radius_ties(ljmd, nspecies, prec):
+    x, sp, box, p = list_radius_ties(nspecies, 40 + nspecies)
+    v = np.zeros_like(x)
+    s = make_system(ljmd, x, v, sp, box, p, prec)
+    cnt, ids = s.neighbors(cap=256)
+    s.sync()
+    cnt, ids = cnt.cpu().numpy(), ids.cpu().numpy()
+    oc, on = oracle.build_lists(x, sp, box, p, mode=0 if prec == FP64 else 1)
+    assert np.array_equal(cnt, oc)
+    for i in range(len(x)):
+        assert set(ids[i, : cnt[i]].tolist()) == set(on[i, : oc[i]].tolist()), i
+
+
 @pytest.mark.parametrize("prec", [FP64, FP32])
 @pytest.mark.parametrize("case", CASES, ids=IDS)
 def test_forces_energy_virial(ljmd, case, prec):
