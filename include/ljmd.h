@@ -236,7 +236,8 @@ int ljmd_energy_grad(ljmd_ctx *ctx, double *gtheta);
 /* Device bytes ljmd_vv_forward needs for nsteps >= 1 steps with a
  * checkpoint every ckpt_every >= 1 steps (0 if an argument is invalid):
  * ceil(nsteps / ckpt_every) + 1 state copies, ckpt_every + 1 position
- * frames for the recompute (nsteps + 1 with LJMD_ADJ_STORE_ALL) and three
+ * frames for the recompute (nsteps + 1 with LJMD_ADJ_STORE_ALL, plus one
+ * int32 rebuild marker per step when ckpt_every <= 64) and three
  * per-particle adjoint vectors. */
 size_t ljmd_adjoint_workspace_size(const ljmd_params *p, int32_t nsteps, int32_t ckpt_every,
                                    int32_t flags);
@@ -260,9 +261,13 @@ int ljmd_vv_forward(ljmd_ctx *ctx, int32_t nsteps, int32_t ckpt_every, int32_t f
  * dynamics (device, 6 float64). Segments are taken last first: each is
  * recomputed from its checkpoint (or read, with LJMD_ADJ_STORE_ALL) and its
  * frames swept backwards with one force VJP per frame (cotangent lam_v / m,
- * weight dt/2 at x_N and x_0, dt between). The lists are built afresh at
- * the first frame of every segment and again whenever a frame is more than
- * skin/2 from the last build. Leaves the context at the final state, as
+ * weight dt/2 at x_N and x_0, dt between). Each segment's sweep starts
+ * from the list of the forward run's last build in it (for segments of at
+ * most 64 steps; longer ones build the list afresh at the first frame), and
+ * lists are built again whenever a frame is more than skin/2 from the last
+ * build. With LJMD_ADJ_STORE_ALL and segments of at most 64 steps the call
+ * waits for the device once (it reads the forward run's rebuild markers).
+ * Leaves the context at the final state, as
  * ljmd_vv_forward did. LJMD_ESTATE if no rollout is recorded or the state
  * changed since. Asynchronous. */
 int ljmd_vv_backward(ljmd_ctx *ctx, const double *lam_x, const double *lam_v, double *gx0,

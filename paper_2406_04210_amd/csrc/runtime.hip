@@ -29,7 +29,14 @@ struct AdjPlan {
     size_t frame_stride = 0;  // bytes of one position frame (record buffer)
     size_t off_frames = 0;    // every + 1 frames (nsteps + 1 when store_all)
     size_t off_lx = 0, off_lv = 0, off_g = 0;
+    // Rebuild markers of every forward step (int32, store_all with segments
+    // of at most kRing steps): where each segment's last list build was.
+    size_t off_marks = 0;
     size_t total = 0;
+    // The sweep starts each segment from the list of the forward run's last
+    // build in it (segments of at most kRing steps, whose markers the step
+    // kernels' ring still holds when the segment ends).
+    bool reuse_lists() const { return every <= kRing; }
 };
 
 // The rollout recorded by the last ljmd_vv_forward.
@@ -578,6 +585,7 @@ AdjPlan adj_plan(const ljmd_params *p, int32_t nsteps, int32_t every, int32_t fl
     a.off_lx = take(sizeof(double4) * (size_t)npad);
     a.off_lv = take(sizeof(double4) * (size_t)npad);
     a.off_g = take(sizeof(double4) * (size_t)npad);
+    if (a.store_all && a.reuse_lists()) a.off_marks = take(sizeof(int32_t) * (size_t)nsteps);
     a.total = off;
     return a;
 }
@@ -1158,7 +1166,20 @@ int ljmd_vv_forward(ljmd_ctx *c, int32_t nsteps, int32_t ckpt_every, int32_t fla
         const int32_t s0 = seg * ckpt_every;
         const int32_t n = std::min(ckpt_every, nsteps - s0);
         if (P.store_all) o.frames = ws + P.off_frames + (size_t)s0 * P.frame_stride;
+        const int64_t sb = c->step + 1;  // step id of the segment's first step
         if ((r = run_steps(c, n, obs_dev ? obs_dev + (size_t)s0 * LJMD_NOBS : nullptr, o))) return r;
+        if (P.store_all && P.reuse_lists()) {
+            // Step sb + k rebuilt (or not) from frame k + 1 of the segment.
+            int32_t *marks = (int32_t *)(ws + P.off_marks) + s0;
+            for (int32_t k = 0; k < n;) {
+                const int slot = (int)((sb + k) % kRing);
+                const int32_t len = std::min(n - k, (int32_t)(kRing - slot));
+                hipError_t e = hipMemcpyAsync(marks + k, c->st.rebuilt + slot, sizeof(int32_t) * (size_t)len,
+                                              hipMemcpyDeviceToDevice, c->stream);
+                if (e != hipSuccess) return hip_fail(c, e, "rebuild markers");
+                k += len;
+            }
+        }
     }
     int r = ckpt_copy(c, ws + P.off_ckpt + (size_t)P.nseg * P.ckpt_stride, true);
     if (r) return r;
@@ -1201,6 +1222,15 @@ int ljmd_vv_backward(ljmd_ctx *c, const double *lam_x, const double *lam_v, doub
     o.frames = frames;
     o.frame_stride = P.frame_stride;
     bool first = true;
+    const bool reuse = P.reuse_lists();
+    std::vector<int32_t> marks;
+    if (reuse && P.store_all) {
+        marks.resize((size_t)N);
+        if ((e = hipMemcpyAsync(marks.data(), ws + P.off_marks, sizeof(int32_t) * (size_t)N, hipMemcpyDeviceToHost,
+                                c->stream)) != hipSuccess ||
+            (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+            return hip_fail(c, e, "vv_backward markers");
+    }
     for (int32_t seg = P.nseg - 1; seg >= 0; --seg) {
         const int32_t s0 = seg * P.every;
         const int32_t n = std::min(P.every, P.nsteps - s0);
@@ -1216,15 +1246,29 @@ int ljmd_vv_backward(ljmd_ctx *c, const double *lam_x, const double *lam_v, doub
             c->step = c->adj.step0 + s0;
             if ((r = run_steps(c, n, nullptr, o))) return r;
         }
-        // Sweep the frames backwards. The lists are built afresh at the first
-        // frame, so the sweep does not depend on how the frames were obtained;
-        // later frames follow the half-skin rule, with step ids that continue
-        // after the segment's end (parity of the displacement words).
+        // Sweep the frames backwards, with step ids that continue after the
+        // segment's end (parity of the displacement words). With reuse, the
+        // sweep starts from the list of the forward run's last build in the
+        // segment: the recompute has just left it in place (and the
+        // displacement word of step id c->step + 1 clear); with stored frames
+        // it is built again from the frame the markers name, so both ways
+        // give the same lists bit for bit. Every frame, the first included,
+        // then follows the half-skin rule. Without reuse the lists are built
+        // afresh at the first frame.
         int64_t t = c->step + 1;
         const int32_t top = seg == P.nseg - 1 ? n : n - 1;
+        if (reuse && P.store_all) {
+            int32_t fl = 1;
+            for (int32_t k = 0; k < n; ++k)
+                if (marks[(size_t)s0 + k]) fl = k + 1;
+            L = launcher(c);
+            set_rec_ptr(c, c->cur, seg_frames + (size_t)fl * P.frame_stride);
+            if ((r = rebuild_sequence(c, t - 1, 1, false))) return r;
+            if ((e = launch_adjoint_cells(L, t - 1, 1)) != hipSuccess) return hip_fail(c, e, "clear cells");
+        }
         for (int32_t j = top; j >= 0; --j, ++t) {
             const int64_t s = (int64_t)s0 + j;
-            const int forced = j == top ? 1 : 0;
+            const int forced = (!reuse && j == top) ? 1 : 0;
             L = launcher(c);
             set_rec_ptr(c, c->cur, seg_frames + (size_t)j * P.frame_stride);
             // Drift (lambda_v += dt lambda_x, none at the last frame) and the

@@ -196,13 +196,17 @@ def test_vv_adjoint_matches_oracle(ljmd, prec, every):
         assert abs(gth[k] - ref) <= TOL_ROLL[prec] * (abs(ref) + 1.0), (k, gth[k], ref)
 
 
+# Segments of up to 64 steps start their sweep from the forward run's last
+# list (stored frames: rebuilt from the frame the markers name); longer ones
+# build the list afresh. Either way both modes agree bit for bit.
 @pytest.mark.parametrize("prec", [FP64, FP32])
-def test_recompute_equals_stored_frames_bitwise(ljmd, prec):
+@pytest.mark.parametrize("nsteps,every", [(25, 10), (70, 66)])
+def test_recompute_equals_stored_frames_bitwise(ljmd, prec, nsteps, every):
     x, v, sp, box, p = rollout_case(51)
     rng = np.random.default_rng(52)
     lam_x, lam_v = rng.standard_normal(x.shape), rng.standard_normal(x.shape)
-    a = gpu_rollout_grad(ljmd, prec, x, v, sp, box, p, 25, 10, lam_x, lam_v, store_all=False)
-    b = gpu_rollout_grad(ljmd, prec, x, v, sp, box, p, 25, 10, lam_x, lam_v, store_all=True)
+    a = gpu_rollout_grad(ljmd, prec, x, v, sp, box, p, nsteps, every, lam_x, lam_v, store_all=False)
+    b = gpu_rollout_grad(ljmd, prec, x, v, sp, box, p, nsteps, every, lam_x, lam_v, store_all=True)
     for u, w in zip(a[1:], b[1:]):
         assert np.array_equal(u, w)
 
