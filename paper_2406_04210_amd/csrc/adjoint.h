@@ -30,6 +30,25 @@ enum : int {
 hipError_t launch_adjoint_pairs(const Launch &L, int mode, const void *gvec, double4 *gx, double weight,
                                 double *gtheta, int init);
 
+// Block rows of the parameter sums of one VJP pass (launch_adjoint_vjp_rows).
+int adjoint_rows(const Geom &g);
+
+// The VJP pass of the reverse sweep: gx[i] += weight * ((dF/dx)^T g)_i, and
+// row b of rows (kNP doubles per block, adjoint_rows(g) blocks) becomes
+// (init ? 0 : row) + weight * that block's parameter sums; the cell counters
+// are cleared if the lists were rebuilt for `step`.
+hipError_t launch_adjoint_vjp_rows(const Launch &L, const void *gvec, double4 *gx, double weight, double *rows,
+                                   int init, int64_t step, int forced);
+
+// gtheta[0..5] = the sums of the block rows, in a fixed order.
+hipError_t launch_adjoint_reduce(const Launch &L, const double *rows, double *gtheta);
+
+// kOpDriftCotangent on (lx, lv, gvec); with disp, the displacement of the
+// positions in record buffer L.cur from the list reference is folded into
+// the rebuild decision of `step` in the same pass.
+hipError_t launch_adjoint_drift(const Launch &L, double4 *lx, double4 *lv, void *gvec, double scale, int64_t step,
+                                int disp);
+
 // Clear the cell counters if the lists were rebuilt for `step` (in a forward
 // run the step kernel does this).
 hipError_t launch_adjoint_cells(const Launch &L, int64_t step, int forced);
@@ -37,8 +56,5 @@ hipError_t launch_adjoint_cells(const Launch &L, int64_t step, int forced);
 hipError_t launch_adjoint_vec(const Launch &L, int op, const double *src_id, double *dst_id, double4 *a,
                               double4 *b, void *gvec, double scale);
 
-// Displacement of the positions in record buffer L.cur from the list
-// reference, folded into the rebuild decision of `step`.
-hipError_t launch_frame_disp(const Launch &L, int64_t step);
 
 }  // namespace ljmd

@@ -42,10 +42,20 @@ struct AdjArgs {
     double c12[3], c6[3];  // (sigma/r_c)^12, (sigma/r_c)^6 per pair type
     double inv_eps[3], inv_sig[3];
     int shifted;
+    // Block partial rows: row = (init ? 0 : row) + rows_weight * block sums.
+    double *rows;
+    double rows_weight;
+    int rows_init;
+    // Cell counters cleared here if the lists were rebuilt for `step`.
+    int clear_cells;
+    int forced;
+    int64_t step;
+    float thr2;
 };
 
-// Six FP64 sums of one block into row `blk` of the partials (stride kNP).
-__device__ inline void block_rows6(const double (&v)[6], double *row) {
+// Six FP64 sums of one block into row `blk` of the partials (stride kNP):
+// row = (init ? 0 : row) + weight * sums.
+__device__ inline void block_rows6(const double (&v)[6], double *row, double weight, int init) {
     constexpr int WPB = kBlock / kWave;
     __shared__ double red[WPB][6];
     double s[6];
@@ -59,7 +69,7 @@ __device__ inline void block_rows6(const double (&v)[6], double *row) {
     if (threadIdx.x < 6) {
         double acc = 0.0;
         for (int w = 0; w < WPB; ++w) acc += red[w][threadIdx.x];
-        row[threadIdx.x] = acc;
+        row[threadIdx.x] = (init ? 0.0 : row[threadIdx.x]) + weight * acc;
     }
 }
 
@@ -96,6 +106,11 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_pairs(AdjArgs a) {
     const int l = lane & (lanes - 1);
     const int64_t i = (chunk << (6 - lg)) + (lane >> lg);
     const bool valid = i < a.g.n;
+    if (a.clear_cells && rebuild_due(st.ctl, a.step, a.forced, a.thr2)) {
+        const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
+        for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < a.box.ncell; c += nthr)
+            st.cell_count[c] = 0;
+    }
     int cnt = valid ? st.nbr_cnt[i] : 0;
     cnt = cnt < a.g.cap ? cnt : a.g.cap;
     const int32_t *__restrict__ nb = st.nbr + ((chunk * (int64_t)a.g.cap) << (6 - lg)) + 4 * lane;
@@ -231,7 +246,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_pairs(AdjArgs a) {
         }
     }
     const double v6[6] = {th.e0, th.e1, th.e2, th.s0, th.s1, th.s2};
-    block_rows6(v6, st.partials + (size_t)blk * kNP);
+    block_rows6(v6, a.rows + (size_t)blk * kNP, a.rows_weight, a.rows_init);
 }
 
 // Clears the cell counters after a rebuild of `step`: the list passes of the
@@ -264,6 +279,40 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_reduce(const double *part, i
     }
 }
 
+// Squared displacement of slot i (record buffer cur) from its list
+// reference, as the bits of a non-negative float (NaN as a quiet NaN).
+template <int PREC>
+__device__ inline uint32_t frame_d2_bits(const State &st, const BoxC &box, int cur, int64_t i) {
+    uint32_t q[3];
+    if constexpr (PREC == LJMD_FP64) {
+        const double4 r = st.rec64[cur][i];
+        q[0] = q_from_d(r.x, box.S[0]);
+        q[1] = q_from_d(r.y, box.S[1]);
+        q[2] = q_from_d(r.z, box.S[2]);
+    } else {
+        const int4 r = st.recq[cur][i];
+        q[0] = (uint32_t)r.x;
+        q[1] = (uint32_t)r.y;
+        q[2] = (uint32_t)r.z;
+    }
+    const int4 xr = st.xref[i];
+    const float dx = disp_q(q[0], (uint32_t)xr.x, box.qs_hi[0], box.qs_lo[0]);
+    const float dy = disp_q(q[1], (uint32_t)xr.y, box.qs_hi[1], box.qs_lo[1]);
+    const float dz = disp_q(q[2], (uint32_t)xr.z, box.qs_hi[2], box.qs_lo[2]);
+    const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    return d2 == d2 ? __float_as_uint(d2) : 0x7fc00000u;
+}
+
+// Every wave folds the largest of its lanes' values into the rebuild word of
+// `step` (only values past the threshold matter).
+__device__ inline void fold_disp(Ctl *ctl, int64_t step, float thr2, uint32_t dm) {
+    dm = wave_max_u(dm);
+    if ((threadIdx.x & 63) == 0 && dm > __float_as_uint(thr2)) {
+        atomicMax(&ctl->maxd[step & 1], dm);
+        if (dm > 0x7f800000u) atomicOr(&ctl->flags, kErrNaN);
+    }
+}
+
 struct VecArgs {
     State st;
     Geom g;
@@ -276,11 +325,17 @@ struct VecArgs {
     double4 *b;
     void *gvec;
     double scale;
+    // kOpDriftCotangent: also fold the frame's displacement from the list
+    // reference into the rebuild word of disp_step (when disp is set).
+    BoxC box;
+    int64_t disp_step;
+    int disp;
 };
 
 template <int PREC>
 __global__ __launch_bounds__(kBlock) void k_adjoint_vec(VecArgs v) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v.disp) fold_disp(v.st.ctl, v.disp_step, v.dyn.thr2, i < v.g.n ? frame_d2_bits<PREC>(v.st, v.box, v.cur, i) : 0u);
     if (i >= v.g.n) return;
     switch (v.op) {
         case kOpGatherById: {
@@ -338,38 +393,6 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_vec(VecArgs v) {
     }
 }
 
-template <int PREC>
-__global__ __launch_bounds__(kBlock) void k_frame_disp(State st, Geom g, BoxC box, int cur, int64_t step,
-                                                       float thr2) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    uint32_t dm = 0u;
-    if (i < g.n) {
-        uint32_t q[3];
-        if constexpr (PREC == LJMD_FP64) {
-            const double4 r = st.rec64[cur][i];
-            q[0] = q_from_d(r.x, box.S[0]);
-            q[1] = q_from_d(r.y, box.S[1]);
-            q[2] = q_from_d(r.z, box.S[2]);
-        } else {
-            const int4 r = st.recq[cur][i];
-            q[0] = (uint32_t)r.x;
-            q[1] = (uint32_t)r.y;
-            q[2] = (uint32_t)r.z;
-        }
-        const int4 xr = st.xref[i];
-        const float dx = disp_q(q[0], (uint32_t)xr.x, box.qs_hi[0], box.qs_lo[0]);
-        const float dy = disp_q(q[1], (uint32_t)xr.y, box.qs_hi[1], box.qs_lo[1]);
-        const float dz = disp_q(q[2], (uint32_t)xr.z, box.qs_hi[2], box.qs_lo[2]);
-        const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        dm = d2 == d2 ? __float_as_uint(d2) : 0x7fc00000u;
-    }
-    dm = wave_max_u(dm);
-    if ((threadIdx.x & 63) == 0 && dm > __float_as_uint(thr2)) {
-        atomicMax(&st.ctl->maxd[step & 1], dm);
-        if (dm > 0x7f800000u) atomicOr(&st.ctl->flags, kErrNaN);
-    }
-}
-
 // ------------------------------------------------------------------------
 static int adjoint_blocks(const Geom &g) {
     const int per_block = (kBlock / kWave) * (kWave / g.lanes);
@@ -384,27 +407,11 @@ static void pairs_launch(int mode, dim3 grid, hipStream_t s, const AdjArgs &aa) 
         hipLaunchKernelGGL((k_adjoint_pairs<PREC, NS, kAdjEnergy>), grid, dim3(kBlock), 0, s, aa);
 }
 
+static AdjArgs pair_args(const Launch &L, const void *gvec, double4 *gx, double weight);
+
 hipError_t launch_adjoint_pairs(const Launch &L, int mode, const void *gvec, double4 *gx, double weight,
                                 double *gtheta, int init) {
-    AdjArgs aa;
-    aa.st = *L.st;
-    aa.g = *L.g;
-    aa.box = *L.box;
-    aa.pc = *L.pc;
-    aa.cur = L.cur;
-    aa.gvec = gvec;
-    aa.gx = gx;
-    aa.weight = weight;
-    aa.shifted = 0;
-    for (int t = 0; t < 3; ++t) {
-        const double c2 = L.pc->sig2[t] / L.pc->rc2[t];
-        aa.c6[t] = c2 * c2 * c2;
-        aa.c12[t] = aa.c6[t] * aa.c6[t];
-        const double eps = L.pc->eps24[t] / 24.0;
-        aa.inv_eps[t] = eps != 0.0 ? 1.0 / eps : 0.0;
-        aa.inv_sig[t] = 1.0 / sqrt(L.pc->sig2[t]);
-        if (L.pc->shift[t] != 0.0) aa.shifted = 1;
-    }
+    AdjArgs aa = pair_args(L, gvec, gx, weight);
     const int nb = adjoint_blocks(*L.g);
     if (nb > L.g->max_blocks) return hipErrorInvalidValue;
     const dim3 grid(nb);
@@ -423,12 +430,74 @@ hipError_t launch_adjoint_pairs(const Launch &L, int mode, const void *gvec, dou
     return hipGetLastError();
 }
 
+int adjoint_rows(const Geom &g) { return adjoint_blocks(g); }
+
+hipError_t launch_adjoint_vjp_rows(const Launch &L, const void *gvec, double4 *gx, double weight, double *rows,
+                                   int init, int64_t step, int forced) {
+    AdjArgs aa = pair_args(L, gvec, gx, weight);
+    aa.rows = rows;
+    aa.rows_weight = weight;
+    aa.rows_init = init;
+    aa.clear_cells = 1;
+    aa.forced = forced;
+    aa.step = step;
+    const int nb = adjoint_blocks(*L.g);
+    const dim3 grid(nb);
+    const bool two = L.g->nspecies == 2;
+    if (L.g->prec == LJMD_FP64) {
+        if (two) pairs_launch<LJMD_FP64, 2>(kAdjVjp, grid, L.stream, aa);
+        else pairs_launch<LJMD_FP64, 1>(kAdjVjp, grid, L.stream, aa);
+    } else {
+        if (two) pairs_launch<LJMD_FP32_DS, 2>(kAdjVjp, grid, L.stream, aa);
+        else pairs_launch<LJMD_FP32_DS, 1>(kAdjVjp, grid, L.stream, aa);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_reduce(const Launch &L, const double *rows, double *gtheta) {
+    hipLaunchKernelGGL(k_adjoint_reduce, dim3(1), dim3(kBlock), 0, L.stream, rows, adjoint_blocks(*L.g), 1.0,
+                       gtheta, 1);
+    return hipGetLastError();
+}
+
+static AdjArgs pair_args(const Launch &L, const void *gvec, double4 *gx, double weight) {
+    AdjArgs aa;
+    aa.st = *L.st;
+    aa.g = *L.g;
+    aa.box = *L.box;
+    aa.pc = *L.pc;
+    aa.cur = L.cur;
+    aa.gvec = gvec;
+    aa.gx = gx;
+    aa.weight = weight;
+    aa.rows = L.st->partials;
+    aa.rows_weight = 1.0;
+    aa.rows_init = 1;
+    aa.clear_cells = 0;
+    aa.forced = 0;
+    aa.step = 0;
+    aa.thr2 = L.dyn->thr2;
+    aa.shifted = 0;
+    for (int t = 0; t < 3; ++t) {
+        const double c2 = L.pc->sig2[t] / L.pc->rc2[t];
+        aa.c6[t] = c2 * c2 * c2;
+        aa.c12[t] = aa.c6[t] * aa.c6[t];
+        const double eps = L.pc->eps24[t] / 24.0;
+        aa.inv_eps[t] = eps != 0.0 ? 1.0 / eps : 0.0;
+        aa.inv_sig[t] = 1.0 / sqrt(L.pc->sig2[t]);
+        if (L.pc->shift[t] != 0.0) aa.shifted = 1;
+    }
+    return aa;
+}
+
 hipError_t launch_adjoint_cells(const Launch &L, int64_t step, int forced) {
     const int nbc = (L.box->ncell + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_adjoint_cells, dim3(nbc < 1024 ? nbc : 1024), dim3(kBlock), 0, L.stream, *L.st,
                        *L.box, step, forced, L.dyn->thr2);
     return hipGetLastError();
 }
+
+static hipError_t vec_launch(const Launch &L, const VecArgs &v);
 
 hipError_t launch_adjoint_vec(const Launch &L, int op, const double *src_id, double *dst_id, double4 *a,
                               double4 *b, void *gvec, double scale) {
@@ -444,22 +513,38 @@ hipError_t launch_adjoint_vec(const Launch &L, int op, const double *src_id, dou
     v.b = b;
     v.gvec = gvec;
     v.scale = scale;
+    v.box = *L.box;
+    v.disp_step = 0;
+    v.disp = 0;
+    return vec_launch(L, v);
+}
+
+hipError_t launch_adjoint_drift(const Launch &L, double4 *lx, double4 *lv, void *gvec, double scale, int64_t step,
+                                int disp) {
+    VecArgs v;
+    v.st = *L.st;
+    v.g = *L.g;
+    v.dyn = *L.dyn;
+    v.cur = L.cur;
+    v.op = kOpDriftCotangent;
+    v.src_id = nullptr;
+    v.dst_id = nullptr;
+    v.a = lx;
+    v.b = lv;
+    v.gvec = gvec;
+    v.scale = scale;
+    v.box = *L.box;
+    v.disp_step = step;
+    v.disp = disp;
+    return vec_launch(L, v);
+}
+
+static hipError_t vec_launch(const Launch &L, const VecArgs &v) {
     const dim3 grid((unsigned)((L.g->n + kBlock - 1) / kBlock));
     if (L.g->prec == LJMD_FP64)
         hipLaunchKernelGGL(k_adjoint_vec<LJMD_FP64>, grid, dim3(kBlock), 0, L.stream, v);
     else
         hipLaunchKernelGGL(k_adjoint_vec<LJMD_FP32_DS>, grid, dim3(kBlock), 0, L.stream, v);
-    return hipGetLastError();
-}
-
-hipError_t launch_frame_disp(const Launch &L, int64_t step) {
-    const dim3 grid((unsigned)((L.g->n + kBlock - 1) / kBlock));
-    if (L.g->prec == LJMD_FP64)
-        hipLaunchKernelGGL(k_frame_disp<LJMD_FP64>, grid, dim3(kBlock), 0, L.stream, *L.st, *L.g, *L.box,
-                           L.cur, step, L.dyn->thr2);
-    else
-        hipLaunchKernelGGL(k_frame_disp<LJMD_FP32_DS>, grid, dim3(kBlock), 0, L.stream, *L.st, *L.g,
-                           *L.box, L.cur, step, L.dyn->thr2);
     return hipGetLastError();
 }
 

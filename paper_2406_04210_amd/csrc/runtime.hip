@@ -32,6 +32,9 @@ struct AdjPlan {
     // Rebuild markers of every forward step (int32, store_all with segments
     // of at most kRing steps): where each segment's last list build was.
     size_t off_marks = 0;
+    // Parameter-gradient rows of the sweep's VJP passes (kNP doubles for
+    // each of at most ceil(n / 64) blocks), summed once at the end.
+    size_t off_rows = 0;
     size_t total = 0;
     // The sweep starts each segment from the list of the forward run's last
     // build in it (segments of at most kRing steps, whose markers the step
@@ -586,6 +589,7 @@ AdjPlan adj_plan(const ljmd_params *p, int32_t nsteps, int32_t every, int32_t fl
     a.off_lv = take(sizeof(double4) * (size_t)npad);
     a.off_g = take(sizeof(double4) * (size_t)npad);
     if (a.store_all && a.reuse_lists()) a.off_marks = take(sizeof(int32_t) * (size_t)nsteps);
+    a.off_rows = take(sizeof(double) * kNP * (size_t)((p->n + 63) / 64));
     a.total = off;
     return a;
 }
@@ -1203,6 +1207,9 @@ int ljmd_vv_backward(ljmd_ctx *c, const double *lam_x, const double *lam_v, doub
     double4 *lx = (double4 *)(ws + P.off_lx);
     double4 *lv = (double4 *)(ws + P.off_lv);
     void *gv = ws + P.off_g;
+    double *rows = (double *)(ws + P.off_rows);
+    if ((size_t)adjoint_rows(c->g) > (size_t)((c->g.n + 63) / 64))
+        return fail(c, LJMD_EINVAL, "internal: adjoint rows");
     uint8_t *frames = ws + P.off_frames;
     const int64_t N = P.nsteps;
     const double dt = c->p.dt, h = 0.5 * c->p.dt;
@@ -1271,23 +1278,23 @@ int ljmd_vv_backward(ljmd_ctx *c, const double *lam_x, const double *lam_v, doub
             const int forced = (!reuse && j == top) ? 1 : 0;
             L = launcher(c);
             set_rec_ptr(c, c->cur, seg_frames + (size_t)j * P.frame_stride);
-            // Drift (lambda_v += dt lambda_x, none at the last frame) and the
-            // force cotangent lambda_v / m in one pass.
-            if ((e = launch_adjoint_vec(L, kOpDriftCotangent, nullptr, nullptr, lx, lv, gv, s != N ? dt : 0.0)) !=
-                hipSuccess)
+            // Drift (lambda_v += dt lambda_x, none at the last frame), the
+            // force cotangent lambda_v / m and, unless the list is forced,
+            // the frame's displacement from the last build, in one pass.
+            if ((e = launch_adjoint_drift(L, lx, lv, gv, s != N ? dt : 0.0, t, forced ? 0 : 1)) != hipSuccess)
                 return hip_fail(c, e, "vv_backward drift and cotangent");
-            if (!forced && (e = launch_frame_disp(L, t)) != hipSuccess)
-                return hip_fail(c, e, "frame displacement");
             if ((r = rebuild_sequence(c, t, forced, false))) return r;
-            if ((e = launch_adjoint_cells(L, t, forced)) != hipSuccess) return hip_fail(c, e, "clear cells");
+            // The VJP pass also clears the cell counters after a rebuild;
+            // its parameter sums stay in block rows until the sweep ends.
             const double w = (s == N || s == 0) ? h : dt;
             Bracket b(c, 4);
-            if ((e = launch_adjoint_pairs(L, kAdjVjp, gv, lx, w, gtheta, first ? 1 : 0)) != hipSuccess)
+            if ((e = launch_adjoint_vjp_rows(L, gv, lx, w, rows, first ? 1 : 0, t, forced)) != hipSuccess)
                 return hip_fail(c, e, "vv_backward vjp");
             first = false;
         }
     }
     L = launcher(c);
+    if ((e = launch_adjoint_reduce(L, rows, gtheta)) != hipSuccess) return hip_fail(c, e, "vv_backward theta");
     if ((e = launch_adjoint_vec(L, kOpScatterById, nullptr, gx0, lx, nullptr, nullptr, 0.0)) != hipSuccess ||
         (e = launch_adjoint_vec(L, kOpScatterById, nullptr, gv0, lv, nullptr, nullptr, 0.0)) != hipSuccess)
         return hip_fail(c, e, "vv_backward scatter");
