@@ -1243,15 +1243,20 @@ int ljmd_vv_backward(ljmd_ctx *c, const double *lam_x, const double *lam_v, doub
         const int32_t n = std::min(P.every, P.nsteps - s0);
         int r;
         uint8_t *seg_frames = frames;
+        // Frames the sweep of this segment reads: 0 .. n for the last
+        // segment, 0 .. n - 1 for the others (their frame n is the next
+        // segment's frame 0, already swept), so the recompute stops one step
+        // short of the segment's end (segments of one step excepted).
+        const int32_t nrec = (seg == P.nseg - 1 || n == 1) ? n : n - 1;
         if (P.store_all) {
             seg_frames = frames + (size_t)s0 * P.frame_stride;
-            c->step = c->adj.step0 + s0 + n;
+            c->step = c->adj.step0 + s0 + nrec;
         } else {
             // Recompute the segment from its stored state, keeping its frames.
             own.restore();
             if ((r = ckpt_copy(c, ws + P.off_ckpt + (size_t)seg * P.ckpt_stride, false))) return r;
             c->step = c->adj.step0 + s0;
-            if ((r = run_steps(c, n, nullptr, o))) return r;
+            if ((r = run_steps(c, nrec, nullptr, o))) return r;
         }
         // Sweep the frames backwards, with step ids that continue after the
         // segment's end (parity of the displacement words). With reuse, the
@@ -1266,7 +1271,7 @@ int ljmd_vv_backward(ljmd_ctx *c, const double *lam_x, const double *lam_v, doub
         const int32_t top = seg == P.nseg - 1 ? n : n - 1;
         if (reuse && P.store_all) {
             int32_t fl = 1;
-            for (int32_t k = 0; k < n; ++k)
+            for (int32_t k = 0; k < nrec; ++k)
                 if (marks[(size_t)s0 + k]) fl = k + 1;
             L = launcher(c);
             set_rec_ptr(c, c->cur, seg_frames + (size_t)fl * P.frame_stride);
