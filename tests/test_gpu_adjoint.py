@@ -196,6 +196,32 @@ def test_vv_adjoint_matches_oracle(ljmd, prec, every):
         assert abs(gth[k] - ref) <= TOL_ROLL[prec] * (abs(ref) + 1.0), (k, gth[k], ref)
 
 
+def rollout_case_mixture(seed=61):
+    x, box = jittered_fcc(5, 0.05, seed)
+    p = W.binary_mixture_params()
+    rng = np.random.default_rng(seed + 1)
+    sp = np.ones(len(x), np.int32)
+    sp[rng.permutation(len(x))[: int(round(0.8 * len(x)))]] = 0
+    v = W.maxwell_boltzmann(len(x), 1.0, p.mass, sp, rng)
+    return x, v, sp, box, p
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_vv_adjoint_mixture_matches_oracle(ljmd, prec):
+    # Two species: per-type parameter sums through the sweep's block rows.
+    x, v, sp, box, p = rollout_case_mixture()
+    rng = np.random.default_rng(63)
+    lam_x, lam_v = rng.standard_normal(x.shape), rng.standard_normal(x.shape)
+    _, gx0, gv0, gth = gpu_rollout_grad(ljmd, prec, x, v, sp, box, p, 20, 7, lam_x, lam_v)
+    ox, ov, ge, gs = oracle.vv_adjoint(x, v, sp, box, p, 20, lam_x, lam_v)
+    ex = float(np.abs(gx0 - ox).max() / np.abs(ox).max())
+    ev = float(np.abs(gv0 - ov).max() / np.abs(ov).max())
+    assert ex <= TOL_ROLL[prec] and ev <= TOL_ROLL[prec], (ex, ev)
+    ref = np.concatenate([ge, gs])
+    for k in range(6):
+        assert abs(gth[k] - ref[k]) <= TOL_ROLL[prec] * (abs(ref[k]) + 1.0), (k, gth[k], ref[k])
+
+
 # Segments of up to 64 steps start their sweep from the forward run's last
 # list (stored frames: rebuilt from the frame the markers name); longer ones
 # build the list afresh. Either way both modes agree bit for bit.
