@@ -65,6 +65,10 @@ def cases():
     out.append(("random256_2cells", r.x, r.v, r.species, r.box, r.params))
     r = W.random_dense(1500, 1.1, seed=7, nspecies=2, min_dist=0.75)
     out.append(("mixture1500", r.x, r.v, r.species, r.box, r.params))
+    # Two cells per axis holding 80 particles each: the list build takes a
+    # cell's home particles in two passes of at most 64.
+    r = W.random_dense(640, 1.1, seed=9, min_dist=0.75)
+    out.append(("random640_80percell", r.x, r.v, r.species, r.box, r.params))
     # Unequal box edges (the scaled-displacement paths): the jittered 8^3
     # lattice cut to 6 of its 8 cells along z, which keeps it periodic; once
     # with one species and once as an 80:20 mixture.
