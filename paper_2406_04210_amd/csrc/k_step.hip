@@ -318,7 +318,9 @@ __device__ inline void step_ds_body(const StepArgs &a, const BoxC &box, Ctl *ctl
             const float ddy = disp_q(qy, (uint32_t)xr.y, qsy, qly);
             const float ddz = disp_q(qz, (uint32_t)xr.z, qsz, qlz);
             const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
-            dm = d2 == d2 ? __float_as_uint(d2) : 0x7fc00000u;
+            // A non-finite position has no fixed-point image: report it as NaN.
+            const bool fin = __builtin_isfinite(x.hi) && __builtin_isfinite(y.hi) && __builtin_isfinite(z.hi);
+            dm = (fin && d2 == d2) ? __float_as_uint(d2) : 0x7fc00000u;
         }
         st.vel_hi[i] = make_float4(vx.hi, vy.hi, vz.hi, 0.f);
         st.vel_lo[i] = make_float4(vx.lo, vy.lo, vz.lo, 0.f);
@@ -459,8 +461,9 @@ __global__ __launch_bounds__(kBlockF64) void k_step_fp64(StepArgs a) {
             const float ddy = disp_q(q_from_d(x[1], a.box.S[1]), (uint32_t)xr.y, a.box.qs_hi[1], a.box.qs_lo[1]);
             const float ddz = disp_q(q_from_d(x[2], a.box.S[2]), (uint32_t)xr.z, a.box.qs_hi[2], a.box.qs_lo[2]);
             const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
-            dm = (d2 == d2 && x[0] == x[0] && x[1] == x[1] && x[2] == x[2]) ? __float_as_uint(d2)
-                                                                          : 0x7fc00000u;
+            dm = (d2 == d2 && __builtin_isfinite(x[0]) && __builtin_isfinite(x[1]) && __builtin_isfinite(x[2]))
+                     ? __float_as_uint(d2)
+                     : 0x7fc00000u;
         }
         st.vel64[i] = v;
         if (a.mode & kStoreForce) st.frc64[i] = make_double4(fx, fy, fz, 0.0);
@@ -507,7 +510,8 @@ __device__ inline void integrate_body(const StepArgs &a, const BoxC &box, Ctl *c
             const float ddy = disp_q(q_from_d(x[1], box.S[1]), (uint32_t)xr.y, box.qs_hi[1], box.qs_lo[1]);
             const float ddz = disp_q(q_from_d(x[2], box.S[2]), (uint32_t)xr.z, box.qs_hi[2], box.qs_lo[2]);
             const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
-            dm = d2 == d2 ? __float_as_uint(d2) : 0x7fc00000u;
+            const bool fin = __builtin_isfinite(x[0]) && __builtin_isfinite(x[1]) && __builtin_isfinite(x[2]);
+            dm = (fin && d2 == d2) ? __float_as_uint(d2) : 0x7fc00000u;
         } else {
             const int4 r = st.recq[a.cur][i];
             const int si = r.w;
@@ -544,7 +548,8 @@ __device__ inline void integrate_body(const StepArgs &a, const BoxC &box, Ctl *c
             const float ddy = disp_q(qy, (uint32_t)xr.y, box.qs_hi[1], box.qs_lo[1]);
             const float ddz = disp_q(qz, (uint32_t)xr.z, box.qs_hi[2], box.qs_lo[2]);
             const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
-            dm = d2 == d2 ? __float_as_uint(d2) : 0x7fc00000u;
+            const bool fin = __builtin_isfinite(x.hi) && __builtin_isfinite(y.hi) && __builtin_isfinite(z.hi);
+            dm = (fin && d2 == d2) ? __float_as_uint(d2) : 0x7fc00000u;
         }
     }
     dm = wave_max_u(dm);

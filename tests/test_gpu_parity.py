@@ -368,6 +368,21 @@ def test_nbr_overflow_is_reported(ljmd):
     assert e.value.code == -5
 
 
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_nonfinite_velocity_is_reported(ljmd, prec):
+    # A NaN velocity gives a NaN position at the next drift, which has no
+    # fixed-point image: the run reports LJMD_ENAN at the next synchronising
+    # call instead of going on with a wrapped coordinate.
+    w = W.config_small()
+    v = w.v.copy()
+    v[17, 1] = np.nan
+    s = make_system(ljmd, w.x, v, w.species, w.box, w.params, prec)
+    with pytest.raises(ljmd.LJMDError) as e:
+        s.run(3)
+        s.sync()
+    assert e.value.code == -6
+
+
 def test_run_before_state_is_rejected(ljmd):
     w = W.config_small()
     s = ljmd.System(w.n, w.box, w.params, precision=FP64)
