@@ -179,7 +179,7 @@ def gpu_rollout_grad(ljmd, prec, x, v, sp, box, p, nsteps, every, lam_x, lam_v, 
 
 
 @pytest.mark.parametrize("prec", [FP64, FP32])
-@pytest.mark.parametrize("every", [10, 7])
+@pytest.mark.parametrize("every", [10, 7, 1])
 def test_vv_adjoint_matches_oracle(ljmd, prec, every):
     x, v, sp, box, p = rollout_case()
     nsteps = 20
@@ -226,7 +226,7 @@ def test_vv_adjoint_mixture_matches_oracle(ljmd, prec):
 # list (stored frames: rebuilt from the frame the markers name); longer ones
 # build the list afresh. Either way both modes agree bit for bit.
 @pytest.mark.parametrize("prec", [FP64, FP32])
-@pytest.mark.parametrize("nsteps,every", [(25, 10), (70, 66)])
+@pytest.mark.parametrize("nsteps,every", [(25, 10), (70, 66), (6, 1)])
 def test_recompute_equals_stored_frames_bitwise(ljmd, prec, nsteps, every):
     x, v, sp, box, p = rollout_case(51)
     rng = np.random.default_rng(52)
