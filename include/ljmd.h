@@ -237,7 +237,7 @@ int ljmd_energy_grad(ljmd_ctx *ctx, double *gtheta);
  * checkpoint every ckpt_every >= 1 steps (0 if an argument is invalid):
  * ceil(nsteps / ckpt_every) + 1 state copies, ckpt_every + 1 position
  * frames for the recompute (nsteps + 1 with LJMD_ADJ_STORE_ALL, plus one
- * int32 rebuild marker per step when ckpt_every <= 64), three
+ * int32 rebuild marker per step when ckpt_every <= 64), four
  * per-particle adjoint vectors and 64 bytes of parameter-gradient sums per
  * 64 particles. */
 size_t ljmd_adjoint_workspace_size(const ljmd_params *p, int32_t nsteps, int32_t ckpt_every,

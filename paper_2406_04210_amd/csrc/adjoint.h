@@ -37,8 +37,20 @@ int adjoint_rows(const Geom &g);
 // row b of rows (kNP doubles per block, adjoint_rows(g) blocks) becomes
 // (init ? 0 : row) + weight * that block's parameter sums; the cell counters
 // are cleared if the lists were rebuilt for `step`.
+// The drift of the next (earlier) frame done by a VJP pass as each slot's
+// gx becomes final: lv += scale * gx (none when scale == 0), gv_next = lv / m
+// (the layout of gvec), and the displacement of that frame's records `rec`
+// from the list reference folded into the rebuild word of `step`. The same
+// arithmetic as kOpDriftCotangent with its displacement check.
+struct AdjNext {
+    double4 *lv;
+    void *gv_next;
+    double scale;
+    int64_t step;
+    const void *rec;
+};
 hipError_t launch_adjoint_vjp_rows(const Launch &L, const void *gvec, double4 *gx, double weight, double *rows,
-                                   int init, int64_t step, int forced);
+                                   int init, int64_t step, int forced, const AdjNext *next);
 
 // gtheta[0..5] = the sums of the block rows, in a fixed order.
 hipError_t launch_adjoint_reduce(const Launch &L, const double *rows, double *gtheta);

@@ -30,6 +30,45 @@
 
 namespace ljmd {
 
+// Squared displacement of slot i (record buffer cur) from its list
+// reference, as the bits of a non-negative float (NaN as a quiet NaN).
+template <int PREC>
+__device__ inline uint32_t frame_d2_rec(const void *recs, const int4 *xref, const BoxC &box, int64_t i) {
+    uint32_t q[3];
+    if constexpr (PREC == LJMD_FP64) {
+        const double4 r = ((const double4 *)recs)[i];
+        q[0] = q_from_d(r.x, box.S[0]);
+        q[1] = q_from_d(r.y, box.S[1]);
+        q[2] = q_from_d(r.z, box.S[2]);
+    } else {
+        const int4 r = ((const int4 *)recs)[i];
+        q[0] = (uint32_t)r.x;
+        q[1] = (uint32_t)r.y;
+        q[2] = (uint32_t)r.z;
+    }
+    const int4 xr = xref[i];
+    const float dx = disp_q(q[0], (uint32_t)xr.x, box.qs_hi[0], box.qs_lo[0]);
+    const float dy = disp_q(q[1], (uint32_t)xr.y, box.qs_hi[1], box.qs_lo[1]);
+    const float dz = disp_q(q[2], (uint32_t)xr.z, box.qs_hi[2], box.qs_lo[2]);
+    const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    return d2 == d2 ? __float_as_uint(d2) : 0x7fc00000u;
+}
+template <int PREC>
+__device__ inline uint32_t frame_d2_bits(const State &st, const BoxC &box, int cur, int64_t i) {
+    const void *recs = PREC == LJMD_FP64 ? (const void *)st.rec64[cur] : (const void *)st.recq[cur];
+    return frame_d2_rec<PREC>(recs, st.xref, box, i);
+}
+
+// Every wave folds the largest of its lanes' values into the rebuild word of
+// `step` (only values past the threshold matter).
+__device__ inline void fold_disp(Ctl *ctl, int64_t step, float thr2, uint32_t dm) {
+    dm = wave_max_u(dm);
+    if ((threadIdx.x & 63) == 0 && dm > __float_as_uint(thr2)) {
+        atomicMax(&ctl->maxd[step & 1], dm);
+        if (dm > 0x7f800000u) atomicOr(&ctl->flags, kErrNaN);
+    }
+}
+
 struct AdjArgs {
     State st;
     Geom g;
@@ -51,6 +90,18 @@ struct AdjArgs {
     int forced;
     int64_t step;
     float thr2;
+    // Reverse sweep (next set): once a slot's gx is final, the drift and
+    // cotangent of the next (earlier) frame for that slot -- lv += next_scale
+    // * gx (skipped when next_scale == 0), gv_next = lv / m -- and that
+    // frame's displacement (records next_rec) folded into the rebuild word of
+    // next_step.
+    int next;
+    double4 *lv;
+    void *gv_next;
+    double next_scale;
+    int64_t next_step;
+    const void *next_rec;
+    double mass[2];
 };
 
 // Six FP64 sums of one block into row `blk` of the partials (stride kNP):
@@ -237,13 +288,34 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_pairs(AdjArgs a) {
             oy += __shfl_xor(oy, o);
             oz += __shfl_xor(oz, o);
         }
+        uint32_t dnext = 0u;
         if (valid && l == 0) {
             double4 acc = a.gx[i];
             acc.x = fma(a.weight, ox, acc.x);
             acc.y = fma(a.weight, oy, acc.y);
             acc.z = fma(a.weight, oz, acc.z);
             a.gx[i] = acc;
+            if (a.next) {
+                // The same operations as kOpDriftCotangent for this slot.
+                double4 y = a.lv[i];
+                if (a.next_scale != 0.0) {
+                    y.x = fma(a.next_scale, acc.x, y.x);
+                    y.y = fma(a.next_scale, acc.y, y.y);
+                    y.z = fma(a.next_scale, acc.z, y.z);
+                    a.lv[i] = y;
+                }
+                if constexpr (PREC == LJMD_FP64) {
+                    const double im = 1.0 / by_s((int)st.rec64[a.cur][i].w, a.mass);
+                    ((double4 *)a.gv_next)[i] = make_double4(y.x * im, y.y * im, y.z * im, 0.0);
+                } else {
+                    const double im = 1.0 / by_s(st.recq[a.cur][i].w, a.mass);
+                    ((float4 *)a.gv_next)[i] =
+                        make_float4((float)(y.x * im), (float)(y.y * im), (float)(y.z * im), 0.f);
+                }
+                dnext = frame_d2_rec<PREC>(a.next_rec, st.xref, a.box, i);
+            }
         }
+        if (a.next) fold_disp(st.ctl, a.next_step, a.thr2, dnext);
     }
     const double v6[6] = {th.e0, th.e1, th.e2, th.s0, th.s1, th.s2};
     block_rows6(v6, a.rows + (size_t)blk * kNP, a.rows_weight, a.rows_init);
@@ -276,40 +348,6 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_reduce(const double *part, i
         }
         if (threadIdx.x == 0) gtheta[q] = (init ? 0.0 : gtheta[q]) + weight * red[0];
         __syncthreads();
-    }
-}
-
-// Squared displacement of slot i (record buffer cur) from its list
-// reference, as the bits of a non-negative float (NaN as a quiet NaN).
-template <int PREC>
-__device__ inline uint32_t frame_d2_bits(const State &st, const BoxC &box, int cur, int64_t i) {
-    uint32_t q[3];
-    if constexpr (PREC == LJMD_FP64) {
-        const double4 r = st.rec64[cur][i];
-        q[0] = q_from_d(r.x, box.S[0]);
-        q[1] = q_from_d(r.y, box.S[1]);
-        q[2] = q_from_d(r.z, box.S[2]);
-    } else {
-        const int4 r = st.recq[cur][i];
-        q[0] = (uint32_t)r.x;
-        q[1] = (uint32_t)r.y;
-        q[2] = (uint32_t)r.z;
-    }
-    const int4 xr = st.xref[i];
-    const float dx = disp_q(q[0], (uint32_t)xr.x, box.qs_hi[0], box.qs_lo[0]);
-    const float dy = disp_q(q[1], (uint32_t)xr.y, box.qs_hi[1], box.qs_lo[1]);
-    const float dz = disp_q(q[2], (uint32_t)xr.z, box.qs_hi[2], box.qs_lo[2]);
-    const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-    return d2 == d2 ? __float_as_uint(d2) : 0x7fc00000u;
-}
-
-// Every wave folds the largest of its lanes' values into the rebuild word of
-// `step` (only values past the threshold matter).
-__device__ inline void fold_disp(Ctl *ctl, int64_t step, float thr2, uint32_t dm) {
-    dm = wave_max_u(dm);
-    if ((threadIdx.x & 63) == 0 && dm > __float_as_uint(thr2)) {
-        atomicMax(&ctl->maxd[step & 1], dm);
-        if (dm > 0x7f800000u) atomicOr(&ctl->flags, kErrNaN);
     }
 }
 
@@ -433,8 +471,16 @@ hipError_t launch_adjoint_pairs(const Launch &L, int mode, const void *gvec, dou
 int adjoint_rows(const Geom &g) { return adjoint_blocks(g); }
 
 hipError_t launch_adjoint_vjp_rows(const Launch &L, const void *gvec, double4 *gx, double weight, double *rows,
-                                   int init, int64_t step, int forced) {
+                                   int init, int64_t step, int forced, const AdjNext *nx) {
     AdjArgs aa = pair_args(L, gvec, gx, weight);
+    if (nx) {
+        aa.next = 1;
+        aa.lv = nx->lv;
+        aa.gv_next = nx->gv_next;
+        aa.next_scale = nx->scale;
+        aa.next_step = nx->step;
+        aa.next_rec = nx->rec;
+    }
     aa.rows = rows;
     aa.rows_weight = weight;
     aa.rows_init = init;
@@ -477,6 +523,14 @@ static AdjArgs pair_args(const Launch &L, const void *gvec, double4 *gx, double 
     aa.forced = 0;
     aa.step = 0;
     aa.thr2 = L.dyn->thr2;
+    aa.next = 0;
+    aa.lv = nullptr;
+    aa.gv_next = nullptr;
+    aa.next_scale = 0.0;
+    aa.next_step = 0;
+    aa.next_rec = nullptr;
+    aa.mass[0] = L.dyn->mass[0];
+    aa.mass[1] = L.dyn->mass[1];
     aa.shifted = 0;
     for (int t = 0; t < 3; ++t) {
         const double c2 = L.pc->sig2[t] / L.pc->rc2[t];

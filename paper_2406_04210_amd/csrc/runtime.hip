@@ -28,7 +28,7 @@ struct AdjPlan {
     size_t off_ckpt = 0;      // (nseg + 1) stored states
     size_t frame_stride = 0;  // bytes of one position frame (record buffer)
     size_t off_frames = 0;    // every + 1 frames (nsteps + 1 when store_all)
-    size_t off_lx = 0, off_lv = 0, off_g = 0;
+    size_t off_lx = 0, off_lv = 0, off_g = 0, off_g2 = 0;  // off_g2: second cotangent buffer
     // Rebuild markers of every forward step (int32, store_all with segments
     // of at most kRing steps): where each segment's last list build was.
     size_t off_marks = 0;
@@ -588,6 +588,7 @@ AdjPlan adj_plan(const ljmd_params *p, int32_t nsteps, int32_t every, int32_t fl
     a.off_lx = take(sizeof(double4) * (size_t)npad);
     a.off_lv = take(sizeof(double4) * (size_t)npad);
     a.off_g = take(sizeof(double4) * (size_t)npad);
+    a.off_g2 = take(sizeof(double4) * (size_t)npad);
     if (a.store_all && a.reuse_lists()) a.off_marks = take(sizeof(int32_t) * (size_t)nsteps);
     a.off_rows = take(sizeof(double) * kNP * (size_t)((p->n + 63) / 64));
     a.total = off;
@@ -1206,7 +1207,10 @@ int ljmd_vv_backward(ljmd_ctx *c, const double *lam_x, const double *lam_v, doub
     uint8_t *ws = c->adj.ws;
     double4 *lx = (double4 *)(ws + P.off_lx);
     double4 *lv = (double4 *)(ws + P.off_lv);
-    void *gv = ws + P.off_g;
+    // Cotangent buffers: a frame's VJP reads one while its epilogue writes
+    // the next frame's into the other.
+    void *gvb[2] = {ws + P.off_g, ws + P.off_g2};
+    int gb = 0;
     double *rows = (double *)(ws + P.off_rows);
     if ((size_t)adjoint_rows(c->g) > (size_t)((c->g.n + 63) / 64))
         return fail(c, LJMD_EINVAL, "internal: adjoint rows");
@@ -1285,17 +1289,23 @@ int ljmd_vv_backward(ljmd_ctx *c, const double *lam_x, const double *lam_v, doub
             set_rec_ptr(c, c->cur, seg_frames + (size_t)j * P.frame_stride);
             // Drift (lambda_v += dt lambda_x, none at the last frame), the
             // force cotangent lambda_v / m and, unless the list is forced,
-            // the frame's displacement from the last build, in one pass.
-            if ((e = launch_adjoint_drift(L, lx, lv, gv, s != N ? dt : 0.0, t, forced ? 0 : 1)) != hipSuccess)
+            // the frame's displacement from the last build, in one pass: at
+            // the segment's first frame on its own, later in the epilogue of
+            // the previous frame's VJP.
+            if (j == top &&
+                (e = launch_adjoint_drift(L, lx, lv, gvb[gb], s != N ? dt : 0.0, t, forced ? 0 : 1)) != hipSuccess)
                 return hip_fail(c, e, "vv_backward drift and cotangent");
             if ((r = rebuild_sequence(c, t, forced, false))) return r;
             // The VJP pass also clears the cell counters after a rebuild;
             // its parameter sums stay in block rows until the sweep ends.
             const double w = (s == N || s == 0) ? h : dt;
+            AdjNext nx{lv, gvb[gb ^ 1], dt, t + 1, j > 0 ? seg_frames + (size_t)(j - 1) * P.frame_stride : nullptr};
             Bracket b(c, 4);
-            if ((e = launch_adjoint_vjp_rows(L, gv, lx, w, rows, first ? 1 : 0, t, forced)) != hipSuccess)
+            if ((e = launch_adjoint_vjp_rows(L, gvb[gb], lx, w, rows, first ? 1 : 0, t, forced, j > 0 ? &nx : nullptr)) !=
+                hipSuccess)
                 return hip_fail(c, e, "vv_backward vjp");
             first = false;
+            gb ^= 1;
         }
     }
     L = launcher(c);
