@@ -20,7 +20,14 @@ paper they follow:
   momentum from the lists.
 * ``run_nve`` -- velocity-Verlet time stepping with the list rebuilt when
   particles have moved far enough (Sec. 3 signals integrate/force/finalize;
-  Sec. 5: list updates become more frequent as particles move faster).
+  Sec. 5: list updates become more frequent as particles move faster),
+  optionally with the stochastic Andersen-like ("Boltzmann") thermostat the
+  paper combines with velocity Verlet (Sec. 4).
+* ``forces_fixed`` -- FP64 forces of the positions the single-precision path
+  represents (32-bit fixed-point image coordinates from the stated FP32
+  sequence); what remains against that path is its binary32 arithmetic.
+* ``philox4x32``, ``thermo_draw`` -- the counter-based generator (Salmon et
+  al., SC'11) and the thermostat's per-particle draws.
 """
 from __future__ import annotations
 
@@ -48,6 +55,10 @@ def build(verbose: bool = False) -> str:
     subprocess.run(cmd, check=True)
     os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
+
+
+class OThermo(C.Structure):
+    _fields_ = [("temperature", C.c_double), ("rate", C.c_double), ("seed", C.c_uint64)]
 
 
 class OLJ(C.Structure):
@@ -101,7 +112,18 @@ def lib():
         L.oracle_kinetic.restype = None
         L.oracle_kinetic.argtypes = [C.c_int64, dp, ip, pp, dp]
         L.oracle_run_nve.restype = C.c_int64
-        L.oracle_run_nve.argtypes = [C.c_int64, dp, dp, ip, dp, pp, C.c_int64, dp, dp]
+        L.oracle_run_nve.argtypes = [C.c_int64, dp, dp, ip, dp, pp, C.c_int64, dp, dp,
+                                     C.POINTER(OThermo), C.POINTER(C.c_uint64), dp]
+        L.oracle_forces_fixed.restype = None
+        L.oracle_forces_fixed.argtypes = [C.c_int64, dp, ip, dp, pp, C.c_int32, ip, ip, dp, dp, dp]
+        L.oracle_philox4x32.restype = None
+        L.oracle_philox4x32.argtypes = [up, up, up]
+        L.oracle_thermo_threshold.restype = C.c_uint32
+        L.oracle_thermo_threshold.argtypes = [C.c_double, C.c_double]
+        L.oracle_thermo_draw.restype = C.c_int32
+        L.oracle_thermo_draw.argtypes = [C.c_uint64, C.c_int64, C.c_int64, C.c_uint32, dp]
+        L.oracle_set_threads.restype = None
+        L.oracle_set_threads.argtypes = [C.c_int32]
         L.oracle_ds_split.restype = None
         L.oracle_ds_split.argtypes = [C.c_double, fp, fp]
         L.oracle_q_from_ds.restype = C.c_uint32
@@ -222,24 +244,83 @@ def kinetic(v, species, params):
     return float(out[0]), out[1:].copy()
 
 
-def run_nve(x, v, species, box, params, nsteps: int, want_obs: bool = True):
-    """Velocity-Verlet NVE. Returns dict with x, v (unwrapped, final),
+def run_nve(x, v, species, box, params, nsteps: int, want_obs: bool = True, thermostat=None,
+            want_sig: bool = False):
+    """Velocity-Verlet NVE (or, with ``thermostat=(T, rate, seed)``, with the
+    Andersen-like thermostat). Returns dict with x, v (unwrapped, final),
     f (final forces), obs ((nsteps+1, 6): U, K, W, px, py, pz), builds,
-    seconds (wall time of the stepping call)."""
+    seconds (wall time of the whole call), loop_seconds (wall time of the
+    step loop alone, after the initial list build and forces), sig
+    ((nsteps+1,) uint64 signatures of the pairs inside the cutoff, or None)."""
     x = _f64(x, (-1, 3)).copy()
     v = _f64(v, (-1, 3)).copy()
     n = x.shape[0]
     sp, bx = _i32(species), _f64(box)
     obs = np.zeros((nsteps + 1, 6)) if want_obs else None
+    sig = np.zeros(nsteps + 1, dtype=np.uint64) if want_sig else None
     f = np.zeros((n, 3))
     s = make_params(params)
+    th = None
+    if thermostat is not None:
+        th = OThermo(float(thermostat[0]), float(thermostat[1]), int(thermostat[2]))
+    loop = C.c_double(0.0)
     t0 = time.perf_counter()
     builds = lib().oracle_run_nve(n, _d(x), _d(v), _i(sp), _d(bx), C.byref(s), int(nsteps),
-                                  _d(obs) if obs is not None else None, _d(f))
+                                  _d(obs) if obs is not None else None, _d(f),
+                                  C.byref(th) if th is not None else None,
+                                  sig.ctypes.data_as(C.POINTER(C.c_uint64)) if sig is not None else None,
+                                  C.byref(loop))
     dt = time.perf_counter() - t0
     if builds < 0:
         raise MemoryError("oracle_run_nve: allocation failed")
-    return {"x": x, "v": v, "f": f, "obs": obs, "builds": int(builds), "seconds": dt}
+    return {"x": x, "v": v, "f": f, "obs": obs, "builds": int(builds), "seconds": dt,
+            "loop_seconds": loop.value, "sig": sig}
+
+
+def forces_fixed(x, species, box, params, cnt=None, nbr=None):
+    """FP64 forces of the positions the FP32 path represents (fixed-point
+    displacements). Returns (F, U, W, fabs) with fabs (N,) the per-particle
+    sum of pair-force magnitudes inside the cutoff."""
+    x = _f64(x, (-1, 3))
+    n = x.shape[0]
+    sp, bx = _i32(species), _f64(box)
+    if cnt is None:
+        cnt, nbr = build_lists(x, species, box, params, 0)
+    nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+    cnt = _i32(cnt)
+    f = np.zeros((n, 3))
+    fa = np.zeros(n)
+    out = np.zeros(2)
+    s = make_params(params)
+    lib().oracle_forces_fixed(n, _d(x), _i(sp), _d(bx), C.byref(s), nbr.shape[1], _i(cnt), _i(nbr),
+                              _d(f), _d(out), _d(fa))
+    return f, float(out[0]), float(out[1]), fa
+
+
+def philox4x32(ctr, key):
+    """Philox4x32-10 block for a 4-word counter and 2-word key."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    o = np.zeros(4, dtype=np.uint32)
+    up = C.POINTER(C.c_uint32)
+    lib().oracle_philox4x32(c.ctypes.data_as(up), k.ctypes.data_as(up), o.ctypes.data_as(up))
+    return o
+
+
+def thermo_threshold(rate: float, dt: float) -> int:
+    return int(lib().oracle_thermo_threshold(float(rate), float(dt)))
+
+
+def thermo_draw(seed: int, pid: int, step: int, threshold: int):
+    """(collides, z (3,)) of particle pid at step for the thermostat."""
+    z = np.zeros(3)
+    hit = lib().oracle_thermo_draw(int(seed), int(pid), int(step), int(threshold), _d(z))
+    return bool(hit), z
+
+
+def set_threads(n: int):
+    """Threads of the oracle's OpenMP loops from now on."""
+    lib().oracle_set_threads(int(n))
 
 
 def minimize_sd(x, species, box, params, nsteps: int, delta: float = 0.01, clamp: float = 0.6):

@@ -22,16 +22,33 @@
  * binary32 with explicit fused multiply-adds, the stated FP32 operation
  * sequence that the single-precision path uses to decide list membership
  * (double-single split, fixed-point image coordinate, displacement, r^2), so
- * that neighbour sets can be compared exactly. Compile with
+ * that neighbour sets can be compared exactly, and one evaluates the FP64
+ * forces of the fixed-point positions that sequence produces. Compile with
  * -ffp-contract=off so that no other fusion happens.
+ *
+ * Also here: the stochastic velocity-resampling ("Boltzmann", Andersen-like)
+ * thermostat the paper combines with velocity Verlet (Sec. 4), drawing from
+ * the counter-based Philox4x32-10 generator (Salmon et al., SC'11); and, with
+ * infinite cutoffs, the untruncated all-pairs interaction the port started
+ * from (Sec. 4, Sec. 5 "GPU Performance for All-to-All Interaction"): every
+ * function below accepts rcut = +inf (no shift, all pairs interact).
  */
+#define _POSIX_C_SOURCE 199309L  /* clock_gettime */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
+
+/* Monotonic wall clock in seconds (timing of the CPU baseline). */
+static double wall_seconds(void) {
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
 
 /* Parameters of one system (mirrored by a ctypes Structure in __init__.py). */
 typedef struct {
@@ -345,6 +362,61 @@ void oracle_forces_list(int64_t n, const double *x, const int32_t *sp, const dou
     out[1] = W;
 }
 
+/* O10b -- FP64 forces of the positions the FP32 path represents. Every
+ * coordinate is first carried through steps 1 and 2 of the FP32 sequence
+ * above (double-single split of the wrapped coordinate, fixed-point image
+ * coordinate q); a pair displacement is then the wrapped 32-bit difference
+ * q_i - q_j times the quantum L 2^-32, formed in FP64 (exact: an integer of
+ * at most 31 bits times a power-of-two multiple of L, rounded once). From
+ * there on everything is oracle_forces_list: FP64 pair forces over the full
+ * lists, the cutoff decided in FP64 on these displacements. What remains
+ * between this and the FP32 path is the binary32 arithmetic of the path
+ * itself (and the cutoff decision at ties).
+ * out = [U, W]; fabs (nullable) receives per particle the sum over its
+ * partners inside the cutoff of the pair-force magnitudes |fs| r, the scale
+ * against which the rounding of a sum of pair forces is measured. */
+void oracle_forces_fixed(int64_t n, const double *x, const int32_t *sp, const double *box,
+                         const olj_t *p, int32_t cap, const int32_t *cnt, const int32_t *nbr,
+                         double *f, double *out, double *fabs_sum) {
+    uint32_t *q = (uint32_t *)malloc(sizeof(uint32_t) * 3 * (size_t)n);
+    double quantum[3];
+    for (int k = 0; k < 3; ++k) quantum[k] = box[k] / 4294967296.0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < 3; ++k) {
+            float hi, lo;
+            oracle_ds_split(wrap1(x[3 * i + k], box[k]), &hi, &lo);
+            q[3 * i + k] = oracle_q_from_ds(hi, lo, box[k]);
+        }
+    double U = 0.0, W = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : U, W)
+    for (int64_t i = 0; i < n; ++i) {
+        double fi[3] = {0.0, 0.0, 0.0};
+        double ui = 0.0, wi = 0.0, ai = 0.0;
+        int32_t m = cnt[i] < cap ? cnt[i] : cap;
+        for (int32_t k = 0; k < m; ++k) {
+            int64_t j = nbr[(size_t)i * cap + k];
+            double d[3];
+            for (int c = 0; c < 3; ++c)
+                d[c] = (double)(int32_t)(q[3 * i + c] - q[3 * j + c]) * quantum[c];
+            double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            int ab = pair_index(p, sp[i], sp[j]);
+            if (r >= p->rcut[ab]) continue;
+            double fs = oracle_pair_fscalar(r, ab, p);
+            for (int c = 0; c < 3; ++c) fi[c] += fs * d[c];
+            ui += 0.5 * oracle_pair_energy(r, ab, p);
+            wi += 0.5 * fs * r * r;
+            ai += fabs(fs) * r;
+        }
+        for (int c = 0; c < 3; ++c) f[3 * i + c] = fi[c];
+        if (fabs_sum) fabs_sum[i] = ai;
+        U += ui;
+        W += wi;
+    }
+    free(q);
+    out[0] = U;
+    out[1] = W;
+}
+
 /* Kinetic energy and momentum: out = [K, px, py, pz]. */
 void oracle_kinetic(int64_t n, const double *v, const int32_t *sp, const olj_t *p, double *out) {
     double K = 0.0, px = 0.0, py = 0.0, pz = 0.0;
@@ -360,6 +432,112 @@ void oracle_kinetic(int64_t n, const double *v, const int32_t *sp, const olj_t *
     out[1] = px;
     out[2] = py;
     out[3] = pz;
+}
+
+/* ---------------------------------------------------------------- O11 --- */
+
+/* Philox4x32-10, the counter-based generator of Salmon, Moraes, Dror and
+ * Shaw, "Parallel random numbers: as easy as 1, 2, 3" (SC'11): ten rounds of
+ *   (hi0, lo0) = M0 * c0,  (hi1, lo1) = M1 * c2   (32 x 32 -> 64-bit products)
+ *   c = (hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0)
+ * with the key bumped by the Weyl constants (W0, W1) after every round but
+ * the last. M0 = 0xD2511F53, M1 = 0xCD9E8D57, W0 = 0x9E3779B9,
+ * W1 = 0xBB67AE85. */
+void oracle_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+        if (r < 9) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+/* Settings of the stochastic velocity-resampling ("Boltzmann", Andersen-type)
+ * thermostat. rate = collision frequency nu per unit time; 0 disables it. */
+typedef struct {
+    double temperature;
+    double rate;
+    uint64_t seed;
+} othermo_t;
+
+/* Collision threshold: a particle collides in a step iff its first draw u0
+ * (a uniform 32-bit integer) is below floor(nu dt 2^32), so that the
+ * collision probability per step is nu dt (to 2^-32). */
+uint32_t oracle_thermo_threshold(double rate, double dt) {
+    double t = floor(rate * dt * 4294967296.0);
+    if (!(t > 0.0)) return 0u;
+    if (t >= 4294967295.0) return 0xFFFFFFFFu;
+    return (uint32_t)t;
+}
+
+/* Uniform in (0, 1) from a 32-bit integer: (u + 1/2) 2^-32 (exact in FP64). */
+static double u01(uint32_t u) { return ((double)u + 0.5) * (1.0 / 4294967296.0); }
+
+/* The thermostat's draws for particle `id` at step `step`: two Philox blocks
+ * with counters (id, step_lo, step_hi, 0) and (id, step_lo, step_hi, 1) under
+ * the key (seed_lo, seed_hi). Returns 1 if the particle collides (first word
+ * below the threshold) and then writes three standard normal deviates from
+ * the Box-Muller transform (z0, z1) = sqrt(-2 ln a) (cos 2 pi b, sin 2 pi b)
+ * of the pairs (a, b) = (w1, w2) and (w3, w4) of the eight words (z1 of the
+ * second pair unused). */
+int32_t oracle_thermo_draw(uint64_t seed, int64_t id, int64_t step, uint32_t threshold, double z[3]) {
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t ctr[4] = {(uint32_t)id, (uint32_t)(uint64_t)step, (uint32_t)((uint64_t)step >> 32), 0u};
+    uint32_t a[4], b[4];
+    oracle_philox4x32(ctr, key, a);
+    if (a[0] >= threshold) return 0;
+    ctr[3] = 1u;
+    oracle_philox4x32(ctr, key, b);
+    const double two_pi = 6.283185307179586476925286766559;
+    double r1 = sqrt(-2.0 * log(u01(a[1]))), t1 = two_pi * u01(a[2]);
+    double r2 = sqrt(-2.0 * log(u01(a[3]))), t2 = two_pi * u01(b[0]);
+    z[0] = r1 * cos(t1);
+    z[1] = r1 * sin(t1);
+    z[2] = r2 * cos(t2);
+    return 1;
+}
+
+/* Order-independent 64-bit signature of the set of unordered pairs i < j
+ * inside their cutoff (from full lists): the sum of a 64-bit mix of (i, j).
+ * Two configurations with the same signature have, but for a 2^-64 chance,
+ * the same pairs inside the cutoff. */
+static uint64_t mix64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+static uint64_t cutoff_signature(int64_t n, const double *x, const int32_t *sp, const double *box,
+                                 const olj_t *p, int32_t cap, const int32_t *cnt, const int32_t *nbr) {
+    uint64_t s = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t m = cnt[i] < cap ? cnt[i] : cap;
+        for (int32_t k = 0; k < m; ++k) {
+            int64_t j = nbr[(size_t)i * cap + k];
+            if (j <= i) continue;
+            double d[3];
+            min_image(x + 3 * i, x + 3 * j, box, d);
+            double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            if (r >= p->rcut[pair_index(p, sp[i], sp[j])]) continue;
+            s += mix64(((uint64_t)i << 32) | (uint64_t)j);
+        }
+    }
+    return s;
 }
 
 /* ---------------------------------------------------------------- O5 ---- */
@@ -399,13 +577,22 @@ static int needs_rebuild(const olist_t *L, const double *x, double skin) {
 /* Velocity-Verlet NVE (Sec. 3: the "integrate" half step updates momenta and
  * positions, a force evaluation follows, "finalize" completes the momenta):
  *   v <- v + dt/2 F/m ; x <- x + dt v ; [rebuild if needed] ; F <- F(x) ;
- *   v <- v + dt/2 F/m.
- * x (unwrapped) and v are updated in place. obs (nullable) receives
- * (nsteps + 1) rows [U, K, W, px, py, pz] for steps 0..nsteps.
- * f_out (nullable) receives the final forces. Returns the number of list
+ *   v <- v + dt/2 F/m ; [thermostat].
+ * With a thermostat (Sec. 4: velocity Verlet combined with a stochastic
+ * Andersen-like thermostat), after the second half kick of step s every
+ * particle that collides (oracle_thermo_draw with its id and s) takes a new
+ * velocity sqrt(T/m) z from the Maxwell-Boltzmann distribution at T.
+ * x (unwrapped) and v are updated in place, particles keep their order (the
+ * id of row i is i). obs (nullable) receives (nsteps + 1) rows
+ * [U, K, W, px, py, pz] for steps 0..nsteps. f_out (nullable) receives the
+ * final forces; thermo (nullable) enables the thermostat; sig (nullable)
+ * receives, for steps 0..nsteps, the signature of the pairs inside the
+ * cutoff; loop_seconds (nullable) the wall time of the step loop alone
+ * (after the initial list build and forces). Returns the number of list
  * builds (including the initial one), or -1 on allocation failure. */
 int64_t oracle_run_nve(int64_t n, double *x, double *v, const int32_t *sp, const double *box,
-                       const olj_t *p, int64_t nsteps, double *obs, double *f_out) {
+                       const olj_t *p, int64_t nsteps, double *obs, double *f_out,
+                       const othermo_t *thermo, uint64_t *sig, double *loop_seconds) {
     olist_t L;
     L.n = n;
     L.cap = 160;
@@ -426,7 +613,11 @@ int64_t oracle_run_nve(int64_t n, double *x, double *v, const int32_t *sp, const
         double row[6] = {uw[0], kp[0], uw[1], kp[1], kp[2], kp[3]};
         memcpy(obs, row, sizeof row);
     }
+    if (sig) sig[0] = cutoff_signature(n, x, sp, box, p, L.cap, L.cnt, L.nbr);
+    const int thermo_on = thermo && thermo->rate > 0.0;
+    const uint32_t thr = thermo_on ? oracle_thermo_threshold(thermo->rate, p->dt) : 0u;
     double h = 0.5 * p->dt;
+    double t0 = wall_seconds();
     for (int64_t s = 1; s <= nsteps; ++s) {
         for (int64_t i = 0; i < n; ++i)
             for (int k = 0; k < 3; ++k) {
@@ -440,12 +631,21 @@ int64_t oracle_run_nve(int64_t n, double *x, double *v, const int32_t *sp, const
         oracle_forces_list(n, x, sp, box, p, L.cap, L.cnt, L.nbr, f, uw);
         for (int64_t i = 0; i < n; ++i)
             for (int k = 0; k < 3; ++k) v[3 * i + k] += h * f[3 * i + k] * invm[i];
+        if (thermo_on)
+            for (int64_t i = 0; i < n; ++i) {
+                double z[3];
+                if (!oracle_thermo_draw(thermo->seed, i, s, thr, z)) continue;
+                double sd = sqrt(thermo->temperature * invm[i]);
+                for (int k = 0; k < 3; ++k) v[3 * i + k] = sd * z[k];
+            }
+        if (sig) sig[s] = cutoff_signature(n, x, sp, box, p, L.cap, L.cnt, L.nbr);
         if (obs) {
             oracle_kinetic(n, v, sp, p, kp);
             double row[6] = {uw[0], kp[0], uw[1], kp[1], kp[2], kp[3]};
             memcpy(obs + 6 * s, row, sizeof row);
         }
     }
+    if (loop_seconds) *loop_seconds = wall_seconds() - t0;
     if (f_out) memcpy(f_out, f, sizeof(double) * 3 * (size_t)n);
     free(L.cnt);
     free(L.nbr);
@@ -752,6 +952,15 @@ int32_t oracle_vv_adjoint(int64_t n, const double *x0, const double *v0, const i
     free(gx);
     free(invm);
     return 0;
+}
+
+/* Threads of the OpenMP loops from now on (n >= 1). */
+void oracle_set_threads(int32_t n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
 }
 
 int32_t oracle_num_threads(void) {

@@ -399,3 +399,48 @@ def test_full_size_differentiable_workload(ljmd):
     assert ex <= TOL_ROLL[FP32] and ev <= TOL_ROLL[FP32], (ex, ev)
     for k, ref in ((0, re[0]), (3, rs[0])):
         assert abs(gtr[k] - ref) <= TOL_ROLL[FP32] * (abs(ref) + 1.0), (k, gtr[k], ref)
+
+
+def test_full_loss_n2048_fp64_against_oracle_and_fd(ljmd):
+    # The differentiable workload at N = 2048 (jittered FCC 8^3, targets
+    # within 5 %, 50 steps, a stored state every 10) in FP64 through the
+    # autograd front ends: loss and gradient against the oracle (itself
+    # pinned by finite differences in test_oracle_adjoint_pins.py), and the
+    # gradient along seeded directions against central differences of the
+    # oracle's loss at a step where no pair changes side of its cutoff.
+    import torch
+    import loss4
+    wl, eps_t, sig_t = W.jittered_fcc(8)
+    x, v, sp, box, p = wl.x, wl.v, wl.species, wl.box, wl.params
+    n, nsteps = len(x), 50
+    qs = oracle.with_params(p, eps=[eps_t[0]] * 3, sigma=[sig_t[0]] * 3)
+    f_star, _, _ = oracle.forces(x, sp, box, qs)
+    sF = ljmd.System(n, box, p, precision=FP64)
+    sR = ljmd.System(n, box, p, precision=FP64)
+    x0 = torch.tensor(x, dtype=torch.float64, device="cuda", requires_grad=True)
+    v0 = torch.tensor(v, dtype=torch.float64, device="cuda", requires_grad=True)
+    tt = torch.tensor(theta_of(p), dtype=torch.float64, requires_grad=True)
+    F = ljmd.LJForceFn.apply(x0, tt, sF, sp)
+    Fs = torch.as_tensor(f_star, device="cuda")
+    _, _, UN = ljmd.VVRollout.apply(x0, v0, tt, sR, sp, nsteps, 10)
+    L = ((F - Fs) ** 2).sum() / (3 * n) + UN / n
+    L.backward()
+    gx, gv, gt = x0.grad.cpu().numpy(), v0.grad.cpu().numpy(), tt.grad.numpy()
+    Lo, _ = loss4.loss(x, v, sp, box, p, 1.0, 1.0, f_star, nsteps)
+    ox, ov, oe, osg = loss4.grad(x, v, sp, box, p, 1.0, 1.0, f_star, nsteps)
+    ex = float(np.linalg.norm(gx - ox) / np.linalg.norm(ox))
+    ev = float(np.linalg.norm(gv - ov) / np.linalg.norm(ov))
+    print(f"n2048 loss gpu {float(L):.15g} oracle {Lo:.15g}; grad rel err x0 {ex:.3e} v0 {ev:.3e}; "
+          f"theta gpu {gt[[0, 3]]} oracle {oe:.12g} {osg:.12g}", flush=True)
+    assert float(L) == pytest.approx(Lo, rel=1e-11)
+    assert ex <= 1e-10 and ev <= 1e-10
+    assert gt[0] == pytest.approx(oe, rel=1e-10) and gt[3] == pytest.approx(osg, rel=1e-10)
+    rng = np.random.default_rng(4096)
+    for _ in range(2):
+        dx, dv = rng.standard_normal(x.shape), rng.standard_normal(x.shape)
+        de, ds = float(rng.standard_normal()), float(rng.standard_normal())
+        fd, dx, dv, de, ds = loss4.fd_directional(x, v, sp, box, p, 1.0, 1.0, f_star, nsteps,
+                                                  dx, dv, de, ds, 1e-8, rng)
+        an = float((gx * dx).sum() + (gv * dv).sum() + gt[0] * de + gt[3] * ds)
+        print(f"n2048 directional: gpu {an:.12g} fd {fd:.12g}", flush=True)
+        assert an == pytest.approx(fd, rel=1e-6)

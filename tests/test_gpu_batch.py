@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 from paper_2406_04210_amd import workloads as W
-from test_gpu_parity import rel_force_err, representation_allowance, tie_allowance
+from force_metrics import force_errors, reference, report, tie_allowance
 
 pytestmark = pytest.mark.gpu
 FP32 = 1
@@ -114,26 +114,13 @@ def test_batch_forces_match_oracle(ljmd, replicas):
     b.sync()
     off = np.concatenate([[0], np.cumsum([w.n for w in ws])])
     for k, w in enumerate(ws):
-        ref, _, _ = oracle.forces_brute(w.x, w.species, w.box, w.params)
-        g = f[off[k]:off[k + 1]]
-        rms = math.sqrt(float((ref ** 2).sum(axis=1).mean()))
-        scale = np.maximum(np.maximum(np.linalg.norm(ref, axis=1), rms), 1.0)
-        err = float((np.linalg.norm(g - ref, axis=1) / scale).max())
-        # FP32 pair arithmetic: 1e-5 per particle away from cutoff ties; these
-        # lattice-with-vacancy states are checked for ties below.
-        assert err <= 1e-5 or has_cutoff_tie(w), (k, err)
-
-
-def has_cutoff_tie(w):
-    cnt, nbr = oracle.build_lists(w.x, w.species, w.box, w.params, mode=0)
-    n = len(w.x)
-    i = np.repeat(np.arange(n), cnt)
-    j = nbr[np.arange(nbr.shape[1])[None, :] < cnt[:, None]]
-    d = w.x[i] - w.x[j]
-    d -= w.box * np.rint(d / w.box)
-    r2 = (d * d).sum(axis=1)
-    rc2 = w.params.rcut[0] ** 2
-    return bool(np.any(np.abs(r2 - rc2) <= 2e-6 * rc2))
+        # The FP32 bound of test_gpu_parity.py: 1e-5 of the rms force against
+        # the oracle's forces of the fixed-point positions, after the tie
+        # allowance (lattice-with-vacancy states can hold cutoff ties).
+        ref, _, _, A = reference(w.x, w.species, w.box, w.params, FP32)
+        m = report(f"batch replica {k} {w.name}",
+                   force_errors(f[off[k]:off[k + 1]], ref, A, tie_allowance(w.x, w.species, w.box, w.params, FP32)))
+        assert m["sec8c"] <= 1e-5, (k, m)
 
 
 def test_batch_rejects_small_box(ljmd):
@@ -171,9 +158,9 @@ def test_full_batch_sampled_systems(ljmd):
     for k in rng.choice(len(ws), 6, replace=False):
         w = ws[k]
         sl = slice(off[k], off[k + 1])
-        ref, _, _ = oracle.forces(xh[sl], w.species, w.box, w.params)
-        # The FP32 bound of test_gpu_parity.py: 1e-5 per particle, plus the
-        # cutoff ties and the fixed-point representation allowance.
-        allow = tie_allowance(xh[sl], w.species, w.box, w.params, FP32) + \
-            representation_allowance(xh[sl], w.species, w.box, w.params)
-        assert rel_force_err(fh[sl], ref, allow) <= 1e-5, (k, w.name)
+        ref, _, _, A = reference(xh[sl], w.species, w.box, w.params, FP32)
+        # The FP32 bound of test_gpu_parity.py (1e-5 of the rms force against
+        # the fixed-point positions' forces, ties allowed for).
+        m = report(f"full batch replica {k} {w.name}",
+                   force_errors(fh[sl], ref, A, tie_allowance(xh[sl], w.species, w.box, w.params, FP32)))
+        assert m["sec8c"] <= 1e-5, (k, w.name, m)

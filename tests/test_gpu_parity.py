@@ -4,19 +4,18 @@ Inputs come from the shared seeded generators; every expected value comes
 from the oracle. Tolerances:
   * neighbour sets: identical (FP64 criterion in the FP64 path, the stated
     FP32 sequence in the FP32 path, both evaluated from the same FP64 input);
-  * forces: relative error per particle, max_i |dF_i| / s_i <= 1e-12 (FP64),
-    <= 1e-5 (FP32+DS), with the scale s_i = max(|F_i|, rms_j |F_j|, 1 eps/sigma):
-    relative to the particle's own force, floored at the rms force (for
-    forces that nearly cancel) and at the unit force (perfect lattice); a
-    particle with a partner at a cutoff tie (|r^2 - r_c^2| within rounding of
-    the path's precision, found from the FP64 positions) may additionally
-    differ by the force jump |F(r_c)| per such partner, because the truncated
-    force is discontinuous there and binary32 decides r^2 < r_c^2;
+  * forces (metrics in force_metrics.py): max_i |dF_i| / max(rms_j |F_j|, 1)
+    <= 1e-12 (FP64, against the oracle's FP64 forces) and <= 1e-5 (FP32+DS,
+    against the oracle's FP64 forces of the fixed-point positions the path
+    represents), after the tie allowance |F(r_c)| per partner at a cutoff
+    tie (the truncated force jumps there); the relaxed 4M mixture, whose net
+    forces are ~1/50 of its pair forces, is held to 1e-5 of the sum of its
+    pair-force magnitudes instead (see that test);
   * U/N, W/N: relative 1e-12 (FP64), 5e-6 (FP32+DS). The FP32 bound follows
     from the arithmetic: s^12 = u^6 multiplies the relative error of r^2
     (~2e-7 from the binary32 displacement) and of the 1-ulp reciprocal
     (1.2e-7) six times, so a repulsion-dominated energy sum can be off by
-    ~2.6e-6 relative;
+    ~2.6e-6 relative (each test prints the measured error);
   * 100-step trajectories (N=2048): max |dx| <= 1e-10 sigma, |dv| <= 1e-9
     (FP64); <= 1e-4 and <= 1e-3 (FP32+DS).
 """
@@ -26,6 +25,7 @@ import numpy as np
 import pytest
 
 import oracle
+from force_metrics import force_errors, reference, report, tie_allowance
 from paper_2406_04210_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -93,69 +93,6 @@ CASES = cases()
 IDS = [c[0] for c in CASES]
 
 
-def tie_allowance(x, sp, box, p, prec):
-    """Per-particle sum of |F(r_c)| over partners at a cutoff tie."""
-    x = np.asarray(x, dtype=np.float64)
-    n = len(x)
-    cnt, nbr = oracle.build_lists(x, sp, box, p, mode=0)
-    i = np.repeat(np.arange(n), cnt)
-    j = nbr[np.arange(nbr.shape[1])[None, :] < cnt[:, None]]
-    d = x[i] - x[j]
-    d -= box * np.rint(d / box)
-    r2 = (d * d).sum(axis=1)
-    ab = sp[i] * 2 + sp[j] if p.nspecies == 2 else np.zeros(len(i), dtype=np.int64)
-    rc = np.asarray(p.rcut)[ab]
-    window = 1e-12 if prec == FP64 else 2e-6
-    tie = np.abs(r2 - rc * rc) <= window * rc * rc
-    out = np.zeros(n)
-    for k in np.nonzero(tie)[0]:
-        a = int(ab[k])
-        jump = abs(oracle.pair_fscalar(rc[k] * (1 - 1e-15), a, p)) * rc[k]
-        out[i[k]] += 1.001 * jump
-    return out
-
-
-def representation_allowance(x, sp, box, p, chunk=250000):
-    """Per-particle force error the FP32 path's representation admits:
-    sum over partners within the cutoff of sqrt(3) * (L / 2^32) * (|dF/dr| +
-    |F| / r) (pair displacement from 32-bit fixed-point coordinates) plus
-    3e-6 |F| (binary32 pair arithmetic and per-lane sums). Pair forces from
-    the oracle's FP64 lists and the textbook LJ formulas."""
-    x = np.asarray(x, dtype=np.float64)
-    n = len(x)
-    cnt, nbr = oracle.build_lists(x, sp, box, p, mode=0)
-    qs = float(np.max(box)) / 2.0 ** 32
-    src = [0, 1, 3] if p.nspecies == 2 else [0, 0, 0]
-    sig_t = np.array([p.sigma[a] for a in src]); eps_t = np.array([p.eps[a] for a in src])
-    rc_t = np.array([p.rcut[a] for a in src])
-    out = np.zeros(n)
-    for a in range(0, n, chunk):
-        b = min(n, a + chunk)
-        c = cnt[a:b]
-        ii = np.repeat(np.arange(a, b), c)
-        jj = nbr[a:b][np.arange(nbr.shape[1])[None, :] < c[:, None]]
-        d = x[ii] - x[jj]
-        d -= box * np.rint(d / box)
-        r = np.sqrt((d * d).sum(axis=1))
-        t = (sp[ii] + sp[jj]) if p.nspecies == 2 else np.zeros(len(ii), dtype=np.int64)
-        u = sig_t[t] / r
-        F = 24.0 * eps_t[t] * (2.0 * u ** 12 - u ** 6) / r
-        dF = 24.0 * eps_t[t] * (-26.0 * u ** 12 + 7.0 * u ** 6) / r ** 2
-        inside = r < rc_t[t]
-        wgt = (math.sqrt(3.0) * qs * (np.abs(dF) + np.abs(F) / r) + 3e-6 * np.abs(F)) * inside
-        out[a:b] += np.bincount(ii - a, weights=wgt, minlength=b - a)
-    return out
-
-
-def rel_force_err(f, g, allowance=None):
-    rms = math.sqrt(float((g ** 2).sum(axis=1).mean()))
-    scale = np.maximum(np.maximum(np.linalg.norm(g, axis=1), rms), 1.0)
-    err = np.linalg.norm(f - g, axis=1)
-    if allowance is not None:
-        err = np.maximum(err - allowance, 0.0)
-    return float((err / scale).max())
-
-
 def make_system(ljmd, x, v, sp, box, p, prec, **kw):
     s = ljmd.System(len(x), box, p, precision=prec, **kw)
     s.set_state(x, v, sp)
@@ -219,6 +156,20 @@ def test_neighbor_sets_at_list_radius_ties(ljmd, nspecies, prec):
         assert set(ids[i, : cnt[i]].tolist()) == set(on[i, : oc[i]].tolist()), i
 
 
+def check_forces(tag, f, x, sp, box, p, prec, tol=None):
+    ref, U, Wv, A = reference(x, sp, box, p, prec)
+    m = report(tag, force_errors(f, ref, A, tie_allowance(x, sp, box, p, prec)))
+    assert m["sec8c"] <= (TOL_F[prec] if tol is None else tol), (tag, m)
+    return U, Wv
+
+
+def energy_errors(tag, o, U, Wv, n):
+    eu = abs(o["U"] - U) / max(1.0, abs(U))
+    ew = abs(o["W"] - Wv) / max(1.0, abs(Wv))
+    print(f"energy errors [{tag}]: U rel {eu:.3e} W rel {ew:.3e}", flush=True)
+    return eu, ew
+
+
 @pytest.mark.parametrize("prec", [FP64, FP32])
 @pytest.mark.parametrize("case", CASES, ids=IDS)
 def test_forces_energy_virial(ljmd, case, prec):
@@ -226,12 +177,11 @@ def test_forces_energy_virial(ljmd, case, prec):
     s = make_system(ljmd, x, v, sp, box, p, prec)
     f = s.forces().cpu().numpy()
     o = s.observables()
-    fb, Ub, Wb = oracle.forces_brute(x, sp, box, p)
+    U, Wv = check_forces(f"{name} prec={prec}", f, x, sp, box, p, prec)
     K, mom = oracle.kinetic(v, sp, p)
-    assert rel_force_err(f, fb, tie_allowance(x, sp, box, p, prec)) <= TOL_F[prec], name
     n = len(x)
-    assert abs(o["U"] - Ub) / n <= TOL_E[prec] * max(1.0, abs(Ub) / n)
-    assert abs(o["W"] - Wb) / n <= TOL_E[prec] * max(1.0, abs(Wb) / n)
+    eu, ew = energy_errors(f"{name} prec={prec}", o, U, Wv, n)
+    assert eu <= TOL_E[prec] and ew <= TOL_E[prec]
     assert o["K"] == pytest.approx(K, rel=1e-12 if prec == FP64 else 1e-6)
     assert o["rebuilds"] == 1 and o["step"] == 0
 
@@ -242,8 +192,7 @@ def test_gather_lanes_agree(ljmd, lanes, prec):
     name, x, v, sp, box, p = CASES[4]
     s = make_system(ljmd, x, v, sp, box, p, prec, lanes=lanes)
     f = s.forces().cpu().numpy()
-    fb, _, _ = oracle.forces_brute(x, sp, box, p)
-    assert rel_force_err(f, fb, tie_allowance(x, sp, box, p, prec)) <= TOL_F[prec]
+    check_forces(f"{name} lanes={lanes} prec={prec}", f, x, sp, box, p, prec)
 
 
 def _trajectory(ljmd, w, prec, nsteps, **kw):
@@ -275,6 +224,36 @@ def test_trajectory_100_steps(ljmd, prec):
     assert np.abs(obs[:, 3:6]).max() < (1e-10 if prec == FP64 else 1e-3)
     o = s.observables()
     assert o["step"] == 100 and o["rebuilds"] == 1 + int(obs[:, 6].sum())
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_trajectory_unequal_masses(ljmd, prec):
+    # Species masses 1 and 2 (every other case has unit masses): the half
+    # kicks divide by the particle's own mass, K and p are mass-weighted.
+    r0 = W.random_dense(1500, 1.1, seed=7, nspecies=2, min_dist=0.75)
+    p = r0.params.copy()
+    p.mass = np.array([1.0, 2.0])
+    v = W.maxwell_boltzmann(r0.n, 1.0, p.mass, r0.species, np.random.default_rng(70))
+    v = v + np.array([0.05, -0.02, 0.03])          # a non-zero total momentum
+    s = make_system(ljmd, r0.x, v, r0.species, r0.box, p, prec, sort_interval=25)
+    obs = s.run(100).cpu().numpy()
+    s.sync()
+    xu = s.unwrapped_positions().cpu().numpy()
+    _, vg, _ = s.get_state()
+    vg = vg.cpu().numpy()
+    r = oracle.run_nve(r0.x, v, r0.species, r0.box, p, 100)
+    dx = np.abs(xu - r["x"]).max()
+    dv = np.abs(vg - r["v"]).max()
+    print(f"unequal masses prec={prec}: max|dx|={dx:.3e} max|dv|={dv:.3e}", flush=True)
+    tol_x, tol_v = (1e-10, 1e-9) if prec == FP64 else (1e-4, 1e-3)
+    assert dx <= tol_x and dv <= tol_v, (dx, dv)
+    ro = r["obs"][1:]
+    tol = 1e-10 if prec == FP64 else 1e-5
+    assert np.abs(obs[:, 1] - ro[:, 1]).max() / r0.n <= tol          # K = sum m v^2 / 2
+    assert np.abs(obs[:, 0] - ro[:, 0]).max() / r0.n <= tol
+    P0 = (p.mass[r0.species][:, None] * v).sum(axis=0)
+    assert np.abs(obs[:, 3:6] - P0[None, :]).max() <= (1e-10 if prec == FP64 else 1e-4) * np.abs(P0).max()
+    assert np.abs(ro[:, 3:6] - P0[None, :]).max() <= 1e-10 * np.abs(P0).max()
 
 
 @pytest.mark.parametrize("nspecies", [1, 2])
@@ -400,14 +379,9 @@ def test_full_size_forces_and_sampled_lists(ljmd, prec):
     s = make_system(ljmd, x, w.v, w.species, box, w.params, prec)
     f = s.forces().cpu().numpy()
     o = s.observables()
-    fo, Uo, Wo = oracle.forces(x, w.species, box, w.params)
-    allow = tie_allowance(x, w.species, box, w.params, prec)
-    assert rel_force_err(f, fo, allow) <= TOL_F[prec]
-    # Away from cutoff ties the plain per-particle bound holds.
-    clean = allow == 0
-    assert rel_force_err(f[clean], fo[clean]) <= TOL_F[prec]
-    assert abs(o["U"] - Uo) <= TOL_E[prec] * abs(Uo)
-    assert abs(o["W"] - Wo) <= TOL_E[prec] * abs(Wo)
+    Uo, Wo = check_forces(f"headline n=256000 prec={prec}", f, x, w.species, box, w.params, prec)
+    eu, ew = energy_errors(f"headline n=256000 prec={prec}", o, Uo, Wo, len(x))
+    assert eu <= TOL_E[prec] and ew <= TOL_E[prec]
     cnt, ids = s.neighbors(cap=256)
     cnt, ids = cnt.cpu().numpy(), ids.cpu().numpy()
     oc, on = oracle.build_lists(x, w.species, box, w.params, mode=0 if prec == FP64 else 1)
@@ -435,32 +409,20 @@ def test_full_size_mixture_after_relaxation(ljmd):
     s.sync()
     del s
     xh = x.cpu().numpy()
-    fo, Uo, Wo = oracle.forces(xh, w.species, w.box, w.params)
-    # Per-particle bound: 1e-5 of max(|F_i|, rms |F|, 1), plus what the
-    # representation allows in a dense, relaxed liquid (net forces far below
-    # the pair forces): pair displacements come from 32-bit fixed-point
-    # coordinates (an error up to sqrt(3) L 2^-32 per pair) and each pair
-    # force from ~10 binary32 operations summed over a few dozen pairs per
-    # lane (3e-6 |F_ij|). A particle above it must owe the excess to
-    # partners at a cutoff tie (found by brute force for those few only).
-    rms = math.sqrt(float((fo ** 2).sum(axis=1).mean()))
-    scale = np.maximum(np.maximum(np.linalg.norm(fo, axis=1), rms), 1.0)
-    allow = representation_allowance(xh, w.species, w.box, w.params)
-    err = np.linalg.norm(f - fo, axis=1)
-    over = np.nonzero(err > TOL_F[FP32] * scale + allow)[0]
-    assert len(over) <= 100, len(over)
-    p = w.params
-    for i in over:
-        d = xh - xh[i]
-        d -= w.box * np.rint(d / w.box)
-        r2 = (d * d).sum(axis=1)
-        ab = w.species[i] * 2 + w.species
-        rc = np.asarray(p.rcut)[ab]
-        near = np.nonzero((np.abs(r2 - rc * rc) <= 2e-6 * rc * rc) & (np.arange(len(xh)) != i))[0]
-        tie = sum(1.001 * abs(oracle.pair_fscalar(rc[j] * (1 - 1e-15), int(ab[j]), p)) * rc[j] for j in near)
-        assert err[i] - tie <= TOL_F[FP32] * scale[i] + allow[i], (i, err[i], tie)
-    assert abs(o["U"] - Uo) <= TOL_E[FP32] * abs(Uo)
-    assert abs(o["W"] - Wo) <= TOL_E[FP32] * abs(Wo)
+    # Reference: the oracle's FP64 forces of the fixed-point positions the
+    # FP32 path holds. In this dense relaxed liquid (rho = 1.2 after steepest
+    # descent) the net forces are ~1/50 of the pair forces that form them:
+    # binary32 rounds r^2 to 2^-24 relative, which the r^-13 repulsion
+    # amplifies ~6.5-fold per pair, so each pair force carries ~4e-7 of its
+    # magnitude and a particle's error is set by the sum of its pair-force
+    # magnitudes A_i, not by the net force. The bound is therefore 1e-5 of
+    # A_i (``cond``); the rms-relative and per-particle errors are printed.
+    ref, Uo, Wo, A = reference(xh, w.species, w.box, w.params, FP32)
+    m = report("mixture n=4000000 relaxed", force_errors(f, ref, A, tie_allowance(xh, w.species, w.box,
+                                                                                   w.params, FP32)))
+    assert m["cond"] <= TOL_F[FP32], m
+    eu, ew = energy_errors("mixture n=4000000 relaxed", o, Uo, Wo, len(xh))
+    assert eu <= TOL_E[FP32] and ew <= TOL_E[FP32]
     oc, on = oracle.build_lists(xh, w.species, w.box, w.params, mode=1, cap=160)
     assert np.array_equal(cnt, oc)
     rng = np.random.default_rng(2)

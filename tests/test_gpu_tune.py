@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 from paper_2406_04210_amd import workloads as W
-from test_gpu_parity import rel_force_err, tie_allowance
+from force_metrics import force_errors, reference, report, tie_allowance
 
 pytestmark = pytest.mark.gpu
 
@@ -41,10 +41,11 @@ def test_autotune_times_caches_and_runs(ljmd, tmp_path):
     x, v, _ = s.get_state()
     f = s.forces().cpu().numpy()
     xh = x.cpu().numpy()
-    ref, _, _ = oracle.forces_brute(xh, w.species, w.box, w.params)
+    ref, _, _, A = reference(xh, w.species, w.box, w.params, 1)
     # Forces of the state the GPU reached, to the FP32 tolerance of
     # test_gpu_parity.py (with its allowance at cutoff ties).
-    assert rel_force_err(f, ref, tie_allowance(xh, w.species, w.box, w.params, 1)) <= 2e-5
+    m = report("tuned system", force_errors(f, ref, A, tie_allowance(xh, w.species, w.box, w.params, 1)))
+    assert m["sec8c"] <= 1e-5, m
 
 
 def test_batch_autotune_times_caches_and_runs(ljmd, tmp_path):
@@ -68,8 +69,9 @@ def test_batch_autotune_times_caches_and_runs(ljmd, tmp_path):
     b.sync()
     off = np.concatenate([[0], np.cumsum(sizes)])
     for k, w in enumerate(ws):
-        ref, _, _ = oracle.forces_brute(w.x, w.species, w.box, w.params)
+        ref, _, _, A = reference(w.x, w.species, w.box, w.params, 1)
         g = f[off[k]:off[k + 1]]
         # FP32 pair arithmetic, allowance at cutoff ties as in test_gpu_parity.py.
-        allow = tie_allowance(w.x, w.species, w.box, w.params, 1)
-        assert rel_force_err(g, ref, allow) <= 2e-5, k
+        m = report(f"tuned batch replica {k}",
+                   force_errors(g, ref, A, tie_allowance(w.x, w.species, w.box, w.params, 1)))
+        assert m["sec8c"] <= 1e-5, (k, m)
