@@ -74,7 +74,7 @@ struct Ctl {
     int32_t max_fill;     // longest current list (computed on request)
     int64_t rebuilds;     // list builds since set_state
     unsigned long long fmax[2];  // steepest descent: max |F| (double bits), by iteration parity
-    int32_t pad[2];
+    int64_t halt;         // 1 + step id of the first step kernel that found an error latched (0: none)
     uint32_t nlq[8];      // list-build work queues (next cell), one per XCD; reset before each build
     double last[kNP];     // observables of the last flushed step: U, W, K, px, py, pz, rebuilt, step
 };
@@ -262,6 +262,20 @@ __device__ inline int cell_of_q(uint32_t qx, uint32_t qy, uint32_t qz, const Box
     *cy = iy;
     *cz = iz;
     return rank_of[(ix * b.nc[1] + iy) * b.nc[2] + iz];
+}
+
+// Once an error is latched (list or cell overflow, non-finite position) no
+// kernel changes the state any more, so that no step runs on a truncated
+// list: the kernels return at once, and the first step kernel to see the
+// error records its step (halt = step + 1), from which the host redoes the
+// run after growing the list. The flags are written by earlier kernels of
+// the stream (or by this kernel, for a non-finite position, after which the
+// state is lost anyway), so every block of a launch sees the same value.
+__device__ inline bool halted(const Ctl *ctl) { return ctl->flags != 0u; }
+__device__ inline bool halted_record(Ctl *ctl, int64_t step, bool recorder) {
+    if (ctl->flags == 0u) return false;
+    if (recorder && threadIdx.x == 0 && ctl->halt == 0) ctl->halt = step + 1;
+    return true;
 }
 
 // Whether the list is rebuilt before the force evaluation of a step: forced

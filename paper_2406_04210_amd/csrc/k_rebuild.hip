@@ -120,7 +120,7 @@ template <int PREC>
 __global__ __launch_bounds__(kRbBlock) void k_bin(State st, Geom g, BoxC box, int cur, int64_t step,
                                                 int forced, float thr2) {
     if (blockIdx.x == 0 && threadIdx.x == 0) st.ctl->maxd[(step + 1) & 1] = 0u;
-    if (!rebuild_due(st.ctl, step, forced, thr2)) return;
+    if (halted(st.ctl) || !rebuild_due(st.ctl, step, forced, thr2)) return;
     if (blockIdx.x == 0 && threadIdx.x < 8) st.ctl->nlq[threadIdx.x] = 0u;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.n; i += stride)
@@ -158,7 +158,7 @@ __device__ inline void canon_cell(const State &st, const Geom &g, int64_t c, typ
 template <int PREC>
 __global__ __launch_bounds__(kRbBlock) void k_canon(State st, Geom g, BoxC box, int64_t step,
                                                  int forced, float thr2) {
-    if (!rebuild_due(st.ctl, step, forced, thr2)) return;
+    if (halted(st.ctl) || !rebuild_due(st.ctl, step, forced, thr2)) return;
     using T = typename CellRec<PREC>::T;
     extern __shared__ int4 sm_raw[];
     const int wv = threadIdx.x >> 6, W = blockDim.x >> 6;
@@ -206,7 +206,10 @@ __device__ inline void scan_cells(const State &st, const Geom &g, int64_t c_off,
     }
 }
 
-__global__ __launch_bounds__(1024) void k_scan(State st, Geom g, int ncell) { scan_cells(st, g, 0, ncell, 0); }
+__global__ __launch_bounds__(1024) void k_scan(State st, Geom g, int ncell) {
+    if (halted(st.ctl)) return;
+    scan_cells(st, g, 0, ncell, 0);
+}
 
 // Resort views of the scratch region (one copy of every per-particle array).
 struct ResortView {
@@ -254,6 +257,7 @@ template <int PREC>
 __global__ __launch_bounds__(kBlock) void k_resort_gather(State st, Geom g, BoxC box, int cur,
                                                           ResortView sv) {
     using CR = CellRec<PREC>;
+    if (halted(st.ctl)) return;
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int64_t c = t / g.cell_cap;
     const int k = (int)(t - c * g.cell_cap);
@@ -288,7 +292,7 @@ __global__ __launch_bounds__(kBlock) void k_resort_gather(State st, Geom g, BoxC
 template <int PREC>
 __global__ __launch_bounds__(kBlock) void k_resort_copy(State st, Geom g, int cur, ResortView sv) {
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (s >= g.n) return;
+    if (s >= g.n || halted(st.ctl)) return;
     if constexpr (PREC == LJMD_FP64) {
         st.rec64[cur][s] = sv.rec64[s];
         st.vel64[s] = sv.vel64[s];
@@ -631,7 +635,7 @@ template <int PREC, int NS, bool QC>
 __global__ __launch_bounds__(kNlWaves * kWave) void k_nlist(State st, Geom g, BoxC box, PairC pc, int cur,
                                                             int64_t step, int forced, float thr2) {
     (void)cur;
-    if (!rebuild_due(st.ctl, step, forced, thr2)) return;
+    if (halted(st.ctl) || !rebuild_due(st.ctl, step, forced, thr2)) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) st.ctl->rebuilds += 1;
     const int wv = threadIdx.x >> 6, W = blockDim.x >> 6;
     const int tw = gridDim.x * W;
@@ -696,7 +700,7 @@ __global__ __launch_bounds__(1024) void k_batch_plan(State st, const SysC *sys, 
     int64_t np = 0, nc = 0;
     for (int s = s0; s < s1; ++s) {
         Ctl *ctl = st.ctl + s;
-        const bool d = rebuild_due(ctl, step, forced, thr2);
+        const bool d = !halted(ctl) && rebuild_due(ctl, step, forced, thr2);
         ctl->maxd[(step + 1) & 1] = 0u;
         bp.due[s] = d ? 1 : 0;
         if (d) {

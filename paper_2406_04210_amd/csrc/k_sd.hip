@@ -45,6 +45,7 @@ __global__ __launch_bounds__(kBlock) void k_sd_force(SdArgs sa) {
     const int l = lane & (lanes - 1);
     const int64_t i = (chunk << (6 - lg)) + (lane >> lg);
     const bool valid = i < a.g.n;
+    if (halted_record(st.ctl, a.step, blockIdx.x == 0)) return;
     // After a rebuild, clear the cell counters for the next binning.
     if (rebuild_due(st.ctl, a.step, a.forced, a.dyn.thr2)) {
         const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
@@ -134,6 +135,7 @@ template <int PREC>
 __global__ __launch_bounds__(kBlock) void k_sd_move(SdArgs sa) {
     const StepArgs &a = sa.s;
     const State &st = a.st;
+    if (halted(st.ctl)) return;
     const unsigned long long fbits = st.ctl->fmax[a.step & 1];
     const double fmax = __longlong_as_double((long long)fbits);
     if (blockIdx.x == 0 && threadIdx.x == 0) {

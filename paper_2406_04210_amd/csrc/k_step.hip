@@ -106,6 +106,7 @@ __device__ inline void step_ds_body(const StepArgs &a, const BoxC &box, Ctl *ctl
     const int l = lane % LANES;
     const int64_t i = chunk * P + lane / LANES;
     const bool valid = i < i_end;
+    if (halted_record(ctl, a.step, bj == 0)) return;
     step_housekeeping(a, ctl, c_lo, c_hi, bj, nbj, rebuilt);
 
     const int4 *__restrict__ rec = st.recq[a.cur];
@@ -360,6 +361,7 @@ __global__ __launch_bounds__(kBlockF64) void k_step_fp64(StepArgs a) {
     const int l = lane % LANES;
     const int64_t i = chunk * P + lane / LANES;
     const bool valid = i < a.g.n;
+    if (halted_record(a.st.ctl, a.step, blockIdx.x == 0)) return;
     step_housekeeping(a, a.st.ctl, 0, a.box.ncell, blockIdx.x, gridDim.x, a.st.rebuilt + a.slot);
 
     const double4 *__restrict__ rec = st.rec64[a.cur];
@@ -475,6 +477,7 @@ __global__ __launch_bounds__(kBlockF64) void k_step_fp64(StepArgs a) {
 template <int PREC>
 __device__ inline void integrate_body(const StepArgs &a, const BoxC &box, Ctl *ctl, int64_t i_end) {
     const State &st = a.st;
+    if (halted(ctl)) return;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     uint32_t dm = 0u;
     if (i < i_end) {

@@ -72,6 +72,11 @@ struct ljmd_ctx {
     std::vector<std::pair<int, size_t>> ev_marks;  // (family, index of start event)
     double ms[LJMD_NKT] = {};
     int64_t count[LJMD_NKT] = {};
+    // The workspace: lists start at off_nbr and may grow to its end.
+    uint8_t *ws = nullptr;
+    size_t ws_bytes = 0, off_nbr = 0;
+    int64_t npad = 0;
+    int32_t recoveries = 0;  // list overflows recovered since ljmd_create
     // Bumped by every call that changes the dynamical state or the potential.
     uint64_t gen = 0;
     AdjRecord adj;
@@ -163,6 +168,7 @@ void grid_dims(const ljmd_params *p, int nc[3]) {
 struct Plan {
     int64_t npad;
     int32_t cap, cell_cap, lanes;
+    int32_t cap_reserve;  // list slots per particle the workspace holds (>= cap): room to grow
     int nc[3];
     int ncell;
     int max_blocks;
@@ -174,6 +180,9 @@ struct Plan {
 };
 
 inline size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Bytes of the neighbour lists of npad slots with cap entries each.
+inline size_t list_bytes(int64_t npad, int32_t cap) { return sizeof(int32_t) * ((size_t)npad * cap + kListPad); }
 
 int32_t round_up(int32_t v, int32_t m) { return (v + m - 1) / m * m; }
 
@@ -197,6 +206,14 @@ Plan make_plan(const ljmd_params *p) {
     // Measured on MI355X at N=256,000: 2 lanes per particle for FP32, 4 for FP64.
     pl.lanes = p->lanes != 0 ? p->lanes : (p->precision == LJMD_FP64 ? 4 : 2);
     pl.cap = std::max<int32_t>(16, round_up(cap, cap_granule(pl.lanes)));
+    // With an automatic capacity the workspace holds twice the initial list
+    // (up to 4096 slots), so that an overflow can be recovered by growing the
+    // list in place; an explicit capacity reserves exactly itself (a larger
+    // workspace passed to ljmd_create adds room).
+    pl.cap_reserve = p->nbr_capacity == 0
+                         ? std::max(pl.cap, std::min<int32_t>(4096 / cap_granule(pl.lanes) * cap_granule(pl.lanes),
+                                                              2 * pl.cap))
+                         : pl.cap;
     int32_t cc = p->cell_capacity;
     if (cc == 0) {
         double cellv = vol / pl.ncell;
@@ -240,9 +257,6 @@ void lay_out(Plan &pl, int prec, int nctl) {
     pl.off_id = take(sizeof(int32_t) * N);
     pl.off_xref = take(sizeof(int4) * N);
     pl.off_cnt = take(sizeof(int32_t) * N);
-    // Lists, plus one row block past the end: the force kernel reads a few
-    // entries beyond a list (they hold valid indices and are not used).
-    pl.off_nbr = take(sizeof(int32_t) * ((size_t)N * pl.cap + kListPad));
     pl.off_ccount = take(sizeof(int32_t) * pl.ncell);
     pl.off_cmem = take(cell_rec_bytes(prec) * (size_t)pl.ncell * pl.cell_cap);
     pl.off_cstart = take(sizeof(int32_t) * (pl.ncell + 1));
@@ -252,6 +266,10 @@ void lay_out(Plan &pl, int prec, int nctl) {
     pl.off_part = take(sizeof(double) * (size_t)kRing * pl.max_blocks * kNP);
     pl.off_rebuilt = take(sizeof(int32_t) * kRing);
     pl.off_ctl = take(sizeof(Ctl) * (size_t)nctl);
+    // Lists last, so that a larger workspace is room for longer lists; one
+    // row block past the end: the force kernel reads a few entries beyond a
+    // list (they hold valid indices and are not used).
+    pl.off_nbr = take(list_bytes(N, std::max(pl.cap, pl.cap_reserve)));
     pl.total = off;
 }
 
@@ -478,6 +496,57 @@ struct RunOpts {
     size_t frame_stride = 0;
 };
 
+// Steps s0 .. s0 + n - 1 from a state at rest before the list build of step
+// s0: positions x_{s0} in record buffer c->cur, velocities half kicked. Row
+// k of obs_dev (nullable) receives the observables of step s0 + k. With
+// frames, every step writes its new records straight into frame k0 + k + 2
+// (k0: the frame offset of step s0 - 1's records). Leaves c->cur at the last
+// step's records and c->step at s0 + n - 1.
+int step_range(ljmd_ctx *c, int64_t s0, int64_t n, double *obs_dev, const RunOpts &o, bool force_first,
+               int64_t k0) {
+    hipError_t e;
+    const bool redirect = o.frames != nullptr;
+    Launch L = launcher(c);
+    int64_t first = s0;
+    int pending = 0;
+    int64_t row = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t s = s0 + k;
+        const bool resort = o.allow_resort && c->p.sort_interval > 0 && s % c->p.sort_interval == 0;
+        const int forced = (resort || (force_first && k == 0)) ? 1 : 0;
+        int r = rebuild_sequence(c, s, forced, resort);
+        if (r) return r;
+        const bool last = k == n - 1;
+        const bool observe = obs_dev != nullptr || (last && o.final_obs);
+        const int mode = kFinalize | (last ? kStoreForce : kIntegrate) | (observe ? kObserve : 0);
+        // Records of step s are frame k0 + k + 1; the integrate half writes frame k0 + k + 2.
+        if (redirect && !last) set_rec_ptr(c, c->cur ^ 1, o.frames + (size_t)(k0 + k + 2) * o.frame_stride);
+        L = launcher(c);
+        {
+            Bracket b(c, 0);
+            if ((e = launch_step(L, s, forced, mode, (int)(s % kRing))) != hipSuccess)
+                return hip_fail(c, e, "step");
+        }
+        if (!last) c->cur ^= 1;
+        ++pending;
+        if (obs_dev && (pending == kRing || last)) {
+            Bracket b(c, 3);
+            if ((e = launch_obs_reduce(L, first, pending, c->nblocks, obs_dev, row)) != hipSuccess)
+                return hip_fail(c, e, "obs");
+            row += pending;
+            first += pending;
+            pending = 0;
+        }
+    }
+    if (!obs_dev && o.final_obs) {
+        Bracket b(c, 3);
+        if ((e = launch_obs_reduce(L, s0 + n - 1, 1, c->nblocks, nullptr, 0)) != hipSuccess)
+            return hip_fail(c, e, "obs");
+    }
+    c->step = s0 + n - 1;
+    return LJMD_OK;
+}
+
 // nsteps velocity-Verlet steps from a state at rest (positions, velocities
 // and forces of step c->step): integrate from the stored forces, then per
 // step the rebuild sequence and the fused step kernel.
@@ -499,42 +568,11 @@ int run_steps(ljmd_ctx *c, int64_t nsteps, double *obs_dev, const RunOpts &o) {
         if ((e = launch_integrate(L, c->step)) != hipSuccess) return hip_fail(c, e, "integrate");
     }
     c->cur ^= 1;
-    int64_t first = c->step + 1;
-    int pending = 0;
-    int64_t row = 0;
-    for (int64_t k = 0; k < nsteps; ++k) {
-        const int64_t s = c->step + 1 + k;
-        const bool resort = o.allow_resort && c->p.sort_interval > 0 && s % c->p.sort_interval == 0;
-        const int forced = (resort || (o.force_first && k == 0)) ? 1 : 0;
-        int r = rebuild_sequence(c, s, forced, resort);
-        if (r) return r;
-        const bool last = k == nsteps - 1;
-        const bool observe = obs_dev != nullptr || (last && o.final_obs);
-        const int mode = kFinalize | (last ? kStoreForce : kIntegrate) | (observe ? kObserve : 0);
-        // Records of step s are frame k + 1; the integrate half writes frame k + 2.
-        if (redirect && !last) set_rec_ptr(c, c->cur ^ 1, o.frames + (size_t)(k + 2) * o.frame_stride);
-        L = launcher(c);
-        {
-            Bracket b(c, 0);
-            if ((e = launch_step(L, s, forced, mode, (int)(s % kRing))) != hipSuccess)
-                return hip_fail(c, e, "step");
-        }
-        if (!last) c->cur ^= 1;
-        ++pending;
-        if (obs_dev && (pending == kRing || last)) {
-            Bracket b(c, 3);
-            if ((e = launch_obs_reduce(L, first, pending, c->nblocks, obs_dev, row)) != hipSuccess)
-                return hip_fail(c, e, "obs");
-            row += pending;
-            first += pending;
-            pending = 0;
-        }
-    }
-    if (!obs_dev && o.final_obs) {
-        Bracket b(c, 3);
-        if ((e = launch_obs_reduce(L, c->step + nsteps, 1, c->nblocks, nullptr, 0)) != hipSuccess)
-            return hip_fail(c, e, "obs");
-    }
+    RunOpts so = o;
+    if (!redirect) so.frames = nullptr;
+    const int64_t s0 = c->step + 1;
+    int r = step_range(c, s0, nsteps, obs_dev, so, o.force_first, 0);
+    if (r) return r;
     if (redirect) {
         void *final_frame = rec_ptr(c, c->cur);
         own.restore();
@@ -542,9 +580,72 @@ int run_steps(ljmd_ctx *c, int64_t nsteps, double *obs_dev, const RunOpts &o) {
             hipSuccess)
             return hip_fail(c, e, "frame copy");
     }
-    c->step += nsteps;
     // Keep the event pool bounded on long profiled runs.
     if (c->profiling && c->ev_used > 8192) return resolve_times(c);
+    return LJMD_OK;
+}
+
+// ---- list overflow: freeze, grow, redo ---------------------------------------
+
+// Control words after the work enqueued so far (synchronises).
+int read_ctl(ljmd_ctx *c, Ctl *h) {
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "synchronise");
+    e = hipMemcpy(h, c->st.ctl, sizeof *h, hipMemcpyDeviceToHost);
+    return e == hipSuccess ? LJMD_OK : hip_fail(c, e, "read control words");
+}
+
+int flags_status(ljmd_ctx *c, uint32_t flags) {
+    if (flags & kErrNaN) return fail(c, LJMD_ENAN, "non-finite position detected");
+    if (flags & kErrCell) return fail(c, LJMD_ECELL, "a cell exceeded cell_capacity=%d", c->g.cell_cap);
+    if (flags & kErrList) return fail(c, LJMD_ENLIST, "a neighbour list exceeded nbr_capacity=%d", c->g.cap);
+    return LJMD_OK;
+}
+
+// Largest list capacity the workspace holds.
+int32_t cap_limit(const ljmd_ctx *c) {
+    const size_t room = c->ws_bytes - c->off_nbr;
+    const size_t pad = sizeof(int32_t) * kListPad;
+    if (room <= pad) return 0;
+    const int64_t slots = (int64_t)((room - pad) / sizeof(int32_t) / (size_t)c->npad);
+    const int32_t gr = cap_granule(c->g.lanes);
+    return (int32_t)std::min<int64_t>(4096, slots / gr * gr);
+}
+
+// After a list overflow (lists of `need` entries): a larger capacity within
+// the workspace, the list area cleared to valid indices, the error and halt
+// words and the cell counters cleared. LJMD_ENLIST if the workspace is too
+// small.
+int grow_lists(ljmd_ctx *c, int32_t need) {
+    const int32_t gr = cap_granule(c->g.lanes);
+    const int32_t want = round_up(std::max<int32_t>(need + 16, (int32_t)std::ceil(1.25 * need)), gr);
+    const int32_t lim = cap_limit(c);
+    if (need > lim)
+        return fail(c, LJMD_ENLIST, "a neighbour list of %d entries exceeds the %d slots the workspace holds "
+                                    "(nbr_capacity=%d)", need, lim, c->g.cap);
+    c->g.cap = std::min(want, lim);
+    hipError_t e = hipMemsetAsync(c->st.nbr, 0, list_bytes(c->npad, c->g.cap), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(&c->st.ctl->flags, 0, sizeof(uint32_t), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(&c->st.ctl->halt, 0, sizeof(int64_t), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->st.cell_count, 0, sizeof(int32_t) * c->box.ncell, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "grow lists");
+    ++c->recoveries;
+    return LJMD_OK;
+}
+
+// Check the latched errors; for a list overflow that the workspace can hold,
+// grow the lists and set *redo (the caller repeats from ctl.halt). Any other
+// error is returned.
+int check_overflow(ljmd_ctx *c, Ctl *h, bool *redo) {
+    *redo = false;
+    hipError_t e = launch_max_fill(launcher(c));
+    if (e != hipSuccess) return hip_fail(c, e, "max_fill");
+    int r = read_ctl(c, h);
+    if (r) return r;
+    if (h->flags == 0u) return LJMD_OK;
+    if (h->flags != kErrList) return flags_status(c, h->flags);
+    if ((r = grow_lists(c, h->max_fill))) return r;
+    *redo = true;
     return LJMD_OK;
 }
 
@@ -793,6 +894,7 @@ BatchLayout batch_layout(const BatchGeom &bg, int nsys) {
     pl.npad = bg.nslots;
     pl.ncell = (int)bg.ncell;
     pl.cap = bg.cap;
+    pl.cap_reserve = bg.cap;
     pl.cell_cap = bg.cell_cap;
     pl.lanes = bg.lanes;
     pl.max_blocks = bg.nblocks;
@@ -894,6 +996,10 @@ int ljmd_create(const ljmd_params *p, void *ws, size_t bytes, void *stream, ljmd
             g.ncu = ncu;
     }
     c->nblocks = pl.max_blocks;
+    c->ws = (uint8_t *)ws;
+    c->ws_bytes = bytes;
+    c->off_nbr = pl.off_nbr;
+    c->npad = pl.npad;
     uint8_t *b = (uint8_t *)ws;
     State &s = c->st;
     bind_state(s, pl, b, p->precision);
@@ -910,8 +1016,7 @@ int ljmd_create(const ljmd_params *p, void *ws, size_t bytes, void *stream, ljmd
     if (e == hipSuccess) e = hipMemsetAsync(s.ctl, 0, sizeof(Ctl), c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s.nbr_cnt, 0, sizeof(int32_t) * pl.npad, c->stream);
     // Every list slot holds a valid particle index from the start (0).
-    if (e == hipSuccess)
-        e = hipMemsetAsync(s.nbr, 0, sizeof(int32_t) * ((size_t)pl.npad * pl.cap + kListPad), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s.nbr, 0, list_bytes(pl.npad, pl.cap), c->stream);
     // The rank table comes from pageable host memory: finish before it goes away.
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
@@ -941,10 +1046,19 @@ int ljmd_set_state(ljmd_ctx *c, const double *x, const double *v, const int32_t 
     if ((e = launch_set_state(L, x, v, species)) != hipSuccess) return hip_fail(c, e, "set_state");
     int r = rebuild_sequence(c, 0, 1, true);
     if (r) return r;
-    L = launcher(c);
-    if ((e = launch_step(L, 0, 1, kStoreForce | kObserve, 0)) != hipSuccess) return hip_fail(c, e, "force");
-    if ((e = launch_obs_reduce(L, 0, 1, c->nblocks, nullptr, 0)) != hipSuccess)
-        return hip_fail(c, e, "obs");
+    for (;;) {
+        L = launcher(c);
+        if ((e = launch_step(L, 0, 1, kStoreForce | kObserve, 0)) != hipSuccess) return hip_fail(c, e, "force");
+        if ((e = launch_obs_reduce(L, 0, 1, c->nblocks, nullptr, 0)) != hipSuccess)
+            return hip_fail(c, e, "obs");
+        // A list overflow of the first build: grow the lists and build again
+        // (the positions stay where the state load put them).
+        Ctl h;
+        bool redo = false;
+        if ((r = check_overflow(c, &h, &redo))) return r;
+        if (!redo) break;
+        if ((r = rebuild_sequence(c, 0, 1, false))) return r;
+    }
     c->have_state = true;
     return LJMD_OK;
 }
@@ -955,7 +1069,27 @@ int ljmd_run(ljmd_ctx *c, int64_t nsteps, double *obs_dev) {
     if (nsteps < 0) return fail(c, LJMD_EINVAL, "nsteps < 0");
     if (nsteps == 0) return LJMD_OK;
     ++c->gen;
-    return run_steps(c, nsteps, obs_dev, RunOpts{});
+    const int64_t first = c->step + 1, last = c->step + nsteps;
+    const int cur_first = c->cur ^ 1;  // the records of step `first`, written by the integrate half
+    int r = run_steps(c, nsteps, obs_dev, RunOpts{});
+    if (r) return r;
+    // One wait at the end: a list that overflowed froze every later kernel
+    // (no step ran on a truncated list); grow the lists and redo from the
+    // step that stopped, until the run is through or the workspace is full.
+    for (;;) {
+        Ctl h;
+        bool redo = false;
+        if ((r = check_overflow(c, &h, &redo))) return r;
+        if (!redo) return LJMD_OK;
+        const int64_t hs = h.halt - 1;
+        if (h.halt == 0 || hs < first || hs > last)
+            return fail(c, LJMD_ENLIST, "internal: list overflow without a halted step in the run");
+        c->cur = cur_first ^ (int)((hs - first) & 1);
+        RunOpts o;
+        if ((r = step_range(c, hs, last - hs + 1, obs_dev ? obs_dev + (size_t)(hs - first) * LJMD_NOBS : nullptr, o,
+                            true, 0)))
+            return r;
+    }
 }
 
 int ljmd_set_profiling(ljmd_ctx *c, int enable) {
@@ -990,22 +1124,41 @@ int ljmd_minimize_sd(ljmd_ctx *c, int32_t nsteps, double max_disp, double clamp,
     if (e != hipSuccess) return hip_fail(c, e, "minimize_sd memset");
     // Iteration s uses the control-word parity of id c->step + 1 + s; the
     // final state load below uses c->step again, as after ljmd_set_state.
-    for (int32_t s = 0; s < nsteps; ++s) {
-        const int64_t t = c->step + 1 + s;
-        int r = rebuild_sequence(c, t, s == 0 ? 1 : 0, false);
+    // After a list overflow (every later kernel frozen) the lists grow and
+    // the iterations resume from the one that stopped.
+    int32_t s_from = 0;
+    bool final_only = false;
+    for (;;) {
+        for (int32_t s = final_only ? nsteps : s_from; s < nsteps; ++s) {
+            const int64_t t = c->step + 1 + s;
+            const int first = s == s_from ? 1 : 0;
+            int r = rebuild_sequence(c, t, first, false);
+            if (r) return r;
+            if ((e = launch_sd(launcher(c), t, first, s, max_disp, clamp, fmax_dev)) != hipSuccess)
+                return hip_fail(c, e, "steepest descent");
+        }
+        int r = rebuild_sequence(c, c->step, 1, true);
         if (r) return r;
-        if ((e = launch_sd(launcher(c), t, s == 0 ? 1 : 0, s, max_disp, clamp, fmax_dev)) !=
-            hipSuccess)
-            return hip_fail(c, e, "steepest descent");
+        Launch L = launcher(c);
+        if ((e = launch_step(L, c->step, 1, kStoreForce | kObserve, (int)(c->step % kRing))) != hipSuccess)
+            return hip_fail(c, e, "force");
+        if ((e = launch_obs_reduce(L, c->step, 1, c->nblocks, nullptr, 0)) != hipSuccess)
+            return hip_fail(c, e, "obs");
+        Ctl h;
+        bool redo = false;
+        if ((r = check_overflow(c, &h, &redo))) return r;
+        if (!redo) return LJMD_OK;
+        // halt = 1 + the step id that stopped: c->step for the final force,
+        // c->step + 1 + s for iteration s.
+        if (h.halt == c->step + 1) {
+            final_only = true;
+        } else if (h.halt >= c->step + 2 && h.halt <= c->step + 1 + nsteps) {
+            s_from = (int32_t)(h.halt - c->step - 2);
+            final_only = false;
+        } else {
+            return fail(c, LJMD_ENLIST, "internal: list overflow without a halted iteration");
+        }
     }
-    int r = rebuild_sequence(c, c->step, 1, true);
-    if (r) return r;
-    Launch L = launcher(c);
-    if ((e = launch_step(L, c->step, 1, kStoreForce | kObserve, (int)(c->step % kRing))) != hipSuccess)
-        return hip_fail(c, e, "force");
-    if ((e = launch_obs_reduce(L, c->step, 1, c->nblocks, nullptr, 0)) != hipSuccess)
-        return hip_fail(c, e, "obs");
-    return LJMD_OK;
 }
 
 int ljmd_get_state(ljmd_ctx *c, double *x, double *v, int32_t *img) {
@@ -1038,12 +1191,7 @@ int ljmd_sync_status(ljmd_ctx *c) {
     uint32_t flags = 0;
     e = hipMemcpy(&flags, &c->st.ctl->flags, sizeof flags, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(c, e, "read flags");
-    if (flags & kErrNaN) return fail(c, LJMD_ENAN, "non-finite position detected");
-    if (flags & kErrCell)
-        return fail(c, LJMD_ECELL, "a cell exceeded cell_capacity=%d", c->g.cell_cap);
-    if (flags & kErrList)
-        return fail(c, LJMD_ENLIST, "a neighbour list exceeded nbr_capacity=%d", c->g.cap);
-    return LJMD_OK;
+    return flags_status(c, flags);
 }
 
 int ljmd_observables(ljmd_ctx *c, ljmd_obs *out) {
@@ -1165,6 +1313,7 @@ int ljmd_vv_forward(ljmd_ctx *c, int32_t nsteps, int32_t ckpt_every, int32_t fla
     o.force_first = true;
     o.allow_resort = false;
     o.frame_stride = P.frame_stride;
+    for (;;) {
     for (int32_t seg = 0; seg < P.nseg; ++seg) {
         int r = ckpt_copy(c, ws + P.off_ckpt + (size_t)seg * P.ckpt_stride, true);
         if (r) return r;
@@ -1189,6 +1338,15 @@ int ljmd_vv_forward(ljmd_ctx *c, int32_t nsteps, int32_t ckpt_every, int32_t fla
     int r = ckpt_copy(c, ws + P.off_ckpt + (size_t)P.nseg * P.ckpt_stride, true);
     if (r) return r;
     if ((r = rebuild_at_rest(c, c->step))) return r;
+    // A list overflow froze the rollout: grow the lists and run it again
+    // from the first stored state.
+    Ctl h;
+    bool redo = false;
+    if ((r = check_overflow(c, &h, &redo))) return r;
+    if (!redo) break;
+    if ((r = ckpt_copy(c, ws + P.off_ckpt, false))) return r;
+    c->step = step0;
+    }
     c->adj.valid = true;
     c->adj.plan = P;
     c->adj.ws = ws;
@@ -1222,7 +1380,11 @@ int ljmd_vv_backward(ljmd_ctx *c, const double *lam_x, const double *lam_v, doub
     // pointed at it); the context's buffers come back before every segment's
     // recompute, at the end and on any error.
     RecBuffers own(c);
-    Launch L = launcher(c);
+    const int cur_entry = c->cur;
+    const int64_t step_entry = c->step;
+    Launch L;
+    for (;;) {
+    L = launcher(c);
     if ((e = launch_adjoint_vec(L, kOpGatherById, lam_x, nullptr, lx, nullptr, nullptr, 0.0)) != hipSuccess ||
         (e = launch_adjoint_vec(L, kOpGatherById, lam_v, nullptr, lv, nullptr, nullptr, 0.0)) != hipSuccess)
         return hip_fail(c, e, "vv_backward gather");
@@ -1233,6 +1395,7 @@ int ljmd_vv_backward(ljmd_ctx *c, const double *lam_x, const double *lam_v, doub
     o.frames = frames;
     o.frame_stride = P.frame_stride;
     bool first = true;
+    gb = 0;
     const bool reuse = P.reuse_lists();
     std::vector<int32_t> marks;
     if (reuse && P.store_all) {
@@ -1307,6 +1470,21 @@ int ljmd_vv_backward(ljmd_ctx *c, const double *lam_x, const double *lam_v, doub
             first = false;
             gb ^= 1;
         }
+    }
+    // The sweep builds lists at frames the forward run did not: a list that
+    // overflowed there froze the recompute and spoilt the VJP passes. Grow
+    // the lists and sweep again (the cotangent inputs are read again; the
+    // outputs are written only after this check).
+    {
+        Ctl h;
+        bool redo = false;
+        int r = check_overflow(c, &h, &redo);
+        if (r) return r;
+        if (!redo) break;
+        own.restore();
+        c->cur = cur_entry;
+        c->step = step_entry;
+    }
     }
     L = launcher(c);
     if ((e = launch_adjoint_reduce(L, rows, gtheta)) != hipSuccess) return hip_fail(c, e, "vv_backward theta");

@@ -204,7 +204,11 @@ class System:
     """
 
     def __init__(self, n: int, box, p, precision: int = FP32_DS, sort_interval: int = 100,
-                 nbr_capacity: int = 0, cell_capacity: int = 0, lanes: int = 0, device=None):
+                 nbr_capacity: int = 0, cell_capacity: int = 0, lanes: int = 0, device=None,
+                 nbr_capacity_max: int = 0):
+        """nbr_capacity_max > nbr_capacity gives the workspace room for lists of
+        that many entries: a list overflow then grows the lists in place and
+        redoes the steps (ljmd_run), instead of reporting LJMD_ENLIST."""
         import torch
         self.torch = torch
         if not torch.cuda.is_available():
@@ -216,6 +220,9 @@ class System:
         self.box = np.asarray(box, dtype=np.float64)
         _check(check_params(self.params))
         size = workspace_size(self.params)
+        if nbr_capacity_max > 0:
+            room = make_params(n, box, p, precision, sort_interval, nbr_capacity_max, cell_capacity, lanes)
+            size = max(size, workspace_size(room))
         self.workspace = torch.empty(size, dtype=torch.uint8, device=self.device)
         self.stream = torch.cuda.current_stream(self.device)
         ctx = C.c_void_p()

@@ -338,13 +338,67 @@ def test_free_flight_ds_matches_closed_form(ljmd):
     assert err_f32 > 100 * err_ds
 
 
-def test_nbr_overflow_is_reported(ljmd):
+def test_nbr_overflow_without_room_is_reported(ljmd):
+    # An explicit capacity reserves no room to grow: the state load (which
+    # waits for its first list build) reports LJMD_ENLIST.
     w = W.config_small()
     s = ljmd.System(w.n, w.box, w.params, precision=FP64, nbr_capacity=32)
-    s.set_state(w.x, w.v, w.species)
     with pytest.raises(ljmd.LJMDError) as e:
+        s.set_state(w.x, w.v, w.species)
         s.sync()
     assert e.value.code == -5
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_nbr_overflow_recovered_in_state_load_and_run(ljmd, prec):
+    # Capacity 80 holds the lattice's 78 partners but not the liquid's longer
+    # lists; with room for 256 the lists grow in place and the overflowing
+    # steps are redone. The trajectory is bitwise that of a system that had
+    # room from the start (list entries keep their order at any capacity),
+    # and matches the oracle. Capacity 32 already overflows at the state load.
+    w = W.config_small()
+    ref = make_system(ljmd, w.x, w.v, w.species, w.box, w.params, prec, sort_interval=25)
+    obs_ref = ref.run(100).cpu().numpy()
+    x_ref = ref.unwrapped_positions().cpu().numpy()
+    o_ref = ref.observables()
+    for cap in (80, 32):
+        s = make_system(ljmd, w.x, w.v, w.species, w.box, w.params, prec, sort_interval=25, nbr_capacity=cap,
+                        nbr_capacity_max=256)
+        obs = s.run(100).cpu().numpy()
+        s.sync()
+        o = s.observables()
+        print(f"overflow recovery prec={prec} cap={cap}: capacity now {o['nbr_capacity']}, "
+              f"max fill {o['max_fill']} (room-from-start max fill {o_ref['max_fill']})", flush=True)
+        assert o["nbr_capacity"] > cap and o["nbr_capacity"] >= o["max_fill"]
+        xu = s.unwrapped_positions().cpu().numpy()
+        assert np.array_equal(xu, x_ref)
+        # Observables of every step, the redone ones included (the rebuild
+        # counter also counts the build that overflowed).
+        assert np.array_equal(obs[:, [0, 1, 2, 3, 4, 5, 7]], obs_ref[:, [0, 1, 2, 3, 4, 5, 7]])
+    r = oracle.run_nve(w.x, w.v, w.species, w.box, w.params, 100)
+    tol_x = 1e-10 if prec == FP64 else 1e-4
+    assert np.abs(xu - r["x"]).max() <= tol_x
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_nbr_overflow_recovered_in_rollout_and_sweep(ljmd, prec):
+    # The differentiable rollout (forward) and its reverse sweep with lists
+    # that overflow: the forward run is repeated from its first stored state
+    # with longer lists, the sweep checks before writing its outputs; the
+    # gradient equals bitwise that of a system with room from the start.
+    w = W.config_small()
+    rng = np.random.default_rng(5)
+    lam_x, lam_v = rng.standard_normal(w.x.shape), rng.standard_normal(w.x.shape)
+    out = []
+    for cap, room in ((0, 0), (80, 256)):
+        s = make_system(ljmd, w.x, w.v, w.species, w.box, w.params, prec, nbr_capacity=cap, nbr_capacity_max=room)
+        s.vv_forward(60, 10)
+        g = s.vv_backward(lam_x, lam_v)
+        s.sync()
+        out.append([t.cpu().numpy() for t in g] + [s.observables()["nbr_capacity"]])
+    assert out[1][3] > 80
+    for a, b in zip(out[0][:3], out[1][:3]):
+        assert np.array_equal(a, b)
 
 
 @pytest.mark.parametrize("prec", [FP64, FP32])
