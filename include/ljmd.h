@@ -180,6 +180,24 @@ int ljmd_sync_status(ljmd_ctx *ctx);
 /* Synchronise and fill *out with the observables of the current step. */
 int ljmd_observables(ljmd_ctx *ctx, ljmd_obs *out);
 
+/* Stochastic velocity resampling, the Andersen-like ("Boltzmann")
+ * thermostat that the paper combines with velocity Verlet (Sec. 4, "Code
+ * migration"; its truncated-force study varies the temperature, Sec. 5).
+ * After the second half kick of every step s of ljmd_run, each particle
+ * collides with probability rate * dt and then takes a new velocity
+ * sqrt(temperature / m) z, z three standard normal deviates. The draws come
+ * from the counter-based generator Philox4x32-10 (Salmon et al., SC'11)
+ * keyed by seed, with counters (id, s mod 2^32, s / 2^32, 0) and
+ * (id, s mod 2^32, s / 2^32, 1) for the particle's original id: the particle
+ * collides iff the first word is below floor(rate dt 2^32), and z comes from
+ * the Box-Muller transform of the word pairs (w1, w2) and (w3, w4), a word u
+ * read as (u + 1/2) 2^-32. Results therefore depend only on the seed and
+ * not on the particle order or the launch shape. rate = 0 switches it off
+ * (the default). Host-side setting, takes effect from the next step;
+ * LJMD_EINVAL for negative or non-finite values. ljmd_vv_forward refuses
+ * to run while it is on (the dynamics would not be differentiable). */
+int ljmd_set_thermostat(ljmd_ctx *ctx, double temperature, double rate, uint64_t seed);
+
 /* Kernel timing with HIP events recorded on the context's stream around
  * every launch of each kernel family during ljmd_run: [0] the fused step
  * kernel (forces + velocity Verlet + reductions), [1] the rebuild sequence

@@ -65,6 +65,13 @@ struct DynC {
     double mass[2];
     float massf[2];
     float thr2;                      // (skin / 2)^2: rebuild when exceeded
+    // Stochastic velocity resampling (the Andersen-like thermostat): a
+    // particle collides in a step when the first word of its Philox block is
+    // below thermo_thr (probability rate * dt), and then takes the velocity
+    // sqrt(T / m) z, z standard normal.
+    int32_t thermo_on;
+    uint32_t thermo_thr, seed_lo, seed_hi;
+    double thermo_sd[2];             // sqrt(T / m) per species
 };
 
 // Control words in device memory.
@@ -212,6 +219,12 @@ __device__ inline dsf ds_mul(dsf a, float b_hi, float b_lo) {
     float e = fmaf(a.hi, b_hi, -p);
     e = fmaf(a.hi, b_lo, fmaf(a.lo, b_hi, e));
     return fast_two_sum(p, e);
+}
+
+// Double-single pair of an FP64 value: the nearest float and the rounded rest.
+__device__ inline dsf ds_of(double v) {
+    const float h = (float)v;
+    return {h, (float)(v - (double)h)};
 }
 
 // Fixed-point image coordinate of a double-single position (binary32 only):

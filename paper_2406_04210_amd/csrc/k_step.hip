@@ -95,7 +95,10 @@ __device__ inline void step_housekeeping(const StepArgs &a, const Ctl *ctl, int6
 // control words, particles below i_end are real (the rest of the block is
 // padding), and the block is number bj of the nbj blocks that share the
 // clearing of its cells [c_lo, c_hi).
-template <int NS, int LANES, bool Q, bool OBS>
+// TH: the thermostat resamples colliding particles' velocities after
+// "finalize" (a separate instantiation, so that the plain NVE kernel keeps
+// its register budget).
+template <int NS, int LANES, bool Q, bool OBS, bool TH = false>
 __device__ inline void step_ds_body(const StepArgs &a, const BoxC &box, Ctl *ctl, int blk, int64_t i_end,
                                     int64_t c_lo, int64_t c_hi, int bj, int nbj, int32_t *rebuilt) {
     constexpr int P = kWave / LANES;
@@ -281,6 +284,15 @@ __device__ inline void step_ds_body(const StepArgs &a, const BoxC &box, Ctl *ctl
             vx = ds_add(vx, ds_mul_f(chi, clo, fx));
             vy = ds_add(vy, ds_mul_f(chi, clo, fy));
             vz = ds_add(vz, ds_mul_f(chi, clo, fz));
+            if constexpr (TH) {
+                double z[3];
+                if (thermo_draw(a.dyn, (uint32_t)st.id[i], a.step, z)) {
+                    const double sd = by_s(si, a.dyn.thermo_sd);
+                    vx = ds_of(sd * z[0]);
+                    vy = ds_of(sd * z[1]);
+                    vz = ds_of(sd * z[2]);
+                }
+            }
         }
         const float ux = vx.hi + vx.lo, uy = vy.hi + vy.lo, uz = vz.hi + vz.lo;
         if constexpr (OBS) {
@@ -330,11 +342,11 @@ __device__ inline void step_ds_body(const StepArgs &a, const BoxC &box, Ctl *ctl
     block_finish<OBS>(a, ctl, blk, pu, pw, pk, ppx, ppy, ppz, dm);
 }
 
-template <int NS, int LANES, bool Q, bool OBS>
+template <int NS, int LANES, bool Q, bool OBS, bool TH>
 __global__ __launch_bounds__(kBlock) void k_step_ds(StepArgs a) {
     static_assert(OBS || Q, "observables are skipped on the quanta path only");
-    step_ds_body<NS, LANES, Q, OBS>(a, a.box, a.st.ctl, xcd_remap(blockIdx.x, gridDim.x), a.g.n, 0, a.box.ncell,
-                               blockIdx.x, gridDim.x, a.st.rebuilt + a.slot);
+    step_ds_body<NS, LANES, Q, OBS, TH>(a, a.box, a.st.ctl, xcd_remap(blockIdx.x, gridDim.x), a.g.n, 0,
+                                        a.box.ncell, blockIdx.x, gridDim.x, a.st.rebuilt + a.slot);
 }
 
 // A batch of independent one-species cubic systems, each over its own run of
@@ -350,7 +362,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_step(StepArgs a, const SysC *s
 }
 
 // ---------------------------------------------------------------- FP64 ---
-template <int NS, int LANES>
+template <int NS, int LANES, bool TH>
 __global__ __launch_bounds__(kBlockF64) void k_step_fp64(StepArgs a) {
     constexpr int P = kWave / LANES;
     constexpr int WPB = kBlockF64 / kWave;
@@ -430,6 +442,15 @@ __global__ __launch_bounds__(kBlockF64) void k_step_fp64(StepArgs a) {
             v.x += c * fx;
             v.y += c * fy;
             v.z += c * fz;
+            if constexpr (TH) {
+                double z[3];
+                if (thermo_draw(a.dyn, (uint32_t)st.id[i], a.step, z)) {
+                    const double sd = by_s(si, a.dyn.thermo_sd);
+                    v.x = sd * z[0];
+                    v.y = sd * z[1];
+                    v.z = sd * z[2];
+                }
+            }
         }
         pk = 0.5 * mass * fma(v.z, v.z, fma(v.y, v.y, v.x * v.x));
         ppx = mass * v.x;
@@ -602,16 +623,25 @@ hipError_t launch_step(const Launch &L, int64_t step, int forced, int mode, int 
     const bool two = L.g->nspecies == 2;
     const bool quanta = ds && L.box->cubic && L.g->n < kQuantaMaxSlots;
     const bool obs = (mode & kObserve) != 0;
-#define STEP(NS, LN)                                                                            \
-    do {                                                                                        \
-        if (ds && quanta && obs)                                                                \
-            hipLaunchKernelGGL((k_step_ds<NS, LN, true, true>), grid, block, 0, L.stream, a);   \
-        else if (ds && quanta)                                                                  \
-            hipLaunchKernelGGL((k_step_ds<NS, LN, true, false>), grid, block, 0, L.stream, a);  \
-        else if (ds)                                                                            \
-            hipLaunchKernelGGL((k_step_ds<NS, LN, false, true>), grid, block, 0, L.stream, a);  \
-        else                                                                                    \
-            hipLaunchKernelGGL((k_step_fp64<NS, LN>), grid, block, 0, L.stream, a);             \
+    // The thermostat acts on "finalize" only.
+    const bool th = L.dyn->thermo_on && (mode & kFinalize);
+#define STEP_TH(NS, LN, TH)                                                                        \
+    do {                                                                                           \
+        if (ds && quanta && obs)                                                                   \
+            hipLaunchKernelGGL((k_step_ds<NS, LN, true, true, TH>), grid, block, 0, L.stream, a);  \
+        else if (ds && quanta)                                                                     \
+            hipLaunchKernelGGL((k_step_ds<NS, LN, true, false, TH>), grid, block, 0, L.stream, a); \
+        else if (ds)                                                                               \
+            hipLaunchKernelGGL((k_step_ds<NS, LN, false, true, TH>), grid, block, 0, L.stream, a); \
+        else                                                                                       \
+            hipLaunchKernelGGL((k_step_fp64<NS, LN, TH>), grid, block, 0, L.stream, a);            \
+    } while (0)
+#define STEP(NS, LN)              \
+    do {                          \
+        if (th)                   \
+            STEP_TH(NS, LN, true);  \
+        else                      \
+            STEP_TH(NS, LN, false); \
     } while (0)
 #define BY_LANES(NS)                          \
     switch (L.g->lanes) {                     \
@@ -628,6 +658,7 @@ hipError_t launch_step(const Launch &L, int64_t step, int forced, int mode, int 
     }
 #undef BY_LANES
 #undef STEP
+#undef STEP_TH
     return hipGetLastError();
 }
 

@@ -1092,6 +1092,22 @@ int ljmd_run(ljmd_ctx *c, int64_t nsteps, double *obs_dev) {
     }
 }
 
+int ljmd_set_thermostat(ljmd_ctx *c, double temperature, double rate, uint64_t seed) {
+    if (!c) return LJMD_EINVAL;
+    if (!(rate >= 0.0) || !std::isfinite(rate) || !(temperature >= 0.0) || !std::isfinite(temperature))
+        return fail(c, LJMD_EINVAL, "set_thermostat: temperature and rate must be finite and >= 0");
+    DynC &d = c->dyn;
+    // Threshold floor(rate dt 2^32), saturated to the largest 32-bit word.
+    const double t = std::floor(rate * c->p.dt * 4294967296.0);
+    d.thermo_thr = !(t > 0.0) ? 0u : (t >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)t);
+    d.thermo_on = rate > 0.0 ? 1 : 0;
+    d.seed_lo = (uint32_t)seed;
+    d.seed_hi = (uint32_t)(seed >> 32);
+    for (int s = 0; s < 2; ++s) d.thermo_sd[s] = std::sqrt(temperature / d.mass[s]);
+    ++c->gen;
+    return LJMD_OK;
+}
+
 int ljmd_set_profiling(ljmd_ctx *c, int enable) {
     if (!c) return LJMD_EINVAL;
     int r = resolve_times(c);
@@ -1300,6 +1316,8 @@ int ljmd_vv_forward(ljmd_ctx *c, int32_t nsteps, int32_t ckpt_every, int32_t fla
     if (!c->have_state) return fail(c, LJMD_ESTATE, "vv_forward before set_state");
     if (nsteps < 1 || ckpt_every < 1) return fail(c, LJMD_EINVAL, "vv_forward: nsteps and ckpt_every must be >= 1");
     if (flags & ~LJMD_ADJ_STORE_ALL) return fail(c, LJMD_EINVAL, "vv_forward: unknown flags");
+    if (c->dyn.thermo_on)
+        return fail(c, LJMD_EINVAL, "vv_forward: the thermostat makes the dynamics stochastic (switch it off)");
     if (!adj_ws || ((uintptr_t)adj_ws & 255) != 0)
         return fail(c, LJMD_EINVAL, "vv_forward: workspace must be non-NULL and 256-byte aligned");
     const AdjPlan P = adj_plan(&c->p, nsteps, ckpt_every, flags);

@@ -79,6 +79,7 @@ SIGNATURES = {
     "ljmd_minimize_sd": (C.c_int, [_vp, C.c_int32, C.c_double, C.c_double, _dp]),
     "ljmd_sync_status": (C.c_int, [_vp]),
     "ljmd_observables": (C.c_int, [_vp, C.POINTER(Obs)]),
+    "ljmd_set_thermostat": (C.c_int, [_vp, C.c_double, C.c_double, C.c_uint64]),
     "ljmd_set_profiling": (C.c_int, [_vp, C.c_int]),
     "ljmd_kernel_times": (C.c_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "ljmd_last_error": (C.c_char_p, [_vp]),
@@ -310,6 +311,12 @@ class System:
 
     def sync(self):
         _check(lib.ljmd_sync_status(self.ctx), self.ctx)
+
+    def set_thermostat(self, temperature: float, rate: float, seed: int = 0):
+        """Andersen-like velocity resampling at `temperature` with collision
+        rate `rate` per unit time (0 switches it off)."""
+        _check(lib.ljmd_set_thermostat(self.ctx, float(temperature), float(rate), int(seed)), self.ctx)
+        self._gen += 1
 
     def set_profiling(self, enable: bool):
         _check(lib.ljmd_set_profiling(self.ctx, int(bool(enable))), self.ctx)
