@@ -53,11 +53,17 @@ enum ljmd_status {
     LJMD_ECELL = -8    /* a cell exceeded cell_capacity */
 };
 
+/* The float types of the paper's modules (Sec. 3, "Code structure": double,
+ * mixed and single precision). */
 enum ljmd_precision {
     LJMD_FP64 = 0,     /* positions, velocities and pair arithmetic in FP64 */
-    LJMD_FP32_DS = 1   /* FP32 pair arithmetic and force accumulation; positions and
+    LJMD_FP32_DS = 1,  /* FP32 pair arithmetic and force accumulation; positions and
                           velocities carried as double-single (unevaluated sums of
                           two floats); FP64 only in the energy/virial reductions */
+    LJMD_FP32 = 2      /* as LJMD_FP32_DS, but positions and velocities carried as
+                          single floats: each half kick and drift is one binary32
+                          product and one binary32 sum (the paper's GPU single
+                          precision); lists and forces as LJMD_FP32_DS */
 };
 
 /* System and run parameters. Pair tables are indexed [a*2+b] for species

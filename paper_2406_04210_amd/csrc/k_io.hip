@@ -38,20 +38,29 @@ __device__ inline void set_one(const State &st, const Geom &g, const BoxC &box, 
         st.rec64[cur][i] = make_double4(w[0], w[1], w[2], (double)s);
         st.vel64[i] = make_double4(vx, vy, vz, 0.0);
     } else {
+        // Double-single, or (plain FP32) the nearest floats with zero lo
+        // parts, a coordinate that rounds up to the box edge wrapping to 0.
+        constexpr bool plain = PREC == LJMD_FP32;
         float hi[3], lo[3];
         uint32_t q[3];
         for (int k = 0; k < 3; ++k) {
             hi[k] = (float)w[k];
-            lo[k] = (float)(w[k] - (double)hi[k]);
+            if (plain && hi[k] >= box.Lhi[k]) {
+                hi[k] -= box.Lhi[k];
+                im[k] += 1;
+            }
+            lo[k] = plain ? 0.0f : (float)(w[k] - (double)hi[k]);
             q[k] = q_from_ds(hi[k], lo[k], box.S_hi[k], box.S_lo[k]);
         }
+        if (plain) st.img[i] = make_int4(im[0], im[1], im[2], 0);
         st.pos_hi[i] = make_float4(hi[0], hi[1], hi[2], 0.f);
         st.pos_lo[i] = make_float4(lo[0], lo[1], lo[2], 0.f);
         st.recq[cur][i] = make_int4((int)q[0], (int)q[1], (int)q[2], s);
         const float vhx = (float)vx, vhy = (float)vy, vhz = (float)vz;
         st.vel_hi[i] = make_float4(vhx, vhy, vhz, 0.f);
-        st.vel_lo[i] = make_float4((float)(vx - (double)vhx), (float)(vy - (double)vhy),
-                                   (float)(vz - (double)vhz), 0.f);
+        st.vel_lo[i] = plain ? make_float4(0.f, 0.f, 0.f, 0.f)
+                             : make_float4((float)(vx - (double)vhx), (float)(vy - (double)vhy),
+                                           (float)(vz - (double)vhz), 0.f);
     }
 }
 
@@ -299,6 +308,9 @@ hipError_t launch_set_state(const Launch &L, const double *x, const double *v, c
     if (L.g->prec == LJMD_FP64)
         hipLaunchKernelGGL(k_set_state<LJMD_FP64>, dim3(nblk(L.g->n)), dim3(kBlock), 0, L.stream,
                            *L.st, *L.g, *L.box, L.cur, x, v, sp);
+    else if (L.g->prec == LJMD_FP32)
+        hipLaunchKernelGGL(k_set_state<LJMD_FP32>, dim3(nblk(L.g->n)), dim3(kBlock), 0,
+                           L.stream, *L.st, *L.g, *L.box, L.cur, x, v, sp);
     else
         hipLaunchKernelGGL(k_set_state<LJMD_FP32_DS>, dim3(nblk(L.g->n)), dim3(kBlock), 0,
                            L.stream, *L.st, *L.g, *L.box, L.cur, x, v, sp);

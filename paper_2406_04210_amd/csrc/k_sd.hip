@@ -131,7 +131,8 @@ __global__ __launch_bounds__(kBlock) void k_sd_force(SdArgs sa) {
     block_max_u64(fm, &st.ctl->fmax[a.step & 1]);
 }
 
-template <int PREC>
+// PLAIN (single-precision state): x += delta F / F_max in one float sum.
+template <int PREC, bool PLAIN = false>
 __global__ __launch_bounds__(kBlock) void k_sd_move(SdArgs sa) {
     const StepArgs &a = sa.s;
     const State &st = a.st;
@@ -170,12 +171,29 @@ __global__ __launch_bounds__(kBlock) void k_sd_move(SdArgs sa) {
             const float sc = (float)scale;
             const float4 ph = st.pos_hi[i], pl = st.pos_lo[i];
             dsf x{ph.x, pl.x}, y{ph.y, pl.y}, z{ph.z, pl.z};
-            x = ds_add(x, dsf{sc * f.x, 0.f});
-            y = ds_add(y, dsf{sc * f.y, 0.f});
-            z = ds_add(z, dsf{sc * f.z, 0.f});
-            wrap_ds(x, a.box.Lhi[0], a.box.Llo[0], d[0]);
-            wrap_ds(y, a.box.Lhi[1], a.box.Llo[1], d[1]);
-            wrap_ds(z, a.box.Lhi[2], a.box.Llo[2], d[2]);
+            if constexpr (PLAIN) {
+                dsf *c3[3] = {&x, &y, &z};
+                const float fc[3] = {f.x, f.y, f.z};
+                for (int k = 0; k < 3; ++k) {
+                    float t = c3[k]->hi + sc * fc[k];
+                    if (t < 0.0f) {
+                        t += a.box.Lhi[k];
+                        d[k] = -1;
+                    } else if (t >= a.box.Lhi[k]) {
+                        t -= a.box.Lhi[k];
+                        d[k] = 1;
+                    }
+                    if (t >= a.box.Lhi[k]) t -= a.box.Lhi[k];
+                    *c3[k] = dsf{t, 0.0f};
+                }
+            } else {
+                x = ds_add(x, dsf{sc * f.x, 0.f});
+                y = ds_add(y, dsf{sc * f.y, 0.f});
+                z = ds_add(z, dsf{sc * f.z, 0.f});
+                wrap_ds(x, a.box.Lhi[0], a.box.Llo[0], d[0]);
+                wrap_ds(y, a.box.Lhi[1], a.box.Llo[1], d[1]);
+                wrap_ds(z, a.box.Lhi[2], a.box.Llo[2], d[2]);
+            }
             q[0] = q_from_ds(x.hi, x.lo, a.box.S_hi[0], a.box.S_lo[0]);
             q[1] = q_from_ds(y.hi, y.lo, a.box.S_hi[1], a.box.S_lo[1]);
             q[2] = q_from_ds(z.hi, z.lo, a.box.S_hi[2], a.box.S_lo[2]);
@@ -238,7 +256,10 @@ hipError_t launch_sd(const Launch &L, int64_t step, int forced, int iter, double
             hipLaunchKernelGGL((k_sd_force<LJMD_FP32_DS, 2>), gf, b, 0, L.stream, sa);
         else
             hipLaunchKernelGGL((k_sd_force<LJMD_FP32_DS, 1>), gf, b, 0, L.stream, sa);
-        hipLaunchKernelGGL(k_sd_move<LJMD_FP32_DS>, gm, b, 0, L.stream, sa);
+        if (L.g->prec == LJMD_FP32)
+            hipLaunchKernelGGL((k_sd_move<LJMD_FP32_DS, true>), gm, b, 0, L.stream, sa);
+        else
+            hipLaunchKernelGGL((k_sd_move<LJMD_FP32_DS, false>), gm, b, 0, L.stream, sa);
     }
     return hipGetLastError();
 }

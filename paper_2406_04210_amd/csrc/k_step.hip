@@ -21,46 +21,6 @@
 
 namespace ljmd {
 
-// Block-level deterministic reduction of the six observable partials and the
-// displacement maximum; one row of partials per block.
-// Without OBS only the displacement maximum is reduced.
-template <bool OBS = true, int BS = kBlock>
-__device__ inline void block_finish(const StepArgs &a, Ctl *ctl, int blk, double u, double w, double k,
-                                    double px, double py, double pz, uint32_t dmax) {
-    constexpr int WPB = BS / kWave;
-    __shared__ double red[WPB][6];
-    __shared__ uint32_t redm[WPB];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    double v6[6] = {u, w, k, px, py, pz};
-    if constexpr (OBS) {
-#pragma unroll
-        for (int q = 0; q < 6; ++q) v6[q] = wave_sum(v6[q]);
-    }
-    dmax = wave_max_u(dmax);
-    if (lane == 0) {
-        if constexpr (OBS) {
-#pragma unroll
-            for (int q = 0; q < 6; ++q) red[wv][q] = v6[q];
-        }
-        redm[wv] = dmax;
-    }
-    __syncthreads();
-    if (OBS && threadIdx.x < kNP) {
-        double s = 0.0;
-        if (threadIdx.x < 6)
-            for (int q = 0; q < WPB; ++q) s += red[q][threadIdx.x];
-        a.st.partials[((size_t)a.slot * a.g.max_blocks + blk) * kNP + threadIdx.x] = s;
-    }
-    if (threadIdx.x == 0 && (a.mode & kIntegrate)) {
-        uint32_t m = 0;
-        for (int q = 0; q < WPB; ++q) m = redm[q] > m ? redm[q] : m;
-        // Only "exceeded or not" decides the rebuild, so blocks below the
-        // threshold skip the same-address atomic entirely.
-        if (m > __float_as_uint(a.dyn.thr2)) atomicMax(&ctl->maxd[(a.step + 1) & 1], m);
-        if (m > 0x7f800000u) atomicOr(&ctl->flags, kErrNaN);
-    }
-}
-
 // Housekeeping shared by both precisions: the rebuilt marker of this step and,
 // after a rebuild, clearing the cell counters for the next binning.
 // Cells [c_lo, c_hi) belong to this system; block bj of its nbj blocks
@@ -98,7 +58,7 @@ __device__ inline void step_housekeeping(const StepArgs &a, const Ctl *ctl, int6
 // TH: the thermostat resamples colliding particles' velocities after
 // "finalize" (a separate instantiation, so that the plain NVE kernel keeps
 // its register budget).
-template <int NS, int LANES, bool Q, bool OBS, bool TH = false>
+template <int NS, int LANES, bool Q, bool OBS, bool TH = false, bool PLAIN = false>
 __device__ inline void step_ds_body(const StepArgs &a, const BoxC &box, Ctl *ctl, int blk, int64_t i_end,
                                     int64_t c_lo, int64_t c_hi, int bj, int nbj, int32_t *rebuilt) {
     constexpr int P = kWave / LANES;
@@ -274,79 +234,18 @@ __device__ inline void step_ds_body(const StepArgs &a, const BoxC &box, Ctl *ctl
     }
     double pu = 0.0, pw = 0.0, pk = 0.0, ppx = 0.0, ppy = 0.0, ppz = 0.0;
     uint32_t dm = 0u;
-    if (valid && l == 0) {
-        const int si = ri.w;
-        const float chi = by_s(si, a.dyn.hdt_m_hi), clo = by_s(si, a.dyn.hdt_m_lo);
-        const float mass = by_s(si, a.dyn.massf);
-        const float4 vh = st.vel_hi[i], vl = st.vel_lo[i];
-        dsf vx{vh.x, vl.x}, vy{vh.y, vl.y}, vz{vh.z, vl.z};
-        if (a.mode & kFinalize) {
-            vx = ds_add(vx, ds_mul_f(chi, clo, fx));
-            vy = ds_add(vy, ds_mul_f(chi, clo, fy));
-            vz = ds_add(vz, ds_mul_f(chi, clo, fz));
-            if constexpr (TH) {
-                double z[3];
-                if (thermo_draw(a.dyn, (uint32_t)st.id[i], a.step, z)) {
-                    const double sd = by_s(si, a.dyn.thermo_sd);
-                    vx = ds_of(sd * z[0]);
-                    vy = ds_of(sd * z[1]);
-                    vz = ds_of(sd * z[2]);
-                }
-            }
-        }
-        const float ux = vx.hi + vx.lo, uy = vy.hi + vy.lo, uz = vz.hi + vz.lo;
-        if constexpr (OBS) {
-            pk = 0.5 * (double)(mass * fmaf(uz, uz, fmaf(uy, uy, ux * ux)));
-            ppx = (double)(mass * ux);
-            ppy = (double)(mass * uy);
-            ppz = (double)(mass * uz);
-            pu = 0.5 * e;
-            pw = 0.5 * w;
-        }
-        if (a.mode & kIntegrate) {
-            vx = ds_add(vx, ds_mul_f(chi, clo, fx));
-            vy = ds_add(vy, ds_mul_f(chi, clo, fy));
-            vz = ds_add(vz, ds_mul_f(chi, clo, fz));
-            const float4 ph = st.pos_hi[i], pl = st.pos_lo[i];
-            dsf x{ph.x, pl.x}, y{ph.y, pl.y}, z{ph.z, pl.z};
-            x = ds_add(x, ds_mul(vx, a.dyn.dt_hi, a.dyn.dt_lo));
-            y = ds_add(y, ds_mul(vy, a.dyn.dt_hi, a.dyn.dt_lo));
-            z = ds_add(z, ds_mul(vz, a.dyn.dt_hi, a.dyn.dt_lo));
-            int ix = 0, iy = 0, iz = 0;
-            wrap_ds(x, box.Lhi[0], box.Llo[0], ix);
-            wrap_ds(y, box.Lhi[1], box.Llo[1], iy);
-            wrap_ds(z, box.Lhi[2], box.Llo[2], iz);
-            if (ix | iy | iz) {
-                int4 im = st.img[i];
-                st.img[i] = make_int4(im.x + ix, im.y + iy, im.z + iz, 0);
-            }
-            const uint32_t qx = q_from_ds(x.hi, x.lo, box.S_hi[0], box.S_lo[0]);
-            const uint32_t qy = q_from_ds(y.hi, y.lo, box.S_hi[1], box.S_lo[1]);
-            const uint32_t qz = q_from_ds(z.hi, z.lo, box.S_hi[2], box.S_lo[2]);
-            st.recq[a.cur ^ 1][i] = make_int4((int)qx, (int)qy, (int)qz, si);
-            st.pos_hi[i] = make_float4(x.hi, y.hi, z.hi, 0.f);
-            st.pos_lo[i] = make_float4(x.lo, y.lo, z.lo, 0.f);
-            const int4 xr = st.xref[i];
-            const float ddx = disp_q(qx, (uint32_t)xr.x, qsx, qlx);
-            const float ddy = disp_q(qy, (uint32_t)xr.y, qsy, qly);
-            const float ddz = disp_q(qz, (uint32_t)xr.z, qsz, qlz);
-            const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
-            // A non-finite position has no fixed-point image: report it as NaN.
-            const bool fin = __builtin_isfinite(x.hi) && __builtin_isfinite(y.hi) && __builtin_isfinite(z.hi);
-            dm = (fin && d2 == d2) ? __float_as_uint(d2) : 0x7fc00000u;
-        }
-        st.vel_hi[i] = make_float4(vx.hi, vy.hi, vz.hi, 0.f);
-        st.vel_lo[i] = make_float4(vx.lo, vy.lo, vz.lo, 0.f);
-        if (a.mode & kStoreForce) st.frc32[i] = make_float4(fx, fy, fz, 0.f);
-    }
+    if (valid && l == 0)
+        finish_ds<OBS, TH, PLAIN>(a, box, i, ri.w, fx, fy, fz, e, w, pu, pw, pk, ppx, ppy, ppz, dm);
     block_finish<OBS>(a, ctl, blk, pu, pw, pk, ppx, ppy, ppz, dm);
 }
 
-template <int NS, int LANES, bool Q, bool OBS, bool TH>
+// PLAIN: the single-precision state (positions and velocities as single
+// floats) instead of double-single.
+template <int NS, int LANES, bool Q, bool OBS, bool TH, bool PLAIN>
 __global__ __launch_bounds__(kBlock) void k_step_ds(StepArgs a) {
     static_assert(OBS || Q, "observables are skipped on the quanta path only");
-    step_ds_body<NS, LANES, Q, OBS, TH>(a, a.box, a.st.ctl, xcd_remap(blockIdx.x, gridDim.x), a.g.n, 0,
-                                        a.box.ncell, blockIdx.x, gridDim.x, a.st.rebuilt + a.slot);
+    step_ds_body<NS, LANES, Q, OBS, TH, PLAIN>(a, a.box, a.st.ctl, xcd_remap(blockIdx.x, gridDim.x), a.g.n, 0,
+                                               a.box.ncell, blockIdx.x, gridDim.x, a.st.rebuilt + a.slot);
 }
 
 // A batch of independent one-species cubic systems, each over its own run of
@@ -434,146 +333,28 @@ __global__ __launch_bounds__(kBlockF64) void k_step_fp64(StepArgs a) {
     }
     double pu = 0.0, pw = 0.0, pk = 0.0, ppx = 0.0, ppy = 0.0, ppz = 0.0;
     uint32_t dm = 0u;
-    if (valid && l == 0) {
-        const double c = by_s(si, a.dyn.hdt_m);
-        const double mass = by_s(si, a.dyn.mass);
-        double4 v = st.vel64[i];
-        if (a.mode & kFinalize) {
-            v.x += c * fx;
-            v.y += c * fy;
-            v.z += c * fz;
-            if constexpr (TH) {
-                double z[3];
-                if (thermo_draw(a.dyn, (uint32_t)st.id[i], a.step, z)) {
-                    const double sd = by_s(si, a.dyn.thermo_sd);
-                    v.x = sd * z[0];
-                    v.y = sd * z[1];
-                    v.z = sd * z[2];
-                }
-            }
-        }
-        pk = 0.5 * mass * fma(v.z, v.z, fma(v.y, v.y, v.x * v.x));
-        ppx = mass * v.x;
-        ppy = mass * v.y;
-        ppz = mass * v.z;
-        pu = 0.5 * e;
-        pw = 0.5 * w;
-        if (a.mode & kIntegrate) {
-            v.x += c * fx;
-            v.y += c * fy;
-            v.z += c * fz;
-            double x[3] = {ri.x + a.dyn.dt * v.x, ri.y + a.dyn.dt * v.y, ri.z + a.dyn.dt * v.z};
-            int d[3] = {0, 0, 0};
-            for (int k = 0; k < 3; ++k) {
-                if (x[k] < 0.0) {
-                    x[k] += a.box.L[k];
-                    d[k] = -1;
-                } else if (x[k] >= a.box.L[k]) {
-                    x[k] -= a.box.L[k];
-                    d[k] = 1;
-                }
-                if (x[k] >= a.box.L[k]) x[k] -= a.box.L[k];
-            }
-            if (d[0] | d[1] | d[2]) {
-                int4 im = st.img[i];
-                st.img[i] = make_int4(im.x + d[0], im.y + d[1], im.z + d[2], 0);
-            }
-            st.rec64[a.cur ^ 1][i] = make_double4(x[0], x[1], x[2], ri.w);
-            const int4 xr = st.xref[i];
-            const float ddx = disp_q(q_from_d(x[0], a.box.S[0]), (uint32_t)xr.x, a.box.qs_hi[0], a.box.qs_lo[0]);
-            const float ddy = disp_q(q_from_d(x[1], a.box.S[1]), (uint32_t)xr.y, a.box.qs_hi[1], a.box.qs_lo[1]);
-            const float ddz = disp_q(q_from_d(x[2], a.box.S[2]), (uint32_t)xr.z, a.box.qs_hi[2], a.box.qs_lo[2]);
-            const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
-            dm = (d2 == d2 && __builtin_isfinite(x[0]) && __builtin_isfinite(x[1]) && __builtin_isfinite(x[2]))
-                     ? __float_as_uint(d2)
-                     : 0x7fc00000u;
-        }
-        st.vel64[i] = v;
-        if (a.mode & kStoreForce) st.frc64[i] = make_double4(fx, fy, fz, 0.0);
-    }
+    if (valid && l == 0)
+        finish_fp64<TH>(a, a.box, i, ri, fx, fy, fz, e, w, pu, pw, pk, ppx, ppy, ppz, dm);
     block_finish<true, kBlockF64>(a, a.st.ctl, blk, pu, pw, pk, ppx, ppy, ppz, dm);
 }
 
-// Start of a run: "integrate" from the stored forces of the current step.
+// Start of a run: "integrate" from the stored forces of the current step
+// (the tail of a step with only its integrate half: a.mode is kIntegrate).
 template <int PREC>
 __device__ inline void integrate_body(const StepArgs &a, const BoxC &box, Ctl *ctl, int64_t i_end) {
     const State &st = a.st;
     if (halted(ctl)) return;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     uint32_t dm = 0u;
+    double pu, pw, pk, ppx, ppy, ppz;
     if (i < i_end) {
         if constexpr (PREC == LJMD_FP64) {
-            const double4 r = st.rec64[a.cur][i];
-            const int si = (int)r.w;
-            const double c = by_s(si, a.dyn.hdt_m);
             const double4 f = st.frc64[i];
-            double4 v = st.vel64[i];
-            v.x += c * f.x;
-            v.y += c * f.y;
-            v.z += c * f.z;
-            double x[3] = {r.x + a.dyn.dt * v.x, r.y + a.dyn.dt * v.y, r.z + a.dyn.dt * v.z};
-            int d[3] = {0, 0, 0};
-            for (int k = 0; k < 3; ++k) {
-                if (x[k] < 0.0) {
-                    x[k] += box.L[k];
-                    d[k] = -1;
-                } else if (x[k] >= box.L[k]) {
-                    x[k] -= box.L[k];
-                    d[k] = 1;
-                }
-                if (x[k] >= box.L[k]) x[k] -= box.L[k];
-            }
-            if (d[0] | d[1] | d[2]) {
-                int4 im = st.img[i];
-                st.img[i] = make_int4(im.x + d[0], im.y + d[1], im.z + d[2], 0);
-            }
-            st.rec64[a.cur ^ 1][i] = make_double4(x[0], x[1], x[2], r.w);
-            st.vel64[i] = v;
-            const int4 xr = st.xref[i];
-            const float ddx = disp_q(q_from_d(x[0], box.S[0]), (uint32_t)xr.x, box.qs_hi[0], box.qs_lo[0]);
-            const float ddy = disp_q(q_from_d(x[1], box.S[1]), (uint32_t)xr.y, box.qs_hi[1], box.qs_lo[1]);
-            const float ddz = disp_q(q_from_d(x[2], box.S[2]), (uint32_t)xr.z, box.qs_hi[2], box.qs_lo[2]);
-            const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
-            const bool fin = __builtin_isfinite(x[0]) && __builtin_isfinite(x[1]) && __builtin_isfinite(x[2]);
-            dm = (fin && d2 == d2) ? __float_as_uint(d2) : 0x7fc00000u;
+            finish_fp64<false>(a, box, i, st.rec64[a.cur][i], f.x, f.y, f.z, 0.0, 0.0, pu, pw, pk, ppx, ppy, ppz, dm);
         } else {
-            const int4 r = st.recq[a.cur][i];
-            const int si = r.w;
-            const float chi = by_s(si, a.dyn.hdt_m_hi), clo = by_s(si, a.dyn.hdt_m_lo);
             const float4 f = st.frc32[i];
-            const float4 vh = st.vel_hi[i], vl = st.vel_lo[i];
-            dsf vx{vh.x, vl.x}, vy{vh.y, vl.y}, vz{vh.z, vl.z};
-            vx = ds_add(vx, ds_mul_f(chi, clo, f.x));
-            vy = ds_add(vy, ds_mul_f(chi, clo, f.y));
-            vz = ds_add(vz, ds_mul_f(chi, clo, f.z));
-            const float4 ph = st.pos_hi[i], pl = st.pos_lo[i];
-            dsf x{ph.x, pl.x}, y{ph.y, pl.y}, z{ph.z, pl.z};
-            x = ds_add(x, ds_mul(vx, a.dyn.dt_hi, a.dyn.dt_lo));
-            y = ds_add(y, ds_mul(vy, a.dyn.dt_hi, a.dyn.dt_lo));
-            z = ds_add(z, ds_mul(vz, a.dyn.dt_hi, a.dyn.dt_lo));
-            int ix = 0, iy = 0, iz = 0;
-            wrap_ds(x, box.Lhi[0], box.Llo[0], ix);
-            wrap_ds(y, box.Lhi[1], box.Llo[1], iy);
-            wrap_ds(z, box.Lhi[2], box.Llo[2], iz);
-            if (ix | iy | iz) {
-                int4 im = st.img[i];
-                st.img[i] = make_int4(im.x + ix, im.y + iy, im.z + iz, 0);
-            }
-            const uint32_t qx = q_from_ds(x.hi, x.lo, box.S_hi[0], box.S_lo[0]);
-            const uint32_t qy = q_from_ds(y.hi, y.lo, box.S_hi[1], box.S_lo[1]);
-            const uint32_t qz = q_from_ds(z.hi, z.lo, box.S_hi[2], box.S_lo[2]);
-            st.recq[a.cur ^ 1][i] = make_int4((int)qx, (int)qy, (int)qz, si);
-            st.pos_hi[i] = make_float4(x.hi, y.hi, z.hi, 0.f);
-            st.pos_lo[i] = make_float4(x.lo, y.lo, z.lo, 0.f);
-            st.vel_hi[i] = make_float4(vx.hi, vy.hi, vz.hi, 0.f);
-            st.vel_lo[i] = make_float4(vx.lo, vy.lo, vz.lo, 0.f);
-            const int4 xr = st.xref[i];
-            const float ddx = disp_q(qx, (uint32_t)xr.x, box.qs_hi[0], box.qs_lo[0]);
-            const float ddy = disp_q(qy, (uint32_t)xr.y, box.qs_hi[1], box.qs_lo[1]);
-            const float ddz = disp_q(qz, (uint32_t)xr.z, box.qs_hi[2], box.qs_lo[2]);
-            const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
-            const bool fin = __builtin_isfinite(x.hi) && __builtin_isfinite(y.hi) && __builtin_isfinite(z.hi);
-            dm = (fin && d2 == d2) ? __float_as_uint(d2) : 0x7fc00000u;
+            finish_ds<false, false, PREC == LJMD_FP32>(a, box, i, st.recq[a.cur][i].w, f.x, f.y, f.z, 0.0, 0.0, pu,
+                                                       pw, pk, ppx, ppy, ppz, dm);
         }
     }
     dm = wave_max_u(dm);
@@ -619,22 +400,30 @@ static StepArgs make_args(const Launch &L, int64_t step, int forced, int mode, i
 hipError_t launch_step(const Launch &L, int64_t step, int forced, int mode, int slot) {
     StepArgs a = make_args(L, step, forced, mode, slot);
     dim3 grid(step_blocks(*L.g)), block(step_block_threads(L.g->prec));
-    const bool ds = L.g->prec == LJMD_FP32_DS;
+    const bool ds = L.g->prec != LJMD_FP64;
+    const bool plain = L.g->prec == LJMD_FP32;
     const bool two = L.g->nspecies == 2;
     const bool quanta = ds && L.box->cubic && L.g->n < kQuantaMaxSlots;
     const bool obs = (mode & kObserve) != 0;
     // The thermostat acts on "finalize" only.
     const bool th = L.dyn->thermo_on && (mode & kFinalize);
-#define STEP_TH(NS, LN, TH)                                                                        \
-    do {                                                                                           \
-        if (ds && quanta && obs)                                                                   \
-            hipLaunchKernelGGL((k_step_ds<NS, LN, true, true, TH>), grid, block, 0, L.stream, a);  \
-        else if (ds && quanta)                                                                     \
-            hipLaunchKernelGGL((k_step_ds<NS, LN, true, false, TH>), grid, block, 0, L.stream, a); \
-        else if (ds)                                                                               \
-            hipLaunchKernelGGL((k_step_ds<NS, LN, false, true, TH>), grid, block, 0, L.stream, a); \
-        else                                                                                       \
-            hipLaunchKernelGGL((k_step_fp64<NS, LN, TH>), grid, block, 0, L.stream, a);            \
+#define STEP_DS(NS, LN, TH, PL)                                                                         \
+    do {                                                                                                \
+        if (quanta && obs)                                                                              \
+            hipLaunchKernelGGL((k_step_ds<NS, LN, true, true, TH, PL>), grid, block, 0, L.stream, a);   \
+        else if (quanta)                                                                                \
+            hipLaunchKernelGGL((k_step_ds<NS, LN, true, false, TH, PL>), grid, block, 0, L.stream, a);  \
+        else                                                                                            \
+            hipLaunchKernelGGL((k_step_ds<NS, LN, false, true, TH, PL>), grid, block, 0, L.stream, a);  \
+    } while (0)
+#define STEP_TH(NS, LN, TH)                                                              \
+    do {                                                                                 \
+        if (ds && plain)                                                                 \
+            STEP_DS(NS, LN, TH, true);                                                   \
+        else if (ds)                                                                     \
+            STEP_DS(NS, LN, TH, false);                                                  \
+        else                                                                             \
+            hipLaunchKernelGGL((k_step_fp64<NS, LN, TH>), grid, block, 0, L.stream, a);  \
     } while (0)
 #define STEP(NS, LN)              \
     do {                          \
@@ -659,6 +448,7 @@ hipError_t launch_step(const Launch &L, int64_t step, int forced, int mode, int 
 #undef BY_LANES
 #undef STEP
 #undef STEP_TH
+#undef STEP_DS
     return hipGetLastError();
 }
 
@@ -667,6 +457,8 @@ hipError_t launch_integrate(const Launch &L, int64_t step) {
     dim3 grid((unsigned)((L.g->n + kBlock - 1) / kBlock)), block(kBlock);
     if (L.g->prec == LJMD_FP64)
         hipLaunchKernelGGL(k_integrate<LJMD_FP64>, grid, block, 0, L.stream, a);
+    else if (L.g->prec == LJMD_FP32)
+        hipLaunchKernelGGL(k_integrate<LJMD_FP32>, grid, block, 0, L.stream, a);
     else
         hipLaunchKernelGGL(k_integrate<LJMD_FP32_DS>, grid, block, 0, L.stream, a);
     return hipGetLastError();

@@ -142,7 +142,8 @@ int validate(const ljmd_params *p, std::string *why) {
     if (!(p->skin >= 0.0) || !std::isfinite(p->skin)) return bad("skin must be finite and >= 0");
     if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return bad("dt must be finite and > 0");
     if (p->sort_interval < 0) return bad("sort_interval must be >= 0");
-    if (p->precision != LJMD_FP64 && p->precision != LJMD_FP32_DS) return bad("unknown precision");
+    if (p->precision != LJMD_FP64 && p->precision != LJMD_FP32_DS && p->precision != LJMD_FP32)
+        return bad("unknown precision");
     if (p->nbr_capacity < 0 || p->nbr_capacity > 4096) return bad("nbr_capacity must be in [0, 4096]");
     if (p->cell_capacity < 0 || p->cell_capacity > 768) return bad("cell_capacity must be in [0, 768]");
     if (p->lanes != 0 && p->lanes != 1 && p->lanes != 2 && p->lanes != 4 && p->lanes != 8 && p->lanes != 16)

@@ -110,5 +110,219 @@ __device__ inline void wrap_ds(dsf &x, float Lhi, float Llo, int &im) {
     }
 }
 
+// Block-level deterministic reduction of the six observable partials and the
+// displacement maximum; one row of partials per block.
+// Without OBS only the displacement maximum is reduced.
+template <bool OBS = true, int BS = kBlock>
+__device__ inline void block_finish(const StepArgs &a, Ctl *ctl, int blk, double u, double w, double k,
+                                    double px, double py, double pz, uint32_t dmax) {
+    constexpr int WPB = BS / kWave;
+    __shared__ double red[WPB][6];
+    __shared__ uint32_t redm[WPB];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double v6[6] = {u, w, k, px, py, pz};
+    if constexpr (OBS) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) v6[q] = wave_sum(v6[q]);
+    }
+    dmax = wave_max_u(dmax);
+    if (lane == 0) {
+        if constexpr (OBS) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) red[wv][q] = v6[q];
+        }
+        redm[wv] = dmax;
+    }
+    __syncthreads();
+    if (OBS && threadIdx.x < kNP) {
+        double s = 0.0;
+        if (threadIdx.x < 6)
+            for (int q = 0; q < WPB; ++q) s += red[q][threadIdx.x];
+        a.st.partials[((size_t)a.slot * a.g.max_blocks + blk) * kNP + threadIdx.x] = s;
+    }
+    if (threadIdx.x == 0 && (a.mode & kIntegrate)) {
+        uint32_t m = 0;
+        for (int q = 0; q < WPB; ++q) m = redm[q] > m ? redm[q] : m;
+        // Only "exceeded or not" decides the rebuild, so blocks below the
+        // threshold skip the same-address atomic entirely.
+        if (m > __float_as_uint(a.dyn.thr2)) atomicMax(&ctl->maxd[(a.step + 1) & 1], m);
+        if (m > 0x7f800000u) atomicOr(&ctl->flags, kErrNaN);
+    }
+}
+
+// The tail of a step for slot i of the single-precision paths, after its
+// forces (fx, fy, fz) and pair-energy and virial sums (e, w: both halves of
+// its pairs) are known: "finalize" of step s (v_s = v' + dt/(2m) F), the
+// thermostat (TH), the particle's observable terms (OBS: K_i, m v_i, e/2,
+// w/2) and "integrate" of step s+1 (v' = v_s + dt/(2m) F, x_{s+1} =
+// x_s + dt v', wrapped into the box with image bookkeeping, the new
+// fixed-point record, the squared displacement from the list reference in
+// dm). Double-single arithmetic, or with PLAIN single floats (the lo parts
+// stay zero).
+template <bool OBS, bool TH, bool PLAIN = false>
+__device__ inline void finish_ds(const StepArgs &a, const BoxC &box, int64_t i, int si, float fx, float fy,
+                                 float fz, double e, double w, double &pu, double &pw, double &pk, double &ppx,
+                                 double &ppy, double &ppz, uint32_t &dm) {
+    const State &st = a.st;
+    const float chi = by_s(si, a.dyn.hdt_m_hi), clo = by_s(si, a.dyn.hdt_m_lo);
+    const float mass = by_s(si, a.dyn.massf);
+    const float4 vh = st.vel_hi[i], vl = st.vel_lo[i];
+    dsf vx{vh.x, vl.x}, vy{vh.y, vl.y}, vz{vh.z, vl.z};
+    // v += dt/(2m) F: double-single, or one float product and one float sum.
+    auto kick = [&](dsf &v, float f) {
+        if constexpr (PLAIN)
+            v = dsf{v.hi + chi * f, 0.0f};
+        else
+            v = ds_add(v, ds_mul_f(chi, clo, f));
+    };
+    if (a.mode & kFinalize) {
+        kick(vx, fx);
+        kick(vy, fy);
+        kick(vz, fz);
+        if constexpr (TH) {
+            double z[3];
+            if (thermo_draw(a.dyn, (uint32_t)st.id[i], a.step, z)) {
+                const double sd = by_s(si, a.dyn.thermo_sd);
+                if constexpr (PLAIN) {
+                    vx = dsf{(float)(sd * z[0]), 0.0f};
+                    vy = dsf{(float)(sd * z[1]), 0.0f};
+                    vz = dsf{(float)(sd * z[2]), 0.0f};
+                } else {
+                    vx = ds_of(sd * z[0]);
+                    vy = ds_of(sd * z[1]);
+                    vz = ds_of(sd * z[2]);
+                }
+            }
+        }
+    }
+    const float ux = vx.hi + vx.lo, uy = vy.hi + vy.lo, uz = vz.hi + vz.lo;
+    if constexpr (OBS) {
+        pk = 0.5 * (double)(mass * fmaf(uz, uz, fmaf(uy, uy, ux * ux)));
+        ppx = (double)(mass * ux);
+        ppy = (double)(mass * uy);
+        ppz = (double)(mass * uz);
+        pu = 0.5 * e;
+        pw = 0.5 * w;
+    }
+    if (a.mode & kIntegrate) {
+        kick(vx, fx);
+        kick(vy, fy);
+        kick(vz, fz);
+        const float4 ph = st.pos_hi[i], pl = st.pos_lo[i];
+        dsf x{ph.x, pl.x}, y{ph.y, pl.y}, z{ph.z, pl.z};
+        int ix = 0, iy = 0, iz = 0;
+        if constexpr (PLAIN) {
+            // x += dt v in floats; wrap by one box edge (as a float).
+            const float dtf = a.dyn.dt_hi;
+            auto drift = [&](dsf &q, float v, float L, int &im) {
+                float t = q.hi + dtf * v;
+                if (t < 0.0f) {
+                    t += L;
+                    im -= 1;
+                } else if (t >= L) {
+                    t -= L;
+                    im += 1;
+                }
+                if (t >= L) t -= L;
+                q = dsf{t, 0.0f};
+            };
+            drift(x, vx.hi, box.Lhi[0], ix);
+            drift(y, vy.hi, box.Lhi[1], iy);
+            drift(z, vz.hi, box.Lhi[2], iz);
+        } else {
+            x = ds_add(x, ds_mul(vx, a.dyn.dt_hi, a.dyn.dt_lo));
+            y = ds_add(y, ds_mul(vy, a.dyn.dt_hi, a.dyn.dt_lo));
+            z = ds_add(z, ds_mul(vz, a.dyn.dt_hi, a.dyn.dt_lo));
+            wrap_ds(x, box.Lhi[0], box.Llo[0], ix);
+            wrap_ds(y, box.Lhi[1], box.Llo[1], iy);
+            wrap_ds(z, box.Lhi[2], box.Llo[2], iz);
+        }
+        if (ix | iy | iz) {
+            int4 im = st.img[i];
+            st.img[i] = make_int4(im.x + ix, im.y + iy, im.z + iz, 0);
+        }
+        const uint32_t qx = q_from_ds(x.hi, x.lo, box.S_hi[0], box.S_lo[0]);
+        const uint32_t qy = q_from_ds(y.hi, y.lo, box.S_hi[1], box.S_lo[1]);
+        const uint32_t qz = q_from_ds(z.hi, z.lo, box.S_hi[2], box.S_lo[2]);
+        st.recq[a.cur ^ 1][i] = make_int4((int)qx, (int)qy, (int)qz, si);
+        st.pos_hi[i] = make_float4(x.hi, y.hi, z.hi, 0.f);
+        st.pos_lo[i] = make_float4(x.lo, y.lo, z.lo, 0.f);
+        const int4 xr = st.xref[i];
+        const float ddx = disp_q(qx, (uint32_t)xr.x, box.qs_hi[0], box.qs_lo[0]);
+        const float ddy = disp_q(qy, (uint32_t)xr.y, box.qs_hi[1], box.qs_lo[1]);
+        const float ddz = disp_q(qz, (uint32_t)xr.z, box.qs_hi[2], box.qs_lo[2]);
+        const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
+        // A non-finite position has no fixed-point image: report it as NaN.
+        const bool fin = __builtin_isfinite(x.hi) && __builtin_isfinite(y.hi) && __builtin_isfinite(z.hi);
+        dm = (fin && d2 == d2) ? __float_as_uint(d2) : 0x7fc00000u;
+    }
+    st.vel_hi[i] = make_float4(vx.hi, vy.hi, vz.hi, 0.f);
+    st.vel_lo[i] = make_float4(vx.lo, vy.lo, vz.lo, 0.f);
+    if (a.mode & kStoreForce) st.frc32[i] = make_float4(fx, fy, fz, 0.f);
+}
+
+// The same tail for the FP64 path (record ri: position and species of slot i).
+template <bool TH>
+__device__ inline void finish_fp64(const StepArgs &a, const BoxC &box, int64_t i, const double4 &ri, double fx,
+                                   double fy, double fz, double e, double w, double &pu, double &pw, double &pk,
+                                   double &ppx, double &ppy, double &ppz, uint32_t &dm) {
+    const State &st = a.st;
+    const int si = (int)ri.w;
+    const double c = by_s(si, a.dyn.hdt_m);
+    const double mass = by_s(si, a.dyn.mass);
+    double4 v = st.vel64[i];
+    if (a.mode & kFinalize) {
+        v.x += c * fx;
+        v.y += c * fy;
+        v.z += c * fz;
+        if constexpr (TH) {
+            double z[3];
+            if (thermo_draw(a.dyn, (uint32_t)st.id[i], a.step, z)) {
+                const double sd = by_s(si, a.dyn.thermo_sd);
+                v.x = sd * z[0];
+                v.y = sd * z[1];
+                v.z = sd * z[2];
+            }
+        }
+    }
+    pk = 0.5 * mass * fma(v.z, v.z, fma(v.y, v.y, v.x * v.x));
+    ppx = mass * v.x;
+    ppy = mass * v.y;
+    ppz = mass * v.z;
+    pu = 0.5 * e;
+    pw = 0.5 * w;
+    if (a.mode & kIntegrate) {
+        v.x += c * fx;
+        v.y += c * fy;
+        v.z += c * fz;
+        double x[3] = {ri.x + a.dyn.dt * v.x, ri.y + a.dyn.dt * v.y, ri.z + a.dyn.dt * v.z};
+        int d[3] = {0, 0, 0};
+        for (int k = 0; k < 3; ++k) {
+            if (x[k] < 0.0) {
+                x[k] += box.L[k];
+                d[k] = -1;
+            } else if (x[k] >= box.L[k]) {
+                x[k] -= box.L[k];
+                d[k] = 1;
+            }
+            if (x[k] >= box.L[k]) x[k] -= box.L[k];
+        }
+        if (d[0] | d[1] | d[2]) {
+            int4 im = st.img[i];
+            st.img[i] = make_int4(im.x + d[0], im.y + d[1], im.z + d[2], 0);
+        }
+        st.rec64[a.cur ^ 1][i] = make_double4(x[0], x[1], x[2], ri.w);
+        const int4 xr = st.xref[i];
+        const float ddx = disp_q(q_from_d(x[0], box.S[0]), (uint32_t)xr.x, box.qs_hi[0], box.qs_lo[0]);
+        const float ddy = disp_q(q_from_d(x[1], box.S[1]), (uint32_t)xr.y, box.qs_hi[1], box.qs_lo[1]);
+        const float ddz = disp_q(q_from_d(x[2], box.S[2]), (uint32_t)xr.z, box.qs_hi[2], box.qs_lo[2]);
+        const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
+        dm = (d2 == d2 && __builtin_isfinite(x[0]) && __builtin_isfinite(x[1]) && __builtin_isfinite(x[2]))
+                 ? __float_as_uint(d2)
+                 : 0x7fc00000u;
+    }
+    st.vel64[i] = v;
+    if (a.mode & kStoreForce) st.frc64[i] = make_double4(fx, fy, fz, 0.0);
+}
 
 }  // namespace ljmd
