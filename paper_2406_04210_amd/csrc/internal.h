@@ -142,6 +142,8 @@ struct Geom {
     int32_t prec;
     int32_t max_blocks;   // rows per ring slot of partials
     int32_t ncu;          // compute units of the device (grid of the per-step rebuild kernels)
+    int32_t all_pairs;    // 1: untruncated all-pairs interaction (no lists, no cells)
+    int32_t pad_;
 };
 
 // ------------------------------------------------------------------------
@@ -336,6 +338,11 @@ hipError_t launch_neighbors(const Launch &L, int32_t *cnt, int32_t *ids, int32_t
 hipError_t launch_max_fill(const Launch &L);
 hipError_t launch_sd(const Launch &L, int64_t step, int forced, int iter, double delta,
                      double clamp, double *fmax_out);
+// All-pairs mode: splits of the j range, bytes of the partial rows (held in
+// the list area), and the two launches of one step.
+int allpairs_splits(int64_t n);
+size_t allpairs_part_bytes(int64_t n, int prec);
+hipError_t launch_allpairs_step(const Launch &L, int64_t step, int mode, int slot);
 size_t resort_scratch_bytes(int64_t npad, int prec);
 size_t cell_rec_bytes(int prec);
 int step_blocks(const Geom &g);

@@ -398,6 +398,7 @@ static StepArgs make_args(const Launch &L, int64_t step, int forced, int mode, i
 }
 
 hipError_t launch_step(const Launch &L, int64_t step, int forced, int mode, int slot) {
+    if (L.g->all_pairs) return launch_allpairs_step(L, step, mode, slot);
     StepArgs a = make_args(L, step, forced, mode, slot);
     dim3 grid(step_blocks(*L.g)), block(step_block_threads(L.g->prec));
     const bool ds = L.g->prec != LJMD_FP64;

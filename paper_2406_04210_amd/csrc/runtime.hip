@@ -111,6 +111,13 @@ int hip_fail(ljmd_ctx *c, hipError_t e, const char *what) {
 
 bool used_pair(const ljmd_params *p, int ab) { return p->nspecies == 2 || ab == 0; }
 
+// Every used cutoff infinite: the untruncated all-pairs interaction.
+bool all_pairs(const ljmd_params *p) {
+    for (int ab = 0; ab < 4; ++ab)
+        if (used_pair(p, ab) && !std::isinf(p->rcut[ab])) return false;
+    return true;
+}
+
 double list_radius_max(const ljmd_params *p) {
     double r = 0.0;
     for (int ab = 0; ab < 4; ++ab)
@@ -132,8 +139,11 @@ int validate(const ljmd_params *p, std::string *why) {
         if (!used_pair(p, ab)) continue;
         if (!(p->eps[ab] >= 0.0) || !std::isfinite(p->eps[ab])) return bad("eps must be finite and >= 0");
         if (!(p->sigma[ab] > 0.0) || !std::isfinite(p->sigma[ab])) return bad("sigma must be finite and > 0");
-        if (!(p->rcut[ab] > 0.0) || !std::isfinite(p->rcut[ab])) return bad("rcut must be finite and > 0");
+        if (!(p->rcut[ab] > 0.0)) return bad("rcut must be > 0 (or +inf for the all-pairs interaction)");
     }
+    bool any_inf = false;
+    for (int ab = 0; ab < 4; ++ab) any_inf = any_inf || (used_pair(p, ab) && std::isinf(p->rcut[ab]));
+    if (any_inf && !all_pairs(p)) return bad("rcut: either every used cutoff is +inf (all pairs) or none");
     if (p->nspecies == 2 &&
         (p->eps[1] != p->eps[2] || p->sigma[1] != p->sigma[2] || p->rcut[1] != p->rcut[2]))
         return bad("pair tables must be symmetric ([1] == [2])");
@@ -149,6 +159,13 @@ int validate(const ljmd_params *p, std::string *why) {
     if (p->lanes != 0 && p->lanes != 1 && p->lanes != 2 && p->lanes != 4 && p->lanes != 8 && p->lanes != 16)
         return bad("lanes must be 0, 1, 2, 4, 8 or 16");
     if (p->reserved != 0) return bad("reserved must be 0");
+    if (all_pairs(p)) {
+        // Minimum image of every pair; the single-precision paths work in
+        // fixed-point quanta of a cubic box.
+        if (p->precision != LJMD_FP64 && !(p->box[0] == p->box[1] && p->box[1] == p->box[2]))
+            return bad("the all-pairs interaction in single precision needs a cubic box");
+        return LJMD_OK;
+    }
     const double rl = list_radius_max(p);
     for (int k = 0; k < 3; ++k)
         if (p->box[k] < 2.0 * rl) {
@@ -194,6 +211,19 @@ Plan make_plan(const ljmd_params *p) {
     pl.npad = (p->n + 63) / 64 * 64;
     grid_dims(p, pl.nc);
     pl.ncell = pl.nc[0] * pl.nc[1] * pl.nc[2];
+    if (all_pairs(p)) {
+        // No lists and one (unused) cell; the list area holds the partial
+        // force rows of the j splits, one particle per lane of the step tail.
+        pl.lanes = 1;
+        pl.cell_cap = 8;
+        const size_t pb = allpairs_part_bytes(p->n, p->precision);
+        pl.cap = 16;
+        pl.cap_reserve = std::max<int32_t>(
+            16, round_up((int32_t)((pb + sizeof(int32_t) * pl.npad - 1) / (sizeof(int32_t) * pl.npad)), 16));
+        pl.max_blocks = (int)((p->n + step_block_threads(p->precision) - 1) / step_block_threads(p->precision));
+        lay_out(pl, p->precision, 1);
+        return pl;
+    }
     const double vol = p->box[0] * p->box[1] * p->box[2];
     const double rho = (double)p->n / vol;
     const double rl = list_radius_max(p);
@@ -437,6 +467,7 @@ Launch launcher(ljmd_ctx *c) {
 // The list rebuild of one step: binning, canonical cell order, [resort],
 // list build. All kernels decide on the device whether to do anything.
 int rebuild_sequence(ljmd_ctx *c, int64_t step, int forced, bool resort) {
+    if (c->g.all_pairs) return LJMD_OK;  // no lists to build
     Launch L = launcher(c);
     hipError_t e;
     if (resort) {
@@ -796,7 +827,7 @@ int batch_geom(const ljmd_params *shared, const ljmd_system *ys, int32_t nsys, B
         bg.why = "batch: NULL argument or nsys outside [1, 65536]";
         return LJMD_EINVAL;
     }
-    if (shared->nspecies != 1 || shared->precision != LJMD_FP32_DS) {
+    if (shared->nspecies != 1 || shared->precision != LJMD_FP32_DS || all_pairs(shared)) {
         bg.why = "batch: one species and the FP32 + double-single path only";
         return LJMD_EINVAL;
     }
@@ -988,6 +1019,7 @@ int ljmd_create(const ljmd_params *p, void *ws, size_t bytes, void *stream, ljmd
     g.nspecies = p->nspecies;
     g.prec = p->precision;
     g.max_blocks = pl.max_blocks;
+    g.all_pairs = all_pairs(p) ? 1 : 0;
     g.ncu = 256;
     if (c->device >= 0) {
         int ncu = 0;
@@ -1132,6 +1164,7 @@ int ljmd_kernel_times(ljmd_ctx *c, double ms[LJMD_NKT], int64_t count[LJMD_NKT])
 
 int ljmd_minimize_sd(ljmd_ctx *c, int32_t nsteps, double max_disp, double clamp, double *fmax_dev) {
     if (!c) return LJMD_EINVAL;
+    if (c->g.all_pairs) return fail(c, LJMD_EINVAL, "minimize_sd: not available for the all-pairs interaction");
     if (!c->have_state) return fail(c, LJMD_ESTATE, "minimize_sd before set_state");
     if (nsteps < 0 || !(max_disp > 0.0) || !std::isfinite(max_disp) || !(clamp >= 0.0) ||
         !std::isfinite(clamp))
@@ -1195,6 +1228,7 @@ int ljmd_get_forces(ljmd_ctx *c, double *f) {
 
 int ljmd_neighbors(ljmd_ctx *c, int32_t *cnt, int32_t *ids, int32_t cap) {
     if (!c) return LJMD_EINVAL;
+    if (c->g.all_pairs) return fail(c, LJMD_EINVAL, "neighbors: not available for the all-pairs interaction");
     if (!c->have_state) return fail(c, LJMD_ESTATE, "neighbors before set_state");
     if (!cnt || !ids || cap < 1) return fail(c, LJMD_EINVAL, "neighbors: bad arguments");
     hipError_t e = launch_neighbors(launcher(c), cnt, ids, cap);
@@ -1272,6 +1306,7 @@ int ljmd_set_pair_params(ljmd_ctx *c, const double eps[4], const double sigma[4]
 
 int ljmd_force_vjp(ljmd_ctx *c, const double *g, double *gx, double *gtheta) {
     if (!c) return LJMD_EINVAL;
+    if (c->g.all_pairs) return fail(c, LJMD_EINVAL, "force_vjp: not available for the all-pairs interaction");
     if (!c->have_state) return fail(c, LJMD_ESTATE, "force_vjp before set_state");
     if (!g || !gx || !gtheta) return fail(c, LJMD_EINVAL, "force_vjp: NULL array");
     // Scratch: the FP64 accumulator, then the cotangent in the path precision.
@@ -1298,6 +1333,7 @@ int ljmd_force_vjp(ljmd_ctx *c, const double *g, double *gx, double *gtheta) {
 
 int ljmd_energy_grad(ljmd_ctx *c, double *gtheta) {
     if (!c) return LJMD_EINVAL;
+    if (c->g.all_pairs) return fail(c, LJMD_EINVAL, "energy_grad: not available for the all-pairs interaction");
     if (!c->have_state) return fail(c, LJMD_ESTATE, "energy_grad before set_state");
     if (!gtheta) return fail(c, LJMD_EINVAL, "energy_grad: NULL array");
     hipError_t e = launch_adjoint_pairs(launcher(c), kAdjEnergy, nullptr, nullptr, 1.0, gtheta, 1);
@@ -1317,6 +1353,7 @@ int ljmd_vv_forward(ljmd_ctx *c, int32_t nsteps, int32_t ckpt_every, int32_t fla
     if (!c->have_state) return fail(c, LJMD_ESTATE, "vv_forward before set_state");
     if (nsteps < 1 || ckpt_every < 1) return fail(c, LJMD_EINVAL, "vv_forward: nsteps and ckpt_every must be >= 1");
     if (flags & ~LJMD_ADJ_STORE_ALL) return fail(c, LJMD_EINVAL, "vv_forward: unknown flags");
+    if (c->g.all_pairs) return fail(c, LJMD_EINVAL, "vv_forward: not available for the all-pairs interaction");
     if (c->dyn.thermo_on)
         return fail(c, LJMD_EINVAL, "vv_forward: the thermostat makes the dynamics stochastic (switch it off)");
     if (!adj_ws || ((uintptr_t)adj_ws & 255) != 0)

@@ -125,6 +125,7 @@ int ljmd_autotune(const ljmd_params *p, const double *x, const double *v, const 
     if (!p || !x || !v || !species || !ws || !out || steps < 1) return LJMD_EINVAL;
     int r = ljmd_check_params(p);
     if (r != LJMD_OK) return r;
+    if (std::isinf(p->rcut[0])) return LJMD_EINVAL;  // the all-pairs interaction has no lists to tune
     std::memset(out, 0, sizeof *out);
     const std::string key = tune_key(p);
     if (cache_path && cache_lookup(cache_path, key, out)) {

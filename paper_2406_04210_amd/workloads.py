@@ -192,6 +192,26 @@ def replica_draws(nrep: int = 512, seed_index: int = 4, nmin: int = 500, nmax: i
     return out
 
 
+def all_pairs_fluid(n: int = 2000, rho: float = 0.8442, temperature: float = 1.0, seed_index: int = 0,
+                    steps: int = 20000) -> Workload:
+    """The all-to-all workload (the paper's 2,000 particles): N sites kept,
+    by a seeded permutation, from the smallest FCC lattice that holds them,
+    scaled to density rho; Maxwell-Boltzmann velocities at T. The cutoffs
+    are infinite: every pair of the minimum image interacts, unshifted."""
+    rng = config_rng(seed_index)
+    m = int(math.ceil((n / 4.0) ** (1.0 / 3.0)))
+    xs, _ = fcc_lattice(m, 1.0)
+    L = (n / rho) ** (1.0 / 3.0)
+    xs = xs * (L / (m * 4.0 ** (1.0 / 3.0)))
+    keep = np.sort(rng.permutation(xs.shape[0])[:n])
+    x = np.ascontiguousarray(xs[keep])
+    sp = np.zeros(n, dtype=np.int32)
+    p = single_species_params()
+    p.rcut = np.full(4, np.inf)
+    v = maxwell_boltzmann(n, temperature, p.mass, sp, rng)
+    return Workload(f"all_pairs_n{n}", x, v, sp, np.full(3, L), p, steps, temperature)
+
+
 def random_dense(n: int, rho: float, seed: int, min_dist: float = 0.85,
                  nspecies: int = 1) -> Workload:
     """Small disordered configuration for tests: random sequential insertion
