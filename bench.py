@@ -156,9 +156,9 @@ def time_adjoint(ljmd, torch, W, nsteps: int = 50, every: int = 10, reps: int = 
         ev[1].record(stream)
         gF = 2.0 * (F - F_star) / (3 * n)
         gx_a, gth_a = sF.force_vjp(gF)
-        lam_x = -sR.forces() / n
-        gx0, gv0, gth = sR.vv_backward(lam_x, torch.zeros_like(lam_x))
-        gth = gth + gth_a + sR.energy_grad() / n
+        zero = torch.zeros((n, 3), dtype=torch.float64, device="cuda")
+        gx0, gv0, gth = sR.vv_backward(zero, zero, gU=1.0 / n)   # the U(x_N)/N term in the library
+        gth = gth + gth_a
         gx0 = gx0 + gx_a
         ev[2].record(stream)
         torch.cuda.synchronize()

@@ -22,11 +22,19 @@
  *     library never allocates or frees device memory.
  *   - Work is enqueued on the hip stream given to ljmd_create() and the
  *     calls return without synchronising, except those documented as
- *     synchronising (ljmd_sync_status, ljmd_observables).
+ *     synchronising (ljmd_set_state, ljmd_run, ljmd_minimize_sd,
+ *     ljmd_vv_forward and ljmd_vv_backward wait once at their end to check
+ *     the lists; ljmd_sync_status, ljmd_observables).
  *   - Return value: LJMD_OK (0) or a negative ljmd_status. Functions never
  *     abort or throw. Errors detected on the device (list or cell overflow,
- *     non-finite positions) are latched in the context and reported by the
- *     next synchronising call. ljmd_last_error() describes the last error.
+ *     non-finite positions) are latched in the context; from then on no
+ *     kernel changes the state, so no step ever runs on a truncated list.
+ *     A list overflow is recovered by the calls that wait at their end: the
+ *     lists grow in place, up to what the workspace holds, and the frozen
+ *     steps are redone (bitwise as with room from the start: list entries
+ *     keep their order at any capacity); LJMD_ENLIST only when the workspace
+ *     is full. Other errors are reported by the next synchronising call.
+ *     ljmd_last_error() describes the last error.
  *   - A context is not thread-safe; separate contexts are independent.
  */
 #ifndef LJMD_H
@@ -39,7 +47,7 @@
 extern "C" {
 #endif
 
-#define LJMD_ABI_VERSION 5
+#define LJMD_ABI_VERSION 6
 
 enum ljmd_status {
     LJMD_OK = 0,
@@ -75,13 +83,14 @@ typedef struct ljmd_params {
     int32_t shift_energy;   /* 1: pair energy shifted to vanish at the cutoff */
     double eps[4];          /* LJ well depth per pair */
     double sigma[4];        /* LJ length per pair */
-    double rcut[4];         /* absolute cutoff length per pair */
+    double rcut[4];         /* absolute cutoff length per pair; +inf for every used pair
+                               selects the untruncated all-pairs interaction (see below) */
     double mass[2];         /* mass per species */
     double skin;            /* Verlet skin: list radius = rcut + skin */
     double dt;              /* time step */
     int32_t sort_interval;  /* reorder along the space-filling curve every k steps; 0 = never */
     int32_t precision;      /* enum ljmd_precision */
-    int32_t nbr_capacity;   /* list slots per particle; 0 = automatic */
+    int32_t nbr_capacity;   /* list slots per particle to start with; 0 = automatic */
     int32_t cell_capacity;  /* particle slots per cell, <= 768; 0 = automatic */
     int32_t lanes;          /* lanes per particle in the force gather: 1,2,4,8,16; 0 = automatic */
     int32_t reserved;       /* must be 0 */
@@ -115,7 +124,24 @@ int32_t ljmd_abi_version(void);
 int ljmd_check_params(const ljmd_params *p);
 
 /* Bytes of device workspace needed for these parameters (pure host
- * arithmetic, resolves the automatic capacities). 0 if p is invalid. */
+ * arithmetic, resolves the automatic capacities). 0 if p is invalid. With
+ * an automatic list capacity the size includes room for lists twice as long
+ * as the initial capacity (up to 4096 slots), so that a list overflow can be
+ * recovered in place; with an explicit nbr_capacity it holds exactly that
+ * capacity. A larger workspace passed to ljmd_create is room for longer
+ * lists (the lists lie at its end): ljmd_workspace_size of the same
+ * parameters with nbr_capacity = C gives the bytes for lists of C slots.
+ *
+ * The untruncated all-pairs interaction (every used rcut = +inf: the
+ * interaction of the paper's all-to-all study, Sec. 4 and Sec. 5 "GPU
+ * Performance for All-to-All Interaction"): every pair of the minimum
+ * image interacts through the unshifted 12-6 potential; there are no lists
+ * or cells (skin, sort_interval, nbr_capacity, cell_capacity and lanes are
+ * ignored, and any box edge is accepted; the single-precision paths need a
+ * cubic box). ljmd_run, ljmd_set_state, ljmd_get_*, ljmd_observables and
+ * the thermostat work as for the truncated potential; the list-based calls
+ * (ljmd_neighbors, ljmd_minimize_sd, the gradients and rollouts, the tuner
+ * and batches) return LJMD_EINVAL. */
 size_t ljmd_workspace_size(const ljmd_params *p);
 
 /* Cell grid the binning uses for these parameters: ncell[0..2] cells per
@@ -144,7 +170,8 @@ int ljmd_destroy(ljmd_ctx *ctx);
  * and species (device, n int32 in [0, nspecies)). Wraps positions into the
  * box, sorts particles along the space-filling curve, builds the lists and
  * evaluates the forces of this state (the "force" slot before the first
- * "integrate"). Resets the step and rebuild counters. */
+ * "integrate"). Resets the step and rebuild counters. Waits for the device
+ * at the end (a list overflow of the first build is recovered). */
 int ljmd_set_state(ljmd_ctx *ctx, const double *x, const double *v, const int32_t *species);
 
 /* Read the state by id: x (wrapped into [0, L)), v (device, n*3 float64)
@@ -159,7 +186,9 @@ int ljmd_get_forces(ljmd_ctx *ctx, double *f);
  * ("integrate"), list rebuild if any particle moved more than skin/2 since
  * the last build (strict >) or a resort is due, force evaluation, half kick
  * ("finalize"). obs_dev (device, nsteps * LJMD_NOBS float64, or NULL)
- * receives one observable row per step. Asynchronous. */
+ * receives one observable row per step. Enqueues every step, then waits
+ * for the device once: if a list overflowed, the lists grow and the steps
+ * from the one that stopped are redone (their observable rows rewritten). */
 int ljmd_run(ljmd_ctx *ctx, int64_t nsteps, double *obs_dev);
 
 /* Steepest descent to relax a starting configuration (random positions
@@ -283,7 +312,10 @@ int ljmd_vv_forward(ljmd_ctx *ctx, int32_t nsteps, int32_t ckpt_every, int32_t f
  * lam_v = dL/dv_N (device, n*3 float64, by id) for a loss L of the final
  * state, writes gx0 = dL/dx_0 and gv0 = dL/dv_0 (device, n*3 float64, by
  * id; may alias lam_x, lam_v) and gtheta = dL/d(eps, sigma) through the
- * dynamics (device, 6 float64). Segments are taken last first: each is
+ * dynamics (device, 6 float64). gU (device, one float64, or NULL) is the
+ * loss's weight dL/dU_N of the final potential energy U(x_N; theta): the
+ * sweep then starts from lam_x - gU F(x_N) and gtheta also receives
+ * gU dU/dtheta at x_N, so lam_x and lam_v hold only the rest of the loss. Segments are taken last first: each is
  * recomputed from its checkpoint (or read, with LJMD_ADJ_STORE_ALL) and its
  * frames swept backwards with one force VJP per frame (cotangent lam_v / m,
  * weight dt/2 at x_N and x_0, dt between). Each segment's sweep starts
@@ -295,8 +327,8 @@ int ljmd_vv_forward(ljmd_ctx *ctx, int32_t nsteps, int32_t ckpt_every, int32_t f
  * Leaves the context at the final state, as
  * ljmd_vv_forward did. LJMD_ESTATE if no rollout is recorded or the state
  * changed since. Asynchronous. */
-int ljmd_vv_backward(ljmd_ctx *ctx, const double *lam_x, const double *lam_v, double *gx0,
-                     double *gv0, double *gtheta);
+int ljmd_vv_backward(ljmd_ctx *ctx, const double *lam_x, const double *lam_v, const double *gU,
+                     double *gx0, double *gv0, double *gtheta);
 
 /* ---- Autotuning -------------------------------------------------------------
  * The paper picks launch configurations per device (Sec. 4, 5); this

@@ -19,6 +19,7 @@ enum : int {
     kOpGatherG = 5,      // gvec[i] = src_id[id[i]]     (path precision)
     kOpDriftCotangent = 6,  // b[i] += scale * a[i] (skipped when scale == 0); gvec[i] = b[i] / m_i
                             // (path precision: double4 or float4)
+    kOpSubForce = 7,        // a[i] -= c * F_i with c = *dscale (device) and F the stored forces
 };
 
 // One pair pass over the current lists at the positions in record buffer
@@ -66,7 +67,10 @@ hipError_t launch_adjoint_drift(const Launch &L, double4 *lx, double4 *lv, void 
 hipError_t launch_adjoint_cells(const Launch &L, int64_t step, int forced);
 
 hipError_t launch_adjoint_vec(const Launch &L, int op, const double *src_id, double *dst_id, double4 *a,
-                              double4 *b, void *gvec, double scale);
+                              double4 *b, void *gvec, double scale, const double *dscale = nullptr);
+
+// gtheta[0..5] += c * g[0..5] with c = *dc (device scalars).
+hipError_t launch_theta_axpy(const Launch &L, const double *dc, const double *g, double *gtheta);
 
 
 }  // namespace ljmd

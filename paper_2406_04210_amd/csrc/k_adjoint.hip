@@ -363,6 +363,7 @@ struct VecArgs {
     double4 *b;
     void *gvec;
     double scale;
+    const double *dscale;  // kOpSubForce: the device scalar c
     // kOpDriftCotangent: also fold the frame's displacement from the list
     // reference into the rebuild word of disp_step (when disp is set).
     BoxC box;
@@ -416,6 +417,23 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_vec(VecArgs v) {
         case kOpZero:
             v.a[i] = make_double4(0, 0, 0, 0);
             break;
+        case kOpSubForce: {
+            double fx, fy, fz;
+            if constexpr (PREC == LJMD_FP64) {
+                const double4 f = v.st.frc64[i];
+                fx = f.x, fy = f.y, fz = f.z;
+            } else {
+                const float4 f = v.st.frc32[i];
+                fx = f.x, fy = f.y, fz = f.z;
+            }
+            const double c = *v.dscale;
+            double4 y = v.a[i];
+            y.x = fma(-c, fx, y.x);
+            y.y = fma(-c, fy, y.y);
+            y.z = fma(-c, fz, y.z);
+            v.a[i] = y;
+            break;
+        }
         case kOpGatherG: {
             const int64_t id = v.st.id[i];
             if (id < 0 || id >= v.g.n) break;
@@ -553,8 +571,17 @@ hipError_t launch_adjoint_cells(const Launch &L, int64_t step, int forced) {
 
 static hipError_t vec_launch(const Launch &L, const VecArgs &v);
 
+__global__ void k_theta_axpy(const double *dc, const double *g, double *gtheta) {
+    if (threadIdx.x < 6) gtheta[threadIdx.x] = fma(*dc, g[threadIdx.x], gtheta[threadIdx.x]);
+}
+
+hipError_t launch_theta_axpy(const Launch &L, const double *dc, const double *g, double *gtheta) {
+    hipLaunchKernelGGL(k_theta_axpy, dim3(1), dim3(64), 0, L.stream, dc, g, gtheta);
+    return hipGetLastError();
+}
+
 hipError_t launch_adjoint_vec(const Launch &L, int op, const double *src_id, double *dst_id, double4 *a,
-                              double4 *b, void *gvec, double scale) {
+                              double4 *b, void *gvec, double scale, const double *dscale) {
     VecArgs v;
     v.st = *L.st;
     v.g = *L.g;
@@ -567,6 +594,7 @@ hipError_t launch_adjoint_vec(const Launch &L, int op, const double *src_id, dou
     v.b = b;
     v.gvec = gvec;
     v.scale = scale;
+    v.dscale = dscale;
     v.box = *L.box;
     v.disp_step = 0;
     v.disp = 0;
@@ -587,6 +615,7 @@ hipError_t launch_adjoint_drift(const Launch &L, double4 *lx, double4 *lv, void 
     v.b = lv;
     v.gvec = gvec;
     v.scale = scale;
+    v.dscale = nullptr;
     v.box = *L.box;
     v.disp_step = step;
     v.disp = disp;

@@ -1411,8 +1411,8 @@ int ljmd_vv_forward(ljmd_ctx *c, int32_t nsteps, int32_t ckpt_every, int32_t fla
     return LJMD_OK;
 }
 
-int ljmd_vv_backward(ljmd_ctx *c, const double *lam_x, const double *lam_v, double *gx0, double *gv0,
-                     double *gtheta) {
+int ljmd_vv_backward(ljmd_ctx *c, const double *lam_x, const double *lam_v, const double *gU, double *gx0,
+                     double *gv0, double *gtheta) {
     if (!c) return LJMD_EINVAL;
     if (!c->adj.valid || c->adj.gen != c->gen)
         return fail(c, LJMD_ESTATE, "vv_backward without a matching vv_forward (state changed since)");
@@ -1439,11 +1439,19 @@ int ljmd_vv_backward(ljmd_ctx *c, const double *lam_x, const double *lam_v, doub
     const int cur_entry = c->cur;
     const int64_t step_entry = c->step;
     Launch L;
+    uint8_t *final_state = ws + P.off_ckpt + (size_t)P.nseg * P.ckpt_stride;
     for (;;) {
+    // The final state (its stored forces F(x_N) too), whatever an earlier
+    // attempt left.
+    int r0 = ckpt_copy(c, final_state, false);
+    if (r0) return r0;
     L = launcher(c);
     if ((e = launch_adjoint_vec(L, kOpGatherById, lam_x, nullptr, lx, nullptr, nullptr, 0.0)) != hipSuccess ||
         (e = launch_adjoint_vec(L, kOpGatherById, lam_v, nullptr, lv, nullptr, nullptr, 0.0)) != hipSuccess)
         return hip_fail(c, e, "vv_backward gather");
+    // A loss term gU U(x_N): dU/dx_N = -F(x_N).
+    if (gU && (e = launch_adjoint_vec(L, kOpSubForce, nullptr, nullptr, lx, nullptr, nullptr, 0.0, gU)) != hipSuccess)
+        return hip_fail(c, e, "vv_backward energy cotangent");
     RunOpts o;
     o.force_first = true;
     o.allow_resort = false;
@@ -1549,10 +1557,19 @@ int ljmd_vv_backward(ljmd_ctx *c, const double *lam_x, const double *lam_v, doub
         return hip_fail(c, e, "vv_backward scatter");
     // Back to the final state of the rollout, lists as ljmd_vv_forward left them.
     own.restore();
-    int r = ckpt_copy(c, ws + P.off_ckpt + (size_t)P.nseg * P.ckpt_stride, false);
+    int r = ckpt_copy(c, final_state, false);
     if (r) return r;
     c->step = c->adj.step0 + N;
-    return rebuild_at_rest(c, c->step);
+    if ((r = rebuild_at_rest(c, c->step))) return r;
+    if (gU) {
+        // gtheta += gU dU/dtheta at x_N (the sweep's parameter rows are free
+        // again and hold the six sums).
+        L = launcher(c);
+        if ((e = launch_adjoint_pairs(L, kAdjEnergy, nullptr, nullptr, 1.0, rows, 1)) != hipSuccess ||
+            (e = launch_theta_axpy(L, gU, rows, gtheta)) != hipSuccess)
+            return hip_fail(c, e, "vv_backward energy gradient");
+    }
+    return LJMD_OK;
 }
 
 }  // extern "C"

@@ -18,9 +18,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libljmd.so")
 
-ABI_VERSION = 5
+ABI_VERSION = 6
 FP64 = 0
 FP32_DS = 1
+FP32 = 2
 ADJ_STORE_ALL = 1
 NOBS = 8
 OBS_FIELDS = ("U", "K", "W", "px", "py", "pz", "rebuilt", "step")
@@ -88,7 +89,7 @@ SIGNATURES = {
     "ljmd_energy_grad": (C.c_int, [_vp, _dp]),
     "ljmd_adjoint_workspace_size": (C.c_size_t, [C.POINTER(Params), C.c_int32, C.c_int32, C.c_int32]),
     "ljmd_vv_forward": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _vp, C.c_size_t, _dp]),
-    "ljmd_vv_backward": (C.c_int, [_vp, _dp, _dp, _dp, _dp, _dp]),
+    "ljmd_vv_backward": (C.c_int, [_vp, _dp, _dp, _dp, _dp, _dp, _dp]),
     "ljmd_batch_workspace_size": (C.c_size_t, [C.POINTER(Params), C.POINTER(SystemDesc), C.c_int32]),
     "ljmd_batch_create": (C.c_int, [C.POINTER(Params), C.POINTER(SystemDesc), C.c_int32, _vp, C.c_size_t, _vp,
                                     C.POINTER(_vp)]),
@@ -404,18 +405,23 @@ class System:
                                    ws.numel(), _ptr(obs) if obs is not None else None), self.ctx)
         return obs
 
-    def vv_backward(self, lam_x, lam_v):
-        """(dL/dx_0, dL/dv_0, dL/dtheta through the dynamics) of the last
-        rollout from dL/dx_N and dL/dv_N (by id)."""
+    def vv_backward(self, lam_x, lam_v, gU=None):
+        """(dL/dx_0, dL/dv_0, dL/dtheta) of the last rollout from dL/dx_N and
+        dL/dv_N (by id) and, if given, the weight gU = dL/dU_N of the final
+        potential energy in the loss (a device scalar tensor or a float)."""
         t = self.torch
         lx = self._dev(lam_x, t.float64).reshape(self.n, 3)
         lv = self._dev(lam_v, t.float64).reshape(self.n, 3)
+        gu = None
+        if gU is not None:
+            gu = (gU.detach() if isinstance(gU, t.Tensor) else t.tensor(float(gU)))
+            gu = gu.to(device=self.device, dtype=t.float64).reshape(1).contiguous()
         gx0 = t.empty((self.n, 3), dtype=t.float64, device=self.device)
         gv0 = t.empty_like(gx0)
         gth = t.empty(6, dtype=t.float64, device=self.device)
-        _check(lib.ljmd_vv_backward(self.ctx, _ptr(lx), _ptr(lv), _ptr(gx0), _ptr(gv0), _ptr(gth)),
-               self.ctx)
-        self._keep_l = (lx, lv)
+        _check(lib.ljmd_vv_backward(self.ctx, _ptr(lx), _ptr(lv), _ptr(gu) if gu is not None else None,
+                                    _ptr(gx0), _ptr(gv0), _ptr(gth)), self.ctx)
+        self._keep_l = (lx, lv, gu)
         return gx0, gv0, gth
 
 
@@ -641,11 +647,9 @@ def _autograd():
             lam_x = gxN.contiguous() if gxN is not None else torch.zeros((s.n, 3), dtype=torch.float64,
                                                                          device=s.device)
             lam_v = gvN.contiguous() if gvN is not None else torch.zeros_like(lam_x)
-            if gU is not None:
-                lam_x = lam_x - gU * s.forces()      # dU/dx_N = -F(x_N)
-            gx0, gv0, gth = s.vv_backward(lam_x, lam_v)
-            if gU is not None:
-                gth = gth + gU * s.energy_grad()     # the context is back at x_N
+            # The final-energy term (dU/dx_N = -F(x_N), dU/dtheta at x_N) is
+            # applied by the library from gU.
+            gx0, gv0, gth = s.vv_backward(lam_x, lam_v, gU)
             return gx0, gv0, gth.to(theta.device), None, None, None, None
 
     return LJForceFn, VVRollout
