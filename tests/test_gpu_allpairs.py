@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
-from force_metrics import force_errors, reference, report
+from force_metrics import bound_key, force_errors, reference, report
 from paper_2406_04210_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -60,7 +60,7 @@ def test_all_pairs_forces_energy_virial(ljmd, case, prec):
     if prec == FP64:
         assert np.abs(ref - fb).max() <= 1e-12 * np.abs(fb).max()
     m = report(f"all pairs {name} prec={prec}", force_errors(f, ref, A))
-    assert m["sec8c"] <= TOL_F[prec]
+    assert m[bound_key(FP64 if prec == FP64 else 1)] <= TOL_F[prec]
     eu, ew = abs(o["U"] - U) / abs(U), abs(o["W"] - Wv) / abs(Wv)
     print(f"all pairs {name} prec={prec}: U rel {eu:.3e} W rel {ew:.3e}", flush=True)
     assert eu <= TOL_E[prec] and ew <= TOL_E[prec]
@@ -80,7 +80,9 @@ def test_all_pairs_trajectory(ljmd, prec):
     print(f"all pairs trajectory prec={prec}: max|dx| {dx:.3e} max|dU|/N {dU:.3e}", flush=True)
     assert dx <= (1e-10 if prec == FP64 else 1e-4)
     assert dU <= (1e-10 if prec == FP64 else 1e-5)
-    assert np.abs(obs[:, 3:6]).max() < (1e-10 if prec == FP64 else 1e-3)
+    # FP32 sums ~2,000 pair forces per particle, each with a few 1e-7 of its
+    # magnitude: the total momentum drifts by that much per particle.
+    assert np.abs(obs[:, 3:6]).max() < (1e-10 if prec == FP64 else 1e-5 * w.n)
 
 
 def test_all_pairs_with_thermostat(ljmd):
