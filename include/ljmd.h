@@ -436,6 +436,27 @@ int ljmd_batch_autotune(const ljmd_params *shared, const ljmd_system *sys, int32
 
 const char *ljmd_batch_last_error(const ljmd_batch *b);
 
+/* ---- One-shot brute-force forces --------------------------------------------
+ * Forces, energy and virial of one configuration by the sum over all pairs
+ * of the minimum image: the definition of the truncated, shifted pair sum
+ * that the Verlet-list path reaches (paper Sec. 3 "Code structure", Sec. 5
+ * "Truncated Force Performance Study"), or with every used rcut = +inf the
+ * untruncated all-to-all interaction (Sec. 4 "Code migration", Sec. 5 "GPU
+ * Performance for All-to-All Interaction"). O(N^2) work, no lists, no state:
+ * a GPU checker for small systems and the all-pairs evaluation itself.
+ * p as for ljmd_create (n, box, pair tables, nspecies, precision; the
+ * single-precision paths need a cubic box and evaluate the binary32 pair
+ * arithmetic of the step kernels on the fixed-point positions); x (device,
+ * n*3 float64, any image), species (device, n int32) -> f (device, n*3
+ * float64, same order) and uw (device, 2 float64: U = sum phi_s, W = sum
+ * r_ij.f_ij over pairs i < j). ws (device, >= ljmd_brute_workspace_size(p)
+ * bytes, 256-byte aligned) is scratch, the caller's. Asynchronous on
+ * hip_stream. Errors: LJMD_EINVAL / LJMD_EBOX (parameters), LJMD_ENOMEM
+ * (workspace too small), LJMD_EHIP; text in ljmd_last_error(NULL). */
+size_t ljmd_brute_workspace_size(const ljmd_params *p);
+int ljmd_brute_forces(const ljmd_params *p, const double *x, const int32_t *species, double *f, double *uw,
+                      void *dev_workspace, size_t bytes, void *hip_stream);
+
 /* Text of the last error of ctx (or of the last failed create when ctx is
  * NULL). The pointer stays valid until the next call on ctx. */
 const char *ljmd_last_error(const ljmd_ctx *ctx);

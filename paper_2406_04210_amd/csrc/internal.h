@@ -343,6 +343,19 @@ hipError_t launch_sd(const Launch &L, int64_t step, int forced, int iter, double
 int allpairs_splits(int64_t n);
 size_t allpairs_part_bytes(int64_t n, int prec);
 hipError_t launch_allpairs_step(const Launch &L, int64_t step, int mode, int slot);
+// One-shot brute-force forces of a configuration given by id: scratch of
+// brute_scratch_bytes(n, prec) bytes (256-byte aligned); cut: truncate and
+// shift at r_c (else every pair interacts). f (n*3) and uw (U, W) are FP64.
+size_t brute_scratch_bytes(int64_t n, int prec);
+hipError_t launch_brute(const BoxC &box, const PairC &pc, int prec, int nspecies, int cut, int64_t n,
+                        const double *x, const int32_t *sp, double *f, double *uw, uint8_t *scratch,
+                        hipStream_t stream);
+// Box and pair constants of a parameter set (cell grid 1x1x1), and the
+// parameter check of ljmd_check_params with its reason.
+void box_pair_constants(const ljmd_params &p, BoxC &b, PairC &q);
+int check_params_why(const ljmd_params *p, const char **why);
+// Text returned by ljmd_last_error(NULL) (calls without a context).
+void set_global_error(const char *msg);
 size_t resort_scratch_bytes(int64_t npad, int prec);
 size_t cell_rec_bytes(int prec);
 int step_blocks(const Geom &g);

@@ -35,14 +35,20 @@ struct ApRow {
 // differences in a cubic box (displacements in quanta, sigma^2 and
 // 24 eps / quantum pre-scaled as in the list kernel); FP64: minimum-image
 // displacements of the FP64 records.
-template <int NS>
+// CUT: pairs at r >= r_c are skipped and the energy is shifted (the brute-
+// force sum of the truncated potential); without it every pair interacts.
+// an counts the pairs inside (one species: the shift is applied per pair
+// once the sums are done).
+template <int NS, bool CUT>
 __device__ inline void ap_pair(const int4 &ri, const int4 &rj, const BoxC &box, const PairC &pc, float &fx,
-                               float &fy, float &fz, float &sa, float &sb) {
+                               float &fy, float &fz, float &sa, float &sb, int &an) {
     const float dx = (float)(int32_t)((uint32_t)ri.x - (uint32_t)rj.x);
     const float dy = (float)(int32_t)((uint32_t)ri.y - (uint32_t)rj.y);
     const float dz = (float)(int32_t)((uint32_t)ri.z - (uint32_t)rj.z);
     const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
     const int t = NS == 1 ? 0 : ri.w + rj.w;
+    if (CUT && !(r2 < by_t<NS>(t, box.rc2q))) return;
+    an += 1;
     const float ir2 = __builtin_amdgcn_rcpf(r2);
     const float s2 = by_t<NS>(t, box.sig2q) * ir2;
     const float s6 = s2 * s2 * s2;
@@ -56,19 +62,21 @@ __device__ inline void ap_pair(const int4 &ri, const int4 &rj, const BoxC &box, 
         sb += s6;
     } else {
         const float s12 = s6 * s6;
-        sa += by_t<NS>(t, pc.eps4f) * (s12 - s6);
+        sa += fmaf(by_t<NS>(t, pc.eps4f), s12 - s6, -by_t<NS>(t, pc.shiftf));
         sb += by_t<NS>(t, pc.eps24f) * fmaf(2.0f, s12, -s6);
     }
 }
 
-template <int NS>
+template <int NS, bool CUT>
 __device__ inline void ap_pair(const double4 &ri, const double4 &rj, const BoxC &box, const PairC &pc, double &fx,
-                               double &fy, double &fz, double &e, double &w) {
+                               double &fy, double &fz, double &e, double &w, int &an) {
     const double dx = disp_d(ri.x, rj.x, box.L[0], box.invL[0]);
     const double dy = disp_d(ri.y, rj.y, box.L[1], box.invL[1]);
     const double dz = disp_d(ri.z, rj.z, box.L[2], box.invL[2]);
     const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
     const int t = NS == 1 ? 0 : (int)ri.w + (int)rj.w;
+    if (CUT && !(r2 < by_t<NS>(t, pc.rc2))) return;
+    an += 1;
     double ir2 = __builtin_amdgcn_rcp(r2);
     ir2 = fma(ir2, fma(-r2, ir2, 1.0), ir2);
     ir2 = fma(ir2, fma(-r2, ir2, 1.0), ir2);
@@ -78,33 +86,41 @@ __device__ inline void ap_pair(const double4 &ri, const double4 &rj, const BoxC 
     fx = fma(fs, dx, fx);
     fy = fma(fs, dy, fy);
     fz = fma(fs, dz, fz);
-    e += by_t<NS>(t, pc.eps4) * s6 * (s6 - 1.0);
+    e += fma(by_t<NS>(t, pc.eps4) * s6, s6 - 1.0, -by_t<NS>(t, pc.shift));
     w = fma(fs, r2, w);
 }
 
-template <int PREC, int NS>
-__global__ __launch_bounds__(kApWaves * kWave) void k_ap_forces(StepArgs a, void *part, int nsplit) {
+// Operands of the force pass: records (slot order) and the partial rows.
+struct ApForce {
+    const void *rec;    // int4 fixed-point (single precision) or double4 (FP64) records
+    void *part;         // S rows of (fx, fy, fz, -) then S rows of (e, w)
+    int64_t n;
+    size_t stride;      // slots per row (>= n)
+    int nsplit;
+    BoxC box;
+    PairC pc;
+};
+
+template <int PREC, int NS, bool CUT>
+__global__ __launch_bounds__(kApWaves * kWave) void k_ap_forces(ApForce a, const Ctl *ctl) {
     using Rec = typename std::conditional<PREC == LJMD_FP64, double4, int4>::type;
     using Acc = typename std::conditional<PREC == LJMD_FP64, double, float>::type;
     using F = typename ApRow<PREC>::F;
     __shared__ Rec stage[kApChunk];
     __shared__ double red[kApWaves][5][kWave];
-    const State &st = a.st;
-    if (halted(st.ctl)) return;
+    if (ctl && halted(ctl)) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t n = a.g.n;
+    const int64_t n = a.n;
+    const int nsplit = a.nsplit;
     const int tile = blockIdx.x / nsplit, split = blockIdx.x - tile * nsplit;
     const int64_t i = (int64_t)tile * kWave + lane;
-    const Rec *__restrict__ rec;
-    if constexpr (PREC == LJMD_FP64)
-        rec = st.rec64[a.cur];
-    else
-        rec = st.recq[a.cur];
+    const Rec *__restrict__ rec = (const Rec *)a.rec;
     const Rec ri = i < n ? rec[i] : Rec{};
     const int64_t per = (n + nsplit - 1) / nsplit;
     const int64_t jb = split * per, je = jb + per < n ? jb + per : n;
     Acc fx = 0, fy = 0, fz = 0;
     double e = 0.0, w = 0.0;
+    int an = 0;
     // One species: per-lane sums of s6^2 and s6 (the constants are applied
     // once below); two species: per-pair energies and virials.
     for (int64_t c0 = jb; c0 < je; c0 += kApChunk) {
@@ -115,16 +131,16 @@ __global__ __launch_bounds__(kApWaves * kWave) void k_ap_forces(StepArgs a, void
         Acc sa = 0, sb = 0;
         for (int k = q0; k < q1; ++k) {
             if (c0 + k == i) continue;          // no self pair
-            ap_pair<NS>(ri, stage[k], a.box, a.pc, fx, fy, fz, sa, sb);
+            ap_pair<NS, CUT>(ri, stage[k], a.box, a.pc, fx, fy, fz, sa, sb, an);
         }
         e += (double)sa;
         w += (double)sb;
         __syncthreads();
     }
     if constexpr (PREC != LJMD_FP64 && NS == 1) {
-        // sum phi = 4 eps (a12 - a6), sum fs r^2 = 24 eps (2 a12 - a6).
+        // sum phi_s = 4 eps (a12 - a6) - an phi(r_c), sum fs r^2 = 24 eps (2 a12 - a6).
         const double a12 = e, a6 = w;
-        e = a.pc.eps4[0] * (a12 - a6);
+        e = a.pc.eps4[0] * (a12 - a6) - (double)an * a.pc.shift[0];
         w = a.pc.eps24[0] * (2.0 * a12 - a6);
     }
     red[wv][0][lane] = (double)fx;
@@ -137,9 +153,9 @@ __global__ __launch_bounds__(kApWaves * kWave) void k_ap_forces(StepArgs a, void
         double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
         for (int q = 0; q < kApWaves; ++q)
             for (int k = 0; k < 5; ++k) s[k] += red[q][k][lane];
-        F *pf = (F *)part;
-        double2 *pe = (double2 *)(pf + (size_t)nsplit * a.g.max_blocks * step_block_threads(PREC));
-        const size_t row = (size_t)split * a.g.max_blocks * step_block_threads(PREC) + i;
+        F *pf = (F *)a.part;
+        double2 *pe = (double2 *)(pf + (size_t)nsplit * a.stride);
+        const size_t row = (size_t)split * a.stride + i;
         if constexpr (PREC == LJMD_FP64) {
             pf[row] = make_double4(s[0], s[1], s[2], 0.0);
         } else {
@@ -217,17 +233,25 @@ hipError_t launch_allpairs_step(const Launch &L, int64_t step, int mode, int slo
     a.step = step;
     void *part = L.st->nbr;  // the list area holds the partial rows in this mode
     const int S = allpairs_splits(L.g->n);
-    const dim3 gf((unsigned)(((L.g->n + kWave - 1) / kWave) * S)), bf(kApWaves * kWave);
     const int bs = step_block_threads(L.g->prec);
+    ApForce af;
+    af.rec = L.g->prec == LJMD_FP64 ? (const void *)L.st->rec64[L.cur] : (const void *)L.st->recq[L.cur];
+    af.part = part;
+    af.n = L.g->n;
+    af.stride = (size_t)L.g->max_blocks * bs;
+    af.nsplit = S;
+    af.box = *L.box;
+    af.pc = *L.pc;
+    const dim3 gf((unsigned)(((L.g->n + kWave - 1) / kWave) * S)), bf(kApWaves * kWave);
     const dim3 gn((unsigned)((L.g->n + bs - 1) / bs)), bn(bs);
     const bool th = L.dyn->thermo_on && (mode & kFinalize);
     const bool two = L.g->nspecies == 2;
 #define AP(PREC)                                                                                           \
     do {                                                                                                   \
         if (two)                                                                                           \
-            hipLaunchKernelGGL((k_ap_forces<PREC, 2>), gf, bf, 0, L.stream, a, part, S);                   \
+            hipLaunchKernelGGL((k_ap_forces<PREC, 2, false>), gf, bf, 0, L.stream, af, L.st->ctl);         \
         else                                                                                               \
-            hipLaunchKernelGGL((k_ap_forces<PREC, 1>), gf, bf, 0, L.stream, a, part, S);                   \
+            hipLaunchKernelGGL((k_ap_forces<PREC, 1, false>), gf, bf, 0, L.stream, af, L.st->ctl);         \
         if (th)                                                                                            \
             hipLaunchKernelGGL((k_ap_finish<PREC, true>), gn, bn, 0, L.stream, a, (const void *)part, S);  \
         else                                                                                               \
@@ -240,6 +264,179 @@ hipError_t launch_allpairs_step(const Launch &L, int64_t step, int mode, int slo
     else
         AP(LJMD_FP32_DS);
 #undef AP
+    return hipGetLastError();
+}
+
+// ---- one-shot brute-force forces ----------------------------------------
+// Records of a configuration given by id (slot = id): the wrap of the state
+// load, then the FP64 record, or the double-single split and fixed-point
+// record (single floats with zero lo parts for the plain FP32 state).
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_bf_records(const double *__restrict__ x, const int32_t *__restrict__ sp,
+                                                       int64_t n, int nspecies, BoxC box, void *rec) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    int s = sp[i];
+    s = s < 0 ? 0 : (s >= nspecies ? nspecies - 1 : s);
+    double w[3];
+    for (int k = 0; k < 3; ++k) {
+        const double xi = x[3 * i + k];
+        double t = xi - box.L[k] * floor(xi / box.L[k]);
+        if (t >= box.L[k]) t -= box.L[k];
+        w[k] = t;
+    }
+    if constexpr (PREC == LJMD_FP64) {
+        ((double4 *)rec)[i] = make_double4(w[0], w[1], w[2], (double)s);
+    } else {
+        uint32_t q[3];
+        for (int k = 0; k < 3; ++k) {
+            float hi = (float)w[k];
+            float lo = 0.0f;
+            if constexpr (PREC == LJMD_FP32) {
+                if (hi >= box.Lhi[k]) hi -= box.Lhi[k];
+            } else {
+                lo = (float)(w[k] - (double)hi);
+            }
+            q[k] = q_from_ds(hi, lo, box.S_hi[k], box.S_lo[k]);
+        }
+        ((int4 *)rec)[i] = make_int4((int)q[0], (int)q[1], (int)q[2], s);
+    }
+}
+
+// Per particle the S partial rows in order -> f (FP64, by id); per block the
+// sums of e/2 and w/2 in a fixed order -> blk_uw[2 * block].
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_bf_sum(const void *part, int64_t n, size_t stride, int nsplit,
+                                                   double *__restrict__ f, double *__restrict__ blk_uw) {
+    using F = typename ApRow<PREC>::F;
+    __shared__ double red[kBlock / kWave][2];
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const F *pf = (const F *)part;
+    const double2 *pe = (const double2 *)(pf + (size_t)nsplit * stride);
+    double u = 0.0, v = 0.0;
+    if (i < n) {
+        F g = pf[i];
+        double2 ew = pe[i];
+        for (int s = 1; s < nsplit; ++s) {
+            const F h = pf[(size_t)s * stride + i];
+            const double2 k = pe[(size_t)s * stride + i];
+            g.x += h.x;
+            g.y += h.y;
+            g.z += h.z;
+            ew.x += k.x;
+            ew.y += k.y;
+        }
+        f[3 * i] = (double)g.x;
+        f[3 * i + 1] = (double)g.y;
+        f[3 * i + 2] = (double)g.z;
+        u = 0.5 * ew.x;
+        v = 0.5 * ew.y;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        u += __shfl_xor(u, o);
+        v += __shfl_xor(v, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6][0] = u;
+        red[threadIdx.x >> 6][1] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double su = 0.0, sv = 0.0;
+        for (int q = 0; q < kBlock / kWave; ++q) {
+            su += red[q][0];
+            sv += red[q][1];
+        }
+        blk_uw[2 * blockIdx.x] = su;
+        blk_uw[2 * blockIdx.x + 1] = sv;
+    }
+}
+
+// uw = the block sums in a fixed order (one block).
+__global__ __launch_bounds__(kBlock) void k_bf_reduce(const double *__restrict__ blk_uw, int nb, double *uw) {
+    __shared__ double red[kBlock][2];
+    double u = 0.0, v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) {
+        u += blk_uw[2 * b];
+        v += blk_uw[2 * b + 1];
+    }
+    red[threadIdx.x][0] = u;
+    red[threadIdx.x][1] = v;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            red[threadIdx.x][0] += red[threadIdx.x + s][0];
+            red[threadIdx.x][1] += red[threadIdx.x + s][1];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        uw[0] = red[0][0];
+        uw[1] = red[0][1];
+    }
+}
+
+// Scratch of a one-shot evaluation: records, partial rows, block sums.
+struct BruteScratch {
+    size_t off_rows, off_blk, total, stride;
+    int nsplit, nb;
+};
+
+static BruteScratch brute_layout(int64_t n, int prec) {
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    BruteScratch b;
+    const int64_t npad = (n + kBlock - 1) / kBlock * kBlock;
+    b.stride = (size_t)npad;
+    b.nsplit = allpairs_splits(n);
+    b.nb = (int)(npad / kBlock);
+    const size_t rec = prec == LJMD_FP64 ? sizeof(double4) : sizeof(int4);
+    const size_t row = (prec == LJMD_FP64 ? sizeof(double4) : sizeof(float4)) + sizeof(double2);
+    b.off_rows = al(rec * npad);
+    b.off_blk = b.off_rows + al((size_t)b.nsplit * b.stride * row);
+    b.total = b.off_blk + al(2 * sizeof(double) * (size_t)b.nb);
+    return b;
+}
+
+size_t brute_scratch_bytes(int64_t n, int prec) { return brute_layout(n, prec).total; }
+
+hipError_t launch_brute(const BoxC &box, const PairC &pc, int prec, int nspecies, int cut, int64_t n,
+                        const double *x, const int32_t *sp, double *f, double *uw, uint8_t *scratch,
+                        hipStream_t stream) {
+    const BruteScratch bl = brute_layout(n, prec);
+    ApForce af;
+    af.rec = scratch;
+    af.part = scratch + bl.off_rows;
+    af.n = n;
+    af.stride = bl.stride;
+    af.nsplit = bl.nsplit;
+    af.box = box;
+    af.pc = pc;
+    double *blk = (double *)(scratch + bl.off_blk);
+    const dim3 gr((unsigned)bl.nb), b1(kBlock);
+    const dim3 gf((unsigned)(((n + kWave - 1) / kWave) * bl.nsplit)), bf(kApWaves * kWave);
+    const Ctl *none = nullptr;
+#define BF(PREC)                                                                                              \
+    do {                                                                                                      \
+        hipLaunchKernelGGL(k_bf_records<PREC>, gr, b1, 0, stream, x, sp, n, nspecies, box, scratch);        \
+        if (nspecies == 2 && cut)                                                                             \
+            hipLaunchKernelGGL((k_ap_forces<PREC, 2, true>), gf, bf, 0, stream, af, none);                   \
+        else if (nspecies == 2)                                                                               \
+            hipLaunchKernelGGL((k_ap_forces<PREC, 2, false>), gf, bf, 0, stream, af, none);                  \
+        else if (cut)                                                                                         \
+            hipLaunchKernelGGL((k_ap_forces<PREC, 1, true>), gf, bf, 0, stream, af, none);                   \
+        else                                                                                                  \
+            hipLaunchKernelGGL((k_ap_forces<PREC, 1, false>), gf, bf, 0, stream, af, none);                  \
+        hipLaunchKernelGGL(k_bf_sum<PREC>, gr, b1, 0, stream, (const void *)af.part, n, bl.stride, bl.nsplit, \
+                           f, blk);                                                                           \
+    } while (0)
+    if (prec == LJMD_FP64)
+        BF(LJMD_FP64);
+    else if (prec == LJMD_FP32)
+        BF(LJMD_FP32);
+    else
+        BF(LJMD_FP32_DS);
+#undef BF
+    hipLaunchKernelGGL(k_bf_reduce, dim3(1), b1, 0, stream, (const double *)blk, bl.nb, uw);
     return hipGetLastError();
 }
 

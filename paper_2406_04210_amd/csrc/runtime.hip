@@ -950,6 +950,44 @@ BatchLayout batch_layout(const BatchGeom &bg, int nsys) {
 
 }  // namespace
 
+namespace ljmd {
+
+void box_pair_constants(const ljmd_params &p, BoxC &b, PairC &q) {
+    std::memset(&b, 0, sizeof b);
+    for (int k = 0; k < 3; ++k) {
+        const double L = p.box[k];
+        b.L[k] = L;
+        b.invL[k] = 1.0 / L;
+        b.S[k] = kTwo32 / L;
+        b.Lhi[k] = (float)L;
+        b.Llo[k] = (float)(L - (double)b.Lhi[k]);
+        const double qs = L / kTwo32;
+        b.qs_hi[k] = (float)qs;
+        b.qs_lo[k] = (float)(qs - (double)b.qs_hi[k]);
+        const double ratio = qs / (double)b.qs_hi[k];
+        b.r2c[k] = (float)(ratio * ratio);
+        b.S_hi[k] = (float)b.S[k];
+        b.S_lo[k] = (float)(b.S[k] - (double)b.S_hi[k]);
+        b.nc[k] = 1;
+    }
+    b.ncell = 1;
+    b.cubic = (p.box[0] == p.box[1] && p.box[1] == p.box[2]) ? 1 : 0;
+    fill_pairs(q, p);
+    fill_quanta(b, q, p.box[0]);
+}
+
+int check_params_why(const ljmd_params *p, const char **why) {
+    static thread_local std::string w;
+    w.clear();
+    const int r = validate(p, &w);
+    if (why) *why = w.c_str();
+    return r;
+}
+
+void set_global_error(const char *msg) { g_create_err = msg; }
+
+}  // namespace ljmd
+
 extern "C" {
 
 int32_t ljmd_abi_version(void) { return LJMD_ABI_VERSION; }

@@ -106,6 +106,8 @@ SIGNATURES = {
     "ljmd_batch_autotune_workspace_size": (C.c_size_t, [C.POINTER(Params), C.POINTER(SystemDesc), C.c_int32]),
     "ljmd_batch_autotune": (C.c_int, [C.POINTER(Params), C.POINTER(SystemDesc), C.c_int32, _dp, _dp, _ip, _vp,
                                       C.c_size_t, _vp, C.c_int32, C.c_char_p, C.POINTER(Tuning)]),
+    "ljmd_brute_workspace_size": (C.c_size_t, [C.POINTER(Params)]),
+    "ljmd_brute_forces": (C.c_int, [C.POINTER(Params), _dp, _ip, _dp, _dp, _vp, C.c_size_t, _vp]),
     "ljmd_autotune_workspace_size": (C.c_size_t, [C.POINTER(Params)]),
     "ljmd_autotune": (C.c_int, [C.POINTER(Params), _dp, _dp, _ip, _vp, C.c_size_t, _vp, C.c_int32, C.c_char_p,
                                 C.POINTER(Tuning)]),
@@ -476,6 +478,29 @@ def autotune_batch(sizes, edges, p, x, v, species, steps: int = 20, cache_path: 
         raise LJMDError(code, lib.ljmd_batch_last_error(None).decode())
     return {"lanes": out.lanes, "nbr_capacity": out.nbr_capacity, "cell_capacity": out.cell_capacity,
             "max_fill": out.max_fill, "ms_per_step": out.ms_per_step, "from_cache": bool(out.from_cache)}
+
+
+def brute_forces(n: int, box, p, x, species, precision: int = FP64):
+    """ljmd_brute_forces: forces (n, 3), U and W of one configuration by the
+    sum over all pairs (device tensors; the scratch is a torch tensor)."""
+    import torch
+    params = make_params(n, box, p, precision, 0)
+    size = int(lib.ljmd_brute_workspace_size(C.byref(params)))
+    if size == 0:
+        _check(check_params(params))
+        raise LJMDError(-1, "invalid parameters")
+    dev = lambda a, dt: (torch.from_numpy(np.ascontiguousarray(a)) if isinstance(a, np.ndarray) else a).to(
+        device="cuda", dtype=dt).contiguous()
+    xs, sp = dev(x, torch.float64).reshape(n, 3), dev(species, torch.int32).reshape(n)
+    ws = torch.empty(size, dtype=torch.uint8, device="cuda")
+    f = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    uw = torch.empty(2, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    code = lib.ljmd_brute_forces(C.byref(params), _ptr(xs), _ptr(sp), _ptr(f), _ptr(uw), C.c_void_p(_ptr(ws)), size,
+                                 C.c_void_p(stream.cuda_stream))
+    if code != 0:
+        raise LJMDError(code, last_error(None))
+    return f, uw
 
 
 class Batch:
