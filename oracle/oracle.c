@@ -111,7 +111,12 @@ static void min_image(const double *xi, const double *xj, const double *box, dou
  * cutoff applied). f: n*3 output. out[0] = U, out[1] = W. */
 void oracle_forces_brute(int64_t n, const double *x, const int32_t *sp, const double *box,
                          const olj_t *p, double *f, double *out) {
-    double U = 0.0, W = 0.0;
+    /* U and W sum up to n(n-1)/2 terms (2e6 for the untruncated 2,000-particle
+     * system), many of them equal on a lattice, so their FP64 roundings do not
+     * cancel: a double accumulator drifts by several 1e-12 of the sum. The
+     * two sums are carried in long double (64-bit significand) and rounded
+     * once at the end. */
+    long double U = 0.0L, W = 0.0L;
     memset(f, 0, sizeof(double) * 3 * (size_t)n);
     for (int64_t i = 0; i < n; ++i) {
         for (int64_t j = i + 1; j < n; ++j) {
@@ -125,12 +130,12 @@ void oracle_forces_brute(int64_t n, const double *x, const int32_t *sp, const do
                 f[3 * i + k] += fs * d[k];
                 f[3 * j + k] -= fs * d[k];
             }
-            U += oracle_pair_energy(r, ab, p);
-            W += fs * r * r;
+            U += (long double)oracle_pair_energy(r, ab, p);
+            W += (long double)(fs * r * r);
         }
     }
-    out[0] = U;
-    out[1] = W;
+    out[0] = (double)U;
+    out[1] = (double)W;
 }
 
 /* ---------------------------------------------------------------- O3 ---- */

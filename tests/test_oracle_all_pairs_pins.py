@@ -83,3 +83,22 @@ def test_list_forces_with_infinite_cutoff_equal_brute_force():
     rms = np.sqrt((fb ** 2).sum(1).mean())
     assert np.abs(fl - fb).max() <= 1e-12 * rms
     assert Ul == pytest.approx(Ub, rel=1e-12)
+
+
+def test_brute_sums_are_correctly_rounded_on_the_2000_particle_fluid():
+    # The all-to-all workload (2,000 particles, 2e6 pairs, many of them at
+    # equal lattice distances): the oracle's U and W equal the correctly
+    # rounded sums (math.fsum) of the pair terms to a few units of the last
+    # place. A plain double accumulator misses them by ~6e-12 relative.
+    w = W.all_pairs_fluid()
+    x, n, L = w.x, w.n, w.box
+    _, U, Wv = oracle.forces_brute(x, w.species, w.box, w.params)
+    i, j = np.triu_indices(n, 1)
+    d = x[i] - x[j]
+    d -= L * np.rint(d / L)
+    r2 = (d * d).sum(axis=1)
+    s6 = (1.0 / r2) ** 3
+    U_exact = math.fsum((4.0 * (s6 * s6 - s6)).tolist())
+    W_exact = math.fsum((24.0 * (2.0 * s6 * s6 - s6)).tolist())
+    assert abs(U - U_exact) <= 1e-14 * abs(U_exact)
+    assert abs(Wv - W_exact) <= 1e-14 * abs(W_exact)
