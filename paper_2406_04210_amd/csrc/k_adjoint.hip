@@ -18,13 +18,16 @@
 // contribute: the truncated force is differentiated where it is smooth.
 //
 // Geometry and pair arithmetic follow the step kernel of the same precision:
-// FP64 repeats its displacement, r^2 and cutoff test; FP32 uses its general
-// form (fixed-point difference times the single-float quantum, r^2 corrected
-// per axis for the quantum's rounding), which the one-species cubic-box force
-// loop evaluates in quanta instead -- the same r^2 up to rounding, so the two
-// can disagree only about pairs within rounding of r_c. The FP32 path
-// accumulates gx in FP32 like the forces; parameter sums are FP64 everywhere,
-// reduced per block and then over blocks in a fixed order.
+// FP64 repeats its displacement, r^2 and cutoff test. FP32 takes the cutoff
+// decision exactly as the force pass of the same box does -- in a cubic box
+// r^2 in squared quanta from the raw fixed-point differences against r_c^2
+// in quanta, otherwise the general form below -- so a pair within rounding
+// of r_c is inside for both or for neither, and the gradient is that of the
+// forces the step computed. The pair terms use the general form
+// (fixed-point difference times the single-float quantum, r^2 corrected per
+// axis for the quantum's rounding). The FP32 path accumulates gx in FP32
+// like the forces; parameter sums are FP64 everywhere, reduced per block and
+// then over blocks in a fixed order.
 #include "adjoint.h"
 #include "step_common.h"
 
@@ -230,6 +233,8 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_pairs(AdjArgs a) {
         const float4 gi = (MODE == kAdjVjp && valid) ? gv[i] : make_float4(0, 0, 0, 0);
         const float qsx = a.box.qs_hi[0], qsy = a.box.qs_hi[1], qsz = a.box.qs_hi[2];
         const float c2x = a.box.r2c[0], c2y = a.box.r2c[1], c2z = a.box.r2c[2];
+        // The force pass's cutoff test (see above).
+        const bool quanta = a.box.cubic && a.g.n < kQuantaMaxSlots;
         float fx = 0.f, fy = 0.f, fz = 0.f;
         for (int m = 0; m < iters; m += U) {
             const int4 grp = *reinterpret_cast<const int4 *>(nb + ((int64_t)(m >> 2) << 8));
@@ -245,12 +250,15 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_pairs(AdjArgs a) {
             for (int u = 0; u < U; ++u) {
                 if (m + u >= iters) continue;
                 const int4 rj = rr[u];
-                const float dx = (float)(int32_t)((uint32_t)ri.x - (uint32_t)rj.x) * qsx;
-                const float dy = (float)(int32_t)((uint32_t)ri.y - (uint32_t)rj.y) * qsy;
-                const float dz = (float)(int32_t)((uint32_t)ri.z - (uint32_t)rj.z) * qsz;
+                const float ax = (float)(int32_t)((uint32_t)ri.x - (uint32_t)rj.x);
+                const float ay = (float)(int32_t)((uint32_t)ri.y - (uint32_t)rj.y);
+                const float az = (float)(int32_t)((uint32_t)ri.z - (uint32_t)rj.z);
+                const float dx = ax * qsx, dy = ay * qsy, dz = az * qsz;
                 const float r2 = fmaf(dz * c2z, dz, fmaf(dy * c2y, dy, (dx * c2x) * dx));
                 const int t = NS == 1 ? 0 : ri.w + rj.w;
-                if (!(r2 < by_t<NS>(t, a.pc.rc2f))) continue;
+                const bool inside = quanta ? fmaf(az, az, fmaf(ay, ay, ax * ax)) < by_t<NS>(t, a.box.rc2q)
+                                           : r2 < by_t<NS>(t, a.pc.rc2f);
+                if (!inside) continue;
                 const float ir2 = __builtin_amdgcn_rcpf(r2);
                 const float s2 = by_t<NS>(t, a.pc.sig2f) * ir2;
                 const float s6 = s2 * s2 * s2;
