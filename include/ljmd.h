@@ -233,9 +233,12 @@ int ljmd_observables(ljmd_ctx *ctx, ljmd_obs *out);
  * to run while it is on (the dynamics would not be differentiable). */
 int ljmd_set_thermostat(ljmd_ctx *ctx, double temperature, double rate, uint64_t seed);
 
-/* Kernel timing with HIP events recorded on the context's stream around
- * every launch of each kernel family during ljmd_run: [0] the fused step
- * kernel (forces + velocity Verlet + reductions), [1] the rebuild sequence
+/* Kernel timing with HIP events on the context's stream for every launch
+ * of each kernel family during ljmd_run: [0] the fused step kernel (forces
+ * + velocity Verlet + reductions; its events are stamped by the dispatch
+ * itself through the extended launch, so they hold the kernel's own start
+ * and end; the other families are bracketed by recorded events, which
+ * add the marker packets' cost), [1] the rebuild sequence
  * (binning, canonical order, list build -- launched every step, working
  * only when a rebuild is due), [2] the space-filling-curve resort,
  * [3] everything else (integrate at run start, observable flushes),

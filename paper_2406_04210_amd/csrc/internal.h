@@ -9,6 +9,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 #include "../../include/ljmd.h"
@@ -111,13 +112,12 @@ struct State {
     double4 *frc64;       // forces of the last step (fx, fy, fz, 0)
     // FP32 + double-single path
     int4 *recq[2];        // gathered record (qx, qy, qz, species) -- ping-pong by step
-    float4 *pos_hi, *pos_lo;
-    float4 *vel_hi, *vel_lo;
+    float4 *dsw[3];       // double-single position and velocity, three unpadded words (DsState)
     float4 *frc32;
     // common
     int4 *img;            // periodic image counters (x, y, z, 0)
     int32_t *id;          // original id of the particle stored at this slot
-    int4 *xref;           // q at the last list build (x, y, z, 0)
+    int4 *xref;           // q at the last list build (x, y, z) and the species
     int32_t *nbr;         // neighbour list, interleaved by wave chunk (see nbr_index)
     int32_t *nbr_cnt;     // list length per particle
     int32_t *cell_count;  // particles binned per cell (cells indexed by Hilbert rank)
@@ -229,6 +229,33 @@ __device__ inline dsf ds_of(double v) {
     return {h, (float)(v - (double)h)};
 }
 
+// Double-single position and velocity of one particle. Stored without
+// padding as three float4 words per slot (State::dsw):
+//   w0 = (x.hi, y.hi, z.hi, x.lo), w1 = (y.lo, z.lo, vx.hi, vy.hi),
+//   w2 = (vz.hi, vx.lo, vy.lo, vz.lo).
+// The plain single-precision state keeps every lo part zero.
+struct DsState {
+    dsf x, y, z, vx, vy, vz;
+};
+__device__ inline DsState ds_unpack(const float4 &w0, const float4 &w1, const float4 &w2) {
+    DsState s;
+    s.x = dsf{w0.x, w0.w};
+    s.y = dsf{w0.y, w1.x};
+    s.z = dsf{w0.z, w1.y};
+    s.vx = dsf{w1.z, w2.y};
+    s.vy = dsf{w1.w, w2.z};
+    s.vz = dsf{w2.x, w2.w};
+    return s;
+}
+__device__ inline DsState ds_load(float4 *const dsw[3], int64_t i) {
+    return ds_unpack(dsw[0][i], dsw[1][i], dsw[2][i]);
+}
+__device__ inline void ds_store(float4 *const dsw[3], int64_t i, const DsState &s) {
+    dsw[0][i] = make_float4(s.x.hi, s.y.hi, s.z.hi, s.x.lo);
+    dsw[1][i] = make_float4(s.y.lo, s.z.lo, s.vx.hi, s.vy.hi);
+    dsw[2][i] = make_float4(s.vz.hi, s.vx.lo, s.vy.lo, s.vz.lo);
+}
+
 // Fixed-point image coordinate of a double-single position (binary32 only):
 // q = round((hi + lo) * S) mod 2^32 with S = 2^32/L given as (S_hi, S_lo).
 __device__ inline uint32_t q_from_ds(float hi, float lo, float S_hi, float S_lo) {
@@ -313,7 +340,20 @@ struct Launch {
     const DynC *dyn;
     hipStream_t stream;
     int cur;              // current ping-pong record buffer
+    // Optional event pair stamped by the dispatch itself (start and end of
+    // the kernel, no marker packets around it): set only for timed launches.
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
+
+// Launch on L.stream; with L.ev0 set, through the extended launch that
+// stamps L.ev0 / L.ev1 with the kernel's own start and end.
+template <typename K, typename... Args>
+inline void launch_k(const Launch &L, K kernel, dim3 grid, dim3 block, Args... args) {
+    if (L.ev0)
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, L.stream, L.ev0, L.ev1, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, L.stream, args...);
+}
 
 hipError_t launch_set_state(const Launch &L, const double *x, const double *v, const int32_t *sp);
 hipError_t launch_bin(const Launch &L, int64_t step, int forced);

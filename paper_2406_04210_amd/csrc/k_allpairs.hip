@@ -195,7 +195,8 @@ __global__ __launch_bounds__(kBlock) void k_ap_finish(StepArgs a, const void *pa
             finish_fp64<TH>(a, a.box, i, a.st.rec64[a.cur][i], f.x, f.y, f.z, ew.x, ew.y, pu, pw, pk, ppx, ppy, ppz,
                             dm);
         else
-            finish_ds<true, TH, PREC == LJMD_FP32>(a, a.box, i, a.st.recq[a.cur][i].w, f.x, f.y, f.z, ew.x, ew.y,
+            finish_ds<true, TH, PREC == LJMD_FP32>(a, a.box, i, a.st.recq[a.cur][i].w, a.st.xref[i], f.x, f.y, f.z,
+                                                   ew.x, ew.y,
                                                    pu, pw, pk, ppx, ppy, ppz, dm);
     }
     block_finish<true, BS>(a, ctl, blockIdx.x, pu, pw, pk, ppx, ppy, ppz, dm);

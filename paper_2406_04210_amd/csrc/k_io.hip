@@ -53,14 +53,20 @@ __device__ inline void set_one(const State &st, const Geom &g, const BoxC &box, 
             q[k] = q_from_ds(hi[k], lo[k], box.S_hi[k], box.S_lo[k]);
         }
         if (plain) st.img[i] = make_int4(im[0], im[1], im[2], 0);
-        st.pos_hi[i] = make_float4(hi[0], hi[1], hi[2], 0.f);
-        st.pos_lo[i] = make_float4(lo[0], lo[1], lo[2], 0.f);
         st.recq[cur][i] = make_int4((int)q[0], (int)q[1], (int)q[2], s);
         const float vhx = (float)vx, vhy = (float)vy, vhz = (float)vz;
-        st.vel_hi[i] = make_float4(vhx, vhy, vhz, 0.f);
-        st.vel_lo[i] = plain ? make_float4(0.f, 0.f, 0.f, 0.f)
-                             : make_float4((float)(vx - (double)vhx), (float)(vy - (double)vhy),
-                                           (float)(vz - (double)vhz), 0.f);
+        DsState d;
+        d.x = dsf{hi[0], lo[0]};
+        d.y = dsf{hi[1], lo[1]};
+        d.z = dsf{hi[2], lo[2]};
+        d.vx = dsf{vhx, plain ? 0.0f : (float)(vx - (double)vhx)};
+        d.vy = dsf{vhy, plain ? 0.0f : (float)(vy - (double)vhy)};
+        d.vz = dsf{vhz, plain ? 0.0f : (float)(vz - (double)vhz)};
+        ds_store(st.dsw, i, d);
+        // The species also rides in the list reference's last word (the
+        // step kernel reads it there); its coordinates are set by the list
+        // build that follows every state load.
+        st.xref[i] = make_int4(0, 0, 0, s);
     }
 }
 
@@ -88,14 +94,13 @@ __global__ __launch_bounds__(kBlock) void k_get_state(State st, Geom g, int cur,
         px = r.x; py = r.y; pz = r.z;
         vx = u.x; vy = u.y; vz = u.z;
     } else {
-        const float4 h = st.pos_hi[i], l = st.pos_lo[i];
-        const float4 vh = st.vel_hi[i], vl = st.vel_lo[i];
-        px = (double)h.x + (double)l.x;
-        py = (double)h.y + (double)l.y;
-        pz = (double)h.z + (double)l.z;
-        vx = (double)vh.x + (double)vl.x;
-        vy = (double)vh.y + (double)vl.y;
-        vz = (double)vh.z + (double)vl.z;
+        const DsState d = ds_load(st.dsw, i);
+        px = (double)d.x.hi + (double)d.x.lo;
+        py = (double)d.y.hi + (double)d.y.lo;
+        pz = (double)d.z.hi + (double)d.z.lo;
+        vx = (double)d.vx.hi + (double)d.vx.lo;
+        vy = (double)d.vy.hi + (double)d.vy.lo;
+        vz = (double)d.vz.hi + (double)d.vz.lo;
     }
     if (x) {
         x[3 * id] = px;
@@ -223,7 +228,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_set_state(State st, Geom g, co
         st.id[i] = -1;
         st.img[i] = make_int4(0, 0, 0, 0);
         st.recq[cur][i] = make_int4(0, 0, 0, 0);
-        st.pos_hi[i] = st.pos_lo[i] = st.vel_hi[i] = st.vel_lo[i] = st.frc32[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        st.dsw[0][i] = st.dsw[1][i] = st.dsw[2][i] = st.frc32[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        st.xref[i] = make_int4(0, 0, 0, 0);
         st.nbr_cnt[i] = 0;
         return;
     }
@@ -240,17 +246,16 @@ __global__ __launch_bounds__(kBlock) void k_batch_get(State st, Geom g, const Sy
     const int64_t row = st.id[i];
     if (row < y.in_off || row >= y.in_off + y.n) return;
     if (x || v) {
-        const float4 h = st.pos_hi[i], l = st.pos_lo[i];
-        const float4 vh = st.vel_hi[i], vl = st.vel_lo[i];
+        const DsState d = ds_load(st.dsw, i);
         if (x) {
-            x[3 * row] = (double)h.x + (double)l.x;
-            x[3 * row + 1] = (double)h.y + (double)l.y;
-            x[3 * row + 2] = (double)h.z + (double)l.z;
+            x[3 * row] = (double)d.x.hi + (double)d.x.lo;
+            x[3 * row + 1] = (double)d.y.hi + (double)d.y.lo;
+            x[3 * row + 2] = (double)d.z.hi + (double)d.z.lo;
         }
         if (v) {
-            v[3 * row] = (double)vh.x + (double)vl.x;
-            v[3 * row + 1] = (double)vh.y + (double)vl.y;
-            v[3 * row + 2] = (double)vh.z + (double)vl.z;
+            v[3 * row] = (double)d.vx.hi + (double)d.vx.lo;
+            v[3 * row + 1] = (double)d.vy.hi + (double)d.vy.lo;
+            v[3 * row + 2] = (double)d.vz.hi + (double)d.vz.lo;
         }
     }
     if (img) {

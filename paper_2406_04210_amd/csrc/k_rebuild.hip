@@ -215,7 +215,7 @@ __global__ __launch_bounds__(1024) void k_scan(State st, Geom g, int ncell) {
 struct ResortView {
     double4 *rec64, *vel64;
     int4 *recq;
-    float4 *pos_hi, *pos_lo, *vel_hi, *vel_lo;
+    float4 *dsw[3];
     int4 *img;
     int32_t *id;
 };
@@ -233,10 +233,7 @@ __host__ __device__ inline ResortView resort_view(uint8_t *base, int64_t npad, i
         v.vel64 = (double4 *)take(sizeof(double4) * npad);
     } else {
         v.recq = (int4 *)take(sizeof(int4) * npad);
-        v.pos_hi = (float4 *)take(sizeof(float4) * npad);
-        v.pos_lo = (float4 *)take(sizeof(float4) * npad);
-        v.vel_hi = (float4 *)take(sizeof(float4) * npad);
-        v.vel_lo = (float4 *)take(sizeof(float4) * npad);
+        for (int k = 0; k < 3; ++k) v.dsw[k] = (float4 *)take(sizeof(float4) * npad);
     }
     v.img = (int4 *)take(sizeof(int4) * npad);
     v.id = (int32_t *)take(sizeof(int32_t) * npad);
@@ -245,7 +242,7 @@ __host__ __device__ inline ResortView resort_view(uint8_t *base, int64_t npad, i
 
 size_t resort_scratch_bytes(int64_t npad, int prec) {
     auto r = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    size_t s = prec == LJMD_FP64 ? 2 * r(sizeof(double4) * npad) : 5 * r(sizeof(float4) * npad);
+    size_t s = prec == LJMD_FP64 ? 2 * r(sizeof(double4) * npad) : 4 * r(sizeof(float4) * npad);
     return s + r(sizeof(int4) * npad) + r(sizeof(int32_t) * npad);
 }
 
@@ -279,10 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_resort_gather(State st, Geom g, BoxC
         sv.vel64[s] = st.vel64[i];
     } else {
         sv.recq[s] = st.recq[cur][i];
-        sv.pos_hi[s] = st.pos_hi[i];
-        sv.pos_lo[s] = st.pos_lo[i];
-        sv.vel_hi[s] = st.vel_hi[i];
-        sv.vel_lo[s] = st.vel_lo[i];
+        for (int w = 0; w < 3; ++w) sv.dsw[w][s] = st.dsw[w][i];
     }
     sv.img[s] = st.img[i];
     sv.id[s] = st.id[i];
@@ -298,10 +292,7 @@ __global__ __launch_bounds__(kBlock) void k_resort_copy(State st, Geom g, int cu
         st.vel64[s] = sv.vel64[s];
     } else {
         st.recq[cur][s] = sv.recq[s];
-        st.pos_hi[s] = sv.pos_hi[s];
-        st.pos_lo[s] = sv.pos_lo[s];
-        st.vel_hi[s] = sv.vel_hi[s];
-        st.vel_lo[s] = sv.vel_lo[s];
+        for (int w = 0; w < 3; ++w) st.dsw[w][s] = sv.dsw[w][s];
     }
     st.img[s] = sv.img[s];
     st.id[s] = sv.id[s];
@@ -618,7 +609,7 @@ __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &bo
                 uint32_t q[3];
                 rec_q(hrec, box, q);
                 st.nbr_cnt[i] = kreg;
-                st.xref[i] = make_int4((int)q[0], (int)q[1], (int)q[2], 0);
+                st.xref[i] = make_int4((int)q[0], (int)q[1], (int)q[2], CR::species(hrec));
                 if (kreg > g.cap) atomicOr(&ctl->flags, kErrList);
             }
         }

@@ -169,8 +169,8 @@ __global__ __launch_bounds__(kBlock) void k_sd_move(SdArgs sa) {
         } else {
             const float4 f = st.frc32[i];
             const float sc = (float)scale;
-            const float4 ph = st.pos_hi[i], pl = st.pos_lo[i];
-            dsf x{ph.x, pl.x}, y{ph.y, pl.y}, z{ph.z, pl.z};
+            DsState ds = ds_load(st.dsw, i);
+            dsf x = ds.x, y = ds.y, z = ds.z;
             if constexpr (PLAIN) {
                 dsf *c3[3] = {&x, &y, &z};
                 const float fc[3] = {f.x, f.y, f.z};
@@ -199,8 +199,10 @@ __global__ __launch_bounds__(kBlock) void k_sd_move(SdArgs sa) {
             q[2] = q_from_ds(z.hi, z.lo, a.box.S_hi[2], a.box.S_lo[2]);
             const int sp = st.recq[a.cur][i].w;
             st.recq[a.cur][i] = make_int4((int)q[0], (int)q[1], (int)q[2], sp);
-            st.pos_hi[i] = make_float4(x.hi, y.hi, z.hi, 0.f);
-            st.pos_lo[i] = make_float4(x.lo, y.lo, z.lo, 0.f);
+            ds.x = x;
+            ds.y = y;
+            ds.z = z;
+            ds_store(st.dsw, i, ds);
         }
         if (d[0] | d[1] | d[2]) {
             const int4 im = st.img[i];

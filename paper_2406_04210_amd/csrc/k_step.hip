@@ -73,7 +73,18 @@ __device__ inline void step_ds_body(const StepArgs &a, const BoxC &box, Ctl *ctl
     step_housekeeping(a, ctl, c_lo, c_hi, bj, nbj, rebuilt);
 
     const int4 *__restrict__ rec = st.recq[a.cur];
-    int4 ri = valid ? rec[i] : make_int4(0, 0, 0, 0);
+    // Own position: the fixed-point image of the double-single state (the
+    // record the previous step wrote for this slot holds the same
+    // coordinates, so it is not read again); the species from the list
+    // reference's last word.
+    const int4 xr = valid ? st.xref[i] : make_int4(0, 0, 0, 0);
+    int4 ri = make_int4(0, 0, 0, xr.w);
+    if (valid) {
+        const float4 w0 = st.dsw[0][i], w1 = st.dsw[1][i];
+        ri.x = (int)q_from_ds(w0.x, w0.w, box.S_hi[0], box.S_lo[0]);
+        ri.y = (int)q_from_ds(w0.y, w1.x, box.S_hi[1], box.S_lo[1]);
+        ri.z = (int)q_from_ds(w0.z, w1.y, box.S_hi[2], box.S_lo[2]);
+    }
     int cnt = valid ? st.nbr_cnt[i] : 0;
     cnt = cnt < a.g.cap ? cnt : a.g.cap;
     const int32_t *__restrict__ nb = st.nbr + chunk * (int64_t)(P * a.g.cap) + 4 * lane;
@@ -235,7 +246,7 @@ __device__ inline void step_ds_body(const StepArgs &a, const BoxC &box, Ctl *ctl
     double pu = 0.0, pw = 0.0, pk = 0.0, ppx = 0.0, ppy = 0.0, ppz = 0.0;
     uint32_t dm = 0u;
     if (valid && l == 0)
-        finish_ds<OBS, TH, PLAIN>(a, box, i, ri.w, fx, fy, fz, e, w, pu, pw, pk, ppx, ppy, ppz, dm);
+        finish_ds<OBS, TH, PLAIN>(a, box, i, ri.w, xr, fx, fy, fz, e, w, pu, pw, pk, ppx, ppy, ppz, dm);
     block_finish<OBS>(a, ctl, blk, pu, pw, pk, ppx, ppy, ppz, dm);
 }
 
@@ -353,7 +364,8 @@ __device__ inline void integrate_body(const StepArgs &a, const BoxC &box, Ctl *c
             finish_fp64<false>(a, box, i, st.rec64[a.cur][i], f.x, f.y, f.z, 0.0, 0.0, pu, pw, pk, ppx, ppy, ppz, dm);
         } else {
             const float4 f = st.frc32[i];
-            finish_ds<false, false, PREC == LJMD_FP32>(a, box, i, st.recq[a.cur][i].w, f.x, f.y, f.z, 0.0, 0.0, pu,
+            finish_ds<false, false, PREC == LJMD_FP32>(a, box, i, st.recq[a.cur][i].w, st.xref[i], f.x, f.y, f.z, 0.0,
+                                                       0.0, pu,
                                                        pw, pk, ppx, ppy, ppz, dm);
         }
     }
@@ -411,11 +423,11 @@ hipError_t launch_step(const Launch &L, int64_t step, int forced, int mode, int 
 #define STEP_DS(NS, LN, TH, PL)                                                                         \
     do {                                                                                                \
         if (quanta && obs)                                                                              \
-            hipLaunchKernelGGL((k_step_ds<NS, LN, true, true, TH, PL>), grid, block, 0, L.stream, a);   \
+            launch_k(L, k_step_ds<NS, LN, true, true, TH, PL>, grid, block, a);                          \
         else if (quanta)                                                                                \
-            hipLaunchKernelGGL((k_step_ds<NS, LN, true, false, TH, PL>), grid, block, 0, L.stream, a);  \
+            launch_k(L, k_step_ds<NS, LN, true, false, TH, PL>, grid, block, a);                         \
         else                                                                                            \
-            hipLaunchKernelGGL((k_step_ds<NS, LN, false, true, TH, PL>), grid, block, 0, L.stream, a);  \
+            launch_k(L, k_step_ds<NS, LN, false, true, TH, PL>, grid, block, a);                         \
     } while (0)
 #define STEP_TH(NS, LN, TH)                                                              \
     do {                                                                                 \
@@ -424,7 +436,7 @@ hipError_t launch_step(const Launch &L, int64_t step, int forced, int mode, int 
         else if (ds)                                                                     \
             STEP_DS(NS, LN, TH, false);                                                  \
         else                                                                             \
-            hipLaunchKernelGGL((k_step_fp64<NS, LN, TH>), grid, block, 0, L.stream, a);  \
+            launch_k(L, k_step_fp64<NS, LN, TH>, grid, block, a);                     \
     } while (0)
 #define STEP(NS, LN)              \
     do {                          \

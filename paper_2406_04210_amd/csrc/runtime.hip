@@ -191,7 +191,7 @@ struct Plan {
     int ncell;
     int max_blocks;
     // byte offsets
-    size_t off_rec[2], off_vel, off_frc, off_pos_hi, off_pos_lo, off_vel_lo, off_img, off_id,
+    size_t off_rec[2], off_vel, off_frc, off_dsw[3], off_img, off_id,
         off_xref, off_nbr, off_cnt, off_ccount, off_cmem, off_cstart, off_rank, off_lin, off_scratch,
         off_part, off_rebuilt, off_ctl;
     size_t total;
@@ -278,10 +278,7 @@ void lay_out(Plan &pl, int prec, int nctl) {
     } else {
         pl.off_rec[0] = take(sizeof(int4) * N);
         pl.off_rec[1] = take(sizeof(int4) * N);
-        pl.off_pos_hi = take(sizeof(float4) * N);
-        pl.off_pos_lo = take(sizeof(float4) * N);
-        pl.off_vel = take(sizeof(float4) * N);
-        pl.off_vel_lo = take(sizeof(float4) * N);
+        for (int k = 0; k < 3; ++k) pl.off_dsw[k] = take(sizeof(float4) * N);
         pl.off_frc = take(sizeof(float4) * N);
     }
     pl.off_img = take(sizeof(int4) * N);
@@ -409,13 +406,16 @@ void fill_quanta(BoxC &b, const PairC &q, double L) {
     }
 }
 
-// Timing bracket around a group of launches of one kernel family.
+// Timing bracket around a group of launches of one kernel family. A
+// stamped bracket records nothing itself: its two events go to a single
+// launch (Launch::ev0 / ev1) that the dispatch stamps with the kernel's own
+// start and end, so the measured time holds no marker packets.
 struct Bracket {
     ljmd_ctx *c;
     int fam;
     size_t start = 0;
-    bool on = false;
-    Bracket(ljmd_ctx *cc, int f) : c(cc), fam(f) {
+    bool on = false, stamp = false;
+    Bracket(ljmd_ctx *cc, int f, bool stamped = false) : c(cc), fam(f), stamp(stamped) {
         if (!c->profiling) return;
         if (c->ev_used + 2 > c->ev_pool.size()) {
             for (int k = 0; k < 64; ++k) {
@@ -426,11 +426,13 @@ struct Bracket {
         }
         start = c->ev_used;
         c->ev_used += 2;
-        on = hipEventRecord(c->ev_pool[start], c->stream) == hipSuccess;
+        on = stamp || hipEventRecord(c->ev_pool[start], c->stream) == hipSuccess;
     }
+    // Events for a stamped launch (null when not profiling).
+    hipEvent_t ev(int k) const { return on && stamp ? c->ev_pool[start + k] : nullptr; }
     ~Bracket() {
         if (!on) return;
-        if (hipEventRecord(c->ev_pool[start + 1], c->stream) == hipSuccess)
+        if (stamp || hipEventRecord(c->ev_pool[start + 1], c->stream) == hipSuccess)
             c->ev_marks.push_back({fam, start});
     }
 };
@@ -555,9 +557,12 @@ int step_range(ljmd_ctx *c, int64_t s0, int64_t n, double *obs_dev, const RunOpt
         if (redirect && !last) set_rec_ptr(c, c->cur ^ 1, o.frames + (size_t)(k0 + k + 2) * o.frame_stride);
         L = launcher(c);
         {
-            Bracket b(c, 0);
-            if ((e = launch_step(L, s, forced, mode, (int)(s % kRing))) != hipSuccess)
-                return hip_fail(c, e, "step");
+            Bracket b(c, 0, !c->g.all_pairs);
+            L.ev0 = b.ev(0);
+            L.ev1 = b.ev(1);
+            e = launch_step(L, s, forced, mode, (int)(s % kRing));
+            L.ev0 = L.ev1 = nullptr;
+            if (e != hipSuccess) return hip_fail(c, e, "step");
         }
         if (!last) c->cur ^= 1;
         ++pending;
@@ -692,7 +697,7 @@ int ckpt_elems(int prec, size_t elem[8]) {
         elem[k++] = sizeof(double4);  // velocities
         elem[k++] = sizeof(double4);  // forces
     } else {
-        for (int q = 0; q < 5; ++q) elem[k++] = sizeof(float4);  // pos hi/lo, vel hi/lo, forces
+        for (int q = 0; q < 4; ++q) elem[k++] = sizeof(float4);  // double-single state words, forces
     }
     elem[k++] = sizeof(int4);  // image counters
     return k;
@@ -737,10 +742,9 @@ int ckpt_copy(ljmd_ctx *c, uint8_t *dst, bool save) {
         arr[k++] = c->st.vel64;
         arr[k++] = c->st.frc64;
     } else {
-        arr[k++] = c->st.pos_hi;
-        arr[k++] = c->st.pos_lo;
-        arr[k++] = c->st.vel_hi;
-        arr[k++] = c->st.vel_lo;
+        arr[k++] = c->st.dsw[0];
+        arr[k++] = c->st.dsw[1];
+        arr[k++] = c->st.dsw[2];
         arr[k++] = c->st.frc32;
     }
     arr[k++] = c->st.img;
@@ -779,10 +783,7 @@ void bind_state(State &s, const Plan &pl, uint8_t *b, int prec) {
     } else {
         s.recq[0] = (int4 *)(b + pl.off_rec[0]);
         s.recq[1] = (int4 *)(b + pl.off_rec[1]);
-        s.pos_hi = (float4 *)(b + pl.off_pos_hi);
-        s.pos_lo = (float4 *)(b + pl.off_pos_lo);
-        s.vel_hi = (float4 *)(b + pl.off_vel);
-        s.vel_lo = (float4 *)(b + pl.off_vel_lo);
+        for (int k = 0; k < 3; ++k) s.dsw[k] = (float4 *)(b + pl.off_dsw[k]);
         s.frc32 = (float4 *)(b + pl.off_frc);
     }
     s.img = (int4 *)(b + pl.off_img);

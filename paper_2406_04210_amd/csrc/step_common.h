@@ -157,17 +157,17 @@ __device__ inline void block_finish(const StepArgs &a, Ctl *ctl, int blk, double
 // w/2) and "integrate" of step s+1 (v' = v_s + dt/(2m) F, x_{s+1} =
 // x_s + dt v', wrapped into the box with image bookkeeping, the new
 // fixed-point record, the squared displacement from the list reference in
-// dm). Double-single arithmetic, or with PLAIN single floats (the lo parts
-// stay zero).
+// dm against the list reference xr). Double-single arithmetic, or with PLAIN
+// single floats (the lo parts stay zero).
 template <bool OBS, bool TH, bool PLAIN = false>
-__device__ inline void finish_ds(const StepArgs &a, const BoxC &box, int64_t i, int si, float fx, float fy,
-                                 float fz, double e, double w, double &pu, double &pw, double &pk, double &ppx,
-                                 double &ppy, double &ppz, uint32_t &dm) {
+__device__ inline void finish_ds(const StepArgs &a, const BoxC &box, int64_t i, int si, const int4 &xr, float fx,
+                                 float fy, float fz, double e, double w, double &pu, double &pw, double &pk,
+                                 double &ppx, double &ppy, double &ppz, uint32_t &dm) {
     const State &st = a.st;
     const float chi = by_s(si, a.dyn.hdt_m_hi), clo = by_s(si, a.dyn.hdt_m_lo);
     const float mass = by_s(si, a.dyn.massf);
-    const float4 vh = st.vel_hi[i], vl = st.vel_lo[i];
-    dsf vx{vh.x, vl.x}, vy{vh.y, vl.y}, vz{vh.z, vl.z};
+    DsState ds = ds_load(st.dsw, i);
+    dsf vx = ds.vx, vy = ds.vy, vz = ds.vz;
     // v += dt/(2m) F: double-single, or one float product and one float sum.
     auto kick = [&](dsf &v, float f) {
         if constexpr (PLAIN)
@@ -208,8 +208,7 @@ __device__ inline void finish_ds(const StepArgs &a, const BoxC &box, int64_t i, 
         kick(vx, fx);
         kick(vy, fy);
         kick(vz, fz);
-        const float4 ph = st.pos_hi[i], pl = st.pos_lo[i];
-        dsf x{ph.x, pl.x}, y{ph.y, pl.y}, z{ph.z, pl.z};
+        dsf x = ds.x, y = ds.y, z = ds.z;
         int ix = 0, iy = 0, iz = 0;
         if constexpr (PLAIN) {
             // x += dt v in floats; wrap by one box edge (as a float).
@@ -245,9 +244,9 @@ __device__ inline void finish_ds(const StepArgs &a, const BoxC &box, int64_t i, 
         const uint32_t qy = q_from_ds(y.hi, y.lo, box.S_hi[1], box.S_lo[1]);
         const uint32_t qz = q_from_ds(z.hi, z.lo, box.S_hi[2], box.S_lo[2]);
         st.recq[a.cur ^ 1][i] = make_int4((int)qx, (int)qy, (int)qz, si);
-        st.pos_hi[i] = make_float4(x.hi, y.hi, z.hi, 0.f);
-        st.pos_lo[i] = make_float4(x.lo, y.lo, z.lo, 0.f);
-        const int4 xr = st.xref[i];
+        ds.x = x;
+        ds.y = y;
+        ds.z = z;
         const float ddx = disp_q(qx, (uint32_t)xr.x, box.qs_hi[0], box.qs_lo[0]);
         const float ddy = disp_q(qy, (uint32_t)xr.y, box.qs_hi[1], box.qs_lo[1]);
         const float ddz = disp_q(qz, (uint32_t)xr.z, box.qs_hi[2], box.qs_lo[2]);
@@ -256,8 +255,10 @@ __device__ inline void finish_ds(const StepArgs &a, const BoxC &box, int64_t i, 
         const bool fin = __builtin_isfinite(x.hi) && __builtin_isfinite(y.hi) && __builtin_isfinite(z.hi);
         dm = (fin && d2 == d2) ? __float_as_uint(d2) : 0x7fc00000u;
     }
-    st.vel_hi[i] = make_float4(vx.hi, vy.hi, vz.hi, 0.f);
-    st.vel_lo[i] = make_float4(vx.lo, vy.lo, vz.lo, 0.f);
+    ds.vx = vx;
+    ds.vy = vy;
+    ds.vz = vz;
+    ds_store(st.dsw, i, ds);
     if (a.mode & kStoreForce) st.frc32[i] = make_float4(fx, fy, fz, 0.f);
 }
 
