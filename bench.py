@@ -61,17 +61,49 @@ def measured_traffic():
     return STEP_KERNEL_TRAFFIC["fetch_bytes"] + STEP_KERNEL_TRAFFIC["write_bytes"]
 
 
-def algorithmic_bytes_per_particle(prec: int, mean_list: float) -> float:
-    """HBM bytes one particle-step of the fused step kernel must move:
-    its list (4 B per entry) and length (4 B), its own record once, its
-    velocity and position state read and written, its reference position,
-    and its new record. Neighbour records are re-reads of records already
-    counted (served by L2/MALL) and are not algorithmic traffic."""
-    if prec == 1:   # FP32 + double-single
-        own_rec, state_rw, rec_out, xref = 16, 2 * (32 + 32), 16, 16
-    else:           # FP64
+def algorithmic_bytes_per_particle(mean_list: float) -> float:
+    """HBM bytes one particle-step of the fused step kernel must move, as
+    the method needs them: its list (4 B per entry) and length (4 B), its
+    double-single position and velocity read and written (3 x 8 B each way
+    for each), and its reference position (12 B) -- 4 n_L + 112 B. Neighbour
+    records are re-reads of positions already counted (served by L2/MALL)
+    and are not algorithmic traffic. The FP64 path needs the same bytes."""
+    return 4.0 * mean_list + 4.0 + 2 * 24 + 2 * 24 + 12
+
+
+def layout_bytes_per_particle(prec: int, mean_list: float) -> float:
+    """Bytes the step kernel's data layout moves per particle-step: the list
+    and its length, the state arrays as stored read and written (FP32+DS:
+    double-single position and velocity in three float4 words; FP64: the
+    own record and the padded velocity), the new record, and the reference
+    position with the species in its last word."""
+    if prec == 1:   # FP32 + double-single: three unpadded state words, no own-record read
+        own_rec, state_rw, rec_out, xref = 0, 2 * 48, 16, 16
+    else:           # FP64: the own record is the position
         own_rec, state_rw, rec_out, xref = 32, 2 * 32, 32, 16
     return 4.0 * mean_list + 4.0 + own_rec + state_rw + rec_out + xref
+
+
+# The paper publishes no absolute throughput for this path; its relative
+# figures, with the hardware they were measured on, as context.
+PAPER_CONTEXT = {
+    "absolute_throughput": "none published (the truncated-force performance figure is missing from the text)",
+    "truncated_lj": {
+        "workload": "N=100,000 LJ, 50,000 steps, several temperatures, GPU single precision",
+        "hardware": "Nvidia A100 SXM4 80GB (CUDA 11.0.2 vs Intel LLVM SYCL 2022.12 on CUDA 11.7); A40 similar",
+        "sycl_vs_cuda_runtime": "SYCL up to 1.8x slower",
+        "force_kernel_slowdown": 1.8,
+        "list_update_slowdown": 1.5,
+        "runtime_share_force_list": [0.6, 0.3],
+        "share_note": "list-update share grows with temperature",
+    },
+    "all_to_all": {
+        "workload": "N=2,000, 20,000 steps (GPU, single precision); 5,000 steps FP64 on CPU",
+        "sycl_vs_cuda": "SYCL about 1.3x faster (A40, A100)",
+        "cpu": "Xeon W-2133: SYCL 1 thread 5.1x over sequential C++, 6 threads 21.9x (efficiency 0.84)",
+        "mi210": "SYCL runs on MI210 (gfx90a, ROCm 5.0); no HIP baseline",
+    },
+}
 
 
 def time_gpu(ljmd, torch, w, prec, steps, warmup, lanes, profile):
@@ -103,20 +135,35 @@ def time_gpu(ljmd, torch, w, prec, steps, warmup, lanes, profile):
     return {"ms": ms, "obs": o, "kt": kt, "mean_list": mean_list, "info": info}
 
 
-def cpu_baseline(w, seconds_target: float = 15.0):
+def cpu_baseline(w, seconds_target: float = 15.0, one_core_seconds: float = 6.0):
+    """The FP64 C oracle on the host cores: the step loop only (the initial
+    list build and forces excluded), on all threads and on one."""
     import oracle
+    threads = oracle.num_threads()
     # Calibrate on a few steps, then time a bounded sample of the same workload.
     r = oracle.run_nve(w.x, w.v, w.species, w.box, w.params, 3, want_obs=False)
-    per_step = r["seconds"] / 4.0
+    per_step = r["loop_seconds"] / 3.0
     steps = int(max(5, min(400, seconds_target / max(per_step, 1e-6))))
     r = oracle.run_nve(w.x, w.v, w.species, w.box, w.params, steps, want_obs=False)
+    value = w.n * steps / r["loop_seconds"]
+    one = None
+    if one_core_seconds > 0:
+        steps1 = int(max(2, min(100, one_core_seconds / max(per_step * threads, 1e-6))))
+        oracle.set_threads(1)
+        try:
+            r1 = oracle.run_nve(w.x, w.v, w.species, w.box, w.params, steps1, want_obs=False)
+        finally:
+            oracle.set_threads(threads)
+        one = {"value": w.n * steps1 / r1["loop_seconds"], "cores": 1, "steps": steps1,
+               "loop_seconds": r1["loop_seconds"]}
     return {
-        "value": w.n * steps / r["seconds"],
+        "value": value,
         "unit": "particle-steps/s",
-        "cores": oracle.num_threads(),
+        "cores": threads,
         "kind": "oracle",
-        "sample": f"FP64 C oracle (OpenMP), N={w.n} same workload, {steps} steps incl. initial "
-                  f"list build and forces, {r['seconds']:.1f} s",
+        "sample": f"FP64 C oracle (OpenMP, {threads} threads), N={w.n} same workload, {steps} steps; "
+                  f"step loop timed ({r['loop_seconds']:.1f} s), initial list build and forces excluded",
+        "one_core": one,
     }
 
 
@@ -234,7 +281,7 @@ def time_mixture(ljmd, torch, W, copy_gbs, steps: int = 500, warmup: int = 20):
     mean_list = float(cnt.double().mean().item())
     step_ms, step_n = kt["step"]
     avg_s = step_ms * 1e-3 / max(step_n, 1)
-    bpp = algorithmic_bytes_per_particle(ljmd.FP32_DS, mean_list)
+    bpp = algorithmic_bytes_per_particle(mean_list)
     achieved = bpp * w.n / avg_s / 1e9
     return {
         "workload": "binary 80:20 LJ mixture N=4000000, rho=1.2, eps_AB=1.5 sigma_AB=0.8 eps_BB=0.5 "
@@ -244,6 +291,7 @@ def time_mixture(ljmd, torch, W, copy_gbs, steps: int = 500, warmup: int = 20):
         "ms_per_step": ms / steps, "rebuilds_in_timed_steps": int(o[:, 6].sum()),
         "energy_per_particle_first_last": [float(E[0]), float(E[-1])],
         "step_kernel_us": avg_s * 1e6, "mean_list_len": mean_list, "bytes_per_particle": bpp,
+        "layout_bytes_per_particle": layout_bytes_per_particle(ljmd.FP32_DS, mean_list),
         "achieved_gbs": achieved, "frac_of_peak": achieved / HBM_PEAK_GBS,
         "frac_of_achievable": achieved / copy_gbs,
     }
@@ -297,6 +345,86 @@ def time_batch(ljmd, torch, W, steps: int = 1000, warmup: int = 50):
     }
 
 
+def time_allpairs(ljmd, torch, W, steps: int = 20000, warmup: int = 500):
+    """The untruncated all-to-all interaction (every pair of the minimum
+    image, no lists): N = 2,000 from a lattice with random vacancies at
+    density 0.8442, T = 1.0, 20,000 NVE steps, in FP32 pair math with
+    double-single state and in plain FP64 (the paper's all-to-all study
+    size)."""
+    w = W.all_pairs_fluid()
+    out = {"workload": f"all-to-all LJ (no cutoff) N={w.n}, rho=0.8442, T=1.0, dt=0.005, {steps} NVE steps",
+           "n": w.n, "steps": steps}
+    stream = torch.cuda.current_stream()
+    for name, prec in (("fp32_ds", ljmd.FP32_DS), ("fp64", ljmd.FP64)):
+        s = ljmd.System(w.n, w.box, w.params, precision=prec, sort_interval=0)
+        s.set_state(w.x, w.v, w.species)
+        s.run(warmup, observe=False)
+        s.sync()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(stream)
+        code = ljmd.lib.ljmd_run(s.ctx, steps, None)
+        b.record(stream)
+        torch.cuda.synchronize()
+        if code != 0:
+            raise ljmd.LJMDError(code, ljmd.last_error(s.ctx))
+        s.sync()
+        ms = a.elapsed_time(b)
+        out[name] = {"value": w.n * steps / (ms * 1e-3), "unit": "particle-steps/s",
+                     "ms_per_step": ms / steps,
+                     "pair_interactions_per_s": w.n * (w.n - 1) * steps / (ms * 1e-3)}
+        s.close()
+    return out
+
+
+def time_thermostat_sweep(ljmd, torch, W, temps=(0.7, 1.0, 1.5, 2.0, 3.0), steps: int = 2000,
+                          warmup: int = 500, rate: float = 1.0):
+    """The paper's truncated-force study shape: N = 100,000 at several
+    temperatures under the Andersen-like thermostat (collision rate `rate`
+    per unit time), FP32 pair math with double-single state. Per T: the
+    throughput of `steps` timed steps, the mean steps between list builds,
+    and the shares of the step kernel (forces) and of the list update
+    (binning, canonical order, list build) in the kernel time of a
+    profiled repeat."""
+    rows = []
+    stream = torch.cuda.current_stream()
+    for T in temps:
+        w = W.thermostat_fluid(temperature=T)
+        s = ljmd.System(w.n, w.box, w.params, precision=ljmd.FP32_DS, sort_interval=100)
+        s.set_state(w.x, w.v, w.species)
+        s.set_thermostat(T, rate, seed=1234)
+        s.run(warmup, observe=False)
+        s.sync()
+        r0 = s.observables()["rebuilds"]
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(stream)
+        code = ljmd.lib.ljmd_run(s.ctx, steps, None)
+        b.record(stream)
+        torch.cuda.synchronize()
+        if code != 0:
+            raise ljmd.LJMDError(code, ljmd.last_error(s.ctx))
+        s.sync()
+        ms = a.elapsed_time(b)
+        o = s.observables()
+        builds = o["rebuilds"] - r0
+        s.set_profiling(True)
+        s.run(steps, observe=False)
+        s.sync()
+        kt = s.kernel_times()
+        s.set_profiling(False)
+        tot = sum(v[0] for v in kt.values())
+        rows.append({"T": T, "value": w.n * steps / (ms * 1e-3), "ms_per_step": ms / steps,
+                     "steps_per_build": steps / max(builds, 1), "T_measured": o["T"],
+                     "force_share": kt["step"][0] / tot,
+                     "list_update_share": (kt["rebuild"][0] + kt["resort"][0]) / tot})
+        s.close()
+    return {"workload": f"LJ fluid N=100000 (FCC 30^3 sites, random vacancies), rho=0.8442, rc=2.5, "
+                        f"skin=0.3, dt=0.005, Andersen-like thermostat rate {rate}, {steps} steps per T, "
+                        "FP32 pair math + DS state",
+            "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -308,7 +436,12 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiable-workload timing")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-replica timing")
     ap.add_argument("--no-mixture", action="store_true", help="skip the 4M binary-mixture timing")
+    ap.add_argument("--no-allpairs", action="store_true", help="skip the all-to-all (N=2000) timing")
+    ap.add_argument("--no-tsweep", action="store_true", help="skip the thermostat temperature sweep")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--mixture-steps", type=int, default=500)
+    ap.add_argument("--only-mixture", action="store_true",
+                    help="time only the 4M binary mixture and print its JSON object (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device (a reference kernel of known "
                          "traffic for hardware byte counters)")
@@ -332,6 +465,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.only_mixture:
+        print(json.dumps(time_mixture(ljmd, torch, W, copy_bandwidth(torch), steps=args.mixture_steps)), flush=True)
+        return
+
     w = W.config_headline()
     print(f"bench: workload {w.name} N={w.n}", file=sys.stderr, flush=True)
 
@@ -343,7 +480,8 @@ def main():
 
     step_ms, step_n = prof_run["kt"]["step"]
     avg_step_kernel_s = step_ms * 1e-3 / max(step_n, 1)
-    bpp = algorithmic_bytes_per_particle(ljmd.FP32_DS, prof_run["mean_list"])
+    bpp = algorithmic_bytes_per_particle(prof_run["mean_list"])
+    lbpp = layout_bytes_per_particle(ljmd.FP32_DS, prof_run["mean_list"])
     achieved = bpp * w.n / avg_step_kernel_s / 1e9
     copy_gbs = copy_bandwidth(torch)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -351,9 +489,14 @@ def main():
                 "achievable_copy_gbs": copy_gbs, "frac_of_achievable": achieved / copy_gbs,
                 "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "algorithmic_bytes_per_launch": bpp * w.n,
+                "algorithmic_bytes_per_particle": bpp,
+                "layout_bytes_per_launch": lbpp * w.n,
+                "layout_bytes_per_particle": lbpp,
                 "kernel": "k_step_ds (forces + velocity Verlet + reductions)",
                 "avg_kernel_us": avg_step_kernel_s * 1e6,
-                "bytes_per_particle": bpp, "mean_list_len": prof_run["mean_list"]}
+                "avg_kernel_us_source": "HIP events stamped by the kernel's own dispatch (extended launch) "
+                                        "on the library's stream, every launch of the timed repeat",
+                "mean_list_len": prof_run["mean_list"]}
     kernel_us = {k: (v[0] * 1e3 / v[1] if v[1] else 0.0) for k, v in prof_run["kt"].items()}
 
     obs = main_run["obs"]
@@ -368,12 +511,23 @@ def main():
         print(f"bench: fp64 {r64['ms']:.2f} ms", file=sys.stderr, flush=True)
 
     if not args.no_mixture:
-        extra["mixture"] = time_mixture(ljmd, torch, W, copy_gbs)
+        extra["mixture"] = time_mixture(ljmd, torch, W, copy_gbs, steps=args.mixture_steps)
         print(f"bench: mixture {extra['mixture']['value']:.3e} particle-steps/s", file=sys.stderr, flush=True)
 
     if not args.no_adjoint:
         extra["adjoint"] = time_adjoint(ljmd, torch, W)
         print(f"bench: adjoint/forward {extra['adjoint']['ratio']:.3f}", file=sys.stderr, flush=True)
+
+    if not args.no_allpairs:
+        extra["all_pairs"] = time_allpairs(ljmd, torch, W)
+        print(f"bench: all-pairs {extra['all_pairs']['fp32_ds']['value']:.3e} particle-steps/s",
+              file=sys.stderr, flush=True)
+
+    if not args.no_tsweep:
+        extra["thermostat_sweep"] = time_thermostat_sweep(ljmd, torch, W)
+        print("bench: T sweep " + " ".join(f"T={r['T']}:{r['list_update_share']:.2f}"
+                                           for r in extra["thermostat_sweep"]["rows"]),
+              file=sys.stderr, flush=True)
 
     if not args.no_batch:
         extra["batched"] = time_batch(ljmd, torch, W)
@@ -404,6 +558,7 @@ def main():
         "cpu_baseline": cpu,
         "kernel_avg_us": kernel_us,
         "rebuilds_in_timed_steps": rebuilds,
+        "paper_context": PAPER_CONTEXT,
         "energy_per_particle_first_last": [float(E[0]), float(E[-1])],
         **extra,
     }

@@ -212,6 +212,26 @@ def all_pairs_fluid(n: int = 2000, rho: float = 0.8442, temperature: float = 1.0
     return Workload(f"all_pairs_n{n}", x, v, sp, np.full(3, L), p, steps, temperature)
 
 
+def thermostat_fluid(n: int = 100_000, rho: float = 0.8442, temperature: float = 1.0, seed_index: int = 1,
+                     steps: int = 2000) -> Workload:
+    """The truncated-force study shape (the paper's 100,000 particles at
+    several temperatures): N sites kept, by a seeded permutation, from the
+    smallest FCC lattice that holds them, scaled to density rho;
+    Maxwell-Boltzmann velocities at T; cutoff 2.5 with energy shift, skin
+    0.3, dt 0.005."""
+    rng = config_rng(seed_index)
+    m = int(math.ceil((n / 4.0) ** (1.0 / 3.0)))
+    xs, _ = fcc_lattice(m, 1.0)
+    L = (n / rho) ** (1.0 / 3.0)
+    xs = xs * (L / (m * 4.0 ** (1.0 / 3.0)))
+    keep = np.sort(rng.permutation(xs.shape[0])[:n])
+    x = np.ascontiguousarray(xs[keep])
+    sp = np.zeros(n, dtype=np.int32)
+    p = single_species_params()
+    v = maxwell_boltzmann(n, temperature, p.mass, sp, rng)
+    return Workload(f"thermostat_fluid_n{n}_T{temperature:g}", x, v, sp, np.full(3, L), p, steps, temperature)
+
+
 def random_dense(n: int, rho: float, seed: int, min_dist: float = 0.85,
                  nspecies: int = 1) -> Workload:
     """Small disordered configuration for tests: random sequential insertion
