@@ -412,7 +412,10 @@ __device__ inline uint32_t wave_max_u32(uint32_t v) {
 // stores, an eighth fewer VALU instructions); the kernel is bound by issue
 // latency as much as by VALU throughput, so the chunk is kept small enough
 // for five waves per SIMD.
-template <int PREC, int NS, bool QC>
+// LG: log2 of the lanes per particle of the list layout when it is known at
+// compile time (the shifts and masks of the entry index fold), -1 to read it
+// from g.lanes.
+template <int PREC, int NS, bool QC, int LG = -1>
 __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &box, const PairC &pc,
                                   const int32_t *rank_of, const int32_t *cell_lin, int64_t c_off, int c,
                                   Ctl *ctl, typename CellRec<PREC>::T *stage) {
@@ -422,8 +425,9 @@ __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &bo
     constexpr int CH = NlistChunk<PREC, FILT>::CH;
     const int lane = threadIdx.x & 63;
     const T *__restrict__ cr = cell_recs<PREC>(st);
-    const int lg = g.lanes >= 16 ? 4 : (g.lanes >= 8 ? 3 : (g.lanes >= 4 ? 2 : (g.lanes >= 2 ? 1 : 0)));
-    const int lmask = g.lanes - 1;
+    const int lg = LG >= 0 ? LG : (g.lanes >= 16 ? 4 : (g.lanes >= 8 ? 3 : (g.lanes >= 4 ? 2 : (g.lanes >= 2 ? 1 : 0))));
+    const int lanes = LG >= 0 ? (1 << LG) : g.lanes;
+    const int lmask = lanes - 1;
     const int lin = cell_lin[c];
     const int cc[3] = {lin / (box.nc[1] * box.nc[2]), (lin / box.nc[2]) % box.nc[1],
                        lin % box.nc[2]};
@@ -568,7 +572,7 @@ __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &bo
                 // Entry kk of particle i: lane kk % lanes, its entry m = kk / lanes
                 // at row[(m / 4) * 256 + (kk % lanes) * 4 + m % 4], addressed
                 // by a 32-bit byte offset from the particle's row.
-                uint8_t *__restrict__ row = (uint8_t *)(st.nbr + nbr_index(i, 0, g.lanes, g.cap));
+                uint8_t *__restrict__ row = (uint8_t *)(st.nbr + nbr_index(i, 0, lanes, g.cap));
 #pragma unroll
                 for (int b = 0; b < CH; ++b) {
                     if (b >= nbk) break;
@@ -622,7 +626,7 @@ struct NlistStage {
     static constexpr int kEntries = (PREC == LJMD_FP32_DS && QC) ? kNlWaves * NlistChunk<PREC, true>::CH * kWave : 1;
 };
 
-template <int PREC, int NS, bool QC>
+template <int PREC, int NS, bool QC, int LG = -1>
 __global__ __launch_bounds__(kNlWaves * kWave) void k_nlist(State st, Geom g, BoxC box, PairC pc, int cur,
                                                             int64_t step, int forced, float thr2) {
     (void)cur;
@@ -641,7 +645,7 @@ __global__ __launch_bounds__(kNlWaves * kWave) void k_nlist(State st, Geom g, Bo
         const int per = (box.ncell + tw - 1) / tw;
         const int cbeg = gw * per, cend = min(cbeg + per, box.ncell);
         for (int c = cbeg; c < cend; ++c)
-            nlist_cell<PREC, NS, QC>(st, g, box, pc, st.rank_of, st.cell_lin, 0, c, st.ctl, stage);
+            nlist_cell<PREC, NS, QC, LG>(st, g, box, pc, st.rank_of, st.cell_lin, 0, c, st.ctl, stage);
         return;
     }
     // Many cells per wave: each XCD (blocks are dispatched to XCD
@@ -658,7 +662,7 @@ __global__ __launch_bounds__(kNlWaves * kWave) void k_nlist(State st, Geom g, Bo
         if (lane == 0) c = lo + (int)atomicAdd(&st.ctl->nlq[q], 1u);
         c = __shfl(c, 0);
         if (c >= hi) break;
-        nlist_cell<PREC, NS, QC>(st, g, box, pc, st.rank_of, st.cell_lin, 0, c, st.ctl, stage);
+        nlist_cell<PREC, NS, QC, LG>(st, g, box, pc, st.rank_of, st.cell_lin, 0, c, st.ctl, stage);
     }
 }
 
@@ -857,7 +861,12 @@ static void nlist_launch(const Launch &L, int64_t step, int forced) {
     const unsigned ncu = L.g->ncu > 0 ? (unsigned)L.g->ncu : 256u;
     const unsigned cap = ncu * kNlBlocksPerCu;
     const unsigned nb = need < cap ? (need > 0 ? need : 1u) : cap;
-    if (PREC == LJMD_FP32_DS && L.box->cubic)
+    // The common layout of the single-precision force pass (two lanes per
+    // particle) has its own instantiation with the entry index folded.
+    if (PREC == LJMD_FP32_DS && L.box->cubic && L.g->lanes == 2)
+        hipLaunchKernelGGL((k_nlist<PREC, NS, PREC == LJMD_FP32_DS, 1>), dim3(nb), dim3(kNlWaves * kWave), 0,
+                           L.stream, *L.st, *L.g, *L.box, *L.pc, L.cur, step, forced, L.dyn->thr2);
+    else if (PREC == LJMD_FP32_DS && L.box->cubic)
         hipLaunchKernelGGL((k_nlist<PREC, NS, PREC == LJMD_FP32_DS>), dim3(nb), dim3(kNlWaves * kWave), 0, L.stream,
                            *L.st, *L.g, *L.box, *L.pc, L.cur, step, forced, L.dyn->thr2);
     else
