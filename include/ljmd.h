@@ -460,6 +460,24 @@ size_t ljmd_brute_workspace_size(const ljmd_params *p);
 int ljmd_brute_forces(const ljmd_params *p, const double *x, const int32_t *species, double *f, double *uw,
                       void *dev_workspace, size_t bytes, void *hip_stream);
 
+/* ---- Allocation-free variant -----------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * evaluation as ljmd_brute_forces, with the same arguments minus the
+ * workspace. Its scratch is a fixed device array of
+ * LJMD_BRUTE_STATIC_SCRATCH_BYTES inside the library (one per GPU, held
+ * until the process ends); the call allocates and frees nothing. Sizes
+ * whose scratch (ljmd_brute_workspace_size) exceeds it are rejected with
+ * LJMD_ENOMEM (above about 349,000 particles in single precision, 208,000
+ * in FP64). Every call on a GPU shares that GPU's array: calls that overlap on
+ * one GPU (other streams, other threads) race and must be serialised by the
+ * caller; calls on one stream are ordered. Nothing in the array needs to
+ * start at zero. Errors as ljmd_brute_forces. */
+#define LJMD_BRUTE_STATIC_SCRATCH_BYTES (16u << 20)
+size_t ljmd_brute_static_scratch_bytes(void);
+int ljmd_brute_forces_noalloc(const ljmd_params *p, const double *x, const int32_t *species, double *f, double *uw,
+                              void *hip_stream);
+
 /* Text of the last error of ctx (or of the last failed create when ctx is
  * NULL). The pointer stays valid until the next call on ctx. */
 const char *ljmd_last_error(const ljmd_ctx *ctx);

@@ -108,6 +108,8 @@ SIGNATURES = {
                                       C.c_size_t, _vp, C.c_int32, C.c_char_p, C.POINTER(Tuning)]),
     "ljmd_brute_workspace_size": (C.c_size_t, [C.POINTER(Params)]),
     "ljmd_brute_forces": (C.c_int, [C.POINTER(Params), _dp, _ip, _dp, _dp, _vp, C.c_size_t, _vp]),
+    "ljmd_brute_static_scratch_bytes": (C.c_size_t, []),
+    "ljmd_brute_forces_noalloc": (C.c_int, [C.POINTER(Params), _dp, _ip, _dp, _dp, _vp]),
     "ljmd_autotune_workspace_size": (C.c_size_t, [C.POINTER(Params)]),
     "ljmd_autotune": (C.c_int, [C.POINTER(Params), _dp, _dp, _ip, _vp, C.c_size_t, _vp, C.c_int32, C.c_char_p,
                                 C.POINTER(Tuning)]),
@@ -498,6 +500,25 @@ def brute_forces(n: int, box, p, x, species, precision: int = FP64):
     stream = torch.cuda.current_stream()
     code = lib.ljmd_brute_forces(C.byref(params), _ptr(xs), _ptr(sp), _ptr(f), _ptr(uw), C.c_void_p(_ptr(ws)), size,
                                  C.c_void_p(stream.cuda_stream))
+    if code != 0:
+        raise LJMDError(code, last_error(None))
+    return f, uw
+
+
+def brute_forces_noalloc(n: int, box, p, x, species, precision: int = FP64):
+    """ljmd_brute_forces_noalloc: as brute_forces, with the library's fixed
+    per-GPU scratch instead of a workspace (the call allocates nothing on the
+    device; only the outputs here are torch tensors)."""
+    import torch
+    params = make_params(n, box, p, precision, 0)
+    dev = lambda a, dt: (torch.from_numpy(np.ascontiguousarray(a)) if isinstance(a, np.ndarray) else a).to(
+        device="cuda", dtype=dt).contiguous()
+    xs, sp = dev(x, torch.float64).reshape(n, 3), dev(species, torch.int32).reshape(n)
+    f = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    uw = torch.empty(2, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    code = lib.ljmd_brute_forces_noalloc(C.byref(params), _ptr(xs), _ptr(sp), _ptr(f), _ptr(uw),
+                                         C.c_void_p(stream.cuda_stream))
     if code != 0:
         raise LJMDError(code, last_error(None))
     return f, uw
