@@ -106,8 +106,8 @@ PAPER_CONTEXT = {
 }
 
 
-def time_gpu(ljmd, torch, w, prec, steps, warmup, lanes, profile):
-    s = ljmd.System(w.n, w.box, w.params, precision=prec, sort_interval=100, lanes=lanes)
+def time_gpu(ljmd, torch, w, prec, steps, warmup, lanes, profile, cell_split=0):
+    s = ljmd.System(w.n, w.box, w.params, precision=prec, sort_interval=100, lanes=lanes, cell_split=cell_split)
     s.set_state(w.x, w.v, w.species)
     if warmup:
         s.run(warmup)
@@ -311,7 +311,7 @@ def time_batch(ljmd, torch, W, steps: int = 1000, warmup: int = 50):
     # Lanes per particle and list capacity from the batch autotuner (not timed).
     tune = ljmd.autotune_batch(sizes, edges, ws[0].params, x, v, sp, steps=20)
     b = ljmd.Batch(sizes, edges, ws[0].params, sort_interval=100, lanes=tune["lanes"],
-                   nbr_capacity=tune["nbr_capacity"])
+                   nbr_capacity=tune["nbr_capacity"], cell_split=tune["cell_split"])
     b.set_state(x, v, sp)
     b.run(warmup)
     b.sync()
@@ -340,7 +340,8 @@ def time_batch(ljmd, torch, W, steps: int = 1000, warmup: int = 50):
         "value": ntot * steps / (ms * 1e-3), "unit": "particle-steps/s", "steps": steps,
         "ms_per_step": ms / steps, "launch": "HIP graph per 100-step resort period",
         "ms_per_step_eager_launches": ms_eager / steps,
-        "autotuned": {"lanes": tune["lanes"], "nbr_capacity": tune["nbr_capacity"], "max_fill": tune["max_fill"]},
+        "autotuned": {"cell_split": tune["cell_split"], "lanes": tune["lanes"], "nbr_capacity": tune["nbr_capacity"],
+                      "max_fill": tune["max_fill"], "ms_per_step_tuning": tune["ms_per_step"]},
         "rebuilds_per_system_mean": float(obs[:, 6].mean()),
     }
 
@@ -431,6 +432,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--cell-split", type=int, default=0,
+                    help="cells per list radius for the headline run (0: the library default, 1)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiable-workload timing")
@@ -442,6 +445,9 @@ def main():
     ap.add_argument("--mixture-steps", type=int, default=500)
     ap.add_argument("--only-mixture", action="store_true",
                     help="time only the 4M binary mixture and print its JSON object (for profiling)")
+    ap.add_argument("--only-allpairs", action="store_true",
+                    help="time only the all-to-all workload and print its JSON object (for profiling)")
+    ap.add_argument("--allpairs-steps", type=int, default=20000)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device (a reference kernel of known "
                          "traffic for hardware byte counters)")
@@ -465,6 +471,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.only_allpairs:
+        print(json.dumps(time_allpairs(ljmd, torch, W, steps=args.allpairs_steps)), flush=True)
+        return
+
     if args.only_mixture:
         print(json.dumps(time_mixture(ljmd, torch, W, copy_bandwidth(torch), steps=args.mixture_steps)), flush=True)
         return
@@ -472,9 +482,9 @@ def main():
     w = W.config_headline()
     print(f"bench: workload {w.name} N={w.n}", file=sys.stderr, flush=True)
 
-    main_run = time_gpu(ljmd, torch, w, ljmd.FP32_DS, args.steps, args.warmup, args.lanes, False)
+    main_run = time_gpu(ljmd, torch, w, ljmd.FP32_DS, args.steps, args.warmup, args.lanes, False, args.cell_split)
     print(f"bench: fp32+ds {main_run['ms']:.2f} ms for {args.steps} steps", file=sys.stderr, flush=True)
-    prof_run = time_gpu(ljmd, torch, w, ljmd.FP32_DS, args.steps, args.warmup, args.lanes, True)
+    prof_run = time_gpu(ljmd, torch, w, ljmd.FP32_DS, args.steps, args.warmup, args.lanes, True, args.cell_split)
     ms_step = main_run["ms"] / args.steps
     value = w.n * args.steps / (main_run["ms"] * 1e-3)
 
@@ -519,7 +529,7 @@ def main():
         print(f"bench: adjoint/forward {extra['adjoint']['ratio']:.3f}", file=sys.stderr, flush=True)
 
     if not args.no_allpairs:
-        extra["all_pairs"] = time_allpairs(ljmd, torch, W)
+        extra["all_pairs"] = time_allpairs(ljmd, torch, W, steps=args.allpairs_steps)
         print(f"bench: all-pairs {extra['all_pairs']['fp32_ds']['value']:.3e} particle-steps/s",
               file=sys.stderr, flush=True)
 
@@ -552,7 +562,7 @@ def main():
                                "skin=0.3, dt=0.005, NVE velocity Verlet, half-skin rebuild, "
                                "SFC resort every 100 steps",
                    "n": w.n, "precision": "fp32 pair math, double-single state",
-                   "lanes": args.lanes or 2,
+                   "lanes": args.lanes or 2, "cell_split": args.cell_split or 1,
                    "nbr_capacity": prof_run["info"]["nbr_capacity"]},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define LJMD_ABI_VERSION 6
+#define LJMD_ABI_VERSION 7
 
 enum ljmd_status {
     LJMD_OK = 0,
@@ -93,7 +93,10 @@ typedef struct ljmd_params {
     int32_t nbr_capacity;   /* list slots per particle to start with; 0 = automatic */
     int32_t cell_capacity;  /* particle slots per cell, <= 768; 0 = automatic */
     int32_t lanes;          /* lanes per particle in the force gather: 1,2,4,8,16; 0 = automatic */
-    int32_t reserved;       /* must be 0 */
+    int32_t cell_split;     /* cells per list radius along each axis for binning and the
+                               list build: 1 (cell edge >= r_L, 27-cell stencil) or 2 (edge
+                               >= r_L / 2, 125-cell stencil); 0 = 1. The lists are the
+                               same sets either way; ljmd_autotune times both */
 } ljmd_params;
 
 /* Per-step observable row written by ljmd_run into a device array:
@@ -336,9 +339,10 @@ int ljmd_vv_backward(ljmd_ctx *ctx, const double *lam_x, const double *lam_v, co
 /* ---- Autotuning -------------------------------------------------------------
  * The paper picks launch configurations per device (Sec. 4, 5); this
  * library's tuner times short runs of a system on the device for each
- * candidate force-gather shape (lanes per particle 1, 2, 4, 8, 16) and sizes
- * the list capacity from the longest list seen (1.25x, at least +24, in
- * units of 16). Results are cached as JSON lines in cache_path (may be NULL)
+ * candidate cell size (cell_split 1 and 2: cells of edge >= r_L or >= r_L/2)
+ * and force-gather shape (lanes per particle 1, 2, 4, 8, 16), keeps the
+ * fastest pair, and sizes the list capacity from the longest list seen
+ * (1.25x, at least +24, in units of 16). Results are cached as JSON lines in cache_path (may be NULL)
  * under a key of device architecture, precision, species count, size (power
  * of two), density (to 0.05) and list radius; a cached key is returned
  * without timing. */
@@ -349,7 +353,7 @@ typedef struct ljmd_tuning {
     int32_t max_fill;       /* longest list seen while timing */
     double ms_per_step;     /* time per step of the fastest shape */
     int32_t from_cache;     /* 1 if read from the cache */
-    int32_t reserved;
+    int32_t cell_split;     /* fastest cell size (ljmd_params.cell_split) */
 } ljmd_tuning;
 
 /* Device bytes the tuner needs for p (the largest workspace of its

@@ -42,6 +42,7 @@ struct BoxC {
     int32_t nc[3];               // cells per axis
     int32_t ncell;
     int32_t cubic;               // all three edges equal: forces may work in quanta
+    int32_t reach;               // list-build stencil half-width in cells (1: edge >= r_L, 2: edge >= r_L / 2)
     // Cubic boxes, per pair type: r_c^2 and sigma^2 in units of the squared
     // quantum (L 2^-32)^2, and 24 eps / quantum, so that the force kernel can
     // use raw fixed-point differences as displacements.

@@ -431,37 +431,24 @@ __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &bo
     const int lin = cell_lin[c];
     const int cc[3] = {lin / (box.nc[1] * box.nc[2]), (lin / box.nc[2]) % box.nc[1],
                        lin % box.nc[2]};
+    // Stencil: the cells within box.reach cells of the home cell along each
+    // axis (3 x 3 x 3 with cells of edge >= r_L, 5 x 5 x 5 with cells of
+    // edge >= r_L / 2), or every cell of an axis that has fewer (each cell
+    // once). Stencil cells are taken 64 at a time, one per lane.
+    const int R = box.reach;
     int lo[3], n3[3];
     for (int a = 0; a < 3; ++a) {
-        if (box.nc[a] >= 3) {
-            lo[a] = -1;
-            n3[a] = 3;
+        if (box.nc[a] >= 2 * R + 1) {
+            lo[a] = -R;
+            n3[a] = 2 * R + 1;
         } else {
             lo[a] = -cc[a];
             n3[a] = box.nc[a];
         }
     }
     const int nst = n3[0] * n3[1] * n3[2];
-    int scell = 0, scnt = 0;
-    if (lane < nst) {
-        const int a = lane / (n3[1] * n3[2]), bb = (lane / n3[2]) % n3[1], d = lane % n3[2];
-        int ax = cc[0] + lo[0] + a, ay = cc[1] + lo[1] + bb, az = cc[2] + lo[2] + d;
-        ax += ax < 0 ? box.nc[0] : (ax >= box.nc[0] ? -box.nc[0] : 0);
-        ay += ay < 0 ? box.nc[1] : (ay >= box.nc[1] ? -box.nc[1] : 0);
-        az += az < 0 ? box.nc[2] : (az >= box.nc[2] ? -box.nc[2] : 0);
-        scell = (int)c_off + rank_of[(ax * box.nc[1] + ay) * box.nc[2] + az];
-        scnt = min(st.cell_count[scell], g.cell_cap);
-    }
-    int incl = scnt;
-    for (int o = 1; o < kWave; o <<= 1) {
-        const int y = __shfl_up(incl, o);
-        if (lane >= o) incl += y;
-    }
-    const int soff = incl - scnt;
-    const int ncand = __shfl(incl, kWave - 1);
-    const int home_s = ((-lo[0]) * n3[1] + (-lo[1])) * n3[2] + (-lo[2]);
-    const int home = __shfl(scell, home_s);
-    const int m = __shfl(scnt, home_s);
+    const int home = (int)c_off + c;
+    const int m = min(st.cell_count[home], g.cell_cap);
     // Largest list radius of any pair type, with the margin of the reduction.
     float reach = 0.0f;
     if constexpr (FILT) {
@@ -486,6 +473,30 @@ __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &bo
             }
         }
         int kreg = 0;
+        for (int s0 = 0; s0 < nst; s0 += kWave) {
+        // Stencil cells s0 .. s0 + nsp - 1: lane e holds cell s0 + e, its
+        // flattened index, its (capped) count and the offset of its first
+        // candidate among this part's candidates.
+        const int nsp = min(nst - s0, kWave);
+        int scell = 0, scnt = 0;
+        if (lane < nsp) {
+            const int sl = s0 + lane;
+            const int a = sl / (n3[1] * n3[2]), bb = (sl / n3[2]) % n3[1], d = sl % n3[2];
+            int ax = cc[0] + lo[0] + a, ay = cc[1] + lo[1] + bb, az = cc[2] + lo[2] + d;
+            ax += ax < 0 ? box.nc[0] : (ax >= box.nc[0] ? -box.nc[0] : 0);
+            ay += ay < 0 ? box.nc[1] : (ay >= box.nc[1] ? -box.nc[1] : 0);
+            az += az < 0 ? box.nc[2] : (az >= box.nc[2] ? -box.nc[2] : 0);
+            scell = (int)c_off + rank_of[(ax * box.nc[1] + ay) * box.nc[2] + az];
+            scnt = min(st.cell_count[scell], g.cell_cap);
+        }
+        int incl = scnt;
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int y = __shfl_up(incl, o);
+            if (lane >= o) incl += y;
+        }
+        const int soff = incl - scnt;
+        const int ncand = __shfl(incl, kWave - 1);
+        const int top = nsp > 32 ? 32 : 16;
         for (int cb = 0; cb < ncand; cb += CH * kWave) {
             // Blocks of 64 candidates this chunk holds (wave-uniform): the
             // last chunk of a cell is usually short.
@@ -504,13 +515,14 @@ __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &bo
                 thr1[b] = 0u;
                 if (b >= nbk) continue;
                 const int t = cb + b * kWave + lane;
-                // Largest stencil cell s with soff[s] <= t: a fixed 5-step
-                // binary search, every lane shuffling in every step.
+                // Largest stencil cell s of this part with soff[s] <= t: a
+                // fixed 5-step (6 with more than 32 cells) binary search,
+                // every lane shuffling in every step.
                 int sel = 0;
-                for (int stp = 16; stp >= 1; stp >>= 1) {
+                for (int stp = top; stp >= 1; stp >>= 1) {
                     const int cand_s = sel + stp;
-                    const int v = __shfl(soff, cand_s < nst ? cand_s : nst - 1);
-                    if (cand_s < nst && v <= t) sel = cand_s;
+                    const int v = __shfl(soff, cand_s < nsp ? cand_s : nsp - 1);
+                    if (cand_s < nsp && v <= t) sel = cand_s;
                 }
                 const int cs = __shfl(scell, sel), os = __shfl(soff, sel);
                 cv[b] = t < ncand;
@@ -606,6 +618,7 @@ __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &bo
                 }
                 kreg = lane == p ? k : kreg;
             }
+        }
         }
         if (lane < hm) {
             const int i = CR::index(hrec);

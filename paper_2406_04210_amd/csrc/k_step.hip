@@ -72,19 +72,12 @@ __device__ inline void step_ds_body(const StepArgs &a, const BoxC &box, Ctl *ctl
     if (halted_record(ctl, a.step, bj == 0)) return;
     step_housekeeping(a, ctl, c_lo, c_hi, bj, nbj, rebuilt);
 
+    // Own record (position and species). The double-single state and the
+    // list reference are read once, by the step tail after the pair loop:
+    // reading the state here as well and again there costs a second fetch,
+    // because the list stream of the loop evicts it from L2.
     const int4 *__restrict__ rec = st.recq[a.cur];
-    // Own position: the fixed-point image of the double-single state (the
-    // record the previous step wrote for this slot holds the same
-    // coordinates, so it is not read again); the species from the list
-    // reference's last word.
-    const int4 xr = valid ? st.xref[i] : make_int4(0, 0, 0, 0);
-    int4 ri = make_int4(0, 0, 0, xr.w);
-    if (valid) {
-        const float4 w0 = st.dsw[0][i], w1 = st.dsw[1][i];
-        ri.x = (int)q_from_ds(w0.x, w0.w, box.S_hi[0], box.S_lo[0]);
-        ri.y = (int)q_from_ds(w0.y, w1.x, box.S_hi[1], box.S_lo[1]);
-        ri.z = (int)q_from_ds(w0.z, w1.y, box.S_hi[2], box.S_lo[2]);
-    }
+    const int4 ri = valid ? rec[i] : make_int4(0, 0, 0, 0);
     int cnt = valid ? st.nbr_cnt[i] : 0;
     cnt = cnt < a.g.cap ? cnt : a.g.cap;
     const int32_t *__restrict__ nb = st.nbr + chunk * (int64_t)(P * a.g.cap) + 4 * lane;
@@ -246,7 +239,7 @@ __device__ inline void step_ds_body(const StepArgs &a, const BoxC &box, Ctl *ctl
     double pu = 0.0, pw = 0.0, pk = 0.0, ppx = 0.0, ppy = 0.0, ppz = 0.0;
     uint32_t dm = 0u;
     if (valid && l == 0)
-        finish_ds<OBS, TH, PLAIN>(a, box, i, ri.w, xr, fx, fy, fz, e, w, pu, pw, pk, ppx, ppy, ppz, dm);
+        finish_ds<OBS, TH, PLAIN>(a, box, i, ri.w, st.xref[i], fx, fy, fz, e, w, pu, pw, pk, ppx, ppy, ppz, dm);
     block_finish<OBS>(a, ctl, blk, pu, pw, pk, ppx, ppy, ppz, dm);
 }
 

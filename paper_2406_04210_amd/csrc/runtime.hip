@@ -158,7 +158,7 @@ int validate(const ljmd_params *p, std::string *why) {
     if (p->cell_capacity < 0 || p->cell_capacity > 768) return bad("cell_capacity must be in [0, 768]");
     if (p->lanes != 0 && p->lanes != 1 && p->lanes != 2 && p->lanes != 4 && p->lanes != 8 && p->lanes != 16)
         return bad("lanes must be 0, 1, 2, 4, 8 or 16");
-    if (p->reserved != 0) return bad("reserved must be 0");
+    if (p->cell_split < 0 || p->cell_split > 2) return bad("cell_split must be 0, 1 or 2");
     if (all_pairs(p)) {
         // Minimum image of every pair; the single-precision paths work in
         // fixed-point quanta of a cubic box.
@@ -175,10 +175,13 @@ int validate(const ljmd_params *p, std::string *why) {
     return LJMD_OK;
 }
 
+// Cells per list radius along each axis (ljmd_params.cell_split).
+int cell_split(const ljmd_params *p) { return p->cell_split == 2 ? 2 : 1; }
+
 void grid_dims(const ljmd_params *p, int nc[3]) {
-    const double rl = list_radius_max(p);
+    const double edge = list_radius_max(p) / cell_split(p);
     for (int k = 0; k < 3; ++k) {
-        double f = std::floor(p->box[k] / (rl * (1.0 + 1e-6)));
+        double f = std::floor(p->box[k] / (edge * (1.0 + 1e-6)));
         nc[k] = (int)std::max(1.0, std::min(f, 1024.0));
     }
 }
@@ -355,6 +358,7 @@ void fill_constants(ljmd_ctx *c, const Plan &pl) {
     }
     b.ncell = pl.ncell;
     b.cubic = (p.box[0] == p.box[1] && p.box[1] == p.box[2]) ? 1 : 0;
+    b.reach = cell_split(&p);
     fill_pairs(c->pc, p);
     fill_quanta(b, c->pc, p.box[0]);
     DynC &d = c->dyn;
@@ -879,6 +883,7 @@ int batch_geom(const ljmd_params *shared, const ljmd_system *ys, int32_t nsys, B
         }
         b.ncell = pk.ncell;
         b.cubic = 1;
+        b.reach = cell_split(&q);
         PairC pc;
         fill_pairs(pc, q);
         fill_quanta(b, pc, q.box[0]);
@@ -973,6 +978,7 @@ void box_pair_constants(const ljmd_params &p, BoxC &b, PairC &q) {
     }
     b.ncell = 1;
     b.cubic = (p.box[0] == p.box[1] && p.box[1] == p.box[2]) ? 1 : 0;
+    b.reach = 1;
     fill_pairs(q, p);
     fill_quanta(b, q, p.box[0]);
 }

@@ -1,6 +1,8 @@
-// tune.hip -- the autotuner: picks the launch shape of the force gather
-// (lanes per particle) for a system by timing short runs on the device, and
-// sizes the list capacity from the longest list seen. Results are cached in a
+// tune.hip -- the autotuner: picks the cell size of the binning and list
+// build (cells of edge >= r_L, or >= r_L / 2 with the 125-cell stencil) and
+// the launch shape of the force gather (lanes per particle) for a system by
+// timing short runs on the device, and sizes the list capacity from the
+// longest list seen. Results are cached in a
 // text file of JSON lines keyed by device, precision, species count, size
 // and density, so a known shape is reused without timing (the paper tunes
 // launch configurations per device, Sec. 4-5; the search here is this
@@ -16,6 +18,7 @@
 namespace {
 
 constexpr int kLaneCandidates[] = {1, 2, 4, 8, 16};
+constexpr int kSplitCandidates[] = {1, 2};
 
 std::string tune_key(const ljmd_params *p) {
     hipDeviceProp_t prop;
@@ -50,7 +53,10 @@ bool cache_lookup(const char *path, const std::string &key, ljmd_tuning *out) {
         const char *s = std::strstr(line, "\"cell_capacity\":");
         const char *t = std::strstr(line, "\"ms_per_step\":");
         const char *u = std::strstr(line, "\"max_fill\":");
-        if (!q || !r || !s || !t || !u) continue;
+        const char *v = std::strstr(line, "\"cell_split\":");
+        if (!q || !r || !s || !t || !u || !v) continue;
+        int split = 0;
+        if (std::sscanf(v, "\"cell_split\": %d", &split) != 1) continue;
         if (std::sscanf(q, "\"lanes\": %d", &lanes) != 1 || std::sscanf(r, "\"nbr_capacity\": %d", &cap) != 1 ||
             std::sscanf(s, "\"cell_capacity\": %d", &cc) != 1 || std::sscanf(t, "\"ms_per_step\": %lf", &ms) != 1 ||
             std::sscanf(u, "\"max_fill\": %d", &fill) != 1)
@@ -60,6 +66,7 @@ bool cache_lookup(const char *path, const std::string &key, ljmd_tuning *out) {
         out->cell_capacity = cc;
         out->ms_per_step = ms;
         out->max_fill = fill;
+        out->cell_split = split;
         found = true;  // the last matching line wins
     }
     std::fclose(f);
@@ -70,9 +77,9 @@ void cache_store(const char *path, const std::string &key, const ljmd_tuning &t)
     FILE *f = std::fopen(path, "a");
     if (!f) return;
     std::fprintf(f,
-                 "{\"key\": \"%s\", \"lanes\": %d, \"nbr_capacity\": %d, \"cell_capacity\": %d, "
-                 "\"ms_per_step\": %.6f, \"max_fill\": %d}\n",
-                 key.c_str(), t.lanes, t.nbr_capacity, t.cell_capacity, t.ms_per_step, t.max_fill);
+                 "{\"key\": \"%s\", \"cell_split\": %d, \"lanes\": %d, \"nbr_capacity\": %d, "
+                 "\"cell_capacity\": %d, \"ms_per_step\": %.6f, \"max_fill\": %d}\n",
+                 key.c_str(), t.cell_split, t.lanes, t.nbr_capacity, t.cell_capacity, t.ms_per_step, t.max_fill);
     std::fclose(f);
 }
 
@@ -110,13 +117,15 @@ extern "C" {
 size_t ljmd_autotune_workspace_size(const ljmd_params *p) {
     if (ljmd_check_params(p) != LJMD_OK) return 0;
     size_t best = 0;
-    for (int lanes : kLaneCandidates) {
-        ljmd_params q = *p;
-        q.lanes = lanes;
-        const size_t s = ljmd_workspace_size(&q);
-        if (s == 0) return 0;
-        best = s > best ? s : best;
-    }
+    for (int split : kSplitCandidates)
+        for (int lanes : kLaneCandidates) {
+            ljmd_params q = *p;
+            q.lanes = lanes;
+            q.cell_split = split;
+            const size_t s = ljmd_workspace_size(&q);
+            if (s == 0) return 0;
+            best = s > best ? s : best;
+        }
     return best;
 }
 
@@ -142,9 +151,11 @@ int ljmd_autotune(const ljmd_params *p, const double *x, const double *v, const 
     }
     double best_ms = 0.0;
     int rc = LJMD_OK;
+    for (int split : kSplitCandidates)
     for (int lanes : kLaneCandidates) {
         ljmd_params q = *p;
         q.lanes = lanes;
+        q.cell_split = split;
         ljmd_ctx *c = nullptr;
         if ((rc = ljmd_create(&q, ws, bytes, stream, &c)) != LJMD_OK) break;
         float ms = 0.f;
@@ -164,6 +175,7 @@ int ljmd_autotune(const ljmd_params *p, const double *x, const double *v, const 
         if (out->lanes == 0 || per < best_ms) {
             best_ms = per;
             out->lanes = lanes;
+            out->cell_split = split;
             out->cell_capacity = q.cell_capacity;
         }
         out->max_fill = o.max_fill > out->max_fill ? o.max_fill : out->max_fill;
@@ -181,13 +193,15 @@ int ljmd_autotune(const ljmd_params *p, const double *x, const double *v, const 
 size_t ljmd_batch_autotune_workspace_size(const ljmd_params *shared, const ljmd_system *sys, int32_t nsys) {
     if (!shared || !sys || nsys < 1) return 0;
     size_t best = 0;
-    for (int lanes : kLaneCandidates) {
-        ljmd_params q = *shared;
-        q.lanes = lanes;
-        const size_t s = ljmd_batch_workspace_size(&q, sys, nsys);
-        if (s == 0) return 0;
-        best = s > best ? s : best;
-    }
+    for (int split : kSplitCandidates)
+        for (int lanes : kLaneCandidates) {
+            ljmd_params q = *shared;
+            q.lanes = lanes;
+            q.cell_split = split;
+            const size_t s = ljmd_batch_workspace_size(&q, sys, nsys);
+            if (s == 0) return 0;
+            best = s > best ? s : best;
+        }
     return best;
 }
 
@@ -213,9 +227,11 @@ int ljmd_batch_autotune(const ljmd_params *shared, const ljmd_system *sys, int32
     }
     double best_ms = 0.0;
     int rc = LJMD_OK;
+    for (int split : kSplitCandidates)
     for (int lanes : kLaneCandidates) {
         ljmd_params q = *shared;
         q.lanes = lanes;
+        q.cell_split = split;
         ljmd_batch *b = nullptr;
         if ((rc = ljmd_batch_create(&q, sys, nsys, ws, bytes, stream, &b)) != LJMD_OK) break;
         float ms = 0.f;
@@ -236,6 +252,7 @@ int ljmd_batch_autotune(const ljmd_params *shared, const ljmd_system *sys, int32
         if (out->lanes == 0 || per < best_ms) {
             best_ms = per;
             out->lanes = lanes;
+            out->cell_split = split;
             out->cell_capacity = q.cell_capacity;
         }
         out->max_fill = fill > out->max_fill ? fill : out->max_fill;

@@ -18,7 +18,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libljmd.so")
 
-ABI_VERSION = 6
+ABI_VERSION = 7
 FP64 = 0
 FP32_DS = 1
 FP32 = 2
@@ -42,7 +42,7 @@ class Params(C.Structure):
                 ("rcut", C.c_double * 4), ("mass", C.c_double * 2), ("skin", C.c_double),
                 ("dt", C.c_double), ("sort_interval", C.c_int32), ("precision", C.c_int32),
                 ("nbr_capacity", C.c_int32), ("cell_capacity", C.c_int32), ("lanes", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("cell_split", C.c_int32)]
 
 
 class Obs(C.Structure):
@@ -59,7 +59,7 @@ class SystemDesc(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("lanes", C.c_int32), ("nbr_capacity", C.c_int32), ("cell_capacity", C.c_int32),
                 ("max_fill", C.c_int32), ("ms_per_step", C.c_double), ("from_cache", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("cell_split", C.c_int32)]
 
 
 # Every exported function: name -> (restype, argtypes).
@@ -152,7 +152,7 @@ def _check(code: int, ctx=None):
 
 
 def make_params(n: int, box, p, precision: int = FP32_DS, sort_interval: int = 100,
-                nbr_capacity: int = 0, cell_capacity: int = 0, lanes: int = 0) -> Params:
+                nbr_capacity: int = 0, cell_capacity: int = 0, lanes: int = 0, cell_split: int = 0) -> Params:
     """Build the C parameter struct from an LJParams-like object ``p``."""
     s = Params()
     s.n = int(n)
@@ -173,7 +173,7 @@ def make_params(n: int, box, p, precision: int = FP32_DS, sort_interval: int = 1
     s.nbr_capacity = int(nbr_capacity)
     s.cell_capacity = int(cell_capacity)
     s.lanes = int(lanes)
-    s.reserved = 0
+    s.cell_split = int(cell_split)
     return s
 
 
@@ -211,7 +211,7 @@ class System:
 
     def __init__(self, n: int, box, p, precision: int = FP32_DS, sort_interval: int = 100,
                  nbr_capacity: int = 0, cell_capacity: int = 0, lanes: int = 0, device=None,
-                 nbr_capacity_max: int = 0):
+                 nbr_capacity_max: int = 0, cell_split: int = 0):
         """nbr_capacity_max > nbr_capacity gives the workspace room for lists of
         that many entries: a list overflow then grows the lists in place and
         redoes the steps (ljmd_run), instead of reporting LJMD_ENLIST."""
@@ -221,13 +221,14 @@ class System:
             raise RuntimeError("ljmd.System needs a HIP GPU; none is visible")
         self.device = torch.device(device if device is not None else "cuda")
         self.params = make_params(n, box, p, precision, sort_interval, nbr_capacity,
-                                  cell_capacity, lanes)
+                                  cell_capacity, lanes, cell_split)
         self.n = int(n)
         self.box = np.asarray(box, dtype=np.float64)
         _check(check_params(self.params))
         size = workspace_size(self.params)
         if nbr_capacity_max > 0:
-            room = make_params(n, box, p, precision, sort_interval, nbr_capacity_max, cell_capacity, lanes)
+            room = make_params(n, box, p, precision, sort_interval, nbr_capacity_max, cell_capacity, lanes,
+                               cell_split)
             size = max(size, workspace_size(room))
         self.workspace = torch.empty(size, dtype=torch.uint8, device=self.device)
         self.stream = torch.cuda.current_stream(self.device)
@@ -431,10 +432,10 @@ class System:
 
 def autotune(n: int, box, p, x, v, species, precision: int = FP32_DS, steps: int = 20,
              cache_path: str | None = None, sort_interval: int = 100) -> dict:
-    """Time every force-gather shape on this state and return the fastest
-    (lanes) with a list capacity sized from the longest list seen; a cached
-    result (same device, precision, species count, size and density) is
-    returned without timing."""
+    """Time every cell size (cell_split 1, 2) and force-gather shape (lanes)
+    on this state and return the fastest pair with a list capacity sized
+    from the longest list seen; a cached result (same device, precision,
+    species count, size and density) is returned without timing."""
     import torch
     params = make_params(n, box, p, precision, sort_interval)
     _check(check_params(params))
@@ -449,13 +450,14 @@ def autotune(n: int, box, p, x, v, species, precision: int = FP32_DS, steps: int
                              C.c_void_p(stream.cuda_stream), int(steps),
                              cache_path.encode() if cache_path else None, C.byref(out))
     _check(code)
-    return {"lanes": out.lanes, "nbr_capacity": out.nbr_capacity, "cell_capacity": out.cell_capacity,
-            "max_fill": out.max_fill, "ms_per_step": out.ms_per_step, "from_cache": bool(out.from_cache)}
+    return {"lanes": out.lanes, "cell_split": out.cell_split, "nbr_capacity": out.nbr_capacity,
+            "cell_capacity": out.cell_capacity, "max_fill": out.max_fill, "ms_per_step": out.ms_per_step,
+            "from_cache": bool(out.from_cache)}
 
 
 def autotune_batch(sizes, edges, p, x, v, species, steps: int = 20, cache_path: str | None = None,
                    sort_interval: int = 100) -> dict:
-    """ljmd_batch_autotune: time every force-gather shape on the whole batch
+    """ljmd_batch_autotune: time every cell size and force-gather shape on the whole batch
     (systems of the given sizes and cubic box edges, state concatenated as
     for Batch.set_state) and return the fastest with a list capacity sized
     from the longest list of any system; cached like autotune()."""
@@ -478,8 +480,9 @@ def autotune_batch(sizes, edges, p, x, v, species, steps: int = 20, cache_path: 
                                    cache_path.encode() if cache_path else None, C.byref(out))
     if code != 0:
         raise LJMDError(code, lib.ljmd_batch_last_error(None).decode())
-    return {"lanes": out.lanes, "nbr_capacity": out.nbr_capacity, "cell_capacity": out.cell_capacity,
-            "max_fill": out.max_fill, "ms_per_step": out.ms_per_step, "from_cache": bool(out.from_cache)}
+    return {"lanes": out.lanes, "cell_split": out.cell_split, "nbr_capacity": out.nbr_capacity,
+            "cell_capacity": out.cell_capacity, "max_fill": out.max_fill, "ms_per_step": out.ms_per_step,
+            "from_cache": bool(out.from_cache)}
 
 
 def brute_forces(n: int, box, p, x, species, precision: int = FP64):
@@ -533,7 +536,7 @@ class Batch:
     """
 
     def __init__(self, sizes, edges, p, sort_interval: int = 100, nbr_capacity: int = 0,
-                 cell_capacity: int = 0, lanes: int = 0, device=None):
+                 cell_capacity: int = 0, lanes: int = 0, device=None, cell_split: int = 0):
         import torch
         self.torch = torch
         if not torch.cuda.is_available():
@@ -547,7 +550,7 @@ class Batch:
         self.ntot = int(self.sizes.sum())
         self.offsets = np.concatenate([[0], np.cumsum(self.sizes)])
         self.params = make_params(int(self.sizes[0]), [self.edges[0]] * 3, p, FP32_DS, sort_interval,
-                                  nbr_capacity, cell_capacity, lanes)
+                                  nbr_capacity, cell_capacity, lanes, cell_split)
         self.desc = (SystemDesc * self.nsys)(*[SystemDesc(int(n), float(L))
                                                for n, L in zip(self.sizes, self.edges)])
         size = int(lib.ljmd_batch_workspace_size(C.byref(self.params), self.desc, self.nsys))

@@ -67,7 +67,7 @@ def test_valid_params_and_workspace():
 @pytest.mark.parametrize("field,value,code", [
     ("n", 1, -1), ("n", 0, -1), ("nspecies", 3, -1), ("precision", 7, -1), ("dt", 0.0, -1),
     ("dt", float("nan"), -1), ("skin", -0.1, -1), ("sort_interval", -1, -1),
-    ("nbr_capacity", -5, -1), ("lanes", 3, -1), ("reserved", 1, -1), ("cell_capacity", 769, -1),
+    ("nbr_capacity", -5, -1), ("lanes", 3, -1), ("cell_split", 3, -1), ("cell_split", -1, -1), ("cell_capacity", 769, -1),
     ("box", (4.0, 13.4, 13.4), -4), ("box", (0.0, 13.4, 13.4), -1), ("mass", (0.0, 1.0), -1),
     ("sigma", (0.0, 1.0, 1.0, 1.0), -1),
 ])

@@ -49,10 +49,11 @@ def make_batch(ljmd, ws, **kw):
     return b
 
 
-def test_batch_matches_single_boxes_bitwise(ljmd, replicas):
+@pytest.mark.parametrize("cell_split", [1, 2])
+def test_batch_matches_single_boxes_bitwise(ljmd, replicas, cell_split):
     import torch
     ws = replicas
-    b = make_batch(ljmd, ws, sort_interval=50)
+    b = make_batch(ljmd, ws, sort_interval=50, cell_split=cell_split)
     b.run(60)
     b.run(75)                       # crosses resorts at steps 50 and 100
     xb, vb, ib = b.get_state()
@@ -61,7 +62,7 @@ def test_batch_matches_single_boxes_bitwise(ljmd, replicas):
     b.sync()
     off = np.concatenate([[0], np.cumsum([w.n for w in ws])])
     for k, w in enumerate(ws):
-        s = ljmd.System(w.n, w.box, w.params, precision=FP32, sort_interval=50)
+        s = ljmd.System(w.n, w.box, w.params, precision=FP32, sort_interval=50, cell_split=cell_split)
         s.set_state(w.x, w.v, w.species)
         s.run(60, observe=False)
         s.run(75, observe=False)

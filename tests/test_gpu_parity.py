@@ -114,6 +114,48 @@ def test_neighbor_sets_exact(ljmd, case, prec):
         assert set(ids[i, : cnt[i]].tolist()) == set(on[i, : oc[i]].tolist()), (name, i)
 
 
+HALF_CELL_CASES = [c for c in CASES if c[0] in ("random777", "random256_2cells", "mixture1500",
+                                                 "fcc8x8x6_noncubic_mixture")]
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("case", HALF_CELL_CASES, ids=[c[0] for c in HALF_CELL_CASES])
+def test_half_size_cells_lists_and_forces(ljmd, case, prec):
+    # Cells of edge >= r_L / 2 and the 125-cell stencil (taken in two parts
+    # of at most 64 cells; random256 has 4 cells per axis, fewer than the
+    # stencil's 5, so each of its cells is visited once): the same neighbour
+    # sets and the same forces as the oracle.
+    name, x, v, sp, box, p = case
+    s = make_system(ljmd, x, v, sp, box, p, prec, cell_split=2)
+    nc = ljmd.cell_grid(s.params)
+    print(f"half cells {name}: grid {nc}", flush=True)
+    cnt, ids = s.neighbors(cap=256)
+    s.sync()
+    cnt, ids = cnt.cpu().numpy(), ids.cpu().numpy()
+    oc, on = oracle.build_lists(x, sp, box, p, mode=0 if prec == FP64 else 1)
+    assert np.array_equal(cnt, oc)
+    for i in range(len(x)):
+        assert set(ids[i, : cnt[i]].tolist()) == set(on[i, : oc[i]].tolist()), (name, i)
+    f = s.forces().cpu().numpy()
+    o = s.observables()
+    U, Wv = check_forces(f"{name} half cells prec={prec}", f, x, sp, box, p, prec)
+    eu, ew = energy_errors(f"{name} half cells prec={prec}", o, U, Wv, len(x))
+    assert eu <= TOL_E[prec] and ew <= TOL_E[prec]
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_half_size_cells_trajectory(ljmd, prec):
+    # 100 steps with resorts every 25 on the 125-cell stencil: the oracle's
+    # trajectory to the same bounds as with full-size cells.
+    w = W.config_small()
+    s, obs, xu, v = _trajectory(ljmd, w, prec, 100, sort_interval=25, cell_split=2)
+    r = oracle.run_nve(w.x, w.v, w.species, w.box, w.params, 100)
+    dx = np.abs(xu - r["x"]).max()
+    dv = np.abs(v - r["v"]).max()
+    tol_x, tol_v = (1e-10, 1e-9) if prec == FP64 else (1e-4, 1e-3)
+    assert dx <= tol_x and dv <= tol_v, (dx, dv)
+
+
 def list_radius_ties(nspecies, seed):
     """Sparse cubic box of partner pairs at the list radius of their pair type
     times (1 + delta), delta from -3e-7 to 3e-7 (a few units of the FP32

@@ -1,6 +1,7 @@
-"""The autotuner through the C ABI: it times every force-gather shape on the
-device, returns the fastest with a list capacity above the longest list seen,
-caches the result and reads it back; a system built with the tuned shape and
+"""The autotuner through the C ABI: it times every cell size (cells of edge
+>= r_L or >= r_L / 2) and force-gather shape on the device, returns the
+fastest pair with a list capacity above the longest list seen, caches the
+result and reads it back; a system built with the tuned cell size, shape and
 capacity gives the forces of the oracle."""
 import pytest
 
@@ -25,16 +26,17 @@ def test_autotune_times_caches_and_runs(ljmd, tmp_path):
     cache = str(tmp_path / "tune.jsonl")
     t = ljmd.autotune(w.n, w.box, w.params, w.x, w.v, w.species, steps=10, cache_path=cache)
     print("tuned", t, flush=True)
-    assert t["lanes"] in (1, 2, 4, 8, 16)
+    assert t["lanes"] in (1, 2, 4, 8, 16) and t["cell_split"] in (1, 2)
     assert t["ms_per_step"] > 0.0 and not t["from_cache"]
     assert t["max_fill"] > 0 and t["nbr_capacity"] >= t["max_fill"] + 16 and t["nbr_capacity"] % 16 == 0
     again = ljmd.autotune(w.n, w.box, w.params, w.x, w.v, w.species, steps=10, cache_path=cache)
     assert again["from_cache"]
-    assert {k: again[k] for k in ("lanes", "nbr_capacity", "max_fill")} == \
-           {k: t[k] for k in ("lanes", "nbr_capacity", "max_fill")}
+    assert {k: again[k] for k in ("lanes", "cell_split", "nbr_capacity", "max_fill")} == \
+           {k: t[k] for k in ("lanes", "cell_split", "nbr_capacity", "max_fill")}
     with open(cache) as fh:
         assert len(fh.readlines()) == 1
-    s = ljmd.System(w.n, w.box, w.params, lanes=t["lanes"], nbr_capacity=t["nbr_capacity"])
+    s = ljmd.System(w.n, w.box, w.params, lanes=t["lanes"], nbr_capacity=t["nbr_capacity"],
+                    cell_split=t["cell_split"])
     s.set_state(w.x, w.v, w.species)
     s.run(50, observe=False)
     s.sync()
@@ -58,11 +60,14 @@ def test_batch_autotune_times_caches_and_runs(ljmd, tmp_path):
     cache = str(tmp_path / "tune_batch.jsonl")
     t = ljmd.autotune_batch(sizes, edges, ws[0].params, x, v, sp, steps=10, cache_path=cache)
     print("tuned batch", t, flush=True)
-    assert t["lanes"] in (1, 2, 4, 8, 16) and t["ms_per_step"] > 0.0 and not t["from_cache"]
+    assert t["lanes"] in (1, 2, 4, 8, 16) and t["cell_split"] in (1, 2)
+    assert t["ms_per_step"] > 0.0 and not t["from_cache"]
     assert t["max_fill"] > 0 and t["nbr_capacity"] >= t["max_fill"] + 16 and t["nbr_capacity"] % 16 == 0
     again = ljmd.autotune_batch(sizes, edges, ws[0].params, x, v, sp, steps=10, cache_path=cache)
     assert again["from_cache"] and again["lanes"] == t["lanes"] and again["nbr_capacity"] == t["nbr_capacity"]
-    b = ljmd.Batch(sizes, edges, ws[0].params, lanes=t["lanes"], nbr_capacity=t["nbr_capacity"])
+    assert again["cell_split"] == t["cell_split"]
+    b = ljmd.Batch(sizes, edges, ws[0].params, lanes=t["lanes"], nbr_capacity=t["nbr_capacity"],
+                   cell_split=t["cell_split"])
     b.set_state(x, v, sp)
     assert 0 < b.max_fill() <= t["nbr_capacity"]
     f = b.forces().cpu().numpy()
