@@ -20,6 +20,7 @@ constexpr int kWave = 64;        // CDNA wavefront width
 constexpr int kBlock = 1024;     // threads per block of the per-particle kernels
 constexpr int kBlockF64 = 256;   // threads per block of the FP64 step kernel (register-heavy)
 __host__ __device__ constexpr int step_block_threads(int prec) { return prec == LJMD_FP64 ? kBlockF64 : kBlock; }
+constexpr int kApFinishBlock = 64;  // threads per block of the all-pairs step tail (one wavefront)
 constexpr int kRing = 64;        // steps of block partials kept before an observable flush
 constexpr int kNP = 8;           // doubles per partial row: U, W, K, px, py, pz, -, -
 

@@ -167,10 +167,13 @@ __global__ __launch_bounds__(kApWaves * kWave) void k_ap_forces(ApForce a, const
     }
 }
 
+// One wavefront per block: a small system spreads its step tail over many
+// compute units, and every lane issues the loads of four split rows before
+// it adds them (in split order).
 template <int PREC, bool TH>
-__global__ __launch_bounds__(kBlock) void k_ap_finish(StepArgs a, const void *part, int nsplit) {
+__global__ __launch_bounds__(kApFinishBlock) void k_ap_finish(StepArgs a, const void *part, int nsplit) {
     using F = typename ApRow<PREC>::F;
-    constexpr int BS = PREC == LJMD_FP64 ? kBlockF64 : kBlock;
+    constexpr int BS = kApFinishBlock;
     Ctl *ctl = a.st.ctl;
     if (halted_record(ctl, a.step, blockIdx.x == 0)) return;
     const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
@@ -182,7 +185,25 @@ __global__ __launch_bounds__(kBlock) void k_ap_finish(StepArgs a, const void *pa
     if (i < a.g.n) {
         F f = pf[i];
         double2 ew = pe[i];
-        for (int s = 1; s < nsplit; ++s) {
+        int s = 1;
+        for (; s + 4 <= nsplit; s += 4) {
+            F g[4];
+            double2 h[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                g[u] = pf[(size_t)(s + u) * stride + i];
+                h[u] = pe[(size_t)(s + u) * stride + i];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                f.x += g[u].x;
+                f.y += g[u].y;
+                f.z += g[u].z;
+                ew.x += h[u].x;
+                ew.y += h[u].y;
+            }
+        }
+        for (; s < nsplit; ++s) {
             const F g = pf[(size_t)s * stride + i];
             const double2 h = pe[(size_t)s * stride + i];
             f.x += g.x;
@@ -214,7 +235,7 @@ int allpairs_splits(int64_t n) {
 // Bytes of the partial rows for n particles: S rows of (forces, e and w)
 // per finish-kernel slot.
 size_t allpairs_part_bytes(int64_t n, int prec) {
-    const int bs = step_block_threads(prec);
+    const int bs = kApFinishBlock;
     const size_t slots = (size_t)((n + bs - 1) / bs) * bs;
     const size_t row = (prec == LJMD_FP64 ? sizeof(double4) : sizeof(float4)) + sizeof(double2);
     return (size_t)allpairs_splits(n) * slots * row;
@@ -234,7 +255,7 @@ hipError_t launch_allpairs_step(const Launch &L, int64_t step, int mode, int slo
     a.step = step;
     void *part = L.st->nbr;  // the list area holds the partial rows in this mode
     const int S = allpairs_splits(L.g->n);
-    const int bs = step_block_threads(L.g->prec);
+    const int bs = kApFinishBlock;
     ApForce af;
     af.rec = L.g->prec == LJMD_FP64 ? (const void *)L.st->rec64[L.cur] : (const void *)L.st->recq[L.cur];
     af.part = part;

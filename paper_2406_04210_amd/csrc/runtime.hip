@@ -223,7 +223,7 @@ Plan make_plan(const ljmd_params *p) {
         pl.cap = 16;
         pl.cap_reserve = std::max<int32_t>(
             16, round_up((int32_t)((pb + sizeof(int32_t) * pl.npad - 1) / (sizeof(int32_t) * pl.npad)), 16));
-        pl.max_blocks = (int)((p->n + step_block_threads(p->precision) - 1) / step_block_threads(p->precision));
+        pl.max_blocks = (int)((p->n + kApFinishBlock - 1) / kApFinishBlock);
         lay_out(pl, p->precision, 1);
         return pl;
     }
