@@ -35,9 +35,9 @@ HBM_PEAK_GBS = 8000.0
 # 512 MiB copy reads), valid only for the kernel sources they were taken on.
 STEP_KERNEL_SOURCES = ("k_step.hip", "step_common.h", "internal.h")
 STEP_KERNEL_TRAFFIC = {
-    "sources_sha256": "7305e8bd5ae35a85713eaeede9aa45839f57995eac8876dfd179856c0d2b1bc1",
-    "fetch_bytes": 2.0 * 54936 * 1024,
-    "write_bytes": 1.0 * 20035 * 1024,
+    "sources_sha256": "df61bafd2317e3a488aae06600d82bf15862ea1f156a1878e33217b606f3b362",
+    "fetch_bytes": 2.0 * 53444 * 1024,
+    "write_bytes": 1.0 * 16035 * 1024,
 }
 
 
@@ -73,12 +73,12 @@ def algorithmic_bytes_per_particle(mean_list: float) -> float:
 
 def layout_bytes_per_particle(prec: int, mean_list: float) -> float:
     """Bytes the step kernel's data layout moves per particle-step: the list
-    and its length, the state arrays as stored read and written (FP32+DS:
-    double-single position and velocity in three float4 words; FP64: the
-    own record and the padded velocity), the new record, and the reference
-    position with the species in its last word."""
-    if prec == 1:   # FP32 + double-single: three unpadded state words, no own-record read
-        own_rec, state_rw, rec_out, xref = 0, 2 * 48, 16, 16
+    and its length, the own record, the state arrays as stored read and
+    written (FP32+DS: double-single position and velocity in three float4
+    words; FP64: the padded velocity), the new record, and the reference
+    position."""
+    if prec == 1:   # FP32 + double-single: three unpadded state words
+        own_rec, state_rw, rec_out, xref = 16, 2 * 48, 16, 16
     else:           # FP64: the own record is the position
         own_rec, state_rw, rec_out, xref = 32, 2 * 32, 32, 16
     return 4.0 * mean_list + 4.0 + own_rec + state_rw + rec_out + xref
