@@ -58,7 +58,8 @@ def build(verbose: bool = False) -> str:
 
 
 class OThermo(C.Structure):
-    _fields_ = [("temperature", C.c_double), ("rate", C.c_double), ("seed", C.c_uint64)]
+    _fields_ = [("temperature", C.c_double), ("rate", C.c_double), ("seed", C.c_uint64),
+                ("dim", C.c_int32), ("pad", C.c_int32)]
 
 
 class OLJ(C.Structure):
@@ -247,7 +248,8 @@ def kinetic(v, species, params):
 def run_nve(x, v, species, box, params, nsteps: int, want_obs: bool = True, thermostat=None,
             want_sig: bool = False):
     """Velocity-Verlet NVE (or, with ``thermostat=(T, rate, seed)``, with the
-    Andersen-like thermostat). Returns dict with x, v (unwrapped, final),
+    Andersen-like thermostat; in a two-dimensional system (params.dim == 2,
+    z = 0) the resampled v_z is 0). Returns dict with x, v (unwrapped, final),
     f (final forces), obs ((nsteps+1, 6): U, K, W, px, py, pz), builds,
     seconds (wall time of the whole call), loop_seconds (wall time of the
     step loop alone, after the initial list build and forces), sig
@@ -262,7 +264,8 @@ def run_nve(x, v, species, box, params, nsteps: int, want_obs: bool = True, ther
     s = make_params(params)
     th = None
     if thermostat is not None:
-        th = OThermo(float(thermostat[0]), float(thermostat[1]), int(thermostat[2]))
+        dim = int(thermostat[3]) if len(thermostat) > 3 else int(getattr(params, "dim", 3))
+        th = OThermo(float(thermostat[0]), float(thermostat[1]), int(thermostat[2]), dim, 0)
     loop = C.c_double(0.0)
     t0 = time.perf_counter()
     builds = lib().oracle_run_nve(n, _d(x), _d(v), _i(sp), _d(bx), C.byref(s), int(nsteps),

@@ -477,6 +477,8 @@ typedef struct {
     double temperature;
     double rate;
     uint64_t seed;
+    int32_t dim;    /* 2: motion in the x-y plane (a resampled v_z is 0); else 3 */
+    int32_t pad;
 } othermo_t;
 
 /* Collision threshold: a particle collides in a step iff its first draw u0
@@ -641,6 +643,7 @@ int64_t oracle_run_nve(int64_t n, double *x, double *v, const int32_t *sp, const
                 double z[3];
                 if (!oracle_thermo_draw(thermo->seed, i, s, thr, z)) continue;
                 double sd = sqrt(thermo->temperature * invm[i]);
+                if (thermo->dim == 2) z[2] = 0.0;
                 for (int k = 0; k < 3; ++k) v[3 * i + k] = sd * z[k];
             }
         if (sig) sig[s] = cutoff_signature(n, x, sp, box, p, L.cap, L.cnt, L.nbr);

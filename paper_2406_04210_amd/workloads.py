@@ -48,11 +48,12 @@ class LJParams:
     shift_energy: int = 1
     skin: float = 0.3
     dt: float = 0.005
+    dim: int = 3
 
     def copy(self) -> "LJParams":
         return LJParams(self.nspecies, self.eps.copy(), self.sigma.copy(),
                         self.rcut.copy(), self.mass.copy(), self.shift_energy,
-                        self.skin, self.dt)
+                        self.skin, self.dt, self.dim)
 
 
 def single_species_params(rc: float = 2.5, skin: float = 0.3, dt: float = 0.005) -> LJParams:
@@ -230,6 +231,56 @@ def thermostat_fluid(n: int = 100_000, rho: float = 0.8442, temperature: float =
     p = single_species_params()
     v = maxwell_boltzmann(n, temperature, p.mass, sp, rng)
     return Workload(f"thermostat_fluid_n{n}_T{temperature:g}", x, v, sp, np.full(3, L), p, steps, temperature)
+
+
+def triangular_lattice(m: int, rho: float) -> tuple[np.ndarray, np.ndarray]:
+    """Two-dimensional triangular lattice of 2 m^2 sites (rectangular cell of
+    two sites, m x m cells) at number density rho per unit area, in the
+    plane z = 0. Returns (positions (2 m^2, 3), box edges (Lx, Ly, Lx)); the
+    box is periodic in x and y (the third edge only sizes the unused z axis)."""
+    a = math.sqrt(2.0 / (math.sqrt(3.0) * rho))      # nearest-neighbour distance
+    bx, by = a, a * math.sqrt(3.0)                   # rectangular cell with 2 sites
+    idx = np.arange(m, dtype=np.float64)
+    gx, gy = np.meshgrid(idx, idx, indexing="ij")
+    base = np.stack([gx.ravel() * bx, gy.ravel() * by], axis=1)
+    sites = np.concatenate([base, base + np.array([0.5 * bx, 0.5 * by])], axis=0)
+    x = np.zeros((sites.shape[0], 3))
+    x[:, :2] = sites
+    L = np.array([m * bx, m * by, m * bx])
+    return x, L
+
+
+def maxwell_boltzmann_2d(n: int, temperature: float, mass: np.ndarray, species: np.ndarray,
+                         rng: np.random.Generator) -> np.ndarray:
+    """In-plane velocities from N(0, T/m) per component, net momentum
+    removed, rescaled so that sum m v^2 / (2N - 2) equals T; v_z = 0."""
+    m = mass[species][:, None]
+    v = np.zeros((n, 3))
+    v[:, :2] = rng.standard_normal((n, 2)) * np.sqrt(temperature / m)
+    p = (m * v).sum(axis=0) / m.sum()
+    v -= p[None, :]
+    v[:, 2] = 0.0
+    t_now = (m * v * v).sum() / (2 * n - 2)
+    v *= math.sqrt(temperature / t_now)
+    return np.ascontiguousarray(v)
+
+
+def lj_fluid_2d(m: int = 32, rho: float = 0.7, temperature: float = 1.0, seed_index: int = 3,
+                jitter: float = 0.05, steps: int = 100) -> Workload:
+    """Two-dimensional LJ fluid (the dimension template of the paper's
+    modules, Sec. 3): a triangular lattice of 2 m^2 sites at areal density
+    rho with a seeded Gaussian jitter in the plane, Maxwell-Boltzmann
+    velocities in the plane; cutoff 2.5 shifted, skin 0.3, dt 0.005."""
+    rng = config_rng(seed_index)
+    x, L = triangular_lattice(m, rho)
+    x[:, :2] += jitter * rng.standard_normal((x.shape[0], 2))
+    x[:, :2] %= L[:2]
+    n = x.shape[0]
+    sp = np.zeros(n, dtype=np.int32)
+    p = single_species_params()
+    p.dim = 2
+    v = maxwell_boltzmann_2d(n, temperature, p.mass, sp, rng)
+    return Workload(f"lj2d_tri{m}_n{n}", np.ascontiguousarray(x), v, sp, L, p, steps, temperature)
 
 
 def random_dense(n: int, rho: float, seed: int, min_dist: float = 0.85,
