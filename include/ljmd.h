@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define LJMD_ABI_VERSION 7
+#define LJMD_ABI_VERSION 8
 
 enum ljmd_status {
     LJMD_OK = 0,
@@ -97,6 +97,16 @@ typedef struct ljmd_params {
                                list build: 1 (cell edge >= r_L, 27-cell stencil) or 2 (edge
                                >= r_L / 2, 125-cell stencil); 0 = 1. The lists are the
                                same sets either way; ljmd_autotune times both */
+    int32_t dim;            /* 3 (0 = 3) or 2 (the paper's modules take the dimension as a
+                               template parameter, Sec. 3): with 2 the particles move in the
+                               x-y plane; the z coordinates and velocities a caller passes
+                               are taken as 0 and come back as 0, box[2] is no period of
+                               the system but must still be a valid edge (>= 2 list radii;
+                               pass box[0] for a square box so that the fixed-point fast
+                               path applies), T = 2K/(2N-2), P = rho T + W/(2A) with the
+                               area A = box[0] box[1]. The gradient calls and batches are
+                               three-dimensional only */
+    int32_t pad;            /* must be 0 */
 } ljmd_params;
 
 /* Per-step observable row written by ljmd_run into a device array:

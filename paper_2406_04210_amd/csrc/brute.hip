@@ -83,8 +83,9 @@ int ljmd_brute_forces(const ljmd_params *p, const double *x, const int32_t *spec
     BoxC box;
     PairC pc;
     box_pair_constants(*p, box, pc);
-    const hipError_t e = launch_brute(box, pc, p->precision, p->nspecies, cut_of(p) ? 1 : 0, p->n, x, species, f, uw,
-                                      (uint8_t *)ws, (hipStream_t)stream);
+    const int dim = p->dim == 2 ? 2 : 3;
+    const hipError_t e = launch_brute(box, pc, p->precision, p->nspecies, dim, cut_of(p) ? 1 : 0, p->n, x, species,
+                                      f, uw, (uint8_t *)ws, (hipStream_t)stream);
     if (e != hipSuccess) return brute_fail(LJMD_EHIP, hipGetErrorString(e));
     return LJMD_OK;
 }
@@ -110,8 +111,9 @@ int ljmd_brute_forces_noalloc(const ljmd_params *p, const double *x, const int32
     BoxC box;
     PairC pc;
     box_pair_constants(*p, box, pc);
-    const hipError_t e = launch_brute(box, pc, p->precision, p->nspecies, cut_of(p) ? 1 : 0, p->n, x, species, f, uw,
-                                      ptr, (hipStream_t)stream);
+    const int dim = p->dim == 2 ? 2 : 3;
+    const hipError_t e = launch_brute(box, pc, p->precision, p->nspecies, dim, cut_of(p) ? 1 : 0, p->n, x, species,
+                                      f, uw, ptr, (hipStream_t)stream);
     if (e != hipSuccess) return brute_fail(LJMD_EHIP, hipGetErrorString(e));
     return LJMD_OK;
 }

@@ -145,7 +145,7 @@ struct Geom {
     int32_t max_blocks;   // rows per ring slot of partials
     int32_t ncu;          // compute units of the device (grid of the per-step rebuild kernels)
     int32_t all_pairs;    // 1: untruncated all-pairs interaction (no lists, no cells)
-    int32_t pad_;
+    int32_t dim;          // 2 (motion in the x-y plane, z and v_z held at 0) or 3
 };
 
 // ------------------------------------------------------------------------
@@ -389,7 +389,7 @@ hipError_t launch_allpairs_step(const Launch &L, int64_t step, int mode, int slo
 // brute_scratch_bytes(n, prec) bytes (256-byte aligned); cut: truncate and
 // shift at r_c (else every pair interacts). f (n*3) and uw (U, W) are FP64.
 size_t brute_scratch_bytes(int64_t n, int prec);
-hipError_t launch_brute(const BoxC &box, const PairC &pc, int prec, int nspecies, int cut, int64_t n,
+hipError_t launch_brute(const BoxC &box, const PairC &pc, int prec, int nspecies, int dim, int cut, int64_t n,
                         const double *x, const int32_t *sp, double *f, double *uw, uint8_t *scratch,
                         hipStream_t stream);
 // Box and pair constants of a parameter set (cell grid 1x1x1), and the

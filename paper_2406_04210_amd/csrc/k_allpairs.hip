@@ -216,7 +216,8 @@ __global__ __launch_bounds__(kApFinishBlock) void k_ap_finish(StepArgs a, const 
             finish_fp64<TH>(a, a.box, i, a.st.rec64[a.cur][i], f.x, f.y, f.z, ew.x, ew.y, pu, pw, pk, ppx, ppy, ppz,
                             dm);
         else
-            finish_ds<true, TH, PREC == LJMD_FP32>(a, a.box, i, a.st.recq[a.cur][i].w, a.st.xref[i], f.x, f.y, f.z,
+            finish_ds<true, TH, PREC == LJMD_FP32>(a, a.box, i, a.st.recq[a.cur][i].w, a.st.xref[i],
+                                                   ds_load(a.st.dsw, i), f.x, f.y, f.z,
                                                    ew.x, ew.y,
                                                    pu, pw, pk, ppx, ppy, ppz, dm);
     }
@@ -295,14 +296,14 @@ hipError_t launch_allpairs_step(const Launch &L, int64_t step, int mode, int slo
 // record (single floats with zero lo parts for the plain FP32 state).
 template <int PREC>
 __global__ __launch_bounds__(kBlock) void k_bf_records(const double *__restrict__ x, const int32_t *__restrict__ sp,
-                                                       int64_t n, int nspecies, BoxC box, void *rec) {
+                                                       int64_t n, int nspecies, int dim, BoxC box, void *rec) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     int s = sp[i];
     s = s < 0 ? 0 : (s >= nspecies ? nspecies - 1 : s);
     double w[3];
     for (int k = 0; k < 3; ++k) {
-        const double xi = x[3 * i + k];
+        const double xi = (k == 2 && dim == 2) ? 0.0 : x[3 * i + k];  // two dimensions: z = 0
         double t = xi - box.L[k] * floor(xi / box.L[k]);
         if (t >= box.L[k]) t -= box.L[k];
         w[k] = t;
@@ -421,7 +422,7 @@ static BruteScratch brute_layout(int64_t n, int prec) {
 
 size_t brute_scratch_bytes(int64_t n, int prec) { return brute_layout(n, prec).total; }
 
-hipError_t launch_brute(const BoxC &box, const PairC &pc, int prec, int nspecies, int cut, int64_t n,
+hipError_t launch_brute(const BoxC &box, const PairC &pc, int prec, int nspecies, int dim, int cut, int64_t n,
                         const double *x, const int32_t *sp, double *f, double *uw, uint8_t *scratch,
                         hipStream_t stream) {
     const BruteScratch bl = brute_layout(n, prec);
@@ -439,7 +440,7 @@ hipError_t launch_brute(const BoxC &box, const PairC &pc, int prec, int nspecies
     const Ctl *none = nullptr;
 #define BF(PREC)                                                                                              \
     do {                                                                                                      \
-        hipLaunchKernelGGL(k_bf_records<PREC>, gr, b1, 0, stream, x, sp, n, nspecies, box, scratch);        \
+        hipLaunchKernelGGL(k_bf_records<PREC>, gr, b1, 0, stream, x, sp, n, nspecies, dim, box, scratch);   \
         if (nspecies == 2 && cut)                                                                             \
             hipLaunchKernelGGL((k_ap_forces<PREC, 2, true>), gf, bf, 0, stream, af, none);                   \
         else if (nspecies == 2)                                                                               \

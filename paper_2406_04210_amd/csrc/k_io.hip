@@ -21,7 +21,8 @@ __device__ inline void set_one(const State &st, const Geom &g, const BoxC &box, 
     double w[3];
     int im[3];
     for (int k = 0; k < 3; ++k) {
-        const double xi = x[3 * row + k];
+        // Two dimensions: z is held at 0 whatever the caller passed.
+        const double xi = (k == 2 && g.dim == 2) ? 0.0 : x[3 * row + k];
         double f = floor(xi / box.L[k]);
         double t = xi - box.L[k] * f;
         if (t >= box.L[k]) {
@@ -33,7 +34,7 @@ __device__ inline void set_one(const State &st, const Geom &g, const BoxC &box, 
     }
     st.img[i] = make_int4(im[0], im[1], im[2], 0);
     st.id[i] = (int32_t)row;
-    const double vx = v[3 * row], vy = v[3 * row + 1], vz = v[3 * row + 2];
+    const double vx = v[3 * row], vy = v[3 * row + 1], vz = g.dim == 2 ? 0.0 : v[3 * row + 2];
     if constexpr (PREC == LJMD_FP64) {
         st.rec64[cur][i] = make_double4(w[0], w[1], w[2], (double)s);
         st.vel64[i] = make_double4(vx, vy, vz, 0.0);

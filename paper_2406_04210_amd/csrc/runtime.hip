@@ -159,6 +159,8 @@ int validate(const ljmd_params *p, std::string *why) {
     if (p->lanes != 0 && p->lanes != 1 && p->lanes != 2 && p->lanes != 4 && p->lanes != 8 && p->lanes != 16)
         return bad("lanes must be 0, 1, 2, 4, 8 or 16");
     if (p->cell_split < 0 || p->cell_split > 2) return bad("cell_split must be 0, 1 or 2");
+    if (p->dim != 0 && p->dim != 2 && p->dim != 3) return bad("dim must be 0, 2 or 3");
+    if (p->pad != 0) return bad("pad must be 0");
     if (all_pairs(p)) {
         // Minimum image of every pair; the single-precision paths work in
         // fixed-point quanta of a cubic box.
@@ -178,12 +180,17 @@ int validate(const ljmd_params *p, std::string *why) {
 // Cells per list radius along each axis (ljmd_params.cell_split).
 int cell_split(const ljmd_params *p) { return p->cell_split == 2 ? 2 : 1; }
 
+// Spatial dimension of a parameter set (0 reads as 3).
+int dim_of(const ljmd_params *p) { return p->dim == 2 ? 2 : 3; }
+
 void grid_dims(const ljmd_params *p, int nc[3]) {
     const double edge = list_radius_max(p) / cell_split(p);
     for (int k = 0; k < 3; ++k) {
         double f = std::floor(p->box[k] / (edge * (1.0 + 1e-6)));
         nc[k] = (int)std::max(1.0, std::min(f, 1024.0));
     }
+    // In two dimensions every particle sits at z = 0: one layer of cells.
+    if (dim_of(p) == 2) nc[2] = 1;
 }
 
 struct Plan {
@@ -832,8 +839,8 @@ int batch_geom(const ljmd_params *shared, const ljmd_system *ys, int32_t nsys, B
         bg.why = "batch: NULL argument or nsys outside [1, 65536]";
         return LJMD_EINVAL;
     }
-    if (shared->nspecies != 1 || shared->precision != LJMD_FP32_DS || all_pairs(shared)) {
-        bg.why = "batch: one species and the FP32 + double-single path only";
+    if (shared->nspecies != 1 || shared->precision != LJMD_FP32_DS || all_pairs(shared) || dim_of(shared) != 3) {
+        bg.why = "batch: one species, three dimensions and the FP32 + double-single path only";
         return LJMD_EINVAL;
     }
     bg.sys.resize(nsys);
@@ -1065,6 +1072,7 @@ int ljmd_create(const ljmd_params *p, void *ws, size_t bytes, void *stream, ljmd
     g.prec = p->precision;
     g.max_blocks = pl.max_blocks;
     g.all_pairs = all_pairs(p) ? 1 : 0;
+    g.dim = dim_of(p);
     g.ncu = 256;
     if (c->device >= 0) {
         int ncu = 0;
@@ -1300,15 +1308,16 @@ int ljmd_observables(ljmd_ctx *c, ljmd_obs *out) {
     hipError_t e = hipMemcpy(&h, c->st.ctl, sizeof h, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(c, e, "read observables");
     const double n = (double)c->p.n;
-    const double vol = c->p.box[0] * c->p.box[1] * c->p.box[2];
+    const double d = (double)c->g.dim;
+    const double vol = c->g.dim == 2 ? c->p.box[0] * c->p.box[1] : c->p.box[0] * c->p.box[1] * c->p.box[2];
     out->U = h.last[0];
     out->K = h.last[1];
     out->W = h.last[2];
     out->p[0] = h.last[3];
     out->p[1] = h.last[4];
     out->p[2] = h.last[5];
-    out->T = 2.0 * out->K / (3.0 * n - 3.0);
-    out->P = n / vol * out->T + out->W / (3.0 * vol);
+    out->T = 2.0 * out->K / (d * n - d);
+    out->P = n / vol * out->T + out->W / (d * vol);
     out->E = out->U + out->K;
     out->step = c->step;
     out->rebuilds = h.rebuilds;
@@ -1352,6 +1361,7 @@ int ljmd_set_pair_params(ljmd_ctx *c, const double eps[4], const double sigma[4]
 int ljmd_force_vjp(ljmd_ctx *c, const double *g, double *gx, double *gtheta) {
     if (!c) return LJMD_EINVAL;
     if (c->g.all_pairs) return fail(c, LJMD_EINVAL, "force_vjp: not available for the all-pairs interaction");
+    if (c->g.dim != 3) return fail(c, LJMD_EINVAL, "force_vjp: three dimensions only");
     if (!c->have_state) return fail(c, LJMD_ESTATE, "force_vjp before set_state");
     if (!g || !gx || !gtheta) return fail(c, LJMD_EINVAL, "force_vjp: NULL array");
     // Scratch: the FP64 accumulator, then the cotangent in the path precision.
@@ -1379,6 +1389,7 @@ int ljmd_force_vjp(ljmd_ctx *c, const double *g, double *gx, double *gtheta) {
 int ljmd_energy_grad(ljmd_ctx *c, double *gtheta) {
     if (!c) return LJMD_EINVAL;
     if (c->g.all_pairs) return fail(c, LJMD_EINVAL, "energy_grad: not available for the all-pairs interaction");
+    if (c->g.dim != 3) return fail(c, LJMD_EINVAL, "energy_grad: three dimensions only");
     if (!c->have_state) return fail(c, LJMD_ESTATE, "energy_grad before set_state");
     if (!gtheta) return fail(c, LJMD_EINVAL, "energy_grad: NULL array");
     hipError_t e = launch_adjoint_pairs(launcher(c), kAdjEnergy, nullptr, nullptr, 1.0, gtheta, 1);
@@ -1399,6 +1410,7 @@ int ljmd_vv_forward(ljmd_ctx *c, int32_t nsteps, int32_t ckpt_every, int32_t fla
     if (nsteps < 1 || ckpt_every < 1) return fail(c, LJMD_EINVAL, "vv_forward: nsteps and ckpt_every must be >= 1");
     if (flags & ~LJMD_ADJ_STORE_ALL) return fail(c, LJMD_EINVAL, "vv_forward: unknown flags");
     if (c->g.all_pairs) return fail(c, LJMD_EINVAL, "vv_forward: not available for the all-pairs interaction");
+    if (c->g.dim != 3) return fail(c, LJMD_EINVAL, "vv_forward: three dimensions only");
     if (c->dyn.thermo_on)
         return fail(c, LJMD_EINVAL, "vv_forward: the thermostat makes the dynamics stochastic (switch it off)");
     if (!adj_ws || ((uintptr_t)adj_ws & 255) != 0)
@@ -1827,6 +1839,7 @@ int ljmd_batch_create(const ljmd_params *shared, const ljmd_system *sys, int32_t
     g.nspecies = 1;
     g.prec = LJMD_FP32_DS;
     g.max_blocks = b->bg.nblocks;
+    g.dim = 3;
     g.ncu = 256;
     if (b->device >= 0) {
         int ncu = 0;

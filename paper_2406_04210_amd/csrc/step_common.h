@@ -157,16 +157,17 @@ __device__ inline void block_finish(const StepArgs &a, Ctl *ctl, int blk, double
 // w/2) and "integrate" of step s+1 (v' = v_s + dt/(2m) F, x_{s+1} =
 // x_s + dt v', wrapped into the box with image bookkeeping, the new
 // fixed-point record, the squared displacement from the list reference in
-// dm against the list reference xr). Double-single arithmetic, or with PLAIN
-// single floats (the lo parts stay zero).
+// dm against the list reference xr). ds_in is the slot's state as read by
+// the caller. Double-single arithmetic, or with PLAIN single floats (the lo
+// parts stay zero).
 template <bool OBS, bool TH, bool PLAIN = false>
-__device__ inline void finish_ds(const StepArgs &a, const BoxC &box, int64_t i, int si, const int4 &xr, float fx,
-                                 float fy, float fz, double e, double w, double &pu, double &pw, double &pk,
-                                 double &ppx, double &ppy, double &ppz, uint32_t &dm) {
+__device__ inline void finish_ds(const StepArgs &a, const BoxC &box, int64_t i, int si, const int4 &xr,
+                                 const DsState &ds_in, float fx, float fy, float fz, double e, double w, double &pu,
+                                 double &pw, double &pk, double &ppx, double &ppy, double &ppz, uint32_t &dm) {
     const State &st = a.st;
     const float chi = by_s(si, a.dyn.hdt_m_hi), clo = by_s(si, a.dyn.hdt_m_lo);
     const float mass = by_s(si, a.dyn.massf);
-    DsState ds = ds_load(st.dsw, i);
+    DsState ds = ds_in;
     dsf vx = ds.vx, vy = ds.vy, vz = ds.vz;
     // v += dt/(2m) F: double-single, or one float product and one float sum.
     auto kick = [&](dsf &v, float f) {
@@ -183,6 +184,7 @@ __device__ inline void finish_ds(const StepArgs &a, const BoxC &box, int64_t i, 
             double z[3];
             if (thermo_draw(a.dyn, (uint32_t)st.id[i], a.step, z)) {
                 const double sd = by_s(si, a.dyn.thermo_sd);
+                if (a.g.dim == 2) z[2] = 0.0;  // motion in the x-y plane
                 if constexpr (PLAIN) {
                     vx = dsf{(float)(sd * z[0]), 0.0f};
                     vy = dsf{(float)(sd * z[1]), 0.0f};
@@ -282,7 +284,7 @@ __device__ inline void finish_fp64(const StepArgs &a, const BoxC &box, int64_t i
                 const double sd = by_s(si, a.dyn.thermo_sd);
                 v.x = sd * z[0];
                 v.y = sd * z[1];
-                v.z = sd * z[2];
+                v.z = a.g.dim == 2 ? 0.0 : sd * z[2];
             }
         }
     }

@@ -18,7 +18,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libljmd.so")
 
-ABI_VERSION = 7
+ABI_VERSION = 8
 FP64 = 0
 FP32_DS = 1
 FP32 = 2
@@ -42,7 +42,7 @@ class Params(C.Structure):
                 ("rcut", C.c_double * 4), ("mass", C.c_double * 2), ("skin", C.c_double),
                 ("dt", C.c_double), ("sort_interval", C.c_int32), ("precision", C.c_int32),
                 ("nbr_capacity", C.c_int32), ("cell_capacity", C.c_int32), ("lanes", C.c_int32),
-                ("cell_split", C.c_int32)]
+                ("cell_split", C.c_int32), ("dim", C.c_int32), ("pad", C.c_int32)]
 
 
 class Obs(C.Structure):
@@ -174,6 +174,8 @@ def make_params(n: int, box, p, precision: int = FP32_DS, sort_interval: int = 1
     s.cell_capacity = int(cell_capacity)
     s.lanes = int(lanes)
     s.cell_split = int(cell_split)
+    s.dim = int(getattr(p, "dim", 3))
+    s.pad = 0
     return s
 
 
