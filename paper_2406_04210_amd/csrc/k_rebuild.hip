@@ -777,6 +777,7 @@ __global__ __launch_bounds__(kRbBlock) void k_batch_canon(State st, Geom g, cons
     }
 }
 
+template <int LG>
 __global__ __launch_bounds__(kNlWaves * kWave) void k_batch_nlist(State st, Geom g, const SysC *sys, BatchPlan bp,
                                                                   PairC pc) {
     const int count = bp.wl_count[0];
@@ -799,8 +800,8 @@ __global__ __launch_bounds__(kNlWaves * kWave) void k_batch_nlist(State st, Geom
         const int k = plan_find(bp.wl_coff, count, w);
         const int s = bp.wl_sys[k];
         const SysC &y = sys[s];
-        nlist_cell<LJMD_FP32_DS, 1, true>(st, g, y.box, pc, st.rank_of + y.c_off, st.cell_lin + y.c_off, y.c_off,
-                                     (int)(w - bp.wl_coff[k]), st.ctl + s, stage);
+        nlist_cell<LJMD_FP32_DS, 1, true, LG>(st, g, y.box, pc, st.rank_of + y.c_off, st.cell_lin + y.c_off,
+                                              y.c_off, (int)(w - bp.wl_coff[k]), st.ctl + s, stage);
     }
 }
 
@@ -926,7 +927,13 @@ hipError_t launch_batch_nlist(const Launch &L, const SysC *sys, const BatchPlan 
     const unsigned ncu = L.g->ncu > 0 ? (unsigned)L.g->ncu : 256u;
     const unsigned cap = ncu * kNlBlocksPerCu;
     const unsigned nb = need < cap ? (need > 0 ? need : 1u) : cap;
-    hipLaunchKernelGGL(k_batch_nlist, dim3(nb), dim3(kNlWaves * kWave), 0, L.stream, *L.st, *L.g, sys, bp, *L.pc);
+    // Two lanes per particle (the usual tuned shape) with the entry index folded.
+    if (L.g->lanes == 2)
+        hipLaunchKernelGGL(k_batch_nlist<1>, dim3(nb), dim3(kNlWaves * kWave), 0, L.stream, *L.st, *L.g, sys, bp,
+                           *L.pc);
+    else
+        hipLaunchKernelGGL(k_batch_nlist<-1>, dim3(nb), dim3(kNlWaves * kWave), 0, L.stream, *L.st, *L.g, sys, bp,
+                           *L.pc);
     return hipGetLastError();
 }
 
