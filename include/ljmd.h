@@ -352,10 +352,10 @@ int ljmd_vv_backward(ljmd_ctx *ctx, const double *lam_x, const double *lam_v, co
  * candidate cell size (cell_split 1 and 2: cells of edge >= r_L or >= r_L/2)
  * and force-gather shape (lanes per particle 1, 2, 4, 8, 16), keeps the
  * fastest pair, and sizes the list capacity from the longest list seen
- * (1.25x, at least +24, in units of 16). Results are cached as JSON lines in cache_path (may be NULL)
- * under a key of device architecture, precision, species count, size (power
- * of two), density (to 0.05) and list radius; a cached key is returned
- * without timing. */
+ * (1.25x, at least +24, in units of 16). Results are cached as JSON lines
+ * in cache_path (may be NULL) under a key of device architecture,
+ * dimension, precision, species count, size (power of two), density (to
+ * 0.05) and list radius; a cached key is returned without timing. */
 typedef struct ljmd_tuning {
     int32_t lanes;          /* fastest lanes per particle */
     int32_t nbr_capacity;   /* suggested list capacity */

@@ -113,7 +113,9 @@ __device__ inline void step_ds_body(const StepArgs &a, const BoxC &box, Ctl *ctl
         float sa = 0.f, sb = 0.f;
         // Eight entries per trip (two 16-byte group loads per lane) keep more
         // of the list stream in flight; groups past a list end read padding
-        // or other lists (valid indices) and are skipped.
+        // or other lists (valid indices) and are skipped. (Masking the loads
+        // of entries past a lane's list end instead, per entry, serialised
+        // them: 38.5 us against 30.3 us per launch at N = 256,000.)
         constexpr int UQ = 8;
         static_assert((size_t)4 * kWave <= kListPad, "list padding below the unroll depth");
         for (int m = 0; m < iters; m += UQ) {

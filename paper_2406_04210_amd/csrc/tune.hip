@@ -28,13 +28,14 @@ std::string tune_key(const ljmd_params *p) {
         arch = prop.gcnArchName;
     for (char &ch : arch)
         if (ch == '"' || ch == ' ') ch = '_';
-    const double vol = p->box[0] * p->box[1] * p->box[2];
+    // Density per volume, or per area in two dimensions (box[2] is no period there).
+    const double vol = p->dim == 2 ? p->box[0] * p->box[1] : p->box[0] * p->box[1] * p->box[2];
     const double rho = (double)p->n / vol;
     char buf[256];
-    // Size in powers of two, density to 0.05, the list radius to 0.1 sigma.
-    std::snprintf(buf, sizeof buf, "%s|prec%d|ns%d|n2^%d|rho%.2f|rl%.1f", arch.c_str(), p->precision, p->nspecies,
-                  (int)std::lround(std::log2((double)p->n)), std::round(rho * 20.0) / 20.0,
-                  p->rcut[0] + p->skin);
+    // Dimension, size in powers of two, density to 0.05, the list radius to 0.1 sigma.
+    std::snprintf(buf, sizeof buf, "%s|dim%d|prec%d|ns%d|n2^%d|rho%.2f|rl%.1f", arch.c_str(), p->dim == 2 ? 2 : 3,
+                  p->precision, p->nspecies, (int)std::lround(std::log2((double)p->n)),
+                  std::round(rho * 20.0) / 20.0, p->rcut[0] + p->skin);
     return buf;
 }
 
