@@ -35,8 +35,8 @@ HBM_PEAK_GBS = 8000.0
 # 512 MiB copy reads), valid only for the kernel sources they were taken on.
 STEP_KERNEL_SOURCES = ("k_step.hip", "step_common.h", "internal.h")
 STEP_KERNEL_TRAFFIC = {
-    "sources_sha256": "df61bafd2317e3a488aae06600d82bf15862ea1f156a1878e33217b606f3b362",
-    "fetch_bytes": 2.0 * 53444 * 1024,
+    "sources_sha256": "3521ef6fa688e203b54cf2a1562ad61800dd943841c20794ce41d4140c316966",
+    "fetch_bytes": 2.0 * 53448 * 1024,
     "write_bytes": 1.0 * 16035 * 1024,
 }
 
