@@ -100,11 +100,11 @@ __device__ inline void bin_one(const State &st, const Geom &g, const BoxC &box, 
     int slot = 0;
     while (pending) {
         const int leader = __ffsll(pending) - 1;
-        const int cl = __shfl(ci, leader);
+        const int cl = __builtin_amdgcn_readlane(ci, leader);
         const unsigned long long same = __ballot(ci == cl);
         int base = 0;
         if (lane == leader) base = atomicAdd(&st.cell_count[cl], __popcll(same));
-        base = __shfl(base, leader);
+        base = __builtin_amdgcn_readlane(base, leader);
         if (ci == cl)
             slot = base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(same >> 32),
                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)same, 0u));
@@ -394,40 +394,138 @@ __device__ inline uint32_t wave_max_u32(uint32_t v) {
     return v;
 }
 
+// Tests the candidate blocks cand[0 .. nbk) (lane e of block b holds one
+// candidate; cv marks the real ones, thr / thr1 their FP32 bounds) against
+// every home particle of the lanes in `homes` (lane p holds home record hrec
+// and its list length so far in kreg) and appends the hits to the
+// particles' lists in candidate order.
+template <int PREC, int NS, bool QC, int LG, int CH>
+__device__ inline void nlist_homes(const State &st, const Geom &g, const BoxC &box, const PairC &pc,
+                                   const typename CellRec<PREC>::T &hrec, int &kreg, uint64_t homes,
+                                   const typename CellRec<PREC>::T (&cand)[CH], const bool (&cv)[CH],
+                                   const uint32_t (&thr)[CH], const uint32_t (&thr1)[CH], int nbk) {
+    using CR = CellRec<PREC>;
+    using T = typename CR::T;
+    const int lane = threadIdx.x & 63;
+    const int lg = LG >= 0 ? LG : (g.lanes >= 16 ? 4 : (g.lanes >= 8 ? 3 : (g.lanes >= 4 ? 2 : (g.lanes >= 2 ? 1 : 0))));
+    const int lanes = LG >= 0 ? (1 << LG) : g.lanes;
+    for (uint64_t mk = homes; mk != 0ull; mk &= mk - 1ull) {
+        const int p = __builtin_ctzll(mk);
+        const T ri = lane_read(hrec, p);
+        const int i = CR::index(ri);
+        if ((unsigned)i >= (unsigned)g.n) continue;
+        const int si = CR::species(ri);
+        int k = lane_read(kreg, p);
+        // Entry kk of particle i: lane kk % lanes, its entry m = kk / lanes
+        // at row[(m / 4) * 256 + (kk % lanes) * 4 + m % 4], addressed by a
+        // 32-bit byte offset from the particle's row.
+        uint8_t *__restrict__ row = (uint8_t *)(st.nbr + nbr_index(i, 0, lanes, g.cap));
+#pragma unroll
+        for (int b = 0; b < CH; ++b) {
+            if (b >= nbk) break;
+            const int j = CR::index(cand[b]);
+            bool hit;
+            if constexpr (PREC == LJMD_FP64) {
+                const int tt = NS == 1 ? 0 : si + CR::species(cand[b]);
+                const double r2 = cand_r2(ri, cand[b], box);
+                hit = cv[b] && r2 > 0.0 && r2 < by_type<NS>(tt, pc.rl2);
+            } else {
+                // 0 < r^2 < r_L^2 as one unsigned compare of the bit
+                // patterns (r^2 >= 0); thr[b] is 0 for empty lanes.
+                const uint32_t lim = (NS == 2 && si != 0) ? thr1[b] : thr[b];
+                const float r2 = QC ? cand_r2q(ri, cand[b]) : cand_r2(ri, cand[b], box);
+                hit = __float_as_uint(r2) - 1u < lim;
+            }
+            const unsigned long long mask = __ballot(hit ? 1 : 0);
+            if (mask == 0ull) continue;
+            const uint32_t kk = __builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, (uint32_t)k));
+            k += __popcll(mask);
+            uint32_t off;
+            if constexpr (LG == 1) {
+                // Two lanes: byte (kk / 8) * 1024 + 4 g(kk % 8) with
+                // g(r) = 4 (r % 2) + r / 2, read from a table of 3-bit fields
+                // (the extract takes its offset modulo 32, and g < 8 keeps
+                // the entry inside its group whatever the offset).
+                const uint32_t g4 = __builtin_amdgcn_ubfe(0x73625140u, kk << 2, 3);
+                off = ((kk << 7) & ~0x3ffu) + (g4 << 2);
+            } else {
+                off = (((kk >> (lg + 2)) << 8) | ((kk & (uint32_t)(lanes - 1)) << 2) |
+                       __builtin_amdgcn_ubfe(kk, lg, 2)) << 2;
+            }
+            // Past the capacity only the overflow count is kept.
+            if (__builtin_expect(k <= g.cap, 1)) {
+                if (hit) *(int32_t *)(row + off) = j;
+            } else if (hit && kk < (uint32_t)g.cap) {
+                *(int32_t *)(row + off) = j;
+            }
+        }
+        kreg = lane == p ? k : kreg;
+    }
+}
+
+// Bit patterns of r_L^2 - 1 ulp for the candidates of a block (0 for empty
+// lanes): thr for a home particle of species 0, thr1 of species 1.
+template <int PREC, int NS, bool QC>
+__device__ inline void nlist_bounds(const BoxC &box, const PairC &pc, const typename CellRec<PREC>::T &cand,
+                                    bool cv, uint32_t &thr, uint32_t &thr1) {
+    using CR = CellRec<PREC>;
+    thr = 0u;
+    thr1 = 0u;
+    if constexpr (PREC == LJMD_FP32_DS) {
+        const float *tab = QC ? box.rl2q : pc.rl2f;
+        if constexpr (NS == 1) {
+            thr = cv ? __float_as_uint(tab[0]) - 1u : 0u;
+        } else {
+            const bool sj = CR::species(cand) != 0;  // pair type = home species + sj
+            thr = cv ? __float_as_uint(sj ? tab[1] : tab[0]) - 1u : 0u;
+            thr1 = cv ? __float_as_uint(sj ? tab[2] : tab[1]) - 1u : 0u;
+        }
+    }
+}
+
+// Candidates per queue of the reduced list build: a chunk of CH blocks is
+// appended to queues holding fewer than CH blocks' worth.
+template <int CH>
+struct NlistQueue {
+    static constexpr int kCap = 2 * CH * kWave;
+};
+
 // One home cell (local Hilbert rank c of a box whose cells start at c_off in
 // the flattened cell arrays; rank_of and cell_lin are that box's tables).
 // QC: FP32 criterion of a cubic box, in squared quanta (raw differences
 // against r_L^2 / quantum^2).
 //
-// With QC, each chunk of candidates is first reduced to those that can be
-// within r_L of some home particle: a candidate is dropped when its distance
-// to the bounding box of the home particles (in quanta, per axis the wrapped
-// gap to the box's extent) exceeds r_L with a margin of 2^-18 relative,
-// which covers the roundings of both that bound and the exact test (a few
-// units of 2^-24 each), so a dropped candidate fails the exact test for
-// every home particle. The survivors keep their order (ballot compaction
-// through LDS), so the lists are the same entries in the same order as
-// without the reduction. At liquid density the home-particle loop then
-// runs over about three quarters of the blocks (a quarter fewer list
-// stores, an eighth fewer VALU instructions); the kernel is bound by issue
-// latency as much as by VALU throughput, so the chunk is kept small enough
-// for five waves per SIMD.
+// With QC the home particles are split in two groups at the middle of their
+// extent along z, and every candidate is first tested against the bounding
+// box of each group: it is dropped for a group when its distance to the box
+// (in quanta, per axis the wrapped gap to the box's extent) exceeds r_L with
+// a margin of 2^-18 relative, which covers the roundings of both that bound
+// and the exact test (a few units of 2^-24 each), so a dropped candidate
+// fails the exact test for every home particle of the group. The survivors'
+// indices go, in candidate order, to a per-group queue in LDS; whenever a
+// queue holds CH blocks' worth (and once more at the end), the wave reloads
+// them from the particles' records and runs the exact test for that group's
+// home particles only. So the lists are the same entries in the same order
+// as without the reduction, while at liquid density the exact test runs
+// over about 0.7 of the (particle, block) pairs of a single reduction per
+// cell (two smaller boxes, and blocks filled across chunks), at the price of
+// a second, cheap test per candidate. rec: the particles' position records,
+// the same as the cell slots hold. queue: 2 x NlistQueue<CH>::kCap entries
+// of this wave.
 // LG: log2 of the lanes per particle of the list layout when it is known at
 // compile time (the shifts and masks of the entry index fold), -1 to read it
 // from g.lanes.
 template <int PREC, int NS, bool QC, int LG = -1>
 __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &box, const PairC &pc,
                                   const int32_t *rank_of, const int32_t *cell_lin, int64_t c_off, int c,
-                                  Ctl *ctl, typename CellRec<PREC>::T *stage) {
+                                  Ctl *ctl, const typename CellRec<PREC>::T *__restrict__ rec, int32_t *queue) {
     using CR = CellRec<PREC>;
     using T = typename CR::T;
     constexpr bool FILT = PREC == LJMD_FP32_DS && QC;
     constexpr int CH = NlistChunk<PREC, FILT>::CH;
     const int lane = threadIdx.x & 63;
     const T *__restrict__ cr = cell_recs<PREC>(st);
-    const int lg = LG >= 0 ? LG : (g.lanes >= 16 ? 4 : (g.lanes >= 8 ? 3 : (g.lanes >= 4 ? 2 : (g.lanes >= 2 ? 1 : 0))));
-    const int lanes = LG >= 0 ? (1 << LG) : g.lanes;
-    const int lmask = lanes - 1;
     const int lin = cell_lin[c];
     const int cc[3] = {lin / (box.nc[1] * box.nc[2]), (lin / box.nc[2]) % box.nc[1],
                        lin % box.nc[2]};
@@ -462,17 +560,57 @@ __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &bo
         T hrec;
         if (lane < hm) hrec = cr[(int64_t)home * g.cell_cap + h0 + lane];
         else hrec = T{};
-        uint32_t bmn[3] = {0u, 0u, 0u}, bspan[3] = {0u, 0u, 0u};
+        const uint64_t all = hm >= kWave ? ~0ull : ((1ull << hm) - 1ull);
+        // FILT: the two groups' lane masks and bounding boxes (wrapped extent
+        // per axis: start and span in quanta), their queue fills.
+        uint64_t gmask[2] = {all, 0ull};
+        uint32_t bmn[2][3] = {{0u, 0u, 0u}, {0u, 0u, 0u}}, bspan[2][3] = {{0u, 0u, 0u}, {0u, 0u, 0u}};
+        int fill[2] = {0, 0};
         if constexpr (FILT) {
+            const bool act = lane < hm;
             const uint32_t hq[3] = {(uint32_t)hrec.x, (uint32_t)hrec.y, (uint32_t)hrec.z};
-            for (int a = 0; a < 3; ++a) {
-                const uint32_t mn = wave_min_u32(lane < hm ? hq[a] : 0xffffffffu);
-                const uint32_t mx = wave_max_u32(lane < hm ? hq[a] : 0u);
-                bmn[a] = (uint32_t)__builtin_amdgcn_readfirstlane((int)mn);
-                bspan[a] = (uint32_t)__builtin_amdgcn_readfirstlane((int)(mx - mn));
+            const uint32_t zmn = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_min_u32(act ? hq[2] : 0xffffffffu));
+            const uint32_t zmx = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_max_u32(act ? hq[2] : 0u));
+            const bool up = act && hq[2] - zmn > ((zmx - zmn) >> 1);
+            gmask[0] = __ballot(act && !up);
+            gmask[1] = __ballot(up);
+            for (int gi = 0; gi < 2; ++gi) {
+                const bool in = ((gmask[gi] >> lane) & 1ull) != 0ull;
+                for (int a = 0; a < 3; ++a) {
+                    const uint32_t mn = wave_min_u32(in ? hq[a] : 0xffffffffu);
+                    const uint32_t mx = wave_max_u32(in ? hq[a] : 0u);
+                    bmn[gi][a] = (uint32_t)__builtin_amdgcn_readfirstlane((int)mn);
+                    bspan[gi][a] = (uint32_t)__builtin_amdgcn_readfirstlane((int)(mx - mn));
+                }
             }
         }
         int kreg = 0;
+        // FILT: test the home particles of group gi against the first cnt
+        // queued candidates (cnt <= CH blocks), reloaded from their records.
+        auto drain = [&](int gi, int cnt) {
+            T cand[CH];
+            bool cv[CH];
+            uint32_t thr[CH], thr1[CH];
+            const int nbk = (cnt + kWave - 1) / kWave;
+            const int32_t *qg = queue + gi * NlistQueue<CH>::kCap;
+#pragma unroll
+            for (int b = 0; b < CH; ++b) {
+                cv[b] = false;
+                cand[b] = T{};
+                thr[b] = thr1[b] = 0u;
+                if (b >= nbk) continue;
+                const int t = b * kWave + lane;
+                cv[b] = t < cnt;
+                const int j = cv[b] ? qg[t] : 0;
+                if (cv[b]) cand[b] = CR::pack(rec[j], j);
+            }
+#pragma unroll
+            for (int b = 0; b < CH; ++b) {
+                if (b >= nbk) break;
+                nlist_bounds<PREC, NS, QC>(box, pc, cand[b], cv[b], thr[b], thr1[b]);
+            }
+            nlist_homes<PREC, NS, QC, LG, CH>(st, g, box, pc, hrec, kreg, gmask[gi], cand, cv, thr, thr1, nbk);
+        };
         for (int s0 = 0; s0 < nst; s0 += kWave) {
         // Stencil cells s0 .. s0 + nsp - 1: lane e holds cell s0 + e, its
         // flattened index, its (capped) count and the offset of its first
@@ -495,24 +633,18 @@ __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &bo
             if (lane >= o) incl += y;
         }
         const int soff = incl - scnt;
-        const int ncand = __shfl(incl, kWave - 1);
+        const int ncand = __builtin_amdgcn_readlane(incl, kWave - 1);  // wave-uniform, in a scalar register
         const int top = nsp > 32 ? 32 : 16;
         for (int cb = 0; cb < ncand; cb += CH * kWave) {
             // Blocks of 64 candidates this chunk holds (wave-uniform): the
             // last chunk of a cell is usually short.
-            int nbk = min(CH, (ncand - cb + kWave - 1) / kWave);
+            const int nbk = min(CH, (ncand - cb + kWave - 1) / kWave);
             T cand[CH];
             bool cv[CH];
-            // FP32 bound of each candidate as bits(r_L^2) - 1 (0 for empty
-            // lanes), for a home particle of species 0 (thr) and, with two
-            // species, of species 1 (thr1).
-            uint32_t thr[CH], thr1[CH];
 #pragma unroll
             for (int b = 0; b < CH; ++b) {
                 cv[b] = false;
                 cand[b] = T{};
-                thr[b] = 0u;
-                thr1[b] = 0u;
                 if (b >= nbk) continue;
                 const int t = cb + b * kWave + lane;
                 // Largest stencil cell s of this part with soff[s] <= t: a
@@ -533,92 +665,71 @@ __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &bo
                 cv[b] = cv[b] && (unsigned)CR::index(cand[b]) < (unsigned)g.n;
             }
             if constexpr (FILT) {
-                // Keep the candidates within reach of the home box, in order.
-                int kept = 0;
+                // Queue, per group, the candidates within reach of its box.
 #pragma unroll
-                for (int b = 0; b < CH; ++b) {
-                    if (b >= nbk) break;
-                    const float gx = (float)gap_q((uint32_t)cand[b].x, bmn[0], bspan[0]);
-                    const float gy = (float)gap_q((uint32_t)cand[b].y, bmn[1], bspan[1]);
-                    const float gz = (float)gap_q((uint32_t)cand[b].z, bmn[2], bspan[2]);
-                    const bool keep = cv[b] && fmaf(gz, gz, fmaf(gy, gy, gx * gx)) <= reach;
-                    const unsigned long long km = __ballot(keep ? 1 : 0);
-                    const uint32_t pos = __builtin_amdgcn_mbcnt_hi(
-                        (uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, (uint32_t)kept));
-                    if (keep) stage[pos] = cand[b];
-                    kept += __popcll(km);
+                for (int gi = 0; gi < 2; ++gi) {
+                    if (gmask[gi] == 0ull) continue;
+                    int32_t *qg = queue + gi * NlistQueue<CH>::kCap;
+#pragma unroll
+                    for (int b = 0; b < CH; ++b) {
+                        if (b >= nbk) break;
+                        const float gx = (float)gap_q((uint32_t)cand[b].x, bmn[gi][0], bspan[gi][0]);
+                        const float gy = (float)gap_q((uint32_t)cand[b].y, bmn[gi][1], bspan[gi][1]);
+                        const float gz = (float)gap_q((uint32_t)cand[b].z, bmn[gi][2], bspan[gi][2]);
+                        const bool keep = cv[b] && fmaf(gz, gz, fmaf(gy, gy, gx * gx)) <= reach;
+                        const unsigned long long km = __ballot(keep ? 1 : 0);
+                        const uint32_t pos = __builtin_amdgcn_mbcnt_hi(
+                            (uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, (uint32_t)fill[gi]));
+                        if (keep) qg[pos] = CR::index(cand[b]);
+                        fill[gi] += __popcll(km);
+                    }
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                 __builtin_amdgcn_wave_barrier();
-                nbk = (kept + kWave - 1) / kWave;
+                // A queue holding CH blocks or more: test its first CH
+                // blocks, then move the rest (fewer than CH blocks) to its
+                // front.
+                for (int gi = 0; gi < 2; ++gi) {
+                    if (fill[gi] < CH * kWave) continue;
+                    drain(gi, CH * kWave);
+                    int32_t *qg = queue + gi * NlistQueue<CH>::kCap;
+                    const int rest = fill[gi] - CH * kWave;
+                    int32_t mv[CH];
+#pragma unroll
+                    for (int b = 0; b < CH; ++b) {
+                        const int t = b * kWave + lane;
+                        mv[b] = t < rest ? qg[CH * kWave + t] : 0;
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                    for (int b = 0; b < CH; ++b) {
+                        const int t = b * kWave + lane;
+                        if (t < rest) qg[t] = mv[b];
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    fill[gi] = rest;
+                }
+            } else {
+                uint32_t thr[CH], thr1[CH];
 #pragma unroll
                 for (int b = 0; b < CH; ++b) {
-                    if (b >= nbk) break;
-                    const int t = b * kWave + lane;
-                    cv[b] = t < kept;
-                    cand[b] = stage[cv[b] ? t : 0];
+                    thr[b] = thr1[b] = 0u;
+                    if (b >= nbk) continue;
+                    nlist_bounds<PREC, NS, QC>(box, pc, cand[b], cv[b], thr[b], thr1[b]);
                 }
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-            }
-            if constexpr (PREC == LJMD_FP32_DS) {
-#pragma unroll
-                for (int b = 0; b < CH; ++b) {
-                    if (b >= nbk) break;
-                    const float *tab = QC ? box.rl2q : pc.rl2f;
-                    if constexpr (NS == 1) {
-                        thr[b] = cv[b] ? __float_as_uint(tab[0]) - 1u : 0u;
-                    } else {
-                        const bool sj = CR::species(cand[b]) != 0;  // pair type = home species + sj
-                        thr[b] = cv[b] ? __float_as_uint(sj ? tab[1] : tab[0]) - 1u : 0u;
-                        thr1[b] = cv[b] ? __float_as_uint(sj ? tab[2] : tab[1]) - 1u : 0u;
-                    }
-                }
-            }
-            for (int p = 0; p < hm; ++p) {
-                const T ri = lane_read(hrec, p);
-                const int i = CR::index(ri);
-                if ((unsigned)i >= (unsigned)g.n) continue;
-                const int si = CR::species(ri);
-                int k = lane_read(kreg, p);
-                // Entry kk of particle i: lane kk % lanes, its entry m = kk / lanes
-                // at row[(m / 4) * 256 + (kk % lanes) * 4 + m % 4], addressed
-                // by a 32-bit byte offset from the particle's row.
-                uint8_t *__restrict__ row = (uint8_t *)(st.nbr + nbr_index(i, 0, lanes, g.cap));
-#pragma unroll
-                for (int b = 0; b < CH; ++b) {
-                    if (b >= nbk) break;
-                    const int j = CR::index(cand[b]);
-                    bool hit;
-                    if constexpr (PREC == LJMD_FP64) {
-                        const int tt = NS == 1 ? 0 : si + CR::species(cand[b]);
-                        const double r2 = cand_r2(ri, cand[b], box);
-                        hit = cv[b] && r2 > 0.0 && r2 < by_type<NS>(tt, pc.rl2);
-                    } else {
-                        // 0 < r^2 < r_L^2 as one unsigned compare of the bit
-                        // patterns (r^2 >= 0); thr[b] is 0 for empty lanes.
-                        const uint32_t lim = (NS == 2 && si != 0) ? thr1[b] : thr[b];
-                        const float r2 = QC ? cand_r2q(ri, cand[b]) : cand_r2(ri, cand[b], box);
-                        hit = __float_as_uint(r2) - 1u < lim;
-                    }
-                    const unsigned long long mask = __ballot(hit ? 1 : 0);
-                    if (mask == 0ull) continue;
-                    const uint32_t kk = __builtin_amdgcn_mbcnt_hi(
-                        (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, (uint32_t)k));
-                    k += __popcll(mask);
-                    // Entry index (m / 4) * 256 + (kk % lanes) * 4 + m % 4.
-                    const uint32_t e = ((kk >> (lg + 2)) << 8) |
-                                       (((kk & (uint32_t)lmask) << 2) | __builtin_amdgcn_ubfe(kk, lg, 2));
-                    // Past the capacity only the overflow count is kept.
-                    if (__builtin_expect(k <= g.cap, 1)) {
-                        if (hit) *(int32_t *)(row + (e << 2)) = j;
-                    } else if (hit && kk < (uint32_t)g.cap) {
-                        *(int32_t *)(row + (e << 2)) = j;
-                    }
-                }
-                kreg = lane == p ? k : kreg;
+                nlist_homes<PREC, NS, QC, LG, CH>(st, g, box, pc, hrec, kreg, all, cand, cv, thr, thr1, nbk);
             }
         }
+        }
+        if constexpr (FILT) {
+            for (int gi = 0; gi < 2; ++gi)
+                if (fill[gi] > 0) drain(gi, fill[gi]);
+            // The next group of home particles (cells over 64) starts on
+            // empty queues; make this group's reads complete first.
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
         }
         if (lane < hm) {
             const int i = CR::index(hrec);
@@ -633,24 +744,26 @@ __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &bo
     }
 }
 
-// Per-wave staging for the candidate reduction (FP32 cubic boxes only).
+// Per-block LDS of the reduced list build (FP32 cubic boxes only): two
+// candidate queues per wave.
 template <int PREC, bool QC>
 struct NlistStage {
-    static constexpr int kEntries = (PREC == LJMD_FP32_DS && QC) ? kNlWaves * NlistChunk<PREC, true>::CH * kWave : 1;
+    static constexpr int kPerWave =
+        (PREC == LJMD_FP32_DS && QC) ? 2 * NlistQueue<NlistChunk<PREC, true>::CH>::kCap : 0;
+    static constexpr int kEntries = kPerWave > 0 ? kNlWaves * kPerWave : 1;
 };
 
 template <int PREC, int NS, bool QC, int LG = -1>
-__global__ __launch_bounds__(kNlWaves * kWave) void k_nlist(State st, Geom g, BoxC box, PairC pc, int cur,
+__global__ __launch_bounds__(kNlWaves * kWave, 5) void k_nlist(State st, Geom g, BoxC box, PairC pc, int cur,
                                                             int64_t step, int forced, float thr2) {
-    (void)cur;
     if (halted(st.ctl) || !rebuild_due(st.ctl, step, forced, thr2)) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) st.ctl->rebuilds += 1;
-    const int wv = threadIdx.x >> 6, W = blockDim.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), W = blockDim.x >> 6;
     const int tw = gridDim.x * W;
-    using T = typename CellRec<PREC>::T;
-    constexpr int SE = NlistStage<PREC, QC>::kEntries;
-    __shared__ T stage_all[SE];
-    T *stage = SE > 1 ? stage_all + wv * (SE / kNlWaves) : stage_all;
+    using Stage = NlistStage<PREC, QC>;
+    __shared__ int32_t queue_all[Stage::kEntries];
+    int32_t *queue = queue_all + wv * Stage::kPerWave;
+    const auto *rec = records<PREC>(st, cur);
     if (box.ncell < 8 * tw) {
         // A few cells per wave: contiguous runs of Hilbert-ranked cells, each
         // XCD one contiguous share of the box.
@@ -658,7 +771,7 @@ __global__ __launch_bounds__(kNlWaves * kWave) void k_nlist(State st, Geom g, Bo
         const int per = (box.ncell + tw - 1) / tw;
         const int cbeg = gw * per, cend = min(cbeg + per, box.ncell);
         for (int c = cbeg; c < cend; ++c)
-            nlist_cell<PREC, NS, QC, LG>(st, g, box, pc, st.rank_of, st.cell_lin, 0, c, st.ctl, stage);
+            nlist_cell<PREC, NS, QC, LG>(st, g, box, pc, st.rank_of, st.cell_lin, 0, c, st.ctl, rec, queue);
         return;
     }
     // Many cells per wave: each XCD (blocks are dispatched to XCD
@@ -673,9 +786,9 @@ __global__ __launch_bounds__(kNlWaves * kWave) void k_nlist(State st, Geom g, Bo
     for (;;) {
         int c = 0;
         if (lane == 0) c = lo + (int)atomicAdd(&st.ctl->nlq[q], 1u);
-        c = __shfl(c, 0);
+        c = __builtin_amdgcn_readfirstlane(c);  // wave-uniform from here on
         if (c >= hi) break;
-        nlist_cell<PREC, NS, QC, LG>(st, g, box, pc, st.rank_of, st.cell_lin, 0, c, st.ctl, stage);
+        nlist_cell<PREC, NS, QC, LG>(st, g, box, pc, st.rank_of, st.cell_lin, 0, c, st.ctl, rec, queue);
     }
 }
 
@@ -778,8 +891,8 @@ __global__ __launch_bounds__(kRbBlock) void k_batch_canon(State st, Geom g, cons
 }
 
 template <int LG>
-__global__ __launch_bounds__(kNlWaves * kWave) void k_batch_nlist(State st, Geom g, const SysC *sys, BatchPlan bp,
-                                                                  PairC pc) {
+__global__ __launch_bounds__(kNlWaves * kWave, 5) void k_batch_nlist(State st, Geom g, const SysC *sys, BatchPlan bp,
+                                                                  PairC pc, int cur) {
     const int count = bp.wl_count[0];
     const int64_t total = bp.wl_coff[count];
     // The flattened cells of the systems due, split into one contiguous share
@@ -789,19 +902,21 @@ __global__ __launch_bounds__(kNlWaves * kWave) void k_batch_nlist(State st, Geom
     const int q = (int)(blockIdx.x % (unsigned)nq);
     const int64_t lo = total * q / nq, hi = total * (q + 1) / nq;
     const int lane = threadIdx.x & 63;
-    constexpr int SE = NlistStage<LJMD_FP32_DS, true>::kEntries;
-    __shared__ int4 stage_all[SE];
-    int4 *stage = stage_all + (threadIdx.x >> 6) * (SE / kNlWaves);
+    using Stage = NlistStage<LJMD_FP32_DS, true>;
+    __shared__ int32_t queue_all[Stage::kEntries];
+    int32_t *queue = queue_all + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * Stage::kPerWave;
+    const int4 *rec = records<LJMD_FP32_DS>(st, cur);
     for (;;) {
         int64_t w = 0;
         if (lane == 0) w = lo + (int64_t)atomicAdd(&st.ctl->nlq[q], 1u);
-        w = __shfl(w, 0);
+        w = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(w >> 32)) << 32) |
+                      (uint32_t)__builtin_amdgcn_readfirstlane((int)w));
         if (w >= hi) break;
         const int k = plan_find(bp.wl_coff, count, w);
         const int s = bp.wl_sys[k];
         const SysC &y = sys[s];
         nlist_cell<LJMD_FP32_DS, 1, true, LG>(st, g, y.box, pc, st.rank_of + y.c_off, st.cell_lin + y.c_off,
-                                              y.c_off, (int)(w - bp.wl_coff[k]), st.ctl + s, stage);
+                                              y.c_off, (int)(w - bp.wl_coff[k]), st.ctl + s, rec, queue);
     }
 }
 
@@ -930,10 +1045,10 @@ hipError_t launch_batch_nlist(const Launch &L, const SysC *sys, const BatchPlan 
     // Two lanes per particle (the usual tuned shape) with the entry index folded.
     if (L.g->lanes == 2)
         hipLaunchKernelGGL(k_batch_nlist<1>, dim3(nb), dim3(kNlWaves * kWave), 0, L.stream, *L.st, *L.g, sys, bp,
-                           *L.pc);
+                           *L.pc, L.cur);
     else
         hipLaunchKernelGGL(k_batch_nlist<-1>, dim3(nb), dim3(kNlWaves * kWave), 0, L.stream, *L.st, *L.g, sys, bp,
-                           *L.pc);
+                           *L.pc, L.cur);
     return hipGetLastError();
 }
 
