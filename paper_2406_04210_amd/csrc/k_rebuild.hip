@@ -351,10 +351,18 @@ struct NlistChunk {
     static constexpr int CH = FILT ? 6 : (PREC == LJMD_FP64 ? 4 : 8);
 };
 
-// Waves per list-build block, and blocks per compute unit when a rebuild is
-// due (the kernel strides over contiguous runs of cells).
+// Waves per list-build block, and blocks per compute unit: with up to
+// 8 cells per wave of a grid of kNlBlocksPerCu blocks per compute unit,
+// each wave takes a contiguous run of cells (measured at N = 256,000: one
+// cell per wave over 12 blocks per compute unit, 52.3 ms per 1000 steps,
+// against 54.8 ms with three cells per wave over 5); larger grids of cells
+// go through the per-XCD queues with kNlQueueBlocksPerCu blocks per compute
+// unit, the five waves per SIMD that fit at once (the 4M mixture 3.99e9 ->
+// 4.01e9 and the 512-replica batch 4.22e9 -> 4.33e9 particle-steps/s
+// against 12).
 constexpr int kNlWaves = 4;
 constexpr int kNlBlocksPerCu = 12;
+constexpr int kNlQueueBlocksPerCu = 5;
 
 __device__ inline int lane_read(int v, int p) { return __builtin_amdgcn_readlane(v, p); }
 __device__ inline int4 lane_read(const int4 &v, int p) {
@@ -436,7 +444,7 @@ __device__ inline void nlist_homes(const State &st, const Geom &g, const BoxC &b
                 const float r2 = QC ? cand_r2q(ri, cand[b]) : cand_r2(ri, cand[b], box);
                 hit = __float_as_uint(r2) - 1u < lim;
             }
-            const unsigned long long mask = __ballot(hit ? 1 : 0);
+            const unsigned long long mask = __builtin_amdgcn_ballot_w64(hit);
             if (mask == 0ull) continue;
             const uint32_t kk = __builtin_amdgcn_mbcnt_hi(
                 (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, (uint32_t)k));
@@ -584,6 +592,17 @@ __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &bo
                 }
             }
         }
+        // Along every axis the grid has at least 2 R + 2 cells: every
+        // candidate then lies within half a box of the home cell, and the
+        // wrapped gap to a group's box is the plain signed one (glo, ghi:
+        // the box's extent relative to group 0's corner).
+        const bool wide = box.nc[0] >= 2 * R + 2 && box.nc[1] >= 2 * R + 2 && box.nc[2] >= 2 * R + 2;
+        int32_t glo[2][3], ghi[2][3];
+        for (int gi = 0; gi < 2; ++gi)
+            for (int a = 0; a < 3; ++a) {
+                glo[gi][a] = (int32_t)(bmn[gi][a] - bmn[0][a]);
+                ghi[gi][a] = glo[gi][a] + (int32_t)bspan[gi][a];
+            }
         int kreg = 0;
         // FILT: test the home particles of group gi against the first cnt
         // queued candidates (cnt <= CH blocks), reloaded from their records.
@@ -667,20 +686,32 @@ __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &bo
             if constexpr (FILT) {
                 // Queue, per group, the candidates within reach of its box.
 #pragma unroll
-                for (int gi = 0; gi < 2; ++gi) {
-                    if (gmask[gi] == 0ull) continue;
-                    int32_t *qg = queue + gi * NlistQueue<CH>::kCap;
+                for (int b = 0; b < CH; ++b) {
+                    if (b >= nbk) break;
+                    // Wide grids: the candidate's coordinates relative to
+                    // group 0's box corner, as signed quanta (the direct
+                    // image is the nearest one).
+                    const int32_t dx = (int32_t)((uint32_t)cand[b].x - bmn[0][0]);
+                    const int32_t dy = (int32_t)((uint32_t)cand[b].y - bmn[0][1]);
+                    const int32_t dz = (int32_t)((uint32_t)cand[b].z - bmn[0][2]);
 #pragma unroll
-                    for (int b = 0; b < CH; ++b) {
-                        if (b >= nbk) break;
-                        const float gx = (float)gap_q((uint32_t)cand[b].x, bmn[gi][0], bspan[gi][0]);
-                        const float gy = (float)gap_q((uint32_t)cand[b].y, bmn[gi][1], bspan[gi][1]);
-                        const float gz = (float)gap_q((uint32_t)cand[b].z, bmn[gi][2], bspan[gi][2]);
+                    for (int gi = 0; gi < 2; ++gi) {
+                        if (gmask[gi] == 0ull) continue;
+                        float gx, gy, gz;
+                        if (wide) {
+                            gx = (float)max(max(glo[gi][0] - dx, dx - ghi[gi][0]), 0);
+                            gy = (float)max(max(glo[gi][1] - dy, dy - ghi[gi][1]), 0);
+                            gz = (float)max(max(glo[gi][2] - dz, dz - ghi[gi][2]), 0);
+                        } else {
+                            gx = (float)gap_q((uint32_t)cand[b].x, bmn[gi][0], bspan[gi][0]);
+                            gy = (float)gap_q((uint32_t)cand[b].y, bmn[gi][1], bspan[gi][1]);
+                            gz = (float)gap_q((uint32_t)cand[b].z, bmn[gi][2], bspan[gi][2]);
+                        }
                         const bool keep = cv[b] && fmaf(gz, gz, fmaf(gy, gy, gx * gx)) <= reach;
-                        const unsigned long long km = __ballot(keep ? 1 : 0);
+                        const unsigned long long km = __builtin_amdgcn_ballot_w64(keep);
                         const uint32_t pos = __builtin_amdgcn_mbcnt_hi(
                             (uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, (uint32_t)fill[gi]));
-                        if (keep) qg[pos] = CR::index(cand[b]);
+                        if (keep) queue[gi * NlistQueue<CH>::kCap + pos] = CR::index(cand[b]);
                         fill[gi] += __popcll(km);
                     }
                 }
@@ -988,7 +1019,9 @@ template <int PREC, int NS>
 static void nlist_launch(const Launch &L, int64_t step, int forced) {
     const unsigned need = blocks_for(L.box->ncell, kNlWaves);
     const unsigned ncu = L.g->ncu > 0 ? (unsigned)L.g->ncu : 256u;
-    const unsigned cap = ncu * kNlBlocksPerCu;
+    // The kernel takes the queue path when the cells outnumber 8 per wave.
+    const bool queued = (int64_t)L.box->ncell >= (int64_t)8 * kNlWaves * kNlBlocksPerCu * ncu;
+    const unsigned cap = ncu * (queued ? kNlQueueBlocksPerCu : kNlBlocksPerCu);
     const unsigned nb = need < cap ? (need > 0 ? need : 1u) : cap;
     // The common layout of the single-precision force pass (two lanes per
     // particle) has its own instantiation with the entry index folded.
@@ -1040,7 +1073,7 @@ hipError_t launch_batch_canon(const Launch &L, const SysC *sys, const BatchPlan 
 hipError_t launch_batch_nlist(const Launch &L, const SysC *sys, const BatchPlan &bp, int64_t total_cells) {
     const unsigned need = blocks_for(total_cells, kNlWaves);
     const unsigned ncu = L.g->ncu > 0 ? (unsigned)L.g->ncu : 256u;
-    const unsigned cap = ncu * kNlBlocksPerCu;
+    const unsigned cap = ncu * kNlQueueBlocksPerCu;
     const unsigned nb = need < cap ? (need > 0 ? need : 1u) : cap;
     // Two lanes per particle (the usual tuned shape) with the entry index folded.
     if (L.g->lanes == 2)
