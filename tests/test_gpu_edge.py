@@ -150,3 +150,32 @@ def test_smallest_box_and_one_below(ljmd):
     with pytest.raises(ljmd.LJMDError) as err:
         ljmd.System(n, np.full(3, L * (1 - 1e-9)), p, precision=FP64)
     assert err.value.code == -4                       # LJMD_EBOX
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32_DS])
+@pytest.mark.parametrize("ncell_axis", [3, 5])
+def test_crowded_cell_lists(ljmd, prec, ncell_axis):
+    # One cell holding about 150 particles (a cluster dropped into a sparse
+    # gas): the list build takes a cell's particles 64 at a time, splits
+    # them in two groups along z and queues each group's candidates; with 3
+    # cells per axis the box test takes the wrapped gap, with 5 the signed
+    # one. Lists must match the oracle's sets exactly.
+    p = W.single_species_params()
+    rl = p.rcut[0] + p.skin
+    L = ncell_axis * rl * 1.01
+    edge = L / ncell_axis
+    rng = np.random.default_rng(31 + ncell_axis)
+    x = np.concatenate([rng.uniform(0.0, L, size=(300, 3)),
+                        edge + rng.uniform(0.02 * edge, 0.98 * edge, size=(140, 3))])
+    sp = np.zeros(len(x), dtype=np.int32)
+    box = (L, L, L)
+    s = ljmd.System(len(x), box, p, precision=prec, nbr_capacity=384, cell_capacity=256)
+    s.set_state(x, np.zeros_like(x), sp)
+    cnt, ids = s.neighbors(cap=512)
+    s.sync()
+    cnt, ids = cnt.cpu().numpy(), ids.cpu().numpy()
+    oc, on = oracle.build_lists(x, sp, box, p, mode=0 if prec == FP64 else 1, cap=512)
+    assert oc.max() > 64 and oc.max() <= 384
+    assert np.array_equal(cnt, oc)
+    for i in range(len(x)):
+        assert set(ids[i, : cnt[i]].tolist()) == set(on[i, : oc[i]].tolist()), i
