@@ -256,6 +256,22 @@ __global__ __launch_bounds__(kBlock) void k_step_ds(StepArgs a) {
     step_ds_body<NS, LANES, Q, OBS, TH, PLAIN>(a, a.box, a.st.ctl, xcd_remap(blockIdx.x, gridDim.x), a.g.n, 0,
                                                a.box.ncell, blockIdx.x, gridDim.x, a.st.rebuilt + a.slot);
 }
+// Two species, NVE: held to 64 VGPRs, eight waves per SIMD (unbounded it
+// takes 65-66 and drops to seven; the 4M mixture's step kernel measured
+// 727 -> 683 us). The thermostat's form would spill under that bound.
+template <int LANES, bool Q, bool OBS, bool PLAIN>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_step_ds_mix(StepArgs a) {
+    static_assert(OBS || Q, "observables are skipped on the quanta path only");
+    step_ds_body<2, LANES, Q, OBS, false, PLAIN>(a, a.box, a.st.ctl, xcd_remap(blockIdx.x, gridDim.x), a.g.n, 0,
+                                                 a.box.ncell, blockIdx.x, gridDim.x, a.st.rebuilt + a.slot);
+}
+template <int NS, int LANES, bool Q, bool OBS, bool TH, bool PLAIN>
+constexpr void (*step_ds_kernel())(StepArgs) {
+    if constexpr (NS == 2 && !TH)
+        return k_step_ds_mix<LANES, Q, OBS, PLAIN>;
+    else
+        return k_step_ds<NS, LANES, Q, OBS, TH, PLAIN>;
+}
 
 // A batch of independent one-species cubic systems, each over its own run of
 // blocks (particle ranges padded to whole blocks): the block finds its
@@ -422,11 +438,11 @@ hipError_t launch_step(const Launch &L, int64_t step, int forced, int mode, int 
 #define STEP_DS(NS, LN, TH, PL)                                                                         \
     do {                                                                                                \
         if (quanta && obs)                                                                              \
-            launch_k(L, k_step_ds<NS, LN, true, true, TH, PL>, grid, block, a);                          \
+            launch_k(L, step_ds_kernel<NS, LN, true, true, TH, PL>(), grid, block, a);                   \
         else if (quanta)                                                                                \
-            launch_k(L, k_step_ds<NS, LN, true, false, TH, PL>, grid, block, a);                         \
+            launch_k(L, step_ds_kernel<NS, LN, true, false, TH, PL>(), grid, block, a);                  \
         else                                                                                            \
-            launch_k(L, k_step_ds<NS, LN, false, true, TH, PL>, grid, block, a);                         \
+            launch_k(L, step_ds_kernel<NS, LN, false, true, TH, PL>(), grid, block, a);                  \
     } while (0)
 #define STEP_TH(NS, LN, TH)                                                              \
     do {                                                                                 \
