@@ -836,6 +836,20 @@ __device__ inline int plan_find(const int64_t *off, int count, int64_t t) {
     return lo;
 }
 
+// Plans of up to kPlanLds systems are searched in LDS: the block copies the
+// offsets there once instead of every lookup walking a chain of dependent
+// global loads.
+constexpr int kPlanLds = 512;
+
+// Copy off[0 .. count] into sh when it fits (every thread of the block must
+// call this); true if it did.
+__device__ inline bool plan_stage(const int64_t *off, int count, int64_t *sh) {
+    if (count > kPlanLds) return false;
+    for (int k = threadIdx.x; k <= count; k += blockDim.x) sh[k] = off[k];
+    __syncthreads();
+    return true;
+}
+
 // One block: per system the rebuild decision (forced, or its largest
 // displacement since its last build exceeded skin/2), the reset of the
 // other parity word, and the compacted list of systems that rebuild with
@@ -894,37 +908,44 @@ __global__ __launch_bounds__(1024) void k_batch_plan(State st, const SysC *sys, 
 }
 
 __global__ __launch_bounds__(kRbBlock) void k_batch_bin(State st, Geom g, const SysC *sys, BatchPlan bp, int cur) {
+    __shared__ int64_t plan_sh[kPlanLds + 1];
     const int count = bp.wl_count[0];
+    const bool lds = plan_stage(bp.wl_poff, count, plan_sh);
     const int64_t total = bp.wl_poff[count];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
-        const int k = plan_find(bp.wl_poff, count, t);
+        const int k = lds ? plan_find(plan_sh, count, t) : plan_find(bp.wl_poff, count, t);
         const int s = bp.wl_sys[k];
         const SysC &y = sys[s];
-        bin_one<LJMD_FP32_DS>(st, g, y.box, st.rank_of + y.c_off, y.c_off, cur, y.p_off + (t - bp.wl_poff[k]),
-                              st.ctl + s);
+        const int64_t first = lds ? plan_sh[k] : bp.wl_poff[k];
+        bin_one<LJMD_FP32_DS>(st, g, y.box, st.rank_of + y.c_off, y.c_off, cur, y.p_off + (t - first), st.ctl + s);
     }
 }
 
 __global__ __launch_bounds__(kRbBlock) void k_batch_canon(State st, Geom g, const SysC *sys, BatchPlan bp) {
     using T = typename CellRec<LJMD_FP32_DS>::T;
     extern __shared__ int4 sm_raw[];
+    __shared__ int64_t plan_sh[kPlanLds + 1];
     const int wv = threadIdx.x >> 6, W = blockDim.x >> 6;
     T *tmp = (T *)((uint8_t *)sm_raw + (size_t)wv * canon_lds_per_wave(g.cell_cap, sizeof(T)));
     int32_t *key = (int32_t *)(tmp + g.cell_cap);
     const int count = bp.wl_count[0];
+    const bool lds = plan_stage(bp.wl_coff, count, plan_sh);
     const int64_t total = bp.wl_coff[count];
     for (int64_t w = (int64_t)blockIdx.x * W + wv; w < total; w += (int64_t)gridDim.x * W) {
-        const int k = plan_find(bp.wl_coff, count, w);
+        const int k = lds ? plan_find(plan_sh, count, w) : plan_find(bp.wl_coff, count, w);
         const SysC &y = sys[bp.wl_sys[k]];
-        canon_cell<LJMD_FP32_DS>(st, g, y.c_off + (w - bp.wl_coff[k]), tmp, key);
+        const int64_t first = lds ? plan_sh[k] : bp.wl_coff[k];
+        canon_cell<LJMD_FP32_DS>(st, g, y.c_off + (w - first), tmp, key);
     }
 }
 
 template <int LG>
 __global__ __launch_bounds__(kNlWaves * kWave, 5) void k_batch_nlist(State st, Geom g, const SysC *sys, BatchPlan bp,
                                                                   PairC pc, int cur) {
+    __shared__ int64_t plan_sh[kPlanLds + 1];
     const int count = bp.wl_count[0];
+    const bool lds = plan_stage(bp.wl_coff, count, plan_sh);
     const int64_t total = bp.wl_coff[count];
     // The flattened cells of the systems due, split into one contiguous share
     // per XCD whose waves take the next cell from a queue (as k_nlist; the
@@ -943,11 +964,12 @@ __global__ __launch_bounds__(kNlWaves * kWave, 5) void k_batch_nlist(State st, G
         w = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(w >> 32)) << 32) |
                       (uint32_t)__builtin_amdgcn_readfirstlane((int)w));
         if (w >= hi) break;
-        const int k = plan_find(bp.wl_coff, count, w);
+        const int k = lds ? plan_find(plan_sh, count, w) : plan_find(bp.wl_coff, count, w);
         const int s = bp.wl_sys[k];
         const SysC &y = sys[s];
+        const int64_t first = lds ? plan_sh[k] : bp.wl_coff[k];
         nlist_cell<LJMD_FP32_DS, 1, true, LG>(st, g, y.box, pc, st.rank_of + y.c_off, st.cell_lin + y.c_off,
-                                              y.c_off, (int)(w - bp.wl_coff[k]), st.ctl + s, rec, queue);
+                                              y.c_off, (int)(w - first), st.ctl + s, rec, queue);
     }
 }
 
@@ -1063,7 +1085,8 @@ hipError_t launch_batch_bin(const Launch &L, const SysC *sys, const BatchPlan &b
 hipError_t launch_batch_canon(const Launch &L, const SysC *sys, const BatchPlan &bp, int64_t total_cells) {
     const size_t per_wave = canon_lds_per_wave(L.g->cell_cap, cell_rec_bytes(LJMD_FP32_DS));
     int W = kRbBlock / kWave;
-    while (W > 1 && (size_t)W * per_wave > 65536) --W;
+    // 64 KiB per block, the staged plan included.
+    while (W > 1 && (size_t)W * per_wave + sizeof(int64_t) * (kPlanLds + 1) > 65536) --W;
     const unsigned nb = rebuild_blocks(L, total_cells, W);
     hipLaunchKernelGGL(k_batch_canon, dim3(nb), dim3(W * kWave), (size_t)W * per_wave, L.stream, *L.st, *L.g, sys,
                        bp);
