@@ -38,6 +38,9 @@ def cases():
     p = r.params.copy()
     p.rcut = np.full(4, np.inf)
     out.append(("mixture900", r.x, r.v, r.species, r.box, p))
+    # More partners than one LDS chunk of records holds in either precision.
+    w = W.all_pairs_fluid(n=4500, seed_index=3)
+    out.append(("fluid4500", w.x, w.v, w.species, w.box, w.params))
     return out
 
 
