@@ -346,8 +346,9 @@ __device__ inline float cand_r2q(const int4 &ri, const int4 &rj) {
 // and the list stores are never waited on.
 template <int PREC, bool FILT = false>
 struct NlistChunk {
-    // 64-candidate blocks per chunk (FILT: chunks reduced before the home
-    // loop; six blocks stay within 88 VGPRs and 6 KiB of LDS per wave)
+    // 64-candidate blocks per chunk (FILT: blocks loaded per round and per
+    // queue drain; six keep the kernel within 96 VGPRs, five waves per SIMD,
+    // and its two queues within 6 KiB of LDS per wave)
     static constexpr int CH = FILT ? 6 : (PREC == LJMD_FP64 ? 4 : 8);
 };
 
