@@ -91,7 +91,7 @@ struct Ctl {
 
 // One system of a batch (independent boxes sharing the potential and the
 // integration constants). Its particles occupy slots [p_off, p_off + n) of
-// the flattened arrays, padded to a multiple of kSysAlign slots; its cells
+// the flattened arrays, padded to whole step-kernel blocks; its cells
 // are [c_off, c_off + box.ncell); its step-kernel blocks [b_off, b_off + nb).
 struct SysC {
     BoxC box;
@@ -104,7 +104,6 @@ struct SysC {
     int32_t nb;      // step-kernel blocks
     int32_t pad;
 };
-constexpr int kSysAlign = 1024;
 
 // Views of the caller's workspace (all device pointers).
 struct State {

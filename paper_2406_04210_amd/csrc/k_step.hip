@@ -396,10 +396,13 @@ __global__ __launch_bounds__(kBlock) void k_integrate(StepArgs a) {
     integrate_body<PREC>(a, a.box, a.st.ctl, a.g.n);
 }
 
-// Batch form: a block of kBlock slots lies inside one system (systems are
-// padded to kSysAlign slots).
-__global__ __launch_bounds__(kBlock) void k_batch_integrate(StepArgs a, const SysC *sys, const int32_t *sys_of_g16) {
-    const SysC &y = sys[sys_of_g16[((int64_t)blockIdx.x * kBlock) >> 4]];
+// Batch form: systems are padded to whole step-kernel blocks (at least 64
+// slots), so the 64 slots of a wave lie inside one system.
+__global__ __launch_bounds__(kBlock) void k_batch_integrate(StepArgs a, const SysC *sys, const int32_t *sys_of_g16,
+                                                            int64_t nslots) {
+    const int64_t w0 = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~(kWave - 1));
+    if (w0 >= nslots) return;
+    const SysC &y = sys[sys_of_g16[w0 >> 4]];
     integrate_body<LJMD_FP32_DS>(a, y.box, a.st.ctl + y.id, y.p_off + y.n);
 }
 
@@ -518,8 +521,8 @@ hipError_t launch_batch_step(const Launch &L, const SysC *sys, const int32_t *sy
 hipError_t launch_batch_integrate(const Launch &L, const SysC *sys, const int32_t *sys_of_g16, int64_t nslots,
                                   int64_t step) {
     StepArgs a = make_args(L, step, 0, kIntegrate, 0);
-    const dim3 grid((unsigned)(nslots / kBlock)), block(kBlock);
-    hipLaunchKernelGGL(k_batch_integrate, grid, block, 0, L.stream, a, sys, sys_of_g16);
+    const dim3 grid((unsigned)((nslots + kBlock - 1) / kBlock)), block(kBlock);
+    hipLaunchKernelGGL(k_batch_integrate, grid, block, 0, L.stream, a, sys, sys_of_g16, nslots);
     return hipGetLastError();
 }
 

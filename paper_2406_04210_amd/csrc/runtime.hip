@@ -862,7 +862,7 @@ int batch_geom(const ljmd_params *shared, const ljmd_system *ys, int32_t nsys, B
         cc = std::max(cc, pk.cell_cap);
         SysC &y = bg.sys[k];
         std::memset(&y, 0, sizeof y);
-        const int64_t npad = (q.n + kSysAlign - 1) / kSysAlign * kSysAlign;
+        const int64_t npad = (q.n + per_block - 1) / per_block * per_block;
         y.p_off = p_off;
         y.in_off = in_off;
         y.n = (int32_t)q.n;
