@@ -453,8 +453,8 @@ def main():
                          "traffic for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "multi-GPU runs are not part of it.", file=sys.stderr)
+        print(f"bench.py: the library steps a system on one GPU (asked for --gpus {args.gpus}); "
+              "there is no multi-GPU path to measure.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
