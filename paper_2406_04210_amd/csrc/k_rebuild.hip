@@ -786,7 +786,7 @@ struct NlistStage {
 };
 
 template <int PREC, int NS, bool QC, int LG = -1>
-__global__ __launch_bounds__(kNlWaves * kWave, 5) void k_nlist(State st, Geom g, BoxC box, PairC pc, int cur,
+__global__ __launch_bounds__(kNlWaves * kWave, NS == 1 ? 6 : 5) void k_nlist(State st, Geom g, BoxC box, PairC pc, int cur,
                                                             int64_t step, int forced, float thr2) {
     if (halted(st.ctl) || !rebuild_due(st.ctl, step, forced, thr2)) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) st.ctl->rebuilds += 1;
