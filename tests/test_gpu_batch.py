@@ -165,3 +165,45 @@ def test_full_batch_sampled_systems(ljmd):
         m = report(f"full batch replica {k} {w.name}",
                    force_errors(fh[sl], ref, A, tie_allowance(xh[sl], w.species, w.box, w.params, FP32)))
         assert m[bound_key(1)] <= 1e-5, (k, w.name, m)
+
+
+def test_many_systems_plan_searched_in_global_memory(ljmd):
+    # 700 small replicas: every system rebuilds on the first step, so the
+    # rebuild plan holds more systems than the list-build kernels stage in
+    # LDS (512) and they search it in global memory instead. Sampled systems
+    # (the first, the last and two drawn) against single-box runs (bitwise,
+    # rebuild counts included) and two against the oracle (forces).
+    import torch
+    ws = W.replica_draws(700, nmin=500, nmax=1500)
+    b = make_batch(ljmd, ws, sort_interval=25)
+    b.run(40)
+    xb, vb, ib = b.get_state()
+    fb = b.forces()
+    ob = b.observables()
+    b.sync()
+    assert int(ob[:, 6].min()) >= 1
+    off = np.concatenate([[0], np.cumsum([w.n for w in ws])])
+    rng = np.random.default_rng(6)
+    picks = [0, len(ws) - 1] + [int(k) for k in rng.choice(np.arange(1, len(ws) - 1), 2, replace=False)]
+    for k in picks:
+        w = ws[k]
+        s = ljmd.System(w.n, w.box, w.params, precision=FP32, sort_interval=25)
+        s.set_state(w.x, w.v, w.species)
+        s.run(40, observe=False)
+        x, v, img = s.get_state()
+        f = s.forces()
+        o = s.observables()
+        s.sync()
+        sl = slice(off[k], off[k + 1])
+        assert torch.equal(x, xb[sl]) and torch.equal(v, vb[sl]), (k, w.name)
+        assert torch.equal(img, ib[sl]) and torch.equal(f, fb[sl]), (k, w.name)
+        assert int(ob[k, 6]) == o["rebuilds"] and int(ob[k, 7]) == o["step"] == 40, (k, ob[k], o)
+    fh = fb.cpu().numpy()
+    xh = xb.cpu().numpy()
+    for k in picks[2:]:
+        w = ws[k]
+        sl = slice(off[k], off[k + 1])
+        ref, _, _, A = reference(xh[sl], w.species, w.box, w.params, FP32)
+        m = report(f"many-system batch replica {k} {w.name}",
+                   force_errors(fh[sl], ref, A, tie_allowance(xh[sl], w.species, w.box, w.params, FP32)))
+        assert m[bound_key(1)] <= 1e-5, (k, w.name, m)
