@@ -447,8 +447,12 @@ __device__ inline void nlist_homes(const State &st, const Geom &g, const BoxC &b
             }
             const unsigned long long mask = __builtin_amdgcn_ballot_w64(hit);
             if (mask == 0ull) continue;
-            const uint32_t kk = __builtin_amdgcn_mbcnt_hi(
+            // Entries past the capacity land on the last slot: a list that
+            // overflows is only counted (its build is flagged and redone
+            // with larger lists), and no branch on the count is needed.
+            uint32_t kk = __builtin_amdgcn_mbcnt_hi(
                 (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, (uint32_t)k));
+            kk = min(kk, (uint32_t)g.cap - 1u);
             k += __popcll(mask);
             uint32_t off;
             if constexpr (LG == 1) {
@@ -462,12 +466,7 @@ __device__ inline void nlist_homes(const State &st, const Geom &g, const BoxC &b
                 off = (((kk >> (lg + 2)) << 8) | ((kk & (uint32_t)(lanes - 1)) << 2) |
                        __builtin_amdgcn_ubfe(kk, lg, 2)) << 2;
             }
-            // Past the capacity only the overflow count is kept.
-            if (__builtin_expect(k <= g.cap, 1)) {
-                if (hit) *(int32_t *)(row + off) = j;
-            } else if (hit && kk < (uint32_t)g.cap) {
-                *(int32_t *)(row + off) = j;
-            }
+            if (hit) *(int32_t *)(row + off) = j;
         }
         kreg = lane == p ? k : kreg;
     }
