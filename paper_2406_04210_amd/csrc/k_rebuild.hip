@@ -523,11 +523,13 @@ struct NlistQueue {
 // of this wave.
 // LG: log2 of the lanes per particle of the list layout when it is known at
 // compile time (the shifts and masks of the entry index fold), -1 to read it
-// from g.lanes.
-template <int PREC, int NS, bool QC, int LG = -1>
-__device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &box, const PairC &pc,
-                                  const int32_t *rank_of, const int32_t *cell_lin, int64_t c_off, int c,
-                                  Ctl *ctl, const typename CellRec<PREC>::T *__restrict__ rec, int32_t *queue) {
+// from g.lanes. WIDE: the grid has at least 2 R + 2 cells along every axis
+// (a compile-time branch, so that the box test's loop carries only the
+// bounds of one form).
+template <int PREC, int NS, bool QC, int LG, bool WIDE>
+__device__ inline void nlist_cell_as(const State &st, const Geom &g, const BoxC &box, const PairC &pc,
+                                     const int32_t *rank_of, const int32_t *cell_lin, int64_t c_off, int c,
+                                     Ctl *ctl, const typename CellRec<PREC>::T *__restrict__ rec, int32_t *queue) {
     using CR = CellRec<PREC>;
     using T = typename CR::T;
     constexpr bool FILT = PREC == LJMD_FP32_DS && QC;
@@ -592,11 +594,13 @@ __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &bo
                 }
             }
         }
-        // Along every axis the grid has at least 2 R + 2 cells: every
+        // An empty group (all home particles at one z) keeps no candidate:
+        // its bound is negative.
+        const float greach[2] = {reach, gmask[1] != 0ull ? reach : -1.0f};
+        // WIDE (along every axis the grid has at least 2 R + 2 cells): every
         // candidate then lies within half a box of the home cell, and the
         // wrapped gap to a group's box is the plain signed one (glo, ghi:
         // the box's extent relative to group 0's corner).
-        const bool wide = box.nc[0] >= 2 * R + 2 && box.nc[1] >= 2 * R + 2 && box.nc[2] >= 2 * R + 2;
         int32_t glo[2][3], ghi[2][3];
         for (int gi = 0; gi < 2; ++gi)
             for (int a = 0; a < 3; ++a) {
@@ -694,11 +698,11 @@ __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &bo
                     const int32_t dx = (int32_t)((uint32_t)cand[b].x - bmn[0][0]);
                     const int32_t dy = (int32_t)((uint32_t)cand[b].y - bmn[0][1]);
                     const int32_t dz = (int32_t)((uint32_t)cand[b].z - bmn[0][2]);
+                    const unsigned long long cvm = __builtin_amdgcn_ballot_w64(cv[b]);
 #pragma unroll
                     for (int gi = 0; gi < 2; ++gi) {
-                        if (gmask[gi] == 0ull) continue;
                         float gx, gy, gz;
-                        if (wide) {
+                        if constexpr (WIDE) {
                             gx = (float)max(max(glo[gi][0] - dx, dx - ghi[gi][0]), 0);
                             gy = (float)max(max(glo[gi][1] - dy, dy - ghi[gi][1]), 0);
                             gz = (float)max(max(glo[gi][2] - dz, dz - ghi[gi][2]), 0);
@@ -707,11 +711,13 @@ __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &bo
                             gy = (float)gap_q((uint32_t)cand[b].y, bmn[gi][1], bspan[gi][1]);
                             gz = (float)gap_q((uint32_t)cand[b].z, bmn[gi][2], bspan[gi][2]);
                         }
-                        const bool keep = cv[b] && fmaf(gz, gz, fmaf(gy, gy, gx * gx)) <= reach;
-                        const unsigned long long km = __builtin_amdgcn_ballot_w64(keep);
+                        // The ballot of the bare compare, masked with the
+                        // real candidates' ballot in scalar registers.
+                        const bool near = fmaf(gz, gz, fmaf(gy, gy, gx * gx)) <= greach[gi];
+                        const unsigned long long km = __builtin_amdgcn_ballot_w64(near) & cvm;
                         const uint32_t pos = __builtin_amdgcn_mbcnt_hi(
                             (uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, (uint32_t)fill[gi]));
-                        if (keep) queue[gi * NlistQueue<CH>::kCap + pos] = CR::index(cand[b]);
+                        if (near && cv[b]) queue[gi * NlistQueue<CH>::kCap + pos] = CR::index(cand[b]);
                         fill[gi] += __popcll(km);
                     }
                 }
@@ -773,6 +779,19 @@ __device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &bo
             }
         }
     }
+}
+
+// The lists of home cell c (see nlist_cell_as).
+template <int PREC, int NS, bool QC, int LG = -1>
+__device__ inline void nlist_cell(const State &st, const Geom &g, const BoxC &box, const PairC &pc,
+                                  const int32_t *rank_of, const int32_t *cell_lin, int64_t c_off, int c,
+                                  Ctl *ctl, const typename CellRec<PREC>::T *__restrict__ rec, int32_t *queue) {
+    constexpr bool FILT = PREC == LJMD_FP32_DS && QC;
+    const int w = 2 * box.reach + 2;
+    if (FILT && box.nc[0] >= w && box.nc[1] >= w && box.nc[2] >= w)
+        nlist_cell_as<PREC, NS, QC, LG, FILT>(st, g, box, pc, rank_of, cell_lin, c_off, c, ctl, rec, queue);
+    else
+        nlist_cell_as<PREC, NS, QC, LG, false>(st, g, box, pc, rank_of, cell_lin, c_off, c, ctl, rec, queue);
 }
 
 // Per-block LDS of the reduced list build (FP32 cubic boxes only): two
