@@ -418,6 +418,10 @@ __device__ inline void nlist_homes(const State &st, const Geom &g, const BoxC &b
     const int lane = threadIdx.x & 63;
     const int lg = LG >= 0 ? LG : (g.lanes >= 16 ? 4 : (g.lanes >= 8 ? 3 : (g.lanes >= 4 ? 2 : (g.lanes >= 2 ? 1 : 0))));
     const int lanes = LG >= 0 ? (1 << LG) : g.lanes;
+    // The two-lane store table (below), held in scalar registers and opaque
+    // to the compiler, so that the merge stays a single bit-field insert.
+    uint64_t g4tab = 0x1C0C180814041000ull;
+    asm volatile("" : "+s"(g4tab));
     for (uint64_t mk = homes; mk != 0ull; mk &= mk - 1ull) {
         const int p = __builtin_ctzll(mk);
         const T ri = lane_read(hrec, p);
@@ -457,11 +461,13 @@ __device__ inline void nlist_homes(const State &st, const Geom &g, const BoxC &b
             uint32_t off;
             if constexpr (LG == 1) {
                 // Two lanes: byte (kk / 8) * 1024 + 4 g(kk % 8) with
-                // g(r) = 4 (r % 2) + r / 2, read from a table of 3-bit fields
-                // (the extract takes its offset modulo 32, and g < 8 keeps
-                // the entry inside its group whatever the offset).
-                const uint32_t g4 = __builtin_amdgcn_ubfe(0x73625140u, kk << 2, 3);
-                off = ((kk << 7) & ~0x3ffu) + (g4 << 2);
+                // g(r) = 4 (r % 2) + r / 2. Byte r of a 64-bit table holds
+                // 4 g(r) (one 64-bit shift by 8 kk, which the hardware takes
+                // modulo 64); its bits 0..9 are exactly 4 g(r), since the
+                // next byte is a multiple of 4, and they are merged into the
+                // group's offset with one bit-field insert.
+                const uint32_t g4 = (uint32_t)(g4tab >> ((kk << 3) & 63u));
+                off = ((kk << 7) & ~0x3ffu) | (g4 & 0x3ffu);
             } else {
                 off = (((kk >> (lg + 2)) << 8) | ((kk & (uint32_t)(lanes - 1)) << 2) |
                        __builtin_amdgcn_ubfe(kk, lg, 2)) << 2;
