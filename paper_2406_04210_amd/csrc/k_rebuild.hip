@@ -93,23 +93,28 @@ __device__ inline void bin_one(const State &st, const Geom &g, const BoxC &box, 
     const int64_t c = c_off + cell_of_q(q[0], q[1], q[2], box, rank_of, &cx, &cy, &cz);
     // The lanes of a wavefront that land in one cell take their slots with a
     // single atomic: consecutive particles (space-filling-curve order) share
-    // a few cells. Every active lane runs the same number of rounds.
+    // a few cells. The groups and their leaders are found first (ballots
+    // only, every active lane runs the same number of rounds); then the
+    // leaders' atomics go out together, one memory round trip per wave.
     const int lane = threadIdx.x & 63;
     const int ci = (int)c;
     unsigned long long pending = __ballot(1);
-    int slot = 0;
+    int leader_of = lane, rank = 0, take = 0;
     while (pending) {
         const int leader = __ffsll(pending) - 1;
         const int cl = __builtin_amdgcn_readlane(ci, leader);
         const unsigned long long same = __ballot(ci == cl);
-        int base = 0;
-        if (lane == leader) base = atomicAdd(&st.cell_count[cl], __popcll(same));
-        base = __builtin_amdgcn_readlane(base, leader);
-        if (ci == cl)
-            slot = base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(same >> 32),
-                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)same, 0u));
+        if (ci == cl) {
+            leader_of = leader;
+            rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(same >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)same, 0u));
+        }
+        if (lane == leader) take = __popcll(same);
         pending &= ~same;
     }
+    int base = 0;
+    if (take > 0) base = atomicAdd(&st.cell_count[ci], take);
+    const int slot = __shfl(base, leader_of) + rank;
     if (slot < g.cell_cap)
         cell_recs<PREC>(st)[c * g.cell_cap + slot] = CR::pack(r, (int)i);
     else
