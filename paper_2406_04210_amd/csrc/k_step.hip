@@ -215,20 +215,32 @@ __device__ inline void step_ds_body(const StepArgs &a, const BoxC &box, Ctl *ctl
     }
     }
     if constexpr (LANES > 1) {
+        // The particle's lanes exchange their sums: within a quad by DPP
+        // moves (no LDS round trip), wider by shuffles.
+        auto xsum = [](auto &v, int o) {
+            using V = std::remove_reference_t<decltype(v)>;
+            if (o == 1 || o == 2) {
+                if constexpr (std::is_same_v<V, double>) v += o == 1 ? dpp_d<kDppXor1>(v) : dpp_d<kDppXor2>(v);
+                else if constexpr (std::is_same_v<V, float>) v += o == 1 ? dpp_f<kDppXor1>(v) : dpp_f<kDppXor2>(v);
+                else v += (V)(o == 1 ? dpp_u<kDppXor1>((uint32_t)v) : dpp_u<kDppXor2>((uint32_t)v));
+            } else {
+                v += __shfl_xor(v, o);
+            }
+        };
 #pragma unroll
         for (int o = LANES / 2; o > 0; o >>= 1) {
-            fx += __shfl_xor(fx, o);
-            fy += __shfl_xor(fy, o);
-            fz += __shfl_xor(fz, o);
+            xsum(fx, o);
+            xsum(fy, o);
+            xsum(fz, o);
             if constexpr (NS == 1) {
                 if constexpr (OBS) {
-                    a12 += __shfl_xor(a12, o);
-                    a6 += __shfl_xor(a6, o);
-                    an += __shfl_xor(an, o);
+                    xsum(a12, o);
+                    xsum(a6, o);
+                    xsum(an, o);
                 }
             } else {
-                e += __shfl_xor(e, o);
-                w += __shfl_xor(w, o);
+                xsum(e, o);
+                xsum(w, o);
             }
         }
     }

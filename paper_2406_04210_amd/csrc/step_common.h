@@ -52,6 +52,50 @@ __device__ inline T wave_sum(T v) {
     return v;
 }
 
+// Data-parallel-primitive (DPP) moves within a row of 16 lanes, no LDS
+// round trip: CTRL is the move (quad permutations 0x00-0xff, row mirrors
+// 0x140 / 0x141, row broadcasts 0x142 / 0x143), ROWM the rows written; other
+// lanes read 0. Every lane of the wavefront must be active.
+template <int CTRL, int ROWM = 0xf>
+__device__ inline uint32_t dpp_u(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWM, 0xf, false);
+}
+template <int CTRL, int ROWM = 0xf>
+__device__ inline float dpp_f(float v) {
+    return __uint_as_float(dpp_u<CTRL, ROWM>(__float_as_uint(v)));
+}
+template <int CTRL, int ROWM = 0xf>
+__device__ inline double dpp_d(double v) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint64_t lo = dpp_u<CTRL, ROWM>((uint32_t)b), hi = dpp_u<CTRL, ROWM>((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)((hi << 32) | lo));
+}
+constexpr int kDppXor1 = 0xb1, kDppXor2 = 0x4e;  // quad permutations [1,0,3,2], [2,3,0,1]
+
+// Sum (max) over the wavefront, complete in lane 63: lane pairs and quads,
+// half-row and row mirrors (after each step every lane of a quad, half row,
+// row holds the same value), then row 0 into row 1 and row 2 into row 3,
+// and row 1 into rows 2 and 3. A fixed order, so the result is
+// reproducible.
+__device__ inline double wave_sum_last(double v) {
+    v += dpp_d<kDppXor1>(v);
+    v += dpp_d<kDppXor2>(v);
+    v += dpp_d<0x141>(v);
+    v += dpp_d<0x140>(v);
+    v += dpp_d<0x142, 0xa>(v);
+    v += dpp_d<0x143, 0xc>(v);
+    return v;
+}
+__device__ inline uint32_t wave_max_last(uint32_t v) {
+    v = max(v, dpp_u<kDppXor1>(v));
+    v = max(v, dpp_u<kDppXor2>(v));
+    v = max(v, dpp_u<0x141>(v));
+    v = max(v, dpp_u<0x140>(v));
+    v = max(v, dpp_u<0x142, 0xa>(v));
+    v = max(v, dpp_u<0x143, 0xc>(v));
+    return v;
+}
+
 __device__ inline uint32_t wave_max_u(uint32_t v) {
     for (int o = 32; o > 0; o >>= 1) {
         uint32_t y = __shfl_xor(v, o);
@@ -123,10 +167,10 @@ __device__ inline void block_finish(const StepArgs &a, Ctl *ctl, int blk, double
     double v6[6] = {u, w, k, px, py, pz};
     if constexpr (OBS) {
 #pragma unroll
-        for (int q = 0; q < 6; ++q) v6[q] = wave_sum(v6[q]);
+        for (int q = 0; q < 6; ++q) v6[q] = wave_sum_last(v6[q]);
     }
-    dmax = wave_max_u(dmax);
-    if (lane == 0) {
+    dmax = wave_max_last(dmax);
+    if (lane == kWave - 1) {
         if constexpr (OBS) {
 #pragma unroll
             for (int q = 0; q < 6; ++q) red[wv][q] = v6[q];
