@@ -35,8 +35,8 @@ HBM_PEAK_GBS = 8000.0
 # 512 MiB copy reads), valid only for the kernel sources they were taken on.
 STEP_KERNEL_SOURCES = ("k_step.hip", "step_common.h", "internal.h")
 STEP_KERNEL_TRAFFIC = {
-    "sources_sha256": "9a4863108aa75421d2dbfe3f79d637f5e5c21264be7ea16390186583f9d329ae",
-    "fetch_bytes": 2.0 * 53444 * 1024,
+    "sources_sha256": "25fed7b0c7dd77b0ef3176e23e4fc6ca21da4fd1965334f8721c28c6047599e4",
+    "fetch_bytes": 2.0 * 53446 * 1024,
     "write_bytes": 1.0 * 16035 * 1024,
 }
 
