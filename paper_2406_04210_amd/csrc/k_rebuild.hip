@@ -393,19 +393,30 @@ __device__ inline uint32_t gap_q(uint32_t q, uint32_t mn, uint32_t span) {
     return t <= span ? 0u : (a < b ? a : b);
 }
 
-__device__ inline uint32_t wave_min_u32(uint32_t v) {
-    for (int o = 32; o >= 1; o >>= 1) {
-        const uint32_t w = (uint32_t)__shfl_xor((int)v, o);
-        v = w < v ? w : v;
-    }
+// Unsigned minimum (MAX false) or maximum over the wavefront, complete in
+// lane 63, by DPP row moves instead of LDS permutes (every lane active):
+// lane pairs and quads, half-row and row mirrors, then row broadcasts; a
+// lane of a row that a broadcast does not write reads the identity.
+template <int CTRL, int ROWM, bool MAX>
+__device__ inline uint32_t dpp_ext(uint32_t v) {
+    const uint32_t w = (uint32_t)__builtin_amdgcn_update_dpp(MAX ? 0 : -1, (int)v, CTRL, ROWM, 0xf, false);
+    return MAX ? (w > v ? w : v) : (w < v ? w : v);
+}
+template <bool MAX>
+__device__ inline uint32_t wave_ext_last(uint32_t v) {
+    v = dpp_ext<0xb1, 0xf, MAX>(v);
+    v = dpp_ext<0x4e, 0xf, MAX>(v);
+    v = dpp_ext<0x141, 0xf, MAX>(v);
+    v = dpp_ext<0x140, 0xf, MAX>(v);
+    v = dpp_ext<0x142, 0xa, MAX>(v);
+    v = dpp_ext<0x143, 0xc, MAX>(v);
     return v;
 }
+__device__ inline uint32_t wave_min_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)wave_ext_last<false>(v), 63);
+}
 __device__ inline uint32_t wave_max_u32(uint32_t v) {
-    for (int o = 32; o >= 1; o >>= 1) {
-        const uint32_t w = (uint32_t)__shfl_xor((int)v, o);
-        v = w > v ? w : v;
-    }
-    return v;
+    return (uint32_t)__builtin_amdgcn_readlane((int)wave_ext_last<true>(v), 63);
 }
 
 // Tests the candidate blocks cand[0 .. nbk) (lane e of block b holds one
@@ -590,8 +601,8 @@ __device__ inline void nlist_cell_as(const State &st, const Geom &g, const BoxC 
         if constexpr (FILT) {
             const bool act = lane < hm;
             const uint32_t hq[3] = {(uint32_t)hrec.x, (uint32_t)hrec.y, (uint32_t)hrec.z};
-            const uint32_t zmn = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_min_u32(act ? hq[2] : 0xffffffffu));
-            const uint32_t zmx = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_max_u32(act ? hq[2] : 0u));
+            const uint32_t zmn = wave_min_u32(act ? hq[2] : 0xffffffffu);
+            const uint32_t zmx = wave_max_u32(act ? hq[2] : 0u);
             const bool up = act && hq[2] - zmn > ((zmx - zmn) >> 1);
             gmask[0] = __ballot(act && !up);
             gmask[1] = __ballot(up);
@@ -600,8 +611,8 @@ __device__ inline void nlist_cell_as(const State &st, const Geom &g, const BoxC 
                 for (int a = 0; a < 3; ++a) {
                     const uint32_t mn = wave_min_u32(in ? hq[a] : 0xffffffffu);
                     const uint32_t mx = wave_max_u32(in ? hq[a] : 0u);
-                    bmn[gi][a] = (uint32_t)__builtin_amdgcn_readfirstlane((int)mn);
-                    bspan[gi][a] = (uint32_t)__builtin_amdgcn_readfirstlane((int)(mx - mn));
+                    bmn[gi][a] = mn;
+                    bspan[gi][a] = mx - mn;
                 }
             }
         }
@@ -815,7 +826,7 @@ struct NlistStage {
 };
 
 template <int PREC, int NS, bool QC, int LG = -1>
-__global__ __launch_bounds__(kNlWaves * kWave, NS == 1 ? 6 : 5) void k_nlist(State st, Geom g, BoxC box, PairC pc, int cur,
+__global__ __launch_bounds__(kNlWaves * kWave, 6) void k_nlist(State st, Geom g, BoxC box, PairC pc, int cur,
                                                             int64_t step, int forced, float thr2) {
     if (halted(st.ctl) || !rebuild_due(st.ctl, step, forced, thr2)) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) st.ctl->rebuilds += 1;
