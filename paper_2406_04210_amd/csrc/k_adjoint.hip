@@ -114,8 +114,8 @@ __device__ inline void block_rows6(const double (&v)[6], double *row, double wei
     __shared__ double red[WPB][6];
     double s[6];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) s[q] = wave_sum(v[q]);
-    if ((threadIdx.x & 63) == 0) {
+    for (int q = 0; q < 6; ++q) s[q] = wave_sum_last(v[q]);
+    if ((threadIdx.x & 63) == kWave - 1) {
 #pragma unroll
         for (int q = 0; q < 6; ++q) red[threadIdx.x >> 6][q] = s[q];
     }
@@ -291,10 +291,21 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_pairs(AdjArgs a) {
         oz = fz;
     }
     if constexpr (MODE == kAdjVjp) {
+        // Within a quad by DPP moves (FP64, both halves), wider by shuffles.
         for (int o = lanes >> 1; o > 0; o >>= 1) {
-            ox += __shfl_xor(ox, o);
-            oy += __shfl_xor(oy, o);
-            oz += __shfl_xor(oz, o);
+            if (o == 1) {
+                ox += dpp_d<kDppXor1>(ox);
+                oy += dpp_d<kDppXor1>(oy);
+                oz += dpp_d<kDppXor1>(oz);
+            } else if (o == 2) {
+                ox += dpp_d<kDppXor2>(ox);
+                oy += dpp_d<kDppXor2>(oy);
+                oz += dpp_d<kDppXor2>(oz);
+            } else {
+                ox += __shfl_xor(ox, o);
+                oy += __shfl_xor(oy, o);
+                oz += __shfl_xor(oz, o);
+            }
         }
         uint32_t dnext = 0u;
         if (valid && l == 0) {
