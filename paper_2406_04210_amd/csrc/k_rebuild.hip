@@ -466,7 +466,6 @@ __device__ inline void nlist_homes(const State &st, const Geom &g, const BoxC &b
                 hit = __float_as_uint(r2) - 1u < lim;
             }
             const unsigned long long mask = __builtin_amdgcn_ballot_w64(hit);
-            if (mask == 0ull) continue;
             // Entries past the capacity land on the last slot: a list that
             // overflows is only counted (its build is flagged and redone
             // with larger lists), and no branch on the count is needed.
